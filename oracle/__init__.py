@@ -1,0 +1,259 @@
+"""CPU oracle: ctypes wrapper around ``oracle.c``.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library; the two are fed the same inputs from
+``paper_2407_06107_amd.inputs`` and compared.
+
+All arrays here are host NumPy arrays.  Results are float64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# enums of the oracle (its own copy; it does not include the library header)
+NEAREST, LINEAR, BSPLINE3 = 0, 1, 2
+BEFORE, AFTER, STOCHASTIC = 0, 1, 2
+RGBA32F, RGBA8, R16F, R32F = 0, 1, 2, 3
+REPEAT, CLAMP = 0, 1
+MIP_NONE, MIP_NEAREST, MIP_LINEAR = 0, 1, 2
+TAP_NONE = np.iinfo(np.int32).min
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` with gcc (OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-fvisibility=hidden", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i32, i64, u32, f32 = C.c_int, C.c_int64, C.c_uint32, C.c_float
+        L.orc_kbs.restype = C.c_double
+        L.orc_kbs.argtypes = [C.c_double]
+        L.orc_ktent.restype = C.c_double
+        L.orc_ktent.argtypes = [C.c_double]
+        L.orc_thresholds.argtypes = [i32, f32, P]
+        L.orc_pick.argtypes = [i32, f32, f32]
+        L.orc_reuse.restype = f32
+        L.orc_reuse.argtypes = [i32, f32, f32, i32]
+        L.orc_pick_pmf.argtypes = [i32, f32, P]
+        L.orc_axis_weights64.argtypes = [i32, C.c_double, P]
+        L.orc_sample_array.argtypes = [P, i32, C.c_double]
+        L.orc_half_to_double.restype = C.c_double
+        L.orc_half_to_double.argtypes = [C.c_uint16]
+        L.orc_pcg4d_batch.argtypes = [P, P, i64]
+        L.orc_shade_ggx.argtypes = [P, P, P]
+        L.orc_filter2d.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, i32, i32, u32,
+                                   i32, i32, P, P, P]
+        L.orc_filter2d_expect.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, i32, P, P]
+        L.orc_reuse_histogram2.argtypes = [i32, f32, f32, P]
+        L.orc_filter3d.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, u32, i32,
+                                   i32, f32, P, P]
+        L.orc_raymarch.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, i32, u32, i32,
+                                   P, P, P, i64]
+        L.orc_raymarch_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# ---------------------------------------------------------------- primitives
+def pcg4d(keys: np.ndarray) -> np.ndarray:
+    keys = _c(keys, np.uint32).reshape(-1, 4)
+    out = np.empty_like(keys)
+    lib().orc_pcg4d_batch(_p(keys), _p(out), keys.shape[0])
+    return out
+
+
+def kbs(x: float) -> float:
+    return lib().orc_kbs(float(x))
+
+
+def ktent(x: float) -> float:
+    return lib().orc_ktent(float(x))
+
+
+def thresholds(filt: int, t: float) -> np.ndarray:
+    c = np.zeros(3, dtype=np.float32)
+    n = lib().orc_thresholds(filt, float(t), _p(c))
+    return c[:n]
+
+
+def pick(filt: int, t: float, u: float) -> int:
+    return int(lib().orc_pick(filt, float(t), float(u)))
+
+
+def reuse(filt: int, t: float, u: float, j: int) -> float:
+    return float(lib().orc_reuse(filt, float(t), float(u), int(j)))
+
+
+def pick_pmf(filt: int, t: float) -> np.ndarray:
+    p = np.zeros(4)
+    lib().orc_pick_pmf(filt, float(t), _p(p))
+    return p
+
+
+def sample_array(w, xi: float) -> int:
+    w = _c(w, np.float64).reshape(-1)
+    return int(lib().orc_sample_array(_p(w), w.size, float(xi)))
+
+
+def axis_weights64(filt: int, t: float) -> np.ndarray:
+    w = np.zeros(4)
+    lib().orc_axis_weights64(filt, float(t), _p(w))
+    return w
+
+
+def half_to_double(bits: int) -> float:
+    return lib().orc_half_to_double(int(bits))
+
+
+def ggx_params(n=(0.0, 0.0, 1.0), wo=(0.2, 0.3, 1.0), wi=(-0.4, 0.1, 1.0), radiance=(1.0, 1.0, 1.0),
+               f0=0.04, r_bias=0.05, r_scale=0.95) -> np.ndarray:
+    """16 doubles: n, wo, wi (normalised here), radiance, f0, r_bias, r_scale, 0."""
+    def nrm(v):
+        v = np.asarray(v, dtype=np.float64)
+        return v / np.linalg.norm(v)
+    p = np.zeros(16)
+    p[0:3], p[3:6], p[6:9] = nrm(n), nrm(wo), nrm(wi)
+    p[9:12] = radiance
+    p[12], p[13], p[14] = f0, r_bias, r_scale
+    return p
+
+
+def shade_ggx(params: np.ndarray, rgba) -> np.ndarray:
+    params = _c(params, np.float64)
+    rgba = _c(rgba, np.float64)
+    out = np.zeros(3)
+    lib().orc_shade_ggx(_p(params), _p(rgba), _p(out))
+    return out
+
+
+def reuse_histogram2(filt: int, tx: float, ty: float) -> np.ndarray:
+    c = np.zeros(16, dtype=np.int64)
+    lib().orc_reuse_histogram2(filt, float(tx), float(ty), _p(c))
+    return c.reshape(4, 4)
+
+
+# ------------------------------------------------------------------ 2-D path
+class Tex2D:
+    """Host texture: packed level buffer + per-level byte offsets."""
+
+    def __init__(self, buf: np.ndarray, w: int, h: int, levels: int, fmt: int, offsets,
+                 wrap: int = REPEAT, mip: int = MIP_NONE):
+        self.buf = np.ascontiguousarray(buf).view(np.uint8).reshape(-1)
+        self.w, self.h, self.levels, self.fmt = w, h, levels, fmt
+        self.off = np.zeros(16, dtype=np.int64)
+        self.off[:levels] = offsets
+        self.wrap, self.mip = wrap, mip
+
+    @classmethod
+    def rgba32f(cls, tex: np.ndarray, wrap=REPEAT):
+        tex = np.ascontiguousarray(tex, dtype=np.float32)
+        return cls(tex, tex.shape[1], tex.shape[0], 1, RGBA32F, [0], wrap, MIP_NONE)
+
+
+def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed: int = 0,
+             variant: int = 0, shade: int = 0, ggx=None, taps: bool = False):
+    q = _c(q, np.float32).reshape(-1, 3)
+    n = q.shape[0]
+    ch = 3 if shade == 1 else 4
+    out = np.zeros((n, ch))
+    tp = np.zeros((n, spp, 3), dtype=np.int32) if taps else None
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_filter2d(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
+                       _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, shade, _p(g), _p(out), _p(tp))
+    return (out, tp) if taps else out
+
+
+def filter2d_expect(tex: Tex2D, q: np.ndarray, filt: int, shade: int = 0, ggx=None):
+    q = _c(q, np.float32).reshape(-1, 3)
+    n = q.shape[0]
+    ch = 3 if shade == 1 else 4
+    out = np.zeros((n, ch))
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_filter2d_expect(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip,
+                              _p(tex.off), _p(q), n, filt, shade, _p(g), _p(out))
+    return out
+
+
+# ------------------------------------------------------------------ 3-D path
+class Grid:
+    """Host density grid ``[nz, ny, nx]`` (float16 or float32), world box
+    starting at ``wmin`` with ``scale`` voxels per world unit."""
+
+    def __init__(self, data: np.ndarray, wmin=(0.0, 0.0, 0.0), scale=None, side: float = None):
+        self.data = np.ascontiguousarray(data)
+        assert self.data.dtype in (np.float16, np.float32)
+        self.nz, self.ny, self.nx = self.data.shape
+        self.fmt = R16F if self.data.dtype == np.float16 else R32F
+        self.wmin = np.asarray(wmin, dtype=np.float32)
+        if scale is None:
+            side = 1.0 if side is None else side
+            scale = (self.nx / side, self.ny / side, self.nz / side)
+        self.scale = np.asarray(scale, dtype=np.float32)
+
+
+def filter3d(g: Grid, pos: np.ndarray, filt: int, mode: int, spp: int = 1, seed: int = 0, variant: int = 0,
+             shade: int = 0, ds: float = 1.0, taps: bool = False):
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    n = pos.shape[0]
+    out = np.zeros(n)
+    tp = np.zeros((n, spp, 3), dtype=np.int32) if taps else None
+    lib().orc_filter3d(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(pos), n, filt, mode,
+                       spp, seed & 0xFFFFFFFF, variant, shade, float(ds), _p(out), _p(tp))
+    return (out, tp) if taps else out
+
+
+def raymarch(g: Grid, rays: np.ndarray, steps: int, filt: int, mode: int, spp: int = 1, seed: int = 0,
+             variant: int = 0, taps: bool = False, subset=None):
+    rays = _c(rays, np.float32).reshape(-1, 8)
+    n = rays.shape[0]
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
+    T = np.zeros(m)
+    tp = np.zeros((m, spp, steps, 3), dtype=np.int32) if taps else None
+    lib().orc_raymarch(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(rays), n, steps, filt,
+                       mode, spp, seed & 0xFFFFFFFF, variant, _p(T), _p(tp), _p(sub), 0 if sub is None else sub.size)
+    return (T, tp) if taps else T
+
+
+def raymarch_expect(g: Grid, rays: np.ndarray, steps: int, filt: int):
+    rays = _c(rays, np.float32).reshape(-1, 8)
+    n = rays.shape[0]
+    T = np.zeros(n)
+    lib().orc_raymarch_expect(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(rays), n, steps,
+                              filt, _p(T))
+    return T

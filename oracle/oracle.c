@@ -1,0 +1,879 @@
+/*
+ * CPU ORACLE for stochastic texture filtering with filtering after shading
+ * (Pharr, Wronski, Salvi, Fajardo, "Filtering After Shading With Stochastic
+ * Texture Filtering", 2024).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library; it is the plain,
+ * slow, obviously-correct statement of what the GPU path must compute.
+ *
+ * Numbers: every texel value, weight used in a deterministic sum, shading
+ * result and accumulation is IEEE binary64.  The few *decisions* (which texel
+ * a sample picks, which MIP level, the raster position of a ray step) are made
+ * in IEEE binary32 with every operation written out (compile with
+ * -ffp-contract=off; fmaf is called explicitly where the decision contract
+ * specifies a fused multiply-add), so that a GPU following the same contract
+ * reaches the same integer decisions bit for bit.
+ *
+ * Paper passages followed (section / equation / listing):
+ *   texture as a lattice of samples ............ Sec. 2.1, eq. texture-definition
+ *   filtered texture as a weighted sum ......... Sec. 2.2, eq. filtered-texture
+ *   one-texel stochastic estimator ............. Sec. 2.2, eq. stochastic-sum
+ *   sampling an array by its running sum ....... Sec. 2.2 "Sampling arrays"
+ *   uniform sample reuse ....................... Sec. 2.2, eq. uniform-sample-reuse
+ *   separable sampling ......................... Sec. 2.2 "Separable functions"
+ *   filter before / after shading .............. Sec. 3, eqs. filter-before-shading,
+ *                                                filtering-after-shading
+ *   FRS on the separable B-spline .............. Sec. 4.1, eq. bicubic-bspline-texfilt
+ *   tent and cubic B-spline kernels ............ Suppl. S.2, eq. cubic-bspline
+ *   stochastic lerp / bilerp ................... Suppl. S.1
+ *   stochastic MIP level selection ............. Sec. 4.2.1
+ *   transmittance in a density grid ............ Sec. 5 (offline rendering)
+ *
+ * Readings where the paper is silent (the GPU side follows the same ones):
+ *   - raster coordinates put texel centres at integers: p = u*N - 0.5;
+ *   - uniforms are 24-bit: u = (w >> 8) * 2^-24, so u lies in [0, 1);
+ *   - the running-sum thresholds of the cubic B-spline are evaluated in the
+ *     factored forms below (algebraically equal to the kernel of S.2);
+ *   - ties advance: the pick is the number of thresholds C_k with u >= C_k;
+ *   - the random stream is the 4-D PCG hash "pcg4d" of Jarzynski and Olano,
+ *     "Hash Functions for GPU Rendering" (JCGT 9(3), 2020), keyed on
+ *     (query, sample, step, seed);
+ *   - 2-D textures repeat or clamp; 3-D grids read zero outside.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_EXPORT __attribute__((visibility("default")))
+
+enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2 };
+enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2 };
+enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3 };
+enum { WRAP_REPEAT = 0, WRAP_CLAMP = 1 };
+enum { MIP_NONE = 0, MIP_NEAREST = 1, MIP_LINEAR = 2 };
+
+static const double PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------------ */
+/* Random stream: pcg4d, from its published definition (JCGT 2020).         */
+/* An LCG step on every word, a cross-multiplying mix, a 16-bit xorshift and */
+/* a second cross-multiplying mix.  All arithmetic is modulo 2^32.           */
+/* ------------------------------------------------------------------------ */
+ORC_EXPORT void orc_pcg4d(const uint32_t in[4], uint32_t out[4])
+{
+    uint32_t x = in[0] * 1664525u + 1013904223u;
+    uint32_t y = in[1] * 1664525u + 1013904223u;
+    uint32_t z = in[2] * 1664525u + 1013904223u;
+    uint32_t w = in[3] * 1664525u + 1013904223u;
+    x += y * w;
+    y += z * x;
+    z += x * y;
+    w += y * z;
+    x ^= x >> 16;
+    y ^= y >> 16;
+    z ^= z >> 16;
+    w ^= w >> 16;
+    x += y * w;
+    y += z * x;
+    z += x * y;
+    w += y * z;
+    out[0] = x;
+    out[1] = y;
+    out[2] = z;
+    out[3] = w;
+}
+
+ORC_EXPORT void orc_pcg4d_batch(const uint32_t *in, uint32_t *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        orc_pcg4d(in + 4 * i, out + 4 * i);
+}
+
+/* 24-bit uniform in [0,1): exactly representable in binary32. */
+static float uniform24(uint32_t w)
+{
+    return (float)(w >> 8) * 0x1p-24f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Filter kernels (Suppl. S.2), binary64 closed forms.                      */
+/* ------------------------------------------------------------------------ */
+ORC_EXPORT double orc_kbs(double x)
+{
+    double a = fabs(x);
+    if (a <= 1.0)
+        return (4.0 - 3.0 * a * a * (2.0 - a)) / 6.0;
+    if (a <= 2.0)
+        return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+    return 0.0;
+}
+
+ORC_EXPORT double orc_ktent(double x)
+{
+    double a = fabs(x);
+    return a < 1.0 ? 1.0 - a : 0.0;
+}
+
+/* Taps and binary64 weights of one axis.  The lookup point sits at fraction
+ * t past texel i0; the cubic B-spline touches i0-1..i0+2 (Sec. 4.1), the tent
+ * i0..i0+1 and the box the nearest texel. Returns the tap count. */
+static int axis_weights(int filter, double t, int *first_off, double w[4])
+{
+    if (filter == F_BSPLINE3) {
+        *first_off = -1;
+        for (int k = 0; k < 4; ++k)
+            w[k] = orc_kbs(t - (double)(k - 1));
+        return 4;
+    }
+    if (filter == F_LINEAR) {
+        *first_off = 0;
+        w[0] = orc_ktent(t);
+        w[1] = orc_ktent(t - 1.0);
+        return 2;
+    }
+    /* nearest (box, S.2 K0): the texel whose cell contains the point */
+    *first_off = (t >= 0.5) ? 1 : 0;
+    w[0] = 1.0;
+    return 1;
+}
+
+ORC_EXPORT void orc_axis_weights64(int filter, double t, double w[4])
+{
+    int off;
+    w[0] = w[1] = w[2] = w[3] = 0.0;
+    axis_weights(filter, t, &off, w);
+}
+
+/* Running-sum thresholds of the axis weights in binary32: the pick is the
+ * first tap j with u < C_j (Sec. 2.2 "Sampling arrays"; the weights already
+ * sum to one).  Returns the number of thresholds (taps - 1).
+ * Cubic B-spline, s = 1 - t:
+ *   C0 = w0          = ((s*s)*s) * (1/6)
+ *   C1 = w0 + w1,  w1 = 2/3 - t^2 (1 - t/2)   (one fused op per product below)
+ *   C2 = 1 - w3,   w3 = ((t*t)*t) * (1/6)
+ * Tent: C0 = 1 - t. */
+ORC_EXPORT int orc_thresholds(int filter, float t, float C[3])
+{
+    if (filter == F_BSPLINE3) {
+        const float k6 = 1.0f / 6.0f, k23 = 2.0f / 3.0f;
+        float s = 1.0f - t;
+        float w0 = ((s * s) * s) * k6;
+        float t2 = t * t;
+        float half = fmaf(-0.5f, t, 1.0f);
+        float w1 = fmaf(-t2, half, k23);
+        float w3 = (t2 * t) * k6;
+        C[0] = w0;
+        C[1] = w0 + w1;
+        C[2] = 1.0f - w3;
+        return 3;
+    }
+    if (filter == F_LINEAR) {
+        C[0] = 1.0f - t;
+        return 1;
+    }
+    return 0;
+}
+
+/* Sampling an array of unnormalised weights (Sec. 2.2 "Sampling arrays"):
+ * the first j whose normalised running sum exceeds xi.  binary64. */
+ORC_EXPORT int orc_sample_array(const double *w, int n, double xi)
+{
+    double total = 0.0, run = 0.0;
+    for (int i = 0; i < n; ++i)
+        total += w[i];
+    for (int j = 0; j < n; ++j) {
+        run += w[j];
+        if (xi < run / total)
+            return j;
+    }
+    return n - 1;
+}
+
+/* Index of the picked tap among the filter's taps (0..3), ties advance. */
+ORC_EXPORT int orc_pick(int filter, float t, float u)
+{
+    float C[3];
+    int nc = orc_thresholds(filter, t, C);
+    if (nc == 0)
+        return t >= 0.5f ? 1 : 0; /* nearest: offset from i0 */
+    int j = 0;
+    for (int k = 0; k < nc; ++k)
+        if (u >= C[k])
+            ++j;
+    return j;
+}
+
+/* Uniform sample reuse (Sec. 2.2 eq. uniform-sample-reuse) generalised to
+ * the bin [lo, hi) that the pick fell into: u' = (u - lo) / (hi - lo). */
+ORC_EXPORT float orc_reuse(int filter, float t, float u, int j)
+{
+    float C[3];
+    int nc = orc_thresholds(filter, t, C);
+    if (nc == 0)
+        return u;
+    float lo = (j == 0) ? 0.0f : C[j - 1];
+    float hi = (j == nc) ? 1.0f : C[j];
+    float r = (u - lo) / (hi - lo);
+    const float top = 0x1.fffffep-1f;
+    return r > top ? top : r;
+}
+
+/* Exact probability that a 24-bit uniform selects tap j: the uniforms are
+ * k*2^-24, k = 0..2^24-1, and u >= C  <=>  k >= ceil(C*2^24). */
+ORC_EXPORT void orc_pick_pmf(int filter, float t, double P[4])
+{
+    float C[3];
+    int nc = orc_thresholds(filter, t, C);
+    P[0] = P[1] = P[2] = P[3] = 0.0;
+    if (nc == 0) {
+        P[0] = 1.0;
+        return;
+    }
+    double prev = 0.0;
+    for (int j = 0; j <= nc; ++j) {
+        double c = (j == nc) ? 16777216.0 : ceil((double)C[j] * 16777216.0);
+        if (c < 0.0)
+            c = 0.0;
+        if (c > 16777216.0)
+            c = 16777216.0;
+        P[j] = (c - prev) / 16777216.0;
+        if (c > prev)
+            prev = c;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scalar formats                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* IEEE 754 binary16 -> binary64, from the format definition. */
+ORC_EXPORT double orc_half_to_double(uint16_t h)
+{
+    int sign = (h >> 15) & 1;
+    int e = (h >> 10) & 0x1f;
+    int m = h & 0x3ff;
+    double v;
+    if (e == 0)
+        v = ldexp((double)m, -24);
+    else if (e == 31)
+        v = m ? NAN : INFINITY;
+    else
+        v = ldexp((double)(m | 0x400), e - 25);
+    return sign ? -v : v;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shading: GGX microfacet specular + Lambert diffuse, times the cosine      */
+/* (the paper's f-hat is BSDF x cosine, Sec. 3), under one directional light. */
+/* p[16]: n[3], wo[3], wi[3], radiance[3], f0, r_bias, r_scale, unused.       */
+/* The texel supplies albedo (RGB) and a roughness parameter A; the          */
+/* perceptual roughness r = r_bias + r_scale*A, alpha = r^2.                 */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+ORC_EXPORT void orc_shade_ggx(const double *p, const double rgba[4], double out[3])
+{
+    const double *n = p, *wo = p + 3, *wi = p + 6, *rad = p + 9;
+    double f0 = p[12], rb = p[13], rs = p[14];
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    double hl = sqrt(dot3(h, h));
+    h[0] /= hl;
+    h[1] /= hl;
+    h[2] /= hl;
+    double nh = dot3(n, h), no = dot3(n, wo), ni = dot3(n, wi), ih = dot3(wi, h);
+    double r = rb + rs * rgba[3];
+    double a = r * r, a2 = a * a;
+    double dd = nh * nh * (a2 - 1.0) + 1.0;
+    double D = a2 / (PI * dd * dd);
+    double G1o = 2.0 * no / (no + sqrt(a2 + (1.0 - a2) * no * no));
+    double G1i = 2.0 * ni / (ni + sqrt(a2 + (1.0 - a2) * ni * ni));
+    double F = f0 + (1.0 - f0) * pow(1.0 - ih, 5.0);
+    double spec = D * G1o * G1i * F / (4.0 * no * ni);
+    for (int c = 0; c < 3; ++c)
+        out[c] = rad[c] * (rgba[c] / PI + spec) * ni;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2-D textures                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const uint8_t *base;
+    int w, h, levels, fmt, wrap, mip;
+    const int64_t *off;
+} tex2d;
+
+static int lvl_dim(int n, int l)
+{
+    int d = n >> l;
+    return d < 1 ? 1 : d;
+}
+
+static void fetch2d(const tex2d *t, int l, int x, int y, double out[4])
+{
+    int wl = lvl_dim(t->w, l);
+    int64_t idx = (int64_t)y * wl + x;
+    const uint8_t *lv = t->base + t->off[l];
+    if (t->fmt == FMT_RGBA32F) {
+        const float *f = (const float *)lv + 4 * idx;
+        for (int c = 0; c < 4; ++c)
+            out[c] = (double)f[c];
+    } else {
+        const uint8_t *b = lv + 4 * idx;
+        for (int c = 0; c < 4; ++c)
+            out[c] = (double)b[c] / 255.0;
+    }
+}
+
+static float wrap_coord(int wrap, float u)
+{
+    if (wrap == WRAP_REPEAT)
+        return u - floorf(u);
+    return fminf(fmaxf(u, 0.0f), 1.0f);
+}
+
+static int wrap_tap(int wrap, int i, int n)
+{
+    if (wrap == WRAP_REPEAT) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+/* Raster position of coordinate u on an axis of n texels (centres at
+ * integers): p = u*n - 0.5 as one fused operation; i0 = floor(p), t = p - i0. */
+static void raster(float u, int n, int *i0, float *t)
+{
+    float p = fmaf(u, (float)n, -0.5f);
+    float f = floorf(p);
+    *i0 = (int)f;
+    *t = p - f;
+}
+
+/* MIP level(s) and their weights from the level of detail lambda
+ * (Sec. 2.1 pyramids; the stochastic single-level choice of Sec. 4.2.1). */
+static void levels_of(const tex2d *t, float lam, int *l0, int *l1, float *f)
+{
+    if (t->mip == MIP_NONE) {
+        *l0 = *l1 = 0;
+        *f = 0.0f;
+        return;
+    }
+    float lc = fminf(fmaxf(lam, 0.0f), (float)(t->levels - 1));
+    float fl = floorf(lc);
+    float fr = lc - fl;
+    int a = (int)fl;
+    if (t->mip == MIP_NEAREST) {
+        a += (fr >= 0.5f) ? 1 : 0;
+        if (a > t->levels - 1)
+            a = t->levels - 1;
+        *l0 = *l1 = a;
+        *f = 0.0f;
+        return;
+    }
+    *l0 = a;
+    *l1 = a + 1 <= t->levels - 1 ? a + 1 : t->levels - 1;
+    *f = fr;
+}
+
+static void shade2d(int shade, const double *ggx, const double rgba[4], double *out)
+{
+    if (shade == 1)
+        orc_shade_ggx(ggx, rgba, out);
+    else
+        for (int c = 0; c < 4; ++c)
+            out[c] = rgba[c];
+}
+
+static int query_finite(const tex2d *t, const float *q)
+{
+    if (!isfinite(q[0]) || !isfinite(q[1]))
+        return 0;
+    if (t->mip != MIP_NONE && !isfinite(q[2]))
+        return 0;
+    return 1;
+}
+
+/* One query of the 2-D filter.  out has 4 (shade none) or 3 (GGX) channels. */
+static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter, int mode, int spp,
+                         uint32_t seed, int variant, int shade, const double *ggx, double *out,
+                         int32_t *taps)
+{
+    int ch = shade == 1 ? 3 : 4;
+    if (!query_finite(t, q)) {
+        for (int c = 0; c < ch; ++c)
+            out[c] = NAN;
+        if (taps && mode == M_STOCH)
+            for (int s = 0; s < spp; ++s)
+                taps[3 * s] = taps[3 * s + 1] = taps[3 * s + 2] = INT32_MIN;
+        return;
+    }
+    float uu = wrap_coord(t->wrap, q[0]);
+    float vv = wrap_coord(t->wrap, q[1]);
+    int l0, l1;
+    float f;
+    levels_of(t, q[2], &l0, &l1, &f);
+
+    if (mode == M_STOCH) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int s = 0; s < spp; ++s) {
+            uint32_t key[4] = {(uint32_t)qi, (uint32_t)s, 0u, seed}, w[4];
+            orc_pcg4d(key, w);
+            float ux = uniform24(w[0]), uy = uniform24(w[1]), ul = uniform24(w[3]);
+            /* level: stochastic choice between l0 and l1 with P(l1) = f */
+            int l = (ul >= 1.0f - f) ? l1 : l0;
+            int wl = lvl_dim(t->w, l), hl = lvl_dim(t->h, l);
+            int ix, iy;
+            float tx, ty;
+            raster(uu, wl, &ix, &tx);
+            raster(vv, hl, &iy, &ty);
+            int offx = filter == F_BSPLINE3 ? -1 : 0;
+            int jx = orc_pick(filter, tx, ux);
+            if (variant == 1)
+                uy = orc_reuse(filter, tx, ux, jx);
+            int jy = orc_pick(filter, ty, uy);
+            int x = wrap_tap(t->wrap, ix + offx + jx, wl);
+            int y = wrap_tap(t->wrap, iy + offx + jy, hl);
+            if (taps) {
+                taps[3 * s] = l;
+                taps[3 * s + 1] = x;
+                taps[3 * s + 2] = y;
+            }
+            double texel[4], v[4];
+            fetch2d(t, l, x, y, texel);
+            shade2d(shade, ggx, texel, v);
+            for (int c = 0; c < ch; ++c)
+                acc[c] += v[c];
+        }
+        for (int c = 0; c < ch; ++c)
+            out[c] = acc[c] / (double)spp;
+        return;
+    }
+
+    /* deterministic: before = shade(sum w*texel), after = sum w*shade(texel) */
+    double sum[4] = {0, 0, 0, 0};
+    int lv[2] = {l0, l1};
+    double pl[2] = {1.0 - (double)f, (double)f};
+    for (int li = 0; li < 2; ++li) {
+        if (pl[li] == 0.0)
+            continue;
+        int l = lv[li];
+        int wl = lvl_dim(t->w, l), hl = lvl_dim(t->h, l);
+        int ix, iy;
+        float tx, ty;
+        raster(uu, wl, &ix, &tx);
+        raster(vv, hl, &iy, &ty);
+        double wx[4], wy[4];
+        int ox, oy;
+        int nx = axis_weights(filter, (double)tx, &ox, wx);
+        int ny = axis_weights(filter, (double)ty, &oy, wy);
+        for (int b = 0; b < ny; ++b)
+            for (int a = 0; a < nx; ++a) {
+                double wgt = pl[li] * wx[a] * wy[b];
+                double texel[4], v[4];
+                fetch2d(t, l, wrap_tap(t->wrap, ix + ox + a, wl), wrap_tap(t->wrap, iy + oy + b, hl), texel);
+                if (mode == M_BEFORE) {
+                    for (int c = 0; c < 4; ++c)
+                        sum[c] += wgt * texel[c];
+                } else {
+                    shade2d(shade, ggx, texel, v);
+                    for (int c = 0; c < ch; ++c)
+                        sum[c] += wgt * v[c];
+                }
+            }
+    }
+    if (mode == M_BEFORE)
+        shade2d(shade, ggx, sum, out);
+    else
+        for (int c = 0; c < ch; ++c)
+            out[c] = sum[c];
+}
+
+ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
+                            const int64_t *level_off, const float *q, int64_t n, int filter, int mode,
+                            int spp, uint32_t seed, int variant, int shade, const double *ggx,
+                            double *out, int32_t *taps)
+{
+    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off};
+    int ch = shade == 1 ? 3 : 4;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i)
+        filter2d_one(&t, q + 3 * i, i, filter, mode, spp, seed, variant, shade, ggx, out + ch * i,
+                     taps ? taps + (int64_t)3 * spp * i : NULL);
+    return 0;
+}
+
+/* Exact expectation of the stochastic estimator with independent 24-bit
+ * uniforms per axis and level: sum over every (level, tap x, tap y) of the
+ * exact pick probabilities times the shaded texel. */
+ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
+                                   const int64_t *level_off, const float *q, int64_t n, int filter,
+                                   int shade, const double *ggx, double *out)
+{
+    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off};
+    int ch = shade == 1 ? 3 : 4;
+    for (int64_t i = 0; i < n; ++i) {
+        const float *qq = q + 3 * i;
+        double *o = out + ch * i;
+        float uu = wrap_coord(t.wrap, qq[0]), vv = wrap_coord(t.wrap, qq[1]);
+        int l0, l1;
+        float f;
+        levels_of(&t, qq[2], &l0, &l1, &f);
+        /* level probability: P(u >= 1-f) over the 24-bit lattice */
+        double c = ceil((double)(1.0f - f) * 16777216.0);
+        double p1 = (16777216.0 - c) / 16777216.0;
+        double pl[2] = {1.0 - p1, p1};
+        int lv[2] = {l0, l1};
+        for (int c2 = 0; c2 < ch; ++c2)
+            o[c2] = 0.0;
+        for (int li = 0; li < 2; ++li) {
+            if (pl[li] == 0.0)
+                continue;
+            int l = lv[li];
+            int wl = lvl_dim(t.w, l), hl = lvl_dim(t.h, l);
+            int ix, iy;
+            float tx, ty;
+            raster(uu, wl, &ix, &tx);
+            raster(vv, hl, &iy, &ty);
+            double Px[4], Py[4];
+            orc_pick_pmf(filter, tx, Px);
+            orc_pick_pmf(filter, ty, Py);
+            int off = filter == F_BSPLINE3 ? -1 : 0;
+            int ntap = filter == F_BSPLINE3 ? 4 : (filter == F_LINEAR ? 2 : 1);
+            int nearx = filter == F_NEAREST ? (tx >= 0.5f) : 0;
+            int neary = filter == F_NEAREST ? (ty >= 0.5f) : 0;
+            for (int b = 0; b < ntap; ++b)
+                for (int a = 0; a < ntap; ++a) {
+                    double pr = pl[li] * Px[a] * Py[b];
+                    if (pr == 0.0)
+                        continue;
+                    double texel[4], v[4];
+                    fetch2d(&t, l, wrap_tap(t.wrap, ix + off + a + nearx, wl),
+                            wrap_tap(t.wrap, iy + off + b + neary, hl), texel);
+                    shade2d(shade, ggx, texel, v);
+                    for (int c2 = 0; c2 < ch; ++c2)
+                        o[c2] += pr * v[c2];
+                }
+        }
+    }
+    return 0;
+}
+
+/* Distribution of (jx, jy) under the reuse variant, by running every one of
+ * the 2^24 uniforms through the pick-and-remap chain.  counts[16]. */
+ORC_EXPORT void orc_reuse_histogram2(int filter, float tx, float ty, int64_t counts[16])
+{
+    memset(counts, 0, 16 * sizeof(int64_t));
+    for (uint32_t k = 0; k < (1u << 24); ++k) {
+        float u = (float)k * 0x1p-24f;
+        int jx = orc_pick(filter, tx, u);
+        float u2 = orc_reuse(filter, tx, u, jx);
+        int jy = orc_pick(filter, ty, u2);
+        counts[jy * 4 + jx]++;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3-D grids                                                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const uint8_t *base;
+    int nx, ny, nz, fmt;
+    float wmin[3], scale[3];
+} grid3d;
+
+static double fetch3d(const grid3d *g, int x, int y, int z)
+{
+    if (x < 0 || y < 0 || z < 0 || x >= g->nx || y >= g->ny || z >= g->nz)
+        return 0.0; /* empty space outside the grid */
+    int64_t idx = ((int64_t)z * g->ny + y) * g->nx + x;
+    if (g->fmt == FMT_R16F)
+        return orc_half_to_double(((const uint16_t *)g->base)[idx]);
+    return (double)((const float *)g->base)[idx];
+}
+
+static double shade3d(int shade, double sigma, double ds)
+{
+    return shade == 1 ? exp(-sigma * ds) : sigma;
+}
+
+/* Three axis picks from the sample's uniforms; variant 1 reuses one. */
+static void pick3(int filter, const float t[3], const uint32_t w[4], int variant, int j[3])
+{
+    float u = uniform24(w[0]);
+    for (int a = 0; a < 3; ++a) {
+        if (variant == 0)
+            u = uniform24(w[a]);
+        j[a] = orc_pick(filter, t[a], u);
+        if (variant == 1)
+            u = orc_reuse(filter, t[a], u, j[a]);
+    }
+}
+
+static int pos_finite(const float *x)
+{
+    return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
+}
+
+ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
+                            const float *scale, const float *pos, int64_t n, int filter, int mode,
+                            int spp, uint32_t seed, int variant, int shade, float ds, double *out,
+                            int32_t *taps)
+{
+    grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
+    int dims[3] = {nx, ny, nz};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *x = pos + 3 * i;
+        int32_t *tp = taps ? taps + (int64_t)3 * spp * i : NULL;
+        int ok = pos_finite(x);
+        float p[3], t[3];
+        int i0[3];
+        for (int a = 0; a < 3 && ok; ++a) {
+            p[a] = fmaf(x[a] - g.wmin[a], g.scale[a], -0.5f);
+            if (!(fabsf(p[a]) <= 4194304.0f))
+                ok = 0;
+        }
+        if (!ok) {
+            out[i] = NAN;
+            if (tp && mode == M_STOCH)
+                for (int k = 0; k < 3 * spp; ++k)
+                    tp[k] = INT32_MIN;
+            continue;
+        }
+        (void)dims;
+        for (int a = 0; a < 3; ++a) {
+            float fl = floorf(p[a]);
+            i0[a] = (int)fl;
+            t[a] = p[a] - fl;
+        }
+        int off = filter == F_BSPLINE3 ? -1 : 0;
+        if (mode == M_STOCH) {
+            double acc = 0.0;
+            for (int s = 0; s < spp; ++s) {
+                uint32_t key[4] = {(uint32_t)i, (uint32_t)s, 0u, seed}, w[4];
+                orc_pcg4d(key, w);
+                int j[3];
+                pick3(filter, t, w, variant, j);
+                int tx = i0[0] + off + j[0], ty = i0[1] + off + j[1], tz = i0[2] + off + j[2];
+                if (tp) {
+                    tp[3 * s] = tx;
+                    tp[3 * s + 1] = ty;
+                    tp[3 * s + 2] = tz;
+                }
+                acc += shade3d(shade, fetch3d(&g, tx, ty, tz), (double)ds);
+            }
+            out[i] = acc / (double)spp;
+        } else {
+            double w[3][4];
+            int o[3], nt[3];
+            for (int a = 0; a < 3; ++a)
+                nt[a] = axis_weights(filter, (double)t[a], &o[a], w[a]);
+            double sum = 0.0;
+            for (int c = 0; c < nt[2]; ++c)
+                for (int b = 0; b < nt[1]; ++b)
+                    for (int a = 0; a < nt[0]; ++a) {
+                        double wgt = w[0][a] * w[1][b] * w[2][c];
+                        double sg = fetch3d(&g, i0[0] + o[0] + a, i0[1] + o[1] + b, i0[2] + o[2] + c);
+                        sum += wgt * (mode == M_BEFORE ? sg : shade3d(shade, sg, (double)ds));
+                    }
+            out[i] = mode == M_BEFORE ? shade3d(shade, sum, (double)ds) : sum;
+        }
+    }
+    return 0;
+}
+
+/* Ray-step raster positions (binary32 contract).  For a ray (o, d, t0, t1)
+ * and S steps: dt = (t1 - t0)/S, the raster origin A = (o - wmin)*scale - 0.5
+ * (fused), direction B = d*scale, entry E = t0*B + A (fused), step G = dt*B,
+ * and the midpoint of step k is p_k = (k + 1/2)*G + E (fused). */
+typedef struct {
+    float E[3], G[3], dt;
+    int ok, empty;
+} ray_setup;
+
+static ray_setup setup_ray(const grid3d *g, const float *r, int steps)
+{
+    ray_setup rs;
+    memset(&rs, 0, sizeof rs);
+    rs.ok = 1;
+    for (int k = 0; k < 8; ++k)
+        if (!isfinite(r[k]))
+            rs.ok = 0;
+    if (!rs.ok)
+        return rs;
+    if (!(r[7] > r[6])) {
+        rs.empty = 1;
+        return rs;
+    }
+    rs.dt = (r[7] - r[6]) / (float)steps;
+    for (int a = 0; a < 3; ++a) {
+        float A = fmaf(r[a] - g->wmin[a], g->scale[a], -0.5f);
+        float B = r[3 + a] * g->scale[a];
+        rs.E[a] = fmaf(r[6], B, A);
+        rs.G[a] = rs.dt * B;
+        float pa = fmaf(0.5f, rs.G[a], rs.E[a]);
+        float pb = fmaf((float)(steps - 1) + 0.5f, rs.G[a], rs.E[a]);
+        if (!(fabsf(pa) <= 4194304.0f) || !(fabsf(pb) <= 4194304.0f))
+            rs.ok = 0;
+    }
+    return rs;
+}
+
+static void step_pos(const ray_setup *rs, int k, int i0[3], float t[3])
+{
+    float kh = (float)k + 0.5f;
+    for (int a = 0; a < 3; ++a) {
+        float p = fmaf(kh, rs->G[a], rs->E[a]);
+        float fl = floorf(p);
+        i0[a] = (int)fl;
+        t[a] = p - fl;
+    }
+}
+
+static double raymarch_one(const grid3d *g, const float *r, int64_t ri, int steps, int filter, int mode,
+                           int spp, uint32_t seed, int variant, int32_t *tp)
+{
+    ray_setup rs = setup_ray(g, r, steps);
+    if (!rs.ok || rs.empty) {
+        if (tp && mode == M_STOCH)
+            for (int64_t k = 0; k < (int64_t)3 * spp * steps; ++k)
+                tp[k] = INT32_MIN;
+        return rs.ok ? 1.0 : NAN;
+    }
+    double dt = (double)rs.dt;
+    int off = filter == F_BSPLINE3 ? -1 : 0;
+    if (mode == M_STOCH) {
+        /* one texel per step and sample; per-sample transmittance
+         * exp(-dt * sum of the picked densities), averaged over samples */
+        double Tsum = 0.0;
+        for (int s = 0; s < spp; ++s) {
+            double tau = 0.0;
+            for (int k = 0; k < steps; ++k) {
+                int i0[3], j[3];
+                float t[3];
+                step_pos(&rs, k, i0, t);
+                uint32_t key[4] = {(uint32_t)ri, (uint32_t)s, (uint32_t)k, seed}, w[4];
+                orc_pcg4d(key, w);
+                pick3(filter, t, w, variant, j);
+                int x = i0[0] + off + j[0], y = i0[1] + off + j[1], z = i0[2] + off + j[2];
+                if (tp) {
+                    int32_t *q = tp + ((int64_t)s * steps + k) * 3;
+                    q[0] = x;
+                    q[1] = y;
+                    q[2] = z;
+                }
+                tau += fetch3d(g, x, y, z);
+            }
+            Tsum += exp(-dt * tau);
+        }
+        return Tsum / (double)spp;
+    }
+    /* deterministic: before = exp(-dt * sum_k sum_i w_i sigma_i);
+     * after = prod_k sum_i w_i exp(-dt sigma_i) */
+    double tau = 0.0, T = 1.0;
+    for (int k = 0; k < steps; ++k) {
+        int i0[3], o[3], nt[3];
+        float t[3];
+        double w[3][4];
+        step_pos(&rs, k, i0, t);
+        for (int a = 0; a < 3; ++a)
+            nt[a] = axis_weights(filter, (double)t[a], &o[a], w[a]);
+        double sum = 0.0;
+        for (int c = 0; c < nt[2]; ++c)
+            for (int b = 0; b < nt[1]; ++b)
+                for (int a = 0; a < nt[0]; ++a) {
+                    double wgt = w[0][a] * w[1][b] * w[2][c];
+                    double sg = fetch3d(g, i0[0] + o[0] + a, i0[1] + o[1] + b, i0[2] + o[2] + c);
+                    sum += wgt * (mode == M_BEFORE ? sg : exp(-dt * sg));
+                }
+        if (mode == M_BEFORE)
+            tau += sum;
+        else
+            T *= sum;
+    }
+    return mode == M_BEFORE ? exp(-dt * tau) : T;
+}
+
+/* rays: n x {ox,oy,oz,dx,dy,dz,t0,t1}.  If subset is non-null only the nsub
+ * listed rays are computed (T and taps are then indexed by position in the
+ * subset, the RNG key still by the ray's own index). */
+ORC_EXPORT int orc_raymarch(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
+                            const float *scale, const float *rays, int64_t n, int steps, int filter,
+                            int mode, int spp, uint32_t seed, int variant, double *T, int32_t *taps,
+                            const int64_t *subset, int64_t nsub)
+{
+    grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
+    int64_t m = subset ? nsub : n;
+    int64_t per = (int64_t)3 * spp * steps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t ri = subset ? subset[i] : i;
+        T[i] = raymarch_one(&g, rays + 8 * ri, ri, steps, filter, mode, spp, seed, variant,
+                            taps ? taps + per * i : NULL);
+    }
+    return 0;
+}
+
+/* Exact expectation of the stochastic transmittance with independent
+ * uniforms: picks at different steps are independent, so
+ * E[T] = prod_k sum_{taps} P(tap) exp(-dt sigma_tap), with the exact 24-bit
+ * pick probabilities. */
+ORC_EXPORT int orc_raymarch_expect(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
+                                   const float *scale, const float *rays, int64_t n, int steps,
+                                   int filter, double *T)
+{
+    grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        ray_setup rs = setup_ray(&g, rays + 8 * i, steps);
+        if (!rs.ok || rs.empty) {
+            T[i] = rs.ok ? 1.0 : NAN;
+            continue;
+        }
+        double dt = (double)rs.dt, prod = 1.0;
+        int off = filter == F_BSPLINE3 ? -1 : 0;
+        int ntap = filter == F_BSPLINE3 ? 4 : (filter == F_LINEAR ? 2 : 1);
+        for (int k = 0; k < steps; ++k) {
+            int i0[3];
+            float t[3];
+            double P[3][4];
+            step_pos(&rs, k, i0, t);
+            int near[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a) {
+                orc_pick_pmf(filter, t[a], P[a]);
+                if (filter == F_NEAREST)
+                    near[a] = t[a] >= 0.5f;
+            }
+            double e = 0.0;
+            for (int c = 0; c < ntap; ++c)
+                for (int b = 0; b < ntap; ++b)
+                    for (int a = 0; a < ntap; ++a) {
+                        double pr = P[0][a] * P[1][b] * P[2][c];
+                        if (pr == 0.0)
+                            continue;
+                        double sg = fetch3d(&g, i0[0] + off + a + near[0], i0[1] + off + b + near[1],
+                                            i0[2] + off + c + near[2]);
+                        e += pr * exp(-dt * sg);
+                    }
+            prod *= e;
+        }
+        T[i] = prod;
+    }
+    return 0;
+}
+
+ORC_EXPORT int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
