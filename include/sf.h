@@ -1,0 +1,215 @@
+/*
+ * sf.h — C ABI of libsf, stochastic texture filtering with filtering after
+ * shading on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Pharr, Wronski, Salvi, Fajardo, "Filtering After Shading With
+ * Stochastic Texture Filtering" (2024).  For each query the library builds
+ * the separable filter weights, picks ONE texel per sample by inverse CDF on
+ * those weights (Sec. 2.2 "Sampling arrays", eq. stochastic-sum; Sec. 4.1
+ * FRS), shades that texel and averages: an unbiased estimate of filtering
+ * after shading (Sec. 3, eq. filtering-after-shading).  The deterministic
+ * filter-before-shading (eq. filter-before-shading) and exact
+ * filter-after-shading sums run beside it.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer (HBM of the current HIP
+ *    device); descriptor structs are HOST structs whose pointer members are
+ *    device pointers.  The caller owns all memory; the library allocates
+ *    nothing and keeps no state besides the thread-local error string.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously; results are valid after the stream
+ *    is synchronised.  No call synchronises on its own.
+ *  - Arguments are validated on the host BEFORE anything is enqueued.  On an
+ *    error nothing is enqueued and the status names the class; sf_last_error()
+ *    gives the message.  n == 0 is a no-op returning SF_OK.
+ *  - Coordinates are raster coordinates with texel centres at integers: a
+ *    texture coordinate u in [0,1) maps to p = u*N - 0.5 (one fused
+ *    multiply-add in binary32); the lookup point sits at fraction
+ *    t = p - floor(p) past texel i0 = floor(p).
+ *  - Random numbers: SF_RNG_VERSION 1 = the 4-D PCG hash of Jarzynski and
+ *    Olano (JCGT 2020) on the key (query index, sample index, step index,
+ *    seed); each 32-bit output word w gives the uniform (w >> 8) * 2^-24.
+ *    Words 0,1,2 drive the x,y,z tap picks, word 3 the MIP level pick.
+ *  - Picks: per axis, the tap index j = #{k : u >= C_k} over the running sums
+ *    C_k of the axis weights, evaluated in binary32 in a fixed operation
+ *    order (the "decision contract"), so that the integer decisions match an
+ *    IEEE-binary32 reference bit for bit.
+ *  - Queries with a non-finite coordinate give NaN and the sentinel tap
+ *    SF_TAP_NONE.
+ */
+#ifndef SF_H
+#define SF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SF_ABI_VERSION 1
+#define SF_RNG_VERSION 1
+#define SF_TAP_NONE INT32_MIN
+#define SF_MAX_LEVELS 16
+#define SF_MAX_STEPS 65536
+#define SF_MAX_SPP 65536
+
+typedef int32_t sf_status;
+enum {
+    SF_OK = 0,
+    SF_E_NULL = 1,        /* a required pointer is NULL                       */
+    SF_E_RANGE = 2,       /* a size / count / enum value is out of range      */
+    SF_E_UNSUPPORTED = 3, /* a valid but unsupported combination              */
+    SF_E_DEVICE = 4,      /* the HIP runtime reported an error while enqueuing */
+    SF_E_WORKSPACE = 5    /* workspace missing or too small                   */
+};
+
+/* Separable reconstruction filter per axis (Suppl. S.2): box K0 (nearest),
+ * tent K1 (bi/trilinear), cubic B-spline K_bs (bi/tricubic, eq. cubic-bspline). */
+enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2 };
+/* SF_BEFORE: shade(sum_i w_i t_i)            (eq. filter-before-shading)
+ * SF_AFTER_EXACT: sum_i w_i shade(t_i)        (eq. filtering-after-shading)
+ * SF_STOCHASTIC: mean over spp of shade(t_j), P(j) = w_j (eq. stochastic-sum) */
+enum { SF_BEFORE = 0, SF_AFTER_EXACT = 1, SF_STOCHASTIC = 2 };
+enum { SF_RGBA32F = 0, SF_RGBA8_UNORM = 1, SF_R16F = 2, SF_R32F = 3 };
+enum { SF_WRAP_REPEAT = 0, SF_WRAP_CLAMP = 1 };
+/* MIP level use (Sec. 2.1 pyramids; single stochastic level, Sec. 4.2.1):
+ * NONE = level 0 only; NEAREST = level round(lambda); LINEAR = levels
+ * floor(lambda) and floor(lambda)+1 with weights (1-f, f), f = frac(lambda)
+ * (a stochastic mode picks ONE of them with those probabilities). */
+enum { SF_MIP_NONE = 0, SF_MIP_NEAREST = 1, SF_MIP_LINEAR = 2 };
+enum { SF_SHADE_NONE = 0, SF_SHADE_GGX = 1 };             /* 2-D */
+enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1 }; /* 3-D points */
+
+typedef struct sf_sampling {
+    int32_t filter;      /* SF_NEAREST | SF_LINEAR | SF_BSPLINE3                     */
+    int32_t mode;        /* SF_BEFORE | SF_AFTER_EXACT | SF_STOCHASTIC                */
+    int32_t spp;         /* samples per query, 1..SF_MAX_SPP (deterministic: ignored) */
+    uint32_t seed;       /* fourth word of the hash key                              */
+    int32_t rng_variant; /* 0: one uniform per axis; 1: one uniform for all spatial
+                            axes, re-derived after each pick by uniform sample reuse
+                            (Sec. 2.2 eq. uniform-sample-reuse): u' = (u-lo)/(hi-lo)
+                            over the picked bin [lo, hi), clamped to 1 - 2^-24      */
+} sf_sampling;
+
+/* A 2-D texture with an optional MIP pyramid.  Level l has
+ * max(1, width >> l) x max(1, height >> l) texels, row-major, 4 channels,
+ * at base + level_offset[l] (bytes).  RGBA8_UNORM channels decode as c/255.
+ * Channels are (albedo R, G, B, roughness parameter A) when shaded. */
+typedef struct sf_tex2d {
+    const void *base;
+    int32_t width, height, levels; /* levels in 1..SF_MAX_LEVELS                 */
+    int32_t format;                /* SF_RGBA32F | SF_RGBA8_UNORM                 */
+    int32_t wrap;                  /* SF_WRAP_REPEAT | SF_WRAP_CLAMP              */
+    int32_t mip;                   /* SF_MIP_NONE | SF_MIP_NEAREST | SF_MIP_LINEAR */
+    int64_t level_offset[SF_MAX_LEVELS];
+} sf_tex2d;
+
+/* GGX microfacet specular + Lambert diffuse times the cosine (the paper's
+ * BSDF-times-cosine f-hat, Sec. 3) for one directional light of `radiance`.
+ * Unit vectors n, wo, wi with n.wo > 0 and n.wi > 0.  The texel's A channel
+ * gives roughness r = r_bias + r_scale*A, alpha = r^2; D is the GGX normal
+ * distribution, G the separable Smith term, F Schlick's with f0. */
+typedef struct sf_ggx {
+    float n[3], wo[3], wi[3], radiance[3];
+    float f0, r_bias, r_scale;
+} sf_ggx;
+
+/* A dense 3-D grid of scalar density (x fastest, then y, then z) occupying
+ * the world box from wmin; scale = voxels per world unit per axis.  World
+ * point x maps to raster p = (x - wmin)*scale - 0.5 (subtract, then one fused
+ * multiply-add).  Taps outside the grid read zero (empty space). */
+typedef struct sf_volume {
+    const void *base;
+    int32_t nx, ny, nz;
+    int32_t format; /* SF_R16F | SF_R32F */
+    float wmin[3], scale[3];
+} sf_volume;
+
+/*
+ * sf_filter2d — filtered (and optionally shaded) lookups in a 2-D texture.
+ *   queries : n x {u, v, lambda} float32; lambda = level of detail (ignored
+ *             with SF_MIP_NONE), clamped to [0, levels-1].
+ *   shade   : SF_SHADE_NONE -> out is n x 4 float32 (filtered RGBA);
+ *             SF_SHADE_GGX  -> out is n x 3 float32 (RGB radiance); ggx required.
+ *   dbg_taps: NULL, or n x spp x {level, x, y} int32 (stochastic mode only):
+ *             the texel each sample read, after wrapping.
+ * Defines: Sec. 2.2 eqs. filtered-texture and stochastic-sum; Sec. 3 eqs.
+ * filter-before-shading and filtering-after-shading; Sec. 4.1 eq.
+ * bicubic-bspline-texfilt; Suppl. S.1 stochastic bilerp; MIP level pick of
+ * Sec. 4.2.1.
+ * Errors: SF_E_NULL (tex, base, queries, out, smp, or ggx when shading);
+ *         SF_E_RANGE (n < 0 or n > 2^31-1, bad enum, spp outside 1..SF_MAX_SPP,
+ *         size <= 0, levels outside 1..SF_MAX_LEVELS or beyond the pyramid);
+ *         SF_E_DEVICE (launch failure).
+ */
+sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,
+                      int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps, void *stream);
+
+/*
+ * sf_filter3d — filtered point lookups in a density grid.
+ *   pos     : n x {x, y, z} float32 world positions.
+ *   shade   : SF_SHADE_DENSITY -> out[i] = filtered sigma;
+ *             SF_SHADE_TRANSMITTANCE -> out[i] = filtered exp(-sigma*ds).
+ *   out     : n float32.
+ *   dbg_taps: NULL, or n x spp x {x, y, z} int32 raw tap indices (before the
+ *             zero-outside rule), stochastic mode only.
+ * Points whose raster coordinate exceeds 2^22 in magnitude give NaN.
+ * Defines: Sec. 4.1 (n-dimensional FRS, 4^n lookups -> 1); Sec. 5 offline
+ * rendering (density lookups).
+ * Errors: as sf_filter2d.
+ */
+sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const sf_sampling *smp,
+                      int32_t shade, float ds, float *out, int32_t *dbg_taps, void *stream);
+
+/*
+ * sf_raymarch — transmittance along rays through a density grid by fixed-step
+ * ray marching, filtering the density at every step.
+ *   rays : n x {ox, oy, oz, dx, dy, dz, t0, t1} float32, d of unit length,
+ *          [t0, t1] the segment to march (already clipped to the grid box by
+ *          the caller; t1 <= t0 means an empty segment, T = 1).
+ *   steps: S in 1..SF_MAX_STEPS.  dt = (t1 - t0)/S; the raster position of
+ *          step k is p_k = (k + 1/2)*G + E per axis with E = t0*B + A and
+ *          G = dt*B (fused multiply-adds), A = (o - wmin)*scale - 0.5 and
+ *          B = d*scale.
+ *   T    : n float32.  SF_STOCHASTIC: mean over spp of exp(-dt * sum_k sigma_k)
+ *          with ONE picked voxel per step (sum accumulated in float64);
+ *          SF_BEFORE: exp(-dt * sum_k sum_i w_i sigma_i);
+ *          SF_AFTER_EXACT: prod_k sum_i w_i exp(-dt*sigma_i).
+ *   dbg_taps: NULL, or n x spp x S x {x, y, z} int32 (stochastic only).
+ * Rays with a non-finite component, or whose raster positions exceed 2^22 in
+ * magnitude, give NaN.
+ * Defines: Sec. 5 "Offline rendering" (density lookups of a volumetric path
+ * tracer with trilinear / tricubic and stochastic variants); Sec. 4.1 FRS;
+ * the transmittance is the shading nonlinearity exp(-sigma*dt) filtered after
+ * shading (Sec. 3).
+ * Errors: as sf_filter2d, plus SF_E_RANGE for steps outside 1..SF_MAX_STEPS.
+ */
+sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_t steps,
+                      const sf_sampling *smp, float *T, int32_t *dbg_taps, void *stream);
+
+/*
+ * sf_error_stats — error statistics of an estimate against a reference,
+ * reduced in float64 on the GPU in a fixed order (bit-reproducible).
+ *   est: n*ch float32; ref: n*ch float64; out: 8 float64 (device):
+ *   {sum err^2, sum err, max |err|, max |err|/|ref| (ref != 0), count,
+ *    sum ref^2, count of non-finite est, unused}, err = est - ref, taken over
+ *   the finite entries.
+ *   workspace: device scratch of sf_error_stats_workspace(n*ch) bytes.
+ * Defines: the MSE measure of Sec. 5 (offline rendering).
+ * Errors: SF_E_NULL, SF_E_RANGE (n < 0, ch < 1), SF_E_WORKSPACE.
+ */
+sf_status sf_error_stats(const float *est, const double *ref, int64_t n, int32_t ch, double *out,
+                         void *workspace, size_t workspace_bytes, void *stream);
+size_t sf_error_stats_workspace(int64_t count);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *sf_last_error(void);
+int32_t sf_abi_version(void);
+int32_t sf_rng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SF_H */

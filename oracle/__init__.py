@@ -65,11 +65,11 @@ def lib():
         L.orc_pcg4d_batch.argtypes = [P, P, i64]
         L.orc_shade_ggx.argtypes = [P, P, P]
         L.orc_filter2d.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, i32, i32, u32,
-                                   i32, i32, P, P, P]
+                                   i32, i32, P, P, P, P, i64]
         L.orc_filter2d_expect.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, i32, P, P]
         L.orc_reuse_histogram2.argtypes = [i32, f32, f32, P]
         L.orc_filter3d.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, u32, i32,
-                                   i32, f32, P, P]
+                                   i32, f32, P, P, P, i64]
         L.orc_raymarch.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, i32, u32, i32,
                                    P, P, P, i64]
         L.orc_raymarch_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
@@ -186,15 +186,20 @@ class Tex2D:
 
 
 def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed: int = 0,
-             variant: int = 0, shade: int = 0, ggx=None, taps: bool = False):
+             variant: int = 0, shade: int = 0, ggx=None, taps: bool = False, subset=None):
+    """Filter every query, or only the rows listed in ``subset`` (their own
+    index keys the random stream)."""
     q = _c(q, np.float32).reshape(-1, 3)
     n = q.shape[0]
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
     ch = 3 if shade == 1 else 4
-    out = np.zeros((n, ch))
-    tp = np.zeros((n, spp, 3), dtype=np.int32) if taps else None
+    out = np.zeros((m, ch))
+    tp = np.zeros((m, spp, 3), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_filter2d(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
-                       _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, shade, _p(g), _p(out), _p(tp))
+                       _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, shade, _p(g), _p(out), _p(tp),
+                       _p(sub), 0 if sub is None else sub.size)
     return (out, tp) if taps else out
 
 
@@ -227,13 +232,16 @@ class Grid:
 
 
 def filter3d(g: Grid, pos: np.ndarray, filt: int, mode: int, spp: int = 1, seed: int = 0, variant: int = 0,
-             shade: int = 0, ds: float = 1.0, taps: bool = False):
+             shade: int = 0, ds: float = 1.0, taps: bool = False, subset=None):
     pos = _c(pos, np.float32).reshape(-1, 3)
     n = pos.shape[0]
-    out = np.zeros(n)
-    tp = np.zeros((n, spp, 3), dtype=np.int32) if taps else None
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
+    out = np.zeros(m)
+    tp = np.zeros((m, spp, 3), dtype=np.int32) if taps else None
     lib().orc_filter3d(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(pos), n, filt, mode,
-                       spp, seed & 0xFFFFFFFF, variant, shade, float(ds), _p(out), _p(tp))
+                       spp, seed & 0xFFFFFFFF, variant, shade, float(ds), _p(out), _p(tp), _p(sub),
+                       0 if sub is None else sub.size)
     return (out, tp) if taps else out
 
 

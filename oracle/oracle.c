@@ -495,17 +495,23 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
             out[c] = sum[c];
 }
 
+/* queries: n x {u, v, lambda}.  If subset is non-null only the nsub listed
+ * queries are computed (out and taps indexed by position in the subset, the
+ * random key by the query's own index). */
 ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
                             const int64_t *level_off, const float *q, int64_t n, int filter, int mode,
                             int spp, uint32_t seed, int variant, int shade, const double *ggx,
-                            double *out, int32_t *taps)
+                            double *out, int32_t *taps, const int64_t *subset, int64_t nsub)
 {
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off};
     int ch = shade == 1 ? 3 : 4;
+    int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i)
-        filter2d_one(&t, q + 3 * i, i, filter, mode, spp, seed, variant, shade, ggx, out + ch * i,
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t qi = subset ? subset[i] : i;
+        filter2d_one(&t, q + 3 * qi, qi, filter, mode, spp, seed, variant, shade, ggx, out + ch * i,
                      taps ? taps + (int64_t)3 * spp * i : NULL);
+    }
     return 0;
 }
 
@@ -624,14 +630,15 @@ static int pos_finite(const float *x)
 ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
                             const float *scale, const float *pos, int64_t n, int filter, int mode,
                             int spp, uint32_t seed, int variant, int shade, float ds, double *out,
-                            int32_t *taps)
+                            int32_t *taps, const int64_t *subset, int64_t nsub)
 {
     grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
-    int dims[3] = {nx, ny, nz};
+    int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t ii = 0; ii < m; ++ii) {
+        int64_t i = subset ? subset[ii] : ii;
         const float *x = pos + 3 * i;
-        int32_t *tp = taps ? taps + (int64_t)3 * spp * i : NULL;
+        int32_t *tp = taps ? taps + (int64_t)3 * spp * ii : NULL;
         int ok = pos_finite(x);
         float p[3], t[3];
         int i0[3];
@@ -641,13 +648,12 @@ ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, c
                 ok = 0;
         }
         if (!ok) {
-            out[i] = NAN;
+            out[ii] = NAN;
             if (tp && mode == M_STOCH)
                 for (int k = 0; k < 3 * spp; ++k)
                     tp[k] = INT32_MIN;
             continue;
         }
-        (void)dims;
         for (int a = 0; a < 3; ++a) {
             float fl = floorf(p[a]);
             i0[a] = (int)fl;
@@ -669,7 +675,7 @@ ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, c
                 }
                 acc += shade3d(shade, fetch3d(&g, tx, ty, tz), (double)ds);
             }
-            out[i] = acc / (double)spp;
+            out[ii] = acc / (double)spp;
         } else {
             double w[3][4];
             int o[3], nt[3];
@@ -683,7 +689,7 @@ ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, c
                         double sg = fetch3d(&g, i0[0] + o[0] + a, i0[1] + o[1] + b, i0[2] + o[2] + c);
                         sum += wgt * (mode == M_BEFORE ? sg : shade3d(shade, sg, (double)ds));
                     }
-            out[i] = mode == M_BEFORE ? shade3d(shade, sum, (double)ds) : sum;
+            out[ii] = mode == M_BEFORE ? shade3d(shade, sum, (double)ds) : sum;
         }
     }
     return 0;

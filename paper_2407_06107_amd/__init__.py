@@ -1,0 +1,265 @@
+"""Python binding of libsf (stochastic texture filtering on MI355X).
+
+Thin ctypes marshalling over the C ABI declared in ``include/sf.h``: every
+function here has the name of the C entry point it calls, checks tensor
+dtype / device / contiguity, builds the descriptor structs and passes device
+pointers plus the current HIP stream.  All computation runs in the HIP
+kernels of ``libsf.so``; there is no fallback path, and importing a function
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsf.so")
+
+# enums (values fixed by include/sf.h)
+SF_OK, SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED, SF_E_DEVICE, SF_E_WORKSPACE = range(6)
+SF_NEAREST, SF_LINEAR, SF_BSPLINE3 = 0, 1, 2
+SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC = 0, 1, 2
+SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F = 0, 1, 2, 3
+SF_WRAP_REPEAT, SF_WRAP_CLAMP = 0, 1
+SF_MIP_NONE, SF_MIP_NEAREST, SF_MIP_LINEAR = 0, 1, 2
+SF_SHADE_NONE, SF_SHADE_GGX = 0, 1
+SF_SHADE_DENSITY, SF_SHADE_TRANSMITTANCE = 0, 1
+SF_TAP_NONE = -(2 ** 31)
+SF_MAX_LEVELS = 16
+
+EXPORTED = ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_error_stats", "sf_error_stats_workspace",
+            "sf_last_error", "sf_abi_version", "sf_rng_version")
+
+
+class sf_sampling(C.Structure):
+    _fields_ = [("filter", C.c_int32), ("mode", C.c_int32), ("spp", C.c_int32), ("seed", C.c_uint32),
+                ("rng_variant", C.c_int32)]
+
+
+class sf_tex2d(C.Structure):
+    _fields_ = [("base", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32), ("levels", C.c_int32),
+                ("format", C.c_int32), ("wrap", C.c_int32), ("mip", C.c_int32),
+                ("level_offset", C.c_int64 * SF_MAX_LEVELS)]
+
+
+class sf_ggx(C.Structure):
+    _fields_ = [("n", C.c_float * 3), ("wo", C.c_float * 3), ("wi", C.c_float * 3), ("radiance", C.c_float * 3),
+                ("f0", C.c_float), ("r_bias", C.c_float), ("r_scale", C.c_float)]
+
+
+class sf_volume(C.Structure):
+    _fields_ = [("base", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("format", C.c_int32), ("wmin", C.c_float * 3), ("scale", C.c_float * 3)]
+
+
+class SFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libsf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libsf.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2407_06107_amd.build.build() "
+                              "(hipcc, gfx950).  There is no CPU fallback.")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.sf_filter2d.argtypes = [P, P, i64, P, i32, P, P, P, P]
+        L.sf_filter3d.argtypes = [P, P, i64, P, i32, C.c_float, P, P, P]
+        L.sf_raymarch.argtypes = [P, P, i64, i32, P, P, P, P]
+        L.sf_error_stats.argtypes = [P, P, i64, i32, P, P, C.c_size_t, P]
+        L.sf_error_stats_workspace.argtypes = [i64]
+        L.sf_error_stats_workspace.restype = C.c_size_t
+        for f in ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_error_stats"):
+            getattr(L, f).restype = i32
+        L.sf_last_error.restype = C.c_char_p
+        L.sf_abi_version.restype = i32
+        L.sf_rng_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def sf_last_error() -> str:
+    return lib().sf_last_error().decode()
+
+
+def sf_abi_version() -> int:
+    return int(lib().sf_abi_version())
+
+
+def sf_rng_version() -> int:
+    return int(lib().sf_rng_version())
+
+
+def _check(status: int):
+    if status != SF_OK:
+        raise SFError(status, sf_last_error())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def sampling(filter: int, mode: int, spp: int = 1, seed: int = 0, rng_variant: int = 0) -> sf_sampling:
+    return sf_sampling(filter, mode, spp, seed & 0xFFFFFFFF, rng_variant)
+
+
+def ggx(n=(0.0, 0.0, 1.0), wo=(0.2, 0.3, 1.0), wi=(-0.4, 0.1, 1.0), radiance=(1.0, 1.0, 1.0), f0=0.04,
+        r_bias=0.05, r_scale=0.95) -> sf_ggx:
+    """GGX + Lambert parameters; direction vectors are normalised here."""
+    import math
+
+    def nrm(v):
+        ln = math.sqrt(sum(x * x for x in v))
+        return (C.c_float * 3)(*[x / ln for x in v])
+    return sf_ggx(nrm(n), nrm(wo), nrm(wi), (C.c_float * 3)(*radiance), f0, r_bias, r_scale)
+
+
+class Texture2D:
+    """A device texture: one byte buffer holding every level plus its
+    descriptor.  ``levels`` is a list of [h, w, 4] arrays (float32 or uint8)."""
+
+    def __init__(self, levels, wrap: int = SF_WRAP_REPEAT, mip: int = SF_MIP_NONE, device="cuda"):
+        import numpy as np
+        levels = [np.ascontiguousarray(lv) for lv in levels]
+        dt = levels[0].dtype
+        if dt == np.float32:
+            fmt, align = SF_RGBA32F, 16
+        elif dt == np.uint8:
+            fmt, align = SF_RGBA8_UNORM, 4
+        else:
+            raise TypeError("levels must be float32 or uint8 RGBA arrays")
+        offs, cur = [], 0
+        for lv in levels:
+            offs.append(cur)
+            cur += (lv.nbytes + 255) // 256 * 256
+        buf = np.zeros(cur, dtype=np.uint8)
+        for lv, o in zip(levels, offs):
+            buf[o:o + lv.nbytes] = np.frombuffer(lv.tobytes(), dtype=np.uint8)
+        self.buffer = torch.from_numpy(buf).to(device)
+        self.offsets = offs
+        self.desc = sf_tex2d()
+        self.desc.base = self.buffer.data_ptr()
+        self.desc.width, self.desc.height = levels[0].shape[1], levels[0].shape[0]
+        self.desc.levels = len(levels)
+        self.desc.format = fmt
+        self.desc.wrap = wrap
+        self.desc.mip = mip
+        for i, o in enumerate(offs):
+            self.desc.level_offset[i] = o
+        del align
+
+
+class Volume:
+    """A device density grid [nz, ny, nx] (float16 or float32) over the world
+    box starting at ``wmin`` with ``scale`` voxels per unit."""
+
+    def __init__(self, data: torch.Tensor, wmin=(0.0, 0.0, 0.0), scale=None, side: float = 1.0):
+        if data.dtype not in (torch.float16, torch.float32):
+            raise TypeError("volume must be float16 or float32")
+        if not data.is_cuda or not data.is_contiguous() or data.dim() != 3:
+            raise ValueError("volume must be a contiguous 3-D device tensor")
+        self.data = data
+        nz, ny, nx = data.shape
+        if scale is None:
+            scale = (nx / side, ny / side, nz / side)
+        self.desc = sf_volume(data.data_ptr(), nx, ny, nz, SF_R16F if data.dtype == torch.float16 else SF_R32F,
+                              (C.c_float * 3)(*wmin), (C.c_float * 3)(*scale))
+
+
+def sf_filter2d(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, shade: int = SF_SHADE_NONE,
+                ggx_params: sf_ggx | None = None, out: torch.Tensor | None = None,
+                dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    _need(queries, torch.float32, "queries")
+    n = queries.numel() // 3
+    ch = 3 if shade == SF_SHADE_GGX else 4
+    if out is None:
+        out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
+    _need(out, torch.float32, "out")
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps")
+        if dbg_taps.numel() < n * smp.spp * 3:
+            raise ValueError("dbg_taps too small")
+    g = C.byref(ggx_params) if ggx_params is not None else None
+    _check(lib().sf_filter2d(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), shade, g, _ptr(out),
+                             _ptr(dbg_taps), _stream(stream)))
+    return out
+
+
+def sf_filter3d(vol: Volume, pos: torch.Tensor, smp: sf_sampling, shade: int = SF_SHADE_DENSITY, ds: float = 1.0,
+                out: torch.Tensor | None = None, dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    _need(pos, torch.float32, "pos")
+    n = pos.numel() // 3
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=pos.device)
+    _need(out, torch.float32, "out")
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps")
+        if dbg_taps.numel() < n * smp.spp * 3:
+            raise ValueError("dbg_taps too small")
+    _check(lib().sf_filter3d(C.byref(vol.desc), _ptr(pos), n, C.byref(smp), shade, ds, _ptr(out), _ptr(dbg_taps),
+                             _stream(stream)))
+    return out
+
+
+def sf_raymarch(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling, T: torch.Tensor | None = None,
+                dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    _need(rays, torch.float32, "rays")
+    n = rays.numel() // 8
+    if T is None:
+        T = torch.empty(n, dtype=torch.float32, device=rays.device)
+    _need(T, torch.float32, "T")
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps")
+        if dbg_taps.numel() < n * smp.spp * steps * 3:
+            raise ValueError("dbg_taps too small")
+    _check(lib().sf_raymarch(C.byref(vol.desc), _ptr(rays), n, steps, C.byref(smp), _ptr(T), _ptr(dbg_taps),
+                             _stream(stream)))
+    return T
+
+
+def sf_error_stats_workspace(count: int) -> int:
+    return int(lib().sf_error_stats_workspace(count))
+
+
+def sf_error_stats(est: torch.Tensor, ref: torch.Tensor, out: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Returns 8 float64 on the device: sum e^2, sum e, max|e|, max rel, count,
+    sum ref^2, non-finite count, 0."""
+    _need(est, torch.float32, "est")
+    _need(ref, torch.float64, "ref")
+    if est.numel() != ref.numel():
+        raise ValueError("est and ref differ in size")
+    count = est.numel()
+    if out is None:
+        out = torch.zeros(8, dtype=torch.float64, device=est.device)
+    if workspace is None:
+        workspace = torch.empty(max(1, sf_error_stats_workspace(count)), dtype=torch.uint8, device=est.device)
+    _check(lib().sf_error_stats(_ptr(est), _ptr(ref), count, 1, _ptr(out), _ptr(workspace), workspace.numel(),
+                                _stream(stream)))
+    return out

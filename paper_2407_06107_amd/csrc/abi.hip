@@ -1,0 +1,302 @@
+// C ABI of libsf: argument validation on the host, derivation of per-call
+// constants, and dispatch to the kernel launchers.  Nothing is enqueued
+// unless every argument is valid.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "sf_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sf_status fail(sf_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+sf_status ok()
+{
+    g_err[0] = '\0';
+    return SF_OK;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+sf_status check_sampling(const sf_sampling *smp)
+{
+    if (!smp)
+        return fail(SF_E_NULL, "sampling descriptor is NULL");
+    if (smp->filter < SF_NEAREST || smp->filter > SF_BSPLINE3)
+        return fail(SF_E_RANGE, "filter %d out of range", smp->filter);
+    if (smp->mode < SF_BEFORE || smp->mode > SF_STOCHASTIC)
+        return fail(SF_E_RANGE, "mode %d out of range", smp->mode);
+    if (smp->spp < 1 || smp->spp > SF_MAX_SPP)
+        return fail(SF_E_RANGE, "spp %d outside 1..%d", smp->spp, SF_MAX_SPP);
+    if (smp->rng_variant != 0 && smp->rng_variant != 1)
+        return fail(SF_E_RANGE, "rng_variant %d must be 0 or 1", smp->rng_variant);
+    return SF_OK;
+}
+
+sf_status check_n(int64_t n)
+{
+    if (n < 0)
+        return fail(SF_E_RANGE, "n = %lld is negative", (long long)n);
+    if (n > 0x7fffffffLL)
+        return fail(SF_E_RANGE, "n = %lld exceeds 2^31-1 (the hash key holds a 32-bit query index)", (long long)n);
+    return SF_OK;
+}
+
+sf_status check_volume(const sf_volume *v, sfk::VolArgs &a)
+{
+    if (!v)
+        return fail(SF_E_NULL, "volume descriptor is NULL");
+    if (!v->base)
+        return fail(SF_E_NULL, "volume base pointer is NULL");
+    if (v->format != SF_R16F && v->format != SF_R32F)
+        return fail(SF_E_UNSUPPORTED, "volume format %d unsupported (R16F or R32F)", v->format);
+    if (v->nx < 1 || v->ny < 1 || v->nz < 1 || v->nx > 4096 || v->ny > 4096 || v->nz > 4096)
+        return fail(SF_E_RANGE, "grid %d x %d x %d outside 1..4096 per axis", v->nx, v->ny, v->nz);
+    const size_t esz = v->format == SF_R16F ? 2 : 4;
+    const uint64_t bytes = (uint64_t)v->nx * v->ny * v->nz * esz;
+    if (bytes > 0x7fffffffULL || (uint64_t)v->ny * v->nz > (1ULL << 24))
+        return fail(SF_E_UNSUPPORTED, "grid of %llu bytes exceeds the 2 GiB addressing of one buffer",
+                    (unsigned long long)bytes);
+    if (!aligned(v->base, esz))
+        return fail(SF_E_RANGE, "volume base pointer misaligned");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(v->wmin[k]) || !std::isfinite(v->scale[k]) || v->scale[k] == 0.0f)
+            return fail(SF_E_RANGE, "volume wmin/scale must be finite, scale non-zero");
+    a.base = v->base;
+    a.nx = v->nx;
+    a.ny = v->ny;
+    a.nz = v->nz;
+    a.fmt = v->format;
+    a.bytes = (uint32_t)bytes;
+    for (int k = 0; k < 3; ++k) {
+        a.wmin[k] = v->wmin[k];
+        a.scale[k] = v->scale[k];
+    }
+    return SF_OK;
+}
+
+sf_status ggx_constants(const sf_ggx *g, sfk::GgxConst &c)
+{
+    double n[3], wo[3], wi[3];
+    for (int k = 0; k < 3; ++k) {
+        n[k] = g->n[k];
+        wo[k] = g->wo[k];
+        wi[k] = g->wi[k];
+    }
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    double hl = std::sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+    double no = n[0] * wo[0] + n[1] * wo[1] + n[2] * wo[2];
+    double ni = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
+    if (!(no > 0.0) || !(ni > 0.0) || !(hl > 0.0))
+        return fail(SF_E_RANGE, "GGX directions need n.wo > 0 and n.wi > 0");
+    for (int k = 0; k < 3; ++k)
+        h[k] /= hl;
+    double nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+    double ih = wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2];
+    double F = g->f0 + (1.0 - g->f0) * std::pow(1.0 - ih, 5.0);
+    const double pi = 3.14159265358979323846;
+    c.nh2 = (float)(nh * nh);
+    c.no = (float)no;
+    c.no2 = (float)(no * no);
+    c.ni = (float)ni;
+    c.ni2 = (float)(ni * ni);
+    c.spec_k = (float)(F / (4.0 * no * ni * pi));
+    for (int k = 0; k < 3; ++k) {
+        c.kd[k] = (float)(g->radiance[k] * ni / pi);
+        c.ks[k] = (float)(g->radiance[k] * ni);
+    }
+    c.r_bias = g->r_bias;
+    c.r_scale = g->r_scale;
+    return SF_OK;
+}
+
+sf_status device_status(hipError_t e)
+{
+    if (e != hipSuccess)
+        return fail(SF_E_DEVICE, "HIP error %d: %s", (int)e, hipGetErrorString(e));
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sf_last_error(void) { return g_err; }
+int32_t sf_abi_version(void) { return SF_ABI_VERSION; }
+int32_t sf_rng_version(void) { return SF_RNG_VERSION; }
+
+sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp, int32_t shade,
+                      const sf_ggx *ggx, float *out, int32_t *dbg_taps, void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (n == 0)
+        return ok();
+    if (!tex || !queries || !out)
+        return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    if (!tex->base)
+        return fail(SF_E_NULL, "texture base pointer is NULL");
+    if (tex->format != SF_RGBA32F && tex->format != SF_RGBA8_UNORM)
+        return fail(SF_E_UNSUPPORTED, "2-D texture format %d unsupported (RGBA32F or RGBA8_UNORM)", tex->format);
+    if (tex->width < 1 || tex->height < 1 || tex->width > 65536 || tex->height > 65536)
+        return fail(SF_E_RANGE, "texture size %d x %d outside 1..65536", tex->width, tex->height);
+    int maxlv = 1;
+    while (((tex->width > tex->height ? tex->width : tex->height) >> maxlv) >= 1)
+        ++maxlv;
+    if (tex->levels < 1 || tex->levels > SF_MAX_LEVELS || tex->levels > maxlv)
+        return fail(SF_E_RANGE, "levels %d outside 1..%d", tex->levels, maxlv < SF_MAX_LEVELS ? maxlv : SF_MAX_LEVELS);
+    if (tex->wrap != SF_WRAP_REPEAT && tex->wrap != SF_WRAP_CLAMP)
+        return fail(SF_E_RANGE, "wrap %d out of range", tex->wrap);
+    if (tex->mip < SF_MIP_NONE || tex->mip > SF_MIP_LINEAR)
+        return fail(SF_E_RANGE, "mip %d out of range", tex->mip);
+    const size_t esz = tex->format == SF_RGBA32F ? 16 : 4;
+    for (int l = 0; l < tex->levels; ++l)
+        if (tex->level_offset[l] < 0 || !aligned((const uint8_t *)tex->base + tex->level_offset[l], esz))
+            return fail(SF_E_RANGE, "level %d offset negative or misaligned", l);
+    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
+        return fail(SF_E_RANGE, "shade %d out of range", shade);
+    if (!aligned(queries, 4) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))
+        return fail(SF_E_RANGE, "queries or out misaligned");
+    sfk::Filter2DCall c{};
+    if (shade == SF_SHADE_GGX) {
+        if (!ggx)
+            return fail(SF_E_NULL, "GGX shading needs ggx parameters");
+        if ((st = ggx_constants(ggx, c.g)) != SF_OK)
+            return st;
+    }
+    c.tex.base = (const uint8_t *)tex->base;
+    c.tex.w = tex->width;
+    c.tex.h = tex->height;
+    c.tex.levels = tex->levels;
+    c.tex.fmt = tex->format;
+    c.tex.wrap = tex->wrap;
+    c.tex.mip = tex->mip;
+    for (int l = 0; l < SF_MAX_LEVELS; ++l)
+        c.tex.off[l] = l < tex->levels ? tex->level_offset[l] : 0;
+    c.q = queries;
+    c.n = n;
+    c.filter = smp->filter;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.variant = smp->rng_variant;
+    c.seed = smp->seed;
+    c.shade = shade;
+    c.out = out;
+    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    return device_status(sfk::launch_filter2d(c, (hipStream_t)stream));
+}
+
+sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const sf_sampling *smp, int32_t shade,
+                      float ds, float *out, int32_t *dbg_taps, void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (n == 0)
+        return ok();
+    if (!pos || !out)
+        return fail(SF_E_NULL, "pos and out must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    sfk::Filter3DCall c{};
+    if ((st = check_volume(vol, c.vol)) != SF_OK)
+        return st;
+    if (shade != SF_SHADE_DENSITY && shade != SF_SHADE_TRANSMITTANCE)
+        return fail(SF_E_RANGE, "shade %d out of range", shade);
+    if (!std::isfinite(ds))
+        return fail(SF_E_RANGE, "ds must be finite");
+    if (!aligned(pos, 4) || !aligned(out, 4))
+        return fail(SF_E_RANGE, "pos or out misaligned");
+    c.pos = pos;
+    c.n = n;
+    c.filter = smp->filter;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.variant = smp->rng_variant;
+    c.seed = smp->seed;
+    c.shade = shade;
+    c.ds = ds;
+    c.out = out;
+    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    return device_status(sfk::launch_filter3d(c, (hipStream_t)stream));
+}
+
+sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_t steps, const sf_sampling *smp,
+                      float *T, int32_t *dbg_taps, void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (steps < 1 || steps > SF_MAX_STEPS)
+        return fail(SF_E_RANGE, "steps %d outside 1..%d", steps, SF_MAX_STEPS);
+    if (n == 0)
+        return ok();
+    if (!rays || !T)
+        return fail(SF_E_NULL, "rays and T must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    sfk::RaymarchCall c{};
+    if ((st = check_volume(vol, c.vol)) != SF_OK)
+        return st;
+    if (!aligned(rays, 16) || !aligned(T, 4))
+        return fail(SF_E_RANGE, "rays must be 16-byte aligned, T 4-byte aligned");
+    c.rays = rays;
+    c.n = n;
+    c.steps = steps;
+    c.filter = smp->filter;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.variant = smp->rng_variant;
+    c.seed = smp->seed;
+    c.T = T;
+    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    return device_status(sfk::launch_raymarch(c, (hipStream_t)stream));
+}
+
+static int32_t err_blocks(int64_t count)
+{
+    int64_t b = (count + 1023) / 1024;
+    return (int32_t)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+size_t sf_error_stats_workspace(int64_t count)
+{
+    if (count < 0)
+        count = 0;
+    return (size_t)err_blocks(count) * 8 * sizeof(double);
+}
+
+sf_status sf_error_stats(const float *est, const double *ref, int64_t n, int32_t ch, double *out, void *workspace,
+                         size_t workspace_bytes, void *stream)
+{
+    if (n < 0 || ch < 1)
+        return fail(SF_E_RANGE, "n must be >= 0 and ch >= 1");
+    if (!out)
+        return fail(SF_E_NULL, "out must be non-NULL");
+    const int64_t count = n * (int64_t)ch;
+    if (count > 0 && (!est || !ref))
+        return fail(SF_E_NULL, "est and ref must be non-NULL");
+    const size_t need = sf_error_stats_workspace(count);
+    if (!workspace || workspace_bytes < need)
+        return fail(SF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? workspace_bytes : 0);
+    if (!aligned(out, 8) || !aligned(workspace, 8) || (ref && !aligned(ref, 8)) || (est && !aligned(est, 4)))
+        return fail(SF_E_RANGE, "misaligned pointer");
+    return device_status(
+        sfk::launch_error_stats(est, ref, count, ch, out, (double *)workspace, err_blocks(count), (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,288 @@
+// 2-D path of libsf: filtered, shaded texture lookups.
+//
+// Stochastic mode (Sec. 2.2 eq. stochastic-sum, Sec. 4.1 FRS): each sample
+// picks one MIP level (Sec. 4.2.1) and one texel per axis by inverse CDF and
+// shades that single texel; a query's samples are spread over a group of G
+// lanes (G a power of two dividing the wavefront) and summed with a
+// butterfly over those lanes.  Deterministic modes (Sec. 3,
+// eqs. filter-before-shading / filtering-after-shading) visit every tap.
+#include "sf_device.hpp"
+#include "sf_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sfk {
+
+__device__ __forceinline__ float wrap_coord(int wrap, float u)
+{
+    return wrap == SF_WRAP_REPEAT ? u - __builtin_floorf(u) : __builtin_fminf(__builtin_fmaxf(u, 0.0f), 1.0f);
+}
+
+// Taps lie in [-2, n+1]: one conditional add or subtract wraps them.
+__device__ __forceinline__ int wrap_tap(int wrap, int i, int n)
+{
+    if (wrap == SF_WRAP_REPEAT) {
+        int r = i < 0 ? i + n : (i >= n ? i - n : i);
+        return n == 1 ? 0 : r;
+    }
+    return min(max(i, 0), n - 1);
+}
+
+__device__ __forceinline__ void raster(float u, int n, int &i0, float &t)
+{
+    float p = __builtin_fmaf(u, (float)n, -0.5f);
+    float f = __builtin_floorf(p);
+    i0 = (int)f;
+    t = p - f;
+}
+
+__device__ __forceinline__ void levels_of(const Tex2DArgs &tx, float lam, int &l0, int &l1, float &f)
+{
+    if (tx.mip == SF_MIP_NONE) {
+        l0 = l1 = 0;
+        f = 0.0f;
+        return;
+    }
+    float lc = __builtin_fminf(__builtin_fmaxf(lam, 0.0f), (float)(tx.levels - 1));
+    float fl = __builtin_floorf(lc);
+    float fr = lc - fl;
+    int a = (int)fl;
+    if (tx.mip == SF_MIP_NEAREST) {
+        a += fr >= 0.5f;
+        a = min(a, tx.levels - 1);
+        l0 = l1 = a;
+        f = 0.0f;
+        return;
+    }
+    l0 = a;
+    l1 = min(a + 1, tx.levels - 1);
+    f = fr;
+}
+
+__device__ __forceinline__ float4 texel(const Tex2DArgs &tx, int l, int x, int y)
+{
+    int wl = max(1, tx.w >> l);
+    int64_t idx = (int64_t)y * wl + x;
+    const uint8_t *lv = tx.base + tx.off[l];
+    if (tx.fmt == SF_RGBA32F)
+        return reinterpret_cast<const float4 *>(lv)[idx];
+    uint32_t px = reinterpret_cast<const uint32_t *>(lv)[idx];
+    const float k = 1.0f / 255.0f;
+    return make_float4((float)(px & 0xffu) * k, (float)((px >> 8) & 0xffu) * k, (float)((px >> 16) & 0xffu) * k,
+                       (float)(px >> 24) * k);
+}
+
+// GGX + Lambert times the cosine, for the fixed directions folded into g.
+__device__ __forceinline__ float3 shade_ggx(const GgxConst &g, float4 c)
+{
+    float r = __builtin_fmaf(g.r_scale, c.w, g.r_bias);
+    float a = r * r;
+    float a2 = a * a;
+    float d = __builtin_fmaf(g.nh2, a2 - 1.0f, 1.0f);
+    float om = 1.0f - a2;
+    float go = (2.0f * g.no) / (g.no + __builtin_sqrtf(__builtin_fmaf(om, g.no2, a2)));
+    float gi = (2.0f * g.ni) / (g.ni + __builtin_sqrtf(__builtin_fmaf(om, g.ni2, a2)));
+    float spec = (a2 * go * gi * g.spec_k) / (d * d);
+    return make_float3(__builtin_fmaf(g.kd[0], c.x, g.ks[0] * spec), __builtin_fmaf(g.kd[1], c.y, g.ks[1] * spec),
+                       __builtin_fmaf(g.kd[2], c.z, g.ks[2] * spec));
+}
+
+template <int SHADE>
+__device__ __forceinline__ float4 shade(const GgxConst &g, float4 c)
+{
+    if constexpr (SHADE == SF_SHADE_GGX) {
+        float3 v = shade_ggx(g, c);
+        return make_float4(v.x, v.y, v.z, 0.0f);
+    } else {
+        return c;
+    }
+}
+
+template <int SHADE>
+__device__ __forceinline__ void store(float *out, int64_t q, float4 v)
+{
+    if constexpr (SHADE == SF_SHADE_GGX) {
+        out[3 * q] = v.x;
+        out[3 * q + 1] = v.y;
+        out[3 * q + 2] = v.z;
+    } else {
+        reinterpret_cast<float4 *>(out)[q] = v;
+    }
+}
+
+__device__ __forceinline__ bool query_ok(const Tex2DArgs &tx, float3 q)
+{
+    bool ok = __builtin_isfinite(q.x) & __builtin_isfinite(q.y);
+    return ok & (tx.mip == SF_MIP_NONE || __builtin_isfinite(q.z));
+}
+
+__device__ __forceinline__ float4 add4(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+
+template <int F, int SHADE, int VAR>
+__global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_g)
+{
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int G = 1 << log_g;
+    const int64_t q = gid >> log_g;
+    const int lane = (int)(gid & (G - 1));
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool active = q < c.n;
+    if (active) {
+        float3 qq = make_float3(c.q[3 * q], c.q[3 * q + 1], c.q[3 * q + 2]);
+        if (!query_ok(c.tex, qq)) {
+            float nan = __builtin_nanf("");
+            acc = make_float4(nan, nan, nan, nan);
+            if (c.taps)
+                for (int s = lane; s < c.spp; s += G) {
+                    int32_t *tp = c.taps + (q * c.spp + s) * 3;
+                    tp[0] = tp[1] = tp[2] = SF_TAP_NONE;
+                }
+        } else {
+            const float uu = wrap_coord(c.tex.wrap, qq.x), vv = wrap_coord(c.tex.wrap, qq.y);
+            int l0, l1;
+            float f;
+            levels_of(c.tex, qq.z, l0, l1, f);
+            const float cl = 1.0f - f;
+            for (int s = lane; s < c.spp; s += G) {
+                uint4 w = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
+                int l = u24(w.w) >= cl ? l1 : l0;
+                int wl = max(1, c.tex.w >> l), hl = max(1, c.tex.h >> l);
+                int ix, iy;
+                float tx, ty;
+                raster(uu, wl, ix, tx);
+                raster(vv, hl, iy, ty);
+                int ox, oy;
+                if constexpr (VAR == 0) {
+                    ox = pick_off<F>(tx, u24(w.x));
+                    oy = pick_off<F>(ty, u24(w.y));
+                } else {
+                    float u = u24(w.x);
+                    ox = pick_off_reuse<F>(tx, u);
+                    oy = pick_off_reuse<F>(ty, u);
+                }
+                int x = wrap_tap(c.tex.wrap, ix + ox, wl);
+                int y = wrap_tap(c.tex.wrap, iy + oy, hl);
+                if (c.taps) {
+                    int32_t *tp = c.taps + (q * c.spp + s) * 3;
+                    tp[0] = l;
+                    tp[1] = x;
+                    tp[2] = y;
+                }
+                acc = add4(acc, shade<SHADE>(c.g, texel(c.tex, l, x, y)));
+            }
+        }
+    }
+    for (int m = G >> 1; m >= 1; m >>= 1) {
+        acc.x += __shfl_xor(acc.x, m);
+        acc.y += __shfl_xor(acc.y, m);
+        acc.z += __shfl_xor(acc.z, m);
+        acc.w += __shfl_xor(acc.w, m);
+    }
+    if (active && lane == 0) {
+        const float inv = 1.0f / (float)c.spp;
+        store<SHADE>(c.out, q, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
+    }
+}
+
+template <int F, int SHADE, int MODE>
+__global__ __launch_bounds__(256) void k_filter2d_det(Filter2DCall c)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= c.n)
+        return;
+    float3 qq = make_float3(c.q[3 * q], c.q[3 * q + 1], c.q[3 * q + 2]);
+    if (!query_ok(c.tex, qq)) {
+        float nan = __builtin_nanf("");
+        store<SHADE>(c.out, q, make_float4(nan, nan, nan, nan));
+        return;
+    }
+    const float uu = wrap_coord(c.tex.wrap, qq.x), vv = wrap_coord(c.tex.wrap, qq.y);
+    int l0, l1;
+    float f;
+    levels_of(c.tex, qq.z, l0, l1, f);
+    constexpr int NT = Taps<F>::n;
+    constexpr int F0 = Taps<F>::first;
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int li = 0; li < 2; ++li) {
+        const float pl = li == 0 ? 1.0f - f : f;
+        if (pl == 0.0f)
+            continue;
+        const int l = li == 0 ? l0 : l1;
+        int wl = max(1, c.tex.w >> l), hl = max(1, c.tex.h >> l);
+        int ix, iy;
+        float tx, ty, wx[4], wy[4];
+        raster(uu, wl, ix, tx);
+        raster(vv, hl, iy, ty);
+        if constexpr (F == NEAREST) {
+            ix += tx >= 0.5f;
+            iy += ty >= 0.5f;
+        }
+        axis_weights<F>(tx, wx);
+        axis_weights<F>(ty, wy);
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            const int y = wrap_tap(c.tex.wrap, iy + F0 + b, hl);
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                const float wgt = pl * wx[a] * wy[b];
+                float4 t = texel(c.tex, l, wrap_tap(c.tex.wrap, ix + F0 + a, wl), y);
+                float4 v = MODE == BEFORE ? t : shade<SHADE>(c.g, t);
+                sum.x = __builtin_fmaf(wgt, v.x, sum.x);
+                sum.y = __builtin_fmaf(wgt, v.y, sum.y);
+                sum.z = __builtin_fmaf(wgt, v.z, sum.z);
+                sum.w = __builtin_fmaf(wgt, v.w, sum.w);
+            }
+        }
+    }
+    store<SHADE>(c.out, q, MODE == BEFORE ? shade<SHADE>(c.g, sum) : sum);
+}
+
+template <int F, int SHADE>
+static void launch_f2(const Filter2DCall &c, hipStream_t s)
+{
+    if (c.mode == STOCH) {
+        int G = 1;
+        while (G * 2 <= c.spp && G * 2 <= 64)
+            G *= 2;
+        int log_g = __builtin_ctz(G);
+        int64_t threads = c.n * G;
+        dim3 grid((uint32_t)((threads + 255) / 256)), block(256);
+        if (c.variant)
+            k_filter2d_stoch<F, SHADE, 1><<<grid, block, 0, s>>>(c, log_g);
+        else
+            k_filter2d_stoch<F, SHADE, 0><<<grid, block, 0, s>>>(c, log_g);
+    } else {
+        dim3 grid((uint32_t)((c.n + 255) / 256)), block(256);
+        if (c.mode == BEFORE)
+            k_filter2d_det<F, SHADE, BEFORE><<<grid, block, 0, s>>>(c);
+        else
+            k_filter2d_det<F, SHADE, AFTER><<<grid, block, 0, s>>>(c);
+    }
+}
+
+template <int F>
+static void launch_f1(const Filter2DCall &c, hipStream_t s)
+{
+    if (c.shade == SF_SHADE_GGX)
+        launch_f2<F, SF_SHADE_GGX>(c, s);
+    else
+        launch_f2<F, SF_SHADE_NONE>(c, s);
+}
+
+hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s)
+{
+    switch (c.filter) {
+    case NEAREST:
+        launch_f1<NEAREST>(c, s);
+        break;
+    case LINEAR:
+        launch_f1<LINEAR>(c, s);
+        break;
+    default:
+        launch_f1<BSPLINE3>(c, s);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sfk

@@ -1,0 +1,350 @@
+// 3-D paths of libsf: transmittance ray marching through a density grid
+// (Sec. 5 "Offline rendering": density lookups with trilinear / tricubic
+// filters and their stochastic one-lookup forms) and filtered point lookups.
+//
+// One lane marches one ray.  The stochastic kernel is the hot path: per step
+// it forms the raster position, hashes (ray, sample, step, seed), picks one
+// tap per axis by inverse CDF on the separable weights (Sec. 4.1 FRS) and
+// gathers ONE voxel; the optical depth is summed in float64, exactly, since
+// every binary16 density is a multiple of 2^-24.
+#include "sf_device.hpp"
+#include "sf_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sfk {
+
+constexpr uint32_t kBufferFlags = 0x00020000u;  // raw buffer, 32-bit data format
+
+struct RayGeom {
+    float E[3], G[3], dt;
+};
+
+// 0: march; 1: empty segment (T = 1); 2: invalid (T = NaN).
+__device__ __forceinline__ int ray_setup(const VolArgs &v, const float *r8, int steps, RayGeom &g)
+{
+    float4 a = *reinterpret_cast<const float4 *>(r8);
+    float4 b = *reinterpret_cast<const float4 *>(r8 + 4);
+    float r[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        fin &= __builtin_isfinite(r[k]);
+    if (!fin)
+        return 2;
+    if (!(r[7] > r[6]))
+        return 1;
+    g.dt = (r[7] - r[6]) / (float)steps;
+    bool ok = true;
+    const float last = (float)(steps - 1) + 0.5f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float A = __builtin_fmaf(r[k] - v.wmin[k], v.scale[k], -0.5f);
+        float B = r[3 + k] * v.scale[k];
+        g.E[k] = __builtin_fmaf(r[6], B, A);
+        g.G[k] = g.dt * B;
+        float pa = __builtin_fmaf(0.5f, g.G[k], g.E[k]);
+        float pb = __builtin_fmaf(last, g.G[k], g.E[k]);
+        ok &= (__builtin_fabsf(pa) <= 4194304.0f) & (__builtin_fabsf(pb) <= 4194304.0f);
+    }
+    return ok ? 0 : 2;
+}
+
+// One voxel; zero outside the grid.  Out-of-range taps read offset 0 (always
+// valid) and the value is then discarded.
+template <bool HALF>
+__device__ __forceinline__ float voxel(__amdgpu_buffer_rsrc_t rs, const VolArgs &v, int x, int y, int z)
+{
+    bool ok = ((uint32_t)x < (uint32_t)v.nx) & ((uint32_t)y < (uint32_t)v.ny) & ((uint32_t)z < (uint32_t)v.nz);
+    uint32_t idx = __umul24(__umul24((uint32_t)z, (uint32_t)v.ny) + (uint32_t)y, (uint32_t)v.nx) + (uint32_t)x;
+    uint32_t off = ok ? idx * (HALF ? 2u : 4u) : 0u;
+    float val;
+    if constexpr (HALF)
+        val = half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0));
+    else
+        val = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    return ok ? val : 0.0f;
+}
+
+__device__ __forceinline__ void step_coords(const RayGeom &g, float kh, int i0[3], float t[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float p = __builtin_fmaf(kh, g.G[a], g.E[a]);
+        float fl = __builtin_floorf(p);
+        i0[a] = (int)fl;
+        t[a] = p - fl;
+    }
+}
+
+template <int F, int VAR>
+__device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
+{
+    if constexpr (VAR == 0) {
+        o[0] = pick_off<F>(t[0], u24(w.x));
+        o[1] = pick_off<F>(t[1], u24(w.y));
+        o[2] = pick_off<F>(t[2], u24(w.z));
+    } else {
+        float u = u24(w.x);
+        o[0] = pick_off_reuse<F>(t[0], u);
+        o[1] = pick_off_reuse<F>(t[1], u);
+        o[2] = pick_off_reuse<F>(t[2], u);
+    }
+}
+
+// ---------------------------------------------------------------- ray march
+template <int F, bool HALF, int VAR, bool DBG>
+__global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_pad)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
+    if (i >= c.n)
+        return;
+    RayGeom g;
+    int st = ray_setup(c.vol, c.rays + 8 * i, c.steps, g);
+    if (st != 0) {
+        c.T[i] = st == 1 ? 1.0f : __builtin_nanf("");
+        if constexpr (DBG) {
+            int64_t per = (int64_t)3 * c.spp * c.steps;
+            for (int64_t k = 0; k < per; ++k)
+                c.taps[per * i + k] = SF_TAP_NONE;
+        }
+        return;
+    }
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
+                                                                  (int)c.vol.bytes, kBufferFlags);
+    double Tsum = 0.0;
+    for (int s = 0; s < c.spp; ++s) {
+        StepHash h;
+        h.init((uint32_t)i, (uint32_t)s, c.seed);
+        double tau = 0.0;
+        float kh = 0.5f;
+        for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
+            int i0[3], o[3];
+            float t[3];
+            step_coords(g, kh, i0, t);
+            pick3<F, VAR>(t, h.at((uint32_t)k), o);
+            int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
+            if constexpr (DBG) {
+                int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
+                tp[0] = x;
+                tp[1] = y;
+                tp[2] = z;
+            }
+            tau += (double)voxel<HALF>(rs, c.vol, x, y, z);
+        }
+        Tsum += exp(-(double)g.dt * tau);
+    }
+    c.T[i] = (float)(Tsum / (double)c.spp);
+}
+
+// Deterministic comparators: all taps of the separable footprint per step.
+// BEFORE: exp(-dt sum_k sum_i w_i sigma_i); AFTER: prod_k sum_i w_i e^{-dt sigma_i}.
+// Weights and the per-step sums are binary64 (the same issue rate as
+// non-packed binary32 on this chip): with binary32 weights the 64 products
+// sum to 1 +- 3e-7, a bias that a 256-factor product would amplify.
+template <int F, bool HALF, int MODE>
+__global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
+    if (i >= c.n)
+        return;
+    RayGeom g;
+    int st = ray_setup(c.vol, c.rays + 8 * i, c.steps, g);
+    if (st != 0) {
+        c.T[i] = st == 1 ? 1.0f : __builtin_nanf("");
+        return;
+    }
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
+                                                                  (int)c.vol.bytes, kBufferFlags);
+    constexpr int NT = Taps<F>::n;
+    constexpr int F0 = Taps<F>::first;
+    const float cexp = (float)(-(double)g.dt * 1.4426950408889634074);   // -dt log2(e)
+    double tau = 0.0, Tp = 1.0;
+    float kh = 0.5f;
+    for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
+        int i0[3];
+        float t[3];
+        double wx[4], wy[4], wz[4];
+        step_coords(g, kh, i0, t);
+        if constexpr (F == NEAREST) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                i0[a] += t[a] >= 0.5f;
+        }
+        axis_weights64<F>(t[0], wx);
+        axis_weights64<F>(t[1], wy);
+        axis_weights64<F>(t[2], wz);
+        double acc = 0.0;
+#pragma unroll
+        for (int cz = 0; cz < NT; ++cz) {
+#pragma unroll
+            for (int by = 0; by < NT; ++by) {
+                double row = 0.0;
+#pragma unroll
+                for (int ax = 0; ax < NT; ++ax) {
+                    float sg = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
+                    float v = MODE == BEFORE ? sg : __builtin_amdgcn_exp2f(sg * cexp);
+                    row = __builtin_fma(wx[ax], (double)v, row);
+                }
+                acc = __builtin_fma(wy[by] * wz[cz], row, acc);
+            }
+        }
+        if constexpr (MODE == BEFORE)
+            tau += acc;
+        else
+            Tp *= acc;
+    }
+    c.T[i] = MODE == BEFORE ? (float)exp(-(double)g.dt * tau) : (float)Tp;
+}
+
+// ------------------------------------------------------------- point lookups
+template <int F, bool HALF>
+__global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= c.n)
+        return;
+    float x[3] = {c.pos[3 * i], c.pos[3 * i + 1], c.pos[3 * i + 2]};
+    bool ok = __builtin_isfinite(x[0]) & __builtin_isfinite(x[1]) & __builtin_isfinite(x[2]);
+    float p[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p[a] = __builtin_fmaf(x[a] - c.vol.wmin[a], c.vol.scale[a], -0.5f);
+        ok &= __builtin_fabsf(p[a]) <= 4194304.0f;
+    }
+    if (!ok) {
+        c.out[i] = __builtin_nanf("");
+        if (c.taps && c.mode == STOCH)
+            for (int k = 0; k < 3 * c.spp; ++k)
+                c.taps[(int64_t)3 * c.spp * i + k] = SF_TAP_NONE;
+        return;
+    }
+    int i0[3];
+    float t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float fl = __builtin_floorf(p[a]);
+        i0[a] = (int)fl;
+        t[a] = p[a] - fl;
+    }
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
+                                                                  (int)c.vol.bytes, kBufferFlags);
+    const bool trans = c.shade == SF_SHADE_TRANSMITTANCE;
+    if (c.mode == STOCH) {
+        double acc = 0.0;
+        for (int s = 0; s < c.spp; ++s) {
+            uint4 w4 = pcg4d(make_uint4((uint32_t)i, (uint32_t)s, 0u, c.seed));
+            uint3 w = make_uint3(w4.x, w4.y, w4.z);
+            int o[3];
+            if (c.variant == 0)
+                pick3<F, 0>(t, w, o);
+            else
+                pick3<F, 1>(t, w, o);
+            int tx = i0[0] + o[0], ty = i0[1] + o[1], tz = i0[2] + o[2];
+            if (c.taps) {
+                int32_t *tp = c.taps + ((int64_t)i * c.spp + s) * 3;
+                tp[0] = tx;
+                tp[1] = ty;
+                tp[2] = tz;
+            }
+            float sg = voxel<HALF>(rs, c.vol, tx, ty, tz);
+            acc += trans ? exp(-(double)sg * (double)c.ds) : (double)sg;
+        }
+        c.out[i] = (float)(acc / (double)c.spp);
+        return;
+    }
+    constexpr int NT = Taps<F>::n;
+    constexpr int F0 = Taps<F>::first;
+    if constexpr (F == NEAREST) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            i0[a] += t[a] >= 0.5f;
+    }
+    double wx[4], wy[4], wz[4];
+    axis_weights64<F>(t[0], wx);
+    axis_weights64<F>(t[1], wy);
+    axis_weights64<F>(t[2], wz);
+    double sum = 0.0;
+    for (int cz = 0; cz < NT; ++cz)
+        for (int by = 0; by < NT; ++by)
+            for (int ax = 0; ax < NT; ++ax) {
+                double wgt = wx[ax] * wy[by] * wz[cz];
+                float sg = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
+                double v = (c.mode == BEFORE || !trans) ? (double)sg : exp(-(double)sg * (double)c.ds);
+                sum += wgt * v;
+            }
+    if (c.mode == BEFORE && trans)
+        sum = exp(-sum * (double)c.ds);
+    c.out[i] = (float)sum;
+}
+
+// ---------------------------------------------------------------- launchers
+static uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
+
+template <int F, bool HALF>
+static hipError_t launch_ray_f(const RaymarchCall &c, hipStream_t s)
+{
+    uint32_t nb = blocks_for(c.n);
+    uint32_t nb_pad = (nb + 7u) & ~7u;
+    dim3 grid(nb_pad), block(256);
+    if (c.mode == STOCH) {
+        if (c.taps) {
+            if (c.variant)
+                k_ray_stoch<F, HALF, 1, true><<<grid, block, 0, s>>>(c, nb_pad);
+            else
+                k_ray_stoch<F, HALF, 0, true><<<grid, block, 0, s>>>(c, nb_pad);
+        } else {
+            if (c.variant)
+                k_ray_stoch<F, HALF, 1, false><<<grid, block, 0, s>>>(c, nb_pad);
+            else
+                k_ray_stoch<F, HALF, 0, false><<<grid, block, 0, s>>>(c, nb_pad);
+        }
+    } else if (c.mode == BEFORE) {
+        k_ray_det<F, HALF, BEFORE><<<grid, block, 0, s>>>(c, nb_pad);
+    } else {
+        k_ray_det<F, HALF, AFTER><<<grid, block, 0, s>>>(c, nb_pad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s)
+{
+    const bool half = c.vol.fmt == SF_R16F;
+    switch (c.filter) {
+    case NEAREST:
+        return half ? launch_ray_f<NEAREST, true>(c, s) : launch_ray_f<NEAREST, false>(c, s);
+    case LINEAR:
+        return half ? launch_ray_f<LINEAR, true>(c, s) : launch_ray_f<LINEAR, false>(c, s);
+    default:
+        return half ? launch_ray_f<BSPLINE3, true>(c, s) : launch_ray_f<BSPLINE3, false>(c, s);
+    }
+}
+
+hipError_t launch_filter3d(const Filter3DCall &c, hipStream_t s)
+{
+    dim3 grid(blocks_for(c.n)), block(256);
+    const bool half = c.vol.fmt == SF_R16F;
+    switch (c.filter) {
+    case NEAREST:
+        if (half)
+            k_filter3d<NEAREST, true><<<grid, block, 0, s>>>(c);
+        else
+            k_filter3d<NEAREST, false><<<grid, block, 0, s>>>(c);
+        break;
+    case LINEAR:
+        if (half)
+            k_filter3d<LINEAR, true><<<grid, block, 0, s>>>(c);
+        else
+            k_filter3d<LINEAR, false><<<grid, block, 0, s>>>(c);
+        break;
+    default:
+        if (half)
+            k_filter3d<BSPLINE3, true><<<grid, block, 0, s>>>(c);
+        else
+            k_filter3d<BSPLINE3, false><<<grid, block, 0, s>>>(c);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sfk

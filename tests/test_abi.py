@@ -1,0 +1,182 @@
+"""The C-ABI library loads, exports every symbol include/sf.h declares, and
+rejects bad arguments on the host before anything is enqueued (these calls
+never reach the device, so they run without a GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import paper_2407_06107_amd as sf
+    if not os.path.exists(sf.LIB_PATH):
+        from paper_2407_06107_amd import build
+        build.build()
+    sf.lib()
+    return sf
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "sf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(sf):
+    declared = _declared_symbols()
+    assert "sf_raymarch" in declared and "sf_filter2d" in declared
+    out = subprocess.run(["nm", "-D", "--defined-only", sf.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sf_\w+)", out))
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    for s in declared:
+        assert hasattr(sf.lib(), s)
+    assert set(sf.EXPORTED) == set(declared)
+
+
+def test_versions(sf):
+    assert sf.sf_abi_version() == 1
+    assert sf.sf_rng_version() == 1
+
+
+def test_struct_layouts_match_header(sf):
+    """ctypes mirrors of the descriptors have the C sizes the header implies."""
+    assert C.sizeof(sf.sf_sampling) == 20
+    assert C.sizeof(sf.sf_tex2d) == 8 + 6 * 4 + 16 * 8
+    assert C.sizeof(sf.sf_ggx) == 15 * 4
+    assert C.sizeof(sf.sf_volume) == 8 + 4 * 4 + 6 * 4
+
+
+def _vol(sf, **kw):
+    v = sf.sf_volume(0x1000, 8, 8, 8, sf.SF_R16F, (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(8, 8, 8))
+    for k, x in kw.items():
+        setattr(v, k, x)
+    return v
+
+
+FAKE = C.c_void_p(0x10000)   # a host-side stand-in pointer: never dereferenced, validation fails first
+
+
+@pytest.mark.parametrize("case, status", [
+    ("n_negative", 2), ("n_zero", 0), ("null_rays", 1), ("steps_zero", 2), ("steps_big", 2),
+    ("bad_filter", 2), ("bad_mode", 2), ("spp_zero", 2), ("bad_variant", 2), ("null_volume", 1),
+    ("bad_format", 3), ("dims_zero", 2), ("scale_zero", 2), ("misaligned_rays", 2), ("n_huge", 2),
+])
+def test_raymarch_validation(sf, case, status):
+    L = sf.lib()
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1)
+    vol = _vol(sf)
+    n, steps, rays, T = 4, 16, FAKE, FAKE
+    if case == "n_negative":
+        n = -1
+    elif case == "n_zero":
+        n = 0
+    elif case == "null_rays":
+        rays = None
+    elif case == "steps_zero":
+        steps = 0
+    elif case == "steps_big":
+        steps = 70000
+    elif case == "bad_filter":
+        smp.filter = 7
+    elif case == "bad_mode":
+        smp.mode = 3
+    elif case == "spp_zero":
+        smp.spp = 0
+    elif case == "bad_variant":
+        smp.rng_variant = 2
+    elif case == "null_volume":
+        vol = None
+    elif case == "bad_format":
+        vol.format = sf.SF_RGBA8_UNORM
+    elif case == "dims_zero":
+        vol.nx = 0
+    elif case == "scale_zero":
+        vol.scale[1] = 0.0
+    elif case == "misaligned_rays":
+        rays = C.c_void_p(0x10004)
+    elif case == "n_huge":
+        n = 2 ** 31
+    st = L.sf_raymarch(C.byref(vol) if vol is not None else None, rays, n, steps, C.byref(smp), T, None, None)
+    assert st == status, sf.sf_last_error()
+    if status:
+        assert sf.sf_last_error()
+
+
+@pytest.mark.parametrize("case, status", [
+    ("ok_zero", 0), ("null_tex", 1), ("null_base", 1), ("bad_format", 3), ("levels_zero", 2),
+    ("levels_too_many", 2), ("bad_wrap", 2), ("bad_mip", 2), ("ggx_missing", 1), ("bad_shade", 2),
+    ("ggx_backfacing", 2), ("misaligned_level", 2), ("width_zero", 2),
+])
+def test_filter2d_validation(sf, case, status):
+    L = sf.lib()
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 4)
+    tex = sf.sf_tex2d()
+    tex.base, tex.width, tex.height, tex.levels = 0x10000, 64, 64, 1
+    tex.format, tex.wrap, tex.mip = sf.SF_RGBA32F, 0, 0
+    n, shade, g = 10, sf.SF_SHADE_NONE, None
+    texp = C.byref(tex)
+    if case == "ok_zero":
+        n = 0
+    elif case == "null_tex":
+        texp = None
+    elif case == "null_base":
+        tex.base = None
+    elif case == "bad_format":
+        tex.format = sf.SF_R16F
+    elif case == "levels_zero":
+        tex.levels = 0
+    elif case == "levels_too_many":
+        tex.levels = 8      # 64x64 has 7 levels
+    elif case == "bad_wrap":
+        tex.wrap = 5
+    elif case == "bad_mip":
+        tex.mip = 3
+    elif case == "ggx_missing":
+        shade = sf.SF_SHADE_GGX
+    elif case == "bad_shade":
+        shade = 4
+    elif case == "ggx_backfacing":
+        shade = sf.SF_SHADE_GGX
+        g = sf.ggx(wi=(0.0, 0.3, -1.0))
+    elif case == "misaligned_level":
+        tex.levels = 2
+        tex.level_offset[1] = 8
+    elif case == "width_zero":
+        tex.width = 0
+    st = L.sf_filter2d(texp, FAKE, n, C.byref(smp), shade, C.byref(g) if g is not None else None, FAKE, None, None)
+    assert st == status, sf.sf_last_error()
+
+
+def test_filter3d_validation(sf):
+    L = sf.lib()
+    smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)
+    vol = _vol(sf)
+    assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(smp), 2, 1.0, FAKE, None, None) == 2
+    assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(smp), 1, float("nan"), FAKE, None, None) == 2
+    assert L.sf_filter3d(C.byref(vol), None, 3, C.byref(smp), 0, 1.0, FAKE, None, None) == 1
+    big = _vol(sf, nx=4096, ny=4096, nz=64)
+    assert L.sf_filter3d(C.byref(big), FAKE, 3, C.byref(smp), 0, 1.0, FAKE, None, None) == 3
+
+
+def test_error_stats_validation(sf):
+    L = sf.lib()
+    need = sf.sf_error_stats_workspace(5000)
+    assert need == 5 * 64
+    assert sf.sf_error_stats_workspace(10 ** 9) == 1024 * 64
+    assert L.sf_error_stats(FAKE, FAKE, 5000, 1, FAKE, FAKE, need - 8, None) == 5
+    assert L.sf_error_stats(FAKE, FAKE, 5000, 0, FAKE, FAKE, need, None) == 2
+    assert L.sf_error_stats(None, FAKE, 5000, 1, FAKE, FAKE, need, None) == 1
+
+
+def test_product_path_has_no_fallback(sf, monkeypatch, tmp_path):
+    """Without the built library the binding raises instead of computing."""
+    monkeypatch.setattr(sf, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(sf, "_lib", None)
+    with pytest.raises(ImportError):
+        sf.lib()

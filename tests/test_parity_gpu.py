@@ -1,0 +1,322 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: tap indices bit-exact given the same random stream; values within
+1e-5 relative (the floating-point tolerance stated for the method's shaded
+values with FP32 texels), with a 1e-7 absolute floor for exact zeros.  Small
+cases span several 256-lane blocks and a ragged tail; full-size cases run in
+the launch configuration the benchmark times and are checked on sampled
+outputs the oracle computes one by one.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2407_06107_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-5, 1e-7
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import paper_2407_06107_amd as sf
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sf.lib()
+    return sf
+
+
+def _close(gpu, ref, rtol=RTOL, atol=ATOL):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape, (gpu.shape, ref.shape)
+    nan_g, nan_r = np.isnan(gpu), np.isnan(ref)
+    assert np.array_equal(nan_g, nan_r), "NaN pattern differs"
+    g, r = gpu[~nan_g], ref[~nan_r]
+    err = np.abs(g - r)
+    bad = err > atol + rtol * np.abs(r)
+    assert not bad.any(), f"{bad.sum()} of {bad.size} outside tolerance; worst rel {np.max(err / (np.abs(r) + atol)):.3e}"
+
+
+def _print_case(*args):
+    print("CASE", *args, flush=True)
+
+
+# ------------------------------------------------------------------ 3-D grids
+@pytest.fixture(scope="module")
+def small_cloud():
+    g = inputs.cloud_grid(48, seed=4).numpy()[:40, :36, :44].copy()   # nz, ny, nx: non-cubic
+    return g
+
+
+def _grids(orc, sf, data, side=1.0):
+    nz, ny, nx = data.shape
+    scale = (nx / side, ny / side, nz / side)
+    og = orc.Grid(data, scale=scale)
+    vol = sf.Volume(torch.from_numpy(data).cuda(), scale=scale)
+    return og, vol
+
+
+MODES3 = [("STOCH", 1, 0), ("STOCH", 3, 1), ("BEFORE", 1, 0), ("AFTER", 1, 0)]
+
+
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("mode, spp, variant", MODES3)
+@pytest.mark.parametrize("dtype", ["float16", "float32"])
+def test_raymarch_small(sf, orc, small_cloud, filt, mode, spp, variant, dtype):
+    _print_case("raymarch_small", filt, mode, spp, variant, dtype)
+    data = small_cloud.astype(dtype)
+    og, vol = _grids(orc, sf, data)
+    rays = inputs.random_rays(3001, 1.0, seed=21)       # 11 full blocks + a ragged tail, some misses
+    steps = 48
+    f = getattr(orc, filt)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(f, m, spp, seed=77, rng_variant=variant)
+    rays_d = torch.from_numpy(rays).cuda()
+    taps_d = torch.empty((rays.shape[0], spp, steps, 3), dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    T = sf.sf_raymarch(vol, rays_d, steps, smp, dbg_taps=taps_d)
+    torch.cuda.synchronize()
+    if m == orc.STOCHASTIC:
+        ref, taps = orc.raymarch(og, rays, steps, f, m, spp=spp, seed=77, variant=variant, taps=True)
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = orc.raymarch(og, rays, steps, f, m, spp=spp, seed=77, variant=variant)
+    _close(T.cpu().numpy(), ref)
+
+
+def test_raymarch_edge_cases(sf, orc, small_cloud):
+    _print_case("raymarch_edge_cases")
+    og, vol = _grids(orc, sf, small_cloud)
+    rays = np.array([
+        [0.5, 0.5, -1.0, 0, 0, 1, 1.0, 2.0],       # through the grid
+        [np.nan, 0.5, 0.5, 0, 0, 1, 0.0, 1.0],     # non-finite -> NaN
+        [0.5, 0.5, 0.5, 0, 0, 1, 0.4, 0.4],        # empty segment -> 1
+        [5.0, 5.0, 5.0, 1, 0, 0, 0.0, 1.0],        # entirely outside -> 1 (zero density)
+        [1e9, 0.5, 0.5, 1, 0, 0, 0.0, 1.0],        # beyond 2^22 voxels -> NaN
+        [0.5, 0.5, 0.5, 0, 1, 0, -0.6, 0.6],       # enters and leaves through the border
+    ], dtype=np.float32)
+    rays_d = torch.from_numpy(rays).cuda()
+    for steps in (1, 7, 64):
+        for filt in (orc.LINEAR, orc.BSPLINE3):
+            for m in (orc.STOCHASTIC, orc.BEFORE, orc.AFTER):
+                smp = sf.sampling(filt, m, 2, seed=3)
+                taps_d = torch.full((6, 2, steps, 3), 7, dtype=torch.int32, device="cuda")
+                T = sf.sf_raymarch(vol, rays_d, steps, smp, dbg_taps=taps_d if m == orc.STOCHASTIC else None)
+                if m == orc.STOCHASTIC:
+                    ref, taps = orc.raymarch(og, rays, steps, filt, m, spp=2, seed=3, taps=True)
+                    assert np.array_equal(taps_d.cpu().numpy(), taps)
+                else:
+                    ref = orc.raymarch(og, rays, steps, filt, m, spp=2, seed=3)
+                _close(T.cpu().numpy(), ref)
+                t = T.cpu().numpy()
+                assert np.isnan(t[1]) and t[2] == 1.0 and t[3] == 1.0 and np.isnan(t[4])
+    # n = 0 is a no-op
+    empty = torch.empty((0, 8), dtype=torch.float32, device="cuda")
+    out = sf.sf_raymarch(vol, empty, 16, sf.sampling(2, 2, 1))
+    assert out.numel() == 0
+
+
+def test_raymarch_deterministic_repeat(sf, orc, small_cloud):
+    _print_case("raymarch_deterministic_repeat")
+    _, vol = _grids(orc, sf, small_cloud)
+    rays = torch.from_numpy(inputs.random_rays(5000, 1.0, seed=2)).cuda()
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=9)
+    a = sf.sf_raymarch(vol, rays, 64, smp).clone()
+    b = sf.sf_raymarch(vol, rays, 64, smp)
+    assert torch.equal(a, b)
+
+
+def test_raymarch_stochastic_mean_matches_expectation(sf, orc, small_cloud):
+    """Unbiasedness on the GPU: the mean over many samples is within 5
+    standard errors of the oracle's exact expectation (= exact after)."""
+    _print_case("raymarch_stochastic_mean")
+    og, vol = _grids(orc, sf, small_cloud)
+    rays = inputs.random_rays(64, 1.0, seed=8)
+    spp = 4096
+    T = sf.sf_raymarch(vol, torch.from_numpy(rays).cuda(), 24, sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, spp, seed=1))
+    e = orc.raymarch_expect(og, rays, 24, orc.BSPLINE3)
+    assert np.max(np.abs(T.cpu().numpy() - e)) < 5 * 0.5 / math.sqrt(spp)
+
+
+@pytest.fixture(scope="module")
+def full_cloud():
+    """Config-3 workload: 512^3 fp16 cloud (cube side 0.25) and 256^2 px x 16 rays."""
+    _print_case("full_cloud generate")
+    side = 0.25
+    data = inputs.cloud_grid(512, seed=4, device="cuda")
+    rays = inputs.ortho_rays(256, 16, side=side, seed=11)
+    return data, rays, side
+
+
+@pytest.mark.parametrize("filt, mode", [("BSPLINE3", "STOCH"), ("LINEAR", "STOCH"), ("BSPLINE3", "BEFORE"),
+                                        ("BSPLINE3", "AFTER"), ("LINEAR", "AFTER")])
+def test_raymarch_full_size_sampled(sf, orc, full_cloud, filt, mode):
+    _print_case("raymarch_full_size", filt, mode)
+    data, rays, side = full_cloud
+    steps = 256
+    vol = sf.Volume(data, side=side)
+    host = data.cpu().numpy()
+    og = orc.Grid(host, side=side)
+    f = getattr(orc, filt)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(f, m, 1, seed=2024)
+    rays_d = torch.from_numpy(rays).cuda()
+    T = sf.sf_raymarch(vol, rays_d, steps, smp).cpu().numpy()
+    rng = np.random.default_rng(5)
+    sub = np.sort(rng.choice(rays.shape[0], 400, replace=False))
+    ref = orc.raymarch(og, rays, steps, f, m, spp=1, seed=2024, subset=sub)
+    _close(T[sub], ref)
+    if m == orc.STOCHASTIC:
+        # taps of a prefix of the same stream (same ray indices, same keys)
+        k = 1024
+        taps_d = torch.empty((k, 1, steps, 3), dtype=torch.int32, device="cuda")
+        Tk = sf.sf_raymarch(vol, rays_d[:k].contiguous(), steps, smp, dbg_taps=taps_d)
+        refk, taps = orc.raymarch(og, rays[:k], steps, f, m, spp=1, seed=2024, taps=True)
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+        _close(Tk.cpu().numpy(), refk)
+        assert np.array_equal(Tk.cpu().numpy(), T[:k])
+
+
+# ------------------------------------------------------------------ 2-D
+@pytest.fixture(scope="module")
+def c1(orc):
+    tex = inputs.texture_uniform(64, seed=1)
+    q = inputs.queries_uniform(4096, seed=2)
+    q[:7, 0] = [-0.25, 1.0, 1.75, 0.999999, -1e-9, 0.5, 0.25]     # wrap cases
+    q[7, 1] = np.nan                                            # non-finite -> NaN
+    return tex, q
+
+
+MODES2 = [("STOCH", 16, 0), ("STOCH", 5, 1), ("STOCH", 1, 0), ("BEFORE", 1, 0), ("AFTER", 1, 0)]
+
+
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("mode, spp, variant", MODES2)
+@pytest.mark.parametrize("shade", [0, 1])
+@pytest.mark.parametrize("wrap", [0, 1])
+def test_filter2d_config1(sf, orc, c1, filt, mode, spp, variant, shade, wrap):
+    _print_case("filter2d_c1", filt, mode, spp, variant, shade, wrap)
+    tex, q = c1
+    ot = orc.Tex2D.rgba32f(tex, wrap=wrap)
+    gt = sf.Texture2D([tex], wrap=wrap)
+    f = getattr(orc, filt)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(f, m, spp, seed=123, rng_variant=variant)
+    qd = torch.from_numpy(q).cuda()
+    taps_d = torch.full((q.shape[0], spp, 3), 99, dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d(gt, qd, smp, shade=shade, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d(ot, q, f, m, spp=spp, seed=123, variant=variant, shade=shade, taps=m == orc.STOCHASTIC)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.fixture(scope="module")
+def c2_small(orc):
+    size = 256
+    lv = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_sinusoids(size, seed=3, waves=12)))
+    q = inputs.plane_queries(160, 90, tex_size=size, levels=len(lv))
+    return lv, q
+
+
+@pytest.mark.parametrize("filt", ["LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("mip", [1, 2])
+@pytest.mark.parametrize("mode, spp", [("STOCH", 16), ("STOCH", 1), ("BEFORE", 1), ("AFTER", 1)])
+def test_filter2d_mips_rgba8(sf, orc, c2_small, filt, mip, mode, spp):
+    _print_case("filter2d_mips", filt, mip, mode, spp)
+    lv, q = c2_small
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, mip)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=mip)
+    assert list(gt.offsets) == list(offs)
+    f = getattr(orc, filt)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(f, m, spp, seed=5)
+    qd = torch.from_numpy(q).cuda()
+    taps_d = torch.empty((q.shape[0], spp, 3), dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d(gt, qd, smp, shade=1, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d(ot, q, f, m, spp=spp, seed=5, shade=1, taps=m == orc.STOCHASTIC)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.fixture(scope="module")
+def c2_full():
+    _print_case("c2_full generate")
+    lv = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_sinusoids(4096, seed=3)))
+    q = inputs.plane_queries(1920, 1080, tex_size=4096, levels=len(lv))
+    return lv, q
+
+
+@pytest.mark.parametrize("filt, mode, spp", [("BSPLINE3", "STOCH", 16), ("BSPLINE3", "STOCH", 1),
+                                             ("LINEAR", "STOCH", 16), ("BSPLINE3", "AFTER", 1),
+                                             ("BSPLINE3", "BEFORE", 1)])
+def test_filter2d_config2_full_sampled(sf, orc, c2_full, filt, mode, spp):
+    _print_case("filter2d_c2_full", filt, mode, spp)
+    lv, q = c2_full
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, 4096, 4096, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    f = getattr(orc, filt)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(f, m, spp, seed=31)
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx()).cpu().numpy()
+    sub = np.sort(np.random.default_rng(1).choice(q.shape[0], 3000, replace=False))
+    ref = orc.filter2d(ot, q, f, m, spp=spp, seed=31, shade=1, subset=sub)
+    _close(out[sub], ref)
+
+
+# ------------------------------------------------------------------ 3-D points
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("mode, spp, variant", [("STOCH", 4, 0), ("STOCH", 3, 1), ("BEFORE", 1, 0), ("AFTER", 1, 0)])
+@pytest.mark.parametrize("shade", [0, 1])
+def test_filter3d_small(sf, orc, small_cloud, filt, mode, spp, variant, shade):
+    _print_case("filter3d", filt, mode, spp, variant, shade)
+    og, vol = _grids(orc, sf, small_cloud)
+    p = inputs.random_points(2999, -0.05, 1.05, seed=4)
+    p[3] = [np.nan, 0.5, 0.5]
+    f = getattr(orc, filt)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(f, m, spp, seed=8, rng_variant=variant)
+    taps_d = torch.empty((p.shape[0], spp, 3), dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter3d(vol, torch.from_numpy(p).cuda(), smp, shade=shade, ds=0.05, dbg_taps=taps_d)
+    res = orc.filter3d(og, p, f, m, spp=spp, seed=8, variant=variant, shade=shade, ds=0.05,
+                       taps=m == orc.STOCHASTIC)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+# ------------------------------------------------------------------ reductions
+def test_error_stats(sf):
+    _print_case("error_stats")
+    rng = np.random.default_rng(0)
+    for n in (1, 1000, 300_001, 3_000_000):
+        ref = rng.random(n) + 0.1
+        est = (ref + 1e-3 * rng.normal(size=n)).astype(np.float32)
+        if n > 3:
+            est[:3] = np.nan
+        out = sf.sf_error_stats(torch.from_numpy(est).cuda(), torch.from_numpy(ref).cuda()).cpu().numpy()
+        e = est.astype(np.float64)
+        fin = np.isfinite(e)
+        d = e[fin] - ref[fin]
+        assert out[4] == fin.sum() and out[6] == (~fin).sum()
+        assert np.isclose(out[0], np.sum(d * d), rtol=1e-12)
+        assert np.isclose(out[1], np.sum(d), rtol=1e-9, atol=1e-12)
+        assert out[2] == np.max(np.abs(d))
+        assert out[3] == np.max(np.abs(d) / np.abs(ref[fin]))
+        assert np.isclose(out[5], np.sum(ref[fin] ** 2), rtol=1e-12)
+        again = sf.sf_error_stats(torch.from_numpy(est).cuda(), torch.from_numpy(ref).cuda()).cpu().numpy()
+        assert np.array_equal(out, again)
