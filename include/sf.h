@@ -119,12 +119,21 @@ typedef struct sf_ggx {
 /* A dense 3-D grid of scalar density (x fastest, then y, then z) occupying
  * the world box from wmin; scale = voxels per world unit per axis.  World
  * point x maps to raster p = (x - wmin)*scale - 0.5 (subtract, then one fused
- * multiply-add).  Taps outside the grid read zero (empty space). */
+ * multiply-add).  Taps outside the grid read zero (empty space).
+ * occupancy: NULL, or the brick mask sf_build_occupancy wrote for this grid
+ * and brick_log2 (the mask must be rebuilt whenever the grid changes).  The
+ * ray march then skips every step whose lookup point lies in a brick whose
+ * 2-voxel dilation holds only zeros: such a step can only read zeros, so the
+ * stochastic result is bit-identical with and without the mask (Sec. 5: the
+ * sparse NanoVDB grid of the paper's offline renderer plays this role). */
 typedef struct sf_volume {
     const void *base;
     int32_t nx, ny, nz;
     int32_t format; /* SF_R16F | SF_R32F */
     float wmin[3], scale[3];
+    const uint32_t *occupancy; /* device, sf_occupancy_words(...) words, or NULL */
+    int32_t brick_log2;        /* brick side 2^brick_log2 voxels, 1..6 (with occupancy) */
+    int32_t reserved;          /* must be 0 */
 } sf_volume;
 
 /*
@@ -188,6 +197,21 @@ sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const s
  */
 sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_t steps,
                       const sf_sampling *smp, float *T, int32_t *dbg_taps, void *stream);
+
+/*
+ * sf_build_occupancy — brick occupancy mask of a density grid for empty-space
+ * skipping in sf_raymarch.
+ *   vol->brick_log2 sets the brick side B = 2^brick_log2 (vol->occupancy is
+ *   ignored).  Bricks are numbered b = (bz*nby + by)*nbx + bx with
+ *   nbx = ceil(nx/B) (likewise y, z); bit (b & 31) of word b >> 5 is 1 iff some
+ *   voxel within 2 voxels of the brick (the support of a cubic B-spline tap
+ *   around any point of the brick) is non-zero or not a number.
+ *   occupancy: device buffer of `words` uint32, at least sf_occupancy_words().
+ * Errors: SF_E_NULL, SF_E_RANGE (brick_log2 outside 1..6, words too small),
+ *         SF_E_UNSUPPORTED (grid as in sf_raymarch), SF_E_DEVICE.
+ */
+sf_status sf_build_occupancy(const sf_volume *vol, uint32_t *occupancy, int64_t words, void *stream);
+int64_t sf_occupancy_words(int32_t nx, int32_t ny, int32_t nz, int32_t brick_log2);
 
 /*
  * sf_error_stats — error statistics of an estimate against a reference,

@@ -73,6 +73,7 @@ def lib():
         L.orc_raymarch.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, i32, u32, i32,
                                    P, P, P, i64]
         L.orc_raymarch_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
+        L.orc_build_occupancy.argtypes = [P, i32, i32, i32, i32, i32, P]
         _lib = L
     return _lib
 
@@ -265,3 +266,11 @@ def raymarch_expect(g: Grid, rays: np.ndarray, steps: int, filt: int):
     lib().orc_raymarch_expect(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(rays), n, steps,
                               filt, _p(T))
     return T
+
+
+def build_occupancy(g: Grid, brick_log2: int) -> np.ndarray:
+    B = 1 << brick_log2
+    nb = -(-g.nx // B) * -(-g.ny // B) * -(-g.nz // B)
+    words = np.zeros((nb + 31) // 32, dtype=np.uint32)
+    lib().orc_build_occupancy(_p(g.data), g.nx, g.ny, g.nz, g.fmt, brick_log2, _p(words))
+    return words

@@ -875,6 +875,32 @@ ORC_EXPORT int orc_raymarch_expect(const void *base, int nx, int ny, int nz, int
     return 0;
 }
 
+/* Brick occupancy: bit b of the mask is set iff some voxel within 2 voxels
+ * of brick b (side 2^lg, x fastest) is non-zero or not a number. */
+ORC_EXPORT void orc_build_occupancy(const void *base, int nx, int ny, int nz, int fmt, int lg, uint32_t *words)
+{
+    grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {0, 0, 0}, {1, 1, 1}};
+    int B = 1 << lg;
+    int nbx = (nx + B - 1) / B, nby = (ny + B - 1) / B, nbz = (nz + B - 1) / B;
+    int64_t nb = (int64_t)nbx * nby * nbz;
+    memset(words, 0, (size_t)((nb + 31) / 32) * sizeof(uint32_t));
+    for (int bz = 0; bz < nbz; ++bz)
+        for (int by = 0; by < nby; ++by)
+            for (int bx = 0; bx < nbx; ++bx) {
+                int any = 0;
+                for (int z = bz * B - 2; z < bz * B + B + 2 && !any; ++z)
+                    for (int y = by * B - 2; y < by * B + B + 2 && !any; ++y)
+                        for (int x = bx * B - 2; x < bx * B + B + 2 && !any; ++x) {
+                            double v = fetch3d(&g, x, y, z);
+                            if (!(v == 0.0))
+                                any = 1;
+                        }
+                int64_t b = ((int64_t)bz * nby + by) * nbx + bx;
+                if (any)
+                    words[b >> 5] |= 1u << (b & 31);
+            }
+}
+
 ORC_EXPORT int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -29,8 +29,8 @@ SF_SHADE_DENSITY, SF_SHADE_TRANSMITTANCE = 0, 1
 SF_TAP_NONE = -(2 ** 31)
 SF_MAX_LEVELS = 16
 
-EXPORTED = ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_error_stats", "sf_error_stats_workspace",
-            "sf_last_error", "sf_abi_version", "sf_rng_version")
+EXPORTED = ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_build_occupancy", "sf_occupancy_words",
+            "sf_error_stats", "sf_error_stats_workspace", "sf_last_error", "sf_abi_version", "sf_rng_version")
 
 
 class sf_sampling(C.Structure):
@@ -51,7 +51,8 @@ class sf_ggx(C.Structure):
 
 class sf_volume(C.Structure):
     _fields_ = [("base", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
-                ("format", C.c_int32), ("wmin", C.c_float * 3), ("scale", C.c_float * 3)]
+                ("format", C.c_int32), ("wmin", C.c_float * 3), ("scale", C.c_float * 3),
+                ("occupancy", C.c_void_p), ("brick_log2", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SFError(RuntimeError):
@@ -76,6 +77,10 @@ def lib() -> C.CDLL:
         L.sf_filter3d.argtypes = [P, P, i64, P, i32, C.c_float, P, P, P]
         L.sf_raymarch.argtypes = [P, P, i64, i32, P, P, P, P]
         L.sf_error_stats.argtypes = [P, P, i64, i32, P, P, C.c_size_t, P]
+        L.sf_build_occupancy.argtypes = [P, P, i64, P]
+        L.sf_build_occupancy.restype = i32
+        L.sf_occupancy_words.argtypes = [i32, i32, i32, i32]
+        L.sf_occupancy_words.restype = i64
         L.sf_error_stats_workspace.argtypes = [i64]
         L.sf_error_stats_workspace.restype = C.c_size_t
         for f in ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_error_stats"):
@@ -177,9 +182,12 @@ class Texture2D:
 
 class Volume:
     """A device density grid [nz, ny, nx] (float16 or float32) over the world
-    box starting at ``wmin`` with ``scale`` voxels per unit."""
+    box starting at ``wmin`` with ``scale`` voxels per unit.  With
+    ``brick_log2`` set, an occupancy mask is built (sf_build_occupancy) and
+    the ray march skips empty bricks."""
 
-    def __init__(self, data: torch.Tensor, wmin=(0.0, 0.0, 0.0), scale=None, side: float = 1.0):
+    def __init__(self, data: torch.Tensor, wmin=(0.0, 0.0, 0.0), scale=None, side: float = 1.0,
+                 brick_log2: int | None = None, stream=None):
         if data.dtype not in (torch.float16, torch.float32):
             raise TypeError("volume must be float16 or float32")
         if not data.is_cuda or not data.is_contiguous() or data.dim() != 3:
@@ -189,7 +197,12 @@ class Volume:
         if scale is None:
             scale = (nx / side, ny / side, nz / side)
         self.desc = sf_volume(data.data_ptr(), nx, ny, nz, SF_R16F if data.dtype == torch.float16 else SF_R32F,
-                              (C.c_float * 3)(*wmin), (C.c_float * 3)(*scale))
+                              (C.c_float * 3)(*wmin), (C.c_float * 3)(*scale), None, 0, 0)
+        self.occupancy = None
+        if brick_log2 is not None:
+            self.occupancy = sf_build_occupancy(self, brick_log2, stream=stream)
+            self.desc.occupancy = self.occupancy.data_ptr()
+            self.desc.brick_log2 = brick_log2
 
 
 def sf_filter2d(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, shade: int = SF_SHADE_NONE,
@@ -241,6 +254,22 @@ def sf_raymarch(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling, T
     _check(lib().sf_raymarch(C.byref(vol.desc), _ptr(rays), n, steps, C.byref(smp), _ptr(T), _ptr(dbg_taps),
                              _stream(stream)))
     return T
+
+
+def sf_occupancy_words(nx: int, ny: int, nz: int, brick_log2: int) -> int:
+    return int(lib().sf_occupancy_words(nx, ny, nz, brick_log2))
+
+
+def sf_build_occupancy(vol: Volume, brick_log2: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Brick occupancy mask of ``vol`` (int32 words, bit layout of sf.h)."""
+    d = vol.desc
+    words = sf_occupancy_words(d.nx, d.ny, d.nz, brick_log2)
+    if out is None:
+        out = torch.zeros(max(words, 1), dtype=torch.int32, device=vol.data.device)
+    _need(out, torch.int32, "out")
+    desc = sf_volume(d.base, d.nx, d.ny, d.nz, d.format, d.wmin, d.scale, None, brick_log2, 0)
+    _check(lib().sf_build_occupancy(C.byref(desc), _ptr(out), out.numel(), _stream(stream)))
+    return out
 
 
 def sf_error_stats_workspace(count: int) -> int:

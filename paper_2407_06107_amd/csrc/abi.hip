@@ -73,6 +73,22 @@ sf_status check_volume(const sf_volume *v, sfk::VolArgs &a)
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(v->wmin[k]) || !std::isfinite(v->scale[k]) || v->scale[k] == 0.0f)
             return fail(SF_E_RANGE, "volume wmin/scale must be finite, scale non-zero");
+    if (v->reserved != 0)
+        return fail(SF_E_RANGE, "volume reserved field must be 0");
+    a.occ = nullptr;
+    a.occ_log2 = a.nbx = a.nby = a.nbz = 0;
+    if (v->occupancy) {
+        if (v->brick_log2 < 1 || v->brick_log2 > 6)
+            return fail(SF_E_RANGE, "brick_log2 %d outside 1..6", v->brick_log2);
+        if (!aligned(v->occupancy, 4))
+            return fail(SF_E_RANGE, "occupancy pointer misaligned");
+        const int32_t B = 1 << v->brick_log2;
+        a.occ = v->occupancy;
+        a.occ_log2 = v->brick_log2;
+        a.nbx = (v->nx + B - 1) / B;
+        a.nby = (v->ny + B - 1) / B;
+        a.nbz = (v->nz + B - 1) / B;
+    }
     a.base = v->base;
     a.nx = v->nx;
     a.ny = v->ny;
@@ -265,6 +281,33 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
     c.T = T;
     c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
     return device_status(sfk::launch_raymarch(c, (hipStream_t)stream));
+}
+
+int64_t sf_occupancy_words(int32_t nx, int32_t ny, int32_t nz, int32_t brick_log2)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || brick_log2 < 1 || brick_log2 > 6)
+        return 0;
+    const int64_t B = 1LL << brick_log2;
+    const int64_t nb = ((nx + B - 1) / B) * ((ny + B - 1) / B) * ((nz + B - 1) / B);
+    return (nb + 31) / 32;
+}
+
+sf_status sf_build_occupancy(const sf_volume *vol, uint32_t *occupancy, int64_t words, void *stream)
+{
+    if (!vol || !occupancy)
+        return fail(SF_E_NULL, "volume and occupancy must be non-NULL");
+    sf_volume v = *vol;
+    v.occupancy = occupancy;    // only to size the bricks below
+    sfk::VolArgs a;
+    sf_status st;
+    if ((st = check_volume(&v, a)) != SF_OK)
+        return st;
+    const int64_t need = sf_occupancy_words(v.nx, v.ny, v.nz, v.brick_log2);
+    if (need > (1LL << 26))
+        return fail(SF_E_UNSUPPORTED, "more than 2^31 bricks");
+    if (words < need)
+        return fail(SF_E_RANGE, "occupancy needs %lld words, %lld given", (long long)need, (long long)words);
+    return device_status(sfk::launch_build_occupancy(a, v.brick_log2, occupancy, words, (hipStream_t)stream));
 }
 
 static int32_t err_blocks(int64_t count)

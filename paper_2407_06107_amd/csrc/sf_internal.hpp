@@ -29,6 +29,8 @@ struct VolArgs {
     int32_t nx, ny, nz, fmt;
     uint32_t bytes;          // size of the grid in bytes (< 2^31)
     float wmin[3], scale[3];
+    const uint32_t *occ;     // brick occupancy mask or null
+    int32_t occ_log2, nbx, nby, nbz;
 };
 
 struct Filter2DCall {
@@ -67,6 +69,7 @@ struct RaymarchCall {
 hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s);
 hipError_t launch_filter3d(const Filter3DCall &c, hipStream_t s);
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s);
+hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ, int64_t words, hipStream_t s);
 hipError_t launch_error_stats(const float *est, const double *ref, int64_t count, int32_t ch, double *out,
                               double *partials, int32_t nblocks, hipStream_t s);
 

@@ -77,6 +77,21 @@ __device__ __forceinline__ void step_coords(const RayGeom &g, float kh, int i0[3
     }
 }
 
+// True unless the lookup point's brick is known to be empty: a tap of any
+// filter lies within [i0-1, i0+2] per axis, inside the brick's 2-voxel
+// dilation, so a clear bit means every tap reads zero.  Bricks outside the
+// grid (points within a voxel of the lower faces) count as occupied.
+__device__ __forceinline__ bool brick_occupied(const VolArgs &v, const int i0[3])
+{
+    const int bx = i0[0] >> v.occ_log2, by = i0[1] >> v.occ_log2, bz = i0[2] >> v.occ_log2;
+    const bool in = ((uint32_t)bx < (uint32_t)v.nbx) & ((uint32_t)by < (uint32_t)v.nby) &
+                    ((uint32_t)bz < (uint32_t)v.nbz);
+    const uint32_t b =
+        __umul24(__umul24((uint32_t)bz, (uint32_t)v.nby) + (uint32_t)by, (uint32_t)v.nbx) + (uint32_t)bx;
+    const uint32_t w = v.occ[in ? (b >> 5) : 0u];
+    return !in | (((w >> (b & 31u)) & 1u) != 0u);
+}
+
 template <int F, int VAR>
 __device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
 {
@@ -93,7 +108,7 @@ __device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
 }
 
 // ---------------------------------------------------------------- ray march
-template <int F, bool HALF, int VAR, bool DBG>
+template <int F, bool HALF, int VAR, bool DBG, bool OCC>
 __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_pad)
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
@@ -122,6 +137,10 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
             int i0[3], o[3];
             float t[3];
             step_coords(g, kh, i0, t);
+            if constexpr (OCC) {
+                if (!brick_occupied(c.vol, i0))
+                    continue;   // the step would add exactly 0.0 to tau
+            }
             pick3<F, VAR>(t, h.at((uint32_t)k), o);
             int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
             if constexpr (DBG) {
@@ -142,7 +161,7 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
 // Weights and the per-step sums are binary64 (the same issue rate as
 // non-packed binary32 on this chip): with binary32 weights the 64 products
 // sum to 1 +- 3e-7, a bias that a 256-factor product would amplify.
-template <int F, bool HALF, int MODE>
+template <int F, bool HALF, int MODE, bool OCC>
 __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad)
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
@@ -166,6 +185,10 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
         float t[3];
         double wx[4], wy[4], wz[4];
         step_coords(g, kh, i0, t);
+        if constexpr (OCC) {
+            if (!brick_occupied(c.vol, i0))
+                continue;   // every tap is zero: before adds 0, after multiplies by sum w = 1
+        }
         if constexpr (F == NEAREST) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -278,8 +301,73 @@ __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
     c.out[i] = (float)sum;
 }
 
+// ---------------------------------------------------------- occupancy bricks
+// One lane per brick scans the brick grown by 2 voxels on every side; a
+// wave's 64 bits are gathered with a ballot and written as two words.
+template <bool HALF>
+__global__ __launch_bounds__(256) void k_build_occ(VolArgs v, int32_t lg, uint32_t *occ, int64_t words)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+    bool bit = false;
+    if (b < nb) {
+        const int bx = (int)(b % v.nbx), by = (int)((b / v.nbx) % v.nby), bz = (int)(b / ((int64_t)v.nbx * v.nby));
+        const int B = 1 << lg;
+        const int x0 = max(bx * B - 2, 0), x1 = min(bx * B + B + 2, v.nx);
+        const int y0 = max(by * B - 2, 0), y1 = min(by * B + B + 2, v.ny);
+        const int z0 = max(bz * B - 2, 0), z1 = min(bz * B + B + 2, v.nz);
+        for (int z = z0; z < z1 && !bit; ++z)
+            for (int y = y0; y < y1 && !bit; ++y) {
+                const int64_t row = ((int64_t)z * v.ny + y) * v.nx;
+                for (int x = x0; x < x1; ++x) {
+                    float val;
+                    if constexpr (HALF)
+                        val = half_bits_to_float(static_cast<const uint16_t *>(v.base)[row + x]);
+                    else
+                        val = static_cast<const float *>(v.base)[row + x];
+                    bit |= !(val == 0.0f);   // non-zero or NaN
+                }
+            }
+    }
+    const uint64_t m = __ballot(bit);
+    if ((threadIdx.x & 63) == 0) {
+        const int64_t w0 = b >> 5;   // b is a multiple of 64 here
+        if (w0 < words)
+            occ[w0] = (uint32_t)m;
+        if (w0 + 1 < words)
+            occ[w0 + 1] = (uint32_t)(m >> 32);
+    }
+}
+
+hipError_t launch_build_occupancy(const VolArgs &v, int32_t lg, uint32_t *occ, int64_t words, hipStream_t s)
+{
+    const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+    dim3 grid((uint32_t)((nb + 255) / 256)), block(256);
+    if (v.fmt == SF_R16F)
+        k_build_occ<true><<<grid, block, 0, s>>>(v, lg, occ, words);
+    else
+        k_build_occ<false><<<grid, block, 0, s>>>(v, lg, occ, words);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 static uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
+
+template <int F, bool HALF, bool OCC>
+static void launch_ray_fo(const RaymarchCall &c, dim3 grid, hipStream_t s, uint32_t nb_pad)
+{
+    dim3 block(256);
+    if (c.mode == STOCH) {
+        if (c.variant)
+            k_ray_stoch<F, HALF, 1, false, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_ray_stoch<F, HALF, 0, false, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+    } else if (c.mode == BEFORE) {
+        k_ray_det<F, HALF, BEFORE, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+    } else {
+        k_ray_det<F, HALF, AFTER, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+    }
+}
 
 template <int F, bool HALF>
 static hipError_t launch_ray_f(const RaymarchCall &c, hipStream_t s)
@@ -287,22 +375,16 @@ static hipError_t launch_ray_f(const RaymarchCall &c, hipStream_t s)
     uint32_t nb = blocks_for(c.n);
     uint32_t nb_pad = (nb + 7u) & ~7u;
     dim3 grid(nb_pad), block(256);
-    if (c.mode == STOCH) {
-        if (c.taps) {
-            if (c.variant)
-                k_ray_stoch<F, HALF, 1, true><<<grid, block, 0, s>>>(c, nb_pad);
-            else
-                k_ray_stoch<F, HALF, 0, true><<<grid, block, 0, s>>>(c, nb_pad);
-        } else {
-            if (c.variant)
-                k_ray_stoch<F, HALF, 1, false><<<grid, block, 0, s>>>(c, nb_pad);
-            else
-                k_ray_stoch<F, HALF, 0, false><<<grid, block, 0, s>>>(c, nb_pad);
-        }
-    } else if (c.mode == BEFORE) {
-        k_ray_det<F, HALF, BEFORE><<<grid, block, 0, s>>>(c, nb_pad);
+    if (c.mode == STOCH && c.taps) {
+        // the tap dump records every step, so it never skips empty bricks
+        if (c.variant)
+            k_ray_stoch<F, HALF, 1, true, false><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_ray_stoch<F, HALF, 0, true, false><<<grid, block, 0, s>>>(c, nb_pad);
+    } else if (c.vol.occ) {
+        launch_ray_fo<F, HALF, true>(c, grid, s, nb_pad);
     } else {
-        k_ray_det<F, HALF, AFTER><<<grid, block, 0, s>>>(c, nb_pad);
+        launch_ray_fo<F, HALF, false>(c, grid, s, nb_pad);
     }
     return hipGetLastError();
 }

@@ -49,11 +49,11 @@ def test_struct_layouts_match_header(sf):
     assert C.sizeof(sf.sf_sampling) == 20
     assert C.sizeof(sf.sf_tex2d) == 8 + 6 * 4 + 16 * 8
     assert C.sizeof(sf.sf_ggx) == 15 * 4
-    assert C.sizeof(sf.sf_volume) == 8 + 4 * 4 + 6 * 4
+    assert C.sizeof(sf.sf_volume) == 8 + 4 * 4 + 6 * 4 + 8 + 4 + 4
 
 
 def _vol(sf, **kw):
-    v = sf.sf_volume(0x1000, 8, 8, 8, sf.SF_R16F, (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(8, 8, 8))
+    v = sf.sf_volume(0x1000, 8, 8, 8, sf.SF_R16F, (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(8, 8, 8), None, 0, 0)
     for k, x in kw.items():
         setattr(v, k, x)
     return v
@@ -66,6 +66,7 @@ FAKE = C.c_void_p(0x10000)   # a host-side stand-in pointer: never dereferenced,
     ("n_negative", 2), ("n_zero", 0), ("null_rays", 1), ("steps_zero", 2), ("steps_big", 2),
     ("bad_filter", 2), ("bad_mode", 2), ("spp_zero", 2), ("bad_variant", 2), ("null_volume", 1),
     ("bad_format", 3), ("dims_zero", 2), ("scale_zero", 2), ("misaligned_rays", 2), ("n_huge", 2),
+    ("bad_brick", 2), ("reserved", 2),
 ])
 def test_raymarch_validation(sf, case, status):
     L = sf.lib()
@@ -102,6 +103,11 @@ def test_raymarch_validation(sf, case, status):
         rays = C.c_void_p(0x10004)
     elif case == "n_huge":
         n = 2 ** 31
+    elif case == "bad_brick":
+        vol.occupancy = 0x20000
+        vol.brick_log2 = 9
+    elif case == "reserved":
+        vol.reserved = 1
     st = L.sf_raymarch(C.byref(vol) if vol is not None else None, rays, n, steps, C.byref(smp), T, None, None)
     assert st == status, sf.sf_last_error()
     if status:
@@ -180,3 +186,15 @@ def test_product_path_has_no_fallback(sf, monkeypatch, tmp_path):
     monkeypatch.setattr(sf, "_lib", None)
     with pytest.raises(ImportError):
         sf.lib()
+
+
+def test_occupancy_words_and_validation(sf):
+    assert sf.sf_occupancy_words(512, 512, 512, 3) == 64 ** 3 // 32
+    assert sf.sf_occupancy_words(10, 9, 8, 2) == -(-(3 * 3 * 2) // 32)
+    assert sf.sf_occupancy_words(8, 8, 8, 0) == 0
+    L = sf.lib()
+    vol = _vol(sf, brick_log2=2)
+    assert L.sf_build_occupancy(C.byref(vol), FAKE, 0, None) == 2         # too few words
+    vol.brick_log2 = 7
+    assert L.sf_build_occupancy(C.byref(vol), FAKE, 100, None) == 2
+    assert L.sf_build_occupancy(None, FAKE, 100, None) == 1

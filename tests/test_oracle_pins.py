@@ -497,3 +497,33 @@ def test_raymarch_border_zero_and_nonfinite(orc):
     T, taps = orc.raymarch(g, rays, 8, orc.BSPLINE3, orc.STOCHASTIC, taps=True)
     assert T[0] == 1.0 and np.isnan(T[1]) and T[2] == 1.0
     assert np.all(taps[1] == orc.TAP_NONE) and np.all(taps[2] == orc.TAP_NONE)
+
+
+def test_occupancy_mask_property(orc):
+    """A clear occupancy bit means every filter tap around any point of the
+    brick reads zero (so skipping the step is exact); a set bit means a
+    non-zero voxel lies within 2 voxels of the brick."""
+    data = inputs.cloud_grid(24, seed=6).numpy()
+    data[:, :, 12:] = 0.0
+    g = _grid(data)
+    lg, B = 2, 4
+    words = orc.build_occupancy(g, lg)
+    nb = 24 // B
+    rng = np.random.default_rng(0)
+    n_clear = 0
+    for bz in range(nb):
+        for by in range(nb):
+            for bx in range(nb):
+                b = (bz * nb + by) * nb + bx
+                bit = (words[b >> 5] >> (b & 31)) & 1
+                lo = np.array([bx, by, bz]) * B
+                sl = tuple(slice(max(c - 2, 0), c + B + 2) for c in (lo[2], lo[1], lo[0]))
+                assert bit == int(np.any(data[sl] != 0))
+                if not bit:
+                    n_clear += 1
+                    # points whose floor(raster) lies in the brick
+                    p = (lo[None] + rng.random((20, 3)) * B + 0.5) / 24.0
+                    for filt in (orc.LINEAR, orc.BSPLINE3):
+                        v = orc.filter3d(g, p.astype(np.float32), filt, orc.BEFORE)
+                        assert np.all(v == 0.0)
+    assert n_clear > 0

@@ -164,6 +164,12 @@ def test_raymarch_full_size_sampled(sf, orc, full_cloud, filt, mode):
     smp = sf.sampling(f, m, 1, seed=2024)
     rays_d = torch.from_numpy(rays).cuda()
     T = sf.sf_raymarch(vol, rays_d, steps, smp).cpu().numpy()
+    vol_skip = sf.Volume(data, side=side, brick_log2=3)            # the benchmark's configuration
+    T_skip = sf.sf_raymarch(vol_skip, rays_d, steps, smp).cpu().numpy()
+    if m == orc.STOCHASTIC:
+        assert np.array_equal(T, T_skip)
+    else:
+        _close(T_skip, T, rtol=1e-12, atol=1e-15)
     rng = np.random.default_rng(5)
     sub = np.sort(rng.choice(rays.shape[0], 400, replace=False))
     ref = orc.raymarch(og, rays, steps, f, m, spp=1, seed=2024, subset=sub)
@@ -177,6 +183,41 @@ def test_raymarch_full_size_sampled(sf, orc, full_cloud, filt, mode):
         assert np.array_equal(taps_d.cpu().numpy(), taps)
         _close(Tk.cpu().numpy(), refk)
         assert np.array_equal(Tk.cpu().numpy(), T[:k])
+
+
+@pytest.mark.parametrize("lg", [1, 2, 3])
+def test_occupancy_parity(sf, orc, small_cloud, lg):
+    _print_case("occupancy_parity", lg)
+    data = small_cloud.copy()
+    data[:, :, 30:] = 0.0                                  # a slab of empty space
+    og, vol = _grids(orc, sf, data)
+    occ = sf.sf_build_occupancy(vol, lg).cpu().numpy().view(np.uint32)
+    ref = orc.build_occupancy(og, lg)
+    assert np.array_equal(occ[:ref.size], ref)
+
+
+@pytest.mark.parametrize("filt", ["LINEAR", "BSPLINE3"])
+def test_raymarch_occupancy_skip_is_exact(sf, orc, small_cloud, filt):
+    """Skipping empty bricks leaves the stochastic result bit-identical and
+    the deterministic ones equal up to float64 rounding; the oracle agrees."""
+    _print_case("raymarch_occupancy_skip", filt)
+    data = small_cloud.copy()
+    data[:, :, 30:] = 0.0
+    og, plain = _grids(orc, sf, data)
+    nz, ny, nx = data.shape
+    skip = sf.Volume(plain.data, scale=(nx, ny, nz), brick_log2=2)
+    rays_d = torch.from_numpy(inputs.random_rays(3001, 1.0, seed=21)).cuda()
+    f = getattr(sf, "SF_" + filt)
+    for mode, spp in ((sf.SF_STOCHASTIC, 1), (sf.SF_STOCHASTIC, 2), (sf.SF_BEFORE, 1), (sf.SF_AFTER_EXACT, 1)):
+        smp = sf.sampling(f, mode, spp, seed=13)
+        a = sf.sf_raymarch(plain, rays_d, 40, smp).cpu().numpy()
+        b = sf.sf_raymarch(skip, rays_d, 40, smp).cpu().numpy()
+        if mode == sf.SF_STOCHASTIC:
+            assert np.array_equal(a, b, equal_nan=True)
+        else:
+            _close(b, a, rtol=1e-12, atol=1e-15)
+        ref = orc.raymarch(og, rays_d.cpu().numpy(), 40, getattr(orc, filt), mode, spp=spp, seed=13)
+        _close(b, ref)
 
 
 # ------------------------------------------------------------------ 2-D
