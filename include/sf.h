@@ -213,6 +213,118 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
 sf_status sf_build_occupancy(const sf_volume *vol, uint32_t *occupancy, int64_t words, void *stream);
 int64_t sf_occupancy_words(int32_t nx, int32_t ny, int32_t nz, int32_t brick_log2);
 
+/* --------------------------------------------------------------------------
+ * Neural latent textures and volumes.  A lattice of latent vectors z_c is
+ * decoded by a 3-layer MLP, D_c = W3^T relu(W2^T relu(W1^T z_c + b1) + b2) + b3
+ * (hidden width 64).  Filtering picks lattice points exactly as the plain
+ * filters pick texels, so the stochastic estimator decodes ONE latent per
+ * sample instead of all 16 (bicubic) or 64 (tricubic) taps (Sec. 4.1 FRS; the
+ * paper motivates stochastic filtering by the cost of evaluating an expensive
+ * decoder per tap, Sec. 1 and the compressed-texture results of Sec. 5).
+ * Supported shapes: 2-D with 8 channels and 4 outputs (RGBA), 3-D with 16
+ * channels and 1 output (density).  Decoding runs on the matrix cores with
+ * BF16 operands and FP32 accumulation.
+ * ------------------------------------------------------------------------ */
+enum { SF_LATENT_F32 = 0, SF_LATENT_BF16 = 1, SF_LATENT_FP8E4M3 = 2 };
+
+/* Lattice point (x, y, z) stores channels at latents + ((z*res[1] + y)*res[0]
+ * + x)*channels.  SF_LATENT_FP8E4M3 (OCP E4M3, saturating): value = code *
+ * block_scale[b], b the block of side 2^block_log2 lattice points holding the
+ * point, blocks numbered x fastest.  2-D grids use res[2] = 1 and map a
+ * texture coordinate u to raster p = u*res - 0.5 with repeat wrap; 3-D grids
+ * map world x to p = (x - wmin)*scale - 0.5 and read zero outside. */
+typedef struct sf_latent_grid {
+    const void *latents;
+    const float *block_scale; /* E4M3 only */
+    int32_t dims;             /* 2 or 3 */
+    int32_t res[3];
+    int32_t channels;         /* 8 (2-D) or 16 (3-D) */
+    int32_t format;           /* SF_LATENT_BF16 | SF_LATENT_FP8E4M3 for decoding */
+    int32_t block_log2;       /* E4M3 block side 2^block_log2, 1..6 */
+    float wmin[3], scale[3];  /* 3-D only */
+} sf_latent_grid;
+
+/* Packed MLP parameters W1 [in x 64], b1 [64], W2 [64 x 64], b2 [64],
+ * W3 [64 x out], b3 [out], row-major; BF16 bits for decoding. */
+typedef struct sf_mlp {
+    const void *params;
+    int32_t in_dim, hidden, out_dim;
+    int32_t reserved; /* must be 0 */
+} sf_mlp;
+
+/* Number of packed MLP parameters (in*h + h + h*h + h + h*out + out). */
+int64_t sf_mlp_nparams(int32_t in_dim, int32_t hidden, int32_t out_dim);
+
+/*
+ * sf_neural_decode — filtered lookups in a 2-D neural texture.
+ *   As sf_filter2d on level 0 with repeat wrap, the decoded texel of lattice
+ *   point c being clamp(D_c, 0, 1) = (albedo RGB, roughness parameter A).
+ *   SF_STOCHASTIC: one decode per sample; SF_AFTER_EXACT: sum_c w_c
+ *   shade(D_c); SF_BEFORE: shade(sum_c w_c D_c).  dbg_taps: n x spp x {x, y}.
+ * Errors: as sf_filter2d; SF_E_UNSUPPORTED for other shapes or formats.
+ */
+sf_status sf_neural_decode(const sf_latent_grid *grid, const sf_mlp *mlp, const float *queries, int64_t n,
+                           const sf_sampling *smp, int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps,
+                           void *stream);
+
+/*
+ * sf_neural_raymarch — sf_raymarch through a 3-D neural density volume,
+ * sigma_c = max(D_c, 0).  SF_STOCHASTIC only (the deterministic forms would
+ * decode 8 or 64 lattice points per step; the CPU reference computes them).
+ * Errors: as sf_raymarch; SF_E_UNSUPPORTED for other modes, shapes, formats.
+ */
+sf_status sf_neural_raymarch(const sf_latent_grid *grid, const sf_mlp *mlp, const float *rays, int64_t n,
+                             int32_t steps, const sf_sampling *smp, float *T, int32_t *dbg_taps, void *stream);
+
+/*
+ * sf_neural_decode_lattice — raw MLP outputs (no clamp) at n lattice points.
+ *   lattice_idx: n int64 linear lattice indices; out: n x out_dim float32.
+ */
+sf_status sf_neural_decode_lattice(const sf_latent_grid *grid, const sf_mlp *mlp, const int64_t *lattice_idx,
+                                   int64_t n, float *out, void *stream);
+
+/*
+ * sf_to_bf16 — binary32 -> bfloat16 bits, round to nearest even (n values).
+ */
+sf_status sf_to_bf16(const float *in, int64_t n, uint16_t *out, void *stream);
+
+/*
+ * sf_neural_quantize — FP32 latents -> the format grid->format names:
+ *   BF16: round to nearest even; E4M3: per block s = amax/448 (binary32,
+ *   1 for an all-zero block), code = E4M3(z/s) round to nearest even,
+ *   saturating.  Writes out_latents (and out_scales, one per block, E4M3).
+ */
+sf_status sf_neural_quantize(const float *latents, const sf_latent_grid *grid, void *out_latents, float *out_scales,
+                             void *stream);
+
+/* Training state, all FP32 device arrays updated in place by a step:
+ * latents [n_lattice x channels], params (packed, sf_mlp layout), and the
+ * Adam moments of both. */
+typedef struct sf_train_state {
+    float *latents, *params, *m_latents, *v_latents, *m_params, *v_params;
+    int64_t n_lattice;
+    int32_t channels, hidden, out_dim;
+    int32_t reserved; /* must be 0 */
+} sf_train_state;
+
+/*
+ * sf_neural_train_step — one Adam step (beta 0.9/0.999, eps 1e-8, bias
+ * correction with `step` >= 1) on the loss (1/B) sum_s ||D(z_{i_s}) -
+ * t_{i_s}||^2 over the batch lattice points i_s = batch_idx[s] (distinct:
+ * each batch entry updates its own latent; duplicates race).  All gradients
+ * are taken at the current values, then latents and parameters move.
+ *   targets: n_lattice x out_dim; loss_out: 1 float (device), the batch loss;
+ *   grad_params (nullable): the summed parameter gradient; grad_latents
+ *   (nullable): batch x channels latent gradients.
+ *   workspace: sf_neural_train_workspace() bytes of device scratch.
+ * Errors: SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED (shape), SF_E_WORKSPACE.
+ */
+sf_status sf_neural_train_step(const sf_train_state *st, const int32_t *batch_idx, const float *targets,
+                               int64_t batch, int32_t step, float lr_latent, float lr_mlp, float *loss_out,
+                               float *grad_params, float *grad_latents, void *workspace, size_t workspace_bytes,
+                               void *stream);
+size_t sf_neural_train_workspace(int32_t channels, int32_t out_dim, int64_t batch);
+
 /*
  * sf_error_stats — error statistics of an estimate against a reference,
  * reduced in float64 on the GPU in a fixed order (bit-reproducible).

@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "neural.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # enums of the oracle (its own copy; it does not include the library header)
@@ -30,10 +31,11 @@ TAP_NONE = np.iinfo(np.int32).min
 
 def build(force: bool = False) -> str:
     """Compile ``oracle.c`` with gcc (OpenMP, no FP contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-fvisibility=hidden", _SRC, "-o", tmp, "-lm"]
+               "-fno-fast-math", "-fvisibility=hidden", *_SRCS, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -74,6 +76,23 @@ def lib():
                                    P, P, P, i64]
         L.orc_raymarch_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
         L.orc_build_occupancy.argtypes = [P, i32, i32, i32, i32, i32, P]
+        L.orc_f32_to_bf16.restype = C.c_uint16
+        L.orc_f32_to_bf16.argtypes = [f32]
+        L.orc_bf16_to_double.restype = C.c_double
+        L.orc_bf16_to_double.argtypes = [C.c_uint16]
+        L.orc_fp8_to_double.restype = C.c_double
+        L.orc_fp8_to_double.argtypes = [C.c_uint8]
+        L.orc_f32_to_fp8.restype = C.c_uint8
+        L.orc_f32_to_fp8.argtypes = [f32]
+        L.orc_quantize_fp8.argtypes = [P, i32, P, i32, i32, P, P]
+        L.orc_mlp_forward.argtypes = [i32, i32, i32, P, P, i64, i32, P]
+        L.orc_mlp_grad.restype = C.c_double
+        L.orc_mlp_grad.argtypes = [i32, i32, i32, P, P, P, i64, P, P]
+        L.orc_adam.argtypes = [P, P, P, P, i64, i32, C.c_double]
+        L.orc_neural_filter2d.argtypes = [i32, i32, i32, i32, i32, P, P, i32, P, i64, i32, i32, i32, u32, i32, P,
+                                          P, P, P, i64]
+        L.orc_neural_raymarch.argtypes = [i32, i32, i32, i32, i32, P, P, i32, P, P, P, i64, i32, i32, i32, i32,
+                                          u32, P, P, P, i64]
         _lib = L
     return _lib
 
@@ -274,3 +293,102 @@ def build_occupancy(g: Grid, brick_log2: int) -> np.ndarray:
     words = np.zeros((nb + 31) // 32, dtype=np.uint32)
     lib().orc_build_occupancy(_p(g.data), g.nx, g.ny, g.nz, g.fmt, brick_log2, _p(words))
     return words
+
+
+# ------------------------------------------------------------------ neural
+def f32_to_bf16(x) -> np.ndarray:
+    """Vectorised over an array via the oracle's scalar routine (slow; tests only)."""
+    x = np.asarray(x, dtype=np.float32)
+    f = lib().orc_f32_to_bf16
+    return np.array([f(float(v)) for v in x.ravel()], dtype=np.uint16).reshape(x.shape)
+
+
+def bf16_to_double(b) -> np.ndarray:
+    b = np.asarray(b, dtype=np.uint16)
+    f = lib().orc_bf16_to_double
+    return np.array([f(int(v)) for v in b.ravel()]).reshape(b.shape)
+
+
+def fp8_table() -> np.ndarray:
+    """binary64 value of each of the 256 E4M3 codes."""
+    return np.array([lib().orc_fp8_to_double(c) for c in range(256)])
+
+
+def f32_to_fp8(x: float) -> int:
+    return int(lib().orc_f32_to_fp8(float(x)))
+
+
+def quantize_fp8(lat: np.ndarray, dims: int, res, C: int, block_log2: int):
+    lat = _c(lat, np.float32)
+    r = np.array(list(res) + [1] * (3 - len(res)), dtype=np.int32)
+    B = 1 << block_log2
+    nb = int(np.prod([-(-int(r[a]) // B) for a in range(dims)]))
+    codes = np.zeros(lat.size, dtype=np.uint8)
+    scales = np.zeros(nb, dtype=np.float32)
+    lib().orc_quantize_fp8(_p(lat), dims, _p(r), C, block_log2, _p(codes), _p(scales))
+    return codes, scales
+
+
+def mlp_nparams(C: int, H: int, O: int) -> int:
+    return C * H + H + H * H + H + H * O + O
+
+
+def mlp_forward(C, H, O, P, Z, act_bf16=False):
+    P = _c(P, np.float64)
+    Z = _c(Z, np.float64).reshape(-1, C)
+    Y = np.zeros((Z.shape[0], O))
+    lib().orc_mlp_forward(C, H, O, _p(P), _p(Z), Z.shape[0], int(act_bf16), _p(Y))
+    return Y
+
+
+def mlp_grad(C, H, O, P, Z, T):
+    P = _c(P, np.float64)
+    Z = _c(Z, np.float64).reshape(-1, C)
+    T = _c(T, np.float64).reshape(-1, O)
+    gP = np.zeros(P.size)
+    gZ = np.zeros_like(Z)
+    loss = lib().orc_mlp_grad(C, H, O, _p(P), _p(Z), _p(T), Z.shape[0], _p(gP), _p(gZ))
+    return loss, gP, gZ
+
+
+def adam(theta, m, v, g, step, lr):
+    """In place on float64 arrays."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _c(g, np.float64)
+    lib().orc_adam(_p(theta), _p(m), _p(v), _p(g), theta.size, step, float(lr))
+
+
+def neural_filter2d(res, C, H, O, Z, P, q, filt, mode, spp=1, seed=0, shade=0, ggx=None, act_bf16=True,
+                    taps=False, subset=None):
+    Z = _c(Z, np.float64)
+    P = _c(P, np.float64)
+    q = _c(q, np.float32).reshape(-1, 3)
+    n = q.shape[0]
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
+    ch = 3 if shade == 1 else O
+    out = np.zeros((m, ch))
+    tp = np.zeros((m, spp, 2), dtype=np.int32) if taps else None
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_neural_filter2d(res[0], res[1], C, H, O, _p(Z), _p(P), int(act_bf16), _p(q), n, filt, mode, spp,
+                              seed & 0xFFFFFFFF, shade, _p(g), _p(out), _p(tp), _p(sub), 0 if sub is None else sub.size)
+    return (out, tp) if taps else out
+
+
+def neural_raymarch(res, C, H, Z, P, wmin, scale, rays, steps, filt, mode, spp=1, seed=0, act_bf16=True,
+                    taps=False, subset=None):
+    Z = _c(Z, np.float64)
+    P = _c(P, np.float64)
+    rays = _c(rays, np.float32).reshape(-1, 8)
+    n = rays.shape[0]
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
+    T = np.zeros(m)
+    tp = np.zeros((m, spp, steps, 3), dtype=np.int32) if taps else None
+    wmin = _c(wmin, np.float32)
+    scale = _c(scale, np.float32)
+    lib().orc_neural_raymarch(res[0], res[1], res[2], C, H, _p(Z), _p(P), int(act_bf16), _p(wmin), _p(scale),
+                              _p(rays), n, steps, filt, mode, spp, seed & 0xFFFFFFFF, _p(T), _p(tp), _p(sub),
+                              0 if sub is None else sub.size)
+    return (T, tp) if taps else T

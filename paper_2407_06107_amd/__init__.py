@@ -30,7 +30,10 @@ SF_TAP_NONE = -(2 ** 31)
 SF_MAX_LEVELS = 16
 
 EXPORTED = ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_build_occupancy", "sf_occupancy_words",
+            "sf_mlp_nparams", "sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
+            "sf_neural_quantize", "sf_neural_train_step", "sf_neural_train_workspace",
             "sf_error_stats", "sf_error_stats_workspace", "sf_last_error", "sf_abi_version", "sf_rng_version")
+SF_LATENT_F32, SF_LATENT_BF16, SF_LATENT_FP8E4M3 = 0, 1, 2
 
 
 class sf_sampling(C.Structure):
@@ -53,6 +56,24 @@ class sf_volume(C.Structure):
     _fields_ = [("base", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("format", C.c_int32), ("wmin", C.c_float * 3), ("scale", C.c_float * 3),
                 ("occupancy", C.c_void_p), ("brick_log2", C.c_int32), ("reserved", C.c_int32)]
+
+
+class sf_latent_grid(C.Structure):
+    _fields_ = [("latents", C.c_void_p), ("block_scale", C.c_void_p), ("dims", C.c_int32), ("res", C.c_int32 * 3),
+                ("channels", C.c_int32), ("format", C.c_int32), ("block_log2", C.c_int32),
+                ("wmin", C.c_float * 3), ("scale", C.c_float * 3)]
+
+
+class sf_mlp(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("in_dim", C.c_int32), ("hidden", C.c_int32), ("out_dim", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class sf_train_state(C.Structure):
+    _fields_ = [("latents", C.c_void_p), ("params", C.c_void_p), ("m_latents", C.c_void_p),
+                ("v_latents", C.c_void_p), ("m_params", C.c_void_p), ("v_params", C.c_void_p),
+                ("n_lattice", C.c_int64), ("channels", C.c_int32), ("hidden", C.c_int32), ("out_dim", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class SFError(RuntimeError):
@@ -81,6 +102,19 @@ def lib() -> C.CDLL:
         L.sf_build_occupancy.restype = i32
         L.sf_occupancy_words.argtypes = [i32, i32, i32, i32]
         L.sf_occupancy_words.restype = i64
+        L.sf_mlp_nparams.argtypes = [i32, i32, i32]
+        L.sf_mlp_nparams.restype = i64
+        L.sf_neural_decode.argtypes = [P, P, P, i64, P, i32, P, P, P, P]
+        L.sf_neural_raymarch.argtypes = [P, P, P, i64, i32, P, P, P, P]
+        L.sf_neural_decode_lattice.argtypes = [P, P, P, i64, P, P]
+        L.sf_to_bf16.argtypes = [P, i64, P, P]
+        L.sf_neural_quantize.argtypes = [P, P, P, P, P]
+        L.sf_neural_train_step.argtypes = [P, P, P, i64, i32, C.c_float, C.c_float, P, P, P, P, C.c_size_t, P]
+        L.sf_neural_train_workspace.argtypes = [i32, i32, i64]
+        L.sf_neural_train_workspace.restype = C.c_size_t
+        for f in ("sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
+                  "sf_neural_quantize", "sf_neural_train_step"):
+            getattr(L, f).restype = i32
         L.sf_error_stats_workspace.argtypes = [i64]
         L.sf_error_stats_workspace.restype = C.c_size_t
         for f in ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_error_stats"):
@@ -292,3 +326,162 @@ def sf_error_stats(est: torch.Tensor, ref: torch.Tensor, out: torch.Tensor | Non
     _check(lib().sf_error_stats(_ptr(est), _ptr(ref), count, 1, _ptr(out), _ptr(workspace), workspace.numel(),
                                 _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------ neural
+def sf_mlp_nparams(in_dim: int, hidden: int, out_dim: int) -> int:
+    return int(lib().sf_mlp_nparams(in_dim, hidden, out_dim))
+
+
+def sf_to_bf16(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """bfloat16 bits (int16 tensor) of a float32 tensor, round to nearest even."""
+    _need(x, torch.float32, "x")
+    if out is None:
+        out = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _need(out, torch.int16, "out")
+    _check(lib().sf_to_bf16(_ptr(x), x.numel(), _ptr(out), _stream(stream)))
+    return out
+
+
+class LatentGrid:
+    """Device latent grid (BF16 or E4M3 + block scales) and its descriptor."""
+
+    def __init__(self, dims, res, channels, fmt, latents, scales=None, block_log2=0, wmin=(0.0, 0.0, 0.0),
+                 scale=(1.0, 1.0, 1.0)):
+        self.latents, self.scales = latents, scales
+        r = list(res) + [1] * (3 - len(res))
+        self.desc = sf_latent_grid(latents.data_ptr(), scales.data_ptr() if scales is not None else None, dims,
+                                   (C.c_int32 * 3)(*r), channels, fmt, block_log2, (C.c_float * 3)(*wmin),
+                                   (C.c_float * 3)(*scale))
+
+
+def sf_neural_quantize(latents: torch.Tensor, dims: int, res, channels: int, fmt: int, block_log2: int = 3,
+                       wmin=(0.0, 0.0, 0.0), scale=(1.0, 1.0, 1.0), stream=None) -> LatentGrid:
+    _need(latents, torch.float32, "latents")
+    r = list(res) + [1] * (3 - len(res))
+    npts = r[0] * r[1] * r[2]
+    if latents.numel() != npts * channels:
+        raise ValueError("latents do not match res x channels")
+    if fmt == SF_LATENT_BF16:
+        out = torch.empty(npts * channels, dtype=torch.int16, device=latents.device)
+        scales = None
+    elif fmt == SF_LATENT_FP8E4M3:
+        out = torch.empty(npts * channels, dtype=torch.uint8, device=latents.device)
+        B = 1 << block_log2
+        nb = 1
+        for a in range(dims):
+            nb *= -(-r[a] // B)
+        scales = torch.empty(nb, dtype=torch.float32, device=latents.device)
+    else:
+        raise ValueError("fmt must be SF_LATENT_BF16 or SF_LATENT_FP8E4M3")
+    grid = LatentGrid(dims, r, channels, fmt, out, scales, block_log2 if fmt == SF_LATENT_FP8E4M3 else 0, wmin,
+                      scale)
+    _check(lib().sf_neural_quantize(_ptr(latents), C.byref(grid.desc), _ptr(out), _ptr(scales), _stream(stream)))
+    return grid
+
+
+class MLP:
+    """BF16 packed MLP parameters for decoding."""
+
+    def __init__(self, params_f32: torch.Tensor, in_dim: int, out_dim: int, hidden: int = 64, stream=None):
+        _need(params_f32, torch.float32, "params")
+        if params_f32.numel() != sf_mlp_nparams(in_dim, hidden, out_dim):
+            raise ValueError("parameter count does not match the shape")
+        self.bits = sf_to_bf16(params_f32, stream=stream)
+        self.desc = sf_mlp(self.bits.data_ptr(), in_dim, hidden, out_dim, 0)
+
+
+def sf_neural_decode(grid: LatentGrid, mlp: MLP, queries: torch.Tensor, smp: sf_sampling, shade: int = SF_SHADE_NONE,
+                     ggx_params: sf_ggx | None = None, out: torch.Tensor | None = None,
+                     dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    _need(queries, torch.float32, "queries")
+    n = queries.numel() // 3
+    ch = 3 if shade == SF_SHADE_GGX else 4
+    if out is None:
+        out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
+    _need(out, torch.float32, "out")
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps")
+        if dbg_taps.numel() < n * smp.spp * 2:
+            raise ValueError("dbg_taps too small")
+    g = C.byref(ggx_params) if ggx_params is not None else None
+    _check(lib().sf_neural_decode(C.byref(grid.desc), C.byref(mlp.desc), _ptr(queries), n, C.byref(smp), shade, g,
+                                  _ptr(out), _ptr(dbg_taps), _stream(stream)))
+    return out
+
+
+def sf_neural_raymarch(grid: LatentGrid, mlp: MLP, rays: torch.Tensor, steps: int, smp: sf_sampling,
+                       T: torch.Tensor | None = None, dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    _need(rays, torch.float32, "rays")
+    n = rays.numel() // 8
+    if T is None:
+        T = torch.empty(n, dtype=torch.float32, device=rays.device)
+    _need(T, torch.float32, "T")
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps")
+        if dbg_taps.numel() < n * smp.spp * steps * 3:
+            raise ValueError("dbg_taps too small")
+    _check(lib().sf_neural_raymarch(C.byref(grid.desc), C.byref(mlp.desc), _ptr(rays), n, steps, C.byref(smp),
+                                    _ptr(T), _ptr(dbg_taps), _stream(stream)))
+    return T
+
+
+def sf_neural_decode_lattice(grid: LatentGrid, mlp: MLP, idx: torch.Tensor, out: torch.Tensor | None = None,
+                             stream=None) -> torch.Tensor:
+    _need(idx, torch.int64, "idx")
+    n = idx.numel()
+    if out is None:
+        out = torch.empty((n, mlp.desc.out_dim), dtype=torch.float32, device=idx.device)
+    _need(out, torch.float32, "out")
+    _check(lib().sf_neural_decode_lattice(C.byref(grid.desc), C.byref(mlp.desc), _ptr(idx), n, _ptr(out),
+                                          _stream(stream)))
+    return out
+
+
+class TrainState:
+    """FP32 master latents and MLP parameters with their Adam moments."""
+
+    def __init__(self, latents: torch.Tensor, params: torch.Tensor, channels: int, out_dim: int, hidden: int = 64):
+        _need(latents, torch.float32, "latents")
+        _need(params, torch.float32, "params")
+        self.latents, self.params = latents, params
+        self.m_lat, self.v_lat = torch.zeros_like(latents), torch.zeros_like(latents)
+        self.m_par, self.v_par = torch.zeros_like(params), torch.zeros_like(params)
+        self.channels, self.out_dim, self.hidden = channels, out_dim, hidden
+        self.n_lattice = latents.numel() // channels
+        self.step = 0
+        self.desc = sf_train_state(latents.data_ptr(), params.data_ptr(), self.m_lat.data_ptr(),
+                                   self.v_lat.data_ptr(), self.m_par.data_ptr(), self.v_par.data_ptr(),
+                                   self.n_lattice, channels, hidden, out_dim, 0)
+        self._ws = None
+
+
+def sf_neural_train_workspace(channels: int, out_dim: int, batch: int) -> int:
+    return int(lib().sf_neural_train_workspace(channels, out_dim, batch))
+
+
+def sf_neural_train_step(st: TrainState, batch_idx: torch.Tensor, targets: torch.Tensor, lr_latent: float,
+                         lr_mlp: float, loss_out: torch.Tensor | None = None, grad_params: torch.Tensor | None = None,
+                         grad_latents: torch.Tensor | None = None, step: int | None = None,
+                         workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """One Adam step; returns the device loss tensor (1 float)."""
+    _need(batch_idx, torch.int32, "batch_idx")
+    _need(targets, torch.float32, "targets")
+    B = batch_idx.numel()
+    if step is None:
+        st.step += 1
+        step = st.step
+    if loss_out is None:
+        loss_out = torch.empty(1, dtype=torch.float32, device=batch_idx.device)
+    need = sf_neural_train_workspace(st.channels, st.out_dim, B)
+    if workspace is None:
+        if st._ws is None or st._ws.numel() < need:
+            st._ws = torch.empty(max(need, 4), dtype=torch.uint8, device=batch_idx.device)
+        workspace = st._ws
+    for t, name in ((grad_params, "grad_params"), (grad_latents, "grad_latents")):
+        if t is not None:
+            _need(t, torch.float32, name)
+    _check(lib().sf_neural_train_step(C.byref(st.desc), _ptr(batch_idx), _ptr(targets), B, step, lr_latent, lr_mlp,
+                                      _ptr(loss_out), _ptr(grad_params), _ptr(grad_latents), _ptr(workspace),
+                                      workspace.numel(), _stream(stream)))
+    return loss_out

@@ -310,6 +310,264 @@ sf_status sf_build_occupancy(const sf_volume *vol, uint32_t *occupancy, int64_t 
     return device_status(sfk::launch_build_occupancy(a, v.brick_log2, occupancy, words, (hipStream_t)stream));
 }
 
+// ---------------------------------------------------------------- neural
+int64_t sf_mlp_nparams(int32_t in_dim, int32_t hidden, int32_t out_dim)
+{
+    if (in_dim < 1 || hidden < 1 || out_dim < 1)
+        return 0;
+    return (int64_t)in_dim * hidden + hidden + (int64_t)hidden * hidden + hidden + (int64_t)hidden * out_dim + out_dim;
+}
+
+static sf_status check_grid(const sf_latent_grid *g, bool need_data, sfk::LatentArgs &a)
+{
+    if (!g)
+        return fail(SF_E_NULL, "latent grid descriptor is NULL");
+    if (g->dims != 2 && g->dims != 3)
+        return fail(SF_E_RANGE, "latent grid dims %d must be 2 or 3", g->dims);
+    const int32_t r2 = g->dims == 2 ? 1 : g->res[2];
+    if (g->res[0] < 1 || g->res[1] < 1 || r2 < 1 || g->res[0] > 65536 || g->res[1] > 65536 || r2 > 4096)
+        return fail(SF_E_RANGE, "latent grid resolution out of range");
+    if ((int64_t)g->res[0] * g->res[1] * r2 > (1LL << 31))
+        return fail(SF_E_UNSUPPORTED, "more than 2^31 lattice points");
+    if (g->channels != (g->dims == 2 ? 8 : 16))
+        return fail(SF_E_UNSUPPORTED, "%d-D latent grids have %d channels here", g->dims, g->dims == 2 ? 8 : 16);
+    if (g->format != SF_LATENT_BF16 && g->format != SF_LATENT_FP8E4M3)
+        return fail(SF_E_UNSUPPORTED, "latent format %d: BF16 or E4M3", g->format);
+    if (g->format == SF_LATENT_FP8E4M3 && (g->block_log2 < 1 || g->block_log2 > 6))
+        return fail(SF_E_RANGE, "block_log2 %d outside 1..6", g->block_log2);
+    if (need_data) {
+        if (!g->latents || (g->format == SF_LATENT_FP8E4M3 && !g->block_scale))
+            return fail(SF_E_NULL, "latents (and E4M3 block scales) must be non-NULL");
+        if (!aligned(g->latents, 16) || (g->block_scale && !aligned(g->block_scale, 4)))
+            return fail(SF_E_RANGE, "latents must be 16-byte aligned");
+    }
+    if (g->dims == 3)
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(g->wmin[k]) || !std::isfinite(g->scale[k]) || g->scale[k] == 0.0f)
+                return fail(SF_E_RANGE, "latent grid wmin/scale must be finite, scale non-zero");
+    a.latents = g->latents;
+    a.scales = g->block_scale;
+    a.dims = g->dims;
+    a.res[0] = g->res[0];
+    a.res[1] = g->res[1];
+    a.res[2] = r2;
+    a.C = g->channels;
+    a.fmt = g->format;
+    a.block_log2 = g->format == SF_LATENT_FP8E4M3 ? g->block_log2 : 0;
+    for (int k = 0; k < 3; ++k) {
+        a.wmin[k] = g->wmin[k];
+        a.scale[k] = g->scale[k];
+    }
+    return SF_OK;
+}
+
+static sf_status check_mlp(const sf_mlp *m, const sfk::LatentArgs &g, sfk::MlpArgs &a)
+{
+    if (!m || !m->params)
+        return fail(SF_E_NULL, "MLP descriptor or parameters NULL");
+    const int32_t out = g.dims == 2 ? 4 : 1;
+    if (m->in_dim != g.C || m->hidden != 64 || m->out_dim != out || m->reserved != 0)
+        return fail(SF_E_UNSUPPORTED, "MLP %d-%d-%d: this grid needs %d-64-%d", m->in_dim, m->hidden, m->out_dim,
+                    g.C, out);
+    if (!aligned(m->params, 2))
+        return fail(SF_E_RANGE, "MLP parameters misaligned");
+    a.params = m->params;
+    a.in_dim = m->in_dim;
+    a.out_dim = m->out_dim;
+    return SF_OK;
+}
+
+sf_status sf_neural_decode(const sf_latent_grid *grid, const sf_mlp *mlp, const float *queries, int64_t n,
+                           const sf_sampling *smp, int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps,
+                           void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (n == 0)
+        return ok();
+    if (!queries || !out)
+        return fail(SF_E_NULL, "queries and out must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    if (smp->rng_variant != 0)
+        return fail(SF_E_UNSUPPORTED, "neural decoding uses independent uniforms (rng_variant 0)");
+    sfk::NeuralCall c{};
+    if ((st = check_grid(grid, true, c.lat)) != SF_OK)
+        return st;
+    if (c.lat.dims != 2)
+        return fail(SF_E_UNSUPPORTED, "sf_neural_decode takes a 2-D grid");
+    if ((st = check_mlp(mlp, c.lat, c.mlp)) != SF_OK)
+        return st;
+    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
+        return fail(SF_E_RANGE, "shade %d out of range", shade);
+    if (shade == SF_SHADE_GGX) {
+        if (!ggx)
+            return fail(SF_E_NULL, "GGX shading needs ggx parameters");
+        if ((st = ggx_constants(ggx, c.g)) != SF_OK)
+            return st;
+    }
+    if (!aligned(queries, 4) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))
+        return fail(SF_E_RANGE, "queries or out misaligned");
+    c.q = queries;
+    c.n = n;
+    c.filter = smp->filter;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.seed = smp->seed;
+    c.shade = shade;
+    c.out = out;
+    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    return device_status(sfk::launch_neural2d(c, (hipStream_t)stream));
+}
+
+sf_status sf_neural_raymarch(const sf_latent_grid *grid, const sf_mlp *mlp, const float *rays, int64_t n,
+                             int32_t steps, const sf_sampling *smp, float *T, int32_t *dbg_taps, void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (steps < 1 || steps > SF_MAX_STEPS)
+        return fail(SF_E_RANGE, "steps %d outside 1..%d", steps, SF_MAX_STEPS);
+    if (n == 0)
+        return ok();
+    if (!rays || !T)
+        return fail(SF_E_NULL, "rays and T must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    if (smp->mode != SF_STOCHASTIC || smp->rng_variant != 0)
+        return fail(SF_E_UNSUPPORTED, "the neural ray march is stochastic with independent uniforms");
+    sfk::NeuralCall c{};
+    if ((st = check_grid(grid, true, c.lat)) != SF_OK)
+        return st;
+    if (c.lat.dims != 3)
+        return fail(SF_E_UNSUPPORTED, "sf_neural_raymarch takes a 3-D grid");
+    if ((st = check_mlp(mlp, c.lat, c.mlp)) != SF_OK)
+        return st;
+    if (!aligned(rays, 16) || !aligned(T, 4))
+        return fail(SF_E_RANGE, "rays must be 16-byte aligned, T 4-byte aligned");
+    c.rays = rays;
+    c.n = n;
+    c.steps = steps;
+    c.filter = smp->filter;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.seed = smp->seed;
+    c.T = T;
+    c.taps = dbg_taps;
+    return device_status(sfk::launch_neural_ray(c, (hipStream_t)stream));
+}
+
+sf_status sf_neural_decode_lattice(const sf_latent_grid *grid, const sf_mlp *mlp, const int64_t *lattice_idx,
+                                   int64_t n, float *out, void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (n == 0)
+        return ok();
+    if (!lattice_idx || !out)
+        return fail(SF_E_NULL, "lattice_idx and out must be non-NULL");
+    sfk::NeuralCall c{};
+    if ((st = check_grid(grid, true, c.lat)) != SF_OK)
+        return st;
+    if ((st = check_mlp(mlp, c.lat, c.mlp)) != SF_OK)
+        return st;
+    if (!aligned(lattice_idx, 8) || !aligned(out, 4))
+        return fail(SF_E_RANGE, "misaligned pointer");
+    c.n = n;
+    c.out = out;
+    return device_status(sfk::launch_decode_lattice(c, lattice_idx, (hipStream_t)stream));
+}
+
+sf_status sf_to_bf16(const float *in, int64_t n, uint16_t *out, void *stream)
+{
+    if (n < 0)
+        return fail(SF_E_RANGE, "n is negative");
+    if (n == 0)
+        return ok();
+    if (!in || !out)
+        return fail(SF_E_NULL, "in and out must be non-NULL");
+    if (!aligned(in, 4) || !aligned(out, 2))
+        return fail(SF_E_RANGE, "misaligned pointer");
+    return device_status(sfk::launch_to_bf16(in, n, out, (hipStream_t)stream));
+}
+
+sf_status sf_neural_quantize(const float *latents, const sf_latent_grid *grid, void *out_latents, float *out_scales,
+                             void *stream)
+{
+    sfk::LatentArgs a{};
+    sf_status st;
+    if ((st = check_grid(grid, false, a)) != SF_OK)
+        return st;
+    if (!latents || !out_latents || (a.fmt == SF_LATENT_FP8E4M3 && !out_scales))
+        return fail(SF_E_NULL, "latents, out_latents (and E4M3 out_scales) must be non-NULL");
+    if (!aligned(latents, 4) || !aligned(out_latents, 2) || (out_scales && !aligned(out_scales, 4)))
+        return fail(SF_E_RANGE, "misaligned pointer");
+    const int64_t count = (int64_t)a.res[0] * a.res[1] * a.res[2] * a.C;
+    if (a.fmt == SF_LATENT_BF16)
+        return device_status(sfk::launch_to_bf16(latents, count, (uint16_t *)out_latents, (hipStream_t)stream));
+    return device_status(sfk::launch_quant_fp8(latents, a, (uint8_t *)out_latents, out_scales, (hipStream_t)stream));
+}
+
+static int train_parts(int64_t batch)
+{
+    int64_t p = (batch + 15) / 16;
+    return (int)(p < 1 ? 1 : (p > 2048 ? 2048 : p));
+}
+
+size_t sf_neural_train_workspace(int32_t channels, int32_t out_dim, int64_t batch)
+{
+    if (!((channels == 8 && out_dim == 4) || (channels == 16 && out_dim == 1)) || batch < 1)
+        return 0;
+    return (size_t)train_parts(batch) * (size_t)(sfk::train_nparams(channels, out_dim) + 1) * sizeof(float);
+}
+
+sf_status sf_neural_train_step(const sf_train_state *stt, const int32_t *batch_idx, const float *targets,
+                               int64_t batch, int32_t step, float lr_latent, float lr_mlp, float *loss_out,
+                               float *grad_params, float *grad_latents, void *workspace, size_t workspace_bytes,
+                               void *stream)
+{
+    if (!stt)
+        return fail(SF_E_NULL, "training state is NULL");
+    if (!((stt->channels == 8 && stt->out_dim == 4) || (stt->channels == 16 && stt->out_dim == 1)) ||
+        stt->hidden != 64 || stt->reserved != 0)
+        return fail(SF_E_UNSUPPORTED, "training shapes: 8-64-4 or 16-64-1");
+    if (batch < 1 || batch > stt->n_lattice || stt->n_lattice < 1 || stt->n_lattice > (1LL << 31) || step < 1)
+        return fail(SF_E_RANGE, "batch must be in 1..n_lattice and step >= 1");
+    if (!std::isfinite(lr_latent) || !std::isfinite(lr_mlp))
+        return fail(SF_E_RANGE, "learning rates must be finite");
+    if (!stt->latents || !stt->params || !stt->m_latents || !stt->v_latents || !stt->m_params || !stt->v_params ||
+        !batch_idx || !targets || !loss_out)
+        return fail(SF_E_NULL, "training arrays, batch_idx, targets and loss_out must be non-NULL");
+    const size_t need = sf_neural_train_workspace(stt->channels, stt->out_dim, batch);
+    if (!workspace || workspace_bytes < need)
+        return fail(SF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? workspace_bytes : 0);
+    sfk::TrainCall t{};
+    t.latents = stt->latents;
+    t.params = stt->params;
+    t.m_lat = stt->m_latents;
+    t.v_lat = stt->v_latents;
+    t.m_par = stt->m_params;
+    t.v_par = stt->v_params;
+    t.idx = batch_idx;
+    t.targets = targets;
+    t.batch = batch;
+    t.n_lattice = stt->n_lattice;
+    t.C = stt->channels;
+    t.O = stt->out_dim;
+    t.lr_latent = lr_latent;
+    t.lr_mlp = lr_mlp;
+    t.bc1 = (float)(1.0 - std::pow(0.9, step));
+    t.bc2 = (float)(1.0 - std::pow(0.999, step));
+    t.loss_out = loss_out;
+    t.grad_params = grad_params;
+    t.grad_latents = grad_latents;
+    const int parts = train_parts(batch);
+    const int64_t chunk = (batch + parts - 1) / parts;
+    return device_status(sfk::launch_train(t, (float *)workspace, parts, chunk, (hipStream_t)stream));
+}
+
 static int32_t err_blocks(int64_t count)
 {
     int64_t b = (count + 1023) / 1024;

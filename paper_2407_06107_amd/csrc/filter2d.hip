@@ -72,26 +72,11 @@ __device__ __forceinline__ float4 texel(const Tex2DArgs &tx, int l, int x, int y
                        (float)(px >> 24) * k);
 }
 
-// GGX + Lambert times the cosine, for the fixed directions folded into g.
-__device__ __forceinline__ float3 shade_ggx(const GgxConst &g, float4 c)
-{
-    float r = __builtin_fmaf(g.r_scale, c.w, g.r_bias);
-    float a = r * r;
-    float a2 = a * a;
-    float d = __builtin_fmaf(g.nh2, a2 - 1.0f, 1.0f);
-    float om = 1.0f - a2;
-    float go = (2.0f * g.no) / (g.no + __builtin_sqrtf(__builtin_fmaf(om, g.no2, a2)));
-    float gi = (2.0f * g.ni) / (g.ni + __builtin_sqrtf(__builtin_fmaf(om, g.ni2, a2)));
-    float spec = (a2 * go * gi * g.spec_k) / (d * d);
-    return make_float3(__builtin_fmaf(g.kd[0], c.x, g.ks[0] * spec), __builtin_fmaf(g.kd[1], c.y, g.ks[1] * spec),
-                       __builtin_fmaf(g.kd[2], c.z, g.ks[2] * spec));
-}
-
 template <int SHADE>
 __device__ __forceinline__ float4 shade(const GgxConst &g, float4 c)
 {
     if constexpr (SHADE == SF_SHADE_GGX) {
-        float3 v = shade_ggx(g, c);
+        float3 v = shade_ggx_dev(g, c);
         return make_float4(v.x, v.y, v.z, 0.0f);
     } else {
         return c;

@@ -1,0 +1,798 @@
+// Neural latent textures / volumes of libsf.
+//
+// A lattice of latent vectors z_c is decoded by a small MLP
+// D_c = W3^T relu(W2^T relu(W1^T z_c + b1) + b2) + b3.  Stochastic filtering
+// picks ONE lattice point per sample with the same inverse-CDF contract as
+// the plain texture (Sec. 4.1 FRS) and therefore runs ONE decode per sample
+// instead of 16 (bicubic) or 64 (tricubic).
+//
+//  - Training (FP32, vector ALU): one wavefront streams a chunk of the batch;
+//    lane h owns hidden unit h, so both matrix-vector products of a sample
+//    are 64-lane broadcasts from LDS.  Per-wavefront parameter gradients are
+//    summed in a fixed order by a second kernel that also applies Adam;
+//    latent gradients are applied at once (each batch entry owns its latent).
+//  - Decoding (BF16 matrix cores, FP32 accumulation): 16 samples form the
+//    columns of one v_mfma_f32_16x16x32_bf16 tile with hidden units as rows,
+//    so one layer's accumulators are, lane for lane, the next layer's B
+//    operand (the weights' K order is permuted to match, see kperm()).
+#include "sf_device.hpp"
+#include "sf_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sfk {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int HID = 64;
+
+// ------------------------------------------------------------------ formats
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+// OCP E4M3 code -> binary32 (codes 0x7f/0xff, NaN in the format, are never
+// produced by the quantizer).
+__device__ __forceinline__ float fp8_to_f32(uint32_t b)
+{
+    const uint32_t em = b & 0x7fu;
+    const uint32_t sign = (b & 0x80u) << 24;
+    float nrm = __builtin_bit_cast(float, sign | ((em << 20) + 0x3c000000u));
+    float sub = __builtin_bit_cast(float, sign | __builtin_bit_cast(uint32_t, (float)em * 0x1p-9f));
+    return em >= 8u ? nrm : sub;
+}
+
+// binary32 -> E4M3, round to nearest even, saturating at +-448.
+__device__ __forceinline__ uint8_t f32_to_fp8_rne(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return 0x7f;
+    const float a = __builtin_fabsf(f);
+    if (a >= 448.0f)
+        return (uint8_t)(sign | 0x7eu);
+    if (a < 0x1p-6f) {   // subnormal range: multiples of 2^-9
+        float m = __builtin_rintf(a * 512.0f);   // exact scaling, RNE
+        return (uint8_t)(sign | (uint32_t)m);    // m == 8 is the smallest normal, code 0x08
+    }
+    const uint32_t au = __builtin_bit_cast(uint32_t, a);
+    uint32_t e = (au >> 23) - 120u;          // E4M3 exponent field, 1..15
+    uint32_t m3 = (au >> 20) & 7u;
+    const uint32_t rem = au & 0xfffffu, halfway = 0x80000u;
+    if (rem > halfway || (rem == halfway && (m3 & 1u)))
+        ++m3;
+    uint32_t code = (e << 3) + m3;          // a mantissa carry rolls into the exponent
+    return (uint8_t)(sign | (code > 0x7eu ? 0x7eu : code));
+}
+
+// ------------------------------------------------------------ quantization
+__global__ __launch_bounds__(256) void k_to_bf16(const float *in, int64_t n, uint16_t *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        out[i] = f32_to_bf16_rne(in[i]);
+}
+
+// One workgroup per block of lattice points: amax over the block (all
+// channels), s = amax/448 (1 for an all-zero block), code = E4M3(z/s).
+__global__ __launch_bounds__(256) void k_quant_fp8(const float *lat, LatentArgs g, uint8_t *codes, float *scales)
+{
+    __shared__ float red[256];
+    const int B = 1 << g.block_log2;
+    const int nbx = (g.res[0] + B - 1) / B, nby = (g.res[1] + B - 1) / B;
+    const int64_t b = blockIdx.x;
+    const int bx = (int)(b % nbx), by = (int)((b / nbx) % nby), bz = (int)(b / ((int64_t)nbx * nby));
+    const int ex = min(B, g.res[0] - bx * B), ey = min(B, g.res[1] - by * B), ez = min(B, g.res[2] - bz * B);
+    const int64_t count = (int64_t)ex * ey * ez * g.C;
+    float amax = 0.0f;
+    for (int64_t k = threadIdx.x; k < count; k += 256) {
+        const int c = (int)(k % g.C);
+        const int64_t p = k / g.C;
+        const int x = bx * B + (int)(p % ex), y = by * B + (int)((p / ex) % ey), z = bz * B + (int)(p / ((int64_t)ex * ey));
+        const int64_t idx = (((int64_t)z * g.res[1] + y) * g.res[0] + x) * g.C + c;
+        amax = __builtin_fmaxf(amax, __builtin_fabsf(lat[idx]));
+    }
+    red[threadIdx.x] = amax;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if ((int)threadIdx.x < m)
+            red[threadIdx.x] = __builtin_fmaxf(red[threadIdx.x], red[threadIdx.x + m]);
+        __syncthreads();
+    }
+    const float s = red[0] > 0.0f ? red[0] / 448.0f : 1.0f;
+    if (threadIdx.x == 0)
+        scales[b] = s;
+    for (int64_t k = threadIdx.x; k < count; k += 256) {
+        const int c = (int)(k % g.C);
+        const int64_t p = k / g.C;
+        const int x = bx * B + (int)(p % ex), y = by * B + (int)((p / ex) % ey), z = bz * B + (int)(p / ((int64_t)ex * ey));
+        const int64_t idx = (((int64_t)z * g.res[1] + y) * g.res[0] + x) * g.C + c;
+        codes[idx] = f32_to_fp8_rne(lat[idx] / s);
+    }
+}
+
+// ----------------------------------------------------------------- training
+// Packed parameter offsets: W1 [C x H], b1 [H], W2 [H x H], b2 [H], W3 [H x O], b3 [O].
+struct POff {
+    int w1, b1, w2, b2, w3, b3, n;
+    __host__ __device__ POff(int C, int O)
+    {
+        w1 = 0;
+        b1 = C * HID;
+        w2 = b1 + HID;
+        b2 = w2 + HID * HID;
+        w3 = b2 + HID;
+        b3 = w3 + HID * O;
+        n = b3 + O;
+    }
+};
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m);
+    return v;
+}
+
+// One wavefront (= one workgroup) per chunk of the batch.  Lane h holds
+// hidden unit h: its column of W1 and W2, its row of W2 and W3, and the
+// matching gradient accumulators.
+template <int C, int O>
+__global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float *partials)
+{
+    __shared__ float sh_h1[HID], sh_da[HID];
+    const POff P(C, O);
+    const int h = threadIdx.x;
+    const float *W = t.params;
+    float w1c[C], w2c[HID], w2r[HID], w3r[O], w1r[HID];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        w1c[c] = W[P.w1 + c * HID + h];
+#pragma unroll
+    for (int k = 0; k < HID; ++k) {
+        w2c[k] = W[P.w2 + k * HID + h];
+        w2r[k] = W[P.w2 + h * HID + k];
+        w1r[k] = h < C ? W[P.w1 + h * HID + k] : 0.0f;
+    }
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+        w3r[o] = W[P.w3 + h * O + o];
+    const float b1 = W[P.b1 + h], b2 = W[P.b2 + h];
+    float b3[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+        b3[o] = W[P.b3 + o];
+
+    float g1[C], g2[HID], g3[O], gb1 = 0.0f, gb2 = 0.0f, gb3[O], loss = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        g1[c] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < HID; ++k)
+        g2[k] = 0.0f;
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+        g3[o] = gb3[o] = 0.0f;
+
+    const float inv_b = 2.0f / (float)t.batch;
+    const int64_t s0 = (int64_t)blockIdx.x * chunk;
+    const int64_t s1 = min(s0 + chunk, t.batch);
+    for (int64_t s = s0; s < s1; ++s) {
+        const int64_t li = t.idx[s];
+        if ((uint64_t)li >= (uint64_t)t.n_lattice)
+            continue;   // an index outside the lattice contributes nothing
+        float z[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            z[c] = t.latents[li * C + c];
+        float a1 = b1;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            a1 = __builtin_fmaf(z[c], w1c[c], a1);
+        const float h1 = a1 > 0.0f ? a1 : 0.0f;
+        sh_h1[h] = h1;
+        __syncthreads();
+        float a2 = b2;
+#pragma unroll
+        for (int k = 0; k < HID; ++k)
+            a2 = __builtin_fmaf(sh_h1[k], w2c[k], a2);
+        const float h2 = a2 > 0.0f ? a2 : 0.0f;
+        float dy[O];
+        float dh2 = 0.0f;
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const float y = wave_sum(h2 * w3r[o]) + b3[o];
+            const float e = y - t.targets[li * O + o];
+            loss = __builtin_fmaf(e, e, loss);
+            dy[o] = e * inv_b;
+            g3[o] = __builtin_fmaf(h2, dy[o], g3[o]);
+            gb3[o] += dy[o];
+            dh2 = __builtin_fmaf(w3r[o], dy[o], dh2);
+        }
+        const float da2 = a2 > 0.0f ? dh2 : 0.0f;
+        gb2 += da2;
+#pragma unroll
+        for (int k = 0; k < HID; ++k)
+            g2[k] = __builtin_fmaf(sh_h1[k], da2, g2[k]);
+        __syncthreads();
+        sh_da[h] = da2;
+        __syncthreads();
+        float dh1 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < HID; ++k)
+            dh1 = __builtin_fmaf(w2r[k], sh_da[k], dh1);
+        const float da1 = a1 > 0.0f ? dh1 : 0.0f;
+        gb1 += da1;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            g1[c] = __builtin_fmaf(z[c], da1, g1[c]);
+        __syncthreads();
+        sh_da[h] = da1;
+        __syncthreads();
+        // latent gradient and its Adam step: lane c owns channel c
+        if (h < C) {
+            float gz = 0.0f;
+#pragma unroll
+            for (int k = 0; k < HID; ++k)
+                gz = __builtin_fmaf(w1r[k], sh_da[k], gz);
+            if (t.grad_latents)
+                t.grad_latents[s * C + h] = gz;
+            const int64_t j = li * C + h;
+            const float m = 0.9f * t.m_lat[j] + 0.1f * gz;
+            const float v = 0.999f * t.v_lat[j] + 0.001f * gz * gz;
+            t.m_lat[j] = m;
+            t.v_lat[j] = v;
+            t.latents[j] -= t.lr_latent * (m / t.bc1) / (__builtin_sqrtf(v / t.bc2) + 1e-8f);
+        }
+        __syncthreads();
+    }
+    // per-wavefront partial gradients in the packed layout, then the loss
+    float *out = partials + (int64_t)blockIdx.x * (P.n + 1);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        out[P.w1 + c * HID + h] = g1[c];
+    out[P.b1 + h] = gb1;
+#pragma unroll
+    for (int k = 0; k < HID; ++k)
+        out[P.w2 + k * HID + h] = g2[k];
+    out[P.b2 + h] = gb2;
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+        out[P.w3 + h * O + o] = g3[o];
+    if (h == 0) {
+#pragma unroll
+        for (int o = 0; o < O; ++o)
+            out[P.b3 + o] = gb3[o];
+        out[P.n] = loss;
+    }
+}
+
+// Sum the per-wavefront partials in order and take one Adam step per
+// parameter; the loss lands in loss_out.
+__global__ __launch_bounds__(256) void k_train_reduce(TrainCall t, int nparts, const float *partials, int npar)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p > npar)
+        return;
+    float g = 0.0f;
+    for (int w = 0; w < nparts; ++w)
+        g += partials[(int64_t)w * (npar + 1) + p];
+    if (p == npar) {
+        t.loss_out[0] = g / (float)t.batch;
+        return;
+    }
+    if (t.grad_params)
+        t.grad_params[p] = g;
+    const float m = 0.9f * t.m_par[p] + 0.1f * g;
+    const float v = 0.999f * t.v_par[p] + 0.001f * g * g;
+    t.m_par[p] = m;
+    t.v_par[p] = v;
+    t.params[p] -= t.lr_mlp * (m / t.bc1) / (__builtin_sqrtf(v / t.bc2) + 1e-8f);
+}
+
+// ------------------------------------------------------- matrix-core decoder
+// Lane l of a 16x16x32 tile: column n = l % 16, K block g = l / 16 (8 K values
+// for A and B), accumulator rows 4g..4g+3.  Hidden unit at K position
+// 8g + j of K step ks: two accumulator tiles (2ks, 2ks+1) interleaved.
+__device__ __forceinline__ int kperm(int ks, int g, int j) { return 16 * (2 * ks + (j >> 2)) + 4 * g + (j & 3); }
+
+template <int C, int O>
+struct MlpFrags {
+    bf16x8 a1[4], a2[4][2], a3[2];
+    f32x4 b1[4], b2[4], b3;
+};
+
+__device__ __forceinline__ float pbf(const uint16_t *P, int i) { return bf16_bits_to_f32(P[i]); }
+
+template <int C, int O>
+__device__ __forceinline__ void load_frags(const uint16_t *P, MlpFrags<C, O> &F)
+{
+    const POff off(C, O);
+    const int l = threadIdx.x & 63, n = l & 15, g = l >> 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = 8 * g + j;
+            F.a1[m][j] = (__bf16)(c < C ? pbf(P, off.w1 + c * HID + 16 * m + n) : 0.0f);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                F.a2[m][ks][j] = (__bf16)pbf(P, off.w2 + kperm(ks, g, j) * HID + 16 * m + n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            F.b1[m][j] = pbf(P, off.b1 + 16 * m + 4 * g + j);
+            F.b2[m][j] = pbf(P, off.b2 + 16 * m + 4 * g + j);
+        }
+    }
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            F.a3[ks][j] = (__bf16)(n < O ? pbf(P, off.w3 + kperm(ks, g, j) * O + n) : 0.0f);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        F.b3[j] = (4 * g + j < O) ? pbf(P, off.b3 + 4 * g + j) : 0.0f;
+}
+
+__device__ __forceinline__ bf16x8 relu_pack(f32x4 lo, f32x4 hi)
+{
+    bf16x8 r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        r[j] = (__bf16)__builtin_fmaxf(lo[j], 0.0f);
+        r[4 + j] = (__bf16)__builtin_fmaxf(hi[j], 0.0f);
+    }
+    return r;
+}
+
+// The MLP on the 16 samples whose latents (K block of this lane) are in zb;
+// column scale cs multiplies layer 1's product (E4M3 block scale; 1 for
+// BF16 latents).  Returns the layer-3 accumulators: lanes 0..15 hold outputs
+// 0..3 of sample (lane).
+template <int C, int O>
+__device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x8 zb, float cs)
+{
+    f32x4 d1[4];
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        d1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[m], zb, zero, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            d1[m][j] = __builtin_fmaf(cs, d1[m][j], F.b1[m][j]);
+    }
+    const bf16x8 h1a = relu_pack(d1[0], d1[1]), h1b = relu_pack(d1[2], d1[3]);
+    f32x4 d2[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        d2[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[m][0], h1a, F.b2[m], 0, 0, 0);
+        d2[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[m][1], h1b, d2[m], 0, 0, 0);
+    }
+    const bf16x8 h2a = relu_pack(d2[0], d2[1]), h2b = relu_pack(d2[2], d2[3]);
+    f32x4 d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a3[0], h2a, F.b3, 0, 0, 0);
+    d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a3[1], h2b, d3, 0, 0, 0);
+    return d3;
+}
+
+// This lane's K block of the latent of lattice point idx (zeros past C, or
+// for idx < 0); blk is the point's scale block (E4M3 latents).
+template <int C, int FMT>
+__device__ __forceinline__ bf16x8 latent_frag(const LatentArgs &g, int64_t idx, int blk, float &scale)
+{
+    const int kb = (threadIdx.x & 63) >> 4;
+    bf16x8 r;
+    scale = 1.0f;
+    if (8 * kb >= C || idx < 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            r[j] = (__bf16)0.0f;
+        return r;
+    }
+    if constexpr (FMT == SF_LATENT_BF16) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(g.latents) + idx * C + 8 * kb);
+        r = __builtin_bit_cast(bf16x8, v);
+    } else {
+        const uint2 v = *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(g.latents) + idx * C + 8 * kb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            r[j] = (__bf16)fp8_to_f32((v.x >> (8 * j)) & 0xffu);
+            r[4 + j] = (__bf16)fp8_to_f32((v.y >> (8 * j)) & 0xffu);
+        }
+        scale = g.scales[blk];
+    }
+    return r;
+}
+
+// Decode one lattice point per lane for the whole wavefront (every lane must
+// take part; idx < 0 marks a lane with nothing to decode).  blk is the
+// point's scale block (E4M3 latents only).  Returns this lane's O raw outputs.
+template <int C, int O, int FMT>
+__device__ __forceinline__ void decode_wave(const LatentArgs &g, const MlpFrags<C, O> &F, int64_t idx, int blk,
+                                            float y[O])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int src = 16 * G + (lane & 15);
+        const int64_t sidx = ((int64_t)__shfl((int)(idx >> 32), src) << 32) | (uint32_t)__shfl((int)idx, src);
+        const int sblk = FMT == SF_LATENT_BF16 ? 0 : __shfl(blk, src);
+        float cs;
+        const bf16x8 zb = latent_frag<C, FMT>(g, sidx, sblk, cs);
+        if constexpr (FMT != SF_LATENT_BF16)
+            cs = __shfl(cs, lane & 15);   // the scale of this lane's column (lanes 0..15 loaded it)
+        const f32x4 d3 = mlp16<C, O>(F, zb, cs);
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const float v = __shfl(d3[o], lane & 15);
+            if ((lane >> 4) == G)
+                y[o] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// 2-D neural texture lookups (repeat wrap).  Decoded texel = clamp(MLP, 0, 1).
+template <int F_, int SHADE, int MODE, int FMT>
+__global__ __launch_bounds__(256) void k_neural2d(NeuralCall c)
+{
+    constexpr int C = 8, O = 4;
+    MlpFrags<C, O> Fr;
+    load_frags<C, O>(static_cast<const uint16_t *>(c.mlp.params), Fr);
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool active = q < c.n;
+    float qx = 0.f, qy = 0.f;
+    if (active) {
+        qx = c.q[3 * q];
+        qy = c.q[3 * q + 1];
+    }
+    const bool ok = active && __builtin_isfinite(qx) && __builtin_isfinite(qy);
+    const int R0 = c.lat.res[0], R1 = c.lat.res[1];
+    int ix = 0, iy = 0;
+    float tx = 0.f, ty = 0.f;
+    if (ok) {
+        const float u = qx - __builtin_floorf(qx), v = qy - __builtin_floorf(qy);
+        const float px = __builtin_fmaf(u, (float)R0, -0.5f), py = __builtin_fmaf(v, (float)R1, -0.5f);
+        const float fx = __builtin_floorf(px), fy = __builtin_floorf(py);
+        ix = (int)fx;
+        iy = (int)fy;
+        tx = px - fx;
+        ty = py - fy;
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    float y[O];
+    if constexpr (MODE == STOCH) {
+        for (int s = 0; s < c.spp; ++s) {
+            int64_t idx = -1;
+            int blk = 0;
+            if (ok) {
+                const uint4 w = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
+                const int x = wrapi(ix + pick_off<F_>(tx, u24(w.x)), R0);
+                const int yy = wrapi(iy + pick_off<F_>(ty, u24(w.y)), R1);
+                idx = (int64_t)yy * R0 + x;
+                blk = c.lat.block_at(x, yy, 0);
+                if (c.taps) {
+                    c.taps[(q * c.spp + s) * 2] = x;
+                    c.taps[(q * c.spp + s) * 2 + 1] = yy;
+                }
+            } else if (active && c.taps) {
+                c.taps[(q * c.spp + s) * 2] = c.taps[(q * c.spp + s) * 2 + 1] = SF_TAP_NONE;
+            }
+            decode_wave<C, O, FMT>(c.lat, Fr, idx, blk, y);
+            float4 d = make_float4(__builtin_fminf(__builtin_fmaxf(y[0], 0.f), 1.f),
+                                   __builtin_fminf(__builtin_fmaxf(y[1], 0.f), 1.f),
+                                   __builtin_fminf(__builtin_fmaxf(y[2], 0.f), 1.f),
+                                   __builtin_fminf(__builtin_fmaxf(y[3], 0.f), 1.f));
+            if constexpr (SHADE == SF_SHADE_GGX) {
+                const float3 r = shade_ggx_dev(c.g, d);
+                acc[0] += r.x;
+                acc[1] += r.y;
+                acc[2] += r.z;
+            } else {
+                acc[0] += d.x;
+                acc[1] += d.y;
+                acc[2] += d.z;
+                acc[3] += d.w;
+            }
+        }
+        const float inv = 1.0f / (float)c.spp;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            acc[k] *= inv;
+    } else {
+        constexpr int NT = Taps<F_>::n;
+        constexpr int F0 = Taps<F_>::first;
+        float wx[4], wy[4];
+        axis_weights<F_>(tx, wx);
+        axis_weights<F_>(ty, wy);
+        if constexpr (F_ == NEAREST) {
+            ix += tx >= 0.5f;
+            iy += ty >= 0.5f;
+        }
+        for (int b = 0; b < NT; ++b)
+            for (int a = 0; a < NT; ++a) {
+                const int xx = wrapi(ix + F0 + a, R0), yy = wrapi(iy + F0 + b, R1);
+                const int64_t idx = ok ? (int64_t)yy * R0 + xx : -1;
+                decode_wave<C, O, FMT>(c.lat, Fr, idx, c.lat.block_at(xx, yy, 0), y);
+                const float w = wx[a] * wy[b];
+                float4 d = make_float4(__builtin_fminf(__builtin_fmaxf(y[0], 0.f), 1.f),
+                                       __builtin_fminf(__builtin_fmaxf(y[1], 0.f), 1.f),
+                                       __builtin_fminf(__builtin_fmaxf(y[2], 0.f), 1.f),
+                                       __builtin_fminf(__builtin_fmaxf(y[3], 0.f), 1.f));
+                if (MODE == AFTER && SHADE == SF_SHADE_GGX) {
+                    const float3 r = shade_ggx_dev(c.g, d);
+                    acc[0] = __builtin_fmaf(w, r.x, acc[0]);
+                    acc[1] = __builtin_fmaf(w, r.y, acc[1]);
+                    acc[2] = __builtin_fmaf(w, r.z, acc[2]);
+                } else {
+                    acc[0] = __builtin_fmaf(w, d.x, acc[0]);
+                    acc[1] = __builtin_fmaf(w, d.y, acc[1]);
+                    acc[2] = __builtin_fmaf(w, d.z, acc[2]);
+                    acc[3] = __builtin_fmaf(w, d.w, acc[3]);
+                }
+            }
+        if (MODE == BEFORE && SHADE == SF_SHADE_GGX) {
+            const float3 r = shade_ggx_dev(c.g, make_float4(acc[0], acc[1], acc[2], acc[3]));
+            acc[0] = r.x;
+            acc[1] = r.y;
+            acc[2] = r.z;
+        }
+    }
+    if (!active)
+        return;
+    if (!ok) {
+        acc[0] = acc[1] = acc[2] = acc[3] = __builtin_nanf("");
+    }
+    if constexpr (SHADE == SF_SHADE_GGX) {
+        c.out[3 * q] = acc[0];
+        c.out[3 * q + 1] = acc[1];
+        c.out[3 * q + 2] = acc[2];
+    } else {
+        reinterpret_cast<float4 *>(c.out)[q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
+}
+
+// Decoded outputs at given lattice points (no filtering, no clamping).
+template <int C, int O, int FMT>
+__global__ __launch_bounds__(256) void k_decode_lattice(NeuralCall c, const int64_t *idx_in)
+{
+    MlpFrags<C, O> Fr;
+    load_frags<C, O>(static_cast<const uint16_t *>(c.mlp.params), Fr);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t npts = (int64_t)c.lat.res[0] * c.lat.res[1] * c.lat.res[2];
+    int64_t idx = i < c.n ? idx_in[i] : -1;
+    const bool valid = (uint64_t)idx < (uint64_t)npts;
+    if (!valid)
+        idx = -1;   // outside the lattice: no load, NaN result
+    int blk = 0;
+    if (FMT != SF_LATENT_BF16 && idx >= 0) {
+        const int64_t plane = (int64_t)c.lat.res[0] * c.lat.res[1];
+        const int z = (int)(idx / plane), y = (int)((idx % plane) / c.lat.res[0]), x = (int)(idx % c.lat.res[0]);
+        blk = c.lat.block_at(x, y, z);
+    }
+    float y[O];
+    decode_wave<C, O, FMT>(c.lat, Fr, idx, blk, y);
+    if (i < c.n)
+#pragma unroll
+        for (int o = 0; o < O; ++o)
+            c.out[i * O + o] = valid ? y[o] : __builtin_nanf("");
+}
+
+// Ray march through a neural density volume: per step the lookup point's
+// picked lattice point is decoded (sigma = max(MLP, 0)); taps outside the
+// lattice read zero and are not decoded.  Every lane walks the same number
+// of steps so the wavefront can batch its decodes on the matrix cores.
+template <int F_, int FMT, bool DBG>
+__global__ __launch_bounds__(256) void k_neural_ray(NeuralCall c, uint32_t nb_pad)
+{
+    constexpr int C = 16, O = 1;
+    MlpFrags<C, O> Fr;
+    load_frags<C, O>(static_cast<const uint16_t *>(c.mlp.params), Fr);
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
+    const bool active = i < c.n;
+    RayGeom g = {};
+    int st = 1;
+    if (active)
+        st = ray_setup_dev(c.lat.wmin, c.lat.scale, c.rays + 8 * i, c.steps, g);
+    const bool march = active && st == 0;
+    double Tsum = 0.0;
+    for (int s = 0; s < c.spp; ++s) {
+        StepHash h;
+        h.init((uint32_t)i, (uint32_t)s, c.seed);
+        double tau = 0.0;
+        float kh = 0.5f;
+        for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
+            int64_t idx = -1;
+            int blk = 0;
+            if (march) {
+                int i0[3], o[3];
+                float t[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float p = __builtin_fmaf(kh, g.G[a], g.E[a]);
+                    const float fl = __builtin_floorf(p);
+                    i0[a] = (int)fl;
+                    t[a] = p - fl;
+                }
+                const uint3 w = h.at((uint32_t)k);
+                o[0] = pick_off<F_>(t[0], u24(w.x));
+                o[1] = pick_off<F_>(t[1], u24(w.y));
+                o[2] = pick_off<F_>(t[2], u24(w.z));
+                const int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
+                if constexpr (DBG) {
+                    int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
+                    tp[0] = x;
+                    tp[1] = y;
+                    tp[2] = z;
+                }
+                const bool in = ((uint32_t)x < (uint32_t)c.lat.res[0]) & ((uint32_t)y < (uint32_t)c.lat.res[1]) &
+                                ((uint32_t)z < (uint32_t)c.lat.res[2]);
+                if (in) {
+                    idx = ((int64_t)z * c.lat.res[1] + y) * c.lat.res[0] + x;
+                    blk = c.lat.block_at(x, y, z);
+                }
+            }
+            float sg[1];
+            decode_wave<C, O, FMT>(c.lat, Fr, idx, blk, sg);
+            if (idx >= 0)
+                tau += (double)__builtin_fmaxf(sg[0], 0.0f);
+        }
+        Tsum += exp(-(double)g.dt * tau);
+    }
+    if (!active)
+        return;
+    if (st != 0) {
+        c.T[i] = st == 1 ? 1.0f : __builtin_nanf("");
+        if constexpr (DBG) {
+            const int64_t per = (int64_t)3 * c.spp * c.steps;
+            for (int64_t k = 0; k < per; ++k)
+                c.taps[per * i + k] = SF_TAP_NONE;
+        }
+        return;
+    }
+    c.T[i] = (float)(Tsum / (double)c.spp);
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_to_bf16(const float *in, int64_t n, uint16_t *out, hipStream_t s)
+{
+    k_to_bf16<<<dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s>>>(in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_fp8(const float *lat, const LatentArgs &g, uint8_t *codes, float *scales, hipStream_t s)
+{
+    k_quant_fp8<<<dim3((uint32_t)g.nblocks()), dim3(256), 0, s>>>(lat, g, codes, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_t chunk, hipStream_t s)
+{
+    if (t.C == 8 && t.O == 4)
+        k_train<8, 4><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
+    else
+        k_train<16, 1><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
+    const int npar = POff(t.C, t.O).n;
+    k_train_reduce<<<dim3((npar + 1 + 255) / 256), dim3(256), 0, s>>>(t, nparts, workspace, npar);
+    return hipGetLastError();
+}
+
+int train_nparams(int C, int O) { return POff(C, O).n; }
+
+template <int F_, int SHADE, int MODE>
+static void launch_n2_m(const NeuralCall &c, hipStream_t s)
+{
+    dim3 grid((uint32_t)((c.n + 255) / 256)), block(256);
+    if (c.lat.fmt == SF_LATENT_BF16)
+        k_neural2d<F_, SHADE, MODE, SF_LATENT_BF16><<<grid, block, 0, s>>>(c);
+    else
+        k_neural2d<F_, SHADE, MODE, SF_LATENT_FP8E4M3><<<grid, block, 0, s>>>(c);
+}
+
+template <int F_, int SHADE>
+static void launch_n2_s(const NeuralCall &c, hipStream_t s)
+{
+    if (c.mode == STOCH)
+        launch_n2_m<F_, SHADE, STOCH>(c, s);
+    else if (c.mode == BEFORE)
+        launch_n2_m<F_, SHADE, BEFORE>(c, s);
+    else
+        launch_n2_m<F_, SHADE, AFTER>(c, s);
+}
+
+template <int F_>
+static void launch_n2_f(const NeuralCall &c, hipStream_t s)
+{
+    if (c.shade == SF_SHADE_GGX)
+        launch_n2_s<F_, SF_SHADE_GGX>(c, s);
+    else
+        launch_n2_s<F_, SF_SHADE_NONE>(c, s);
+}
+
+hipError_t launch_neural2d(const NeuralCall &c, hipStream_t s)
+{
+    switch (c.filter) {
+    case NEAREST:
+        launch_n2_f<NEAREST>(c, s);
+        break;
+    case LINEAR:
+        launch_n2_f<LINEAR>(c, s);
+        break;
+    default:
+        launch_n2_f<BSPLINE3>(c, s);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_decode_lattice(const NeuralCall &c, const int64_t *idx, hipStream_t s)
+{
+    dim3 grid((uint32_t)((c.n + 255) / 256)), block(256);
+    if (c.mlp.in_dim == 8) {
+        if (c.lat.fmt == SF_LATENT_BF16)
+            k_decode_lattice<8, 4, SF_LATENT_BF16><<<grid, block, 0, s>>>(c, idx);
+        else
+            k_decode_lattice<8, 4, SF_LATENT_FP8E4M3><<<grid, block, 0, s>>>(c, idx);
+    } else {
+        if (c.lat.fmt == SF_LATENT_BF16)
+            k_decode_lattice<16, 1, SF_LATENT_BF16><<<grid, block, 0, s>>>(c, idx);
+        else
+            k_decode_lattice<16, 1, SF_LATENT_FP8E4M3><<<grid, block, 0, s>>>(c, idx);
+    }
+    return hipGetLastError();
+}
+
+template <int F_>
+static void launch_nr_f(const NeuralCall &c, hipStream_t s, dim3 grid, uint32_t nb_pad)
+{
+    dim3 block(256);
+    if (c.lat.fmt == SF_LATENT_BF16) {
+        if (c.taps)
+            k_neural_ray<F_, SF_LATENT_BF16, true><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_neural_ray<F_, SF_LATENT_BF16, false><<<grid, block, 0, s>>>(c, nb_pad);
+    } else {
+        if (c.taps)
+            k_neural_ray<F_, SF_LATENT_FP8E4M3, true><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_neural_ray<F_, SF_LATENT_FP8E4M3, false><<<grid, block, 0, s>>>(c, nb_pad);
+    }
+}
+
+hipError_t launch_neural_ray(const NeuralCall &c, hipStream_t s)
+{
+    const uint32_t nb = (uint32_t)((c.n + 255) / 256);
+    const uint32_t nb_pad = (nb + 7u) & ~7u;
+    dim3 grid(nb_pad);
+    switch (c.filter) {
+    case NEAREST:
+        launch_nr_f<NEAREST>(c, s, grid, nb_pad);
+        break;
+    case LINEAR:
+        launch_nr_f<LINEAR>(c, s, grid, nb_pad);
+        break;
+    default:
+        launch_nr_f<BSPLINE3>(c, s, grid, nb_pad);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sfk

@@ -65,11 +65,61 @@ struct RaymarchCall {
     int32_t *taps;
 };
 
+struct LatentArgs {
+    const void *latents;
+    const float *scales;
+    int32_t dims, res[3], C, fmt, block_log2;
+    float wmin[3], scale[3];
+    __host__ __device__ int32_t nb(int a) const { return (res[a] + (1 << block_log2) - 1) >> block_log2; }
+    __host__ __device__ int64_t nblocks() const { return (int64_t)nb(0) * nb(1) * nb(2); }
+    // block of lattice point (x, y, z)
+    __host__ __device__ int32_t block_at(int x, int y, int z) const
+    {
+        return ((z >> block_log2) * nb(1) + (y >> block_log2)) * nb(0) + (x >> block_log2);
+    }
+};
+
+struct MlpArgs {
+    const void *params;   // packed BF16: W1, b1, W2, b2, W3, b3
+    int32_t in_dim, out_dim;
+};
+
+struct NeuralCall {
+    LatentArgs lat;
+    MlpArgs mlp;
+    const float *q;
+    const float *rays;
+    int64_t n;
+    int32_t steps, filter, mode, spp, shade;
+    uint32_t seed;
+    GgxConst g;
+    float *out;
+    float *T;
+    int32_t *taps;
+};
+
+struct TrainCall {
+    float *latents, *params, *m_lat, *v_lat, *m_par, *v_par;
+    const int32_t *idx;
+    const float *targets;
+    int64_t batch, n_lattice;
+    int32_t C, O;
+    float lr_latent, lr_mlp, bc1, bc2;
+    float *loss_out, *grad_params, *grad_latents;
+};
+
 // Launchers return hipSuccess or the launch error; arguments are validated.
 hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s);
 hipError_t launch_filter3d(const Filter3DCall &c, hipStream_t s);
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s);
 hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ, int64_t words, hipStream_t s);
+hipError_t launch_to_bf16(const float *in, int64_t n, uint16_t *out, hipStream_t s);
+hipError_t launch_quant_fp8(const float *lat, const LatentArgs &g, uint8_t *codes, float *scales, hipStream_t s);
+hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_t chunk, hipStream_t s);
+int train_nparams(int C, int O);
+hipError_t launch_neural2d(const NeuralCall &c, hipStream_t s);
+hipError_t launch_neural_ray(const NeuralCall &c, hipStream_t s);
+hipError_t launch_decode_lattice(const NeuralCall &c, const int64_t *idx, hipStream_t s);
 hipError_t launch_error_stats(const float *est, const double *ref, int64_t count, int32_t ch, double *out,
                               double *partials, int32_t nblocks, hipStream_t s);
 

@@ -16,40 +16,6 @@ namespace sfk {
 
 constexpr uint32_t kBufferFlags = 0x00020000u;  // raw buffer, 32-bit data format
 
-struct RayGeom {
-    float E[3], G[3], dt;
-};
-
-// 0: march; 1: empty segment (T = 1); 2: invalid (T = NaN).
-__device__ __forceinline__ int ray_setup(const VolArgs &v, const float *r8, int steps, RayGeom &g)
-{
-    float4 a = *reinterpret_cast<const float4 *>(r8);
-    float4 b = *reinterpret_cast<const float4 *>(r8 + 4);
-    float r[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-    bool fin = true;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        fin &= __builtin_isfinite(r[k]);
-    if (!fin)
-        return 2;
-    if (!(r[7] > r[6]))
-        return 1;
-    g.dt = (r[7] - r[6]) / (float)steps;
-    bool ok = true;
-    const float last = (float)(steps - 1) + 0.5f;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        float A = __builtin_fmaf(r[k] - v.wmin[k], v.scale[k], -0.5f);
-        float B = r[3 + k] * v.scale[k];
-        g.E[k] = __builtin_fmaf(r[6], B, A);
-        g.G[k] = g.dt * B;
-        float pa = __builtin_fmaf(0.5f, g.G[k], g.E[k]);
-        float pb = __builtin_fmaf(last, g.G[k], g.E[k]);
-        ok &= (__builtin_fabsf(pa) <= 4194304.0f) & (__builtin_fabsf(pb) <= 4194304.0f);
-    }
-    return ok ? 0 : 2;
-}
-
 // One voxel; zero outside the grid.  Out-of-range taps read offset 0 (always
 // valid) and the value is then discarded.
 template <bool HALF>
@@ -115,7 +81,7 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
     if (i >= c.n)
         return;
     RayGeom g;
-    int st = ray_setup(c.vol, c.rays + 8 * i, c.steps, g);
+    int st = ray_setup_dev(c.vol.wmin, c.vol.scale, c.rays + 8 * i, c.steps, g);
     if (st != 0) {
         c.T[i] = st == 1 ? 1.0f : __builtin_nanf("");
         if constexpr (DBG) {
@@ -168,7 +134,7 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
     if (i >= c.n)
         return;
     RayGeom g;
-    int st = ray_setup(c.vol, c.rays + 8 * i, c.steps, g);
+    int st = ray_setup_dev(c.vol.wmin, c.vol.scale, c.rays + 8 * i, c.steps, g);
     if (st != 0) {
         c.T[i] = st == 1 ? 1.0f : __builtin_nanf("");
         return;

@@ -1,0 +1,236 @@
+"""GPU parity of the neural latent texture / volume path against the oracle.
+
+Integer decisions (lattice taps, quantised codes, scales) are bit-exact.
+Decoded values: the matrix cores take BF16 operands and round the hidden
+activations to BF16; the oracle emulates that storage in FP64, so the
+residual differences are FP32-vs-FP64 accumulation and the rare BF16
+rounding flip it causes (one activation off by one BF16 step, ~0.4%).
+Tolerance: normwise relative 2e-3 and elementwise 2e-2 of the output scale.
+Training gradients are FP32 on the GPU vs FP64 in the oracle: normwise 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2407_06107_amd import inputs
+
+pytestmark = pytest.mark.gpu
+H = 64
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import paper_2407_06107_amd as sf
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sf.lib()
+    return sf
+
+
+def _case(*a):
+    print("CASE", *a, flush=True)
+
+
+def _bf16(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16).double().numpy()
+
+
+def _close_bf16(g, o, norm_tol=2e-3, elem_tol=2e-2):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    assert g.shape == o.shape
+    assert np.array_equal(np.isnan(g), np.isnan(o))
+    m = ~np.isnan(o)
+    g, o = g[m], o[m]
+    scale = max(np.sqrt(np.mean(o ** 2)), 1e-6)
+    assert np.linalg.norm(g - o) <= norm_tol * np.linalg.norm(o) + 1e-9, \
+        f"normwise {np.linalg.norm(g - o) / (np.linalg.norm(o) + 1e-30):.2e}"
+    worst = np.max(np.abs(g - o)) / scale if g.size else 0.0
+    assert worst <= elem_tol, f"elementwise {worst:.2e} of the output scale"
+
+
+def _params(C, O, seed, scale=0.25):
+    rng = np.random.default_rng(seed)
+    n = C * H + H + H * H + H + H * O + O
+    P = rng.normal(size=n).astype(np.float32) * scale
+    # a positive output bias keeps the clamped 2-D outputs inside (0, 1) mostly
+    P[-O:] = 0.5
+    return P
+
+
+def _grid(sf, orc, dims, res, C, fmt, seed, block_log2=2, wmin=(0, 0, 0), scale=(1, 1, 1)):
+    rng = np.random.default_rng(seed)
+    npts = int(np.prod(res))
+    lat = (rng.normal(size=(npts, C)) * rng.uniform(0.2, 2.0, size=(npts, 1))).astype(np.float32)
+    lat_d = torch.from_numpy(lat.ravel()).cuda()
+    grid = sf.sf_neural_quantize(lat_d, dims, res, C, fmt, block_log2, wmin, scale)
+    if fmt == sf.SF_LATENT_BF16:
+        Z = _bf16(lat)
+    else:
+        codes, scales = orc.quantize_fp8(lat.ravel(), dims, res, C, block_log2)
+        assert np.array_equal(grid.latents.cpu().numpy(), codes)
+        assert np.array_equal(grid.scales.cpu().numpy(), scales)
+        B = 1 << block_log2
+        nb = [-(-r // B) for r in list(res) + [1] * (3 - len(res))]
+        r3 = list(res) + [1] * (3 - len(res))
+        z, y, x = np.meshgrid(np.arange(r3[2]), np.arange(r3[1]), np.arange(r3[0]), indexing="ij")
+        blk = (((z // B) * nb[1] + (y // B)) * nb[0] + (x // B)).ravel()
+        Z = orc.fp8_table()[codes.reshape(npts, C)] * scales[blk][:, None].astype(np.float64)
+    return grid, Z
+
+
+def test_to_bf16_parity(sf):
+    _case("to_bf16")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(size=50000) * 10.0 ** rng.integers(-30, 30, 50000),
+                        [np.inf, -np.inf, 0.0, -0.0, 1e-45, 3.4e38, 1.00390625, 1.01171875]]).astype(np.float32)
+    got = sf.sf_to_bf16(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy()
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dims, res, C, lg", [(3, (20, 18, 17), 16, 2), (2, (40, 33), 8, 3), (3, (16, 16, 16), 16, 3)])
+def test_quantize_fp8_parity(sf, orc, dims, res, C, lg):
+    _case("quantize_fp8", dims, res, lg)
+    _grid(sf, orc, dims, res, C, sf.SF_LATENT_FP8E4M3, seed=1, block_log2=lg)   # asserts codes and scales
+
+
+@pytest.mark.parametrize("C, O, dims, res", [(8, 4, 2, (32, 24)), (16, 1, 3, (10, 9, 8))])
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_decode_lattice_parity(sf, orc, C, O, dims, res, fmt):
+    _case("decode_lattice", C, O, fmt)
+    grid, Z = _grid(sf, orc, dims, res, C, fmt, seed=2)
+    P = _params(C, O, 3)
+    mlp = sf.MLP(torch.from_numpy(P).cuda(), C, O)
+    npts = int(np.prod(res))
+    idx = np.random.default_rng(4).permutation(npts).astype(np.int64)[: npts - 7]   # ragged
+    out = sf.sf_neural_decode_lattice(grid, mlp, torch.from_numpy(idx).cuda()).cpu().numpy()
+    ref = orc.mlp_forward(C, H, O, _bf16(P), Z[idx], act_bf16=True)
+    _close_bf16(out, ref)
+
+
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("mode, spp", [("STOCHASTIC", 3), ("STOCHASTIC", 1), ("BEFORE", 1), ("AFTER", 1)])
+@pytest.mark.parametrize("fmt", [1, 2])
+@pytest.mark.parametrize("shade", [0, 1])
+def test_neural_filter2d_parity(sf, orc, filt, mode, spp, fmt, shade):
+    _case("neural_filter2d", filt, mode, spp, fmt, shade)
+    res = (32, 24)
+    grid, Z = _grid(sf, orc, 2, res, 8, fmt, seed=5)
+    P = _params(8, 4, 6)
+    mlp = sf.MLP(torch.from_numpy(P).cuda(), 8, 4)
+    q = inputs.queries_uniform(3001, seed=7)
+    q[:3, 0] = [-0.3, 1.25, np.nan]
+    f, m = getattr(sf, "SF_" + filt), getattr(sf, "SF_" + mode.replace("AFTER", "AFTER_EXACT"))
+    smp = sf.sampling(f, m, spp, seed=11)
+    taps = torch.empty((q.shape[0], spp, 2), dtype=torch.int32, device="cuda") if mode == "STOCHASTIC" else None
+    out = sf.sf_neural_decode(grid, mlp, torch.from_numpy(q).cuda(), smp, shade=shade, ggx_params=sf.ggx(),
+                              dbg_taps=taps).cpu().numpy()
+    om = {"STOCHASTIC": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    res_ = orc.neural_filter2d(res, 8, H, 4, Z, _bf16(P), q, getattr(orc, filt), om, spp=spp, seed=11, shade=shade,
+                               act_bf16=True, taps=mode == "STOCHASTIC")
+    if mode == "STOCHASTIC":
+        ref, rt = res_
+        assert np.array_equal(taps.cpu().numpy(), rt)
+    else:
+        ref = res_
+    _close_bf16(out, ref)
+
+
+@pytest.mark.parametrize("filt", ["LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_neural_raymarch_parity(sf, orc, filt, fmt):
+    _case("neural_raymarch", filt, fmt)
+    res = (12, 11, 10)
+    grid, Z = _grid(sf, orc, 3, res, 16, fmt, seed=8, wmin=(0, 0, 0), scale=res)
+    P = _params(16, 1, 9, scale=0.2)
+    P[-1] = 0.3
+    mlp = sf.MLP(torch.from_numpy(P).cuda(), 16, 1)
+    rays = inputs.random_rays(1001, 1.0, seed=10)
+    rays[0, 0] = np.nan
+    steps, spp = 24, 2
+    f = getattr(sf, "SF_" + filt)
+    smp = sf.sampling(f, sf.SF_STOCHASTIC, spp, seed=12)
+    taps = torch.empty((rays.shape[0], spp, steps, 3), dtype=torch.int32, device="cuda")
+    T = sf.sf_neural_raymarch(grid, mlp, torch.from_numpy(rays).cuda(), steps, smp, dbg_taps=taps).cpu().numpy()
+    ref, rt = orc.neural_raymarch(res, 16, H, Z, _bf16(P), (0, 0, 0), np.array(res, np.float32), rays, steps,
+                                  getattr(orc, filt), orc.STOCHASTIC, spp=spp, seed=12, act_bf16=True, taps=True)
+    assert np.array_equal(taps.cpu().numpy(), rt)
+    # compare optical depths (T = mean of exp(-tau)); relative decode error carries to tau
+    _close_bf16(T, ref)
+    # without the tap dump the same stream gives the same result
+    T2 = sf.sf_neural_raymarch(grid, mlp, torch.from_numpy(rays).cuda(), steps, smp).cpu().numpy()
+    assert np.array_equal(T, T2, equal_nan=True)
+
+
+def _normwise(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("C, O", [(8, 4), (16, 1)])
+def test_train_step_parity(sf, orc, C, O):
+    """Gradients of one step (FP32 GPU) vs the FP64 oracle at the same
+    inputs; the Adam updates follow from the GPU's own gradients; latents
+    outside the batch are untouched."""
+    _case("train_step", C, O)
+    rng = np.random.default_rng(20)
+    nlat, B = 2000, 700
+    lat = rng.normal(size=(nlat, C)).astype(np.float32)
+    P = _params(C, O, 21, scale=0.2)
+    targets = rng.uniform(0, 1, size=(nlat, O)).astype(np.float32)
+    idx = rng.permutation(nlat)[:B].astype(np.int32)
+    st = sf.TrainState(torch.from_numpy(lat.ravel()).cuda(), torch.from_numpy(P).cuda(), C, O)
+    gP = torch.zeros(P.size, dtype=torch.float32, device="cuda")
+    gZ = torch.zeros((B, C), dtype=torch.float32, device="cuda")
+    loss = sf.sf_neural_train_step(st, torch.from_numpy(idx).cuda(), torch.from_numpy(targets.ravel()).cuda(),
+                                   lr_latent=1e-2, lr_mlp=1e-3, grad_params=gP, grad_latents=gZ)
+    oloss, ogP, ogZ = orc.mlp_grad(C, H, O, P.astype(np.float64), lat[idx].astype(np.float64),
+                                   targets[idx].astype(np.float64))
+    assert abs(loss.item() - oloss) <= 1e-5 * oloss
+    gp = gP.cpu().numpy()
+    offs = np.cumsum([0, C * H, H, H * H, H, H * O, O])
+    for a, b in zip(offs[:-1], offs[1:]):
+        assert _normwise(gp[a:b], ogP[a:b]) <= 1e-5, (a, b, _normwise(gp[a:b], ogP[a:b]))
+    assert _normwise(gZ.cpu().numpy(), ogZ) <= 1e-5
+    # Adam step from the GPU's own gradients (first step: lr g / (|g| + eps))
+    newP = st.params.cpu().numpy().astype(np.float64)
+    g = gp.astype(np.float64)
+    assert np.allclose(newP, P + -1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=2e-7)
+    newZ = st.latents.cpu().numpy().reshape(nlat, C).astype(np.float64)
+    gz = gZ.cpu().numpy().astype(np.float64)
+    assert np.allclose(newZ[idx], lat[idx] - 1e-2 * gz / (np.abs(gz) + 1e-8), rtol=0, atol=2e-6)
+    rest = np.setdiff1d(np.arange(nlat), idx)
+    assert np.array_equal(newZ[rest], lat[rest].astype(np.float64))
+
+
+def test_training_converges_and_decodes(sf, orc):
+    """A small neural texture trained on plain B-spline magnification
+    targets: the loss drops by more than 20x and the BF16 matrix-core
+    decoder reproduces the targets closely."""
+    _case("train_converge")
+    src = inputs.texture_uniform(8, seed=1)
+    R = 64
+    lat_uv = np.zeros((R * R, 3), np.float32)
+    yy, xx = np.mgrid[0:R, 0:R]
+    lat_uv[:, 0] = ((xx + 0.5) / R).ravel()
+    lat_uv[:, 1] = ((yy + 0.5) / R).ravel()
+    tex = sf.Texture2D([src])
+    targets = sf.sf_filter2d(tex, torch.from_numpy(lat_uv).cuda(), sf.sampling(sf.SF_BSPLINE3, sf.SF_BEFORE, 1))
+    rng = np.random.default_rng(3)
+    lat = (rng.normal(size=(R * R, 8)) * 0.1).astype(np.float32)
+    P = _params(8, 4, 4, scale=0.15)
+    st = sf.TrainState(torch.from_numpy(lat.ravel()).cuda(), torch.from_numpy(P).cuda(), 8, 4)
+    losses = []
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    for it in range(600):
+        perm = torch.randperm(R * R, device="cuda", generator=gen)[:1024].to(torch.int32)
+        l = sf.sf_neural_train_step(st, perm, targets, lr_latent=1e-2, lr_mlp=2e-3)
+        if it % 50 == 0 or it == 599:
+            losses.append(l.item())
+    assert losses[-1] < losses[0] / 20, losses
+    grid = sf.sf_neural_quantize(st.latents, 2, (R, R), 8, sf.SF_LATENT_BF16)
+    mlp = sf.MLP(st.params, 8, 4)
+    dec = sf.sf_neural_decode_lattice(grid, mlp, torch.arange(R * R, device="cuda", dtype=torch.int64))
+    rmse = torch.sqrt(torch.mean((dec - targets) ** 2)).item()
+    assert rmse < 0.05, rmse
