@@ -66,8 +66,12 @@ enum {
 };
 
 /* Separable reconstruction filter per axis (Suppl. S.2): box K0 (nearest),
- * tent K1 (bi/trilinear), cubic B-spline K_bs (bi/tricubic, eq. cubic-bspline). */
-enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2 };
+ * tent K1 (bi/trilinear), cubic B-spline K_bs (bi/tricubic, eq. cubic-bspline),
+ * and the interpolating cubic K3 with a = -1/2 (Keys), whose negative lobes
+ * the stochastic mode handles by positivisation (Sec. 2.2 "Positivization"):
+ * one tap drawn from the positive and one from the negative product
+ * weights, estimate W+ f(t+) - W- f(t-).  SF_KEYS3 is a 2-D texture filter. */
+enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3 };
 /* SF_BEFORE: shade(sum_i w_i t_i)            (eq. filter-before-shading)
  * SF_AFTER_EXACT: sum_i w_i shade(t_i)        (eq. filtering-after-shading)
  * SF_STOCHASTIC: mean over spp of shade(t_j), P(j) = w_j (eq. stochastic-sum) */
@@ -119,7 +123,9 @@ typedef struct sf_ggx {
 /* A dense 3-D grid of scalar density (x fastest, then y, then z) occupying
  * the world box from wmin; scale = voxels per world unit per axis.  World
  * point x maps to raster p = (x - wmin)*scale - 0.5 (subtract, then one fused
- * multiply-add).  Taps outside the grid read zero (empty space).
+ * multiply-add).  Taps outside the grid read zero (empty space).  A grid
+ * holds at most 4 GiB (it is addressed with 32-bit byte offsets) and
+ * ny*nz <= 2^24.
  * occupancy: NULL, or the brick mask sf_build_occupancy wrote for this grid
  * and brick_log2 (the mask must be rebuilt whenever the grid changes).  The
  * ray march then skips every step whose lookup point lies in a brick whose
@@ -143,7 +149,17 @@ typedef struct sf_volume {
  *   shade   : SF_SHADE_NONE -> out is n x 4 float32 (filtered RGBA);
  *             SF_SHADE_GGX  -> out is n x 3 float32 (RGB radiance); ggx required.
  *   dbg_taps: NULL, or n x spp x {level, x, y} int32 (stochastic mode only):
- *             the texel each sample read, after wrapping.
+ *             the texel each sample read, after wrapping; with SF_KEYS3
+ *             n x spp x {level, x+, y+, x-, y-} (SF_TAP_NONE when the negative
+ *             weights vanish).  Keys decisions (binary32): per axis
+ *             m0 = (t/2)(s s), m3 = (s/2)(t t), p1 = fma(t t, fma(3/2, t, -5/2), 1),
+ *             p2 likewise in s = 1-t, P+ = p1 + p2, P- = m0 + m3; a positive pair
+ *             takes its first tap iff u P+ < p1, a negative pair iff u P- < m0;
+ *             the positive sample is in block (+,+) iff u (A+B) < A, A = P+x P+y,
+ *             B = P-x P-y; the negative one in (+,-) iff u (C+D) < C, C = P+x P-y,
+ *             D = P-x P+y; uniforms: words 0,1,2 of the sample's key for the
+ *             positive draw (x, y, block) and of its key with step 1 for the
+ *             negative draw.
  * Defines: Sec. 2.2 eqs. filtered-texture and stochastic-sum; Sec. 3 eqs.
  * filter-before-shading and filtering-after-shading; Sec. 4.1 eq.
  * bicubic-bspline-texfilt; Suppl. S.1 stochastic bilerp; MIP level pick of

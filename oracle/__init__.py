@@ -21,7 +21,7 @@ _SRCS = [_SRC, os.path.join(_HERE, "neural.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # enums of the oracle (its own copy; it does not include the library header)
-NEAREST, LINEAR, BSPLINE3 = 0, 1, 2
+NEAREST, LINEAR, BSPLINE3, KEYS3 = 0, 1, 2, 3
 BEFORE, AFTER, STOCHASTIC = 0, 1, 2
 RGBA32F, RGBA8, R16F, R32F = 0, 1, 2, 3
 REPEAT, CLAMP = 0, 1
@@ -76,6 +76,10 @@ def lib():
                                    P, P, P, i64]
         L.orc_raymarch_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
         L.orc_build_occupancy.argtypes = [P, i32, i32, i32, i32, i32, P]
+        L.orc_k3.restype = C.c_double
+        L.orc_k3.argtypes = [C.c_double]
+        L.orc_keys_pick.argtypes = [f32, f32, P, P, P]
+        L.orc_keys_expect2d.argtypes = [P, i32, i32, i32, i32, P, i64, i32, P, P]
         L.orc_f32_to_bf16.restype = C.c_uint16
         L.orc_f32_to_bf16.argtypes = [f32]
         L.orc_bf16_to_double.restype = C.c_double
@@ -208,14 +212,15 @@ class Tex2D:
 def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed: int = 0,
              variant: int = 0, shade: int = 0, ggx=None, taps: bool = False, subset=None):
     """Filter every query, or only the rows listed in ``subset`` (their own
-    index keys the random stream)."""
+    index keys the random stream).  Taps: {level, x, y} per sample, or
+    {level, x+, y+, x-, y-} for the positivised Keys cubic."""
     q = _c(q, np.float32).reshape(-1, 3)
     n = q.shape[0]
     sub = None if subset is None else _c(subset, np.int64)
     m = n if sub is None else sub.size
     ch = 3 if shade == 1 else 4
     out = np.zeros((m, ch))
-    tp = np.zeros((m, spp, 3), dtype=np.int32) if taps else None
+    tp = np.zeros((m, spp, 5 if filt == KEYS3 else 3), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_filter2d(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
                        _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, shade, _p(g), _p(out), _p(tp),
@@ -392,3 +397,24 @@ def neural_raymarch(res, C, H, Z, P, wmin, scale, rays, steps, filt, mode, spp=1
                               _p(rays), n, steps, filt, mode, spp, seed & 0xFFFFFFFF, _p(T), _p(tp), _p(sub),
                               0 if sub is None else sub.size)
     return (T, tp) if taps else T
+
+
+def k3(x: float) -> float:
+    return lib().orc_k3(float(x))
+
+
+def keys_pick(tx: float, ty: float, u) -> tuple:
+    uu = _c(u, np.float32)
+    off = np.zeros(4, dtype=np.int32)
+    hn = np.zeros(1, dtype=np.int32)
+    lib().orc_keys_pick(float(tx), float(ty), _p(uu), _p(off), _p(hn))
+    return off, bool(hn[0])
+
+
+def keys_expect2d(tex: Tex2D, q: np.ndarray, shade: int = 0, ggx=None):
+    q = _c(q, np.float32).reshape(-1, 3)
+    ch = 3 if shade == 1 else 4
+    out = np.zeros((q.shape[0], ch))
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_keys_expect2d(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(q), q.shape[0], shade, _p(g), _p(out))
+    return out

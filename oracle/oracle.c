@@ -52,7 +52,7 @@
 
 #define ORC_EXPORT __attribute__((visibility("default")))
 
-enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2 };
+enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2, F_KEYS3 = 3 };
 enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2 };
 enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3 };
 enum { WRAP_REPEAT = 0, WRAP_CLAMP = 1 };
@@ -114,6 +114,19 @@ ORC_EXPORT double orc_kbs(double x)
     return 0.0;
 }
 
+/* Interpolating cubic K3 of S.2 with a = -1/2 (Keys): negative lobes on
+ * 1 < |x| < 2. */
+ORC_EXPORT double orc_k3(double x)
+{
+    const double a = -0.5;
+    double t = fabs(x);
+    if (t < 1.0)
+        return (a + 2.0) * t * t * t - (a + 3.0) * t * t + 1.0;
+    if (t < 2.0)
+        return a * t * t * t - 5.0 * a * t * t + 8.0 * a * t - 4.0 * a;
+    return 0.0;
+}
+
 ORC_EXPORT double orc_ktent(double x)
 {
     double a = fabs(x);
@@ -136,6 +149,12 @@ static int axis_weights(int filter, double t, int *first_off, double w[4])
         w[0] = orc_ktent(t);
         w[1] = orc_ktent(t - 1.0);
         return 2;
+    }
+    if (filter == F_KEYS3) {
+        *first_off = -1;
+        for (int k = 0; k < 4; ++k)
+            w[k] = orc_k3(t - (double)(k - 1));
+        return 4;
     }
     /* nearest (box, S.2 K0): the texel whose cell contains the point */
     *first_off = (t >= 0.5) ? 1 : 0;
@@ -193,6 +212,76 @@ ORC_EXPORT int orc_sample_array(const double *w, int n, double xi)
             return j;
     }
     return n - 1;
+}
+
+/* Positivisation of the separable Keys cubic (Sec. 2.2 "Positivization").
+ * Per axis, taps i0-1..i0+2 carry weights (-m0, p1, p2, -m3) with
+ * m0 = t s^2/2, m3 = s t^2/2, p1 = 1 - 5t^2/2 + 3t^3/2, p2 the same in s = 1-t
+ * (S.2's K3 at a = -1/2, factored); their sums are P+ = p1 + p2 and
+ * P- = m0 + m3.  A 2-D product weight is positive on (+,+) and (-,-) and
+ * negative on (+,-) and (-,+).  One tap is drawn from each set in proportion
+ * to |w|: first the block (by the block sums), then one tap per axis inside
+ * the axis' positive or negative pair.  binary32 decision contract:
+ * s = 1-t; m0 = (0.5 t)(s s); m3 = (0.5 s)(t t); Pm = m0 + m3;
+ * p1 = fma(t t, fma(1.5, t, -2.5), 1); p2 likewise in s; Pp = p1 + p2;
+ * inside the positive pair the first tap is taken iff u*Pp < p1, inside the
+ * negative pair iff u*Pm < m0; block (+,+) iff u*(A+B) < A with A = Ppx*Ppy,
+ * B = Pmx*Pmy; block (+,-) iff u*(Cn+Dn) < Cn with Cn = Ppx*Pmy, Dn = Pmx*Ppy. */
+typedef struct {
+    float m0, m3, Pm, p1, p2, Pp;
+} keys_axis;
+
+static keys_axis keys_axis_of(float t)
+{
+    keys_axis k;
+    float s = 1.0f - t;
+    k.m0 = (0.5f * t) * (s * s);
+    k.m3 = (0.5f * s) * (t * t);
+    k.Pm = k.m0 + k.m3;
+    k.p1 = fmaf(t * t, fmaf(1.5f, t, -2.5f), 1.0f);
+    k.p2 = fmaf(s * s, fmaf(1.5f, s, -2.5f), 1.0f);
+    k.Pp = k.p1 + k.p2;
+    return k;
+}
+
+/* Tap offsets (relative to i0) of the positive and negative samples; *has_neg
+ * is 0 when the negative set is empty (t = 0 on both axes' lobes). */
+ORC_EXPORT void orc_keys_pick(float tx, float ty, const float u[6], int off[4], int *has_neg)
+{
+    keys_axis kx = keys_axis_of(tx), ky = keys_axis_of(ty);
+    float A = kx.Pp * ky.Pp, B = kx.Pm * ky.Pm;
+    int pp = u[2] * (A + B) < A;               /* positive block: (+,+) or (-,-) */
+    if (pp) {
+        off[0] = (u[0] * kx.Pp < kx.p1) ? 0 : 1;
+        off[1] = (u[1] * ky.Pp < ky.p1) ? 0 : 1;
+    } else {
+        off[0] = (u[0] * kx.Pm < kx.m0) ? -1 : 2;
+        off[1] = (u[1] * ky.Pm < ky.m0) ? -1 : 2;
+    }
+    float Cn = kx.Pp * ky.Pm, Dn = kx.Pm * ky.Pp;
+    *has_neg = (Cn + Dn) > 0.0f;
+    int xpos = u[5] * (Cn + Dn) < Cn;          /* negative block: (+,-) or (-,+) */
+    if (xpos) {
+        off[2] = (u[3] * kx.Pp < kx.p1) ? 0 : 1;
+        off[3] = (u[4] * ky.Pm < ky.m0) ? -1 : 2;
+    } else {
+        off[2] = (u[3] * kx.Pm < kx.m0) ? -1 : 2;
+        off[3] = (u[4] * ky.Pp < ky.p1) ? 0 : 1;
+    }
+}
+
+/* binary64 block sums of the positive and negative product weights. */
+static void keys_block_sums(double tx, double ty, double *Wp, double *Wm)
+{
+    double wx[4], wy[4];
+    for (int k = 0; k < 4; ++k) {
+        wx[k] = orc_k3(tx - (double)(k - 1));
+        wy[k] = orc_k3(ty - (double)(k - 1));
+    }
+    double Ppx = wx[1] + wx[2], Pmx = -(wx[0] + wx[3]);
+    double Ppy = wy[1] + wy[2], Pmy = -(wy[0] + wy[3]);
+    *Wp = Ppx * Ppy + Pmx * Pmy;
+    *Wm = Ppx * Pmy + Pmx * Ppy;
 }
 
 /* Index of the picked tap among the filter's taps (0..3), ties advance. */
@@ -410,8 +499,8 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
         for (int c = 0; c < ch; ++c)
             out[c] = NAN;
         if (taps && mode == M_STOCH)
-            for (int s = 0; s < spp; ++s)
-                taps[3 * s] = taps[3 * s + 1] = taps[3 * s + 2] = INT32_MIN;
+            for (int s = 0; s < (filter == F_KEYS3 ? 5 : 3) * spp; ++s)
+                taps[s] = INT32_MIN;
         return;
     }
     float uu = wrap_coord(t->wrap, q[0]);
@@ -433,6 +522,38 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
             float tx, ty;
             raster(uu, wl, &ix, &tx);
             raster(vv, hl, &iy, &ty);
+            if (filter == F_KEYS3) {
+                /* positivised estimator: W+ shade(t+) - W- shade(t-) */
+                uint32_t key2[4] = {(uint32_t)qi, (uint32_t)s, 1u, seed}, w2[4];
+                orc_pcg4d(key2, w2);
+                float u6[6] = {ux, uy, uniform24(w[2]), uniform24(w2[0]), uniform24(w2[1]), uniform24(w2[2])};
+                int off[4], has_neg;
+                orc_keys_pick(tx, ty, u6, off, &has_neg);
+                double Wp, Wm;
+                keys_block_sums((double)tx, (double)ty, &Wp, &Wm);
+                int xp = wrap_tap(t->wrap, ix + off[0], wl), yp = wrap_tap(t->wrap, iy + off[1], hl);
+                int xn = wrap_tap(t->wrap, ix + off[2], wl), yn = wrap_tap(t->wrap, iy + off[3], hl);
+                if (taps) {
+                    int32_t *q5 = taps + 5 * s;
+                    q5[0] = l;
+                    q5[1] = xp;
+                    q5[2] = yp;
+                    q5[3] = has_neg ? xn : INT32_MIN;
+                    q5[4] = has_neg ? yn : INT32_MIN;
+                }
+                double texel[4], v[4], vn[4];
+                fetch2d(t, l, xp, yp, texel);
+                shade2d(shade, ggx, texel, v);
+                for (int c = 0; c < ch; ++c)
+                    acc[c] += Wp * v[c];
+                if (has_neg) {
+                    fetch2d(t, l, xn, yn, texel);
+                    shade2d(shade, ggx, texel, vn);
+                    for (int c = 0; c < ch; ++c)
+                        acc[c] -= Wm * vn[c];
+                }
+                continue;
+            }
             int offx = filter == F_BSPLINE3 ? -1 : 0;
             int jx = orc_pick(filter, tx, ux);
             if (variant == 1)
@@ -509,8 +630,9 @@ ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt,
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i) {
         int64_t qi = subset ? subset[i] : i;
+        int tw = filter == F_KEYS3 ? 5 : 3;
         filter2d_one(&t, q + 3 * qi, qi, filter, mode, spp, seed, variant, shade, ggx, out + ch * i,
-                     taps ? taps + (int64_t)3 * spp * i : NULL);
+                     taps ? taps + (int64_t)tw * spp * i : NULL);
     }
     return 0;
 }
@@ -567,6 +689,57 @@ ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, i
                         o[c2] += pr * v[c2];
                 }
         }
+    }
+    return 0;
+}
+
+/* Fraction of the 2^24 uniforms u with u*P < p in binary32 (brute force). */
+static double frac_lt(float P, float p)
+{
+    int64_t c = 0;
+    for (uint32_t k = 0; k < (1u << 24); ++k)
+        c += ((float)k * 0x1p-24f) * P < p;
+    return (double)c / 16777216.0;
+}
+
+/* Exact expectation of the positivised Keys estimator (level 0, shade as in
+ * filter2d) over the 24-bit uniforms: every decision's probability counted
+ * by brute force, the block sums in binary64. */
+ORC_EXPORT int orc_keys_expect2d(const void *base, int w, int h, int fmt, int wrap, const float *q, int64_t n,
+                                 int shade, const double *ggx, double *out)
+{
+    const int64_t off0 = 0;
+    tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0};
+    int ch = shade == 1 ? 3 : 4;
+    for (int64_t i = 0; i < n; ++i) {
+        float uu = wrap_coord(wrap, q[3 * i]), vv = wrap_coord(wrap, q[3 * i + 1]);
+        int ix, iy;
+        float tx, ty;
+        raster(uu, w, &ix, &tx);
+        raster(vv, h, &iy, &ty);
+        keys_axis kx = keys_axis_of(tx), ky = keys_axis_of(ty);
+        double Wp, Wm;
+        keys_block_sums((double)tx, (double)ty, &Wp, &Wm);
+        /* per-axis pair probabilities: P(first tap | positive pair), P(first | negative pair) */
+        double pxp = frac_lt(kx.Pp, kx.p1), pxm = frac_lt(kx.Pm, kx.m0);
+        double pyp = frac_lt(ky.Pp, ky.p1), pym = frac_lt(ky.Pm, ky.m0);
+        float A = kx.Pp * ky.Pp, B = kx.Pm * ky.Pm, Cn = kx.Pp * ky.Pm, Dn = kx.Pm * ky.Pp;
+        double pblk = frac_lt(A + B, A), nblk = (Cn + Dn) > 0.0f ? frac_lt(Cn + Dn, Cn) : 0.0;
+        double PX[2][4] = {{0, pxp, 1 - pxp, 0}, {pxm, 0, 0, 1 - pxm}}; /* [pos/neg pair][tap] */
+        double PY[2][4] = {{0, pyp, 1 - pyp, 0}, {pym, 0, 0, 1 - pym}};
+        double acc[4] = {0, 0, 0, 0};
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                double texel[4], v[4];
+                fetch2d(&t, 0, wrap_tap(wrap, ix - 1 + a, w), wrap_tap(wrap, iy - 1 + b, h), texel);
+                shade2d(shade, ggx, texel, v);
+                double ppos = pblk * PX[0][a] * PY[0][b] + (1 - pblk) * PX[1][a] * PY[1][b];
+                double pneg = nblk * PX[0][a] * PY[1][b] + (1 - nblk) * PX[1][a] * PY[0][b];
+                for (int c = 0; c < ch; ++c)
+                    acc[c] += Wp * ppos * v[c] - ((Cn + Dn) > 0.0f ? Wm * pneg * v[c] : 0.0);
+            }
+        for (int c = 0; c < ch; ++c)
+            out[ch * i + c] = acc[c];
     }
     return 0;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libsf.so")
 
 # enums (values fixed by include/sf.h)
 SF_OK, SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED, SF_E_DEVICE, SF_E_WORKSPACE = range(6)
-SF_NEAREST, SF_LINEAR, SF_BSPLINE3 = 0, 1, 2
+SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3 = 0, 1, 2, 3
 SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC = 0, 1, 2
 SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F = 0, 1, 2, 3
 SF_WRAP_REPEAT, SF_WRAP_CLAMP = 0, 1
@@ -250,7 +250,7 @@ def sf_filter2d(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, shade: 
     _need(out, torch.float32, "out")
     if dbg_taps is not None:
         _need(dbg_taps, torch.int32, "dbg_taps")
-        if dbg_taps.numel() < n * smp.spp * 3:
+        if dbg_taps.numel() < n * smp.spp * (5 if smp.filter == SF_KEYS3 else 3):
             raise ValueError("dbg_taps too small")
     g = C.byref(ggx_params) if ggx_params is not None else None
     _check(lib().sf_filter2d(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), shade, g, _ptr(out),

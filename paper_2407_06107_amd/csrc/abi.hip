@@ -33,7 +33,7 @@ sf_status check_sampling(const sf_sampling *smp)
 {
     if (!smp)
         return fail(SF_E_NULL, "sampling descriptor is NULL");
-    if (smp->filter < SF_NEAREST || smp->filter > SF_BSPLINE3)
+    if (smp->filter < SF_NEAREST || smp->filter > SF_KEYS3)
         return fail(SF_E_RANGE, "filter %d out of range", smp->filter);
     if (smp->mode < SF_BEFORE || smp->mode > SF_STOCHASTIC)
         return fail(SF_E_RANGE, "mode %d out of range", smp->mode);
@@ -65,8 +65,9 @@ sf_status check_volume(const sf_volume *v, sfk::VolArgs &a)
         return fail(SF_E_RANGE, "grid %d x %d x %d outside 1..4096 per axis", v->nx, v->ny, v->nz);
     const size_t esz = v->format == SF_R16F ? 2 : 4;
     const uint64_t bytes = (uint64_t)v->nx * v->ny * v->nz * esz;
-    if (bytes > 0x7fffffffULL || (uint64_t)v->ny * v->nz > (1ULL << 24))
-        return fail(SF_E_UNSUPPORTED, "grid of %llu bytes exceeds the 2 GiB addressing of one buffer",
+    // one raw buffer resource addresses the grid with 32-bit byte offsets
+    if (bytes > 0xffffffffULL || (uint64_t)v->ny * v->nz > (1ULL << 24))
+        return fail(SF_E_UNSUPPORTED, "grid of %llu bytes exceeds the 4 GiB addressing of one buffer",
                     (unsigned long long)bytes);
     if (!aligned(v->base, esz))
         return fail(SF_E_RANGE, "volume base pointer misaligned");
@@ -88,6 +89,11 @@ sf_status check_volume(const sf_volume *v, sfk::VolArgs &a)
         a.nbx = (v->nx + B - 1) / B;
         a.nby = (v->ny + B - 1) / B;
         a.nbz = (v->nz + B - 1) / B;
+    }
+    a.lx = a.ly = -1;
+    if ((v->nx & (v->nx - 1)) == 0 && (v->ny & (v->ny - 1)) == 0) {
+        a.lx = __builtin_ctz((unsigned)v->nx);
+        a.ly = __builtin_ctz((unsigned)v->ny);
     }
     a.base = v->base;
     a.nx = v->nx;
@@ -164,6 +170,8 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
         return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
+    if (smp->filter == SF_KEYS3 && smp->rng_variant != 0)
+        return fail(SF_E_UNSUPPORTED, "the positivised Keys cubic draws independent uniforms (rng_variant 0)");
     if (!tex->base)
         return fail(SF_E_NULL, "texture base pointer is NULL");
     if (tex->format != SF_RGBA32F && tex->format != SF_RGBA8_UNORM)
@@ -228,6 +236,8 @@ sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const s
         return fail(SF_E_NULL, "pos and out must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
+    if (smp->filter == SF_KEYS3)
+        return fail(SF_E_UNSUPPORTED, "the Keys cubic is a 2-D texture filter here");
     sfk::Filter3DCall c{};
     if ((st = check_volume(vol, c.vol)) != SF_OK)
         return st;
@@ -265,6 +275,8 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
         return fail(SF_E_NULL, "rays and T must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
+    if (smp->filter == SF_KEYS3)
+        return fail(SF_E_UNSUPPORTED, "the Keys cubic is a 2-D texture filter here");
     sfk::RaymarchCall c{};
     if ((st = check_volume(vol, c.vol)) != SF_OK)
         return st;
@@ -390,8 +402,8 @@ sf_status sf_neural_decode(const sf_latent_grid *grid, const sf_mlp *mlp, const 
         return fail(SF_E_NULL, "queries and out must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
-    if (smp->rng_variant != 0)
-        return fail(SF_E_UNSUPPORTED, "neural decoding uses independent uniforms (rng_variant 0)");
+    if (smp->rng_variant != 0 || smp->filter == SF_KEYS3)
+        return fail(SF_E_UNSUPPORTED, "neural decoding: NEAREST, LINEAR or BSPLINE3 with independent uniforms");
     sfk::NeuralCall c{};
     if ((st = check_grid(grid, true, c.lat)) != SF_OK)
         return st;
@@ -435,8 +447,9 @@ sf_status sf_neural_raymarch(const sf_latent_grid *grid, const sf_mlp *mlp, cons
         return fail(SF_E_NULL, "rays and T must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
-    if (smp->mode != SF_STOCHASTIC || smp->rng_variant != 0)
-        return fail(SF_E_UNSUPPORTED, "the neural ray march is stochastic with independent uniforms");
+    if (smp->mode != SF_STOCHASTIC || smp->rng_variant != 0 || smp->filter == SF_KEYS3)
+        return fail(SF_E_UNSUPPORTED, "the neural ray march is stochastic (NEAREST, LINEAR or BSPLINE3) with "
+                                      "independent uniforms");
     sfk::NeuralCall c{};
     if ((st = check_grid(grid, true, c.lat)) != SF_OK)
         return st;

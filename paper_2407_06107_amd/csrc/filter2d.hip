@@ -117,11 +117,12 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
         if (!query_ok(c.tex, qq)) {
             float nan = __builtin_nanf("");
             acc = make_float4(nan, nan, nan, nan);
-            if (c.taps)
-                for (int s = lane; s < c.spp; s += G) {
-                    int32_t *tp = c.taps + (q * c.spp + s) * 3;
-                    tp[0] = tp[1] = tp[2] = SF_TAP_NONE;
-                }
+            if (c.taps) {
+                constexpr int TW = F == KEYS3 ? 5 : 3;
+                for (int s = lane; s < c.spp; s += G)
+                    for (int k = 0; k < TW; ++k)
+                        c.taps[(q * c.spp + s) * TW + k] = SF_TAP_NONE;
+            }
         } else {
             const float uu = wrap_coord(c.tex.wrap, qq.x), vv = wrap_coord(c.tex.wrap, qq.y);
             int l0, l1;
@@ -136,6 +137,49 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
                 float tx, ty;
                 raster(uu, wl, ix, tx);
                 raster(vv, hl, iy, ty);
+                if constexpr (F == KEYS3) {
+                    // positivisation (Sec. 2.2): one tap from the positive and
+                    // one from the negative product weights, W+ f(t+) - W- f(t-)
+                    const uint4 w2 = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 1u, c.seed));
+                    const KeysAxis kx = keys_axis(tx), ky = keys_axis(ty);
+                    const float A = kx.Pp * ky.Pp, B = kx.Pm * ky.Pm, Cn = kx.Pp * ky.Pm, Dn = kx.Pm * ky.Pp;
+                    int ox, oy, nx, ny;
+                    if (u24(w.z) * (A + B) < A) {
+                        ox = u24(w.x) * kx.Pp < kx.p1 ? 0 : 1;
+                        oy = u24(w.y) * ky.Pp < ky.p1 ? 0 : 1;
+                    } else {
+                        ox = u24(w.x) * kx.Pm < kx.m0 ? -1 : 2;
+                        oy = u24(w.y) * ky.Pm < ky.m0 ? -1 : 2;
+                    }
+                    const bool has_neg = (Cn + Dn) > 0.0f;
+                    if (u24(w2.z) * (Cn + Dn) < Cn) {
+                        nx = u24(w2.x) * kx.Pp < kx.p1 ? 0 : 1;
+                        ny = u24(w2.y) * ky.Pm < ky.m0 ? -1 : 2;
+                    } else {
+                        nx = u24(w2.x) * kx.Pm < kx.m0 ? -1 : 2;
+                        ny = u24(w2.y) * ky.Pp < ky.p1 ? 0 : 1;
+                    }
+                    const int xp = wrap_tap(c.tex.wrap, ix + ox, wl), yp = wrap_tap(c.tex.wrap, iy + oy, hl);
+                    const int xn = wrap_tap(c.tex.wrap, ix + nx, wl), yn = wrap_tap(c.tex.wrap, iy + ny, hl);
+                    if (c.taps) {
+                        int32_t *tp = c.taps + (q * c.spp + s) * 5;
+                        tp[0] = l;
+                        tp[1] = xp;
+                        tp[2] = yp;
+                        tp[3] = has_neg ? xn : SF_TAP_NONE;
+                        tp[4] = has_neg ? yn : SF_TAP_NONE;
+                    }
+                    const float Wp = A + B, Wm = Cn + Dn;
+                    const float4 vp = shade<SHADE>(c.g, texel(c.tex, l, xp, yp));
+                    float4 vn = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (has_neg)
+                        vn = shade<SHADE>(c.g, texel(c.tex, l, xn, yn));
+                    acc.x += Wp * vp.x - Wm * vn.x;
+                    acc.y += Wp * vp.y - Wm * vn.y;
+                    acc.z += Wp * vp.z - Wm * vn.z;
+                    acc.w += Wp * vp.w - Wm * vn.w;
+                    continue;
+                }
                 int ox, oy;
                 if constexpr (VAR == 0) {
                     ox = pick_off<F>(tx, u24(w.x));
@@ -232,7 +276,7 @@ static void launch_f2(const Filter2DCall &c, hipStream_t s)
         int log_g = __builtin_ctz(G);
         int64_t threads = c.n * G;
         dim3 grid((uint32_t)((threads + 255) / 256)), block(256);
-        if (c.variant)
+        if (c.variant && F != KEYS3)
             k_filter2d_stoch<F, SHADE, 1><<<grid, block, 0, s>>>(c, log_g);
         else
             k_filter2d_stoch<F, SHADE, 0><<<grid, block, 0, s>>>(c, log_g);
@@ -262,6 +306,9 @@ hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s)
         break;
     case LINEAR:
         launch_f1<LINEAR>(c, s);
+        break;
+    case KEYS3:
+        launch_f1<KEYS3>(c, s);
         break;
     default:
         launch_f1<BSPLINE3>(c, s);

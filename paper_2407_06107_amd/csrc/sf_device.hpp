@@ -14,7 +14,7 @@
 
 namespace sfk {
 
-enum { NEAREST = 0, LINEAR = 1, BSPLINE3 = 2 };
+enum { NEAREST = 0, LINEAR = 1, BSPLINE3 = 2, KEYS3 = 3 };
 enum { BEFORE = 0, AFTER = 1, STOCH = 2 };
 
 // ---------------------------------------------------------------- random stream
@@ -139,6 +139,25 @@ __device__ __forceinline__ int pick_off_reuse(float t, float &u)
     }
 }
 
+// Interpolating Keys cubic (S.2's K3, a = -1/2) on taps i0-1..i0+2, split
+// into its positive pair (p1, p2) and negative pair (-m0, -m3), factored:
+// m0 = t s^2/2, m3 = s t^2/2, p1 = 1 - 5t^2/2 + 3t^3/2, p2 likewise in s = 1-t.
+struct KeysAxis {
+    float m0, m3, Pm, p1, p2, Pp;
+};
+__device__ __forceinline__ KeysAxis keys_axis(float t)
+{
+    KeysAxis k;
+    const float s = 1.0f - t;
+    k.m0 = (0.5f * t) * (s * s);
+    k.m3 = (0.5f * s) * (t * t);
+    k.Pm = k.m0 + k.m3;
+    k.p1 = __builtin_fmaf(t * t, __builtin_fmaf(1.5f, t, -2.5f), 1.0f);
+    k.p2 = __builtin_fmaf(s * s, __builtin_fmaf(1.5f, s, -2.5f), 1.0f);
+    k.Pp = k.p1 + k.p2;
+    return k;
+}
+
 // Weights of the taps (value path, binary32), same tap order as pick_off.
 template <int F>
 __device__ __forceinline__ void axis_weights(float t, float w[4])
@@ -154,6 +173,12 @@ __device__ __forceinline__ void axis_weights(float t, float w[4])
     } else if constexpr (F == LINEAR) {
         w[0] = 1.0f - t;
         w[1] = t;
+    } else if constexpr (F == KEYS3) {
+        const KeysAxis k = keys_axis(t);
+        w[0] = -k.m0;
+        w[1] = k.p1;
+        w[2] = k.p2;
+        w[3] = -k.m3;
     } else {
         w[0] = 1.0f;
     }
@@ -181,8 +206,8 @@ __device__ __forceinline__ void axis_weights64(float tf, double w[4])
 
 template <int F>
 struct Taps {
-    static constexpr int n = F == BSPLINE3 ? 4 : (F == LINEAR ? 2 : 1);
-    static constexpr int first = F == BSPLINE3 ? -1 : 0;
+    static constexpr int n = (F == BSPLINE3 || F == KEYS3) ? 4 : (F == LINEAR ? 2 : 1);
+    static constexpr int first = (F == BSPLINE3 || F == KEYS3) ? -1 : 0;
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip; map the

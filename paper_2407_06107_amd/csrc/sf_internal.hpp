@@ -27,10 +27,11 @@ struct Tex2DArgs {
 struct VolArgs {
     const void *base;
     int32_t nx, ny, nz, fmt;
-    uint32_t bytes;          // size of the grid in bytes (< 2^31)
+    uint32_t bytes;          // size of the grid in bytes (< 2^32)
     float wmin[3], scale[3];
     const uint32_t *occ;     // brick occupancy mask or null
     int32_t occ_log2, nbx, nby, nbz;
+    int32_t lx, ly;          // log2(nx), log2(ny) when both are powers of two, else -1
 };
 
 struct Filter2DCall {

@@ -16,19 +16,52 @@ namespace sfk {
 
 constexpr uint32_t kBufferFlags = 0x00020000u;  // raw buffer, 32-bit data format
 
-// One voxel; zero outside the grid.  Out-of-range taps read offset 0 (always
-// valid) and the value is then discarded.
+// Byte offset of voxel (x, y, z) and whether it lies in the grid.  A tap
+// outside the grid gets offset 0 (always valid) and its value is discarded.
+// P2: nx and ny are powers of two, so the index is built with shifts.
+template <bool HALF, bool P2>
+__device__ __forceinline__ uint32_t voxel_offset(const VolArgs &v, int x, int y, int z, bool &ok)
+{
+    ok = ((uint32_t)x < (uint32_t)v.nx) & ((uint32_t)y < (uint32_t)v.ny) & ((uint32_t)z < (uint32_t)v.nz);
+    uint32_t idx;
+    if constexpr (P2)
+        idx = ((((uint32_t)z << v.ly) | (uint32_t)y) << v.lx) | (uint32_t)x;
+    else
+        idx = __umul24(__umul24((uint32_t)z, (uint32_t)v.ny) + (uint32_t)y, (uint32_t)v.nx) + (uint32_t)x;
+    return ok ? idx * (HALF ? 2u : 4u) : 0u;
+}
+
+template <bool HALF>
+__device__ __forceinline__ uint32_t voxel_bits(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+{
+    if constexpr (HALF)
+        return __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+}
+
+template <bool HALF>
+__device__ __forceinline__ float bits_value(uint32_t b)
+{
+    if constexpr (HALF)
+        return half_bits_to_float((uint16_t)b);
+    else
+        return __builtin_bit_cast(float, b);
+}
+
+template <bool HALF>
+__device__ __forceinline__ float voxel_load(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+{
+    return bits_value<HALF>(voxel_bits<HALF>(rs, off));
+}
+
+// One voxel; zero outside the grid.
 template <bool HALF>
 __device__ __forceinline__ float voxel(__amdgpu_buffer_rsrc_t rs, const VolArgs &v, int x, int y, int z)
 {
-    bool ok = ((uint32_t)x < (uint32_t)v.nx) & ((uint32_t)y < (uint32_t)v.ny) & ((uint32_t)z < (uint32_t)v.nz);
-    uint32_t idx = __umul24(__umul24((uint32_t)z, (uint32_t)v.ny) + (uint32_t)y, (uint32_t)v.nx) + (uint32_t)x;
-    uint32_t off = ok ? idx * (HALF ? 2u : 4u) : 0u;
-    float val;
-    if constexpr (HALF)
-        val = half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0));
-    else
-        val = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    bool ok;
+    const uint32_t off = voxel_offset<HALF, false>(v, x, y, z, ok);
+    const float val = voxel_load<HALF>(rs, off);
     return ok ? val : 0.0f;
 }
 
@@ -74,7 +107,7 @@ __device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
 }
 
 // ---------------------------------------------------------------- ray march
-template <int F, bool HALF, int VAR, bool DBG, bool OCC>
+template <int F, bool HALF, int VAR, bool DBG, bool OCC, bool P2>
 __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_pad)
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
@@ -98,6 +131,10 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
         StepHash h;
         h.init((uint32_t)i, (uint32_t)s, c.seed);
         double tau = 0.0;
+        // software pipeline: a step's voxel is added one step later, so its
+        // load overlaps the next step's arithmetic
+        uint32_t pend = 0;
+        bool pend_ok = false;
         float kh = 0.5f;
         for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
             int i0[3], o[3];
@@ -115,8 +152,13 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
                 tp[1] = y;
                 tp[2] = z;
             }
-            tau += (double)voxel<HALF>(rs, c.vol, x, y, z);
+            bool ok;
+            const uint32_t off = voxel_offset<HALF, P2>(c.vol, x, y, z, ok);
+            tau += (double)(pend_ok ? bits_value<HALF>(pend) : 0.0f);   // step k-1
+            pend = voxel_bits<HALF>(rs, off);                           // step k
+            pend_ok = ok;
         }
+        tau += (double)(pend_ok ? bits_value<HALF>(pend) : 0.0f);
         Tsum += exp(-(double)g.dt * tau);
     }
     c.T[i] = (float)(Tsum / (double)c.spp);
@@ -319,15 +361,15 @@ hipError_t launch_build_occupancy(const VolArgs &v, int32_t lg, uint32_t *occ, i
 // ---------------------------------------------------------------- launchers
 static uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
 
-template <int F, bool HALF, bool OCC>
+template <int F, bool HALF, bool OCC, bool P2>
 static void launch_ray_fo(const RaymarchCall &c, dim3 grid, hipStream_t s, uint32_t nb_pad)
 {
     dim3 block(256);
     if (c.mode == STOCH) {
         if (c.variant)
-            k_ray_stoch<F, HALF, 1, false, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+            k_ray_stoch<F, HALF, 1, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
         else
-            k_ray_stoch<F, HALF, 0, false, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+            k_ray_stoch<F, HALF, 0, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
     } else if (c.mode == BEFORE) {
         k_ray_det<F, HALF, BEFORE, OCC><<<grid, block, 0, s>>>(c, nb_pad);
     } else {
@@ -341,16 +383,23 @@ static hipError_t launch_ray_f(const RaymarchCall &c, hipStream_t s)
     uint32_t nb = blocks_for(c.n);
     uint32_t nb_pad = (nb + 7u) & ~7u;
     dim3 grid(nb_pad), block(256);
+    const bool p2 = c.vol.lx >= 0;
     if (c.mode == STOCH && c.taps) {
         // the tap dump records every step, so it never skips empty bricks
         if (c.variant)
-            k_ray_stoch<F, HALF, 1, true, false><<<grid, block, 0, s>>>(c, nb_pad);
+            k_ray_stoch<F, HALF, 1, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
         else
-            k_ray_stoch<F, HALF, 0, true, false><<<grid, block, 0, s>>>(c, nb_pad);
+            k_ray_stoch<F, HALF, 0, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
     } else if (c.vol.occ) {
-        launch_ray_fo<F, HALF, true>(c, grid, s, nb_pad);
+        if (p2)
+            launch_ray_fo<F, HALF, true, true>(c, grid, s, nb_pad);
+        else
+            launch_ray_fo<F, HALF, true, false>(c, grid, s, nb_pad);
     } else {
-        launch_ray_fo<F, HALF, false>(c, grid, s, nb_pad);
+        if (p2)
+            launch_ray_fo<F, HALF, false, true>(c, grid, s, nb_pad);
+        else
+            launch_ray_fo<F, HALF, false, false>(c, grid, s, nb_pad);
     }
     return hipGetLastError();
 }

@@ -251,7 +251,7 @@ def cloud_grid(n: int = 512, seed: int = 4, device: str = "cpu", octaves: int = 
     fBm of value noise (``octaves`` octaves, lacunarity 2, gain 0.5, lowest
     octave ``base_cells`` cells across the grid) minus a radial falloff
     0.6*(r/r_max)^2 about the centre.  The ``empty_frac`` quantile theta of that
-    field maps to exactly zero and sigma = sigma_max*((n-theta)/(n_max-theta))^2
+    field (over a strided sample of 2^27 voxels for larger grids) maps to exactly zero and sigma = sigma_max*((n-theta)/(n_max-theta))^2
     above it, so about ``empty_frac`` of the voxels are exact zeros and sigma
     lies in [0, sigma_max].  Computed in float64, rounded once to float16.
     """
@@ -271,8 +271,14 @@ def cloud_grid(n: int = 512, seed: int = 4, device: str = "cpu", octaves: int = 
         r2 = (xx - 0.5) ** 2 + (yy - 0.5) ** 2 + (zz - 0.5) ** 2
         field[z0:z1] = acc / norm - 0.6 * r2 / (rmax * rmax)
     flat = field.reshape(-1)
-    k = max(1, int(round(empty_frac * flat.numel())))
-    theta = torch.kthvalue(flat.cpu() if dev.type == "cpu" else flat, k).values
+    if flat.numel() > (1 << 27):
+        # beyond 2^27 voxels the quantile is taken on an evenly strided sample
+        # of 2^27 of them
+        flat_q = flat[:: flat.numel() >> 27].contiguous()
+    else:
+        flat_q = flat
+    k = max(1, int(round(empty_frac * flat_q.numel())))
+    theta = torch.kthvalue(flat_q.cpu() if dev.type == "cpu" else flat_q, k).values
     nmax = flat.max()
     sig = torch.clamp(field - theta, min=0.0) / (nmax - theta)
     sig = sigma_max * sig * sig

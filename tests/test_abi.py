@@ -117,7 +117,8 @@ def test_raymarch_validation(sf, case, status):
 @pytest.mark.parametrize("case, status", [
     ("ok_zero", 0), ("null_tex", 1), ("null_base", 1), ("bad_format", 3), ("levels_zero", 2),
     ("levels_too_many", 2), ("bad_wrap", 2), ("bad_mip", 2), ("ggx_missing", 1), ("bad_shade", 2),
-    ("ggx_backfacing", 2), ("misaligned_level", 2), ("width_zero", 2),
+    ("ggx_backfacing", 2), ("misaligned_level", 2), ("width_zero", 2), ("keys_ok_zero", 0),
+    ("keys_reuse", 3), ("filter_4", 2),
 ])
 def test_filter2d_validation(sf, case, status):
     L = sf.lib()
@@ -155,6 +156,13 @@ def test_filter2d_validation(sf, case, status):
         tex.level_offset[1] = 8
     elif case == "width_zero":
         tex.width = 0
+    elif case == "keys_ok_zero":
+        smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 4)
+        n = 0
+    elif case == "keys_reuse":
+        smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 4, rng_variant=1)
+    elif case == "filter_4":
+        smp = sf.sampling(4, sf.SF_STOCHASTIC, 4)
     st = L.sf_filter2d(texp, FAKE, n, C.byref(smp), shade, C.byref(g) if g is not None else None, FAKE, None, None)
     assert st == status, sf.sf_last_error()
 
@@ -166,8 +174,11 @@ def test_filter3d_validation(sf):
     assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(smp), 2, 1.0, FAKE, None, None) == 2
     assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(smp), 1, float("nan"), FAKE, None, None) == 2
     assert L.sf_filter3d(C.byref(vol), None, 3, C.byref(smp), 0, 1.0, FAKE, None, None) == 1
-    big = _vol(sf, nx=4096, ny=4096, nz=64)
+    big = _vol(sf, nx=4096, ny=4096, nz=256)     # 8 GiB: beyond one 32-bit-offset buffer
     assert L.sf_filter3d(C.byref(big), FAKE, 3, C.byref(smp), 0, 1.0, FAKE, None, None) == 3
+    keys = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 1)      # the Keys cubic is 2-D only
+    assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(keys), 0, 1.0, FAKE, None, None) == 3
+    assert L.sf_raymarch(C.byref(vol), FAKE, 3, 8, C.byref(keys), FAKE, None, None) == 3
 
 
 def test_error_stats_validation(sf):
@@ -198,3 +209,77 @@ def test_occupancy_words_and_validation(sf):
     vol.brick_log2 = 7
     assert L.sf_build_occupancy(C.byref(vol), FAKE, 100, None) == 2
     assert L.sf_build_occupancy(None, FAKE, 100, None) == 1
+
+
+def _latgrid(sf, **kw):
+    g = sf.sf_latent_grid(0x10000, 0x20000, 2, (C.c_int32 * 3)(32, 32, 1), 8, sf.SF_LATENT_BF16, 0,
+                          (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(1, 1, 1))
+    for k, x in kw.items():
+        setattr(g, k, x)
+    return g
+
+
+def test_neural_shapes_and_sizes(sf):
+    assert sf.sf_mlp_nparams(8, 64, 4) == 4996          # config-4 network
+    assert sf.sf_mlp_nparams(16, 64, 1) == 5313         # config-5 network
+    assert sf.sf_neural_train_workspace(8, 4, 1000) == 63 * (4996 + 1) * 4
+    assert sf.sf_neural_train_workspace(8, 3, 1000) == 0
+    assert C.sizeof(sf.sf_latent_grid) == 8 + 8 + 4 + 12 + 4 * 3 + 24 + 4   # padded to pointer alignment
+    assert C.sizeof(sf.sf_mlp) == 8 + 16
+    assert C.sizeof(sf.sf_train_state) == 6 * 8 + 8 + 16
+
+
+@pytest.mark.parametrize("case, status", [
+    ("ok_zero", 0), ("null_grid", 1), ("bad_dims", 2), ("bad_channels", 3), ("bad_format", 3),
+    ("mlp_shape", 3), ("null_mlp", 1), ("variant", 3), ("grid3d", 3), ("misaligned", 2),
+])
+def test_neural_decode_validation(sf, case, status):
+    L = sf.lib()
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1)
+    g = _latgrid(sf)
+    m = sf.sf_mlp(0x30000, 8, 64, 4, 0)
+    n, gp, mp = 10, C.byref(g), C.byref(m)
+    if case == "ok_zero":
+        n = 0
+    elif case == "null_grid":
+        gp = None
+    elif case == "bad_dims":
+        g.dims = 4
+    elif case == "bad_channels":
+        g.channels = 12
+    elif case == "bad_format":
+        g.format = sf.SF_LATENT_F32
+    elif case == "mlp_shape":
+        m.out_dim = 3
+    elif case == "null_mlp":
+        mp = None
+    elif case == "variant":
+        smp.rng_variant = 1
+    elif case == "grid3d":
+        g.dims, g.channels = 3, 16
+        g.res[2] = 8
+    elif case == "misaligned":
+        g.latents = 0x10008
+    st = L.sf_neural_decode(gp, mp, FAKE, n, C.byref(smp), 0, None, FAKE, None, None)
+    assert st == status, sf.sf_last_error()
+
+
+def test_neural_raymarch_and_train_validation(sf):
+    L = sf.lib()
+    g = _latgrid(sf, dims=3, channels=16)
+    g.res[2] = 8
+    m = sf.sf_mlp(0x30000, 16, 64, 1, 0)
+    det = sf.sampling(sf.SF_BSPLINE3, sf.SF_AFTER_EXACT, 1)
+    assert L.sf_neural_raymarch(C.byref(g), C.byref(m), FAKE, 5, 16, C.byref(det), FAKE, None, None) == 3
+    g2 = _latgrid(sf)
+    sto = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1)
+    m2 = sf.sf_mlp(0x30000, 8, 64, 4, 0)
+    assert L.sf_neural_raymarch(C.byref(g2), C.byref(m2), FAKE, 5, 16, C.byref(sto), FAKE, None, None) == 3
+    st = sf.sf_train_state(0x1000, 0x2000, 0x3000, 0x4000, 0x5000, 0x6000, 100, 8, 64, 4, 0)
+    ws = sf.sf_neural_train_workspace(8, 4, 50)
+    args = (FAKE, FAKE, 50, 1, 1e-2, 1e-3, FAKE, None, None, FAKE)
+    assert L.sf_neural_train_step(C.byref(st), *args, ws - 4, None) == 5
+    assert L.sf_neural_train_step(C.byref(st), FAKE, FAKE, 500, 1, 1e-2, 1e-3, FAKE, None, None, FAKE, 10 ** 9, None) == 2
+    assert L.sf_neural_train_step(C.byref(st), FAKE, FAKE, 50, 0, 1e-2, 1e-3, FAKE, None, None, FAKE, ws, None) == 2
+    st.hidden = 32
+    assert L.sf_neural_train_step(C.byref(st), *args, ws, None) == 3

@@ -527,3 +527,50 @@ def test_occupancy_mask_property(orc):
                         v = orc.filter3d(g, p.astype(np.float32), filt, orc.BEFORE)
                         assert np.all(v == 0.0)
     assert n_clear > 0
+
+
+# ------------------------------------------------- Keys cubic, positivisation
+def test_keys_cubic_interpolates_and_reproduces_quadratics(orc):
+    """S.2's K3 with a = -1/2 interpolates (K3(0) = 1, K3(+-1) = K3(+-2) = 0)
+    and, for that a, reproduces polynomials up to degree two (Keys 1981)."""
+    assert orc.k3(0.0) == 1.0
+    for x in (1.0, -1.0, 2.0, -2.0, 2.5):
+        assert orc.k3(x) == 0.0
+    for t in np.linspace(0, 0.999, 31):
+        w = orc.axis_weights64(orc.KEYS3, t)
+        k = np.arange(4) - 1.0
+        assert abs(w.sum() - 1.0) < 1e-14
+        assert abs(np.dot(w, k) - t) < 1e-14
+        assert abs(np.dot(w, k * k) - t * t) < 1e-14
+        if 0 < t < 1:
+            assert w[0] < 0 and w[3] < 0 and w[1] > 0 and w[2] > 0
+
+
+def test_keys_positivised_expectation_equals_after(orc):
+    """The exact expectation of W+ f(t+) - W- f(t-) over the 24-bit uniforms
+    (every binary32 decision counted by brute force) equals the exact
+    filter-after value (signed Keys weights)."""
+    T = orc.Tex2D.rgba32f(inputs.texture_uniform(8, seed=4))
+    q = inputs.queries_uniform(4, seed=5)
+    e = orc.keys_expect2d(T, q, shade=1)
+    a = orc.filter2d(T, q, orc.KEYS3, orc.AFTER, shade=1)
+    assert np.max(np.abs(e - a)) < 2e-6
+
+
+def test_keys_stochastic_mean_and_texel_centres(orc):
+    """The stochastic estimator converges to the filter-after value; at texel
+    centres (t = 0) the negative set is empty and every sample returns the
+    centre texel itself (zero variance)."""
+    tex = inputs.texture_uniform(8, seed=4)
+    T = orc.Tex2D.rgba32f(tex)
+    q = inputs.queries_uniform(8, seed=6)
+    spp = 20000
+    s = orc.filter2d(T, q, orc.KEYS3, orc.STOCHASTIC, spp=spp, seed=3, shade=1)
+    a = orc.filter2d(T, q, orc.KEYS3, orc.AFTER, shade=1)
+    one = orc.filter2d(T, q, orc.KEYS3, orc.STOCHASTIC, spp=64, seed=3, shade=1)
+    assert np.max(np.abs(s - a)) < 5 * 3.0 / math.sqrt(spp)
+    qc = np.array([[(3 + 0.5) / 8, (5 + 0.5) / 8, 0.0]], np.float32)
+    v, taps = orc.filter2d(T, qc, orc.KEYS3, orc.STOCHASTIC, spp=16, seed=1, shade=0, taps=True)
+    assert np.allclose(v[0], tex[5, 3], rtol=1e-14)
+    assert np.all(taps[0, :, 1] == 3) and np.all(taps[0, :, 2] == 5) and np.all(taps[0, :, 3] == orc.TAP_NONE)
+    del one

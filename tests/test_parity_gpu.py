@@ -316,6 +316,88 @@ def test_filter2d_config2_full_sampled(sf, orc, c2_full, filt, mode, spp):
     _close(out[sub], ref)
 
 
+# ------------------------------------------------------------------ 2-D Keys cubic (positivised)
+def _close_signed(gpu, ref, scale):
+    """Positivised estimates subtract a negative-lobe term from a positive
+    one, so the binary32 rounding error scales with the terms' magnitude
+    (at most about 1.6 times the largest shaded value: the Keys block sums
+    are below 1.28 and 0.28), not with the possibly near-zero difference."""
+    _close(gpu, ref, atol=RTOL * 1.6 * scale)
+
+
+@pytest.mark.parametrize("mode, spp", [("STOCH", 16), ("STOCH", 5), ("STOCH", 1), ("BEFORE", 1), ("AFTER", 1)])
+@pytest.mark.parametrize("shade", [0, 1])
+@pytest.mark.parametrize("wrap", [0, 1])
+def test_filter2d_keys_config1(sf, orc, c1, mode, spp, shade, wrap):
+    _print_case("filter2d_keys_c1", mode, spp, shade, wrap)
+    tex, q = c1
+    ot = orc.Tex2D.rgba32f(tex, wrap=wrap)
+    gt = sf.Texture2D([tex], wrap=wrap)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(sf.SF_KEYS3, m, spp, seed=77)
+    taps_d = torch.full((q.shape[0], spp, 5), 99, dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=shade, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d(ot, q, orc.KEYS3, m, spp=spp, seed=77, shade=shade, taps=m == orc.STOCHASTIC)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close_signed(out.cpu().numpy(), ref, np.nanmax(np.abs(ref)))
+
+
+@pytest.mark.parametrize("mip", [0, 2])
+@pytest.mark.parametrize("mode, spp", [("STOCH", 8), ("AFTER", 1)])
+def test_filter2d_keys_mips_rgba8(sf, orc, c2_small, mip, mode, spp):
+    _print_case("filter2d_keys_mips", mip, mode, spp)
+    lv, q = c2_small
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, mip)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=mip)
+    m = {"STOCH": orc.STOCHASTIC, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(sf.SF_KEYS3, m, spp, seed=6)
+    taps_d = torch.empty((q.shape[0], spp, 5), dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d(ot, q, orc.KEYS3, m, spp=spp, seed=6, shade=1, taps=m == orc.STOCHASTIC)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close_signed(out.cpu().numpy(), ref, np.nanmax(np.abs(ref)))
+
+
+def test_filter2d_keys_texel_centres_exact(sf, orc):
+    """At texel centres the Keys cubic interpolates: t = 0 on both axes
+    leaves no negative weight, so every sample reads the centre texel and
+    the estimate is that texel exactly."""
+    R = 32
+    tex = inputs.texture_uniform(R, seed=8)
+    iy, ix = np.meshgrid(np.arange(R), np.arange(R), indexing="ij")
+    q = np.stack([(ix.ravel() + 0.5) / R, (iy.ravel() + 0.5) / R, np.zeros(R * R)], 1).astype(np.float32)
+    gt = sf.Texture2D([tex])
+    taps_d = torch.empty((R * R, 4, 5), dtype=torch.int32, device="cuda")
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 4, seed=1),
+                         dbg_taps=taps_d).cpu().numpy()
+    t = taps_d.cpu().numpy()
+    assert np.all(t[..., 3:] == orc.TAP_NONE)
+    assert np.array_equal(t[..., 1], np.repeat(ix.ravel()[:, None], 4, 1))
+    assert np.array_equal(out, tex.reshape(-1, 4))
+
+
+def test_filter2d_keys_config2_full_sampled(sf, orc, c2_full):
+    _print_case("filter2d_keys_c2_full")
+    lv, q = c2_full
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, 4096, 4096, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 16, seed=32)
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx()).cpu().numpy()
+    sub = np.sort(np.random.default_rng(2).choice(q.shape[0], 3000, replace=False))
+    ref = orc.filter2d(ot, q, orc.KEYS3, orc.STOCHASTIC, spp=16, seed=32, shade=1, subset=sub)
+    _close_signed(out[sub], ref, np.nanmax(np.abs(ref)))
+
+
 # ------------------------------------------------------------------ 3-D points
 @pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("mode, spp, variant", [("STOCH", 4, 0), ("STOCH", 3, 1), ("BEFORE", 1, 0), ("AFTER", 1, 0)])
