@@ -21,7 +21,8 @@ _SRCS = [_SRC, os.path.join(_HERE, "neural.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # enums of the oracle (its own copy; it does not include the library header)
-NEAREST, LINEAR, BSPLINE3, KEYS3 = 0, 1, 2, 3
+NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS = 0, 1, 2, 3, 4, 5, 6
+SIGMA_MIN, SIGMA_MAX = 1.0 / 16.0, 4.0     # Gaussian standard deviation, texels
 BEFORE, AFTER, STOCHASTIC = 0, 1, 2
 RGBA32F, RGBA8, R16F, R32F = 0, 1, 2, 3
 REPEAT, CLAMP = 0, 1
@@ -67,8 +68,23 @@ def lib():
         L.orc_pcg4d_batch.argtypes = [P, P, i64]
         L.orc_shade_ggx.argtypes = [P, P, P]
         L.orc_filter2d.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, i32, i32, u32,
-                                   i32, i32, P, P, P, P, i64]
-        L.orc_filter2d_expect.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, i32, P, P]
+                                   i32, f32, i32, P, P, P, P, i64]
+        L.orc_filter2d_expect.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, f32, i32, P, P]
+        L.orc_lnc.argtypes = [f32]
+        L.orc_lnc.restype = f32
+        L.orc_expc.argtypes = [f32]
+        L.orc_expc.restype = f32
+        L.orc_elementary_batch.argtypes = [i32, P, P, P, i64]
+        L.orc_fis_gauss_offset.argtypes = [f32, f32, f32, P, P]
+        L.orc_fis_nearest.argtypes = [f32, f32]
+        L.orc_fis_nearest.restype = i32
+        L.orc_fis_bspline_pick.argtypes = [f32, u32, u32, u32]
+        L.orc_fis_bspline_pick.restype = i32
+        L.orc_fis_bspline_pmf.argtypes = [f32, P]
+        L.orc_gauss_thresholds.argtypes = [f32, f32, P]
+        L.orc_gauss_h.argtypes = [f32]
+        L.orc_gauss_h.restype = f32
+        L.orc_gauss_pick_pmf.argtypes = [f32, f32, P]
         L.orc_reuse_histogram2.argtypes = [i32, f32, f32, P]
         L.orc_filter3d.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, u32, i32,
                                    i32, f32, P, P, P, i64]
@@ -209,11 +225,18 @@ class Tex2D:
         return cls(tex, tex.shape[1], tex.shape[0], 1, RGBA32F, [0], wrap, MIP_NONE)
 
 
+def _check_sigma(filt, sigma):
+    if filt in (GAUSS_FRS, GAUSS_FIS) and not (SIGMA_MIN <= sigma <= SIGMA_MAX):
+        raise ValueError(f"sigma {sigma} outside [{SIGMA_MIN}, {SIGMA_MAX}]")
+
+
 def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed: int = 0,
-             variant: int = 0, shade: int = 0, ggx=None, taps: bool = False, subset=None):
+             variant: int = 0, shade: int = 0, ggx=None, taps: bool = False, subset=None, sigma: float = 0.5):
     """Filter every query, or only the rows listed in ``subset`` (their own
     index keys the random stream).  Taps: {level, x, y} per sample, or
-    {level, x+, y+, x-, y-} for the positivised Keys cubic."""
+    {level, x+, y+, x-, y-} for the positivised Keys cubic.  ``sigma``: the
+    Gaussian filters' standard deviation in texels of the level read."""
+    _check_sigma(filt, sigma)
     q = _c(q, np.float32).reshape(-1, 3)
     n = q.shape[0]
     sub = None if subset is None else _c(subset, np.int64)
@@ -223,20 +246,82 @@ def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed
     tp = np.zeros((m, spp, 5 if filt == KEYS3 else 3), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_filter2d(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
-                       _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, shade, _p(g), _p(out), _p(tp),
+                       _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, sigma, shade, _p(g), _p(out), _p(tp),
                        _p(sub), 0 if sub is None else sub.size)
     return (out, tp) if taps else out
 
 
-def filter2d_expect(tex: Tex2D, q: np.ndarray, filt: int, shade: int = 0, ggx=None):
+def filter2d_expect(tex: Tex2D, q: np.ndarray, filt: int, shade: int = 0, ggx=None, sigma: float = 0.5):
+    """Exact expectation of the stochastic estimator (not for KEYS3 or GAUSS_FIS)."""
+    _check_sigma(filt, sigma)
     q = _c(q, np.float32).reshape(-1, 3)
     n = q.shape[0]
     ch = 3 if shade == 1 else 4
     out = np.zeros((n, ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
-    lib().orc_filter2d_expect(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip,
-                              _p(tex.off), _p(q), n, filt, shade, _p(g), _p(out))
+    st = lib().orc_filter2d_expect(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip,
+                                   _p(tex.off), _p(q), n, filt, sigma, shade, _p(g), _p(out))
+    if st != 0:
+        raise ValueError("no exact expectation for this filter")
     return out
+
+
+# ------------------------------------------------------------------ Gaussian / FIS contract
+def lnc(x):
+    x = _c(x, np.float32).ravel()
+    y = np.empty_like(x)
+    lib().orc_elementary_batch(0, _p(x), _p(y), None, x.size)
+    return y
+
+
+def expc(x):
+    x = _c(x, np.float32).ravel()
+    y = np.empty_like(x)
+    lib().orc_elementary_batch(1, _p(x), _p(y), None, x.size)
+    return y
+
+
+def sincos2pi(v):
+    v = _c(v, np.float32).ravel()
+    c, s = np.empty_like(v), np.empty_like(v)
+    lib().orc_elementary_batch(2, _p(v), _p(c), _p(s), v.size)
+    return c, s
+
+
+def fis_gauss_offset(u1: float, u2: float, sigma: float):
+    dx, dy = C.c_float(), C.c_float()
+    lib().orc_fis_gauss_offset(u1, u2, sigma, C.byref(dx), C.byref(dy))
+    return dx.value, dy.value
+
+
+def fis_nearest(t: float, d: float) -> int:
+    return lib().orc_fis_nearest(t, d)
+
+
+def fis_bspline_pick(t: float, a: int, b: int, c: int) -> int:
+    return lib().orc_fis_bspline_pick(t, a, b, c)
+
+
+def fis_bspline_pmf(t: float) -> np.ndarray:
+    P = np.zeros(4)
+    lib().orc_fis_bspline_pmf(t, _p(P))
+    return P
+
+
+def gauss_h(sigma: float) -> float:
+    return lib().orc_gauss_h(sigma)
+
+
+def gauss_thresholds(t: float, sigma: float) -> np.ndarray:
+    Cv = np.zeros(3, dtype=np.float32)
+    lib().orc_gauss_thresholds(t, gauss_h(sigma), _p(Cv))
+    return Cv
+
+
+def gauss_pick_pmf(t: float, sigma: float) -> np.ndarray:
+    P = np.zeros(4)
+    lib().orc_gauss_pick_pmf(t, gauss_h(sigma), _p(P))
+    return P
 
 
 # ------------------------------------------------------------------ 3-D path

@@ -29,6 +29,9 @@
  *   tent and cubic B-spline kernels ............ Suppl. S.2, eq. cubic-bspline
  *   stochastic lerp / bilerp ................... Suppl. S.1
  *   stochastic MIP level selection ............. Sec. 4.2.1
+ *   positivisation of negative lobes ........... Sec. 2.2 "Positivization"
+ *   filter importance sampling (FIS) ........... Sec. 4.2; Sec. 5 "Magnification, Filter
+ *                                                Importance Sampling"; Suppl. S.4.2
  *   transmittance in a density grid ............ Sec. 5 (offline rendering)
  *
  * Readings where the paper is silent (the GPU side follows the same ones):
@@ -52,7 +55,8 @@
 
 #define ORC_EXPORT __attribute__((visibility("default")))
 
-enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2, F_KEYS3 = 3 };
+enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2, F_KEYS3 = 3, F_GAUSS_FRS = 4, F_GAUSS_FIS = 5,
+       F_BSPLINE3_FIS = 6 };
 enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2 };
 enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3 };
 enum { WRAP_REPEAT = 0, WRAP_CLAMP = 1 };
@@ -338,6 +342,229 @@ ORC_EXPORT void orc_pick_pmf(int filter, float t, double P[4])
 }
 
 /* ------------------------------------------------------------------------ */
+/* Binary32 elementary functions of the decision contract.  The Gaussian     */
+/* samplers decide texels through exp, log, sin and cos; for the GPU to       */
+/* reach the same decisions bit for bit, both sides evaluate these with one  */
+/* written-out sequence of correctly rounded binary32 operations (+ - * /,   */
+/* sqrt, fma, floor, frexp, ldexp).  Accuracy is pinned against libm.        */
+/* ------------------------------------------------------------------------ */
+static const float LN2_HI = 0x1.62e4p-1f;      /* ln 2 to 17 bits: n * LN2_HI is exact for |n| < 128 */
+static const float LN2_LO = 1.42860677e-6f;    /* ln 2 - LN2_HI */
+
+/* ln x for x in (0, 1]: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m =
+ * 2 atanh(s), s = (m - 1)/(m + 1), by the series 2 s (1 + s^2/3 + s^4/5 +
+ * s^6/7 + s^8/9) (|s| <= 0.1716); ln x = e ln 2 + ln m with ln 2 in two
+ * parts (the reduction of Cody and Waite). */
+ORC_EXPORT float orc_lnc(float x)
+{
+    int e;
+    float m = frexpf(x, &e);
+    if (m < 0.70710678f) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    float s = (m - 1.0f) / (m + 1.0f);
+    float z = s * s;
+    float p = fmaf(z, fmaf(z, fmaf(z, fmaf(z, 1.0f / 9.0f, 1.0f / 7.0f), 1.0f / 5.0f), 1.0f / 3.0f), 1.0f);
+    float r = (2.0f * s) * p;
+    float fe = (float)e;
+    return fmaf(fe, LN2_HI, fmaf(fe, LN2_LO, r));
+}
+
+/* e^x for x in [-80, 0] (0 below): n = floor(x log2 e + 1/2), r = x - n ln 2
+ * (two parts), e^r by its Taylor polynomial to r^7 (|r| <= 0.35), times 2^n. */
+ORC_EXPORT float orc_expc(float x)
+{
+    if (!(x >= -80.0f))
+        return 0.0f;
+    float n = floorf(fmaf(x, 1.44269504f, 0.5f));
+    float r = fmaf(-n, LN2_HI, x);
+    r = fmaf(-n, LN2_LO, r);
+    float p = fmaf(r, 1.0f / 5040.0f, 1.0f / 720.0f);
+    p = fmaf(r, p, 1.0f / 120.0f);
+    p = fmaf(r, p, 1.0f / 24.0f);
+    p = fmaf(r, p, 1.0f / 6.0f);
+    p = fmaf(r, p, 0.5f);
+    p = fmaf(r, p, 1.0f);
+    p = fmaf(r, p, 1.0f);
+    return ldexpf(p, (int)n);
+}
+
+/* cos and sin of 2 pi v, v in [0, 1): the quadrant from 4v (exact), the rest
+ * folded into an angle x in [0, pi/4], Taylor series to x^9 (sin) and x^10
+ * (cos), then rotated into the quadrant. */
+ORC_EXPORT void orc_sincos2pi(float v, float *c, float *s)
+{
+    float a = 4.0f * v;
+    float qf = floorf(a);
+    float f = a - qf;
+    int q = (int)qf & 3;
+    int fold = f > 0.5f;
+    float h = fold ? 1.0f - f : f;
+    float x = h * 1.57079637f;
+    float z = x * x;
+    float sp = fmaf(z, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    sp = fmaf(z, sp, 1.0f / 120.0f);
+    sp = fmaf(z, sp, -1.0f / 6.0f);
+    sp = fmaf(z, sp, 1.0f);
+    float sn = x * sp;
+    float cp = fmaf(z, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    cp = fmaf(z, cp, -1.0f / 720.0f);
+    cp = fmaf(z, cp, 1.0f / 24.0f);
+    cp = fmaf(z, cp, -0.5f);
+    float cs = fmaf(z, cp, 1.0f);
+    float c0 = fold ? sn : cs, s0 = fold ? cs : sn;
+    switch (q) {
+    case 0: *c = c0; *s = s0; break;
+    case 1: *c = -s0; *s = c0; break;
+    case 2: *c = -c0; *s = -s0; break;
+    default: *c = s0; *s = -c0; break;
+    }
+}
+
+ORC_EXPORT void orc_elementary_batch(int which, const float *x, float *y, float *y2, int64_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (which == 0)
+            y[i] = orc_lnc(x[i]);
+        else if (which == 1)
+            y[i] = orc_expc(x[i]);
+        else
+            orc_sincos2pi(x[i], &y[i], &y2[i]);
+    }
+}
+
+/* Gaussian filter importance sampling (Sec. 4.2, FIS): an offset drawn from
+ * the isotropic normal of standard deviation sigma (texels) by the
+ * Box-Muller transform (Box and Muller 1958) of two uniforms, radius
+ * sigma sqrt(-2 ln(1 - u1)) (1 - u1 lies in (0, 1]), angle 2 pi u2.  The
+ * nearest texel of the offset point is then read: with raster position
+ * p = i0 + t the tap offset is floor((t + 1/2) + d).  Its probability is the
+ * Gaussian's mass over the texel's cell, so FIS with nearest lookup realises
+ * the Gaussian convolved with the unit box. */
+ORC_EXPORT void orc_fis_gauss_offset(float u1, float u2, float sigma, float *dx, float *dy)
+{
+    float r = sigma * sqrtf(-2.0f * orc_lnc(1.0f - u1));
+    float c, s;
+    orc_sincos2pi(u2, &c, &s);
+    *dx = r * c;
+    *dy = r * s;
+}
+
+ORC_EXPORT int orc_fis_nearest(float t, float d) { return (int)floorf((t + 0.5f) + d); }
+
+/* Cubic B-spline by FIS (Sec. 4.2): the cubic B-spline is the quadratic one
+ * convolved with the unit box (Cox-de Boor), and the sum of three uniforms
+ * has the quadratic B-spline density on [0, 3]; so the nearest texel of
+ * p + (xi1 + xi2 + xi3 - 3/2) is distributed by the cubic B-spline weights.
+ * Decision: S = a + b + c of the three 24-bit words (exact integer),
+ * S = 2^24 q + r; tap offset q - 1 + [r 2^-24 >= 1 - t], which is
+ * floor(t + S 2^-24 - 1) whenever 1 - t is a multiple of 2^-24. */
+ORC_EXPORT int orc_fis_bspline_pick(float t, uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t S = (a >> 8) + (b >> 8) + (c >> 8);
+    int q = (int)(S >> 24);
+    float r = (float)(S & 0xffffffu) * 0x1p-24f;
+    return q - 1 + (r >= 1.0f - t ? 1 : 0);
+}
+
+/* Exact probabilities of the four offsets of orc_fis_bspline_pick over all
+ * 2^72 word triples: the number of triples of 24-bit integers with sum
+ * below X is sum_j (-1)^j C(3,j) C(X - j 2^24 + 2, 3) (stars and bars with
+ * inclusion-exclusion). */
+static unsigned __int128 below3(int64_t X)
+{
+    const int64_t M = 1 << 24;
+    __int128 acc = 0;
+    const int sgn[4] = {1, -3, 3, -1};
+    for (int j = 0; j < 4; ++j) {
+        __int128 n = (__int128)X - (__int128)j * M + 2;
+        if (n >= 3)
+            acc += (__int128)sgn[j] * (n * (n - 1) * (n - 2) / 6);
+    }
+    return (unsigned __int128)acc;
+}
+
+ORC_EXPORT void orc_fis_bspline_pmf(float t, double P[4])
+{
+    const int64_t M = 1 << 24;
+    /* smallest r with r 2^-24 >= 1 - t */
+    int64_t R = (int64_t)ceil((double)(1.0f - t) * 16777216.0);
+    if (R < 0)
+        R = 0;
+    if (R > M)
+        R = M;
+    const long double total = (long double)M * (long double)M * (long double)M;
+    for (int k = 0; k < 4; ++k)
+        P[k] = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        int64_t a = q * M, b = q * M + R, c = (q + 1) * M;
+        P[q] += (double)((long double)(below3(b) - below3(a)) / total);      /* offset q - 1 */
+        P[q + 1] += (double)((long double)(below3(c) - below3(b)) / total);  /* offset q */
+    }
+}
+
+/* Discrete Gaussian on the nearest 4x4 texels (FRS, Sec. 4.1; the comparison
+ * of Sec. 5 "Magnification, Filter Importance Sampling"; Suppl. S.4.2),
+ * sampled per axis by its running sum: with
+ * h = 1/(2 sigma^2), a_k = (d_k d_k) h for d_k = (k - 1) - t, k = 0..3, the
+ * weights g_k = e^(a_min - a_k) (the common factor e^(-a_min) cancels in
+ * the normalisation and keeps the largest weight at 1), W = g0+g1+g2+g3,
+ * C0 = g0/W, C1 = (g0+g1)/W, C2 = (g0+g1+g2)/W.  The 2-D weight is the
+ * product of the axis weights, so the separable pick has the 2-D weights'
+ * distribution over the 16 texels. */
+ORC_EXPORT void orc_gauss_thresholds(float t, float h, float C[3])
+{
+    float a[4], g[4];
+    for (int k = 0; k < 4; ++k) {
+        float d = (float)(k - 1) - t;
+        a[k] = (d * d) * h;
+    }
+    float amin = fminf(fminf(a[0], a[1]), fminf(a[2], a[3]));
+    for (int k = 0; k < 4; ++k)
+        g[k] = orc_expc(amin - a[k]);
+    float s1 = g[0] + g[1];
+    float s2 = s1 + g[2];
+    float W = s2 + g[3];
+    C[0] = g[0] / W;
+    C[1] = s1 / W;
+    C[2] = s2 / W;
+}
+
+ORC_EXPORT float orc_gauss_h(float sigma) { return 0.5f / (sigma * sigma); }
+
+/* Exact pick probabilities for the discrete Gaussian over the 24-bit lattice. */
+ORC_EXPORT void orc_gauss_pick_pmf(float t, float h, double P[4])
+{
+    float C[3];
+    orc_gauss_thresholds(t, h, C);
+    double prev = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        double c = (j == 3) ? 16777216.0 : ceil((double)C[j] * 16777216.0);
+        if (c > 16777216.0)
+            c = 16777216.0;
+        if (c < prev)
+            c = prev;
+        P[j] = (c - prev) / 16777216.0;
+        prev = c;
+    }
+}
+
+/* Binary64 weights of the Gaussian filters.  Discrete: e^(-d_k^2 h) over the
+ * 4 taps, normalised.  FIS with nearest lookup: the mass of N(0, sigma^2)
+ * over each texel's cell, Phi((k + 1/2 - t)/sigma) - Phi((k - 1/2 - t)/sigma),
+ * for offsets k in [-R, R+1], R = ceil(7 sigma) + 1 (the mass left outside
+ * is below 2 Phi(-7) = 2.6e-12 per axis). */
+static int gauss_fis_radius(double sigma) { return (int)ceil(7.0 * sigma) + 1; }
+
+static double gauss_cell(double sigma, double t, int k)
+{
+    double r2 = sqrt(2.0) * sigma;
+    return 0.5 * (erfc(((double)k - 0.5 - t) / r2) - erfc(((double)k + 0.5 - t) / r2));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Scalar formats                                                            */
 /* ------------------------------------------------------------------------ */
 
@@ -489,9 +716,13 @@ static int query_finite(const tex2d *t, const float *q)
     return 1;
 }
 
+/* Widest axis window: the FIS Gaussian at sigma = 4 texels (2 R + 2 = 60 taps). */
+#define AXIS_TAPS_MAX 64
+static int axis_weights_s(int filter, float sigma, double t, int *first_off, double *w);
+
 /* One query of the 2-D filter.  out has 4 (shade none) or 3 (GGX) channels. */
 static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter, int mode, int spp,
-                         uint32_t seed, int variant, int shade, const double *ggx, double *out,
+                         uint32_t seed, int variant, float sigma, int shade, const double *ggx, double *out,
                          int32_t *taps)
 {
     int ch = shade == 1 ? 3 : 4;
@@ -554,13 +785,38 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
                 }
                 continue;
             }
-            int offx = filter == F_BSPLINE3 ? -1 : 0;
-            int jx = orc_pick(filter, tx, ux);
-            if (variant == 1)
-                uy = orc_reuse(filter, tx, ux, jx);
-            int jy = orc_pick(filter, ty, uy);
-            int x = wrap_tap(t->wrap, ix + offx + jx, wl);
-            int y = wrap_tap(t->wrap, iy + offx + jy, hl);
+            int ox, oy;
+            if (filter == F_GAUSS_FRS) {
+                /* discrete Gaussian: running-sum pick per axis on the 4 taps */
+                float h = orc_gauss_h(sigma), Cx[3], Cy[3];
+                orc_gauss_thresholds(tx, h, Cx);
+                orc_gauss_thresholds(ty, h, Cy);
+                ox = -1 + (ux >= Cx[0]) + (ux >= Cx[1]) + (ux >= Cx[2]);
+                oy = -1 + (uy >= Cy[0]) + (uy >= Cy[1]) + (uy >= Cy[2]);
+            } else if (filter == F_GAUSS_FIS) {
+                /* Box-Muller offset, then the nearest texel */
+                float dx, dy;
+                orc_fis_gauss_offset(ux, uy, sigma, &dx, &dy);
+                ox = orc_fis_nearest(tx, dx);
+                oy = orc_fis_nearest(ty, dy);
+            } else if (filter == F_BSPLINE3_FIS) {
+                /* three uniforms per axis: words 0, 1, 2 of the key with
+                 * step 0 for x, of the key with step 1 for y */
+                uint32_t key2[4] = {(uint32_t)qi, (uint32_t)s, 1u, seed}, w2[4];
+                orc_pcg4d(key2, w2);
+                ox = orc_fis_bspline_pick(tx, w[0], w[1], w[2]);
+                oy = orc_fis_bspline_pick(ty, w2[0], w2[1], w2[2]);
+            } else {
+                int first = filter == F_BSPLINE3 ? -1 : 0;
+                int jx = orc_pick(filter, tx, ux);
+                if (variant == 1)
+                    uy = orc_reuse(filter, tx, ux, jx);
+                int jy = orc_pick(filter, ty, uy);
+                ox = first + jx;
+                oy = first + jy;
+            }
+            int x = wrap_tap(t->wrap, ix + ox, wl);
+            int y = wrap_tap(t->wrap, iy + oy, hl);
             if (taps) {
                 taps[3 * s] = l;
                 taps[3 * s + 1] = x;
@@ -590,10 +846,10 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
         float tx, ty;
         raster(uu, wl, &ix, &tx);
         raster(vv, hl, &iy, &ty);
-        double wx[4], wy[4];
+        double wx[AXIS_TAPS_MAX], wy[AXIS_TAPS_MAX];
         int ox, oy;
-        int nx = axis_weights(filter, (double)tx, &ox, wx);
-        int ny = axis_weights(filter, (double)ty, &oy, wy);
+        int nx = axis_weights_s(filter, sigma, (double)tx, &ox, wx);
+        int ny = axis_weights_s(filter, sigma, (double)ty, &oy, wy);
         for (int b = 0; b < ny; ++b)
             for (int a = 0; a < nx; ++a) {
                 double wgt = pl[li] * wx[a] * wy[b];
@@ -616,12 +872,41 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
             out[c] = sum[c];
 }
 
+/* Axis weights of every 2-D filter, including the Gaussians (binary64):
+ * the discrete Gaussian's normalised e^(-d^2 h) on taps -1..2, the FIS
+ * Gaussian's cell masses on -R..R+1, and the B-spline FIS = the cubic
+ * B-spline (the filter it realises). */
+static int axis_weights_s(int filter, float sigma, double t, int *first_off, double *w)
+{
+    if (filter == F_GAUSS_FRS) {
+        double h = 0.5 / ((double)sigma * (double)sigma), W = 0.0;
+        *first_off = -1;
+        for (int k = 0; k < 4; ++k) {
+            double d = (double)(k - 1) - t;
+            w[k] = exp(-d * d * h);
+            W += w[k];
+        }
+        for (int k = 0; k < 4; ++k)
+            w[k] /= W;
+        return 4;
+    }
+    if (filter == F_GAUSS_FIS) {
+        int R = gauss_fis_radius(sigma);
+        *first_off = -R;
+        for (int k = -R; k <= R + 1; ++k)
+            w[k + R] = gauss_cell(sigma, t, k);
+        return 2 * R + 2;
+    }
+    return axis_weights(filter == F_BSPLINE3_FIS ? F_BSPLINE3 : filter, t, first_off, w);
+}
+
+
 /* queries: n x {u, v, lambda}.  If subset is non-null only the nsub listed
  * queries are computed (out and taps indexed by position in the subset, the
  * random key by the query's own index). */
 ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
                             const int64_t *level_off, const float *q, int64_t n, int filter, int mode,
-                            int spp, uint32_t seed, int variant, int shade, const double *ggx,
+                            int spp, uint32_t seed, int variant, float sigma, int shade, const double *ggx,
                             double *out, int32_t *taps, const int64_t *subset, int64_t nsub)
 {
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off};
@@ -631,7 +916,7 @@ ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt,
     for (int64_t i = 0; i < m; ++i) {
         int64_t qi = subset ? subset[i] : i;
         int tw = filter == F_KEYS3 ? 5 : 3;
-        filter2d_one(&t, q + 3 * qi, qi, filter, mode, spp, seed, variant, shade, ggx, out + ch * i,
+        filter2d_one(&t, q + 3 * qi, qi, filter, mode, spp, seed, variant, sigma, shade, ggx, out + ch * i,
                      taps ? taps + (int64_t)tw * spp * i : NULL);
     }
     return 0;
@@ -639,11 +924,15 @@ ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt,
 
 /* Exact expectation of the stochastic estimator with independent 24-bit
  * uniforms per axis and level: sum over every (level, tap x, tap y) of the
- * exact pick probabilities times the shaded texel. */
+ * exact pick probabilities times the shaded texel.  Filters: nearest,
+ * linear, cubic B-spline, discrete Gaussian and B-spline FIS (returns -1
+ * for the others). */
 ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
                                    const int64_t *level_off, const float *q, int64_t n, int filter,
-                                   int shade, const double *ggx, double *out)
+                                   float sigma, int shade, const double *ggx, double *out)
 {
+    if (filter == F_KEYS3 || filter == F_GAUSS_FIS)
+        return -1;
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off};
     int ch = shade == 1 ? 3 : 4;
     for (int64_t i = 0; i < n; ++i) {
@@ -670,10 +959,19 @@ ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, i
             raster(uu, wl, &ix, &tx);
             raster(vv, hl, &iy, &ty);
             double Px[4], Py[4];
-            orc_pick_pmf(filter, tx, Px);
-            orc_pick_pmf(filter, ty, Py);
-            int off = filter == F_BSPLINE3 ? -1 : 0;
-            int ntap = filter == F_BSPLINE3 ? 4 : (filter == F_LINEAR ? 2 : 1);
+            if (filter == F_GAUSS_FRS) {
+                orc_gauss_pick_pmf(tx, orc_gauss_h(sigma), Px);
+                orc_gauss_pick_pmf(ty, orc_gauss_h(sigma), Py);
+            } else if (filter == F_BSPLINE3_FIS) {
+                orc_fis_bspline_pmf(tx, Px);
+                orc_fis_bspline_pmf(ty, Py);
+            } else {
+                orc_pick_pmf(filter, tx, Px);
+                orc_pick_pmf(filter, ty, Py);
+            }
+            int cubic = filter == F_BSPLINE3 || filter == F_GAUSS_FRS || filter == F_BSPLINE3_FIS;
+            int off = cubic ? -1 : 0;
+            int ntap = cubic ? 4 : (filter == F_LINEAR ? 2 : 1);
             int nearx = filter == F_NEAREST ? (tx >= 0.5f) : 0;
             int neary = filter == F_NEAREST ? (ty >= 0.5f) : 0;
             for (int b = 0; b < ntap; ++b)
