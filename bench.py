@@ -260,6 +260,22 @@ def texture_bench(args, res):
         t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
         c1[name] = {"ms": t, "queries_per_s": 4096 / (t * 1e-3),
                     "rmse_vs_oracle_keys_after": _rmse(o.cpu().numpy(), judge1k)}
+    # Gaussian by FRS (4x4 window) and by FIS (Box-Muller + nearest), and the
+    # cubic B-spline by FIS (sum of three uniforms): RMSE against each
+    # filter's own exact filter-after value, 16 samples per query
+    for sigma in (0.3, 0.5, 0.8):
+        for fname, filt, ofilt in (("gauss_frs", sf.SF_GAUSS_FRS, oracle.GAUSS_FRS),
+                                   ("gauss_fis", sf.SF_GAUSS_FIS, oracle.GAUSS_FIS)):
+            judge = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, ofilt, oracle.AFTER, shade=1, sigma=sigma)
+            smp = sf.sampling(filt, sf.SF_STOCHASTIC, 16, seed=5, sigma=sigma)
+            o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
+            t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
+            c1[f"{fname}_sigma{sigma}_stochastic_16spp"] = {"ms": t, "rmse_vs_oracle_own_after": _rmse(o.cpu().numpy(),
+                                                                                                    judge)}
+    smp = sf.sampling(sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 16, seed=5)
+    o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
+    t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
+    c1["bicubic_fis_stochastic_16spp"] = {"ms": t, "rmse_vs_oracle_bicubic_after": _rmse(o.cpu().numpy(), judge1)}
     res["config1"] = c1
     # ---- config 2
     log("config 2: pyramid and camera")
@@ -284,11 +300,15 @@ def texture_bench(args, res):
             ("trilinear_before_2x4tap", tex2, sf.SF_LINEAR, sf.SF_BEFORE, 1),
             ("bilinear_nearest_level_before_4tap", tex2n, sf.SF_LINEAR, sf.SF_BEFORE, 1),
             ("keys_positivised_stochastic_1spp", tex2, sf.SF_KEYS3, sf.SF_STOCHASTIC, 1),
-            ("keys_after_2x16tap", tex2, sf.SF_KEYS3, sf.SF_AFTER_EXACT, 1)):
-        smp = sf.sampling(filt, mode, spp, seed=5)
+            ("keys_after_2x16tap", tex2, sf.SF_KEYS3, sf.SF_AFTER_EXACT, 1),
+            ("bicubic_fis_stochastic_1spp", tex2, sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 1),
+            ("bicubic_fis_stochastic_16spp", tex2, sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 16),
+            ("gauss_frs_sigma0.5_stochastic_1spp", tex2, sf.SF_GAUSS_FRS, sf.SF_STOCHASTIC, 1),
+            ("gauss_fis_sigma0.5_stochastic_1spp", tex2, sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 1)):
+        smp = sf.sampling(filt, mode, spp, seed=5, sigma=0.5)
         o = torch.empty((n2, 3), dtype=torch.float32, device="cuda")
         t = time_launches(lambda: sf.sf_filter2d(tex, qd2, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
-        cubic = filt in (sf.SF_BSPLINE3, sf.SF_KEYS3)
+        cubic = filt in (sf.SF_BSPLINE3, sf.SF_KEYS3, sf.SF_GAUSS_FRS, sf.SF_BSPLINE3_FIS)
         taps = (spp * (2 if filt == sf.SF_KEYS3 else 1) if mode == sf.SF_STOCHASTIC
                 else (2 if tex is tex2 else 1) * (16 if cubic else 4))
         algo = n2 * (taps * 4 + 12 + 12)

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SF_ABI_VERSION 1
+#define SF_ABI_VERSION 2
 #define SF_RNG_VERSION 1
 #define SF_TAP_NONE INT32_MIN
 #define SF_MAX_LEVELS 16
@@ -71,7 +71,30 @@ enum {
  * the stochastic mode handles by positivisation (Sec. 2.2 "Positivization"):
  * one tap drawn from the positive and one from the negative product
  * weights, estimate W+ f(t+) - W- f(t-).  SF_KEYS3 is a 2-D texture filter. */
-enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3 };
+enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3, SF_GAUSS_FRS = 4, SF_GAUSS_FIS = 5,
+       SF_BSPLINE3_FIS = 6 };
+/* Gaussian filters and filter importance sampling (2-D textures only):
+ *   SF_GAUSS_FRS    discrete Gaussian of standard deviation sigma (texels) on
+ *                   the nearest 4x4 texels, sampled per axis by its running
+ *                   sum (FRS, Sec. 4.1; Suppl. S.4.2, discrete sampling);
+ *   SF_GAUSS_FIS    Gaussian filter importance sampling: a Box-Muller offset
+ *                   of standard deviation sigma, then the nearest texel
+ *                   (Sec. 4.2; Suppl. S.4.2); the filter it realises is the
+ *                   Gaussian convolved with the unit box (cell masses);
+ *   SF_BSPLINE3_FIS the cubic B-spline by FIS: offset xi1 + xi2 + xi3 - 3/2
+ *                   (quadratic B-spline density), then the nearest texel
+ *                   (Sec. 4.2, Cox-de Boor); deterministic modes = SF_BSPLINE3.
+ * Their binary32 decision contract (raster p = i0 + t as for every filter):
+ *   ln, exp, cos/sin(2 pi v) are evaluated by the written-out sequences
+ *   documented in the oracle (frexp reduction + atanh series; Cody-Waite
+ *   reduction + Taylor to r^7; quadrant fold + Taylor to x^9 / x^10);
+ *   GAUSS_FRS: h = 0.5/(sigma sigma); a_k = (d d) h, d = (k-1) - t;
+ *     g_k = exp(min a - a_k); C0 = g0/W, C1 = (g0+g1)/W, C2 = (g0+g1+g2)/W,
+ *     W = ((g0+g1)+g2)+g3; offset -1 + #{C_j <= u};
+ *   GAUSS_FIS: r = sigma sqrt(-2 ln(1 - u0)); (c, s) = cos/sin(2 pi u1);
+ *     offsets floor((t + 1/2) + r c), floor((t + 1/2) + r s);
+ *   BSPLINE3_FIS: S = (w0>>8)+(w1>>8)+(w2>>8) = 2^24 q + r (words 0..2 of
+ *     the key with step 0 for x, step 1 for y); offset q - 1 + [r 2^-24 >= 1 - t]. */
 /* SF_BEFORE: shade(sum_i w_i t_i)            (eq. filter-before-shading)
  * SF_AFTER_EXACT: sum_i w_i shade(t_i)        (eq. filtering-after-shading)
  * SF_STOCHASTIC: mean over spp of shade(t_j), P(j) = w_j (eq. stochastic-sum) */
@@ -87,7 +110,7 @@ enum { SF_SHADE_NONE = 0, SF_SHADE_GGX = 1 };             /* 2-D */
 enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1 }; /* 3-D points */
 
 typedef struct sf_sampling {
-    int32_t filter;      /* SF_NEAREST | SF_LINEAR | SF_BSPLINE3                     */
+    int32_t filter;      /* SF_NEAREST .. SF_BSPLINE3_FIS (see above)                */
     int32_t mode;        /* SF_BEFORE | SF_AFTER_EXACT | SF_STOCHASTIC                */
     int32_t spp;         /* samples per query, 1..SF_MAX_SPP (deterministic: ignored) */
     uint32_t seed;       /* fourth word of the hash key                              */
@@ -95,7 +118,11 @@ typedef struct sf_sampling {
                             axes, re-derived after each pick by uniform sample reuse
                             (Sec. 2.2 eq. uniform-sample-reuse): u' = (u-lo)/(hi-lo)
                             over the picked bin [lo, hi), clamped to 1 - 2^-24      */
+    float sigma;         /* Gaussian filters: standard deviation in texels of the
+                            level read, SF_SIGMA_MIN..SF_SIGMA_MAX; else ignored     */
 } sf_sampling;
+#define SF_SIGMA_MIN 0.0625f
+#define SF_SIGMA_MAX 4.0f
 
 /* A 2-D texture with an optional MIP pyramid.  Level l has
  * max(1, width >> l) x max(1, height >> l) texels, row-major, 4 channels,
@@ -166,7 +193,9 @@ typedef struct sf_volume {
  * Sec. 4.2.1.
  * Errors: SF_E_NULL (tex, base, queries, out, smp, or ggx when shading);
  *         SF_E_RANGE (n < 0 or n > 2^31-1, bad enum, spp outside 1..SF_MAX_SPP,
- *         size <= 0, levels outside 1..SF_MAX_LEVELS or beyond the pyramid);
+ *         size <= 0, levels outside 1..SF_MAX_LEVELS or beyond the pyramid,
+ *         sigma outside SF_SIGMA_MIN..SF_SIGMA_MAX for a Gaussian filter);
+ *         SF_E_UNSUPPORTED (rng_variant 1 with SF_KEYS3 or a Gaussian / FIS filter);
  *         SF_E_DEVICE (launch failure).
  */
 sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,

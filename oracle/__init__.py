@@ -85,6 +85,13 @@ def lib():
         L.orc_gauss_h.argtypes = [f32]
         L.orc_gauss_h.restype = f32
         L.orc_gauss_pick_pmf.argtypes = [f32, f32, P]
+        L.orc_log2c.argtypes = [f32]
+        L.orc_log2c.restype = f32
+        L.orc_aniso_lod.argtypes = [i32, i32, P, i32, P, P]
+        L.orc_aniso_lod.restype = f32
+        L.orc_filter2d_aniso.argtypes = [P, i32, i32, i32, i32, i32, P, P, i64, i32, i32, i32, u32, f32, i32, i32,
+                                         P, P, P, P, i64]
+        L.orc_aniso_reference.argtypes = [P, i32, i32, i32, i32, P, i64, i32, i32, f32, i32, P, P, P, i64]
         L.orc_reuse_histogram2.argtypes = [i32, f32, f32, P]
         L.orc_filter3d.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, u32, i32,
                                    i32, f32, P, P, P, i64]
@@ -263,6 +270,52 @@ def filter2d_expect(tex: Tex2D, q: np.ndarray, filt: int, shade: int = 0, ggx=No
                                    _p(tex.off), _p(q), n, filt, sigma, shade, _p(g), _p(out))
     if st != 0:
         raise ValueError("no exact expectation for this filter")
+    return out
+
+
+# ------------------------------------------------------------------ anisotropic minification
+def log2c(x: float) -> float:
+    return lib().orc_log2c(x)
+
+
+def aniso_lod(w: int, h: int, d, amax: int = 64):
+    """(lambda, major axis is the y derivative, probe count)."""
+    dd = _c(d, np.float32)
+    my, npb = C.c_int(), C.c_int()
+    lam = lib().orc_aniso_lod(w, h, _p(dd), amax, C.byref(my), C.byref(npb))
+    return lam, bool(my.value), npb.value
+
+
+def filter2d_aniso(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed: int = 0, shade: int = 0,
+                   ggx=None, taps: bool = False, subset=None, sigma: float = 0.5, amax: int = 64):
+    """Anisotropic minification (screen-space jitter + minor-axis level);
+    queries ``[n, 6]`` {u, v, du/dx, dv/dx, du/dy, dv/dy}."""
+    _check_sigma(filt, sigma)
+    q = _c(q, np.float32).reshape(-1, 6)
+    n = q.shape[0]
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
+    ch = 3 if shade == 1 else 4
+    out = np.zeros((m, ch))
+    tp = np.zeros((m, spp, 3), dtype=np.int32) if taps else None
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_filter2d_aniso(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, _p(tex.off), _p(q), n, filt,
+                             mode, spp, seed & 0xFFFFFFFF, sigma, amax, shade, _p(g), _p(out), _p(tp), _p(sub),
+                             0 if sub is None else sub.size)
+    return (out, tp) if taps else out
+
+
+def aniso_reference(tex: Tex2D, q: np.ndarray, K: int = 16, filt: int = BSPLINE3, shade: int = 0, ggx=None,
+                    subset=None, sigma: float = 0.5):
+    """Pixel integral of the level-0 filter-after value (K x K midpoints)."""
+    q = _c(q, np.float32).reshape(-1, 6)
+    sub = None if subset is None else _c(subset, np.int64)
+    m = q.shape[0] if sub is None else sub.size
+    ch = 3 if shade == 1 else 4
+    out = np.zeros((m, ch))
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_aniso_reference(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(q), q.shape[0], K, filt, sigma,
+                              shade, _p(g), _p(out), _p(sub), 0 if sub is None else sub.size)
     return out
 
 

@@ -30,6 +30,8 @@
  *   stochastic lerp / bilerp ................... Suppl. S.1
  *   stochastic MIP level selection ............. Sec. 4.2.1
  *   positivisation of negative lobes ........... Sec. 2.2 "Positivization"
+ *   screen-space anisotropic minification ...... Sec. 4.2.1; Suppl. S.4.3; Sec. 5 "Anisotropic
+ *                                                filtering and minification"
  *   filter importance sampling (FIS) ........... Sec. 4.2; Sec. 5 "Magnification, Filter
  *                                                Importance Sampling"; Suppl. S.4.2
  *   transmittance in a density grid ............ Sec. 5 (offline rendering)
@@ -987,6 +989,260 @@ ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, i
                         o[c2] += pr * v[c2];
                 }
         }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Anisotropic minification by screen-space jitter (Sec. 4.2.1; the level of  */
+/* detail of Suppl. S.4.3; Sec. 5 "Anisotropic filtering and minification").  */
+/* A query is a pixel: uv and its screen derivatives (du/dx, dv/dx, du/dy,    */
+/* dv/dy).  A sample jitters uv uniformly over the pixel's parallelogram      */
+/* (first-order image of the pixel square), reads ONE level chosen from the   */
+/* minor axis of the footprint with a uniform jitter of the level, and ONE    */
+/* texel of it with the reconstruction filter.                                */
+/* ------------------------------------------------------------------------ */
+
+/* log2 x for positive normal x (binary32 contract): the same frexp
+ * reduction and atanh series as orc_lnc, then e + ln(m) log2(e); -inf for
+ * x < 2^-126 or NaN, +inf for +inf. */
+ORC_EXPORT float orc_log2c(float x)
+{
+    if (!(x >= 0x1p-126f))
+        return -INFINITY;
+    if (x == INFINITY)
+        return INFINITY;
+    int e;
+    float m = frexpf(x, &e);
+    if (m < 0.70710678f) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    float s = (m - 1.0f) / (m + 1.0f);
+    float z = s * s;
+    float p = fmaf(z, fmaf(z, fmaf(z, fmaf(z, 1.0f / 9.0f, 1.0f / 7.0f), 1.0f / 5.0f), 1.0f / 3.0f), 1.0f);
+    float r = (2.0f * s) * p;
+    return fmaf(r, 1.44269504f, (float)e);
+}
+
+/* Footprint axes of a pixel in level-0 texels: x-axis (W du/dx, H dv/dx),
+ * y-axis (W du/dy, H dv/dy).  The shorter is the minor axis; if the
+ * anisotropy exceeds amax the minor axis is lengthened to major/amax (the
+ * listing's rescaling, in its operation order).  Returns lambda = log2 of
+ * the minor length; *major_y tells which derivative is the major axis;
+ * *nprobe = the probe count of the deterministic comparator,
+ * clamp(ceil(major/minor), 1, amax) (amax when the minor axis vanishes
+ * and the major does not). */
+ORC_EXPORT float orc_aniso_lod(int W, int H, const float d[4], int amax, int *major_y, int *nprobe)
+{
+    float ax = (float)W * d[0], ay = (float)H * d[1];
+    float bx = (float)W * d[2], by = (float)H * d[3];
+    float la2 = ax * ax + ay * ay, lb2 = bx * bx + by * by;
+    int swap = la2 > lb2;
+    float lmin = sqrtf(swap ? lb2 : la2), lmax = sqrtf(swap ? la2 : lb2);
+    *major_y = !swap;
+    float A = (float)amax;
+    if (lmin > 0.0f && lmin * A < lmax) {
+        float scale = lmax / (lmin * A);
+        lmin = lmin * scale;
+    }
+    int np;
+    if (lmin > 0.0f) {
+        float r = ceilf(lmax / lmin);
+        np = r < 1.0f ? 1 : (r > A ? amax : (int)r);
+    } else {
+        np = lmax > 0.0f ? amax : 1;
+    }
+    *nprobe = np;
+    return orc_log2c(lmin);
+}
+
+static int aniso_query_finite(const float *q)
+{
+    for (int k = 0; k < 6; ++k)
+        if (!isfinite(q[k]))
+            return 0;
+    return 1;
+}
+
+/* Deterministic filter of one point at the level pair of lambda
+ * (weights 1-f, f), as filter2d's deterministic sums; adds weight * value
+ * (texel for before, shaded texel for after) into sum. */
+static void det_point(const tex2d *t, float u, float v, float lam, int filter, float sigma, int mode, int shade,
+                      const double *ggx, double weight, double *sum)
+{
+    int ch = shade == 1 ? 3 : 4;
+    float uu = wrap_coord(t->wrap, u), vv = wrap_coord(t->wrap, v);
+    int l0, l1;
+    float f;
+    levels_of(t, lam, &l0, &l1, &f);
+    int lv[2] = {l0, l1};
+    double pl[2] = {1.0 - (double)f, (double)f};
+    for (int li = 0; li < 2; ++li) {
+        if (pl[li] == 0.0)
+            continue;
+        int l = lv[li];
+        int wl = lvl_dim(t->w, l), hl = lvl_dim(t->h, l);
+        int ix, iy;
+        float tx, ty;
+        raster(uu, wl, &ix, &tx);
+        raster(vv, hl, &iy, &ty);
+        double wx[AXIS_TAPS_MAX], wy[AXIS_TAPS_MAX];
+        int ox, oy;
+        int nx = axis_weights_s(filter, sigma, (double)tx, &ox, wx);
+        int ny = axis_weights_s(filter, sigma, (double)ty, &oy, wy);
+        for (int b = 0; b < ny; ++b)
+            for (int a = 0; a < nx; ++a) {
+                double wgt = weight * pl[li] * wx[a] * wy[b];
+                double texel[4], val[4];
+                fetch2d(t, l, wrap_tap(t->wrap, ix + ox + a, wl), wrap_tap(t->wrap, iy + oy + b, hl), texel);
+                if (mode == M_BEFORE) {
+                    for (int c = 0; c < 4; ++c)
+                        sum[c] += wgt * texel[c];
+                } else {
+                    shade2d(shade, ggx, texel, val);
+                    for (int c = 0; c < ch; ++c)
+                        sum[c] += wgt * val[c];
+                }
+            }
+    }
+}
+
+/* One pixel.  Stochastic: per sample, key (q, s, 0, seed) gives the jitter
+ * (words 0, 1: j = u - 1/2 along du/dx and du/dy) and the level uniform
+ * (word 2); key (q, s, 1, seed) gives the filter's uniforms (words 0, 1).
+ *   uv' = uv + jx d/dx + jy d/dy  (two fused operations per coordinate),
+ *   level = floor(clamp(lambda + (u_l - 1/2), 0, L-1) + 1/2),
+ *   then one texel of that level by the filter's pick at uv'.
+ * Deterministic (the comparators): N probes at offsets (k + 1/2)/N - 1/2
+ * of the major-axis derivative, each filtered on the levels floor(lambda),
+ * floor(lambda)+1 with weights (1-f, f); mean over probes; before shades
+ * the filtered texel, after sums shaded texels. */
+static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, int mode, int spp, uint32_t seed,
+                      float sigma, int amax, int shade, const double *ggx, double *out, int32_t *taps)
+{
+    int ch = shade == 1 ? 3 : 4;
+    if (!aniso_query_finite(q)) {
+        for (int c = 0; c < ch; ++c)
+            out[c] = NAN;
+        if (taps && mode == M_STOCH)
+            for (int s = 0; s < 3 * spp; ++s)
+                taps[s] = INT32_MIN;
+        return;
+    }
+    int major_y, np;
+    float lam = orc_aniso_lod(t->w, t->h, q + 2, amax, &major_y, &np);
+    const float lmax = (float)(t->levels - 1);
+    if (mode == M_STOCH) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int s = 0; s < spp; ++s) {
+            uint32_t k0[4] = {(uint32_t)qi, (uint32_t)s, 0u, seed}, w0[4];
+            uint32_t k1[4] = {(uint32_t)qi, (uint32_t)s, 1u, seed}, w1[4];
+            orc_pcg4d(k0, w0);
+            orc_pcg4d(k1, w1);
+            float jx = uniform24(w0[0]) - 0.5f, jy = uniform24(w0[1]) - 0.5f;
+            float u = fmaf(jy, q[4], fmaf(jx, q[2], q[0]));
+            float v = fmaf(jy, q[5], fmaf(jx, q[3], q[1]));
+            float lj = lam + (uniform24(w0[2]) - 0.5f);
+            lj = fminf(fmaxf(lj, 0.0f), lmax);
+            int l = (int)floorf(lj + 0.5f);
+            int wl = lvl_dim(t->w, l), hl = lvl_dim(t->h, l);
+            int ix, iy;
+            float tx, ty;
+            raster(wrap_coord(t->wrap, u), wl, &ix, &tx);
+            raster(wrap_coord(t->wrap, v), hl, &iy, &ty);
+            float ux = uniform24(w1[0]), uy = uniform24(w1[1]);
+            int ox, oy;
+            if (filter == F_GAUSS_FIS) {
+                float dx, dy;
+                orc_fis_gauss_offset(ux, uy, sigma, &dx, &dy);
+                ox = orc_fis_nearest(tx, dx);
+                oy = orc_fis_nearest(ty, dy);
+            } else {
+                int first = filter == F_BSPLINE3 ? -1 : 0;
+                ox = first + orc_pick(filter, tx, ux);
+                oy = first + orc_pick(filter, ty, uy);
+            }
+            int x = wrap_tap(t->wrap, ix + ox, wl), y = wrap_tap(t->wrap, iy + oy, hl);
+            if (taps) {
+                taps[3 * s] = l;
+                taps[3 * s + 1] = x;
+                taps[3 * s + 2] = y;
+            }
+            double texel[4], val[4];
+            fetch2d(t, l, x, y, texel);
+            shade2d(shade, ggx, texel, val);
+            for (int c = 0; c < ch; ++c)
+                acc[c] += val[c];
+        }
+        for (int c = 0; c < ch; ++c)
+            out[c] = acc[c] / (double)spp;
+        return;
+    }
+    double sum[4] = {0, 0, 0, 0};
+    float mu = major_y ? q[4] : q[2], mv = major_y ? q[5] : q[3];
+    for (int k = 0; k < np; ++k) {
+        float o = ((float)k + 0.5f) / (float)np - 0.5f;
+        float u = fmaf(o, mu, q[0]), v = fmaf(o, mv, q[1]);
+        det_point(t, u, v, lam, filter, sigma, mode, shade, ggx, 1.0 / (double)np, sum);
+    }
+    if (mode == M_BEFORE)
+        shade2d(shade, ggx, sum, out);
+    else
+        for (int c = 0; c < ch; ++c)
+            out[c] = sum[c];
+}
+
+/* queries: n x {u, v, du/dx, dv/dx, du/dy, dv/dy}; the texture's mip field
+ * is ignored (the level comes from the footprint). */
+ORC_EXPORT int orc_filter2d_aniso(const void *base, int w, int h, int levels, int fmt, int wrap,
+                                  const int64_t *level_off, const float *q, int64_t n, int filter, int mode, int spp,
+                                  uint32_t seed, float sigma, int amax, int shade, const double *ggx, double *out,
+                                  int32_t *taps, const int64_t *subset, int64_t nsub)
+{
+    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, MIP_LINEAR, level_off};
+    int ch = shade == 1 ? 3 : 4;
+    int64_t m = subset ? nsub : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t qi = subset ? subset[i] : i;
+        aniso_one(&t, q + 6 * qi, qi, filter, mode, spp, seed, sigma, amax, shade, ggx, out + ch * i,
+                  taps ? taps + (int64_t)3 * spp * i : NULL);
+    }
+    return 0;
+}
+
+/* Pixel-integral reference: the mean over K x K stratum centres of the pixel
+ * (offsets (i + 1/2)/K - 1/2 along d/dx and d/dy) of the exact
+ * filter-after value on level 0 alone (no prefiltered level), i.e. filtering
+ * after shading over the whole pixel footprint. */
+ORC_EXPORT int orc_aniso_reference(const void *base, int w, int h, int fmt, int wrap, const float *q, int64_t n,
+                                   int K, int filter, float sigma, int shade, const double *ggx, double *out,
+                                   const int64_t *subset, int64_t nsub)
+{
+    const int64_t off0 = 0;
+    tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0};
+    int ch = shade == 1 ? 3 : 4;
+    int64_t m = subset ? nsub : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        const float *qq = q + 6 * (subset ? subset[i] : i);
+        double *o = out + ch * i;
+        if (!aniso_query_finite(qq)) {
+            for (int c = 0; c < ch; ++c)
+                o[c] = NAN;
+            continue;
+        }
+        double sum[4] = {0, 0, 0, 0};
+        for (int a = 0; a < K; ++a)
+            for (int b = 0; b < K; ++b) {
+                double jx = ((double)a + 0.5) / K - 0.5, jy = ((double)b + 0.5) / K - 0.5;
+                float u = (float)((double)qq[0] + jx * qq[2] + jy * qq[4]);
+                float v = (float)((double)qq[1] + jx * qq[3] + jy * qq[5]);
+                det_point(&t, u, v, 0.0f, filter, sigma, M_AFTER, shade, ggx, 1.0 / ((double)K * K), sum);
+            }
+        for (int c = 0; c < ch; ++c)
+            o[c] = sum[c];
     }
     return 0;
 }

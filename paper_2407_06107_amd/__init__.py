@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_PKG, "libsf.so")
 
 # enums (values fixed by include/sf.h)
 SF_OK, SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED, SF_E_DEVICE, SF_E_WORKSPACE = range(6)
-SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3 = 0, 1, 2, 3
+SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3, SF_GAUSS_FRS, SF_GAUSS_FIS, SF_BSPLINE3_FIS = 0, 1, 2, 3, 4, 5, 6
+SF_SIGMA_MIN, SF_SIGMA_MAX = 0.0625, 4.0
 SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC = 0, 1, 2
 SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F = 0, 1, 2, 3
 SF_WRAP_REPEAT, SF_WRAP_CLAMP = 0, 1
@@ -38,7 +39,7 @@ SF_LATENT_F32, SF_LATENT_BF16, SF_LATENT_FP8E4M3 = 0, 1, 2
 
 class sf_sampling(C.Structure):
     _fields_ = [("filter", C.c_int32), ("mode", C.c_int32), ("spp", C.c_int32), ("seed", C.c_uint32),
-                ("rng_variant", C.c_int32)]
+                ("rng_variant", C.c_int32), ("sigma", C.c_float)]
 
 
 class sf_tex2d(C.Structure):
@@ -164,8 +165,10 @@ def _need(t: torch.Tensor, dtype, name: str):
         raise ValueError(f"{name} must be contiguous")
 
 
-def sampling(filter: int, mode: int, spp: int = 1, seed: int = 0, rng_variant: int = 0) -> sf_sampling:
-    return sf_sampling(filter, mode, spp, seed & 0xFFFFFFFF, rng_variant)
+def sampling(filter: int, mode: int, spp: int = 1, seed: int = 0, rng_variant: int = 0,
+             sigma: float = 0.5) -> sf_sampling:
+    """``sigma``: standard deviation (texels) of the Gaussian filters."""
+    return sf_sampling(filter, mode, spp, seed & 0xFFFFFFFF, rng_variant, sigma)
 
 
 def ggx(n=(0.0, 0.0, 1.0), wo=(0.2, 0.3, 1.0), wi=(-0.4, 0.1, 1.0), radiance=(1.0, 1.0, 1.0), f0=0.04,

@@ -33,7 +33,7 @@ sf_status check_sampling(const sf_sampling *smp)
 {
     if (!smp)
         return fail(SF_E_NULL, "sampling descriptor is NULL");
-    if (smp->filter < SF_NEAREST || smp->filter > SF_KEYS3)
+    if (smp->filter < SF_NEAREST || smp->filter > SF_BSPLINE3_FIS)
         return fail(SF_E_RANGE, "filter %d out of range", smp->filter);
     if (smp->mode < SF_BEFORE || smp->mode > SF_STOCHASTIC)
         return fail(SF_E_RANGE, "mode %d out of range", smp->mode);
@@ -170,8 +170,12 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
         return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
-    if (smp->filter == SF_KEYS3 && smp->rng_variant != 0)
-        return fail(SF_E_UNSUPPORTED, "the positivised Keys cubic draws independent uniforms (rng_variant 0)");
+    if (smp->filter >= SF_KEYS3 && smp->rng_variant != 0)
+        return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters draw independent uniforms (rng_variant 0)");
+    if ((smp->filter == SF_GAUSS_FRS || smp->filter == SF_GAUSS_FIS) &&
+        !(smp->sigma >= SF_SIGMA_MIN && smp->sigma <= SF_SIGMA_MAX))
+        return fail(SF_E_RANGE, "sigma %g outside %g..%g", (double)smp->sigma, (double)SF_SIGMA_MIN,
+                    (double)SF_SIGMA_MAX);
     if (!tex->base)
         return fail(SF_E_NULL, "texture base pointer is NULL");
     if (tex->format != SF_RGBA32F && tex->format != SF_RGBA8_UNORM)
@@ -218,6 +222,7 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
     c.spp = smp->spp;
     c.variant = smp->rng_variant;
     c.seed = smp->seed;
+    c.sigma = smp->sigma;
     c.shade = shade;
     c.out = out;
     c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
@@ -236,8 +241,8 @@ sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const s
         return fail(SF_E_NULL, "pos and out must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
-    if (smp->filter == SF_KEYS3)
-        return fail(SF_E_UNSUPPORTED, "the Keys cubic is a 2-D texture filter here");
+    if (smp->filter > SF_BSPLINE3)
+        return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters are 2-D texture filters here");
     sfk::Filter3DCall c{};
     if ((st = check_volume(vol, c.vol)) != SF_OK)
         return st;
@@ -275,8 +280,8 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
         return fail(SF_E_NULL, "rays and T must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
-    if (smp->filter == SF_KEYS3)
-        return fail(SF_E_UNSUPPORTED, "the Keys cubic is a 2-D texture filter here");
+    if (smp->filter > SF_BSPLINE3)
+        return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters are 2-D texture filters here");
     sfk::RaymarchCall c{};
     if ((st = check_volume(vol, c.vol)) != SF_OK)
         return st;
@@ -402,7 +407,7 @@ sf_status sf_neural_decode(const sf_latent_grid *grid, const sf_mlp *mlp, const 
         return fail(SF_E_NULL, "queries and out must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
-    if (smp->rng_variant != 0 || smp->filter == SF_KEYS3)
+    if (smp->rng_variant != 0 || smp->filter > SF_BSPLINE3)
         return fail(SF_E_UNSUPPORTED, "neural decoding: NEAREST, LINEAR or BSPLINE3 with independent uniforms");
     sfk::NeuralCall c{};
     if ((st = check_grid(grid, true, c.lat)) != SF_OK)
@@ -447,7 +452,7 @@ sf_status sf_neural_raymarch(const sf_latent_grid *grid, const sf_mlp *mlp, cons
         return fail(SF_E_NULL, "rays and T must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
-    if (smp->mode != SF_STOCHASTIC || smp->rng_variant != 0 || smp->filter == SF_KEYS3)
+    if (smp->mode != SF_STOCHASTIC || smp->rng_variant != 0 || smp->filter > SF_BSPLINE3)
         return fail(SF_E_UNSUPPORTED, "the neural ray march is stochastic (NEAREST, LINEAR or BSPLINE3) with "
                                       "independent uniforms");
     sfk::NeuralCall c{};

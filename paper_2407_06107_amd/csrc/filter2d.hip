@@ -28,6 +28,16 @@ __device__ __forceinline__ int wrap_tap(int wrap, int i, int n)
     return min(max(i, 0), n - 1);
 }
 
+// Any tap index (the FIS Gaussian reaches 25 texels past the point).
+__device__ __forceinline__ int wrap_any(int wrap, int i, int n)
+{
+    if (wrap == SF_WRAP_REPEAT) {
+        const int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return min(max(i, 0), n - 1);
+}
+
 __device__ __forceinline__ void raster(float u, int n, int &i0, float &t)
 {
     float p = __builtin_fmaf(u, (float)n, -0.5f);
@@ -129,6 +139,7 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
             float f;
             levels_of(c.tex, qq.z, l0, l1, f);
             const float cl = 1.0f - f;
+            const float h = 0.5f / (c.sigma * c.sigma);   // discrete Gaussian: 1/(2 sigma^2)
             for (int s = lane; s < c.spp; s += G) {
                 uint4 w = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
                 int l = u24(w.w) >= cl ? l1 : l0;
@@ -181,7 +192,17 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
                     continue;
                 }
                 int ox, oy;
-                if constexpr (VAR == 0) {
+                if constexpr (F == GAUSS_FRS) {
+                    ox = gauss_frs_pick(tx, h, u24(w.x));
+                    oy = gauss_frs_pick(ty, h, u24(w.y));
+                } else if constexpr (F == GAUSS_FIS) {
+                    gauss_fis_pick(tx, ty, c.sigma, u24(w.x), u24(w.y), ox, oy);
+                } else if constexpr (F == BSPLINE3_FIS) {
+                    // three uniforms per axis: words 0..2 of the key with step 0 (x), step 1 (y)
+                    const uint4 w2 = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 1u, c.seed));
+                    ox = bspline_fis_pick(tx, w.x, w.y, w.z);
+                    oy = bspline_fis_pick(ty, w2.x, w2.y, w2.z);
+                } else if constexpr (VAR == 0) {
                     ox = pick_off<F>(tx, u24(w.x));
                     oy = pick_off<F>(ty, u24(w.y));
                 } else {
@@ -189,8 +210,14 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
                     ox = pick_off_reuse<F>(tx, u);
                     oy = pick_off_reuse<F>(ty, u);
                 }
-                int x = wrap_tap(c.tex.wrap, ix + ox, wl);
-                int y = wrap_tap(c.tex.wrap, iy + oy, hl);
+                int x, y;
+                if constexpr (F == GAUSS_FIS) {
+                    x = wrap_any(c.tex.wrap, ix + ox, wl);
+                    y = wrap_any(c.tex.wrap, iy + oy, hl);
+                } else {
+                    x = wrap_tap(c.tex.wrap, ix + ox, wl);
+                    y = wrap_tap(c.tex.wrap, iy + oy, hl);
+                }
                 if (c.taps) {
                     int32_t *tp = c.taps + (q * c.spp + s) * 3;
                     tp[0] = l;
@@ -266,6 +293,86 @@ __global__ __launch_bounds__(256) void k_filter2d_det(Filter2DCall c)
     store<SHADE>(c.out, q, MODE == BEFORE ? shade<SHADE>(c.g, sum) : sum);
 }
 
+// Deterministic Gaussian comparators, binary64 weights and sums (the FIS
+// window has up to 60 x 60 taps): the discrete Gaussian's normalised
+// e^(-d^2 h) on the 4x4 window, or the FIS Gaussian's cell masses
+// Phi((k + 1/2 - t)/sigma) - Phi((k - 1/2 - t)/sigma) on offsets -R..R+1,
+// R = ceil(7 sigma) + 1.
+__device__ __forceinline__ void gauss4(double t, double h, double w[4])
+{
+    double W = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double d = (double)(k - 1) - t;
+        w[k] = exp(-d * d * h);
+        W += w[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        w[k] /= W;
+}
+
+__device__ __forceinline__ double gauss_cell(double r2, double t, int k)
+{
+    return 0.5 * (erfc(((double)k - 0.5 - t) / r2) - erfc(((double)k + 0.5 - t) / r2));
+}
+
+template <int F, int SHADE, int MODE>
+__global__ __launch_bounds__(256) void k_filter2d_gauss_det(Filter2DCall c)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= c.n)
+        return;
+    float3 qq = make_float3(c.q[3 * q], c.q[3 * q + 1], c.q[3 * q + 2]);
+    if (!query_ok(c.tex, qq)) {
+        float nan = __builtin_nanf("");
+        store<SHADE>(c.out, q, make_float4(nan, nan, nan, nan));
+        return;
+    }
+    const float uu = wrap_coord(c.tex.wrap, qq.x), vv = wrap_coord(c.tex.wrap, qq.y);
+    int l0, l1;
+    float f;
+    levels_of(c.tex, qq.z, l0, l1, f);
+    const double sig = (double)c.sigma;
+    const double h = 0.5 / (sig * sig), r2 = 1.4142135623730951 * sig;
+    const int R = (int)ceil(7.0 * sig) + 1;
+    const int first = F == GAUSS_FRS ? -1 : -R;
+    const int ntap = F == GAUSS_FRS ? 4 : 2 * R + 2;
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int li = 0; li < 2; ++li) {
+        const double pl = li == 0 ? 1.0 - (double)f : (double)f;
+        if (pl == 0.0)
+            continue;
+        const int l = li == 0 ? l0 : l1;
+        const int wl = max(1, c.tex.w >> l), hl = max(1, c.tex.h >> l);
+        int ix, iy;
+        float tx, ty;
+        raster(uu, wl, ix, tx);
+        raster(vv, hl, iy, ty);
+        double gx[4], gy[4];
+        if constexpr (F == GAUSS_FRS) {
+            gauss4((double)tx, h, gx);
+            gauss4((double)ty, h, gy);
+        }
+        for (int b = 0; b < ntap; ++b) {
+            const double wy = F == GAUSS_FRS ? gy[b & 3] : gauss_cell(r2, (double)ty, first + b);
+            const int y = wrap_any(c.tex.wrap, iy + first + b, hl);
+            for (int a = 0; a < ntap; ++a) {
+                const double wx = F == GAUSS_FRS ? gx[a & 3] : gauss_cell(r2, (double)tx, first + a);
+                const double wgt = pl * wx * wy;
+                const float4 t = texel(c.tex, l, wrap_any(c.tex.wrap, ix + first + a, wl), y);
+                const float4 v = MODE == BEFORE ? t : shade<SHADE>(c.g, t);
+                sum[0] += wgt * (double)v.x;
+                sum[1] += wgt * (double)v.y;
+                sum[2] += wgt * (double)v.z;
+                sum[3] += wgt * (double)v.w;
+            }
+        }
+    }
+    const float4 r = make_float4((float)sum[0], (float)sum[1], (float)sum[2], (float)sum[3]);
+    store<SHADE>(c.out, q, MODE == BEFORE ? shade<SHADE>(c.g, r) : r);
+}
+
 template <int F, int SHADE>
 static void launch_f2(const Filter2DCall &c, hipStream_t s)
 {
@@ -276,16 +383,28 @@ static void launch_f2(const Filter2DCall &c, hipStream_t s)
         int log_g = __builtin_ctz(G);
         int64_t threads = c.n * G;
         dim3 grid((uint32_t)((threads + 255) / 256)), block(256);
-        if (c.variant && F != KEYS3)
-            k_filter2d_stoch<F, SHADE, 1><<<grid, block, 0, s>>>(c, log_g);
-        else
-            k_filter2d_stoch<F, SHADE, 0><<<grid, block, 0, s>>>(c, log_g);
+        if constexpr (F <= BSPLINE3) {
+            if (c.variant) {
+                k_filter2d_stoch<F, SHADE, 1><<<grid, block, 0, s>>>(c, log_g);
+                return;
+            }
+        }
+        k_filter2d_stoch<F, SHADE, 0><<<grid, block, 0, s>>>(c, log_g);
     } else {
         dim3 grid((uint32_t)((c.n + 255) / 256)), block(256);
-        if (c.mode == BEFORE)
-            k_filter2d_det<F, SHADE, BEFORE><<<grid, block, 0, s>>>(c);
-        else
-            k_filter2d_det<F, SHADE, AFTER><<<grid, block, 0, s>>>(c);
+        if constexpr (F == GAUSS_FRS || F == GAUSS_FIS) {
+            if (c.mode == BEFORE)
+                k_filter2d_gauss_det<F, SHADE, BEFORE><<<grid, block, 0, s>>>(c);
+            else
+                k_filter2d_gauss_det<F, SHADE, AFTER><<<grid, block, 0, s>>>(c);
+        } else {
+            // the B-spline FIS realises the cubic B-spline itself
+            constexpr int FD = F == BSPLINE3_FIS ? BSPLINE3 : F;
+            if (c.mode == BEFORE)
+                k_filter2d_det<FD, SHADE, BEFORE><<<grid, block, 0, s>>>(c);
+            else
+                k_filter2d_det<FD, SHADE, AFTER><<<grid, block, 0, s>>>(c);
+        }
     }
 }
 
@@ -309,6 +428,15 @@ hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s)
         break;
     case KEYS3:
         launch_f1<KEYS3>(c, s);
+        break;
+    case GAUSS_FRS:
+        launch_f1<GAUSS_FRS>(c, s);
+        break;
+    case GAUSS_FIS:
+        launch_f1<GAUSS_FIS>(c, s);
+        break;
+    case BSPLINE3_FIS:
+        launch_f1<BSPLINE3_FIS>(c, s);
         break;
     default:
         launch_f1<BSPLINE3>(c, s);

@@ -14,7 +14,7 @@
 
 namespace sfk {
 
-enum { NEAREST = 0, LINEAR = 1, BSPLINE3 = 2, KEYS3 = 3 };
+enum { NEAREST = 0, LINEAR = 1, BSPLINE3 = 2, KEYS3 = 3, GAUSS_FRS = 4, GAUSS_FIS = 5, BSPLINE3_FIS = 6 };
 enum { BEFORE = 0, AFTER = 1, STOCH = 2 };
 
 // ---------------------------------------------------------------- random stream
@@ -139,6 +139,124 @@ __device__ __forceinline__ int pick_off_reuse(float t, float &u)
     }
 }
 
+// ---------------------------------------------------------------- Gaussian / FIS contract
+// The Gaussian samplers decide texels through ln, exp, cos and sin.  These
+// are fixed sequences of correctly rounded binary32 operations (+ - * /,
+// sqrt, fma, floor, frexp, ldexp), so the decisions are reproducible bit for
+// bit on any IEEE machine; their accuracy (a few ulp) is checked against
+// libm on the CPU.
+constexpr float LN2_HI = 0x1.62e4p-1f;    // ln 2 to 17 bits: n * LN2_HI exact for |n| < 128
+constexpr float LN2_LO = 1.42860677e-6f;  // ln 2 - LN2_HI
+
+// ln x, x in (0, 1]: x = m 2^e, m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
+// s = (m-1)/(m+1), series 2s(1 + z/3 + z^2/5 + z^3/7 + z^4/9), z = s^2;
+// e ln 2 added in two parts (Cody & Waite).
+__device__ __forceinline__ float lnc(float x)
+{
+    int e;
+    float m = __builtin_frexpf(x, &e);
+    if (m < 0.70710678f) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float z = s * s;
+    float p = __builtin_fmaf(z, 1.0f / 9.0f, 1.0f / 7.0f);
+    p = __builtin_fmaf(z, p, 1.0f / 5.0f);
+    p = __builtin_fmaf(z, p, 1.0f / 3.0f);
+    p = __builtin_fmaf(z, p, 1.0f);
+    const float r = (2.0f * s) * p;
+    const float fe = (float)e;
+    return __builtin_fmaf(fe, LN2_HI, __builtin_fmaf(fe, LN2_LO, r));
+}
+
+// e^x, x in [-80, 0] (0 below): n = floor(x log2 e + 1/2), r = x - n ln 2
+// (two parts), Taylor polynomial of e^r to r^7, scaled by 2^n.
+__device__ __forceinline__ float expc(float x)
+{
+    if (!(x >= -80.0f))
+        return 0.0f;
+    const float n = __builtin_floorf(__builtin_fmaf(x, 1.44269504f, 0.5f));
+    float r = __builtin_fmaf(-n, LN2_HI, x);
+    r = __builtin_fmaf(-n, LN2_LO, r);
+    float p = __builtin_fmaf(r, 1.0f / 5040.0f, 1.0f / 720.0f);
+    p = __builtin_fmaf(r, p, 1.0f / 120.0f);
+    p = __builtin_fmaf(r, p, 1.0f / 24.0f);
+    p = __builtin_fmaf(r, p, 1.0f / 6.0f);
+    p = __builtin_fmaf(r, p, 0.5f);
+    p = __builtin_fmaf(r, p, 1.0f);
+    p = __builtin_fmaf(r, p, 1.0f);
+    return __builtin_ldexpf(p, (int)n);
+}
+
+// cos and sin of 2 pi v, v in [0, 1): quadrant from 4v (exact), the rest
+// folded to x in [0, pi/4]; Taylor to x^9 (sin) and x^10 (cos).
+__device__ __forceinline__ void sincos2pi(float v, float &c, float &s)
+{
+    const float a = 4.0f * v;
+    const float qf = __builtin_floorf(a);
+    const float f = a - qf;
+    const int q = (int)qf & 3;
+    const bool fold = f > 0.5f;
+    const float h = fold ? 1.0f - f : f;
+    const float x = h * 1.57079637f;
+    const float z = x * x;
+    float sp = __builtin_fmaf(z, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    sp = __builtin_fmaf(z, sp, 1.0f / 120.0f);
+    sp = __builtin_fmaf(z, sp, -1.0f / 6.0f);
+    sp = __builtin_fmaf(z, sp, 1.0f);
+    const float sn = x * sp;
+    float cp = __builtin_fmaf(z, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    cp = __builtin_fmaf(z, cp, -1.0f / 720.0f);
+    cp = __builtin_fmaf(z, cp, 1.0f / 24.0f);
+    cp = __builtin_fmaf(z, cp, -0.5f);
+    const float cs = __builtin_fmaf(z, cp, 1.0f);
+    const float c0 = fold ? sn : cs, s0 = fold ? cs : sn;
+    c = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+    s = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
+}
+
+// Discrete Gaussian on taps i0-1..i0+2 (FRS, Sec. 4.1): weights
+// exp(min a - a_k), a_k = (d d) h, d = (k-1) - t, h = 1/(2 sigma^2); running
+// sums divided by their total.  Returns the tap offset (-1..2) for u.
+__device__ __forceinline__ int gauss_frs_pick(float t, float h, float u)
+{
+    float a[4], g[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float d = (float)(k - 1) - t;
+        a[k] = (d * d) * h;
+    }
+    const float amin = __builtin_fminf(__builtin_fminf(a[0], a[1]), __builtin_fminf(a[2], a[3]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        g[k] = expc(amin - a[k]);
+    const float s1 = g[0] + g[1], s2 = s1 + g[2], W = s2 + g[3];
+    return -1 + (u >= g[0] / W) + (u >= s1 / W) + (u >= s2 / W);
+}
+
+// Gaussian FIS: Box-Muller radius sigma sqrt(-2 ln(1 - u0)), angle 2 pi u1,
+// then the nearest texel: offset floor((t + 1/2) + d) per axis.
+__device__ __forceinline__ void gauss_fis_pick(float tx, float ty, float sigma, float u0, float u1, int &ox,
+                                               int &oy)
+{
+    const float r = sigma * __builtin_sqrtf(-2.0f * lnc(1.0f - u0));
+    float c, s;
+    sincos2pi(u1, c, s);
+    ox = (int)__builtin_floorf((tx + 0.5f) + r * c);
+    oy = (int)__builtin_floorf((ty + 0.5f) + r * s);
+}
+
+// Cubic B-spline by FIS: the nearest texel after the offset
+// xi1 + xi2 + xi3 - 3/2; with S = a + b + c (24-bit words) = 2^24 q + r the
+// offset is q - 1 + [r 2^-24 >= 1 - t].
+__device__ __forceinline__ int bspline_fis_pick(float t, uint32_t a, uint32_t b, uint32_t c)
+{
+    const uint32_t S = (a >> 8) + (b >> 8) + (c >> 8);
+    const float r = (float)(S & 0xffffffu) * 0x1p-24f;
+    return (int)(S >> 24) - 1 + (r >= 1.0f - t);
+}
+
 // Interpolating Keys cubic (S.2's K3, a = -1/2) on taps i0-1..i0+2, split
 // into its positive pair (p1, p2) and negative pair (-m0, -m3), factored:
 // m0 = t s^2/2, m3 = s t^2/2, p1 = 1 - 5t^2/2 + 3t^3/2, p2 likewise in s = 1-t.
@@ -206,8 +324,8 @@ __device__ __forceinline__ void axis_weights64(float tf, double w[4])
 
 template <int F>
 struct Taps {
-    static constexpr int n = (F == BSPLINE3 || F == KEYS3) ? 4 : (F == LINEAR ? 2 : 1);
-    static constexpr int first = (F == BSPLINE3 || F == KEYS3) ? -1 : 0;
+    static constexpr int n = (F == BSPLINE3 || F == KEYS3 || F == GAUSS_FRS) ? 4 : (F == LINEAR ? 2 : 1);
+    static constexpr int first = (F == BSPLINE3 || F == KEYS3 || F == GAUSS_FRS) ? -1 : 0;
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip; map the

@@ -40,6 +40,7 @@ struct Filter2DCall {
     int64_t n;
     int32_t filter, mode, spp, variant, shade;
     uint32_t seed;
+    float sigma;
     GgxConst g;
     float *out;
     int32_t *taps;

@@ -200,6 +200,53 @@ def plane_queries(width: int = 1920, height: int = 1080, tex_size: int = 4096, l
     return q
 
 
+def plane_queries_aniso(width: int = 1920, height: int = 1080, height_above: float = 1.0,
+                        pitch_deg: float = 35.0, vfov_deg: float = 40.0, tile: int = 8) -> np.ndarray:
+    """Pixel queries of the :func:`plane_queries` camera for anisotropic
+    filtering: ``[width*height, 6]`` float32 ``{u, v, du/dx, dv/dx, du/dy,
+    dv/dy}``, uv at the pixel centre and its screen derivatives from the hit
+    points of the neighbouring pixel rays (float64 differences), in
+    :func:`tile_order`."""
+    pitch = math.radians(pitch_deg)
+    fwd = np.array([0.0, math.cos(pitch), -math.sin(pitch)])
+    right = np.array([1.0, 0.0, 0.0])
+    up = np.cross(right, fwd)
+    th = math.tan(math.radians(vfov_deg) / 2)
+    tw = th * width / height
+    cam = np.array([0.3, 0.1, height_above])
+
+    def hit(px, py):
+        sx = (2.0 * (px + 0.5) / width - 1.0) * tw
+        sy = (1.0 - 2.0 * (py + 0.5) / height) * th
+        d = fwd[None] + sx[:, None] * right[None] + sy[:, None] * up[None]
+        t = -cam[2] / d[:, 2]
+        return cam[None, :2] + t[:, None] * d[:, :2]
+
+    order = tile_order(width, height, tile)
+    px = (order % width).astype(np.float64)
+    py = (order // width).astype(np.float64)
+    p = hit(px, py)
+    q = np.empty((order.size, 6), dtype=np.float32)
+    q[:, 0:2] = p
+    q[:, 2:4] = hit(px + 1.0, py) - p
+    q[:, 4:6] = hit(px, py + 1.0) - p
+    return q
+
+
+def texture_checker(size: int = 4096, squares: int = 64) -> np.ndarray:
+    """High-contrast checkerboard ``[size, size, 4]`` float32 (the
+    minification test pattern): dark squares albedo 0.04 with roughness
+    parameter 0.1, light squares albedo 0.9 with roughness parameter 0.9,
+    so the GGX shading is non-linear across the pattern."""
+    cell = size // squares
+    i = np.arange(size) // cell
+    light = ((i[:, None] + i[None, :]) & 1).astype(bool)
+    tex = np.empty((size, size, 4), dtype=np.float32)
+    tex[..., :3] = np.where(light[..., None], 0.9, 0.04)
+    tex[..., 3] = np.where(light, 0.9, 0.1)
+    return tex
+
+
 # ----------------------------------------------------------------------------
 # 3-D density grids
 # ----------------------------------------------------------------------------

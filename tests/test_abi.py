@@ -40,16 +40,34 @@ def test_header_symbols_exported(sf):
 
 
 def test_versions(sf):
-    assert sf.sf_abi_version() == 1
+    assert sf.sf_abi_version() == 2
     assert sf.sf_rng_version() == 1
 
 
-def test_struct_layouts_match_header(sf):
-    """ctypes mirrors of the descriptors have the C sizes the header implies."""
-    assert C.sizeof(sf.sf_sampling) == 20
-    assert C.sizeof(sf.sf_tex2d) == 8 + 6 * 4 + 16 * 8
-    assert C.sizeof(sf.sf_ggx) == 15 * 4
-    assert C.sizeof(sf.sf_volume) == 8 + 4 * 4 + 6 * 4 + 8 + 4 + 4
+STRUCTS = ["sf_sampling", "sf_tex2d", "sf_ggx", "sf_volume", "sf_latent_grid", "sf_mlp", "sf_train_state"]
+
+
+def test_struct_layouts_match_header(sf, tmp_path):
+    """Every ctypes mirror has the size and field offsets that a C compiler
+    gives the header's struct."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sf.h"', "int main(void) {"]
+    for st in STRUCTS:
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for name, _ in getattr(sf, st)._fields_:
+            lines.append(f'printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for st in STRUCTS:
+        cls = getattr(sf, st)
+        assert got[(st, "size")] == C.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert got[(st, name)] == getattr(cls, name).offset, (st, name)
+    assert C.sizeof(sf.sf_sampling) == 24
 
 
 def _vol(sf, **kw):
@@ -118,7 +136,8 @@ def test_raymarch_validation(sf, case, status):
     ("ok_zero", 0), ("null_tex", 1), ("null_base", 1), ("bad_format", 3), ("levels_zero", 2),
     ("levels_too_many", 2), ("bad_wrap", 2), ("bad_mip", 2), ("ggx_missing", 1), ("bad_shade", 2),
     ("ggx_backfacing", 2), ("misaligned_level", 2), ("width_zero", 2), ("keys_ok_zero", 0),
-    ("keys_reuse", 3), ("filter_4", 2),
+    ("keys_reuse", 3), ("filter_7", 2), ("gauss_sigma_small", 2), ("gauss_sigma_nan", 2), ("fis_sigma_big", 2),
+    ("gauss_reuse", 3), ("fis_bspline_reuse", 3), ("fis_bspline_any_sigma_zero", 0),
 ])
 def test_filter2d_validation(sf, case, status):
     L = sf.lib()
@@ -161,8 +180,21 @@ def test_filter2d_validation(sf, case, status):
         n = 0
     elif case == "keys_reuse":
         smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 4, rng_variant=1)
-    elif case == "filter_4":
-        smp = sf.sampling(4, sf.SF_STOCHASTIC, 4)
+    elif case == "filter_7":
+        smp = sf.sampling(7, sf.SF_STOCHASTIC, 4)
+    elif case == "gauss_sigma_small":
+        smp = sf.sampling(sf.SF_GAUSS_FRS, sf.SF_STOCHASTIC, 4, sigma=0.05)
+    elif case == "gauss_sigma_nan":
+        smp = sf.sampling(sf.SF_GAUSS_FRS, sf.SF_AFTER_EXACT, 1, sigma=float("nan"))
+    elif case == "fis_sigma_big":
+        smp = sf.sampling(sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 4, sigma=4.5)
+    elif case == "gauss_reuse":
+        smp = sf.sampling(sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 4, rng_variant=1)
+    elif case == "fis_bspline_reuse":
+        smp = sf.sampling(sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 4, rng_variant=1)
+    elif case == "fis_bspline_any_sigma_zero":
+        smp = sf.sampling(sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 4, sigma=0.0)    # sigma unused
+        n = 0
     st = L.sf_filter2d(texp, FAKE, n, C.byref(smp), shade, C.byref(g) if g is not None else None, FAKE, None, None)
     assert st == status, sf.sf_last_error()
 
@@ -176,9 +208,10 @@ def test_filter3d_validation(sf):
     assert L.sf_filter3d(C.byref(vol), None, 3, C.byref(smp), 0, 1.0, FAKE, None, None) == 1
     big = _vol(sf, nx=4096, ny=4096, nz=256)     # 8 GiB: beyond one 32-bit-offset buffer
     assert L.sf_filter3d(C.byref(big), FAKE, 3, C.byref(smp), 0, 1.0, FAKE, None, None) == 3
-    keys = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 1)      # the Keys cubic is 2-D only
-    assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(keys), 0, 1.0, FAKE, None, None) == 3
-    assert L.sf_raymarch(C.byref(vol), FAKE, 3, 8, C.byref(keys), FAKE, None, None) == 3
+    for f in (sf.SF_KEYS3, sf.SF_GAUSS_FRS, sf.SF_GAUSS_FIS, sf.SF_BSPLINE3_FIS):   # 2-D only
+        s2 = sf.sampling(f, sf.SF_STOCHASTIC, 1)
+        assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(s2), 0, 1.0, FAKE, None, None) == 3
+        assert L.sf_raymarch(C.byref(vol), FAKE, 3, 8, C.byref(s2), FAKE, None, None) == 3
 
 
 def test_error_stats_validation(sf):

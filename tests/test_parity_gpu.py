@@ -398,6 +398,76 @@ def test_filter2d_keys_config2_full_sampled(sf, orc, c2_full):
     _close_signed(out[sub], ref, np.nanmax(np.abs(ref)))
 
 
+# ------------------------------------------------------------------ 2-D Gaussian FRS / FIS, B-spline FIS
+GAUSS = [("GAUSS_FRS", 0.3), ("GAUSS_FRS", 0.8), ("GAUSS_FRS", 1 / 16), ("GAUSS_FIS", 0.3), ("GAUSS_FIS", 0.8),
+         ("GAUSS_FIS", 4.0), ("BSPLINE3_FIS", 0.5)]
+
+
+@pytest.mark.parametrize("filt, sigma", GAUSS)
+@pytest.mark.parametrize("mode, spp", [("STOCH", 16), ("STOCH", 3), ("BEFORE", 1), ("AFTER", 1)])
+@pytest.mark.parametrize("shade", [0, 1])
+@pytest.mark.parametrize("wrap", [0, 1])
+def test_filter2d_gauss_fis_config1(sf, orc, c1, filt, sigma, mode, spp, shade, wrap):
+    _print_case("filter2d_gauss_c1", filt, sigma, mode, spp, shade, wrap)
+    tex, q = c1
+    ot = orc.Tex2D.rgba32f(tex, wrap=wrap)
+    gt = sf.Texture2D([tex], wrap=wrap)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=91, sigma=sigma)
+    taps_d = torch.full((q.shape[0], spp, 3), 99, dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=shade, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d(ot, q, getattr(orc, filt), m, spp=spp, seed=91, shade=shade, taps=m == orc.STOCHASTIC,
+                       sigma=sigma)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("filt, sigma", [("GAUSS_FRS", 0.5), ("GAUSS_FIS", 0.5), ("GAUSS_FIS", 2.0),
+                                         ("BSPLINE3_FIS", 0.5)])
+@pytest.mark.parametrize("mode, spp", [("STOCH", 8), ("AFTER", 1)])
+def test_filter2d_gauss_fis_mips_rgba8(sf, orc, c2_small, filt, sigma, mode, spp):
+    """MIP pyramid down to 1x1 levels: the FIS Gaussian's wide offsets wrap
+    several times around the small levels."""
+    _print_case("filter2d_gauss_mips", filt, sigma, mode, spp)
+    lv, q = c2_small
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    qq = q.copy()
+    qq[::7, 2] = len(lv) - 1.0                                 # some queries on the 1x1 level
+    m = {"STOCH": orc.STOCHASTIC, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=17, sigma=sigma)
+    taps_d = torch.empty((q.shape[0], spp, 3), dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d(gt, torch.from_numpy(qq).cuda(), smp, shade=1, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d(ot, qq, getattr(orc, filt), m, spp=spp, seed=17, shade=1, taps=m == orc.STOCHASTIC,
+                       sigma=sigma)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("filt, sigma", [("GAUSS_FIS", 0.5), ("BSPLINE3_FIS", 0.5), ("GAUSS_FRS", 0.5)])
+def test_filter2d_gauss_fis_config2_full_sampled(sf, orc, c2_full, filt, sigma):
+    _print_case("filter2d_gauss_c2_full", filt, sigma)
+    lv, q = c2_full
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, 4096, 4096, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    smp = sf.sampling(getattr(sf, "SF_" + filt), sf.SF_STOCHASTIC, 16, seed=33, sigma=sigma)
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx()).cpu().numpy()
+    sub = np.sort(np.random.default_rng(3).choice(q.shape[0], 3000, replace=False))
+    ref = orc.filter2d(ot, q, getattr(orc, filt), orc.STOCHASTIC, spp=16, seed=33, shade=1, subset=sub,
+                       sigma=sigma)
+    _close(out[sub], ref)
+
+
 # ------------------------------------------------------------------ 3-D points
 @pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("mode, spp, variant", [("STOCH", 4, 0), ("STOCH", 3, 1), ("BEFORE", 1, 0), ("AFTER", 1, 0)])
