@@ -323,6 +323,43 @@ def texture_bench(args, res):
     c2["cpu_oracle_bicubic_stochastic_16spp"] = {"queries_per_s": sub.size / dt, "cores": oracle.num_threads(),
                                                  "sample": f"{sub.size} queries, {dt:.2f} s"}
     res["config2"] = c2
+    del tex2, tex2n, qd2
+    # ---- config 2, anisotropic: checkerboard plane, footprint-driven levels
+    log("config 2 anisotropic: checkerboard")
+    lvc = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_checker(4096, 64)))
+    qa = inputs.plane_queries_aniso(1920, 1080)
+    qi = inputs.plane_queries(1920, 1080, tex_size=4096, levels=len(lvc))
+    na = qa.shape[0]
+    texc = sf.Texture2D(lvc, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    qad, qid = torch.from_numpy(qa).cuda(), torch.from_numpy(qi).cuda()
+    bufc, offc = inputs.pack_levels(lvc)
+    otc0 = oracle.Tex2D(bufc, 4096, 4096, 1, oracle.RGBA8, offc[:1], oracle.REPEAT, oracle.MIP_NONE)
+    suba = np.sort(rng.choice(na, 2000, replace=False))
+    t0 = time.perf_counter()
+    ref_a = oracle.aniso_reference(otc0, qa, K=16, filt=oracle.BSPLINE3, shade=1, subset=suba)
+    dt_ref = time.perf_counter() - t0
+    ca = {"queries": na, "reference": f"pixel integral, 16x16 midpoints x bicubic filter-after on level 0, "
+                                      f"{suba.size} pixels ({dt_ref:.1f} s on the CPU)"}
+    for name, filt, mode, spp, amax in (
+            ("aniso_bicubic_stochastic_1spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, 64),
+            ("aniso_bicubic_stochastic_16spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 16, 64),
+            ("aniso_bilinear_stochastic_1spp", sf.SF_LINEAR, sf.SF_STOCHASTIC, 1, 64),
+            ("aniso_gauss_fis_stochastic_16spp", sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 16, 64),
+            ("aniso16_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 16),
+            ("aniso64_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 64),
+            ("aniso64_trilinear_probes_after", sf.SF_LINEAR, sf.SF_AFTER_EXACT, 1, 64)):
+        smp = sf.sampling(filt, mode, spp, seed=5, sigma=0.5)
+        o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
+        t = time_launches(lambda: sf.sf_filter2d_aniso(texc, qad, smp, amax, sf.SF_SHADE_GGX, g, out=o), 10, 3,
+                          torch)
+        ca[name] = {"ms": t, "queries_per_s": na / (t * 1e-3),
+                    "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
+    smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)
+    o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
+    t = time_launches(lambda: sf.sf_filter2d(texc, qid, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
+    ca["isotropic_trilinear_before"] = {"ms": t, "queries_per_s": na / (t * 1e-3),
+                                        "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
+    res["config2_aniso"] = ca
 
 
 def neural_bench(args):

@@ -54,6 +54,7 @@ extern "C" {
 #define SF_MAX_LEVELS 16
 #define SF_MAX_STEPS 65536
 #define SF_MAX_SPP 65536
+#define SF_MAX_ANISO 64
 
 typedef int32_t sf_status;
 enum {
@@ -200,6 +201,39 @@ typedef struct sf_volume {
  */
 sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,
                       int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps, void *stream);
+
+/*
+ * sf_filter2d_aniso — minification with anisotropic footprints by
+ * screen-space jitter (Sec. 4.2.1 "Screen-Space Anisotropic Minification";
+ * the level of detail of Suppl. S.4.3; Sec. 5 "Anisotropic filtering and
+ * minification").
+ *   queries : n x {u, v, du/dx, dv/dx, du/dy, dv/dy} float32 (24 B): the
+ *             pixel centre's texture coordinate and its screen derivatives.
+ *   smp     : filter NEAREST | LINEAR | BSPLINE3 (FRS) | GAUSS_FIS (stochastic
+ *             only, with smp->sigma); rng_variant 0.
+ *   aniso_max: 1..SF_MAX_ANISO (the paper's limit is 64).
+ *   tex->mip is ignored: the level comes from the footprint.  Footprint
+ *   axes in level-0 texels a = (W du/dx, H dv/dx), b = (W du/dy, H dv/dy);
+ *   minor = the shorter, lengthened to major/aniso_max if the ratio exceeds
+ *   aniso_max (as major/(minor aniso_max) * minor); lambda = log2(minor)
+ *   (binary32 contract: frexp reduction + atanh series, as the Gaussian
+ *   filters' ln).
+ *   SF_STOCHASTIC, per sample: key (query, sample, 0, seed) words 0, 1 give
+ *     the jitter j = u - 1/2 and word 2 the level uniform; key (.., 1, ..)
+ *     words 0, 1 the filter's uniforms.  uv' = fma(jy, d/dy, fma(jx, d/dx, uv)),
+ *     level = floor(clamp(lambda + (u_l - 1/2), 0, levels-1) + 1/2), then
+ *     one texel of that level at uv'.  dbg_taps: n x spp x {level, x, y}.
+ *   SF_BEFORE / SF_AFTER_EXACT: the probe comparator (hardware-style
+ *     anisotropic filtering): N = clamp(ceil(major/minor), 1, aniso_max)
+ *     probes at offsets (k + 1/2)/N - 1/2 of the major-axis derivative, each
+ *     filtered on levels floor(lambda), floor(lambda)+1 (weights 1-f, f),
+ *     averaged; before shades the average, after averages shaded texels.
+ * Errors: as sf_filter2d; SF_E_UNSUPPORTED for other filters or variants;
+ *         SF_E_RANGE for aniso_max or sigma out of range.
+ */
+sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,
+                            int32_t aniso_max, int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps,
+                            void *stream);
 
 /*
  * sf_filter3d — filtered point lookups in a density grid.

@@ -30,8 +30,8 @@ SF_SHADE_DENSITY, SF_SHADE_TRANSMITTANCE = 0, 1
 SF_TAP_NONE = -(2 ** 31)
 SF_MAX_LEVELS = 16
 
-EXPORTED = ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_build_occupancy", "sf_occupancy_words",
-            "sf_mlp_nparams", "sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
+EXPORTED = ("sf_filter2d", "sf_filter2d_aniso", "sf_filter3d", "sf_raymarch", "sf_build_occupancy",
+            "sf_occupancy_words", "sf_mlp_nparams", "sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
             "sf_neural_quantize", "sf_neural_train_step", "sf_neural_train_workspace",
             "sf_error_stats", "sf_error_stats_workspace", "sf_last_error", "sf_abi_version", "sf_rng_version")
 SF_LATENT_F32, SF_LATENT_BF16, SF_LATENT_FP8E4M3 = 0, 1, 2
@@ -96,6 +96,7 @@ def lib() -> C.CDLL:
         L = C.CDLL(LIB_PATH)
         P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.sf_filter2d.argtypes = [P, P, i64, P, i32, P, P, P, P]
+        L.sf_filter2d_aniso.argtypes = [P, P, i64, P, i32, i32, P, P, P, P]
         L.sf_filter3d.argtypes = [P, P, i64, P, i32, C.c_float, P, P, P]
         L.sf_raymarch.argtypes = [P, P, i64, i32, P, P, P, P]
         L.sf_error_stats.argtypes = [P, P, i64, i32, P, P, C.c_size_t, P]
@@ -118,7 +119,7 @@ def lib() -> C.CDLL:
             getattr(L, f).restype = i32
         L.sf_error_stats_workspace.argtypes = [i64]
         L.sf_error_stats_workspace.restype = C.c_size_t
-        for f in ("sf_filter2d", "sf_filter3d", "sf_raymarch", "sf_error_stats"):
+        for f in ("sf_filter2d", "sf_filter2d_aniso", "sf_filter3d", "sf_raymarch", "sf_error_stats"):
             getattr(L, f).restype = i32
         L.sf_last_error.restype = C.c_char_p
         L.sf_abi_version.restype = i32
@@ -154,7 +155,9 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _need(t: torch.Tensor, dtype, name: str):
+def _need(t: torch.Tensor, dtype, name: str, numel: int | None = None):
+    """Type, device, layout and (for buffers the library writes) size checks:
+    the C ABI trusts the sizes it is given."""
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.dtype != dtype:
@@ -163,6 +166,8 @@ def _need(t: torch.Tensor, dtype, name: str):
         raise ValueError(f"{name} must be a device tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
 
 
 def sampling(filter: int, mode: int, spp: int = 1, seed: int = 0, rng_variant: int = 0,
@@ -250,14 +255,32 @@ def sf_filter2d(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, shade: 
     ch = 3 if shade == SF_SHADE_GGX else 4
     if out is None:
         out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
-    _need(out, torch.float32, "out")
+    _need(out, torch.float32, "out", n * ch)
     if dbg_taps is not None:
-        _need(dbg_taps, torch.int32, "dbg_taps")
-        if dbg_taps.numel() < n * smp.spp * (5 if smp.filter == SF_KEYS3 else 3):
-            raise ValueError("dbg_taps too small")
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * (5 if smp.filter == SF_KEYS3 else 3))
     g = C.byref(ggx_params) if ggx_params is not None else None
     _check(lib().sf_filter2d(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), shade, g, _ptr(out),
                              _ptr(dbg_taps), _stream(stream)))
+    return out
+
+
+def sf_filter2d_aniso(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, aniso_max: int = 64,
+                      shade: int = SF_SHADE_NONE, ggx_params: sf_ggx | None = None, out: torch.Tensor | None = None,
+                      dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Anisotropic minification; queries ``[n, 6]`` {u, v, du/dx, dv/dx, du/dy, dv/dy}."""
+    _need(queries, torch.float32, "queries")
+    if queries.numel() % 6:
+        raise ValueError("queries must hold 6 floats per pixel")
+    n = queries.numel() // 6
+    ch = 3 if shade == SF_SHADE_GGX else 4
+    if out is None:
+        out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
+    _need(out, torch.float32, "out", n * ch)
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * 3)
+    g = C.byref(ggx_params) if ggx_params is not None else None
+    _check(lib().sf_filter2d_aniso(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), aniso_max, shade, g,
+                                   _ptr(out), _ptr(dbg_taps), _stream(stream)))
     return out
 
 
@@ -267,11 +290,9 @@ def sf_filter3d(vol: Volume, pos: torch.Tensor, smp: sf_sampling, shade: int = S
     n = pos.numel() // 3
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=pos.device)
-    _need(out, torch.float32, "out")
+    _need(out, torch.float32, "out", n)
     if dbg_taps is not None:
-        _need(dbg_taps, torch.int32, "dbg_taps")
-        if dbg_taps.numel() < n * smp.spp * 3:
-            raise ValueError("dbg_taps too small")
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * 3)
     _check(lib().sf_filter3d(C.byref(vol.desc), _ptr(pos), n, C.byref(smp), shade, ds, _ptr(out), _ptr(dbg_taps),
                              _stream(stream)))
     return out
@@ -283,11 +304,9 @@ def sf_raymarch(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling, T
     n = rays.numel() // 8
     if T is None:
         T = torch.empty(n, dtype=torch.float32, device=rays.device)
-    _need(T, torch.float32, "T")
+    _need(T, torch.float32, "T", n)
     if dbg_taps is not None:
-        _need(dbg_taps, torch.int32, "dbg_taps")
-        if dbg_taps.numel() < n * smp.spp * steps * 3:
-            raise ValueError("dbg_taps too small")
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * steps * 3)
     _check(lib().sf_raymarch(C.byref(vol.desc), _ptr(rays), n, steps, C.byref(smp), _ptr(T), _ptr(dbg_taps),
                              _stream(stream)))
     return T
@@ -324,6 +343,7 @@ def sf_error_stats(est: torch.Tensor, ref: torch.Tensor, out: torch.Tensor | Non
     count = est.numel()
     if out is None:
         out = torch.zeros(8, dtype=torch.float64, device=est.device)
+    _need(out, torch.float64, "out", 8)
     if workspace is None:
         workspace = torch.empty(max(1, sf_error_stats_workspace(count)), dtype=torch.uint8, device=est.device)
     _check(lib().sf_error_stats(_ptr(est), _ptr(ref), count, 1, _ptr(out), _ptr(workspace), workspace.numel(),
@@ -341,7 +361,7 @@ def sf_to_bf16(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) ->
     _need(x, torch.float32, "x")
     if out is None:
         out = torch.empty(x.shape, dtype=torch.int16, device=x.device)
-    _need(out, torch.int16, "out")
+    _need(out, torch.int16, "out", x.numel())
     _check(lib().sf_to_bf16(_ptr(x), x.numel(), _ptr(out), _stream(stream)))
     return out
 
@@ -402,11 +422,9 @@ def sf_neural_decode(grid: LatentGrid, mlp: MLP, queries: torch.Tensor, smp: sf_
     ch = 3 if shade == SF_SHADE_GGX else 4
     if out is None:
         out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
-    _need(out, torch.float32, "out")
+    _need(out, torch.float32, "out", n * ch)
     if dbg_taps is not None:
-        _need(dbg_taps, torch.int32, "dbg_taps")
-        if dbg_taps.numel() < n * smp.spp * 2:
-            raise ValueError("dbg_taps too small")
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * 2)
     g = C.byref(ggx_params) if ggx_params is not None else None
     _check(lib().sf_neural_decode(C.byref(grid.desc), C.byref(mlp.desc), _ptr(queries), n, C.byref(smp), shade, g,
                                   _ptr(out), _ptr(dbg_taps), _stream(stream)))
@@ -419,11 +437,9 @@ def sf_neural_raymarch(grid: LatentGrid, mlp: MLP, rays: torch.Tensor, steps: in
     n = rays.numel() // 8
     if T is None:
         T = torch.empty(n, dtype=torch.float32, device=rays.device)
-    _need(T, torch.float32, "T")
+    _need(T, torch.float32, "T", n)
     if dbg_taps is not None:
-        _need(dbg_taps, torch.int32, "dbg_taps")
-        if dbg_taps.numel() < n * smp.spp * steps * 3:
-            raise ValueError("dbg_taps too small")
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * steps * 3)
     _check(lib().sf_neural_raymarch(C.byref(grid.desc), C.byref(mlp.desc), _ptr(rays), n, steps, C.byref(smp),
                                     _ptr(T), _ptr(dbg_taps), _stream(stream)))
     return T
@@ -435,7 +451,7 @@ def sf_neural_decode_lattice(grid: LatentGrid, mlp: MLP, idx: torch.Tensor, out:
     n = idx.numel()
     if out is None:
         out = torch.empty((n, mlp.desc.out_dim), dtype=torch.float32, device=idx.device)
-    _need(out, torch.float32, "out")
+    _need(out, torch.float32, "out", n * mlp.desc.out_dim)
     _check(lib().sf_neural_decode_lattice(C.byref(grid.desc), C.byref(mlp.desc), _ptr(idx), n, _ptr(out),
                                           _stream(stream)))
     return out
@@ -447,6 +463,8 @@ class TrainState:
     def __init__(self, latents: torch.Tensor, params: torch.Tensor, channels: int, out_dim: int, hidden: int = 64):
         _need(latents, torch.float32, "latents")
         _need(params, torch.float32, "params")
+        if params.numel() != sf_mlp_nparams(channels, hidden, out_dim) or latents.numel() % channels:
+            raise ValueError("latents or params do not match the shape")
         self.latents, self.params = latents, params
         self.m_lat, self.v_lat = torch.zeros_like(latents), torch.zeros_like(latents)
         self.m_par, self.v_par = torch.zeros_like(params), torch.zeros_like(params)
@@ -469,7 +487,7 @@ def sf_neural_train_step(st: TrainState, batch_idx: torch.Tensor, targets: torch
                          workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """One Adam step; returns the device loss tensor (1 float)."""
     _need(batch_idx, torch.int32, "batch_idx")
-    _need(targets, torch.float32, "targets")
+    _need(targets, torch.float32, "targets", st.n_lattice * st.out_dim)
     B = batch_idx.numel()
     if step is None:
         st.step += 1
@@ -481,9 +499,11 @@ def sf_neural_train_step(st: TrainState, batch_idx: torch.Tensor, targets: torch
         if st._ws is None or st._ws.numel() < need:
             st._ws = torch.empty(max(need, 4), dtype=torch.uint8, device=batch_idx.device)
         workspace = st._ws
-    for t, name in ((grad_params, "grad_params"), (grad_latents, "grad_latents")):
+    _need(loss_out, torch.float32, "loss_out", 1)
+    for t, name, k in ((grad_params, "grad_params", st.params.numel()), (grad_latents, "grad_latents",
+                                                                         B * st.channels)):
         if t is not None:
-            _need(t, torch.float32, name)
+            _need(t, torch.float32, name, k)
     _check(lib().sf_neural_train_step(C.byref(st.desc), _ptr(batch_idx), _ptr(targets), B, step, lr_latent, lr_mlp,
                                       _ptr(loss_out), _ptr(grad_params), _ptr(grad_latents), _ptr(workspace),
                                       workspace.numel(), _stream(stream)))

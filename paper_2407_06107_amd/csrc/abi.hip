@@ -158,24 +158,8 @@ const char *sf_last_error(void) { return g_err; }
 int32_t sf_abi_version(void) { return SF_ABI_VERSION; }
 int32_t sf_rng_version(void) { return SF_RNG_VERSION; }
 
-sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp, int32_t shade,
-                      const sf_ggx *ggx, float *out, int32_t *dbg_taps, void *stream)
+static sf_status check_tex2d(const sf_tex2d *tex)
 {
-    sf_status st;
-    if ((st = check_n(n)) != SF_OK)
-        return st;
-    if (n == 0)
-        return ok();
-    if (!tex || !queries || !out)
-        return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
-    if ((st = check_sampling(smp)) != SF_OK)
-        return st;
-    if (smp->filter >= SF_KEYS3 && smp->rng_variant != 0)
-        return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters draw independent uniforms (rng_variant 0)");
-    if ((smp->filter == SF_GAUSS_FRS || smp->filter == SF_GAUSS_FIS) &&
-        !(smp->sigma >= SF_SIGMA_MIN && smp->sigma <= SF_SIGMA_MAX))
-        return fail(SF_E_RANGE, "sigma %g outside %g..%g", (double)smp->sigma, (double)SF_SIGMA_MIN,
-                    (double)SF_SIGMA_MAX);
     if (!tex->base)
         return fail(SF_E_NULL, "texture base pointer is NULL");
     if (tex->format != SF_RGBA32F && tex->format != SF_RGBA8_UNORM)
@@ -195,6 +179,42 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
     for (int l = 0; l < tex->levels; ++l)
         if (tex->level_offset[l] < 0 || !aligned((const uint8_t *)tex->base + tex->level_offset[l], esz))
             return fail(SF_E_RANGE, "level %d offset negative or misaligned", l);
+    return SF_OK;
+}
+
+static void tex_args(const sf_tex2d *tex, sfk::Tex2DArgs &a)
+{
+    a.base = (const uint8_t *)tex->base;
+    a.w = tex->width;
+    a.h = tex->height;
+    a.levels = tex->levels;
+    a.fmt = tex->format;
+    a.wrap = tex->wrap;
+    a.mip = tex->mip;
+    for (int l = 0; l < SF_MAX_LEVELS; ++l)
+        a.off[l] = l < tex->levels ? tex->level_offset[l] : 0;
+}
+
+sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp, int32_t shade,
+                      const sf_ggx *ggx, float *out, int32_t *dbg_taps, void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (n == 0)
+        return ok();
+    if (!tex || !queries || !out)
+        return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    if (smp->filter >= SF_KEYS3 && smp->rng_variant != 0)
+        return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters draw independent uniforms (rng_variant 0)");
+    if ((smp->filter == SF_GAUSS_FRS || smp->filter == SF_GAUSS_FIS) &&
+        !(smp->sigma >= SF_SIGMA_MIN && smp->sigma <= SF_SIGMA_MAX))
+        return fail(SF_E_RANGE, "sigma %g outside %g..%g", (double)smp->sigma, (double)SF_SIGMA_MIN,
+                    (double)SF_SIGMA_MAX);
+    if ((st = check_tex2d(tex)) != SF_OK)
+        return st;
     if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
         return fail(SF_E_RANGE, "shade %d out of range", shade);
     if (!aligned(queries, 4) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))
@@ -206,15 +226,7 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
         if ((st = ggx_constants(ggx, c.g)) != SF_OK)
             return st;
     }
-    c.tex.base = (const uint8_t *)tex->base;
-    c.tex.w = tex->width;
-    c.tex.h = tex->height;
-    c.tex.levels = tex->levels;
-    c.tex.fmt = tex->format;
-    c.tex.wrap = tex->wrap;
-    c.tex.mip = tex->mip;
-    for (int l = 0; l < SF_MAX_LEVELS; ++l)
-        c.tex.off[l] = l < tex->levels ? tex->level_offset[l] : 0;
+    tex_args(tex, c.tex);
     c.q = queries;
     c.n = n;
     c.filter = smp->filter;
@@ -227,6 +239,59 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
     c.out = out;
     c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
     return device_status(sfk::launch_filter2d(c, (hipStream_t)stream));
+}
+
+sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,
+                            int32_t aniso_max, int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps,
+                            void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (n == 0)
+        return ok();
+    if (!tex || !queries || !out)
+        return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    const int f = smp->filter;
+    if (f != SF_NEAREST && f != SF_LINEAR && f != SF_BSPLINE3 && f != SF_GAUSS_FIS)
+        return fail(SF_E_UNSUPPORTED, "anisotropic filtering takes NEAREST, LINEAR, BSPLINE3 or GAUSS_FIS");
+    if (f == SF_GAUSS_FIS && smp->mode != SF_STOCHASTIC)
+        return fail(SF_E_UNSUPPORTED, "the FIS Gaussian has no probe comparator here");
+    if (smp->rng_variant != 0)
+        return fail(SF_E_UNSUPPORTED, "anisotropic filtering draws independent uniforms (rng_variant 0)");
+    if (f == SF_GAUSS_FIS && !(smp->sigma >= SF_SIGMA_MIN && smp->sigma <= SF_SIGMA_MAX))
+        return fail(SF_E_RANGE, "sigma %g outside %g..%g", (double)smp->sigma, (double)SF_SIGMA_MIN,
+                    (double)SF_SIGMA_MAX);
+    if (aniso_max < 1 || aniso_max > SF_MAX_ANISO)
+        return fail(SF_E_RANGE, "aniso_max %d outside 1..%d", aniso_max, SF_MAX_ANISO);
+    if ((st = check_tex2d(tex)) != SF_OK)
+        return st;
+    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
+        return fail(SF_E_RANGE, "shade %d out of range", shade);
+    if (!aligned(queries, 4) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))
+        return fail(SF_E_RANGE, "queries or out misaligned");
+    sfk::AnisoCall c{};
+    if (shade == SF_SHADE_GGX) {
+        if (!ggx)
+            return fail(SF_E_NULL, "GGX shading needs ggx parameters");
+        if ((st = ggx_constants(ggx, c.g)) != SF_OK)
+            return st;
+    }
+    tex_args(tex, c.tex);
+    c.q = queries;
+    c.n = n;
+    c.filter = f;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.seed = smp->seed;
+    c.sigma = smp->sigma;
+    c.amax = aniso_max;
+    c.shade = shade;
+    c.out = out;
+    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    return device_status(sfk::launch_aniso(c, (hipStream_t)stream));
 }
 
 sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const sf_sampling *smp, int32_t shade,

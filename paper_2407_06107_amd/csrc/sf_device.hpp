@@ -170,6 +170,30 @@ __device__ __forceinline__ float lnc(float x)
     return __builtin_fmaf(fe, LN2_HI, __builtin_fmaf(fe, LN2_LO, r));
 }
 
+// log2 x for positive normal x: the same reduction and series, then
+// e + ln(m) log2(e); -inf below 2^-126 (and for NaN), +inf for +inf.
+__device__ __forceinline__ float log2c(float x)
+{
+    if (!(x >= 0x1p-126f))
+        return -__builtin_inff();
+    if (x == __builtin_inff())
+        return x;
+    int e;
+    float m = __builtin_frexpf(x, &e);
+    if (m < 0.70710678f) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float z = s * s;
+    float p = __builtin_fmaf(z, 1.0f / 9.0f, 1.0f / 7.0f);
+    p = __builtin_fmaf(z, p, 1.0f / 5.0f);
+    p = __builtin_fmaf(z, p, 1.0f / 3.0f);
+    p = __builtin_fmaf(z, p, 1.0f);
+    const float r = (2.0f * s) * p;
+    return __builtin_fmaf(r, 1.44269504f, (float)e);
+}
+
 // e^x, x in [-80, 0] (0 below): n = floor(x log2 e + 1/2), r = x - n ln 2
 // (two parts), Taylor polynomial of e^r to r^7, scaled by 2^n.
 __device__ __forceinline__ float expc(float x)

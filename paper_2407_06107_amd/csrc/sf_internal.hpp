@@ -46,6 +46,18 @@ struct Filter2DCall {
     int32_t *taps;
 };
 
+struct AnisoCall {
+    Tex2DArgs tex;
+    const float *q;  // n x {u, v, du/dx, dv/dx, du/dy, dv/dy}
+    int64_t n;
+    int32_t filter, mode, spp, shade, amax;
+    uint32_t seed;
+    float sigma;
+    GgxConst g;
+    float *out;
+    int32_t *taps;
+};
+
 struct Filter3DCall {
     VolArgs vol;
     const float *pos;
@@ -112,6 +124,7 @@ struct TrainCall {
 
 // Launchers return hipSuccess or the launch error; arguments are validated.
 hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s);
+hipError_t launch_aniso(const AnisoCall &c, hipStream_t s);
 hipError_t launch_filter3d(const Filter3DCall &c, hipStream_t s);
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s);
 hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ, int64_t words, hipStream_t s);

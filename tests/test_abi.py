@@ -199,6 +199,45 @@ def test_filter2d_validation(sf, case, status):
     assert st == status, sf.sf_last_error()
 
 
+@pytest.mark.parametrize("case, status", [
+    ("ok_zero", 0), ("null_tex", 1), ("null_q", 1), ("keys", 3), ("gauss_frs", 3), ("fis_det", 3),
+    ("reuse", 3), ("aniso_0", 2), ("aniso_65", 2), ("fis_sigma", 2), ("bad_levels", 2), ("bad_shade", 2),
+])
+def test_filter2d_aniso_validation(sf, case, status):
+    L = sf.lib()
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 4)
+    tex = sf.sf_tex2d()
+    tex.base, tex.width, tex.height, tex.levels = 0x10000, 64, 64, 7
+    tex.format, tex.wrap, tex.mip = sf.SF_RGBA32F, 0, 0
+    n, amax, shade, texp, q = 10, 64, sf.SF_SHADE_NONE, C.byref(tex), FAKE
+    if case == "ok_zero":
+        n = 0
+    elif case == "null_tex":
+        texp = None
+    elif case == "null_q":
+        q = None
+    elif case == "keys":
+        smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 4)
+    elif case == "gauss_frs":
+        smp = sf.sampling(sf.SF_GAUSS_FRS, sf.SF_STOCHASTIC, 4)
+    elif case == "fis_det":
+        smp = sf.sampling(sf.SF_GAUSS_FIS, sf.SF_AFTER_EXACT, 1)
+    elif case == "reuse":
+        smp = sf.sampling(sf.SF_LINEAR, sf.SF_STOCHASTIC, 4, rng_variant=1)
+    elif case == "aniso_0":
+        amax = 0
+    elif case == "aniso_65":
+        amax = 65
+    elif case == "fis_sigma":
+        smp = sf.sampling(sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 4, sigma=0.01)
+    elif case == "bad_levels":
+        tex.levels = 8
+    elif case == "bad_shade":
+        shade = 3
+    st = L.sf_filter2d_aniso(texp, q, n, C.byref(smp), amax, shade, None, FAKE, None, None)
+    assert st == status, sf.sf_last_error()
+
+
 def test_filter3d_validation(sf):
     L = sf.lib()
     smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)

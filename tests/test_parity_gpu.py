@@ -468,6 +468,69 @@ def test_filter2d_gauss_fis_config2_full_sampled(sf, orc, c2_full, filt, sigma):
     _close(out[sub], ref)
 
 
+# ------------------------------------------------------------------ 2-D anisotropic minification
+@pytest.fixture(scope="module")
+def aniso_small(orc):
+    size = 256
+    lv = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_sinusoids(size, seed=3, waves=12)))
+    q = inputs.plane_queries_aniso(160, 90)
+    q[5, 2:] = 0.0                                 # zero footprint: level 0, no jitter
+    q[6, 0] = np.inf                               # non-finite -> NaN
+    q[7, 2:] = [3e-3, 0.0, 0.0, 1e-7]              # anisotropy far beyond the limit
+    return lv, q
+
+
+@pytest.mark.parametrize("filt, sigma", [("NEAREST", 0.5), ("LINEAR", 0.5), ("BSPLINE3", 0.5), ("GAUSS_FIS", 0.7)])
+@pytest.mark.parametrize("mode, spp", [("STOCH", 8), ("STOCH", 1), ("BEFORE", 1), ("AFTER", 1)])
+@pytest.mark.parametrize("amax", [64, 4])
+@pytest.mark.parametrize("shade", [0, 1])
+def test_filter2d_aniso_parity(sf, orc, aniso_small, filt, sigma, mode, spp, amax, shade):
+    if filt == "GAUSS_FIS" and mode != "STOCH":
+        pytest.skip("the FIS Gaussian has no probe comparator")
+    _print_case("filter2d_aniso", filt, mode, spp, amax, shade)
+    lv, q = aniso_small
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=29, sigma=sigma)
+    taps_d = torch.full((q.shape[0], spp, 3), 99, dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d_aniso(gt, torch.from_numpy(q).cuda(), smp, aniso_max=amax, shade=shade,
+                               ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d_aniso(ot, q, getattr(orc, filt), m, spp=spp, seed=29, shade=shade, taps=m == orc.STOCHASTIC,
+                             sigma=sigma, amax=amax)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.fixture(scope="module")
+def checker_full():
+    _print_case("checker_full generate")
+    lv = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_checker(4096, 64)))
+    q = inputs.plane_queries_aniso(1920, 1080)
+    return lv, q
+
+
+@pytest.mark.parametrize("filt, mode, spp", [("BSPLINE3", "STOCH", 1), ("BSPLINE3", "STOCH", 16),
+                                             ("LINEAR", "BEFORE", 1), ("LINEAR", "AFTER", 1)])
+def test_filter2d_aniso_checker_full_sampled(sf, orc, checker_full, filt, mode, spp):
+    _print_case("filter2d_aniso_checker_full", filt, mode, spp)
+    lv, q = checker_full
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, 4096, 4096, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=41)
+    out = sf.sf_filter2d_aniso(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx()).cpu().numpy()
+    sub = np.sort(np.random.default_rng(4).choice(q.shape[0], 3000, replace=False))
+    ref = orc.filter2d_aniso(ot, q, getattr(orc, filt), m, spp=spp, seed=41, shade=1, subset=sub)
+    _close(out[sub], ref)
+
+
 # ------------------------------------------------------------------ 3-D points
 @pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("mode, spp, variant", [("STOCH", 4, 0), ("STOCH", 3, 1), ("BEFORE", 1, 0), ("AFTER", 1, 0)])
