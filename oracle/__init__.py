@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS = 0, 1, 2, 3, 4, 5, 6
 SIGMA_MIN, SIGMA_MAX = 1.0 / 16.0, 4.0     # Gaussian standard deviation, texels
 BEFORE, AFTER, STOCHASTIC = 0, 1, 2
-RGBA32F, RGBA8, R16F, R32F = 0, 1, 2, 3
+RGBA32F, RGBA8, R16F, R32F, DCT8 = 0, 1, 2, 3, 4
 REPEAT, CLAMP = 0, 1
 MIP_NONE, MIP_NEAREST, MIP_LINEAR = 0, 1, 2
 TAP_NONE = np.iinfo(np.int32).min
@@ -67,9 +67,16 @@ def lib():
         L.orc_half_to_double.argtypes = [C.c_uint16]
         L.orc_pcg4d_batch.argtypes = [P, P, i64]
         L.orc_shade_ggx.argtypes = [P, P, P]
-        L.orc_filter2d.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, i32, i32, u32,
+        L.orc_filter2d.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, u32,
                                    i32, f32, i32, P, P, P, P, i64]
-        L.orc_filter2d_expect.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, i64, i32, f32, i32, P, P]
+        L.orc_filter2d_expect.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, P, i64, i32, f32, i32, P, P]
+        L.orc_dct_basis32.argtypes = [i32, i32]
+        L.orc_dct_basis32.restype = f32
+        L.orc_dct_encode_level.argtypes = [P, i32, i32, P, P]
+        L.orc_tri_pick.argtypes = [P, f32]
+        L.orc_tri_pick.restype = i32
+        L.orc_triplanar.argtypes = [P, i32, i32, i32, i32, i32, i32, P, P, P, i64, f32, i32, i32, i32, i32, u32,
+                                    i32, P, P, P, P, i64]
         L.orc_lnc.argtypes = [f32]
         L.orc_lnc.restype = f32
         L.orc_expc.argtypes = [f32]
@@ -89,9 +96,9 @@ def lib():
         L.orc_log2c.restype = f32
         L.orc_aniso_lod.argtypes = [i32, i32, P, i32, P, P]
         L.orc_aniso_lod.restype = f32
-        L.orc_filter2d_aniso.argtypes = [P, i32, i32, i32, i32, i32, P, P, i64, i32, i32, i32, u32, f32, i32, i32,
-                                         P, P, P, P, i64]
-        L.orc_aniso_reference.argtypes = [P, i32, i32, i32, i32, P, i64, i32, i32, f32, i32, P, P, P, i64]
+        L.orc_filter2d_aniso.argtypes = [P, i32, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, u32, f32, i32,
+                                         i32, P, P, P, P, i64]
+        L.orc_aniso_reference.argtypes = [P, i32, i32, i32, i32, P, P, i64, i32, i32, f32, i32, P, P, P, i64]
         L.orc_reuse_histogram2.argtypes = [i32, f32, f32, P]
         L.orc_filter3d.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, u32, i32,
                                    i32, f32, P, P, P, i64]
@@ -219,12 +226,39 @@ class Tex2D:
     """Host texture: packed level buffer + per-level byte offsets."""
 
     def __init__(self, buf: np.ndarray, w: int, h: int, levels: int, fmt: int, offsets,
-                 wrap: int = REPEAT, mip: int = MIP_NONE):
+                 wrap: int = REPEAT, mip: int = MIP_NONE, dct_range=None):
         self.buf = np.ascontiguousarray(buf).view(np.uint8).reshape(-1)
         self.w, self.h, self.levels, self.fmt = w, h, levels, fmt
         self.off = np.zeros(16, dtype=np.int64)
         self.off[:levels] = offsets
         self.wrap, self.mip = wrap, mip
+        self.dct_range = None if dct_range is None else _c(dct_range, np.float32).reshape(-1)
+        if fmt == DCT8 and (self.dct_range is None or self.dct_range.size < 4 * levels):
+            raise ValueError("a DCT texture needs 4 AC ranges per level")
+
+    @classmethod
+    def dct(cls, levels, wrap: int = REPEAT, mip: int = MIP_NONE):
+        """Encode RGBA8 levels (list of [h, w, 4] uint8) with the oracle's DCT
+        encoder: blocks of each level at 256-byte aligned offsets."""
+        chunks, offs, ranges, pos = [], [], [], 0
+        for lv in levels:
+            lv = _c(lv, np.uint8)
+            hl, wl = lv.shape[:2]
+            bw, bh = (wl + 7) // 8, (hl + 7) // 8
+            blocks = np.zeros(bw * bh * 4, dtype=np.uint32)
+            rng = np.zeros(4, dtype=np.float32)
+            lib().orc_dct_encode_level(_p(lv), wl, hl, _p(blocks), _p(rng))
+            pad = (-pos) % 256
+            if pad:
+                chunks.append(np.zeros(pad, np.uint8))
+                pos += pad
+            offs.append(pos)
+            chunks.append(blocks.view(np.uint8))
+            pos += blocks.nbytes
+            ranges.append(rng)
+        buf = np.concatenate(chunks) if chunks else np.zeros(0, np.uint8)
+        w0, h0 = levels[0].shape[1], levels[0].shape[0]
+        return cls(buf, w0, h0, len(levels), DCT8, offs, wrap, mip, np.concatenate(ranges))
 
     @classmethod
     def rgba32f(cls, tex: np.ndarray, wrap=REPEAT):
@@ -253,7 +287,7 @@ def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed
     tp = np.zeros((m, spp, 5 if filt == KEYS3 else 3), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_filter2d(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
-                       _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, sigma, shade, _p(g), _p(out), _p(tp),
+                       _p(tex.dct_range), _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, sigma, shade, _p(g), _p(out), _p(tp),
                        _p(sub), 0 if sub is None else sub.size)
     return (out, tp) if taps else out
 
@@ -267,7 +301,7 @@ def filter2d_expect(tex: Tex2D, q: np.ndarray, filt: int, shade: int = 0, ggx=No
     out = np.zeros((n, ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     st = lib().orc_filter2d_expect(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip,
-                                   _p(tex.off), _p(q), n, filt, sigma, shade, _p(g), _p(out))
+                                   _p(tex.off), _p(tex.dct_range), _p(q), n, filt, sigma, shade, _p(g), _p(out))
     if st != 0:
         raise ValueError("no exact expectation for this filter")
     return out
@@ -299,7 +333,8 @@ def filter2d_aniso(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1
     out = np.zeros((m, ch))
     tp = np.zeros((m, spp, 3), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
-    lib().orc_filter2d_aniso(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, _p(tex.off), _p(q), n, filt,
+    lib().orc_filter2d_aniso(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, _p(tex.off),
+                             _p(tex.dct_range), _p(q), n, filt,
                              mode, spp, seed & 0xFFFFFFFF, sigma, amax, shade, _p(g), _p(out), _p(tp), _p(sub),
                              0 if sub is None else sub.size)
     return (out, tp) if taps else out
@@ -314,9 +349,39 @@ def aniso_reference(tex: Tex2D, q: np.ndarray, K: int = 16, filt: int = BSPLINE3
     ch = 3 if shade == 1 else 4
     out = np.zeros((m, ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
-    lib().orc_aniso_reference(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(q), q.shape[0], K, filt, sigma,
+    lib().orc_aniso_reference(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(tex.dct_range), _p(q), q.shape[0],
+                              K, filt, sigma,
                               shade, _p(g), _p(out), _p(sub), 0 if sub is None else sub.size)
     return out
+
+
+# ------------------------------------------------------------------ DCT textures, triplanar mapping
+def dct_basis32() -> np.ndarray:
+    """The encoder's binary32 basis c_k(x), k = 0..2, x = 0..7."""
+    return np.array([[lib().orc_dct_basis32(k, x) for x in range(8)] for k in range(3)], dtype=np.float32)
+
+
+def tri_pick(nrm, u: float) -> int:
+    nn = _c(nrm, np.float32)
+    return lib().orc_tri_pick(_p(nn), u)
+
+
+def triplanar(tex: Tex2D, q: np.ndarray, scale: float, plane_mode: int, filt: int, mode: int, spp: int = 1,
+              seed: int = 0, shade: int = 0, ggx=None, taps: bool = False, subset=None):
+    """Triplanar mapping; queries ``[n, 8]`` {p, n, lambda, unused}.
+    plane_mode 0 blends the planes, 1 picks one per sample."""
+    q = _c(q, np.float32).reshape(-1, 8)
+    n = q.shape[0]
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
+    ch = 3 if shade == 1 else 4
+    out = np.zeros((m, ch))
+    tp = np.zeros((m, spp, 4), dtype=np.int32) if taps else None
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_triplanar(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
+                        _p(tex.dct_range), _p(q), n, scale, plane_mode, filt, mode, spp, seed & 0xFFFFFFFF, shade,
+                        _p(g), _p(out), _p(tp), _p(sub), 0 if sub is None else sub.size)
+    return (out, tp) if taps else out
 
 
 # ------------------------------------------------------------------ Gaussian / FIS contract

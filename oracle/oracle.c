@@ -32,6 +32,7 @@
  *   positivisation of negative lobes ........... Sec. 2.2 "Positivization"
  *   screen-space anisotropic minification ...... Sec. 4.2.1; Suppl. S.4.3; Sec. 5 "Anisotropic
  *                                                filtering and minification"
+ *   DCT-compressed textures, triplanar mapping . Sec. 5 "Texture compression", "Triplanar mapping"
  *   filter importance sampling (FIS) ........... Sec. 4.2; Sec. 5 "Magnification, Filter
  *                                                Importance Sampling"; Suppl. S.4.2
  *   transmittance in a density grid ............ Sec. 5 (offline rendering)
@@ -60,7 +61,7 @@
 enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2, F_KEYS3 = 3, F_GAUSS_FRS = 4, F_GAUSS_FIS = 5,
        F_BSPLINE3_FIS = 6 };
 enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2 };
-enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3 };
+enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3, FMT_DCT8 = 4 };
 enum { WRAP_REPEAT = 0, WRAP_CLAMP = 1 };
 enum { MIP_NONE = 0, MIP_NEAREST = 1, MIP_LINEAR = 2 };
 
@@ -624,6 +625,7 @@ typedef struct {
     const uint8_t *base;
     int w, h, levels, fmt, wrap, mip;
     const int64_t *off;
+    const float *dct_range; /* FMT_DCT8: AC range of channel c on level l at [4 l + c] */
 } tex2d;
 
 static int lvl_dim(int n, int l)
@@ -632,11 +634,124 @@ static int lvl_dim(int n, int l)
     return d < 1 ? 1 : d;
 }
 
+/* ------------------------------------------------------------------------ */
+/* DCT texture compression (Sec. 5 "Texture compression"): 8x8 texel blocks, */
+/* per channel the six lowest-frequency coefficients of the orthonormal 2-D  */
+/* DCT-II in zigzag order, DC in 7 bits and the five AC in 5 bits each: one  */
+/* 32-bit word per channel, 16 bytes per RGBA block (16x smaller than RGBA8).*/
+/* Readings: coefficients of the texel values v = byte/255; blocks past the  */
+/* level's edge replicate the edge texels; DC = 8 x block mean in [0, 8] is  */
+/* quantised uniformly to 0..127; AC uniformly to -15..15 over [-R, R] with  */
+/* R the largest |AC| of that channel on that level (stored beside the       */
+/* blocks); decoded values are clamped to [0, 1].                            */
+/* ------------------------------------------------------------------------ */
+/* zigzag order (u = horizontal, v = vertical frequency) */
+static const int DCT_U[6] = {0, 1, 0, 0, 1, 2};
+static const int DCT_V[6] = {0, 0, 1, 2, 1, 0};
+
+/* binary64 basis alpha(k) cos((2x+1) k pi / 16), alpha(0) = sqrt(1/8), else 1/2 */
+static double dct_basis64(int k, int x)
+{
+    double a = k == 0 ? sqrt(0.125) : 0.5;
+    return a * cos((2.0 * x + 1.0) * k * PI / 16.0);
+}
+
+/* the same rounded to binary32: the encoder's constants */
+ORC_EXPORT float orc_dct_basis32(int k, int x) { return (float)dct_basis64(k, x); }
+
+/* Six coefficients of one channel of one block in binary32: rows first,
+ * R_u(y) = sum_x c_u(x) v(x, y), then C(u, v) = sum_y c_v(y) R_u(y), each
+ * sum a chain of fused multiply-adds in increasing index from 0. */
+static void dct_block_coeffs(const uint8_t *lv, int wl, int hl, int bx, int by, int c, float C[6])
+{
+    float R[3][8];
+    for (int y = 0; y < 8; ++y) {
+        int yy = by * 8 + y < hl ? by * 8 + y : hl - 1;
+        float v[8];
+        for (int x = 0; x < 8; ++x) {
+            int xx = bx * 8 + x < wl ? bx * 8 + x : wl - 1;
+            v[x] = (float)lv[4 * ((int64_t)yy * wl + xx) + c] / 255.0f;
+        }
+        for (int u = 0; u < 3; ++u) {
+            float acc = 0.0f;
+            for (int x = 0; x < 8; ++x)
+                acc = fmaf(orc_dct_basis32(u, x), v[x], acc);
+            R[u][y] = acc;
+        }
+    }
+    for (int k = 0; k < 6; ++k) {
+        float acc = 0.0f;
+        for (int y = 0; y < 8; ++y)
+            acc = fmaf(orc_dct_basis32(DCT_V[k], y), R[DCT_U[k]][y], acc);
+        C[k] = acc;
+    }
+}
+
+/* Encode one RGBA8 level (wl x hl) into ceil(wl/8) x ceil(hl/8) blocks of
+ * four words and its four AC ranges.  Codes (binary32 decisions):
+ *   DC: clamp(floor(C0 * 15.875 + 1/2), 0, 127);
+ *   AC: R > 0 ? clamp(floor(Ck * (15/R) + 1/2), -15, 15) + 15 : 15;
+ *   word = DC | AC1 << 7 | AC2 << 12 | AC3 << 17 | AC4 << 22 | AC5 << 27. */
+ORC_EXPORT void orc_dct_encode_level(const uint8_t *lv, int wl, int hl, uint32_t *blocks, float range[4])
+{
+    int bw = (wl + 7) / 8, bh = (hl + 7) / 8;
+    for (int c = 0; c < 4; ++c) {
+        float r = 0.0f;
+        for (int by = 0; by < bh; ++by)
+            for (int bx = 0; bx < bw; ++bx) {
+                float C[6];
+                dct_block_coeffs(lv, wl, hl, bx, by, c, C);
+                for (int k = 1; k < 6; ++k)
+                    r = fmaxf(r, fabsf(C[k]));
+            }
+        range[c] = r;
+        float sc = r > 0.0f ? 15.0f / r : 0.0f;
+        for (int by = 0; by < bh; ++by)
+            for (int bx = 0; bx < bw; ++bx) {
+                float C[6];
+                dct_block_coeffs(lv, wl, hl, bx, by, c, C);
+                int dc = (int)floorf(C[0] * 15.875f + 0.5f);
+                dc = dc < 0 ? 0 : (dc > 127 ? 127 : dc);
+                uint32_t word = (uint32_t)dc;
+                for (int k = 1; k < 6; ++k) {
+                    int a = 15;
+                    if (r > 0.0f) {
+                        a = (int)floorf(C[k] * sc + 0.5f);
+                        a = (a < -15 ? -15 : (a > 15 ? 15 : a)) + 15;
+                    }
+                    word |= (uint32_t)a << (7 + 5 * (k - 1));
+                }
+                blocks[4 * ((int64_t)by * bw + bx) + c] = word;
+            }
+    }
+}
+
+/* Decoded texel (binary64 arithmetic, basis in binary64), clamped to [0, 1]. */
+static void dct_decode(const uint32_t *blk, const float *range, int x, int y, double out[4])
+{
+    for (int c = 0; c < 4; ++c) {
+        uint32_t wd = blk[c];
+        double v = (double)(wd & 127u) * (8.0 / 127.0) * dct_basis64(0, x) * dct_basis64(0, y);
+        for (int k = 1; k < 6; ++k) {
+            int a = (int)((wd >> (7 + 5 * (k - 1))) & 31u) - 15;
+            double coef = (double)a * (double)range[c] / 15.0;
+            v += coef * dct_basis64(DCT_U[k], x) * dct_basis64(DCT_V[k], y);
+        }
+        out[c] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    }
+}
+
 static void fetch2d(const tex2d *t, int l, int x, int y, double out[4])
 {
     int wl = lvl_dim(t->w, l);
     int64_t idx = (int64_t)y * wl + x;
     const uint8_t *lv = t->base + t->off[l];
+    if (t->fmt == FMT_DCT8) {
+        int bw = (wl + 7) / 8;
+        const uint32_t *blk = (const uint32_t *)lv + 4 * ((int64_t)(y / 8) * bw + x / 8);
+        dct_decode(blk, t->dct_range + 4 * l, x % 8, y % 8, out);
+        return;
+    }
     if (t->fmt == FMT_RGBA32F) {
         const float *f = (const float *)lv + 4 * idx;
         for (int c = 0; c < 4; ++c)
@@ -907,11 +1022,12 @@ static int axis_weights_s(int filter, float sigma, double t, int *first_off, dou
  * queries are computed (out and taps indexed by position in the subset, the
  * random key by the query's own index). */
 ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
-                            const int64_t *level_off, const float *q, int64_t n, int filter, int mode,
+                            const int64_t *level_off, const float *dct_range, const float *q, int64_t n,
+                            int filter, int mode,
                             int spp, uint32_t seed, int variant, float sigma, int shade, const double *ggx,
                             double *out, int32_t *taps, const int64_t *subset, int64_t nsub)
 {
-    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off};
+    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off, dct_range};
     int ch = shade == 1 ? 3 : 4;
     int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -930,12 +1046,13 @@ ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt,
  * linear, cubic B-spline, discrete Gaussian and B-spline FIS (returns -1
  * for the others). */
 ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
-                                   const int64_t *level_off, const float *q, int64_t n, int filter,
+                                   const int64_t *level_off, const float *dct_range, const float *q, int64_t n,
+                                   int filter,
                                    float sigma, int shade, const double *ggx, double *out)
 {
     if (filter == F_KEYS3 || filter == F_GAUSS_FIS)
         return -1;
-    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off};
+    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off, dct_range};
     int ch = shade == 1 ? 3 : 4;
     for (int64_t i = 0; i < n; ++i) {
         const float *qq = q + 3 * i;
@@ -1196,11 +1313,12 @@ static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, in
 /* queries: n x {u, v, du/dx, dv/dx, du/dy, dv/dy}; the texture's mip field
  * is ignored (the level comes from the footprint). */
 ORC_EXPORT int orc_filter2d_aniso(const void *base, int w, int h, int levels, int fmt, int wrap,
-                                  const int64_t *level_off, const float *q, int64_t n, int filter, int mode, int spp,
+                                  const int64_t *level_off, const float *dct_range, const float *q, int64_t n,
+                                  int filter, int mode, int spp,
                                   uint32_t seed, float sigma, int amax, int shade, const double *ggx, double *out,
                                   int32_t *taps, const int64_t *subset, int64_t nsub)
 {
-    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, MIP_LINEAR, level_off};
+    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, MIP_LINEAR, level_off, dct_range};
     int ch = shade == 1 ? 3 : 4;
     int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -1216,12 +1334,13 @@ ORC_EXPORT int orc_filter2d_aniso(const void *base, int w, int h, int levels, in
  * (offsets (i + 1/2)/K - 1/2 along d/dx and d/dy) of the exact
  * filter-after value on level 0 alone (no prefiltered level), i.e. filtering
  * after shading over the whole pixel footprint. */
-ORC_EXPORT int orc_aniso_reference(const void *base, int w, int h, int fmt, int wrap, const float *q, int64_t n,
+ORC_EXPORT int orc_aniso_reference(const void *base, int w, int h, int fmt, int wrap, const float *dct_range,
+                                   const float *q, int64_t n,
                                    int K, int filter, float sigma, int shade, const double *ggx, double *out,
                                    const int64_t *subset, int64_t nsub)
 {
     const int64_t off0 = 0;
-    tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0};
+    tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0, dct_range};
     int ch = shade == 1 ? 3 : 4;
     int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -1243,6 +1362,167 @@ ORC_EXPORT int orc_aniso_reference(const void *base, int w, int h, int fmt, int 
             }
         for (int c = 0; c < ch; ++c)
             o[c] = sum[c];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Triplanar mapping (Sec. 5 "Triplanar mapping").  A surface point p with   */
+/* unit normal n is textured from three planar projections, uv = (p.y, p.z), */
+/* (p.x, p.z), (p.x, p.y) times the texture scale, blended with weights      */
+/* b_i = n_i^4 / sum_j n_j^4 (reading: the usual sharpness 4; the paper does */
+/* not fix the blend).  The blend is a weighted mean of three filtered       */
+/* values, so one plane picked with probability b_i estimates it             */
+/* (eq. stochastic-sum).  Binary32 decision contract: a_i = n_i n_i,         */
+/* w_i = a_i a_i, W = (w0 + w1) + w2, plane = [u >= w0/W] + [u >= (w0+w1)/W] */
+/* with u = word 2 of the sample's key; words 0, 1 and 3 drive the filter's  */
+/* x and y picks and the MIP level pick as in filter2d.                      */
+/* ------------------------------------------------------------------------ */
+static void tri_weights32(const float *nrm, float w[3], float *W)
+{
+    for (int i = 0; i < 3; ++i) {
+        float a = nrm[i] * nrm[i];
+        w[i] = a * a;
+    }
+    *W = (w[0] + w[1]) + w[2];
+}
+
+ORC_EXPORT int orc_tri_pick(const float nrm[3], float u)
+{
+    float w[3], W;
+    tri_weights32(nrm, w, &W);
+    return (u >= w[0] / W) + (u >= (w[0] + w[1]) / W);
+}
+
+static void tri_uv(const float *p, int plane, float scale, float *u, float *v)
+{
+    const float a = plane == 0 ? p[1] : p[0];
+    const float b = plane == 2 ? p[1] : p[2];
+    *u = a * scale;
+    *v = b * scale;
+}
+
+/* One stochastic single-texel lookup at (u, v, lambda) with uniforms
+ * (ux, uy, ul): level pick, raster, per-axis pick, fetch, shade. */
+static void stoch_point(const tex2d *t, float u, float v, float lam, int filter, float ux, float uy, float ul,
+                        int shade, const double *ggx, double *val, int32_t *tap3)
+{
+    float uu = wrap_coord(t->wrap, u), vv = wrap_coord(t->wrap, v);
+    int l0, l1;
+    float f;
+    levels_of(t, lam, &l0, &l1, &f);
+    int l = (ul >= 1.0f - f) ? l1 : l0;
+    int wl = lvl_dim(t->w, l), hl = lvl_dim(t->h, l);
+    int ix, iy;
+    float tx, ty;
+    raster(uu, wl, &ix, &tx);
+    raster(vv, hl, &iy, &ty);
+    int first = filter == F_BSPLINE3 ? -1 : 0;
+    int x = wrap_tap(t->wrap, ix + first + orc_pick(filter, tx, ux), wl);
+    int y = wrap_tap(t->wrap, iy + first + orc_pick(filter, ty, uy), hl);
+    if (tap3) {
+        tap3[0] = l;
+        tap3[1] = x;
+        tap3[2] = y;
+    }
+    double texel[4];
+    fetch2d(t, l, x, y, texel);
+    shade2d(shade, ggx, texel, val);
+}
+
+/* queries: n x {p.x, p.y, p.z, n.x, n.y, n.z, lambda, unused}.
+ * plane_mode 0 blends the three planes (weights b in binary64), 1 picks one
+ * plane per sample.  Filter modes: stochastic (per sample, one texel per
+ * plane used), before (shade the blend of the filtered texels), after
+ * (blend of filtered shaded texels).  With plane_mode 1 and a deterministic
+ * filter the result is the mean over spp samples of the picked plane's
+ * deterministic value.  taps (plane_mode 1 only): n x spp x {plane, level,
+ * x, y}, the last three TAP_NONE for a deterministic filter. */
+ORC_EXPORT int orc_triplanar(const void *base, int w, int h, int levels, int fmt, int wrap, int mip,
+                             const int64_t *level_off, const float *dct_range, const float *q, int64_t n,
+                             float scale, int plane_mode, int filter, int mode, int spp, uint32_t seed, int shade,
+                             const double *ggx, double *out, int32_t *taps, const int64_t *subset, int64_t nsub)
+{
+    tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off, dct_range};
+    int ch = shade == 1 ? 3 : 4;
+    int64_t m = subset ? nsub : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t qi = subset ? subset[i] : i;
+        const float *qq = q + 8 * qi;
+        double *o = out + ch * i;
+        int32_t *tp = taps ? taps + (int64_t)4 * spp * i : NULL;
+        int finite = 1;
+        for (int k = 0; k < 7; ++k)
+            finite &= isfinite(qq[k]) != 0;
+        if (!finite) {
+            for (int c = 0; c < ch; ++c)
+                o[c] = NAN;
+            if (tp)
+                for (int k = 0; k < 4 * spp; ++k)
+                    tp[k] = INT32_MIN;
+            continue;
+        }
+        double b[3], B = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double a = (double)qq[3 + k] * (double)qq[3 + k];
+            b[k] = a * a;
+            B += b[k];
+        }
+        for (int k = 0; k < 3; ++k)
+            b[k] /= B;
+        double acc[4] = {0, 0, 0, 0};
+        if (plane_mode == 0 && mode != M_STOCH) {
+            for (int j = 0; j < 3; ++j) {
+                float u, v;
+                tri_uv(qq, j, scale, &u, &v);
+                det_point(&t, u, v, qq[6], filter, 0.5f, mode, shade, ggx, b[j], acc);
+            }
+            if (mode == M_BEFORE)
+                shade2d(shade, ggx, acc, o);
+            else
+                for (int c = 0; c < ch; ++c)
+                    o[c] = acc[c];
+            continue;
+        }
+        for (int s = 0; s < spp; ++s) {
+            uint32_t key[4] = {(uint32_t)qi, (uint32_t)s, 0u, seed}, wd[4];
+            orc_pcg4d(key, wd);
+            float ux = uniform24(wd[0]), uy = uniform24(wd[1]), up = uniform24(wd[2]), ul = uniform24(wd[3]);
+            if (plane_mode == 0) {
+                for (int j = 0; j < 3; ++j) {
+                    float u, v;
+                    double val[4];
+                    tri_uv(qq, j, scale, &u, &v);
+                    stoch_point(&t, u, v, qq[6], filter, ux, uy, ul, shade, ggx, val, NULL);
+                    for (int c = 0; c < ch; ++c)
+                        acc[c] += b[j] * val[c];
+                }
+                continue;
+            }
+            int j = orc_tri_pick(qq + 3, up);
+            float u, v;
+            tri_uv(qq, j, scale, &u, &v);
+            if (tp)
+                tp[4 * s] = j;
+            if (mode == M_STOCH) {
+                double val[4];
+                stoch_point(&t, u, v, qq[6], filter, ux, uy, ul, shade, ggx, val, tp ? tp + 4 * s + 1 : NULL);
+                for (int c = 0; c < ch; ++c)
+                    acc[c] += val[c];
+            } else {
+                double sum[4] = {0, 0, 0, 0}, val[4];
+                det_point(&t, u, v, qq[6], filter, 0.5f, mode, shade, ggx, 1.0, sum);
+                if (mode == M_BEFORE)
+                    shade2d(shade, ggx, sum, val);
+                for (int c = 0; c < ch; ++c)
+                    acc[c] += mode == M_BEFORE ? val[c] : sum[c];
+                if (tp)
+                    tp[4 * s + 1] = tp[4 * s + 2] = tp[4 * s + 3] = INT32_MIN;
+            }
+        }
+        for (int c = 0; c < ch; ++c)
+            o[c] = acc[c] / (double)spp;
     }
     return 0;
 }

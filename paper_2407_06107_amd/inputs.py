@@ -247,6 +247,47 @@ def texture_checker(size: int = 4096, squares: int = 64) -> np.ndarray:
     return tex
 
 
+def sphere_queries(width: int = 1920, height: int = 1080, tex_size: int = 4096, levels: int = 13,
+                   scale: float = 1.0, distance: float = 3.0, vfov_deg: float = 40.0, tile: int = 8) -> np.ndarray:
+    """Triplanar-mapping queries: a unit sphere at the origin seen by a
+    pinhole camera at (0.3, 0.2, distance) looking at the origin.  One query
+    per pixel whose ray hits the sphere, in :func:`tile_order`:
+    ``[n, 8]`` float32 {p.x, p.y, p.z, n.x, n.y, n.z, lambda, 0}, with n = p
+    (unit normal) and lambda = log2 of the pixel's footprint on the surface
+    in level-0 texels (texture scale ``scale`` repeats per world unit),
+    ``tex_size * scale * t * pixel_angle / |n . d|``, clamped to
+    [0, levels-1]; float64 throughout."""
+    eye = np.array([0.3, 0.2, distance])
+    fwd = -eye / np.linalg.norm(eye)
+    right = np.cross(fwd, np.array([0.0, 1.0, 0.0]))
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    th = math.tan(math.radians(vfov_deg) / 2)
+    tw = th * width / height
+    order = tile_order(width, height, tile)
+    px = (order % width).astype(np.float64)
+    py = (order // width).astype(np.float64)
+    sx = (2.0 * (px + 0.5) / width - 1.0) * tw
+    sy = (1.0 - 2.0 * (py + 0.5) / height) * th
+    d = fwd[None] + sx[:, None] * right[None] + sy[:, None] * up[None]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    b = d @ eye
+    disc = b * b - (eye @ eye - 1.0)
+    hit = disc > 0
+    t = -b[hit] - np.sqrt(disc[hit])
+    p = eye[None] + t[:, None] * d[hit]
+    nrm = p / np.linalg.norm(p, axis=1, keepdims=True)
+    cosv = np.abs(np.sum(nrm * d[hit], axis=1))
+    pix = 2.0 * th / height
+    foot = tex_size * scale * t * pix / np.maximum(cosv, 1e-3)
+    lam = np.clip(np.log2(foot), 0.0, levels - 1)
+    q = np.zeros((p.shape[0], 8), dtype=np.float32)
+    q[:, 0:3] = p
+    q[:, 3:6] = nrm
+    q[:, 6] = lam
+    return q
+
+
 # ----------------------------------------------------------------------------
 # 3-D density grids
 # ----------------------------------------------------------------------------
