@@ -100,7 +100,7 @@ enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3, SF_GAUSS_FR
  * SF_AFTER_EXACT: sum_i w_i shade(t_i)        (eq. filtering-after-shading)
  * SF_STOCHASTIC: mean over spp of shade(t_j), P(j) = w_j (eq. stochastic-sum) */
 enum { SF_BEFORE = 0, SF_AFTER_EXACT = 1, SF_STOCHASTIC = 2 };
-enum { SF_RGBA32F = 0, SF_RGBA8_UNORM = 1, SF_R16F = 2, SF_R32F = 3 };
+enum { SF_RGBA32F = 0, SF_RGBA8_UNORM = 1, SF_R16F = 2, SF_R32F = 3, SF_DCT8 = 4 };
 enum { SF_WRAP_REPEAT = 0, SF_WRAP_CLAMP = 1 };
 /* MIP level use (Sec. 2.1 pyramids; single stochastic level, Sec. 4.2.1):
  * NONE = level 0 only; NEAREST = level round(lambda); LINEAR = levels
@@ -132,11 +132,27 @@ typedef struct sf_sampling {
 typedef struct sf_tex2d {
     const void *base;
     int32_t width, height, levels; /* levels in 1..SF_MAX_LEVELS                 */
-    int32_t format;                /* SF_RGBA32F | SF_RGBA8_UNORM                 */
+    int32_t format;                /* SF_RGBA32F | SF_RGBA8_UNORM | SF_DCT8       */
     int32_t wrap;                  /* SF_WRAP_REPEAT | SF_WRAP_CLAMP              */
     int32_t mip;                   /* SF_MIP_NONE | SF_MIP_NEAREST | SF_MIP_LINEAR */
     int64_t level_offset[SF_MAX_LEVELS];
+    const float *dct_range;        /* SF_DCT8: AC range of channel c on level l at
+                                      [4 l + c] (device); NULL otherwise          */
 } sf_tex2d;
+
+/* SF_DCT8 — DCT-compressed texture (Sec. 5 "Texture compression").  Level l
+ * holds ceil(w_l/8) x ceil(h_l/8) blocks of 8x8 texels, row-major, 16 bytes
+ * each: one 32-bit word per channel (R, G, B, A) with the six
+ * lowest-frequency coefficients of the orthonormal 2-D DCT-II of the texel
+ * values v = byte/255, in zigzag order (u horizontal, v vertical frequency)
+ * (0,0), (1,0), (0,1), (0,2), (1,1), (2,0):
+ *   bits 0..6   DC code d, coefficient d * 8/127;
+ *   bits 7..31  five 5-bit AC codes a (0..30), coefficient (a - 15) R/15,
+ *               R = dct_range[4 l + c].
+ * A texel decodes to clamp(sum_k coef_k c_uk(x) c_vk(y), 0, 1) with
+ * c_0 = sqrt(1/8), c_k(x) = cos((2x+1) k pi/16)/2: one block read and 24
+ * multiply-adds, independent of the filter — the decode that stochastic
+ * filtering performs once per sample instead of once per tap. */
 
 /* GGX microfacet specular + Lambert diffuse times the cosine (the paper's
  * BSDF-times-cosine f-hat, Sec. 3) for one directional light of `radiance`.
@@ -234,6 +250,52 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
 sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,
                             int32_t aniso_max, int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps,
                             void *stream);
+
+/*
+ * sf_dct_layout — byte offsets (256-byte aligned, written to level_offset)
+ * of the SF_DCT8 levels of a width x height pyramid with `levels` levels;
+ * returns the total bytes, or -1 for sizes out of range.
+ */
+int64_t sf_dct_layout(int32_t width, int32_t height, int32_t levels, int64_t *level_offset);
+
+/*
+ * sf_dct_encode — compress an SF_RGBA8_UNORM pyramid into SF_DCT8 (the
+ * compressor of Sec. 5 "Texture compression").  dst_base (device,
+ * sf_dct_layout bytes) receives the blocks at dst_level_offset[l];
+ * dst_range (device, 4 x levels floats) the AC ranges R = max |AC| over the
+ * level's blocks per channel.  Codes are decided in binary32: rows
+ * R_u(y) = fma-chain over x = 0..7 of c_u(x) v(x, y) with v = byte/255.0f,
+ * then C = fma-chain over y of c_v(y) R_u(y); c_k(x) the binary32 roundings
+ * of the basis; blocks past the level's edge replicate its edge texels;
+ * d = clamp(floor(C0 * 15.875 + 1/2), 0, 127);
+ * a = R > 0 ? clamp(floor(Ck * (15/R) + 1/2), -15, 15) + 15 : 15.
+ * Errors: SF_E_NULL, SF_E_RANGE (src not RGBA8, levels, misaligned offsets).
+ */
+sf_status sf_dct_encode(const sf_tex2d *src, void *dst_base, const int64_t *dst_level_offset, float *dst_range,
+                        void *stream);
+
+/*
+ * sf_triplanar — triplanar mapping (Sec. 5 "Triplanar mapping").
+ *   queries : n x {p.x, p.y, p.z, n.x, n.y, n.z, lambda, unused} float32
+ *             (32 B): surface point, unit normal, level of detail.
+ *   The three planar projections read the texture at (p.y, p.z), (p.x, p.z)
+ *   and (p.x, p.y) times tex_scale; their blend weights are
+ *   b_i = n_i^4 / sum_j n_j^4.  plane_mode 0 blends all three planes;
+ *   plane_mode 1 picks one plane per sample with probability b_i (a
+ *   stochastic estimate of the blend, eq. stochastic-sum): binary32
+ *   a_i = n_i n_i, w_i = a_i a_i, W = (w0 + w1) + w2,
+ *   plane = [u >= w0/W] + [u >= (w0 + w1)/W], u from word 2 of the sample's
+ *   key.  smp: NEAREST | LINEAR | BSPLINE3, any mode (the filter on a plane
+ *   is as sf_filter2d's, words 0, 1, 3 of the same key); plane_mode 1 with a
+ *   deterministic filter averages spp samples of the picked plane's
+ *   deterministic value.  SF_BEFORE shades the blended filtered texel.
+ *   dbg_taps (plane_mode 1 only): n x spp x {plane, level, x, y} (level, x, y
+ *   SF_TAP_NONE for a deterministic filter).
+ * Errors: as sf_filter2d; SF_E_UNSUPPORTED for other filters or variants.
+ */
+sf_status sf_triplanar(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,
+                       float tex_scale, int32_t plane_mode, int32_t shade, const sf_ggx *ggx, float *out,
+                       int32_t *dbg_taps, void *stream);
 
 /*
  * sf_filter3d — filtered point lookups in a density grid.

@@ -22,7 +22,7 @@ SF_OK, SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED, SF_E_DEVICE, SF_E_WORKSPACE = ra
 SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3, SF_GAUSS_FRS, SF_GAUSS_FIS, SF_BSPLINE3_FIS = 0, 1, 2, 3, 4, 5, 6
 SF_SIGMA_MIN, SF_SIGMA_MAX = 0.0625, 4.0
 SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC = 0, 1, 2
-SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F = 0, 1, 2, 3
+SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F, SF_DCT8 = 0, 1, 2, 3, 4
 SF_WRAP_REPEAT, SF_WRAP_CLAMP = 0, 1
 SF_MIP_NONE, SF_MIP_NEAREST, SF_MIP_LINEAR = 0, 1, 2
 SF_SHADE_NONE, SF_SHADE_GGX = 0, 1
@@ -30,7 +30,8 @@ SF_SHADE_DENSITY, SF_SHADE_TRANSMITTANCE = 0, 1
 SF_TAP_NONE = -(2 ** 31)
 SF_MAX_LEVELS = 16
 
-EXPORTED = ("sf_filter2d", "sf_filter2d_aniso", "sf_filter3d", "sf_raymarch", "sf_build_occupancy",
+EXPORTED = ("sf_filter2d", "sf_filter2d_aniso", "sf_dct_layout", "sf_dct_encode", "sf_triplanar",
+            "sf_filter3d", "sf_raymarch", "sf_build_occupancy",
             "sf_occupancy_words", "sf_mlp_nparams", "sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
             "sf_neural_quantize", "sf_neural_train_step", "sf_neural_train_workspace",
             "sf_error_stats", "sf_error_stats_workspace", "sf_last_error", "sf_abi_version", "sf_rng_version")
@@ -45,7 +46,7 @@ class sf_sampling(C.Structure):
 class sf_tex2d(C.Structure):
     _fields_ = [("base", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32), ("levels", C.c_int32),
                 ("format", C.c_int32), ("wrap", C.c_int32), ("mip", C.c_int32),
-                ("level_offset", C.c_int64 * SF_MAX_LEVELS)]
+                ("level_offset", C.c_int64 * SF_MAX_LEVELS), ("dct_range", C.c_void_p)]
 
 
 class sf_ggx(C.Structure):
@@ -97,6 +98,10 @@ def lib() -> C.CDLL:
         P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.sf_filter2d.argtypes = [P, P, i64, P, i32, P, P, P, P]
         L.sf_filter2d_aniso.argtypes = [P, P, i64, P, i32, i32, P, P, P, P]
+        L.sf_dct_layout.argtypes = [i32, i32, i32, P]
+        L.sf_dct_layout.restype = i64
+        L.sf_dct_encode.argtypes = [P, P, P, P, P]
+        L.sf_triplanar.argtypes = [P, P, i64, P, C.c_float, i32, i32, P, P, P, P]
         L.sf_filter3d.argtypes = [P, P, i64, P, i32, C.c_float, P, P, P]
         L.sf_raymarch.argtypes = [P, P, i64, i32, P, P, P, P]
         L.sf_error_stats.argtypes = [P, P, i64, i32, P, P, C.c_size_t, P]
@@ -119,7 +124,8 @@ def lib() -> C.CDLL:
             getattr(L, f).restype = i32
         L.sf_error_stats_workspace.argtypes = [i64]
         L.sf_error_stats_workspace.restype = C.c_size_t
-        for f in ("sf_filter2d", "sf_filter2d_aniso", "sf_filter3d", "sf_raymarch", "sf_error_stats"):
+        for f in ("sf_filter2d", "sf_filter2d_aniso", "sf_dct_encode", "sf_triplanar", "sf_filter3d", "sf_raymarch",
+                  "sf_error_stats"):
             getattr(L, f).restype = i32
         L.sf_last_error.restype = C.c_char_p
         L.sf_abi_version.restype = i32
@@ -221,6 +227,49 @@ class Texture2D:
             self.desc.level_offset[i] = o
         del align
 
+    @classmethod
+    def dct(cls, src: "Texture2D", stream=None) -> "Texture2D":
+        """Compress an RGBA8 device texture into SF_DCT8 (sf_dct_encode)."""
+        if src.desc.format != SF_RGBA8_UNORM:
+            raise TypeError("the DCT compressor takes an RGBA8 texture")
+        d = src.desc
+        offs = (C.c_int64 * SF_MAX_LEVELS)()
+        nbytes = sf_dct_layout(d.width, d.height, d.levels, offs)
+        dev = src.buffer.device
+        self = cls.__new__(cls)
+        self.buffer = torch.zeros(max(nbytes, 16), dtype=torch.uint8, device=dev)
+        self.ranges = torch.zeros(4 * d.levels, dtype=torch.float32, device=dev)
+        self.offsets = [offs[i] for i in range(d.levels)]
+        self.desc = sf_tex2d()
+        self.desc.base = self.buffer.data_ptr()
+        self.desc.width, self.desc.height, self.desc.levels = d.width, d.height, d.levels
+        self.desc.format, self.desc.wrap, self.desc.mip = SF_DCT8, d.wrap, d.mip
+        for i in range(d.levels):
+            self.desc.level_offset[i] = offs[i]
+        self.desc.dct_range = self.ranges.data_ptr()
+        _check(lib().sf_dct_encode(C.byref(d), _ptr(self.buffer), offs, _ptr(self.ranges), _stream(stream)))
+        self.source = src
+        return self
+
+    def with_sampling(self, wrap: int | None = None, mip: int | None = None) -> "Texture2D":
+        """The same texture memory with another wrap or MIP mode."""
+        t = Texture2D.__new__(Texture2D)
+        t.__dict__.update(self.__dict__)
+        t.desc = sf_tex2d.from_buffer_copy(self.desc)
+        if wrap is not None:
+            t.desc.wrap = wrap
+        if mip is not None:
+            t.desc.mip = mip
+        return t
+
+
+def sf_dct_layout(width: int, height: int, levels: int, level_offset=None) -> int:
+    """Bytes of an SF_DCT8 pyramid; fills ``level_offset`` (c_int64 array)."""
+    n = int(lib().sf_dct_layout(width, height, levels, level_offset))
+    if n < 0:
+        raise ValueError("texture size or level count out of range")
+    return n
+
 
 class Volume:
     """A device density grid [nz, ny, nx] (float16 or float32) over the world
@@ -281,6 +330,26 @@ def sf_filter2d_aniso(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, a
     g = C.byref(ggx_params) if ggx_params is not None else None
     _check(lib().sf_filter2d_aniso(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), aniso_max, shade, g,
                                    _ptr(out), _ptr(dbg_taps), _stream(stream)))
+    return out
+
+
+def sf_triplanar(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, tex_scale: float = 1.0,
+                 plane_mode: int = 1, shade: int = SF_SHADE_NONE, ggx_params: sf_ggx | None = None,
+                 out: torch.Tensor | None = None, dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Triplanar mapping; queries ``[n, 8]`` {p, n, lambda, unused}."""
+    _need(queries, torch.float32, "queries")
+    if queries.numel() % 8:
+        raise ValueError("queries must hold 8 floats per point")
+    n = queries.numel() // 8
+    ch = 3 if shade == SF_SHADE_GGX else 4
+    if out is None:
+        out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
+    _need(out, torch.float32, "out", n * ch)
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * 4)
+    g = C.byref(ggx_params) if ggx_params is not None else None
+    _check(lib().sf_triplanar(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), tex_scale, plane_mode, shade, g,
+                              _ptr(out), _ptr(dbg_taps), _stream(stream)))
     return out
 
 

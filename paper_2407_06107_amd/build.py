@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsf.so")
 
-SOURCES = ["abi.hip", "filter2d.hip", "aniso.hip", "volume.hip", "neural.hip", "reduce.hip"]
+SOURCES = ["abi.hip", "filter2d.hip", "aniso.hip", "dct.hip", "triplanar.hip", "volume.hip", "neural.hip",
+           "reduce.hip"]
 ARCH = "gfx950"
 
 CFLAGS = [

@@ -162,8 +162,11 @@ static sf_status check_tex2d(const sf_tex2d *tex)
 {
     if (!tex->base)
         return fail(SF_E_NULL, "texture base pointer is NULL");
-    if (tex->format != SF_RGBA32F && tex->format != SF_RGBA8_UNORM)
-        return fail(SF_E_UNSUPPORTED, "2-D texture format %d unsupported (RGBA32F or RGBA8_UNORM)", tex->format);
+    if (tex->format != SF_RGBA32F && tex->format != SF_RGBA8_UNORM && tex->format != SF_DCT8)
+        return fail(SF_E_UNSUPPORTED, "2-D texture format %d unsupported (RGBA32F, RGBA8_UNORM or DCT8)",
+                    tex->format);
+    if (tex->format == SF_DCT8 && (!tex->dct_range || !aligned(tex->dct_range, 16)))
+        return fail(tex->dct_range ? SF_E_RANGE : SF_E_NULL, "a DCT8 texture needs 16-byte aligned dct_range");
     if (tex->width < 1 || tex->height < 1 || tex->width > 65536 || tex->height > 65536)
         return fail(SF_E_RANGE, "texture size %d x %d outside 1..65536", tex->width, tex->height);
     int maxlv = 1;
@@ -175,7 +178,7 @@ static sf_status check_tex2d(const sf_tex2d *tex)
         return fail(SF_E_RANGE, "wrap %d out of range", tex->wrap);
     if (tex->mip < SF_MIP_NONE || tex->mip > SF_MIP_LINEAR)
         return fail(SF_E_RANGE, "mip %d out of range", tex->mip);
-    const size_t esz = tex->format == SF_RGBA32F ? 16 : 4;
+    const size_t esz = tex->format == SF_RGBA8_UNORM ? 4 : 16;
     for (int l = 0; l < tex->levels; ++l)
         if (tex->level_offset[l] < 0 || !aligned((const uint8_t *)tex->base + tex->level_offset[l], esz))
             return fail(SF_E_RANGE, "level %d offset negative or misaligned", l);
@@ -193,7 +196,10 @@ static void tex_args(const sf_tex2d *tex, sfk::Tex2DArgs &a)
     a.mip = tex->mip;
     for (int l = 0; l < SF_MAX_LEVELS; ++l)
         a.off[l] = l < tex->levels ? tex->level_offset[l] : 0;
+    a.dct_range = tex->format == SF_DCT8 ? tex->dct_range : nullptr;
 }
+
+static int level_dim(int n, int l) { return (n >> l) > 0 ? (n >> l) : 1; }
 
 sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp, int32_t shade,
                       const sf_ggx *ggx, float *out, int32_t *dbg_taps, void *stream)
@@ -292,6 +298,99 @@ sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n
     c.out = out;
     c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
     return device_status(sfk::launch_aniso(c, (hipStream_t)stream));
+}
+
+int64_t sf_dct_layout(int32_t width, int32_t height, int32_t levels, int64_t *level_offset)
+{
+    if (width < 1 || height < 1 || width > 65536 || height > 65536 || levels < 1 || levels > SF_MAX_LEVELS)
+        return -1;
+    int64_t pos = 0;
+    for (int l = 0; l < levels; ++l) {
+        pos = (pos + 255) & ~(int64_t)255;
+        if (level_offset)
+            level_offset[l] = pos;
+        const int64_t bw = (level_dim(width, l) + 7) / 8, bh = (level_dim(height, l) + 7) / 8;
+        pos += 16 * bw * bh;
+    }
+    return pos;
+}
+
+sf_status sf_dct_encode(const sf_tex2d *src, void *dst_base, const int64_t *dst_level_offset, float *dst_range,
+                        void *stream)
+{
+    sf_status st;
+    if (!src || !dst_base || !dst_level_offset || !dst_range)
+        return fail(SF_E_NULL, "src, dst_base, dst_level_offset and dst_range must be non-NULL");
+    if ((st = check_tex2d(src)) != SF_OK)
+        return st;
+    if (src->format != SF_RGBA8_UNORM)
+        return fail(SF_E_RANGE, "the DCT compressor takes an RGBA8_UNORM pyramid");
+    if (!aligned(dst_range, 16))
+        return fail(SF_E_RANGE, "dst_range must be 16-byte aligned");
+    sfk::DctEncodeCall c{};
+    c.src = (const uint8_t *)src->base;
+    c.dst = (uint8_t *)dst_base;
+    c.range = dst_range;
+    c.w = src->width;
+    c.h = src->height;
+    c.levels = src->levels;
+    c.first_block[0] = 0;
+    for (int l = 0; l < src->levels; ++l) {
+        if (dst_level_offset[l] < 0 || !aligned((const uint8_t *)dst_base + dst_level_offset[l], 16))
+            return fail(SF_E_RANGE, "dst level %d offset negative or misaligned", l);
+        c.src_off[l] = src->level_offset[l];
+        c.dst_off[l] = dst_level_offset[l];
+        const int64_t bw = (level_dim(c.w, l) + 7) / 8, bh = (level_dim(c.h, l) + 7) / 8;
+        c.first_block[l + 1] = c.first_block[l] + bw * bh;
+    }
+    return device_status(sfk::launch_dct_encode(c, (hipStream_t)stream));
+}
+
+sf_status sf_triplanar(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp, float tex_scale,
+                       int32_t plane_mode, int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps,
+                       void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (n == 0)
+        return ok();
+    if (!tex || !queries || !out)
+        return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    if (smp->filter > SF_BSPLINE3 || smp->rng_variant != 0)
+        return fail(SF_E_UNSUPPORTED, "triplanar mapping takes NEAREST, LINEAR or BSPLINE3 with rng_variant 0");
+    if (plane_mode != 0 && plane_mode != 1)
+        return fail(SF_E_RANGE, "plane_mode %d must be 0 (blend) or 1 (pick one plane)", plane_mode);
+    if (!(tex_scale > 0.0f) || !(tex_scale < 1e30f))
+        return fail(SF_E_RANGE, "tex_scale must be positive and finite");
+    if ((st = check_tex2d(tex)) != SF_OK)
+        return st;
+    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
+        return fail(SF_E_RANGE, "shade %d out of range", shade);
+    if (!aligned(queries, 16) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))
+        return fail(SF_E_RANGE, "queries (16 B) or out misaligned");
+    sfk::TriplanarCall c{};
+    if (shade == SF_SHADE_GGX) {
+        if (!ggx)
+            return fail(SF_E_NULL, "GGX shading needs ggx parameters");
+        if ((st = ggx_constants(ggx, c.g)) != SF_OK)
+            return st;
+    }
+    tex_args(tex, c.tex);
+    c.q = queries;
+    c.n = n;
+    c.filter = smp->filter;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.seed = smp->seed;
+    c.scale = tex_scale;
+    c.plane_mode = plane_mode;
+    c.shade = shade;
+    c.out = out;
+    c.taps = plane_mode == 1 ? dbg_taps : nullptr;
+    return device_status(sfk::launch_triplanar(c, (hipStream_t)stream));
 }
 
 sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const sf_sampling *smp, int32_t shade,

@@ -22,6 +22,7 @@ struct Tex2DArgs {
     const uint8_t *base;
     int32_t w, h, levels, fmt, wrap, mip;
     int64_t off[SF_MAX_LEVELS];
+    const float *dct_range;  // SF_DCT8 only
 };
 
 struct VolArgs {
@@ -53,6 +54,28 @@ struct AnisoCall {
     int32_t filter, mode, spp, shade, amax;
     uint32_t seed;
     float sigma;
+    GgxConst g;
+    float *out;
+    int32_t *taps;
+};
+
+struct DctEncodeCall {
+    const uint8_t *src;
+    int64_t src_off[SF_MAX_LEVELS];
+    uint8_t *dst;
+    int64_t dst_off[SF_MAX_LEVELS];
+    float *range;
+    int32_t w, h, levels;
+    int64_t first_block[SF_MAX_LEVELS + 1];  // prefix sums of the levels' block counts
+};
+
+struct TriplanarCall {
+    Tex2DArgs tex;
+    const float *q;  // n x {p, n, lambda, unused}
+    int64_t n;
+    int32_t filter, mode, spp, shade, plane_mode;
+    uint32_t seed;
+    float scale;
     GgxConst g;
     float *out;
     int32_t *taps;
@@ -125,6 +148,8 @@ struct TrainCall {
 // Launchers return hipSuccess or the launch error; arguments are validated.
 hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s);
 hipError_t launch_aniso(const AnisoCall &c, hipStream_t s);
+hipError_t launch_dct_encode(const DctEncodeCall &c, hipStream_t s);
+hipError_t launch_triplanar(const TriplanarCall &c, hipStream_t s);
 hipError_t launch_filter3d(const Filter3DCall &c, hipStream_t s);
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s);
 hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ, int64_t words, hipStream_t s);

@@ -65,11 +65,53 @@ __device__ __forceinline__ void levels_of(const Tex2DArgs &tx, float lam, int &l
     f = fr;
 }
 
+// DCT basis c_k(x) = alpha(k) cos((2x+1) k pi / 16) for k = 1, 2 from the
+// symmetries of the cosine: |c_1| takes four values mirrored about x = 3.5
+// with the sign of x < 4; |c_2| is a for x in {0, 3, 4, 7} and b otherwise,
+// negative for x in 2..5.
+__device__ __forceinline__ float dct_c1(int x)
+{
+    const int m = min(x, 7 - x);
+    const float v = m == 0 ? 0.49039262533187866f
+                           : (m == 1 ? 0.41573479771614075f : (m == 2 ? 0.27778512239456177f : 0.09754516184329987f));
+    return x < 4 ? v : -v;
+}
+
+__device__ __forceinline__ float dct_c2(int x)
+{
+    const float v = ((x + 1) >> 1) & 1 ? 0.19134171307086945f : 0.4619397521018982f;
+    return ((x + 2) >> 2) & 1 ? -v : v;
+}
+
+constexpr float DCT_C0 = 0.3535533845424652f;
+
+// One channel of a DCT block word at block position (x, y).
+__device__ __forceinline__ float dct_channel(uint32_t wd, float R, float c1x, float c2x, float c1y, float c2y)
+{
+    const float q = R * (1.0f / 15.0f);
+    float v = (float)(wd & 127u) * ((8.0f / 127.0f) * (DCT_C0 * DCT_C0));
+    v = __builtin_fmaf((float)((int)((wd >> 7) & 31u) - 15) * q, c1x * DCT_C0, v);    // (1,0)
+    v = __builtin_fmaf((float)((int)((wd >> 12) & 31u) - 15) * q, DCT_C0 * c1y, v);   // (0,1)
+    v = __builtin_fmaf((float)((int)((wd >> 17) & 31u) - 15) * q, DCT_C0 * c2y, v);   // (0,2)
+    v = __builtin_fmaf((float)((int)((wd >> 22) & 31u) - 15) * q, c1x * c1y, v);      // (1,1)
+    v = __builtin_fmaf((float)((int)(wd >> 27) - 15) * q, c2x * DCT_C0, v);           // (2,0)
+    return __builtin_fminf(__builtin_fmaxf(v, 0.0f), 1.0f);
+}
+
 __device__ __forceinline__ float4 texel(const Tex2DArgs &tx, int l, int x, int y)
 {
     int wl = max(1, tx.w >> l);
     int64_t idx = (int64_t)y * wl + x;
     const uint8_t *lv = tx.base + tx.off[l];
+    if (tx.fmt == SF_DCT8) {
+        const int bw = (wl + 7) >> 3;
+        const uint4 b = reinterpret_cast<const uint4 *>(lv)[(int64_t)(y >> 3) * bw + (x >> 3)];
+        const float4 R = reinterpret_cast<const float4 *>(tx.dct_range)[l];
+        const int xi = x & 7, yi = y & 7;
+        const float c1x = dct_c1(xi), c2x = dct_c2(xi), c1y = dct_c1(yi), c2y = dct_c2(yi);
+        return make_float4(dct_channel(b.x, R.x, c1x, c2x, c1y, c2y), dct_channel(b.y, R.y, c1x, c2x, c1y, c2y),
+                           dct_channel(b.z, R.z, c1x, c2x, c1y, c2y), dct_channel(b.w, R.w, c1x, c2x, c1y, c2y));
+    }
     if (tx.fmt == SF_RGBA32F)
         return reinterpret_cast<const float4 *>(lv)[idx];
     uint32_t px = reinterpret_cast<const uint32_t *>(lv)[idx];

@@ -238,6 +238,62 @@ def test_filter2d_aniso_validation(sf, case, status):
     assert st == status, sf.sf_last_error()
 
 
+def test_dct_layout_and_validation(sf):
+    L = sf.lib()
+    offs = (C.c_int64 * 16)()
+    assert sf.sf_dct_layout(4096, 4096, 13, offs) == 5593360            # 16x below the RGBA8 pyramid
+    assert [offs[i] % 256 for i in range(13)] == [0] * 13
+    assert sf.sf_dct_layout(60, 44, 1) == 8 * 6 * 16
+    assert L.sf_dct_layout(0, 4, 1, None) == -1 and L.sf_dct_layout(8, 8, 17, None) == -1
+    tex = sf.sf_tex2d()
+    tex.base, tex.width, tex.height, tex.levels = 0x10000, 64, 64, 1
+    tex.format, tex.wrap, tex.mip = sf.SF_RGBA32F, 0, 0
+    rng = C.c_void_p(0x20000)
+    assert L.sf_dct_encode(C.byref(tex), FAKE, offs, rng, None) == 2          # not RGBA8
+    tex.format = sf.SF_RGBA8_UNORM
+    assert L.sf_dct_encode(None, FAKE, offs, rng, None) == 1
+    assert L.sf_dct_encode(C.byref(tex), FAKE, offs, C.c_void_p(0x20004), None) == 2   # misaligned ranges
+    # a DCT texture needs its ranges
+    tex.format = sf.SF_DCT8
+    smp = sf.sampling(sf.SF_LINEAR, sf.SF_STOCHASTIC, 1)
+    assert L.sf_filter2d(C.byref(tex), FAKE, 4, C.byref(smp), 0, None, FAKE, None, None) == 1
+    tex.dct_range = 0x20008
+    assert L.sf_filter2d(C.byref(tex), FAKE, 4, C.byref(smp), 0, None, FAKE, None, None) == 2
+
+
+@pytest.mark.parametrize("case, status", [
+    ("ok_zero", 0), ("null_q", 1), ("gauss", 3), ("reuse", 3), ("plane_mode", 2), ("scale0", 2), ("scale_nan", 2),
+    ("misaligned_q", 2), ("bad_shade", 2),
+])
+def test_triplanar_validation(sf, case, status):
+    L = sf.lib()
+    smp = sf.sampling(sf.SF_LINEAR, sf.SF_STOCHASTIC, 4)
+    tex = sf.sf_tex2d()
+    tex.base, tex.width, tex.height, tex.levels = 0x10000, 64, 64, 1
+    tex.format, tex.wrap, tex.mip = sf.SF_RGBA8_UNORM, 0, 0
+    n, q, pm, scale, shade = 10, FAKE, 1, 1.0, 0
+    if case == "ok_zero":
+        n = 0
+    elif case == "null_q":
+        q = None
+    elif case == "gauss":
+        smp = sf.sampling(sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 4)
+    elif case == "reuse":
+        smp = sf.sampling(sf.SF_LINEAR, sf.SF_STOCHASTIC, 4, rng_variant=1)
+    elif case == "plane_mode":
+        pm = 2
+    elif case == "scale0":
+        scale = 0.0
+    elif case == "scale_nan":
+        scale = float("nan")
+    elif case == "misaligned_q":
+        q = C.c_void_p(0x10008)
+    elif case == "bad_shade":
+        shade = 2
+    st = L.sf_triplanar(C.byref(tex), q, n, C.byref(smp), scale, pm, shade, None, FAKE, None, None)
+    assert st == status, sf.sf_last_error()
+
+
 def test_filter3d_validation(sf):
     L = sf.lib()
     smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)

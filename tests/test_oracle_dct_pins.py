@@ -86,8 +86,8 @@ def test_decode_is_the_truncated_inverse_dct(orc):
 
 
 def test_constant_and_quantisation_error(orc):
-    """A constant texture decodes to the constant within half a DC step; a
-    smooth texture stays within the 6-coefficient approximation error."""
+    """A constant texture decodes to the constant within half a DC step,
+    with zero AC range."""
     lv = np.full((24, 32, 4), 77, np.uint8)
     tex = orc.Tex2D.dct([lv])
     q = inputs.queries_uniform(200, seed=1)

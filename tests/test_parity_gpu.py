@@ -531,6 +531,88 @@ def test_filter2d_aniso_checker_full_sampled(sf, orc, checker_full, filt, mode, 
     _close(out[sub], ref)
 
 
+# ------------------------------------------------------------------ DCT-compressed textures, triplanar
+@pytest.fixture(scope="module")
+def dct_pair(orc, sf):
+    """An RGBA8 pyramid whose sizes are not multiples of 8 (edge blocks),
+    compressed by the oracle and by the GPU."""
+    full = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_sinusoids(256, seed=9, waves=12)))
+    lv = [np.ascontiguousarray(f[:max(1, 200 >> l), :max(1, 232 >> l)]) for l, f in enumerate(full[:8])]
+    ot = orc.Tex2D.dct(lv, wrap=orc.REPEAT, mip=orc.MIP_LINEAR)
+    gt = sf.Texture2D.dct(sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR))
+    torch.cuda.synchronize()
+    return lv, ot, gt
+
+
+def test_dct_encoder_codes_bit_exact(sf, orc, dct_pair):
+    """The GPU compressor's blocks and AC ranges equal the oracle's bit for bit."""
+    _print_case("dct_encode")
+    lv, ot, gt = dct_pair
+    assert list(gt.offsets) == list(ot.off[:len(lv)])
+    gbuf = gt.buffer.cpu().numpy()
+    for l in range(len(lv)):
+        hl, wl = lv[l].shape[:2]
+        nbytes = 16 * (-(-wl // 8)) * (-(-hl // 8))
+        o = gt.offsets[l]
+        assert np.array_equal(gbuf[o:o + nbytes], ot.buf[o:o + nbytes]), l
+    assert np.array_equal(gt.ranges.cpu().numpy(), ot.dct_range)
+
+
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("mode, spp", [("STOCH", 4), ("BEFORE", 1), ("AFTER", 1)])
+def test_dct_filtering_parity(sf, orc, dct_pair, filt, mode, spp):
+    _print_case("dct_filter", filt, mode, spp)
+    lv, ot, gt = dct_pair
+    q = inputs.plane_queries(96, 64, tex_size=232, levels=len(lv))
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=13)
+    taps_d = torch.empty((q.shape[0], spp, 3), dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d(ot, q, getattr(orc, filt), m, spp=spp, seed=13, shade=1, taps=m == orc.STOCHASTIC)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.fixture(scope="module")
+def tri_small(orc, sf):
+    lv = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_sinusoids(128, seed=10, waves=10)))
+    q = inputs.sphere_queries(120, 80, tex_size=128, levels=len(lv))
+    q[3, 0] = np.nan
+    q[4, 3:6] = [1.0, 0.0, 0.0]                      # axis-aligned normal: one plane only
+    buf, offs = inputs.pack_levels(lv)
+    plain = (orc.Tex2D(buf, 128, 128, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR),
+             sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR))
+    dct = (orc.Tex2D.dct(lv, wrap=orc.REPEAT, mip=orc.MIP_LINEAR), sf.Texture2D.dct(plain[1]))
+    return q, {"rgba8": plain, "dct": dct}
+
+
+@pytest.mark.parametrize("texkind", ["rgba8", "dct"])
+@pytest.mark.parametrize("filt", ["LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("plane_mode, mode, spp", [(1, "STOCH", 4), (1, "STOCH", 1), (1, "AFTER", 3), (1, "BEFORE", 2),
+                                                   (0, "STOCH", 2), (0, "BEFORE", 1), (0, "AFTER", 1)])
+def test_triplanar_parity(sf, orc, tri_small, texkind, filt, plane_mode, mode, spp):
+    _print_case("triplanar", texkind, filt, plane_mode, mode, spp)
+    q, texs = tri_small
+    ot, gt = texs[texkind]
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=21)
+    want_taps = plane_mode == 1
+    taps_d = torch.empty((q.shape[0], spp, 4), dtype=torch.int32, device="cuda") if want_taps else None
+    out = sf.sf_triplanar(gt, torch.from_numpy(q).cuda(), smp, 1.5, plane_mode, shade=1, ggx_params=sf.ggx(),
+                          dbg_taps=taps_d)
+    res = orc.triplanar(ot, q, 1.5, plane_mode, getattr(orc, filt), m, spp=spp, seed=21, shade=1, taps=want_taps)
+    if want_taps:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
 # ------------------------------------------------------------------ 3-D points
 @pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("mode, spp, variant", [("STOCH", 4, 0), ("STOCH", 3, 1), ("BEFORE", 1, 0), ("AFTER", 1, 0)])
