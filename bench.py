@@ -323,7 +323,8 @@ def texture_bench(args, res):
     c2["cpu_oracle_bicubic_stochastic_16spp"] = {"queries_per_s": sub.size / dt, "cores": oracle.num_threads(),
                                                  "sample": f"{sub.size} queries, {dt:.2f} s"}
     res["config2"] = c2
-    del tex2, tex2n, qd2
+    qd2b = qd2
+    del tex2, tex2n
     # ---- config 2, anisotropic: checkerboard plane, footprint-driven levels
     log("config 2 anisotropic: checkerboard")
     lvc = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_checker(4096, 64)))
@@ -360,6 +361,46 @@ def texture_bench(args, res):
     ca["isotropic_trilinear_before"] = {"ms": t, "queries_per_s": na / (t * 1e-3),
                                         "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
     res["config2_aniso"] = ca
+    del texc, qad, qid
+    # ---- DCT-compressed pyramid (the config 2 texture) and triplanar mapping
+    log("DCT texture and triplanar mapping")
+    src8 = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    texd = sf.Texture2D.dct(src8)
+    t_enc = time_launches(lambda: sf.Texture2D.dct(src8), 3, 1, torch)
+    otd = oracle.Tex2D.dct(lv, wrap=oracle.REPEAT, mip=oracle.MIP_LINEAR)
+    cd = {"compressed_bytes": int(texd.buffer.numel()), "rgba8_bytes": int(buf.size), "encode_ms": t_enc,
+          "codes_equal_oracle": bool(np.array_equal(texd.buffer.cpu().numpy()[:otd.buf.size], otd.buf))}
+    judged = oracle.filter2d(otd, q2, oracle.LINEAR, oracle.BEFORE, shade=1, subset=sub)
+    for name, filt, mode in (("dct_trilinear_before_8decodes", sf.SF_LINEAR, sf.SF_BEFORE),
+                             ("dct_trilinear_stochastic_1spp", sf.SF_LINEAR, sf.SF_STOCHASTIC),
+                             ("dct_bicubic_after_32decodes", sf.SF_BSPLINE3, sf.SF_AFTER_EXACT),
+                             ("dct_bicubic_stochastic_1spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC)):
+        smp = sf.sampling(filt, mode, 1, seed=5)
+        o = torch.empty((n2, 3), dtype=torch.float32, device="cuda")
+        t = time_launches(lambda: sf.sf_filter2d(texd, qd2b, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
+        cd[name] = {"ms": t, "queries_per_s": n2 / (t * 1e-3),
+                    "rmse_vs_oracle_dct_trilinear_before": _rmse(o.cpu().numpy()[sub], judged)}
+    cd["stochastic_trilinear_speedup"] = (cd["dct_trilinear_before_8decodes"]["ms"] /
+                                          cd["dct_trilinear_stochastic_1spp"]["ms"])
+    qs = inputs.sphere_queries(1920, 1080, tex_size=4096, levels=len(lv))
+    qsd = torch.from_numpy(qs).cuda()
+    ns = qs.shape[0]
+    subs = np.sort(rng.choice(ns, 5000, replace=False))
+    judget = oracle.triplanar(otd, qs, 1.0, 0, oracle.LINEAR, oracle.BEFORE, shade=1, subset=subs)
+    ct = {"queries": ns}
+    for name, pm, mode in (("blend_trilinear_before_24decodes", 0, sf.SF_BEFORE),
+                           ("blend_trilinear_stochastic_3decodes", 0, sf.SF_STOCHASTIC),
+                           ("pick_trilinear_before_8decodes", 1, sf.SF_BEFORE),
+                           ("pick_trilinear_stochastic_1decode", 1, sf.SF_STOCHASTIC)):
+        smp = sf.sampling(sf.SF_LINEAR, mode, 1, seed=5)
+        o = torch.empty((ns, 3), dtype=torch.float32, device="cuda")
+        t = time_launches(lambda: sf.sf_triplanar(texd, qsd, smp, 1.0, pm, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
+        ct[name] = {"ms": t, "queries_per_s": ns / (t * 1e-3),
+                    "rmse_vs_oracle_blend_trilinear_before": _rmse(o.cpu().numpy()[subs], judget)}
+    ct["fully_stochastic_speedup"] = (ct["blend_trilinear_before_24decodes"]["ms"] /
+                                      ct["pick_trilinear_stochastic_1decode"]["ms"])
+    cd["triplanar_sphere_1920x1080"] = ct
+    res["dct_triplanar"] = cd
 
 
 def neural_bench(args):
