@@ -244,6 +244,8 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
  *     probes at offsets (k + 1/2)/N - 1/2 of the major-axis derivative, each
  *     filtered on levels floor(lambda), floor(lambda)+1 (weights 1-f, f),
  *     averaged; before shades the average, after averages shaded texels.
+ * Queries with a non-finite value, or whose extreme jittered coordinate
+ * |u| + |du/dx| + |du/dy| (or the same for v) overflows binary32, give NaN.
  * Errors: as sf_filter2d; SF_E_UNSUPPORTED for other filters or variants;
  *         SF_E_RANGE for aniso_max or sigma out of range.
  */
@@ -291,6 +293,8 @@ sf_status sf_dct_encode(const sf_tex2d *src, void *dst_base, const int64_t *dst_
  *   deterministic value.  SF_BEFORE shades the blended filtered texel.
  *   dbg_taps (plane_mode 1 only): n x spp x {plane, level, x, y} (level, x, y
  *   SF_TAP_NONE for a deterministic filter).
+ *   Queries with a non-finite value or a projected coordinate p_k tex_scale
+ *   that overflows binary32 give NaN.
  * Errors: as sf_filter2d; SF_E_UNSUPPORTED for other filters or variants.
  */
 sf_status sf_triplanar(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,

@@ -1166,7 +1166,7 @@ ORC_EXPORT float orc_aniso_lod(int W, int H, const float d[4], int amax, int *ma
     int np;
     if (lmin > 0.0f) {
         float r = ceilf(lmax / lmin);
-        np = r < 1.0f ? 1 : (r > A ? amax : (int)r);
+        np = r < 1.0f ? 1 : (!(r <= A) ? amax : (int)r);
     } else {
         np = lmax > 0.0f ? amax : 1;
     }
@@ -1174,12 +1174,16 @@ ORC_EXPORT float orc_aniso_lod(int W, int H, const float d[4], int amax, int *ma
     return orc_log2c(lmin);
 }
 
+/* A query is usable when its six values are finite and so are the extreme
+ * jittered coordinates |u| + |du/dx| + |du/dy| (and for v) in binary32. */
 static int aniso_query_finite(const float *q)
 {
     for (int k = 0; k < 6; ++k)
         if (!isfinite(q[k]))
             return 0;
-    return 1;
+    float eu = (fabsf(q[0]) + fabsf(q[2])) + fabsf(q[4]);
+    float ev = (fabsf(q[1]) + fabsf(q[3])) + fabsf(q[5]);
+    return isfinite(eu) && isfinite(ev);
 }
 
 /* Deterministic filter of one point at the level pair of lambda
@@ -1455,6 +1459,8 @@ ORC_EXPORT int orc_triplanar(const void *base, int w, int h, int levels, int fmt
         int finite = 1;
         for (int k = 0; k < 7; ++k)
             finite &= isfinite(qq[k]) != 0;
+        for (int k = 0; k < 3; ++k)
+            finite &= isfinite(qq[k] * scale) != 0;     /* projected coordinates */
         if (!finite) {
             for (int c = 0; c < ch; ++c)
                 o[c] = NAN;

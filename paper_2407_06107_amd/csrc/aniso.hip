@@ -44,7 +44,7 @@ __device__ __forceinline__ AnisoLod aniso_lod(int W, int H, float d0, float d1, 
     r.major_y = !swap;
     if (lmin > 0.0f) {
         const float k = __builtin_ceilf(lmax / lmin);
-        r.nprobe = k < 1.0f ? 1 : (k > A ? amax : (int)k);
+        r.nprobe = k < 1.0f ? 1 : (!(k <= A) ? amax : (int)k);
     } else {
         r.nprobe = lmax > 0.0f ? amax : 1;
     }
@@ -52,13 +52,17 @@ __device__ __forceinline__ AnisoLod aniso_lod(int W, int H, float d0, float d1, 
     return r;
 }
 
+// Usable query: six finite values, and finite extreme jittered coordinates
+// |u| + |du/dx| + |du/dy| (and for v).
 __device__ __forceinline__ bool aniso_finite(const float *q)
 {
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         ok &= __builtin_isfinite(q[k]);
-    return ok;
+    const float eu = (__builtin_fabsf(q[0]) + __builtin_fabsf(q[2])) + __builtin_fabsf(q[4]);
+    const float ev = (__builtin_fabsf(q[1]) + __builtin_fabsf(q[3])) + __builtin_fabsf(q[5]);
+    return ok & __builtin_isfinite(eu) & __builtin_isfinite(ev);
 }
 
 template <int F, int SHADE>

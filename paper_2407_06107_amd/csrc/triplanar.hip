@@ -90,12 +90,17 @@ __device__ __forceinline__ void det_point(const TriplanarCall &c, float u, float
     }
 }
 
-__device__ __forceinline__ bool tri_finite(const float *q)
+// Usable query: finite point, normal and lambda, and finite projected
+// coordinates p_k * scale.
+__device__ __forceinline__ bool tri_finite(const float *q, float scale)
 {
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 7; ++k)
         ok &= __builtin_isfinite(q[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        ok &= __builtin_isfinite(q[k] * scale);
     return ok;
 }
 
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(256) void k_tri_sampled(TriplanarCall c, int log_g)
         const float4 a0 = reinterpret_cast<const float4 *>(c.q)[2 * q];
         const float4 a1 = reinterpret_cast<const float4 *>(c.q)[2 * q + 1];
         qq[0] = a0.x, qq[1] = a0.y, qq[2] = a0.z, qq[3] = a0.w, qq[4] = a1.x, qq[5] = a1.y, qq[6] = a1.z;
-        if (!tri_finite(qq)) {
+        if (!tri_finite(qq, c.scale)) {
             const float nan = __builtin_nanf("");
             acc = make_float4(nan, nan, nan, nan);
             if (c.taps)
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(256) void k_tri_det(TriplanarCall c)
     const float4 a0 = reinterpret_cast<const float4 *>(c.q)[2 * q];
     const float4 a1 = reinterpret_cast<const float4 *>(c.q)[2 * q + 1];
     qq[0] = a0.x, qq[1] = a0.y, qq[2] = a0.z, qq[3] = a0.w, qq[4] = a1.x, qq[5] = a1.y, qq[6] = a1.z;
-    if (!tri_finite(qq)) {
+    if (!tri_finite(qq, c.scale)) {
         const float nan = __builtin_nanf("");
         store<SHADE>(c.out, q, make_float4(nan, nan, nan, nan));
         return;
