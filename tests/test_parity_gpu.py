@@ -477,6 +477,7 @@ def aniso_small(orc):
     q[5, 2:] = 0.0                                 # zero footprint: level 0, no jitter
     q[6, 0] = np.inf                               # non-finite -> NaN
     q[7, 2:] = [3e-3, 0.0, 0.0, 1e-7]              # anisotropy far beyond the limit
+    q[8, 2:] = [3e38, 0.0, 3e38, 0.0]              # jittered coordinates overflow -> NaN
     return lv, q
 
 
@@ -583,6 +584,7 @@ def tri_small(orc, sf):
     q = inputs.sphere_queries(120, 80, tex_size=128, levels=len(lv))
     q[3, 0] = np.nan
     q[4, 3:6] = [1.0, 0.0, 0.0]                      # axis-aligned normal: one plane only
+    q[5, 0] = 3e38                                   # projected coordinate overflows -> NaN
     buf, offs = inputs.pack_levels(lv)
     plain = (orc.Tex2D(buf, 128, 128, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR),
              sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR))
