@@ -38,9 +38,11 @@ HBM_PEAK_GBS = 8000.0
 # tera lane-operations per second (an FMA counts as one operation).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Lane operations per ray step of the stochastic tricubic decision contract
-# plus its gather and accumulation (itemised in the design doc): position (13),
-# then hash, uniforms, thresholds, picks, address and accumulation (88).
-OPS_POSITION, OPS_OCCUPIED = 13, 88
+# plus its gather and accumulation: position (13), then hash (10), uniform
+# lattice indices (6: shift and convert per axis; the 2^-24 scale is folded
+# into the thresholds), thresholds (33), picks (21), address (12) and
+# accumulation (3).
+OPS_POSITION, OPS_OCCUPIED = 13, 85
 BRICK_LOG2 = 3
 
 

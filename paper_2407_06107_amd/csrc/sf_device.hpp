@@ -100,6 +100,30 @@ __device__ __forceinline__ Thr3 bspline_thresholds(float t)
     return c;
 }
 
+// The cubic B-spline thresholds times 2^24.  Every operand of the binary32
+// contract is scaled by a power of two, so each rounded result is exactly
+// 2^24 times the unscaled one, and [u >= C] == [(float)(w >> 8) >= 2^24 C]
+// for u = (w >> 8) 2^-24: the same decisions without converting the word
+// into [0, 1).
+__device__ __forceinline__ Thr3 bspline_thresholds_2p24(float t)
+{
+    const float k6 = (1.0f / 6.0f) * 16777216.0f, k23 = (2.0f / 3.0f) * 16777216.0f;
+    const float s = 1.0f - t;
+    const float t2 = t * t;
+    const float w0 = ((s * s) * s) * k6;
+    const float half = __builtin_fmaf(-8388608.0f, t, 16777216.0f);
+    const float w1 = __builtin_fmaf(-t2, half, k23);
+    const float w3 = (t2 * t) * k6;
+    Thr3 c;
+    c.c0 = w0;
+    c.c1 = w0 + w1;
+    c.c2 = 16777216.0f - w3;
+    return c;
+}
+
+// The word's 24-bit lattice index as a float (exact).
+__device__ __forceinline__ float u24i(uint32_t w) { return (float)(w >> 8); }
+
 // Tap offset relative to i0 picked by uniform u (ties advance).
 template <int F>
 __device__ __forceinline__ int pick_off(float t, float u)
@@ -109,6 +133,21 @@ __device__ __forceinline__ int pick_off(float t, float u)
         return -1 + (u >= c.c0) + (u >= c.c1) + (u >= c.c2);
     } else if constexpr (F == LINEAR) {
         return (u >= 1.0f - t) ? 1 : 0;
+    } else {
+        return (t >= 0.5f) ? 1 : 0;
+    }
+}
+
+// pick_off on the lattice index ui = w >> 8 of the uniform's word, against
+// thresholds scaled by 2^24 (identical decisions, one multiply fewer per axis).
+template <int F>
+__device__ __forceinline__ int pick_off_2p24(float t, float ui)
+{
+    if constexpr (F == BSPLINE3) {
+        const Thr3 c = bspline_thresholds_2p24(t);
+        return -1 + (ui >= c.c0) + (ui >= c.c1) + (ui >= c.c2);
+    } else if constexpr (F == LINEAR) {
+        return ui >= __builtin_fmaf(-16777216.0f, t, 16777216.0f) ? 1 : 0;
     } else {
         return (t >= 0.5f) ? 1 : 0;
     }

@@ -95,9 +95,9 @@ template <int F, int VAR>
 __device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
 {
     if constexpr (VAR == 0) {
-        o[0] = pick_off<F>(t[0], u24(w.x));
-        o[1] = pick_off<F>(t[1], u24(w.y));
-        o[2] = pick_off<F>(t[2], u24(w.z));
+        o[0] = pick_off_2p24<F>(t[0], u24i(w.x));
+        o[1] = pick_off_2p24<F>(t[1], u24i(w.y));
+        o[2] = pick_off_2p24<F>(t[2], u24i(w.z));
     } else {
         float u = u24(w.x);
         o[0] = pick_off_reuse<F>(t[0], u);
