@@ -702,7 +702,9 @@ size_t sf_neural_train_workspace(int32_t channels, int32_t out_dim, int64_t batc
 {
     if (!((channels == 8 && out_dim == 4) || (channels == 16 && out_dim == 1)) || batch < 1)
         return 0;
-    return (size_t)train_parts(batch) * (size_t)(sfk::train_nparams(channels, out_dim) + 1) * sizeof(float);
+    const int parts = train_parts(batch);
+    return (size_t)(parts + sfk::train_reduce_chunks(parts)) * (size_t)(sfk::train_nparams(channels, out_dim) + 1) *
+           sizeof(float);
 }
 
 sf_status sf_neural_train_step(const sf_train_state *stt, const int32_t *batch_idx, const float *targets,

@@ -15,6 +15,8 @@
 //    columns of one v_mfma_f32_16x16x32_bf16 tile with hidden units as rows,
 //    so one layer's accumulators are, lane for lane, the next layer's B
 //    operand (the weights' K order is permuted to match, see kperm()).
+#include <type_traits>
+
 #include "sf_device.hpp"
 #include "sf_internal.hpp"
 
@@ -277,16 +279,33 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
     }
 }
 
-// Sum the per-wavefront partials in order and take one Adam step per
-// parameter; the loss lands in loss_out.
-__global__ __launch_bounds__(256) void k_train_reduce(TrainCall t, int nparts, const float *partials, int npar)
+// First stage of the gradient sum: chunk c (blockIdx.y) of REDUCE_CHUNK
+// consecutive per-wavefront partials, summed in order.
+constexpr int REDUCE_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void k_train_chunks(int nparts, const float *partials, int npar, float *chunks)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p > npar)
+        return;
+    const int w0 = blockIdx.y * REDUCE_CHUNK, w1 = min(w0 + REDUCE_CHUNK, nparts);
+    float g = 0.0f;
+    for (int w = w0; w < w1; ++w)
+        g += partials[(int64_t)w * (npar + 1) + p];
+    chunks[(int64_t)blockIdx.y * (npar + 1) + p] = g;
+}
+
+// Sum the chunk sums in order (a fixed order overall: the result does not
+// depend on scheduling) and take one Adam step per parameter; the loss lands
+// in loss_out.
+__global__ __launch_bounds__(256) void k_train_reduce(TrainCall t, int nchunks, const float *chunks, int npar)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p > npar)
         return;
     float g = 0.0f;
-    for (int w = 0; w < nparts; ++w)
-        g += partials[(int64_t)w * (npar + 1) + p];
+    for (int w = 0; w < nchunks; ++w)
+        g += chunks[(int64_t)w * (npar + 1) + p];
     if (p == npar) {
         t.loss_out[0] = g / (float)t.batch;
         return;
@@ -595,6 +614,73 @@ __global__ __launch_bounds__(256) void k_decode_lattice(NeuralCall c, const int6
             c.out[i * O + o] = valid ? y[o] : __builtin_nanf("");
 }
 
+// Latents of one ray step for the wave's four 16-sample groups, as loaded
+// (E4M3 codes or BF16 bits), with each lane's column scale.  Issuing the
+// loads of step k+1 before the MLP of step k keeps one step of gathers in
+// flight behind the matrix-core work.
+template <int FMT>
+struct StepLatents {
+    using Raw = typename std::conditional<FMT == SF_LATENT_BF16, uint4, uint2>::type;
+    Raw raw[4];
+    float cs[4];
+};
+
+template <int C, int FMT>
+__device__ __forceinline__ void issue_latents(const LatentArgs &g, int64_t idx, int blk, StepLatents<FMT> &L)
+{
+    const int lane = threadIdx.x & 63, kb = lane >> 4;
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int src = 16 * G + (lane & 15);
+        const int64_t sidx = ((int64_t)__shfl((int)(idx >> 32), src) << 32) | (uint32_t)__shfl((int)idx, src);
+        const bool use = 8 * kb < C && sidx >= 0;
+        L.cs[G] = 1.0f;
+        if constexpr (FMT == SF_LATENT_BF16) {
+            L.raw[G] = use ? *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(g.latents) + sidx * C + 8 * kb)
+                           : make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            const int sblk = __shfl(blk, src);
+            L.raw[G] = use ? *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(g.latents) + sidx * C + 8 * kb)
+                           : make_uint2(0u, 0u);
+            if (sidx >= 0)
+                L.cs[G] = g.scales[sblk];   // the scale of this lane's column
+        }
+    }
+}
+
+template <int FMT>
+__device__ __forceinline__ bf16x8 latents_bf16(const typename StepLatents<FMT>::Raw &v)
+{
+    if constexpr (FMT == SF_LATENT_BF16) {
+        return __builtin_bit_cast(bf16x8, v);
+    } else {
+        bf16x8 r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            r[j] = (__bf16)fp8_to_f32((v.x >> (8 * j)) & 0xffu);
+            r[4 + j] = (__bf16)fp8_to_f32((v.y >> (8 * j)) & 0xffu);
+        }
+        return r;
+    }
+}
+
+// The wave's MLPs on loaded step latents; y = this lane's O raw outputs.
+template <int C, int O, int FMT>
+__device__ __forceinline__ void decode_loaded(const MlpFrags<C, O> &F, const StepLatents<FMT> &L, float y[O])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const f32x4 d3 = mlp16<C, O>(F, latents_bf16<FMT>(L.raw[G]), L.cs[G]);
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const float v = __shfl(d3[o], lane & 15);
+            if ((lane >> 4) == G)
+                y[o] = v;
+        }
+    }
+}
+
 // Ray march through a neural density volume: per step the lookup point's
 // picked lattice point is decoded (sigma = max(MLP, 0)); taps outside the
 // lattice read zero and are not decoded.  Every lane walks the same number
@@ -613,46 +699,62 @@ __global__ __launch_bounds__(256) void k_neural_ray(NeuralCall c, uint32_t nb_pa
         st = ray_setup_dev(c.lat.wmin, c.lat.scale, c.rays + 8 * i, c.steps, g);
     const bool march = active && st == 0;
     double Tsum = 0.0;
+    // lattice point (and scale block) of step k of this lane's ray; idx -1
+    // outside the lattice or for lanes without a ray
+    auto step_point = [&](const StepHash &h, int k, int s, int64_t &idx, int &blk) {
+        idx = -1;
+        blk = 0;
+        if (!march)
+            return;
+        int i0[3], o[3];
+        float t[3];
+        const float kh = (float)k + 0.5f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float p = __builtin_fmaf(kh, g.G[a], g.E[a]);
+            const float fl = __builtin_floorf(p);
+            i0[a] = (int)fl;
+            t[a] = p - fl;
+        }
+        const uint3 w = h.at((uint32_t)k);
+        o[0] = pick_off<F_>(t[0], u24(w.x));
+        o[1] = pick_off<F_>(t[1], u24(w.y));
+        o[2] = pick_off<F_>(t[2], u24(w.z));
+        const int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
+        if constexpr (DBG) {
+            int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
+            tp[0] = x;
+            tp[1] = y;
+            tp[2] = z;
+        }
+        const bool in = ((uint32_t)x < (uint32_t)c.lat.res[0]) & ((uint32_t)y < (uint32_t)c.lat.res[1]) &
+                        ((uint32_t)z < (uint32_t)c.lat.res[2]);
+        if (in) {
+            idx = ((int64_t)z * c.lat.res[1] + y) * c.lat.res[0] + x;
+            blk = c.lat.block_at(x, y, z);
+        }
+    };
     for (int s = 0; s < c.spp; ++s) {
         StepHash h;
         h.init((uint32_t)i, (uint32_t)s, c.seed);
         double tau = 0.0;
-        float kh = 0.5f;
-        for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
-            int64_t idx = -1;
-            int blk = 0;
-            if (march) {
-                int i0[3], o[3];
-                float t[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float p = __builtin_fmaf(kh, g.G[a], g.E[a]);
-                    const float fl = __builtin_floorf(p);
-                    i0[a] = (int)fl;
-                    t[a] = p - fl;
-                }
-                const uint3 w = h.at((uint32_t)k);
-                o[0] = pick_off<F_>(t[0], u24(w.x));
-                o[1] = pick_off<F_>(t[1], u24(w.y));
-                o[2] = pick_off<F_>(t[2], u24(w.z));
-                const int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
-                if constexpr (DBG) {
-                    int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
-                    tp[0] = x;
-                    tp[1] = y;
-                    tp[2] = z;
-                }
-                const bool in = ((uint32_t)x < (uint32_t)c.lat.res[0]) & ((uint32_t)y < (uint32_t)c.lat.res[1]) &
-                                ((uint32_t)z < (uint32_t)c.lat.res[2]);
-                if (in) {
-                    idx = ((int64_t)z * c.lat.res[1] + y) * c.lat.res[0] + x;
-                    blk = c.lat.block_at(x, y, z);
-                }
-            }
+        int64_t idx;
+        int blk;
+        step_point(h, 0, s, idx, blk);
+        StepLatents<FMT> cur, nxt;
+        issue_latents<C, FMT>(c.lat, idx, blk, cur);
+        for (int k = 0; k < c.steps; ++k) {
+            int64_t idx_n = -1;
+            int blk_n = 0;
+            if (k + 1 < c.steps)
+                step_point(h, k + 1, s, idx_n, blk_n);
+            issue_latents<C, FMT>(c.lat, idx_n, blk_n, nxt);   // step k+1 in flight
             float sg[1];
-            decode_wave<C, O, FMT>(c.lat, Fr, idx, blk, sg);
+            decode_loaded<C, O, FMT>(Fr, cur, sg);             // step k
             if (idx >= 0)
                 tau += (double)__builtin_fmaxf(sg[0], 0.0f);
+            cur = nxt;
+            idx = idx_n;
         }
         Tsum += exp(-(double)g.dt * tau);
     }
@@ -690,9 +792,14 @@ hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_
     else
         k_train<16, 1><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
     const int npar = POff(t.C, t.O).n;
-    k_train_reduce<<<dim3((npar + 1 + 255) / 256), dim3(256), 0, s>>>(t, nparts, workspace, npar);
+    const int nchunks = (nparts + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    float *chunks = workspace + (int64_t)nparts * (npar + 1);
+    k_train_chunks<<<dim3((npar + 1 + 255) / 256, nchunks), dim3(256), 0, s>>>(nparts, workspace, npar, chunks);
+    k_train_reduce<<<dim3((npar + 1 + 255) / 256), dim3(256), 0, s>>>(t, nchunks, chunks, npar);
     return hipGetLastError();
 }
+
+int train_reduce_chunks(int nparts) { return (nparts + REDUCE_CHUNK - 1) / REDUCE_CHUNK; }
 
 int train_nparams(int C, int O) { return POff(C, O).n; }
 

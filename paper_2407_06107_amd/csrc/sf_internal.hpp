@@ -157,6 +157,7 @@ hipError_t launch_to_bf16(const float *in, int64_t n, uint16_t *out, hipStream_t
 hipError_t launch_quant_fp8(const float *lat, const LatentArgs &g, uint8_t *codes, float *scales, hipStream_t s);
 hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_t chunk, hipStream_t s);
 int train_nparams(int C, int O);
+int train_reduce_chunks(int nparts);
 hipError_t launch_neural2d(const NeuralCall &c, hipStream_t s);
 hipError_t launch_neural_ray(const NeuralCall &c, hipStream_t s);
 hipError_t launch_decode_lattice(const NeuralCall &c, const int64_t *idx, hipStream_t s);

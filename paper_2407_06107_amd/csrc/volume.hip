@@ -91,6 +91,16 @@ __device__ __forceinline__ bool brick_occupied(const VolArgs &v, const int i0[3]
     return !in | (((w >> (b & 31u)) & 1u) != 0u);
 }
 
+// The loaded bits, or 0 (the value 0.0) for a tap outside the grid.  The
+// empty asm keeps the select on the 32-bit word: otherwise it is moved past
+// the conversions and done twice on the float64 halves.
+__device__ __forceinline__ uint32_t masked_bits(uint32_t b, bool ok)
+{
+    uint32_t r = ok ? b : 0u;
+    asm volatile("" : "+v"(r));
+    return r;
+}
+
 template <int F, int VAR>
 __device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
 {
@@ -154,11 +164,11 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
             }
             bool ok;
             const uint32_t off = voxel_offset<HALF, P2>(c.vol, x, y, z, ok);
-            tau += (double)(pend_ok ? bits_value<HALF>(pend) : 0.0f);   // step k-1
-            pend = voxel_bits<HALF>(rs, off);                           // step k
+            tau += (double)bits_value<HALF>(masked_bits(pend, pend_ok));   // step k-1
+            pend = voxel_bits<HALF>(rs, off);                               // step k
             pend_ok = ok;
         }
-        tau += (double)(pend_ok ? bits_value<HALF>(pend) : 0.0f);
+        tau += (double)bits_value<HALF>(masked_bits(pend, pend_ok));
         Tsum += exp(-(double)g.dt * tau);
     }
     c.T[i] = (float)(Tsum / (double)c.spp);

@@ -350,7 +350,9 @@ def _latgrid(sf, **kw):
 def test_neural_shapes_and_sizes(sf):
     assert sf.sf_mlp_nparams(8, 64, 4) == 4996          # config-4 network
     assert sf.sf_mlp_nparams(16, 64, 1) == 5313         # config-5 network
-    assert sf.sf_neural_train_workspace(8, 4, 1000) == 63 * (4996 + 1) * 4
+    # 63 per-wavefront partials + 1 chunk sum (chunks of 64 partials), each nparams + 1 floats
+    assert sf.sf_neural_train_workspace(8, 4, 1000) == (63 + 1) * (4996 + 1) * 4
+    assert sf.sf_neural_train_workspace(16, 1, 1 << 20) == (2048 + 32) * (5313 + 1) * 4
     assert sf.sf_neural_train_workspace(8, 3, 1000) == 0
     assert C.sizeof(sf.sf_latent_grid) == 8 + 8 + 4 + 12 + 4 * 3 + 24 + 4   # padded to pointer alignment
     assert C.sizeof(sf.sf_mlp) == 8 + 16
