@@ -19,6 +19,11 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsf.so")
 
+# Per-source flags: the neural decoder's matrix-core accumulators live in
+# ordinary VGPRs (gfx950 MFMA accepts them), so the bias / ReLU / packing
+# code that follows each layer reads them without AGPR-to-VGPR copies.
+EXTRA_FLAGS = {"neural.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
 SOURCES = ["abi.hip", "filter2d.hip", "aniso.hip", "dct.hip", "triplanar.hip", "volume.hip", "neural.hip",
            "reduce.hip"]
 ARCH = "gfx950"
@@ -45,7 +50,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *CFLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

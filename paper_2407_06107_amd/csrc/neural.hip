@@ -366,15 +366,43 @@ __device__ __forceinline__ void load_frags(const uint16_t *P, MlpFrags<C, O> &F)
         F.b3[j] = (4 * g + j < O) ? pbf(P, off.b3 + 4 * g + j) : 0.0f;
 }
 
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats -> one word of two bfloat16 (round to nearest even, one packed
+// conversion).
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// A packed word of two bfloat16 with its negative halves (-0 included)
+// zeroed: a negative bfloat16 is a negative int16.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, w), (s16x2)0));
+}
+
+// bfloat16(max(x, 0)) for eight accumulators: rounding first and rectifying
+// the rounded values gives the same numbers.
 __device__ __forceinline__ bf16x8 relu_pack(f32x4 lo, f32x4 hi)
 {
-    bf16x8 r;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        r[j] = (__bf16)__builtin_fmaxf(lo[j], 0.0f);
-        r[4 + j] = (__bf16)__builtin_fmaxf(hi[j], 0.0f);
-    }
-    return r;
+    const uint4 w = make_uint4(relu_bf16x2(pack_bf16(lo[0], lo[1])), relu_bf16x2(pack_bf16(lo[2], lo[3])),
+                               relu_bf16x2(pack_bf16(hi[0], hi[1])), relu_bf16x2(pack_bf16(hi[2], hi[3])));
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+// Eight OCP E4M3 codes (two words) -> bfloat16, exactly (an E4M3 value has 4
+// significant bits), through the packed FP8 conversion of the vector ALU.
+__device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint32_t lo, uint32_t hi)
+{
+    const f32x2 a0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)lo, false), a1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)lo, true);
+    const f32x2 b0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)hi, false), b1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)hi, true);
+    const uint4 w = make_uint4(pack_bf16(a0.x, a0.y), pack_bf16(a1.x, a1.y), pack_bf16(b0.x, b0.y),
+                               pack_bf16(b1.x, b1.y));
+    return __builtin_bit_cast(bf16x8, w);
 }
 
 // The MLP on the 16 samples whose latents (K block of this lane) are in zb;
@@ -425,11 +453,7 @@ __device__ __forceinline__ bf16x8 latent_frag(const LatentArgs &g, int64_t idx, 
         r = __builtin_bit_cast(bf16x8, v);
     } else {
         const uint2 v = *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(g.latents) + idx * C + 8 * kb);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            r[j] = (__bf16)fp8_to_f32((v.x >> (8 * j)) & 0xffu);
-            r[4 + j] = (__bf16)fp8_to_f32((v.y >> (8 * j)) & 0xffu);
-        }
+        r = fp8x8_to_bf16(v.x, v.y);
         scale = g.scales[blk];
     }
     return r;
@@ -654,13 +678,7 @@ __device__ __forceinline__ bf16x8 latents_bf16(const typename StepLatents<FMT>::
     if constexpr (FMT == SF_LATENT_BF16) {
         return __builtin_bit_cast(bf16x8, v);
     } else {
-        bf16x8 r;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            r[j] = (__bf16)fp8_to_f32((v.x >> (8 * j)) & 0xffu);
-            r[4 + j] = (__bf16)fp8_to_f32((v.y >> (8 * j)) & 0xffu);
-        }
-        return r;
+        return fp8x8_to_bf16(v.x, v.y);
     }
 }
 
