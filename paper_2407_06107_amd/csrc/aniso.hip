@@ -107,8 +107,8 @@ __global__ __launch_bounds__(256) void k_aniso_stoch(AnisoCall c, int log_g)
                 if constexpr (F == GAUSS_FIS) {
                     gauss_fis_pick(tx, ty, c.sigma, u24(w1.x), u24(w1.y), ox, oy);
                 } else {
-                    ox = pick_off<F>(tx, u24(w1.x));
-                    oy = pick_off<F>(ty, u24(w1.y));
+                    ox = pick_off_2p24<F>(tx, u24i(w1.x));
+                    oy = pick_off_2p24<F>(ty, u24i(w1.y));
                 }
                 const int x = wrap_any(c.tex.wrap, ix + ox, wl), y = wrap_any(c.tex.wrap, iy + oy, hl);
                 if (c.taps) {

@@ -104,8 +104,8 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
                     ox = bspline_fis_pick(tx, w.x, w.y, w.z);
                     oy = bspline_fis_pick(ty, w2.x, w2.y, w2.z);
                 } else if constexpr (VAR == 0) {
-                    ox = pick_off<F>(tx, u24(w.x));
-                    oy = pick_off<F>(ty, u24(w.y));
+                    ox = pick_off_2p24<F>(tx, u24i(w.x));
+                    oy = pick_off_2p24<F>(ty, u24i(w.y));
                 } else {
                     float u = u24(w.x);
                     ox = pick_off_reuse<F>(tx, u);

@@ -148,11 +148,14 @@ __device__ __forceinline__ float wave_sum(float v)
 
 // One wavefront (= one workgroup) per chunk of the batch.  Lane h holds
 // hidden unit h: its column of W1 and W2, its row of W2 and W3, and the
-// matching gradient accumulators.
-template <int C, int O>
+// matching gradient accumulators.  S consecutive samples are processed
+// together: their loads and their multiply-add chains are independent, so
+// they overlap, while every per-sample sum and every accumulator update
+// keeps the sample order (the results equal those of one sample at a time).
+template <int C, int O, int S>
 __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float *partials)
 {
-    __shared__ float sh_h1[HID], sh_da[HID];
+    __shared__ float sh_h1[HID][S], sh_da[HID][S];
     const POff P(C, O);
     const int h = threadIdx.x;
     const float *W = t.params;
@@ -189,72 +192,121 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
     const float inv_b = 2.0f / (float)t.batch;
     const int64_t s0 = (int64_t)blockIdx.x * chunk;
     const int64_t s1 = min(s0 + chunk, t.batch);
-    for (int64_t s = s0; s < s1; ++s) {
-        const int64_t li = t.idx[s];
-        if ((uint64_t)li >= (uint64_t)t.n_lattice)
-            continue;   // an index outside the lattice contributes nothing
-        float z[C];
+    for (int64_t sb = s0; sb < s1; sb += S) {
+        // the group's samples; an index outside the lattice (or past the
+        // chunk) contributes nothing
+        int64_t li[S];
+        bool use[S];
+        float z[S][C], tg[S][O];
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            z[c] = t.latents[li * C + c];
-        float a1 = b1;
+        for (int j = 0; j < S; ++j) {
+            li[j] = sb + j < s1 ? t.idx[sb + j] : -1;
+            use[j] = (uint64_t)li[j] < (uint64_t)t.n_lattice;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            a1 = __builtin_fmaf(z[c], w1c[c], a1);
-        const float h1 = a1 > 0.0f ? a1 : 0.0f;
-        sh_h1[h] = h1;
-        __syncthreads();
-        float a2 = b2;
+            for (int c = 0; c < C; ++c)
+                z[j][c] = use[j] ? t.latents[li[j] * C + c] : 0.0f;
 #pragma unroll
-        for (int k = 0; k < HID; ++k)
-            a2 = __builtin_fmaf(sh_h1[k], w2c[k], a2);
-        const float h2 = a2 > 0.0f ? a2 : 0.0f;
-        float dy[O];
-        float dh2 = 0.0f;
-#pragma unroll
-        for (int o = 0; o < O; ++o) {
-            const float y = wave_sum(h2 * w3r[o]) + b3[o];
-            const float e = y - t.targets[li * O + o];
-            loss = __builtin_fmaf(e, e, loss);
-            dy[o] = e * inv_b;
-            g3[o] = __builtin_fmaf(h2, dy[o], g3[o]);
-            gb3[o] += dy[o];
-            dh2 = __builtin_fmaf(w3r[o], dy[o], dh2);
+            for (int o = 0; o < O; ++o)
+                tg[j][o] = use[j] ? t.targets[li[j] * O + o] : 0.0f;
         }
-        const float da2 = a2 > 0.0f ? dh2 : 0.0f;
-        gb2 += da2;
+        float a1[S], a2[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            a1[j] = b1;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                a1[j] = __builtin_fmaf(z[j][c], w1c[c], a1[j]);
+            sh_h1[h][j] = a1[j] > 0.0f ? a1[j] : 0.0f;
+            a2[j] = b2;
+        }
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < HID; ++k)
-            g2[k] = __builtin_fmaf(sh_h1[k], da2, g2[k]);
-        __syncthreads();
-        sh_da[h] = da2;
-        __syncthreads();
-        float dh1 = 0.0f;
 #pragma unroll
-        for (int k = 0; k < HID; ++k)
-            dh1 = __builtin_fmaf(w2r[k], sh_da[k], dh1);
-        const float da1 = a1 > 0.0f ? dh1 : 0.0f;
-        gb1 += da1;
+            for (int j = 0; j < S; ++j)
+                a2[j] = __builtin_fmaf(sh_h1[k][j], w2c[k], a2[j]);
+        float da2[S];
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            g1[c] = __builtin_fmaf(z[c], da1, g1[c]);
-        __syncthreads();
-        sh_da[h] = da1;
-        __syncthreads();
-        // latent gradient and its Adam step: lane c owns channel c
-        if (h < C) {
-            float gz = 0.0f;
+        for (int j = 0; j < S; ++j) {
+            const float h2 = a2[j] > 0.0f ? a2[j] : 0.0f;
+            float dh2 = 0.0f;
+#pragma unroll
+            for (int o = 0; o < O; ++o) {
+                const float y = wave_sum(h2 * w3r[o]) + b3[o];
+                const float e = y - tg[j][o];
+                const float dy = e * inv_b;
+                if (use[j]) {
+                    loss = __builtin_fmaf(e, e, loss);
+                    g3[o] = __builtin_fmaf(h2, dy, g3[o]);
+                    gb3[o] += dy;
+                }
+                dh2 = __builtin_fmaf(w3r[o], dy, dh2);
+            }
+            da2[j] = use[j] && a2[j] > 0.0f ? dh2 : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (!use[j])
+                continue;
+            gb2 += da2[j];
 #pragma unroll
             for (int k = 0; k < HID; ++k)
-                gz = __builtin_fmaf(w1r[k], sh_da[k], gz);
-            if (t.grad_latents)
-                t.grad_latents[s * C + h] = gz;
-            const int64_t j = li * C + h;
-            const float m = 0.9f * t.m_lat[j] + 0.1f * gz;
-            const float v = 0.999f * t.v_lat[j] + 0.001f * gz * gz;
-            t.m_lat[j] = m;
-            t.v_lat[j] = v;
-            t.latents[j] -= t.lr_latent * (m / t.bc1) / (__builtin_sqrtf(v / t.bc2) + 1e-8f);
+                g2[k] = __builtin_fmaf(sh_h1[k][j], da2[j], g2[k]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            sh_da[h][j] = da2[j];
+        __syncthreads();
+        float dh1[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            dh1[j] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < HID; ++k)
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                dh1[j] = __builtin_fmaf(w2r[k], sh_da[k][j], dh1[j]);
+        float da1[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            da1[j] = a1[j] > 0.0f ? dh1[j] : 0.0f;
+            if (!use[j])
+                continue;
+            gb1 += da1[j];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                g1[c] = __builtin_fmaf(z[j][c], da1[j], g1[c]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            sh_da[h][j] = da1[j];
+        __syncthreads();
+        // latent gradients and their Adam steps: lane c owns channel c
+        if (h < C) {
+            float gz[S];
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                gz[j] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < HID; ++k)
+#pragma unroll
+                for (int j = 0; j < S; ++j)
+                    gz[j] = __builtin_fmaf(w1r[k], sh_da[k][j], gz[j]);
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                if (!use[j])
+                    continue;
+                if (t.grad_latents)
+                    t.grad_latents[(sb + j) * C + h] = gz[j];
+                const int64_t q = li[j] * C + h;
+                const float m = 0.9f * t.m_lat[q] + 0.1f * gz[j];
+                const float v = 0.999f * t.v_lat[q] + 0.001f * gz[j] * gz[j];
+                t.m_lat[q] = m;
+                t.v_lat[q] = v;
+                t.latents[q] -= t.lr_latent * (m / t.bc1) / (__builtin_sqrtf(v / t.bc2) + 1e-8f);
+            }
         }
         __syncthreads();
     }
@@ -278,6 +330,8 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
         out[P.n] = loss;
     }
 }
+
+constexpr int TRAIN_GROUP = 2;   // samples per iteration of k_train
 
 // First stage of the gradient sum: chunk c (blockIdx.y) of REDUCE_CHUNK
 // consecutive per-wavefront partials, summed in order.
@@ -527,8 +581,8 @@ __global__ __launch_bounds__(256) void k_neural2d(NeuralCall c)
             int blk = 0;
             if (ok) {
                 const uint4 w = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
-                const int x = wrapi(ix + pick_off<F_>(tx, u24(w.x)), R0);
-                const int yy = wrapi(iy + pick_off<F_>(ty, u24(w.y)), R1);
+                const int x = wrapi(ix + pick_off_2p24<F_>(tx, u24i(w.x)), R0);
+                const int yy = wrapi(iy + pick_off_2p24<F_>(ty, u24i(w.y)), R1);
                 idx = (int64_t)yy * R0 + x;
                 blk = c.lat.block_at(x, yy, 0);
                 if (c.taps) {
@@ -735,9 +789,9 @@ __global__ __launch_bounds__(256) void k_neural_ray(NeuralCall c, uint32_t nb_pa
             t[a] = p - fl;
         }
         const uint3 w = h.at((uint32_t)k);
-        o[0] = pick_off<F_>(t[0], u24(w.x));
-        o[1] = pick_off<F_>(t[1], u24(w.y));
-        o[2] = pick_off<F_>(t[2], u24(w.z));
+        o[0] = pick_off_2p24<F_>(t[0], u24i(w.x));
+        o[1] = pick_off_2p24<F_>(t[1], u24i(w.y));
+        o[2] = pick_off_2p24<F_>(t[2], u24i(w.z));
         const int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
         if constexpr (DBG) {
             int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
@@ -806,9 +860,9 @@ hipError_t launch_quant_fp8(const float *lat, const LatentArgs &g, uint8_t *code
 hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_t chunk, hipStream_t s)
 {
     if (t.C == 8 && t.O == 4)
-        k_train<8, 4><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
+        k_train<8, 4, TRAIN_GROUP><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
     else
-        k_train<16, 1><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
+        k_train<16, 1, TRAIN_GROUP><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
     const int npar = POff(t.C, t.O).n;
     const int nchunks = (nparts + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
     float *chunks = workspace + (int64_t)nparts * (npar + 1);

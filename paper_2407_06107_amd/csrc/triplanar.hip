@@ -22,7 +22,8 @@ __device__ __forceinline__ void tri_uv(const float *p, int plane, float scale, f
 }
 
 // One texel per sample on one plane: level pick (u_l), raster, per-axis
-// inverse-CDF picks (u_x, u_y), fetch, shade.
+// inverse-CDF picks on the 24-bit lattice indices ix_u, iy_u of the x and y
+// uniforms, fetch, shade.
 template <int F, int SHADE>
 __device__ __forceinline__ float4 stoch_point(const TriplanarCall &c, float u, float v, float lam, float ux,
                                               float uy, float ul, int32_t *tap3)
@@ -36,8 +37,8 @@ __device__ __forceinline__ float4 stoch_point(const TriplanarCall &c, float u, f
     float tx, ty;
     raster(wrap_coord(c.tex.wrap, u), wl, ix, tx);
     raster(wrap_coord(c.tex.wrap, v), hl, iy, ty);
-    const int x = wrap_tap(c.tex.wrap, ix + pick_off<F>(tx, ux), wl);
-    const int y = wrap_tap(c.tex.wrap, iy + pick_off<F>(ty, uy), hl);
+    const int x = wrap_tap(c.tex.wrap, ix + pick_off_2p24<F>(tx, ux), wl);
+    const int y = wrap_tap(c.tex.wrap, iy + pick_off_2p24<F>(ty, uy), hl);
     if (tap3) {
         tap3[0] = l;
         tap3[1] = x;
@@ -142,7 +143,8 @@ __global__ __launch_bounds__(256) void k_tri_sampled(TriplanarCall c, int log_g)
             const float C0 = w[0] / W, C1 = (w[0] + w[1]) / W;
             for (int s = lane; s < c.spp; s += G) {
                 const uint4 wd = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
-                const float ux = u24(wd.x), uy = u24(wd.y), up = u24(wd.z), ul = u24(wd.w);
+                // x and y as 24-bit lattice indices (thresholds scaled by 2^24), plane and level as uniforms
+                const float ux = u24i(wd.x), uy = u24i(wd.y), up = u24(wd.z), ul = u24(wd.w);
                 if (c.plane_mode == 0) {
                     // MODE == STOCH here: all three planes with the sample's uniforms
 #pragma unroll
