@@ -21,7 +21,7 @@ _SRCS = [_SRC, os.path.join(_HERE, "neural.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # enums of the oracle (its own copy; it does not include the library header)
-NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS = 0, 1, 2, 3, 4, 5, 6
+NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS, EWA = 0, 1, 2, 3, 4, 5, 6, 7
 SIGMA_MIN, SIGMA_MAX = 1.0 / 16.0, 4.0     # Gaussian standard deviation, texels
 BEFORE, AFTER, STOCHASTIC = 0, 1, 2
 RGBA32F, RGBA8, R16F, R32F, DCT8 = 0, 1, 2, 3, 4
@@ -92,6 +92,12 @@ def lib():
         L.orc_gauss_h.argtypes = [f32]
         L.orc_gauss_h.restype = f32
         L.orc_gauss_pick_pmf.argtypes = [f32, f32, P]
+        L.orc_ewa_lut.argtypes = [i32]
+        L.orc_ewa_lut.restype = f32
+        L.orc_ewa_lod.argtypes = [P, i32, i32]
+        L.orc_ewa_lod.restype = f32
+        L.orc_ewa_pick_pmf.argtypes = [i32, i32, i32, i32, P, i32, i32, P, i32, P]
+        L.orc_ewa_weights.argtypes = [i32, i32, i32, i32, P, i32, i32, P, i32]
         L.orc_log2c.argtypes = [f32]
         L.orc_log2c.restype = f32
         L.orc_aniso_lod.argtypes = [i32, i32, P, i32, P, P]
@@ -338,6 +344,38 @@ def filter2d_aniso(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1
                              mode, spp, seed & 0xFFFFFFFF, sigma, amax, shade, _p(g), _p(out), _p(tp), _p(sub),
                              0 if sub is None else sub.size)
     return (out, tp) if taps else out
+
+
+def ewa_lut() -> np.ndarray:
+    return np.array([lib().orc_ewa_lut(i) for i in range(128)], dtype=np.float32)
+
+
+def ewa_lod(q, levels: int, amax: int = 8) -> float:
+    """Level of detail of the EWA footprint: max(0, L-1 + log2(shorter axis))
+    after the anisotropy limit (binary32)."""
+    return float(lib().orc_ewa_lod(_p(_c(q, np.float32)), levels, amax))
+
+
+def ewa_pick_pmf(w: int, h: int, levels: int, q, level: int, amax: int = 8, wrap: int = REPEAT, maxcells: int = 4096):
+    """Exact pick probabilities of the one-uniform reservoir over the level's
+    bounding box (all 2^24 uniforms), with the box (s0, s1, t0, t1)."""
+    qq = _c(q, np.float32)
+    P = np.zeros(maxcells)
+    box = np.zeros(4, dtype=np.int32)
+    k = lib().orc_ewa_pick_pmf(w, h, levels, wrap, _p(qq), amax, level, _p(P), maxcells, _p(box))
+    if k < 0:
+        raise ValueError("bounding box too large")
+    nx, ny = box[1] - box[0] + 1, box[3] - box[2] + 1
+    return P[:k].reshape(ny, nx), tuple(int(b) for b in box)
+
+
+def ewa_weights(w: int, h: int, levels: int, q, level: int, amax: int = 8, wrap: int = REPEAT, maxcells: int = 4096):
+    qq = _c(q, np.float32)
+    P = np.zeros(maxcells)
+    k = lib().orc_ewa_weights(w, h, levels, wrap, _p(qq), amax, level, _p(P), maxcells)
+    if k < 0:
+        raise ValueError("bounding box too large")
+    return P[:k]
 
 
 def aniso_reference(tex: Tex2D, q: np.ndarray, K: int = 16, filt: int = BSPLINE3, shade: int = 0, ggx=None,

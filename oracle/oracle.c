@@ -33,6 +33,7 @@
  *   screen-space anisotropic minification ...... Sec. 4.2.1; Suppl. S.4.3; Sec. 5 "Anisotropic
  *                                                filtering and minification"
  *   DCT-compressed textures, triplanar mapping . Sec. 5 "Texture compression", "Triplanar mapping"
+ *   stochastic EWA by reservoir sampling ....... Sec. 4.1 (EWA paragraph); Suppl. S.4 (EWA listing)
  *   filter importance sampling (FIS) ........... Sec. 4.2; Sec. 5 "Magnification, Filter
  *                                                Importance Sampling"; Suppl. S.4.2
  *   transmittance in a density grid ............ Sec. 5 (offline rendering)
@@ -59,7 +60,7 @@
 #define ORC_EXPORT __attribute__((visibility("default")))
 
 enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2, F_KEYS3 = 3, F_GAUSS_FRS = 4, F_GAUSS_FIS = 5,
-       F_BSPLINE3_FIS = 6 };
+       F_BSPLINE3_FIS = 6, F_EWA = 7 };
 enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2 };
 enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3, FMT_DCT8 = 4 };
 enum { WRAP_REPEAT = 0, WRAP_CLAMP = 1 };
@@ -1314,6 +1315,300 @@ static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, in
             out[c] = sum[c];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Elliptically weighted average (EWA) and its stochastic form (Sec. 4.1:    */
+/* select a MIP level from the ellipse's extent, evaluate all EWA weights,   */
+/* keep one texel by weighted reservoir sampling; Suppl. S.4, EWA listing).  */
+/* The ellipse is the pixel footprint given by the derivatives; weights are  */
+/* the truncated Gaussian e^(-2 r^2) - e^(-2) of the ellipse radius, read     */
+/* from a 128-entry table.  Binary32 contract, in the listing's order:        */
+/*   axes a = (du/dx, dv/dx), b = (du/dy, dv/dy) (texture units), longer     */
+/*   first; the shorter is lengthened to longer/amax beyond the limit        */
+/*   (longer/(shorter amax) * shorter); lod = max(0, (L-1) + log2(shorter)); */
+/*   lod > L-1 (a footprint wider than the texture) reads texel (0, 0) of    */
+/*   the last level; else level floor(lod) + [u_l >= 1 - f], at most L-1.    */
+/*   At level l (W_l x H_l texels): s = u W_l - 1/2,                         */
+/*   t = v H_l - 1/2, axes scaled by (W_l, H_l); A = a_y a_y + b_y b_y + 1,   */
+/*   B = -2 (a_x a_y + b_x b_y), C = a_x a_x + b_x b_x + 1,                  */
+/*   F = 1/(A C - B B/4), A, B, C times F; det = -B B + 4 A C,               */
+/*   s0 = ceil(s - 2 sqrt(det C)/det), s1 = floor(s + 2 sqrt(det C)/det),    */
+/*   t0, t1 likewise with sqrt(A det); for it = t0..t1, is = s0..s1:          */
+/*   r2 = A (ss ss) + (B ss) tt + C (tt tt), ss = is - s, tt = it - t;       */
+/*   skip r2 >= 1; w = LUT[min(floor(r2 128), 127)], skip w <= 0; reservoir: */
+/*   W += w, p = w/W, u < p ? (pick, u = u/p) : u = (u - p)/(1 - p).          */
+/*   LUT[i] = exp(-2 i/127) - exp(-2) with the binary32 exp of the contract. */
+/* Uniforms: word 0 of the sample's key drives the reservoir, word 3 the     */
+/* level.  Comparators: the EWA sums on levels floor(lod), floor(lod)+1      */
+/* (weights 1-f, f), each normalised by its weight total.                    */
+/* ------------------------------------------------------------------------ */
+#define EWA_LUT 128
+static float ewa_lut[EWA_LUT];
+static void ewa_lut_init(void)
+{
+    const float e2 = orc_expc(-2.0f);
+    for (int i = 0; i < EWA_LUT; ++i) {
+        float r2 = (float)i / 127.0f;
+        ewa_lut[i] = orc_expc(-2.0f * r2) - e2;
+    }
+}
+
+ORC_EXPORT float orc_ewa_lut(int i)
+{
+    ewa_lut_init();
+    return ewa_lut[i];
+}
+
+typedef struct {
+    float lod;
+    float a[2], b[2]; /* the axes after the anisotropy limit, texture units */
+} ewa_frame;
+
+static ewa_frame ewa_setup(const float *q, int levels, int amax)
+{
+    ewa_frame e;
+    float a0 = q[2], a1 = q[3], b0 = q[4], b1 = q[5];
+    float la = sqrtf(a0 * a0 + a1 * a1), lb = sqrtf(b0 * b0 + b1 * b1);
+    if (la < lb) {
+        float x = a0, y = a1, l = la;
+        a0 = b0, a1 = b1, la = lb;
+        b0 = x, b1 = y, lb = l;
+    }
+    if (lb * (float)amax < la && lb > 0.0f) {
+        float scale = la / (lb * (float)amax);
+        b0 = b0 * scale;
+        b1 = b1 * scale;
+        lb = lb * scale;
+    }
+    e.a[0] = a0, e.a[1] = a1, e.b[0] = b0, e.b[1] = b1;
+    e.lod = fmaxf(0.0f, (float)(levels - 1) + orc_log2c(lb));
+    return e;
+}
+
+ORC_EXPORT float orc_ewa_lod(const float *q, int levels, int amax)
+{
+    return ewa_setup(q, levels, amax).lod;
+}
+
+typedef struct {
+    float s, t, A, B, C;
+    int s0, s1, t0, t1;
+} ewa_level;
+
+static ewa_level ewa_at(const tex2d *tx, const float *q, const ewa_frame *e, int l)
+{
+    ewa_level v;
+    int wl = lvl_dim(tx->w, l), hl = lvl_dim(tx->h, l);
+    float u = wrap_coord(tx->wrap, q[0]), w = wrap_coord(tx->wrap, q[1]);
+    v.s = u * (float)wl - 0.5f;
+    v.t = w * (float)hl - 0.5f;
+    float d00 = e->a[0] * (float)wl, d01 = e->a[1] * (float)hl;
+    float d10 = e->b[0] * (float)wl, d11 = e->b[1] * (float)hl;
+    float A = d01 * d01 + d11 * d11 + 1.0f;
+    float B = -2.0f * (d00 * d01 + d10 * d11);
+    float C = d00 * d00 + d10 * d10 + 1.0f;
+    float invF = 1.0f / (A * C - B * B * 0.25f);
+    A = A * invF;
+    B = B * invF;
+    C = C * invF;
+    float det = -B * B + 4.0f * A * C;
+    float invDet = 1.0f / det;
+    float uS = sqrtf(fmaxf(0.0f, det * C)), vS = sqrtf(fmaxf(0.0f, A * det));
+    v.s0 = (int)ceilf(v.s - 2.0f * invDet * uS);
+    v.s1 = (int)floorf(v.s + 2.0f * invDet * uS);
+    v.t0 = (int)ceilf(v.t - 2.0f * invDet * vS);
+    v.t1 = (int)floorf(v.t + 2.0f * invDet * vS);
+    v.A = A, v.B = B, v.C = C;
+    return v;
+}
+
+static int ewa_weight(const ewa_level *v, int is, int it, float *w)
+{
+    float ss = (float)is - v->s, tt = (float)it - v->t;
+    float r2 = v->A * (ss * ss) + v->B * ss * tt + v->C * (tt * tt);
+    if (!(r2 < 1.0f))
+        return 0;
+    int idx = (int)(r2 * (float)EWA_LUT);
+    if (idx > EWA_LUT - 1)
+        idx = EWA_LUT - 1;
+    *w = ewa_lut[idx];
+    return *w > 0.0f;
+}
+
+/* one texel by weighted reservoir sampling with one uniform; returns 0 when
+ * no weight is positive (then the sample reads nothing) */
+static int ewa_pick(const ewa_level *v, float u, int *px, int *py)
+{
+    float sum = 0.0f;
+    int found = 0;
+    for (int it = v->t0; it <= v->t1; ++it)
+        for (int is = v->s0; is <= v->s1; ++is) {
+            float w;
+            if (!ewa_weight(v, is, it, &w))
+                continue;
+            sum += w;
+            float p = w / sum;
+            if (u < p) {
+                *px = is, *py = it;
+                found = 1;
+                u = u / p;
+            } else {
+                u = (u - p) / (1.0f - p);
+            }
+        }
+    return found;
+}
+
+static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int spp, uint32_t seed, int amax,
+                    int shade, const double *ggx, double *out, int32_t *taps)
+{
+    int ch = shade == 1 ? 3 : 4;
+    ewa_frame e = ewa_setup(q, tx->levels, amax);
+    const float lmax = (float)(tx->levels - 1);
+    if (e.lod > lmax) {
+        /* a footprint wider than the whole texture reads texel (0, 0) of the
+         * coarsest level (as pbrt's EWA does) */
+        double texel[4], val[4];
+        fetch2d(tx, tx->levels - 1, 0, 0, texel);
+        shade2d(shade, ggx, texel, val);
+        for (int c = 0; c < ch; ++c)
+            out[c] = val[c];
+        if (taps && mode == M_STOCH)
+            for (int s = 0; s < spp; ++s) {
+                taps[3 * s] = tx->levels - 1;
+                taps[3 * s + 1] = taps[3 * s + 2] = 0;
+            }
+        return;
+    }
+    if (mode == M_STOCH) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int s = 0; s < spp; ++s) {
+            uint32_t key[4] = {(uint32_t)qi, (uint32_t)s, 0u, seed}, w[4];
+            orc_pcg4d(key, w);
+            float lc = fminf(e.lod, lmax);
+            float fl = floorf(lc);
+            int l = (int)fl + (uniform24(w[3]) >= 1.0f - (lc - fl) ? 1 : 0);
+            if (l > tx->levels - 1)
+                l = tx->levels - 1;
+            ewa_level v = ewa_at(tx, q, &e, l);
+            int x = 0, y = 0;
+            int found = ewa_pick(&v, uniform24(w[0]), &x, &y);
+            int wl = lvl_dim(tx->w, l), hl = lvl_dim(tx->h, l);
+            if (taps) {
+                taps[3 * s] = found ? l : INT32_MIN;
+                taps[3 * s + 1] = found ? wrap_tap(tx->wrap, x, wl) : INT32_MIN;
+                taps[3 * s + 2] = found ? wrap_tap(tx->wrap, y, hl) : INT32_MIN;
+            }
+            if (!found)
+                continue;
+            double texel[4], val[4];
+            fetch2d(tx, l, wrap_tap(tx->wrap, x, wl), wrap_tap(tx->wrap, y, hl), texel);
+            shade2d(shade, ggx, texel, val);
+            for (int c = 0; c < ch; ++c)
+                acc[c] += val[c];
+        }
+        for (int c = 0; c < ch; ++c)
+            out[c] = acc[c] / (double)spp;
+        return;
+    }
+    double sum[4] = {0, 0, 0, 0};
+    float lc = fminf(e.lod, lmax);
+    float fl = floorf(lc);
+    int lv[2] = {(int)fl, (int)fl + 1 > tx->levels - 1 ? tx->levels - 1 : (int)fl + 1};
+    double pl[2] = {1.0 - (double)(lc - fl), (double)(lc - fl)};
+    for (int li = 0; li < 2; ++li) {
+        if (pl[li] == 0.0)
+            continue;
+        ewa_level v = ewa_at(tx, q, &e, lv[li]);
+        int wl = lvl_dim(tx->w, lv[li]), hl = lvl_dim(tx->h, lv[li]);
+        double part[4] = {0, 0, 0, 0}, W = 0.0;
+        for (int it = v.t0; it <= v.t1; ++it)
+            for (int is = v.s0; is <= v.s1; ++is) {
+                float w;
+                if (!ewa_weight(&v, is, it, &w))
+                    continue;
+                double texel[4], val[4];
+                fetch2d(tx, lv[li], wrap_tap(tx->wrap, is, wl), wrap_tap(tx->wrap, it, hl), texel);
+                W += (double)w;
+                if (mode == M_BEFORE) {
+                    for (int c = 0; c < 4; ++c)
+                        part[c] += (double)w * texel[c];
+                } else {
+                    shade2d(shade, ggx, texel, val);
+                    for (int c = 0; c < ch; ++c)
+                        part[c] += (double)w * val[c];
+                }
+            }
+        for (int c = 0; c < 4; ++c)
+            sum[c] += W > 0.0 ? pl[li] * part[c] / W : 0.0;
+    }
+    if (mode == M_BEFORE)
+        shade2d(shade, ggx, sum, out);
+    else
+        for (int c = 0; c < ch; ++c)
+            out[c] = sum[c];
+}
+
+/* Exact pick probabilities of the one-uniform reservoir at one level, by
+ * running the chain on all 2^24 uniforms; P[(it - t0) * nx + (is - s0)]. */
+ORC_EXPORT int orc_ewa_pick_pmf(int w, int h, int levels, int wrap, const float *q, int amax, int level, double *P,
+                                int maxcells, int32_t *box)
+{
+    ewa_lut_init();
+    const int64_t off0 = 0;
+    tex2d tx = {NULL, w, h, levels, FMT_RGBA32F, wrap, MIP_LINEAR, &off0, NULL};
+    ewa_frame e = ewa_setup(q, levels, amax);
+    ewa_level v = ewa_at(&tx, q, &e, level);
+    int nx = v.s1 - v.s0 + 1, ny = v.t1 - v.t0 + 1;
+    box[0] = v.s0, box[1] = v.s1, box[2] = v.t0, box[3] = v.t1;
+    if (nx * ny > maxcells || nx <= 0 || ny <= 0)
+        return -1;
+    int64_t *cnt = (int64_t *)calloc((size_t)nx * ny, sizeof(int64_t));
+#pragma omp parallel
+    {
+        int64_t *loc = (int64_t *)calloc((size_t)nx * ny, sizeof(int64_t));
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < (1 << 24); ++k) {
+            int x, y;
+            if (ewa_pick(&v, (float)k * 0x1p-24f, &x, &y))
+                loc[(y - v.t0) * nx + (x - v.s0)]++;
+        }
+#pragma omp critical
+        for (int i = 0; i < nx * ny; ++i)
+            cnt[i] += loc[i];
+        free(loc);
+    }
+    for (int i = 0; i < nx * ny; ++i)
+        P[i] = (double)cnt[i] / 16777216.0;
+    free(cnt);
+    return nx * ny;
+}
+
+/* The normalised EWA weights at one level on the same box (binary64 of the
+ * binary32 table weights). */
+ORC_EXPORT int orc_ewa_weights(int w, int h, int levels, int wrap, const float *q, int amax, int level, double *P,
+                               int maxcells)
+{
+    ewa_lut_init();
+    const int64_t off0 = 0;
+    tex2d tx = {NULL, w, h, levels, FMT_RGBA32F, wrap, MIP_LINEAR, &off0, NULL};
+    ewa_frame e = ewa_setup(q, levels, amax);
+    ewa_level v = ewa_at(&tx, q, &e, level);
+    int nx = v.s1 - v.s0 + 1, ny = v.t1 - v.t0 + 1;
+    if (nx * ny > maxcells || nx <= 0 || ny <= 0)
+        return -1;
+    double W = 0.0;
+    for (int it = v.t0; it <= v.t1; ++it)
+        for (int is = v.s0; is <= v.s1; ++is) {
+            float wt;
+            double x = ewa_weight(&v, is, it, &wt) ? (double)wt : 0.0;
+            P[(it - v.t0) * nx + (is - v.s0)] = x;
+            W += x;
+        }
+    for (int i = 0; i < nx * ny; ++i)
+        P[i] /= W;
+    return nx * ny;
+}
+
 /* queries: n x {u, v, du/dx, dv/dx, du/dy, dv/dy}; the texture's mip field
  * is ignored (the level comes from the footprint). */
 ORC_EXPORT int orc_filter2d_aniso(const void *base, int w, int h, int levels, int fmt, int wrap,
@@ -1325,11 +1620,17 @@ ORC_EXPORT int orc_filter2d_aniso(const void *base, int w, int h, int levels, in
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, MIP_LINEAR, level_off, dct_range};
     int ch = shade == 1 ? 3 : 4;
     int64_t m = subset ? nsub : n;
+    if (filter == F_EWA)
+        ewa_lut_init();
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i) {
         int64_t qi = subset ? subset[i] : i;
-        aniso_one(&t, q + 6 * qi, qi, filter, mode, spp, seed, sigma, amax, shade, ggx, out + ch * i,
-                  taps ? taps + (int64_t)3 * spp * i : NULL);
+        const float *qq = q + 6 * qi;
+        int32_t *tp = taps ? taps + (int64_t)3 * spp * i : NULL;
+        if (filter == F_EWA && aniso_query_finite(qq))
+            ewa_one(&t, qq, qi, mode, spp, seed, amax, shade, ggx, out + ch * i, tp);
+        else
+            aniso_one(&t, qq, qi, filter, mode, spp, seed, sigma, amax, shade, ggx, out + ch * i, tp);
     }
     return 0;
 }

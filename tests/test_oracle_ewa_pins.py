@@ -1,0 +1,163 @@
+"""Pins of the oracle's EWA filter and its stochastic form (Sec. 4.1: a MIP
+level from the ellipse's extent, all EWA weights, one texel by weighted
+reservoir sampling; Suppl. S.4 EWA listing) against libm, exact enumeration
+of the 24-bit uniforms and closed cases."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2407_06107_amd import inputs
+
+U24 = 2.0 ** -24
+
+
+def test_weight_table(orc):
+    """Truncated Gaussian e^(-2 r^2) - e^(-2) at r^2 = i/127: libm values,
+    positive and decreasing, zero at the ellipse boundary."""
+    lut = orc.ewa_lut().astype(np.float64)
+    r2 = (np.arange(128) / 127.0).astype(np.float32).astype(np.float64)
+    ref = np.exp(-2.0 * r2) - math.exp(-2.0)
+    assert np.all(np.abs(lut - ref) <= 2.0 ** -23)
+    assert lut[-1] == 0.0 and np.all(np.diff(lut) < 0)
+
+
+def _pyr(N=64):
+    tex = inputs.texture_uniform(N, seed=12)
+    lv = inputs.mip_chain(tex)
+    buf, offs = inputs.pack_levels(lv)
+    return lv, buf, offs
+
+
+QUERIES = [
+    [0.3, 0.6, 3.0 / 64, 1.0 / 64, -0.5 / 64, 1.5 / 64],     # tilted ellipse, ratio ~2
+    [0.71, 0.22, 6.0 / 64, 0.0, 0.0, 1.0 / 64],              # axis-aligned, ratio 6
+    [0.5, 0.5, 0.5 / 64, 0.5 / 64, -0.5 / 64, 0.5 / 64],     # small, rotated 45 degrees
+    [0.12, 0.93, 20.0 / 64, 3.0 / 64, -0.2 / 64, 1.2 / 64],  # beyond the anisotropy limit 8
+]
+
+
+@pytest.mark.parametrize("qi", range(len(QUERIES)))
+def test_reservoir_pmf_by_enumeration(orc, qi):
+    """The one-uniform reservoir picks texel i with probability w_i / sum w
+    (all 2^24 uniforms run through the chain).  Reusing the uniform costs
+    resolution: u / p stretches the lattice by 1/p and (u - p)/(1 - p)
+    rounds on every step, so the binary32 chain drifts from the exact
+    probabilities as the number n of positive weights grows; measured
+    drift stays under n^2 2^-24 with a margin of 5 or more, and a chain of
+    at most four weights is exact to a few lattice points."""
+    q = np.array(QUERIES[qi], np.float32)
+    L = 7
+    lam, _, _ = orc.aniso_lod(64, 64, q[2:], 8)
+    fl = int(math.floor(max(lam, 0.0)))
+    for level in sorted({min(fl, L - 1), min(fl + 1, L - 1)}):
+        P, box = orc.ewa_pick_pmf(64, 64, L, q, level)
+        W = orc.ewa_weights(64, 64, L, q, level).reshape(P.shape)
+        n = int((W > 0).sum())
+        assert abs(P.sum() - 1.0) < 1e-12
+        assert np.all(P[W == 0] == 0)
+        tol = (4 if n <= 4 else n * n) * U24
+        assert np.max(np.abs(P - W)) <= tol, (level, n, np.max(np.abs(P - W)) / U24)
+
+
+def test_reservoir_two_and_three_weights_exact(orc):
+    """Few taps: the ellipse of a tiny footprint centred between texels
+    covers 2 x 2 texels of equal weight; each is picked with probability
+    1/4 exactly on the 24-bit lattice."""
+    q = np.array([32.0 / 64, 17.0 / 64, 0.0, 0.0, 0.0, 0.0], np.float32)
+    P, box = orc.ewa_pick_pmf(64, 64, 7, q, 0)
+    W = orc.ewa_weights(64, 64, 7, q, 0).reshape(P.shape)
+    pos = W > 0
+    assert pos.sum() == 4 and np.allclose(W[pos], 0.25, rtol=0, atol=1e-7)
+    assert np.all(np.abs(P[pos] - W[pos]) <= 2 * U24)
+
+
+def test_zero_footprint_reads_the_centre_texel(orc):
+    """Zero derivatives: the ellipse is the unit disk in level-0 texels, so a
+    query at a texel centre has one positive weight — the texel itself."""
+    lv, buf, offs = _pyr()
+    ot = orc.Tex2D(buf, 64, 64, len(lv), orc.RGBA32F, offs, orc.REPEAT, orc.MIP_LINEAR)
+    iy, ix = np.meshgrid(np.arange(0, 64, 7), np.arange(0, 64, 5), indexing="ij")
+    q = np.zeros((ix.size, 6), np.float32)
+    q[:, 0] = (ix.ravel() + 0.5) / 64
+    q[:, 1] = (iy.ravel() + 0.5) / 64
+    for m in (orc.BEFORE, orc.AFTER):
+        out = orc.filter2d_aniso(ot, q, orc.EWA, m, amax=8)
+        assert np.allclose(out, lv[0][iy.ravel(), ix.ravel()], rtol=0, atol=1e-12)
+    S, taps = orc.filter2d_aniso(ot, q, orc.EWA, orc.STOCHASTIC, spp=8, seed=2, amax=8, taps=True)
+    assert np.all(taps[..., 0] == 0) and np.all(taps[..., 1] == ix.ravel()[:, None])
+
+
+def test_after_is_the_level_blend_of_normalised_weights(orc):
+    """The deterministic EWA after shading is the definition written out:
+    (1-f) times the weight-normalised sum of shaded texels on level
+    floor(lod) plus f times that on the next level; and the stochastic
+    estimator's exact expectation (enumerated pick probabilities, 24-bit
+    level probability) is within the reservoir's drift of it."""
+    lv, buf, offs = _pyr()
+    ot = orc.Tex2D(buf, 64, 64, len(lv), orc.RGBA32F, offs, orc.REPEAT, orc.MIP_LINEAR)
+    g = orc.ggx_params()
+    for qv in QUERIES[:3]:
+        q = np.array(qv, np.float32)
+        A = orc.filter2d_aniso(ot, q[None], orc.EWA, orc.AFTER, shade=1, amax=8)[0]
+        lc = np.float32(min(orc.ewa_lod(q, 7), 6.0))
+        fl = int(math.floor(lc))
+        f = float(np.float32(lc - np.float32(fl)))
+        c = math.ceil(float(np.float32(1.0) - np.float32(f)) * 2 ** 24)
+        p1 = (2 ** 24 - c) / 2 ** 24                   # P(u24 >= 1 - f)
+        D = np.zeros(3)
+        E = np.zeros(3)
+        drift = 0.0
+        for level, pd, pe in ((fl, 1 - f, 1 - p1), (min(fl + 1, 6), f, p1)):
+            P, (s0, s1, t0, t1) = orc.ewa_pick_pmf(64, 64, 7, q, level)
+            W = orc.ewa_weights(64, 64, 7, q, level).reshape(P.shape)
+            n = 64 >> level
+            vals = np.zeros(P.shape + (3,))
+            for yy in range(t0, t1 + 1):
+                for xx in range(s0, s1 + 1):
+                    vals[yy - t0, xx - s0] = orc.shade_ggx(g, lv[level][yy % n, xx % n].astype(np.float64))
+            D += pd * np.einsum("ij,ijc->c", W, vals)
+            E += pe * np.einsum("ij,ijc->c", P, vals)
+            drift += pe * np.abs(P - W).sum() * np.abs(vals).max()
+        assert np.max(np.abs(D - A)) <= 1e-12 * max(1.0, np.abs(A).max()), (D, A)
+        assert np.max(np.abs(E - A)) <= drift + abs(p1 - f) * 2 * np.abs(A).max() + 1e-12
+
+
+def test_lod_uses_the_minor_axis(orc):
+    """The EWA level comes from the shorter axis after the anisotropy limit:
+    lod = log2(shorter in level-0 texels) on a square 64^2 pyramid; the
+    shorter axis is lengthened to longer/amax beyond the limit; and it
+    agrees with the anisotropic filter's level."""
+    for k in (0, 1, 3):
+        q = np.array([0.4, 0.4, 2.0 ** k * 4 / 64, 0.0, 0.0, 2.0 ** k / 64], np.float32)
+        assert orc.ewa_lod(q, 7) == k
+        q = np.array([0.4, 0.4, 0.0, 2.0 ** k / 64, -(2.0 ** k) * 4 / 64, 0.0], np.float32)   # axes swapped
+        assert orc.ewa_lod(q, 7) == k
+    q = np.array([0.4, 0.4, 32.0 / 64, 0.0, 0.0, 1.0 / 64], np.float32)
+    assert orc.ewa_lod(q, 7, amax=8) == 2.0 and orc.ewa_lod(q, 7, amax=64) == 0.0
+    assert orc.ewa_lod(np.zeros(6, np.float32), 7) == 0.0
+    for qv in QUERIES:
+        q = np.array(qv, np.float32)
+        lam, _, _ = orc.aniso_lod(64, 64, q[2:], 8)
+        assert abs(orc.ewa_lod(q, 7) - max(lam, 0.0)) <= 1e-5
+
+
+def test_stochastic_mean_within_five_sigma(orc):
+    lv, buf, offs = _pyr()
+    ot = orc.Tex2D(buf, 64, 64, len(lv), orc.RGBA32F, offs, orc.REPEAT, orc.MIP_LINEAR)
+    q = inputs.plane_queries_aniso(40, 30)
+    q = q[::20]
+    A = orc.filter2d_aniso(ot, q, orc.EWA, orc.AFTER, shade=1, amax=8)
+    spp = 4096
+    S = orc.filter2d_aniso(ot, q, orc.EWA, orc.STOCHASTIC, spp=spp, seed=5, shade=1, amax=8)
+    assert np.all(np.abs(S - A) <= 5 * 1.0 / math.sqrt(spp))
+
+
+def test_footprint_wider_than_the_texture(orc):
+    lv, buf, offs = _pyr()
+    ot = orc.Tex2D(buf, 64, 64, len(lv), orc.RGBA32F, offs, orc.REPEAT, orc.MIP_LINEAR)
+    q = np.array([[0.3, 0.3, 3.0, 0.0, 0.0, 2.0]], np.float32)       # 128+ texels per pixel on a 64^2 texture
+    for m in (orc.AFTER, orc.BEFORE):
+        assert np.allclose(orc.filter2d_aniso(ot, q, orc.EWA, m, amax=8), lv[-1][0, 0], atol=1e-12)
+    _, taps = orc.filter2d_aniso(ot, q, orc.EWA, orc.STOCHASTIC, spp=3, amax=8, taps=True)
+    assert np.all(taps[0] == [len(lv) - 1, 0, 0])
