@@ -94,7 +94,8 @@ def lib():
         L.orc_gauss_pick_pmf.argtypes = [f32, f32, P]
         L.orc_ewa_lut.argtypes = [i32]
         L.orc_ewa_lut.restype = f32
-        L.orc_ewa_lod.argtypes = [P, i32, i32]
+        L.orc_ewa_lod.argtypes = [P, i32, i32, i32]
+        L.orc_ewa_box.argtypes = [i32, i32, i32, P, i32, i32, P]
         L.orc_ewa_lod.restype = f32
         L.orc_ewa_pick_pmf.argtypes = [i32, i32, i32, i32, P, i32, i32, P, i32, P]
         L.orc_ewa_weights.argtypes = [i32, i32, i32, i32, P, i32, i32, P, i32]
@@ -350,10 +351,17 @@ def ewa_lut() -> np.ndarray:
     return np.array([lib().orc_ewa_lut(i) for i in range(128)], dtype=np.float32)
 
 
-def ewa_lod(q, levels: int, amax: int = 8) -> float:
-    """Level of detail of the EWA footprint: max(0, L-1 + log2(shorter axis))
-    after the anisotropy limit (binary32)."""
-    return float(lib().orc_ewa_lod(_p(_c(q, np.float32)), levels, amax))
+def ewa_lod(q, w: int, h: int, amax: int = 8) -> float:
+    """Level of detail of the EWA footprint: max(0, log2(shorter axis in
+    level-0 texels)) after the anisotropy limit (binary32)."""
+    return float(lib().orc_ewa_lod(_p(_c(q, np.float32)), w, h, amax))
+
+
+def ewa_box(w: int, h: int, levels: int, q, level: int, amax: int = 8):
+    """The ellipse's bounding box (s0, s1, t0, t1) at one level."""
+    box = np.zeros(4, dtype=np.int32)
+    lib().orc_ewa_box(w, h, levels, _p(_c(q, np.float32)), amax, level, _p(box))
+    return tuple(int(b) for b in box)
 
 
 def ewa_pick_pmf(w: int, h: int, levels: int, q, level: int, amax: int = 8, wrap: int = REPEAT, maxcells: int = 4096):

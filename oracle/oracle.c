@@ -1322,11 +1322,15 @@ static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, in
 /* The ellipse is the pixel footprint given by the derivatives; weights are  */
 /* the truncated Gaussian e^(-2 r^2) - e^(-2) of the ellipse radius, read     */
 /* from a 128-entry table.  Binary32 contract, in the listing's order:        */
-/*   axes a = (du/dx, dv/dx), b = (du/dy, dv/dy) (texture units), longer     */
-/*   first; the shorter is lengthened to longer/amax beyond the limit        */
-/*   (longer/(shorter amax) * shorter); lod = max(0, (L-1) + log2(shorter)); */
-/*   lod > L-1 (a footprint wider than the texture) reads texel (0, 0) of    */
-/*   the last level; else level floor(lod) + [u_l >= 1 - f], at most L-1.    */
+/*   axes a = (du/dx, dv/dx), b = (du/dy, dv/dy) (texture units); lengths in  */
+/*   level-0 texels |(W a_x, H a_y)|, longer first; beyond the limit the      */
+/*   shorter is lengthened to longer/amax (b and its length times            */
+/*   longer/(shorter amax)); a zero shorter axis takes the length            */
+/*   longer/amax (b stays zero); lod = max(0, log2(shorter)), the level of   */
+/*   detail of the anisotropic filter.  The pyramid is complete (its last    */
+/*   level is 1 x 1): lod > L-1, a footprint wider than the texture, reads   */
+/*   the last level's one texel; else level floor(lod) + [u_l >= 1 - f],     */
+/*   at most L-1.                                                            */
 /*   At level l (W_l x H_l texels): s = u W_l - 1/2,                         */
 /*   t = v H_l - 1/2, axes scaled by (W_l, H_l); A = a_y a_y + b_y b_y + 1,   */
 /*   B = -2 (a_x a_y + b_x b_y), C = a_x a_x + b_x b_x + 1,                  */
@@ -1363,30 +1367,35 @@ typedef struct {
     float a[2], b[2]; /* the axes after the anisotropy limit, texture units */
 } ewa_frame;
 
-static ewa_frame ewa_setup(const float *q, int levels, int amax)
+static ewa_frame ewa_setup(const float *q, int w, int h, int amax)
 {
     ewa_frame e;
     float a0 = q[2], a1 = q[3], b0 = q[4], b1 = q[5];
-    float la = sqrtf(a0 * a0 + a1 * a1), lb = sqrtf(b0 * b0 + b1 * b1);
-    if (la < lb) {
-        float x = a0, y = a1, l = la;
-        a0 = b0, a1 = b1, la = lb;
-        b0 = x, b1 = y, lb = l;
+    float ax = (float)w * a0, ay = (float)h * a1, bx = (float)w * b0, by = (float)h * b1;
+    float la2 = ax * ax + ay * ay, lb2 = bx * bx + by * by;
+    if (la2 < lb2) {
+        float x = a0, y = a1, l = la2;
+        a0 = b0, a1 = b1, la2 = lb2;
+        b0 = x, b1 = y, lb2 = l;
     }
-    if (lb * (float)amax < la && lb > 0.0f) {
-        float scale = la / (lb * (float)amax);
+    float la = sqrtf(la2), lb = sqrtf(lb2);
+    const float A = (float)amax;
+    if (lb > 0.0f && lb * A < la) {
+        float scale = la / (lb * A);
         b0 = b0 * scale;
         b1 = b1 * scale;
         lb = lb * scale;
+    } else if (lb == 0.0f) {
+        lb = la / A;
     }
     e.a[0] = a0, e.a[1] = a1, e.b[0] = b0, e.b[1] = b1;
-    e.lod = fmaxf(0.0f, (float)(levels - 1) + orc_log2c(lb));
+    e.lod = fmaxf(0.0f, orc_log2c(lb));
     return e;
 }
 
-ORC_EXPORT float orc_ewa_lod(const float *q, int levels, int amax)
+ORC_EXPORT float orc_ewa_lod(const float *q, int w, int h, int amax)
 {
-    return ewa_setup(q, levels, amax).lod;
+    return ewa_setup(q, w, h, amax).lod;
 }
 
 typedef struct {
@@ -1462,7 +1471,7 @@ static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int s
                     int shade, const double *ggx, double *out, int32_t *taps)
 {
     int ch = shade == 1 ? 3 : 4;
-    ewa_frame e = ewa_setup(q, tx->levels, amax);
+    ewa_frame e = ewa_setup(q, tx->w, tx->h, amax);
     const float lmax = (float)(tx->levels - 1);
     if (e.lod > lmax) {
         /* a footprint wider than the whole texture reads texel (0, 0) of the
@@ -1556,7 +1565,7 @@ ORC_EXPORT int orc_ewa_pick_pmf(int w, int h, int levels, int wrap, const float 
     ewa_lut_init();
     const int64_t off0 = 0;
     tex2d tx = {NULL, w, h, levels, FMT_RGBA32F, wrap, MIP_LINEAR, &off0, NULL};
-    ewa_frame e = ewa_setup(q, levels, amax);
+    ewa_frame e = ewa_setup(q, w, h, amax);
     ewa_level v = ewa_at(&tx, q, &e, level);
     int nx = v.s1 - v.s0 + 1, ny = v.t1 - v.t0 + 1;
     box[0] = v.s0, box[1] = v.s1, box[2] = v.t0, box[3] = v.t1;
@@ -1583,6 +1592,16 @@ ORC_EXPORT int orc_ewa_pick_pmf(int w, int h, int levels, int wrap, const float 
     return nx * ny;
 }
 
+/* The ellipse's bounding box (s0, s1, t0, t1) at one level. */
+ORC_EXPORT void orc_ewa_box(int w, int h, int levels, const float *q, int amax, int level, int32_t *box)
+{
+    const int64_t off0 = 0;
+    tex2d tx = {NULL, w, h, levels, FMT_RGBA32F, WRAP_REPEAT, MIP_LINEAR, &off0, NULL};
+    ewa_frame e = ewa_setup(q, w, h, amax);
+    ewa_level v = ewa_at(&tx, q, &e, level);
+    box[0] = v.s0, box[1] = v.s1, box[2] = v.t0, box[3] = v.t1;
+}
+
 /* The normalised EWA weights at one level on the same box (binary64 of the
  * binary32 table weights). */
 ORC_EXPORT int orc_ewa_weights(int w, int h, int levels, int wrap, const float *q, int amax, int level, double *P,
@@ -1591,7 +1610,7 @@ ORC_EXPORT int orc_ewa_weights(int w, int h, int levels, int wrap, const float *
     ewa_lut_init();
     const int64_t off0 = 0;
     tex2d tx = {NULL, w, h, levels, FMT_RGBA32F, wrap, MIP_LINEAR, &off0, NULL};
-    ewa_frame e = ewa_setup(q, levels, amax);
+    ewa_frame e = ewa_setup(q, w, h, amax);
     ewa_level v = ewa_at(&tx, q, &e, level);
     int nx = v.s1 - v.s0 + 1, ny = v.t1 - v.t0 + 1;
     if (nx * ny > maxcells || nx <= 0 || ny <= 0)

@@ -100,7 +100,7 @@ def test_after_is_the_level_blend_of_normalised_weights(orc):
     for qv in QUERIES[:3]:
         q = np.array(qv, np.float32)
         A = orc.filter2d_aniso(ot, q[None], orc.EWA, orc.AFTER, shade=1, amax=8)[0]
-        lc = np.float32(min(orc.ewa_lod(q, 7), 6.0))
+        lc = np.float32(min(orc.ewa_lod(q, 64, 64), 6.0))
         fl = int(math.floor(lc))
         f = float(np.float32(lc - np.float32(fl)))
         c = math.ceil(float(np.float32(1.0) - np.float32(f)) * 2 ** 24)
@@ -124,22 +124,57 @@ def test_after_is_the_level_blend_of_normalised_weights(orc):
 
 
 def test_lod_uses_the_minor_axis(orc):
-    """The EWA level comes from the shorter axis after the anisotropy limit:
-    lod = log2(shorter in level-0 texels) on a square 64^2 pyramid; the
-    shorter axis is lengthened to longer/amax beyond the limit; and it
-    agrees with the anisotropic filter's level."""
+    """The EWA level is the anisotropic filter's level of detail: log2 of the
+    shorter axis in level-0 texels after the anisotropy limit, clamped at 0;
+    a zero shorter axis counts as longer/amax."""
     for k in (0, 1, 3):
         q = np.array([0.4, 0.4, 2.0 ** k * 4 / 64, 0.0, 0.0, 2.0 ** k / 64], np.float32)
-        assert orc.ewa_lod(q, 7) == k
+        assert orc.ewa_lod(q, 64, 64) == k
         q = np.array([0.4, 0.4, 0.0, 2.0 ** k / 64, -(2.0 ** k) * 4 / 64, 0.0], np.float32)   # axes swapped
-        assert orc.ewa_lod(q, 7) == k
+        assert orc.ewa_lod(q, 64, 64) == k
+        q = np.array([0.4, 0.4, 2.0 ** k / 256, 0.0, 0.0, 2.0 ** k * 2 / 32], np.float32)   # 256 x 32 texels
+        assert orc.ewa_lod(q, 256, 32) == k
     q = np.array([0.4, 0.4, 32.0 / 64, 0.0, 0.0, 1.0 / 64], np.float32)
-    assert orc.ewa_lod(q, 7, amax=8) == 2.0 and orc.ewa_lod(q, 7, amax=64) == 0.0
-    assert orc.ewa_lod(np.zeros(6, np.float32), 7) == 0.0
+    assert orc.ewa_lod(q, 64, 64, amax=8) == 2.0 and orc.ewa_lod(q, 64, 64, amax=64) == 0.0
+    assert orc.ewa_lod(np.array([0.4, 0.4, 32.0 / 64, 0, 0, 0], np.float32), 64, 64, amax=8) == 2.0
+    assert orc.ewa_lod(np.zeros(6, np.float32), 64, 64) == 0.0
+    assert orc.ewa_lod(np.array([0.4, 0.4, 0.1 / 64, 0, 0, 0.2 / 64], np.float32), 64, 64) == 0.0
     for qv in QUERIES:
         q = np.array(qv, np.float32)
         lam, _, _ = orc.aniso_lod(64, 64, q[2:], 8)
-        assert abs(orc.ewa_lod(q, 7) - max(lam, 0.0)) <= 1e-5
+        assert orc.ewa_lod(q, 64, 64) == max(lam, 0.0)
+
+
+@pytest.mark.parametrize("wh", [(64, 64), (256, 32), (16, 128), (8, 1), (2048, 2048)])
+@pytest.mark.parametrize("amax", [1, 4, 16])
+def test_bounding_box_is_bounded(orc, wh, amax):
+    """On a complete pyramid, at the levels a sample can read, the ellipse's
+    box has at most (4 r_x (amax + 1) + 3) x (4 r_y (amax + 1) + 3) cells,
+    r_x = max(W, H)/W, r_y = max(W, H)/H: the longer axis is at most amax
+    times the shorter, which is 1 to 2 texels at level floor(lod) (one axis
+    of a non-square texture stops shrinking at 1 texel), and the box's
+    half-width along s is sqrt(a_s^2 + b_s^2 + 1)."""
+    w, h = wh
+    L = int(math.floor(math.log2(max(w, h)))) + 1
+    rx, ry = max(w, h) / w, max(w, h) / h
+    bx, by = 4 * rx * (amax + 1) + 3, 4 * ry * (amax + 1) + 3
+    rng = np.random.default_rng(amax * 7 + w)
+    for _ in range(3000):
+        mag = 10.0 ** rng.uniform(-7, 3, size=2)
+        ang = rng.uniform(0, 2 * np.pi, size=2)
+        if rng.random() < 0.3:
+            ang[1] = ang[0] + rng.normal(0, 0.01)          # nearly parallel axes
+        q = np.array([rng.random(), rng.random(), mag[0] * np.cos(ang[0]), mag[0] * np.sin(ang[0]),
+                      mag[1] * np.cos(ang[1]), mag[1] * np.sin(ang[1])], np.float32)
+        if rng.random() < 0.1:
+            q[4:6] = 0
+        lod = orc.ewa_lod(q, w, h, amax)
+        if lod > L - 1:
+            continue
+        fl = int(math.floor(lod))
+        for l in {fl, min(fl + 1, L - 1)}:
+            s0, s1, t0, t1 = orc.ewa_box(w, h, L, q, l, amax)
+            assert 1 <= s1 - s0 + 1 <= bx and 1 <= t1 - t0 + 1 <= by, (q, l, (s0, s1, t0, t1))
 
 
 def test_stochastic_mean_within_five_sigma(orc):
