@@ -55,6 +55,8 @@ extern "C" {
 #define SF_MAX_STEPS 65536
 #define SF_MAX_SPP 65536
 #define SF_MAX_ANISO 64
+#define SF_EWA_MAX_ANISO 16  /* EWA: anisotropy limit (bounds the ellipse's box)    */
+#define SF_EWA_MAX_ASPECT 8  /* EWA: max(width, height) <= 8 min(width, height)     */
 
 typedef int32_t sf_status;
 enum {
@@ -73,7 +75,10 @@ enum {
  * one tap drawn from the positive and one from the negative product
  * weights, estimate W+ f(t+) - W- f(t-).  SF_KEYS3 is a 2-D texture filter. */
 enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3, SF_GAUSS_FRS = 4, SF_GAUSS_FIS = 5,
-       SF_BSPLINE3_FIS = 6 };
+       SF_BSPLINE3_FIS = 6, SF_EWA = 7 };
+/* SF_EWA: the elliptically weighted average over the pixel footprint, and
+ * its stochastic form (one texel per sample by weighted reservoir sampling);
+ * sf_filter2d_aniso only (it needs the screen derivatives). */
 /* Gaussian filters and filter importance sampling (2-D textures only):
  *   SF_GAUSS_FRS    discrete Gaussian of standard deviation sigma (texels) on
  *                   the nearest 4x4 texels, sampled per axis by its running
@@ -111,7 +116,7 @@ enum { SF_SHADE_NONE = 0, SF_SHADE_GGX = 1 };             /* 2-D */
 enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1 }; /* 3-D points */
 
 typedef struct sf_sampling {
-    int32_t filter;      /* SF_NEAREST .. SF_BSPLINE3_FIS (see above)                */
+    int32_t filter;      /* SF_NEAREST .. SF_EWA (see above)                         */
     int32_t mode;        /* SF_BEFORE | SF_AFTER_EXACT | SF_STOCHASTIC                */
     int32_t spp;         /* samples per query, 1..SF_MAX_SPP (deterministic: ignored) */
     uint32_t seed;       /* fourth word of the hash key                              */
@@ -226,7 +231,7 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
  *   queries : n x {u, v, du/dx, dv/dx, du/dy, dv/dy} float32 (24 B): the
  *             pixel centre's texture coordinate and its screen derivatives.
  *   smp     : filter NEAREST | LINEAR | BSPLINE3 (FRS) | GAUSS_FIS (stochastic
- *             only, with smp->sigma); rng_variant 0.
+ *             only, with smp->sigma) | EWA (below); rng_variant 0.
  *   aniso_max: 1..SF_MAX_ANISO (the paper's limit is 64).
  *   tex->mip is ignored: the level comes from the footprint.  Footprint
  *   axes in level-0 texels a = (W du/dx, H dv/dx), b = (W du/dy, H dv/dy);
@@ -244,10 +249,42 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
  *     probes at offsets (k + 1/2)/N - 1/2 of the major-axis derivative, each
  *     filtered on levels floor(lambda), floor(lambda)+1 (weights 1-f, f),
  *     averaged; before shades the average, after averages shaded texels.
+ * SF_EWA (Sec. 4.1, stochastic EWA: a level chosen from the ellipse's
+ *   extent, then one texel of all the EWA weights by weighted reservoir
+ *   sampling; Suppl. S.4, the EWA kernel).  Needs a complete pyramid
+ *   (levels = floor(log2(max(W, H))) + 1, the last level 1 x 1), aspect
+ *   max(W, H) <= SF_EWA_MAX_ASPECT min(W, H) and aniso_max <=
+ *   SF_EWA_MAX_ANISO, which bound the ellipse's box at a level a sample
+ *   reads to (4 r_x (aniso_max + 1) + 3) x (4 r_y (aniso_max + 1) + 3) cells,
+ *   r_x = max(W, H)/W, r_y = max(W, H)/H.  Binary32 contract:
+ *   a = (du/dx, dv/dx), b = (du/dy, dv/dy); lengths |(W a_x, H a_y)|, longer
+ *   first; beyond the limit b and its length times longer/(shorter
+ *   aniso_max); a zero shorter length becomes longer/aniso_max;
+ *   lod = max(0, log2(shorter)).  lod > levels-1: every mode returns the
+ *   (shaded) texel of the 1 x 1 level.  Else at level l (W_l x H_l):
+ *   s = u W_l - 1/2, t = v H_l - 1/2 (u, v wrapped); axes scaled by
+ *   (W_l, H_l): A = a_y^2 + b_y^2 + 1, B = -2 (a_x a_y + b_x b_y),
+ *   C = a_x^2 + b_x^2 + 1; A, B, C divided by A C - B^2/4;
+ *   det = -B^2 + 4 A C; s0 = ceil(s - 2/det sqrt(det C)),
+ *   s1 = floor(s + 2/det sqrt(det C)), t0, t1 likewise with sqrt(A det);
+ *   rows it = t0..t1, columns is = s0..s1: r^2 = A ss^2 + B ss tt + C tt^2,
+ *   ss = is - s, tt = it - t; cells with r^2 >= 1 skipped; weight
+ *   LUT[min(floor(128 r^2), 127)], LUT[i] = exp(-2 i/127) - exp(-2) with
+ *   the contract exp; zero weights skipped.
+ *   SF_STOCHASTIC, per sample: key (query, sample, 0, seed); word 3 picks
+ *     level floor(lod) + [u_3 >= 1 - frac(lod)] (at most levels-1); word 0
+ *     is the reservoir's uniform u: per weight w, W += w, p = w/W; u < p
+ *     picks the cell and sets u = u/p, else u = (u - p)/(1 - p).
+ *     dbg_taps: n x spp x {level, x, y} of the picked (wrapped) texel.
+ *   SF_BEFORE / SF_AFTER_EXACT: the EWA sums on levels floor(lod) and
+ *     floor(lod)+1 (weights 1-f, f), each divided by its weight total;
+ *     before shades the blend of texels, after blends shaded texels.
  * Queries with a non-finite value, or whose extreme jittered coordinate
  * |u| + |du/dx| + |du/dy| (or the same for v) overflows binary32, give NaN.
  * Errors: as sf_filter2d; SF_E_UNSUPPORTED for other filters or variants;
- *         SF_E_RANGE for aniso_max or sigma out of range.
+ *         SF_E_RANGE for aniso_max or sigma out of range (EWA: aniso_max above
+ *         SF_EWA_MAX_ANISO); SF_E_UNSUPPORTED for EWA on an incomplete
+ *         pyramid or beyond the aspect limit.
  */
 sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp,
                             int32_t aniso_max, int32_t shade, const sf_ggx *ggx, float *out, int32_t *dbg_taps,

@@ -1436,9 +1436,11 @@ static int ewa_weight(const ewa_level *v, int is, int it, float *w)
     float r2 = v->A * (ss * ss) + v->B * ss * tt + v->C * (tt * tt);
     if (!(r2 < 1.0f))
         return 0;
-    int idx = (int)(r2 * (float)EWA_LUT);
+    int idx = (int)(r2 * (float)EWA_LUT); /* r2 >= 0 up to rounding: index 0 */
     if (idx > EWA_LUT - 1)
         idx = EWA_LUT - 1;
+    if (idx < 0)
+        idx = 0;
     *w = ewa_lut[idx];
     return *w > 0.0f;
 }

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_PKG, "libsf.so")
 
 # enums (values fixed by include/sf.h)
 SF_OK, SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED, SF_E_DEVICE, SF_E_WORKSPACE = range(6)
-SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3, SF_GAUSS_FRS, SF_GAUSS_FIS, SF_BSPLINE3_FIS = 0, 1, 2, 3, 4, 5, 6
+SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3, SF_GAUSS_FRS, SF_GAUSS_FIS, SF_BSPLINE3_FIS, SF_EWA = range(8)
+SF_MAX_ANISO, SF_EWA_MAX_ANISO, SF_EWA_MAX_ASPECT = 64, 16, 8
 SF_SIGMA_MIN, SF_SIGMA_MAX = 0.0625, 4.0
 SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC = 0, 1, 2
 SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F, SF_DCT8 = 0, 1, 2, 3, 4

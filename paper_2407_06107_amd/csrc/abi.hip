@@ -33,7 +33,7 @@ sf_status check_sampling(const sf_sampling *smp)
 {
     if (!smp)
         return fail(SF_E_NULL, "sampling descriptor is NULL");
-    if (smp->filter < SF_NEAREST || smp->filter > SF_BSPLINE3_FIS)
+    if (smp->filter < SF_NEAREST || smp->filter > SF_EWA)
         return fail(SF_E_RANGE, "filter %d out of range", smp->filter);
     if (smp->mode < SF_BEFORE || smp->mode > SF_STOCHASTIC)
         return fail(SF_E_RANGE, "mode %d out of range", smp->mode);
@@ -213,6 +213,8 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
         return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
+    if (smp->filter == SF_EWA)
+        return fail(SF_E_UNSUPPORTED, "EWA needs the screen derivatives: use sf_filter2d_aniso");
     if (smp->filter >= SF_KEYS3 && smp->rng_variant != 0)
         return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters draw independent uniforms (rng_variant 0)");
     if ((smp->filter == SF_GAUSS_FRS || smp->filter == SF_GAUSS_FIS) &&
@@ -261,8 +263,8 @@ sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n
     if ((st = check_sampling(smp)) != SF_OK)
         return st;
     const int f = smp->filter;
-    if (f != SF_NEAREST && f != SF_LINEAR && f != SF_BSPLINE3 && f != SF_GAUSS_FIS)
-        return fail(SF_E_UNSUPPORTED, "anisotropic filtering takes NEAREST, LINEAR, BSPLINE3 or GAUSS_FIS");
+    if (f != SF_NEAREST && f != SF_LINEAR && f != SF_BSPLINE3 && f != SF_GAUSS_FIS && f != SF_EWA)
+        return fail(SF_E_UNSUPPORTED, "anisotropic filtering takes NEAREST, LINEAR, BSPLINE3, GAUSS_FIS or EWA");
     if (f == SF_GAUSS_FIS && smp->mode != SF_STOCHASTIC)
         return fail(SF_E_UNSUPPORTED, "the FIS Gaussian has no probe comparator here");
     if (smp->rng_variant != 0)
@@ -274,6 +276,21 @@ sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n
         return fail(SF_E_RANGE, "aniso_max %d outside 1..%d", aniso_max, SF_MAX_ANISO);
     if ((st = check_tex2d(tex)) != SF_OK)
         return st;
+    if (f == SF_EWA) {
+        if (aniso_max > SF_EWA_MAX_ANISO)
+            return fail(SF_E_RANGE, "EWA: aniso_max %d above %d", aniso_max, SF_EWA_MAX_ANISO);
+        const int32_t big = tex->width > tex->height ? tex->width : tex->height;
+        const int32_t small = tex->width > tex->height ? tex->height : tex->width;
+        int full = 1;
+        while ((1 << (full - 1)) * 2 <= big)
+            ++full;
+        if (tex->levels != full)
+            return fail(SF_E_UNSUPPORTED, "EWA needs the complete pyramid: %d levels for %dx%d, got %d", full,
+                        tex->width, tex->height, tex->levels);
+        if ((int64_t)big > (int64_t)SF_EWA_MAX_ASPECT * small)
+            return fail(SF_E_UNSUPPORTED, "EWA: aspect %dx%d beyond %d:1", tex->width, tex->height,
+                        SF_EWA_MAX_ASPECT);
+    }
     if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
         return fail(SF_E_RANGE, "shade %d out of range", shade);
     if (!aligned(queries, 4) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))

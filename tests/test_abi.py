@@ -102,7 +102,7 @@ def test_raymarch_validation(sf, case, status):
     elif case == "steps_big":
         steps = 70000
     elif case == "bad_filter":
-        smp.filter = 7
+        smp.filter = 8
     elif case == "bad_mode":
         smp.mode = 3
     elif case == "spp_zero":
@@ -136,7 +136,7 @@ def test_raymarch_validation(sf, case, status):
     ("ok_zero", 0), ("null_tex", 1), ("null_base", 1), ("bad_format", 3), ("levels_zero", 2),
     ("levels_too_many", 2), ("bad_wrap", 2), ("bad_mip", 2), ("ggx_missing", 1), ("bad_shade", 2),
     ("ggx_backfacing", 2), ("misaligned_level", 2), ("width_zero", 2), ("keys_ok_zero", 0),
-    ("keys_reuse", 3), ("filter_7", 2), ("gauss_sigma_small", 2), ("gauss_sigma_nan", 2), ("fis_sigma_big", 2),
+    ("keys_reuse", 3), ("filter_8", 2), ("ewa", 3), ("gauss_sigma_small", 2), ("gauss_sigma_nan", 2), ("fis_sigma_big", 2),
     ("gauss_reuse", 3), ("fis_bspline_reuse", 3), ("fis_bspline_any_sigma_zero", 0),
 ])
 def test_filter2d_validation(sf, case, status):
@@ -180,8 +180,10 @@ def test_filter2d_validation(sf, case, status):
         n = 0
     elif case == "keys_reuse":
         smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 4, rng_variant=1)
-    elif case == "filter_7":
-        smp = sf.sampling(7, sf.SF_STOCHASTIC, 4)
+    elif case == "filter_8":
+        smp = sf.sampling(8, sf.SF_STOCHASTIC, 4)
+    elif case == "ewa":
+        smp = sf.sampling(sf.SF_EWA, sf.SF_STOCHASTIC, 4)
     elif case == "gauss_sigma_small":
         smp = sf.sampling(sf.SF_GAUSS_FRS, sf.SF_STOCHASTIC, 4, sigma=0.05)
     elif case == "gauss_sigma_nan":
@@ -202,6 +204,8 @@ def test_filter2d_validation(sf, case, status):
 @pytest.mark.parametrize("case, status", [
     ("ok_zero", 0), ("null_tex", 1), ("null_q", 1), ("keys", 3), ("gauss_frs", 3), ("fis_det", 3),
     ("reuse", 3), ("aniso_0", 2), ("aniso_65", 2), ("fis_sigma", 2), ("bad_levels", 2), ("bad_shade", 2),
+    ("ewa_ok_zero", 0), ("ewa_amax17", 2), ("ewa_partial", 3), ("ewa_aspect", 3), ("ewa_reuse", 3),
+    ("ewa_aspect8_partial", 3),
 ])
 def test_filter2d_aniso_validation(sf, case, status):
     L = sf.lib()
@@ -234,6 +238,19 @@ def test_filter2d_aniso_validation(sf, case, status):
         tex.levels = 8
     elif case == "bad_shade":
         shade = 3
+    elif case.startswith("ewa"):
+        smp = sf.sampling(sf.SF_EWA, sf.SF_STOCHASTIC, 4, rng_variant=1 if case == "ewa_reuse" else 0)
+        amax = 16
+        if case == "ewa_ok_zero":
+            n = 0
+        elif case == "ewa_amax17":
+            amax = 17
+        elif case == "ewa_partial":
+            tex.levels = 6
+        elif case == "ewa_aspect":
+            tex.width, tex.height, tex.levels = 1024, 64, 11           # 16:1
+        elif case == "ewa_aspect8_partial":
+            tex.width, tex.height, tex.levels = 512, 64, 9            # 8:1 needs 10 levels
     st = L.sf_filter2d_aniso(texp, q, n, C.byref(smp), amax, shade, None, FAKE, None, None)
     assert st == status, sf.sf_last_error()
 

@@ -532,6 +532,77 @@ def test_filter2d_aniso_checker_full_sampled(sf, orc, checker_full, filt, mode, 
     _close(out[sub], ref)
 
 
+# ------------------------------------------------------------------ stochastic EWA
+@pytest.mark.parametrize("mode, spp", [("STOCH", 8), ("STOCH", 1), ("BEFORE", 1), ("AFTER", 1)])
+@pytest.mark.parametrize("amax", [16, 4, 1])
+@pytest.mark.parametrize("shade", [0, 1])
+def test_filter2d_ewa_parity(sf, orc, aniso_small, mode, spp, amax, shade):
+    """EWA on a 256^2 RGBA8 pyramid (zero, over-limit, non-finite and
+    overflowing footprints included): picked texels bit-exact, values to
+    the float tolerance."""
+    _print_case("filter2d_ewa", mode, spp, amax, shade)
+    lv, q = aniso_small
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(sf.SF_EWA, m, spp, seed=31)
+    taps_d = torch.full((q.shape[0], spp, 3), 99, dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d_aniso(gt, torch.from_numpy(q).cuda(), smp, aniso_max=amax, shade=shade,
+                               ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d_aniso(ot, q, orc.EWA, m, spp=spp, seed=31, shade=shade, taps=m == orc.STOCHASTIC, amax=amax)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("mode, spp", [("STOCH", 4), ("AFTER", 1), ("BEFORE", 1)])
+def test_filter2d_ewa_nonsquare_clamp(sf, orc, mode, spp):
+    """A 256 x 32 float pyramid (aspect 8, one axis reaching 1 texel early),
+    clamped addressing, footprints scaled up to wider than the texture."""
+    _print_case("filter2d_ewa_nonsquare", mode, spp)
+    lv = [x.astype(np.float32) for x in inputs.mip_chain(inputs.texture_sinusoids(256, seed=5, waves=9)[:32])]
+    q = inputs.plane_queries_aniso(64, 40)
+    q[:, 2:] *= np.float32(1.0) + np.arange(q.shape[0], dtype=np.float32)[:, None] % 7 * np.float32(3.0)
+    q[:, :2] = q[:, :2] * np.float32(1.3) - np.float32(0.15)          # some coordinates outside [0, 1]
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, 256, 32, len(lv), orc.RGBA32F, offs, orc.CLAMP, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_CLAMP, mip=sf.SF_MIP_LINEAR)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(sf.SF_EWA, m, spp, seed=7)
+    taps_d = torch.full((q.shape[0], spp, 3), 99, dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
+    out = sf.sf_filter2d_aniso(gt, torch.from_numpy(q).cuda(), smp, aniso_max=16, shade=1,
+                               ggx_params=sf.ggx(), dbg_taps=taps_d)
+    res = orc.filter2d_aniso(ot, q, orc.EWA, m, spp=spp, seed=7, shade=1, taps=m == orc.STOCHASTIC, amax=16)
+    if m == orc.STOCHASTIC:
+        ref, taps = res
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("mode, spp", [("STOCH", 1), ("STOCH", 4), ("AFTER", 1)])
+def test_filter2d_ewa_checker_full_sampled(sf, orc, checker_full, mode, spp):
+    """1920 x 1080 pixels over the 4096^2 checkerboard at aniso_max 16, the
+    launch the benchmark times; 3000 sampled pixels against the oracle."""
+    _print_case("filter2d_ewa_checker_full", mode, spp)
+    lv, q = checker_full
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, 4096, 4096, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(sf.SF_EWA, m, spp, seed=43)
+    out = sf.sf_filter2d_aniso(gt, torch.from_numpy(q).cuda(), smp, aniso_max=16, shade=1,
+                               ggx_params=sf.ggx()).cpu().numpy()
+    sub = np.sort(np.random.default_rng(5).choice(q.shape[0], 3000, replace=False))
+    ref = orc.filter2d_aniso(ot, q, orc.EWA, m, spp=spp, seed=43, shade=1, subset=sub, amax=16)
+    _close(out[sub], ref)
+
+
 # ------------------------------------------------------------------ DCT-compressed textures, triplanar
 @pytest.fixture(scope="module")
 def dct_pair(orc, sf):
