@@ -228,6 +228,62 @@ def _rmse(a, b):
     return float(np.sqrt(np.mean((a - b) ** 2)))
 
 
+def aniso_bench(res):
+    """Config 2, anisotropic: a 4096^2 RGBA8 checkerboard pyramid under a
+    1920x1080 plane camera, footprint-driven levels; jittered minification,
+    hardware-style probes and EWA, against the pixel-integral reference."""
+    import torch
+    import oracle
+    import paper_2407_06107_amd as sf
+    from paper_2407_06107_amd import inputs
+
+    g = sf.ggx()
+    rng = np.random.default_rng(9)
+    log("config 2 anisotropic: checkerboard")
+    lvc = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_checker(4096, 64)))
+    qa = inputs.plane_queries_aniso(1920, 1080)
+    qi = inputs.plane_queries(1920, 1080, tex_size=4096, levels=len(lvc))
+    na = qa.shape[0]
+    texc = sf.Texture2D(lvc, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    qad, qid = torch.from_numpy(qa).cuda(), torch.from_numpy(qi).cuda()
+    bufc, offc = inputs.pack_levels(lvc)
+    otc0 = oracle.Tex2D(bufc, 4096, 4096, 1, oracle.RGBA8, offc[:1], oracle.REPEAT, oracle.MIP_NONE)
+    suba = np.sort(rng.choice(na, 2000, replace=False))
+    t0 = time.perf_counter()
+    ref_a = oracle.aniso_reference(otc0, qa, K=16, filt=oracle.BSPLINE3, shade=1, subset=suba)
+    dt_ref = time.perf_counter() - t0
+    ca = {"queries": na, "reference": f"pixel integral, 16x16 midpoints x bicubic filter-after on level 0, "
+                                      f"{suba.size} pixels ({dt_ref:.1f} s on the CPU)"}
+    for name, filt, mode, spp, amax in (
+            ("aniso_bicubic_stochastic_1spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, 64),
+            ("aniso_bicubic_stochastic_16spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 16, 64),
+            ("aniso_bilinear_stochastic_1spp", sf.SF_LINEAR, sf.SF_STOCHASTIC, 1, 64),
+            ("aniso_gauss_fis_stochastic_16spp", sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 16, 64),
+            ("aniso16_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 16),
+            ("aniso64_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 64),
+            ("aniso64_trilinear_probes_after", sf.SF_LINEAR, sf.SF_AFTER_EXACT, 1, 64),
+            ("ewa16_after", sf.SF_EWA, sf.SF_AFTER_EXACT, 1, 16),
+            ("ewa16_before", sf.SF_EWA, sf.SF_BEFORE, 1, 16),
+            ("ewa16_stochastic_1spp", sf.SF_EWA, sf.SF_STOCHASTIC, 1, 16),
+            ("ewa16_stochastic_16spp", sf.SF_EWA, sf.SF_STOCHASTIC, 16, 16)):
+        smp = sf.sampling(filt, mode, spp, seed=5, sigma=0.5)
+        o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
+        t = time_launches(lambda: sf.sf_filter2d_aniso(texc, qad, smp, amax, sf.SF_SHADE_GGX, g, out=o), 10, 3,
+                          torch)
+        ca[name] = {"ms": t, "queries_per_s": na / (t * 1e-3),
+                    "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
+        if name == "ewa16_after":
+            ewa_after = o.cpu().numpy()
+        elif filt == sf.SF_EWA:
+            ca[name]["rmse_vs_ewa_after"] = _rmse(o.cpu().numpy(), ewa_after)
+    smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)
+    o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
+    t = time_launches(lambda: sf.sf_filter2d(texc, qid, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
+    ca["isotropic_trilinear_before"] = {"ms": t, "queries_per_s": na / (t * 1e-3),
+                                        "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
+    res["config2_aniso"] = ca
+
+
 def texture_bench(args, res):
     """Configs 1 and 2: the 2-D path (magnification of a 64^2 RGBA32F texture;
     a 4096^2 RGBA8 pyramid seen by a 1920x1080 camera), GGX + Lambert."""
@@ -331,43 +387,7 @@ def texture_bench(args, res):
     res["config2"] = c2
     qd2b = qd2
     del tex2, tex2n
-    # ---- config 2, anisotropic: checkerboard plane, footprint-driven levels
-    log("config 2 anisotropic: checkerboard")
-    lvc = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_checker(4096, 64)))
-    qa = inputs.plane_queries_aniso(1920, 1080)
-    qi = inputs.plane_queries(1920, 1080, tex_size=4096, levels=len(lvc))
-    na = qa.shape[0]
-    texc = sf.Texture2D(lvc, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
-    qad, qid = torch.from_numpy(qa).cuda(), torch.from_numpy(qi).cuda()
-    bufc, offc = inputs.pack_levels(lvc)
-    otc0 = oracle.Tex2D(bufc, 4096, 4096, 1, oracle.RGBA8, offc[:1], oracle.REPEAT, oracle.MIP_NONE)
-    suba = np.sort(rng.choice(na, 2000, replace=False))
-    t0 = time.perf_counter()
-    ref_a = oracle.aniso_reference(otc0, qa, K=16, filt=oracle.BSPLINE3, shade=1, subset=suba)
-    dt_ref = time.perf_counter() - t0
-    ca = {"queries": na, "reference": f"pixel integral, 16x16 midpoints x bicubic filter-after on level 0, "
-                                      f"{suba.size} pixels ({dt_ref:.1f} s on the CPU)"}
-    for name, filt, mode, spp, amax in (
-            ("aniso_bicubic_stochastic_1spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, 64),
-            ("aniso_bicubic_stochastic_16spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 16, 64),
-            ("aniso_bilinear_stochastic_1spp", sf.SF_LINEAR, sf.SF_STOCHASTIC, 1, 64),
-            ("aniso_gauss_fis_stochastic_16spp", sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 16, 64),
-            ("aniso16_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 16),
-            ("aniso64_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 64),
-            ("aniso64_trilinear_probes_after", sf.SF_LINEAR, sf.SF_AFTER_EXACT, 1, 64)):
-        smp = sf.sampling(filt, mode, spp, seed=5, sigma=0.5)
-        o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
-        t = time_launches(lambda: sf.sf_filter2d_aniso(texc, qad, smp, amax, sf.SF_SHADE_GGX, g, out=o), 10, 3,
-                          torch)
-        ca[name] = {"ms": t, "queries_per_s": na / (t * 1e-3),
-                    "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
-    smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)
-    o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
-    t = time_launches(lambda: sf.sf_filter2d(texc, qid, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
-    ca["isotropic_trilinear_before"] = {"ms": t, "queries_per_s": na / (t * 1e-3),
-                                        "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
-    res["config2_aniso"] = ca
-    del texc, qad, qid
+    aniso_bench(res)
     # ---- DCT-compressed pyramid (the config 2 texture) and triplanar mapping
     log("DCT texture and triplanar mapping")
     src8 = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
@@ -551,6 +571,7 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=1 << 20, help="rays in the CPU oracle sample")
     ap.add_argument("--suite", action="store_true",
                     help="configs 1, 2 (2-D path), 4 and 5 (neural forms): one JSON line beside the headline run")
+    ap.add_argument("--suite-aniso", action="store_true", help="only the anisotropic section of the suite")
     ap.add_argument("--epochs4", type=int, default=200)
     ap.add_argument("--epochs5", type=int, default=60)
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -561,6 +582,11 @@ def main():
               f"a split of the ray stream, described in DESIGN.md). --gpus {args.gpus} is not supported.",
               file=sys.stderr)
         sys.exit(2)
+    if args.suite_aniso:
+        res = {}
+        aniso_bench(res)
+        print(json.dumps(res))
+        return
     if args.suite:
         neural_bench(args)
         return
