@@ -28,6 +28,8 @@ RGBA32F, RGBA8, R16F, R32F, DCT8 = 0, 1, 2, 3, 4
 REPEAT, CLAMP = 0, 1
 MIP_NONE, MIP_NEAREST, MIP_LINEAR = 0, 1, 2
 TAP_NONE = np.iinfo(np.int32).min
+DENSITY, TRANSMITTANCE, PLANCK = 0, 1, 2     # 3-D shading
+PLANCK_NM = (700.0, 546.1, 435.8)           # wavelengths of an emission result
 
 
 def build(force: bool = False) -> str:
@@ -112,6 +114,11 @@ def lib():
         L.orc_raymarch.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, i32, u32, i32,
                                    P, P, P, i64]
         L.orc_raymarch_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
+        L.orc_raymarch_emission.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, i32, u32,
+                                            i32, P, P, P, i64]
+        L.orc_raymarch_emission_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
+        L.orc_planck.argtypes = [C.c_double, C.c_double]
+        L.orc_planck.restype = C.c_double
         L.orc_build_occupancy.argtypes = [P, i32, i32, i32, i32, i32, P]
         L.orc_k3.restype = C.c_double
         L.orc_k3.argtypes = [C.c_double]
@@ -511,7 +518,7 @@ def filter3d(g: Grid, pos: np.ndarray, filt: int, mode: int, spp: int = 1, seed:
     n = pos.shape[0]
     sub = None if subset is None else _c(subset, np.int64)
     m = n if sub is None else sub.size
-    out = np.zeros(m)
+    out = np.zeros((m, 3)) if shade == PLANCK else np.zeros(m)
     tp = np.zeros((m, spp, 3), dtype=np.int32) if taps else None
     lib().orc_filter3d(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(pos), n, filt, mode,
                        spp, seed & 0xFFFFFFFF, variant, shade, float(ds), _p(out), _p(tp), _p(sub),
@@ -539,6 +546,36 @@ def raymarch_expect(g: Grid, rays: np.ndarray, steps: int, filt: int):
     lib().orc_raymarch_expect(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(rays), n, steps,
                               filt, _p(T))
     return T
+
+
+def planck(lambda_nm: float, T: float) -> float:
+    """Black-body spectral radiance, W sr^-1 m^-2 nm^-1 (float64)."""
+    return lib().orc_planck(float(lambda_nm), float(T))
+
+
+def raymarch_emission(g: Grid, rays: np.ndarray, steps: int, filt: int, mode: int, spp: int = 1, seed: int = 0,
+                      variant: int = 0, taps: bool = False, subset=None):
+    """Emission gathered along rays through a temperature grid: [m, 3]
+    (700, 546.1, 435.8 nm)."""
+    rays = _c(rays, np.float32).reshape(-1, 8)
+    n = rays.shape[0]
+    sub = None if subset is None else _c(subset, np.int64)
+    m = n if sub is None else sub.size
+    L = np.zeros((m, 3))
+    tp = np.zeros((m, spp, steps, 3), dtype=np.int32) if taps else None
+    lib().orc_raymarch_emission(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(rays), n, steps,
+                                filt, mode, spp, seed & 0xFFFFFFFF, variant, _p(L), _p(tp), _p(sub),
+                                0 if sub is None else sub.size)
+    return (L, tp) if taps else L
+
+
+def raymarch_emission_expect(g: Grid, rays: np.ndarray, steps: int, filt: int):
+    rays = _c(rays, np.float32).reshape(-1, 8)
+    n = rays.shape[0]
+    L = np.zeros((n, 3))
+    lib().orc_raymarch_emission_expect(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(rays), n,
+                                       steps, filt, _p(L))
+    return L
 
 
 def build_occupancy(g: Grid, brick_log2: int) -> np.ndarray:

@@ -37,6 +37,7 @@
  *   filter importance sampling (FIS) ........... Sec. 4.2; Sec. 5 "Magnification, Filter
  *                                                Importance Sampling"; Suppl. S.4.2
  *   transmittance in a density grid ............ Sec. 5 (offline rendering)
+ *   black-body emission of a temperature grid .. Sec. 5 "Filtering nonlinear physical properties"
  *
  * Readings where the paper is silent (the GPU side follows the same ones):
  *   - raster coordinates put texel centres at integers: p = u*N - 0.5;
@@ -1944,6 +1945,33 @@ static double shade3d(int shade, double sigma, double ds)
     return shade == 1 ? exp(-sigma * ds) : sigma;
 }
 
+/* Black-body emission (Sec. 5, "Filtering nonlinear physical properties": a
+ * grid of temperatures shaded by Planck's law, filtered before or after the
+ * shading).  Spectral radiance per nanometre of wavelength, in
+ * W sr^-1 m^-2 nm^-1, of a black body at temperature T (kelvin):
+ *   B(lambda, T) = 2 h c^2 / (lambda^5 (exp(h c / (lambda k T)) - 1)) * 1e-9,
+ * lambda in metres, with the exact SI values of h, c and k.  T <= 0 (empty
+ * space) emits nothing; NaN stays NaN.  The three wavelengths of an emission
+ * result are the CIE 1931 RGB primaries, 700, 546.1 and 435.8 nm. */
+static const double PLANCK_NM[3] = {700.0, 546.1, 435.8};
+
+ORC_EXPORT double orc_planck(double lambda_nm, double T)
+{
+    if (isnan(T))
+        return NAN;
+    if (!(T > 0.0))
+        return 0.0;
+    const double h = 6.62607015e-34, c = 299792458.0, k = 1.380649e-23;
+    const double l = lambda_nm * 1e-9;
+    return 2.0 * h * c * c / (pow(l, 5.0) * expm1(h * c / (l * k * T))) * 1e-9;
+}
+
+static void planck3(double T, double *out)
+{
+    for (int c = 0; c < 3; ++c)
+        out[c] = orc_planck(PLANCK_NM[c], T);
+}
+
 /* Three axis picks from the sample's uniforms; variant 1 reuses one. */
 static void pick3(int filter, const float t[3], const uint32_t w[4], int variant, int j[3])
 {
@@ -1962,6 +1990,9 @@ static int pos_finite(const float *x)
     return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
 }
 
+/* Point lookups.  shade: 0 the filtered value, 1 the transmittance
+ * exp(-value ds) of a segment of length ds, 2 black-body emission of the
+ * value as a temperature (three wavelengths: out is n x 3). */
 ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
                             const float *scale, const float *pos, int64_t n, int filter, int mode,
                             int spp, uint32_t seed, int variant, int shade, float ds, double *out,
@@ -1969,10 +2000,12 @@ ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, c
 {
     grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
     int64_t m = subset ? nsub : n;
+    const int ch = shade == 2 ? 3 : 1;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t ii = 0; ii < m; ++ii) {
         int64_t i = subset ? subset[ii] : ii;
         const float *x = pos + 3 * i;
+        double *o_ = out + ch * ii;
         int32_t *tp = taps ? taps + (int64_t)3 * spp * ii : NULL;
         int ok = pos_finite(x);
         float p[3], t[3];
@@ -1983,7 +2016,8 @@ ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, c
                 ok = 0;
         }
         if (!ok) {
-            out[ii] = NAN;
+            for (int c = 0; c < ch; ++c)
+                o_[c] = NAN;
             if (tp && mode == M_STOCH)
                 for (int k = 0; k < 3 * spp; ++k)
                     tp[k] = INT32_MIN;
@@ -1995,8 +2029,9 @@ ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, c
             t[a] = p[a] - fl;
         }
         int off = filter == F_BSPLINE3 ? -1 : 0;
+        double e[3];
         if (mode == M_STOCH) {
-            double acc = 0.0;
+            double acc[3] = {0.0, 0.0, 0.0};
             for (int s = 0; s < spp; ++s) {
                 uint32_t key[4] = {(uint32_t)i, (uint32_t)s, 0u, seed}, w[4];
                 orc_pcg4d(key, w);
@@ -2008,23 +2043,45 @@ ORC_EXPORT int orc_filter3d(const void *base, int nx, int ny, int nz, int fmt, c
                     tp[3 * s + 1] = ty;
                     tp[3 * s + 2] = tz;
                 }
-                acc += shade3d(shade, fetch3d(&g, tx, ty, tz), (double)ds);
+                double v = fetch3d(&g, tx, ty, tz);
+                if (shade == 2) {
+                    planck3(v, e);
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += e[c];
+                } else {
+                    acc[0] += shade3d(shade, v, (double)ds);
+                }
             }
-            out[ii] = acc / (double)spp;
+            for (int c = 0; c < ch; ++c)
+                o_[c] = acc[c] / (double)spp;
         } else {
             double w[3][4];
             int o[3], nt[3];
             for (int a = 0; a < 3; ++a)
                 nt[a] = axis_weights(filter, (double)t[a], &o[a], w[a]);
-            double sum = 0.0;
+            double sum[3] = {0.0, 0.0, 0.0};
             for (int c = 0; c < nt[2]; ++c)
                 for (int b = 0; b < nt[1]; ++b)
                     for (int a = 0; a < nt[0]; ++a) {
                         double wgt = w[0][a] * w[1][b] * w[2][c];
                         double sg = fetch3d(&g, i0[0] + o[0] + a, i0[1] + o[1] + b, i0[2] + o[2] + c);
-                        sum += wgt * (mode == M_BEFORE ? sg : shade3d(shade, sg, (double)ds));
+                        if (mode == M_BEFORE) {
+                            sum[0] += wgt * sg;
+                        } else if (shade == 2) {
+                            planck3(sg, e);
+                            for (int q = 0; q < 3; ++q)
+                                sum[q] += wgt * e[q];
+                        } else {
+                            sum[0] += wgt * shade3d(shade, sg, (double)ds);
+                        }
                     }
-            out[ii] = mode == M_BEFORE ? shade3d(shade, sum, (double)ds) : sum;
+            if (mode == M_BEFORE && shade == 2)
+                planck3(sum[0], o_);
+            else if (mode == M_BEFORE)
+                o_[0] = shade3d(shade, sum[0], (double)ds);
+            else
+                for (int c = 0; c < ch; ++c)
+                    o_[c] = sum[c];
         }
     }
     return 0;
@@ -2206,6 +2263,147 @@ ORC_EXPORT int orc_raymarch_expect(const void *base, int nx, int ny, int nz, int
             prod *= e;
         }
         T[i] = prod;
+    }
+    return 0;
+}
+
+/* Emission ray march through a temperature grid (Sec. 5, "Filtering
+ * nonlinear physical properties"): an emitting, non-absorbing medium, so the
+ * radiance a ray gathers is dt * sum over its steps of the step's emission
+ * at three wavelengths.  The step's emission is B(sum_i w_i T_i) before
+ * shading, sum_i w_i B(T_i) after, and B(T_j) of the one picked voxel in the
+ * stochastic mode (mean over samples).  Picks, keys and raster positions as
+ * in the transmittance ray march.  L: n x 3; a ray that misses reads 0, a
+ * ray with a non-finite value or an overflowing raster position NaN. */
+static void emission_one(const grid3d *g, const float *r, int64_t ri, int steps, int filter, int mode, int spp,
+                         uint32_t seed, int variant, double *L, int32_t *tp)
+{
+    ray_setup rs = setup_ray(g, r, steps);
+    if (!rs.ok || rs.empty) {
+        if (tp && mode == M_STOCH)
+            for (int64_t k = 0; k < (int64_t)3 * spp * steps; ++k)
+                tp[k] = INT32_MIN;
+        for (int c = 0; c < 3; ++c)
+            L[c] = rs.ok ? 0.0 : NAN;
+        return;
+    }
+    const double dt = (double)rs.dt;
+    const int off = filter == F_BSPLINE3 ? -1 : 0;
+    double e[3], acc[3] = {0.0, 0.0, 0.0};
+    if (mode == M_STOCH) {
+        for (int s = 0; s < spp; ++s)
+            for (int k = 0; k < steps; ++k) {
+                int i0[3], j[3];
+                float t[3];
+                step_pos(&rs, k, i0, t);
+                uint32_t key[4] = {(uint32_t)ri, (uint32_t)s, (uint32_t)k, seed}, w[4];
+                orc_pcg4d(key, w);
+                pick3(filter, t, w, variant, j);
+                int x = i0[0] + off + j[0], y = i0[1] + off + j[1], z = i0[2] + off + j[2];
+                if (tp) {
+                    int32_t *q = tp + ((int64_t)s * steps + k) * 3;
+                    q[0] = x;
+                    q[1] = y;
+                    q[2] = z;
+                }
+                planck3(fetch3d(g, x, y, z), e);
+                for (int c = 0; c < 3; ++c)
+                    acc[c] += e[c];
+            }
+        for (int c = 0; c < 3; ++c)
+            L[c] = dt * acc[c] / (double)spp;
+        return;
+    }
+    for (int k = 0; k < steps; ++k) {
+        int i0[3], o[3], nt[3];
+        float t[3];
+        double w[3][4], sum[3] = {0.0, 0.0, 0.0};
+        step_pos(&rs, k, i0, t);
+        for (int a = 0; a < 3; ++a)
+            nt[a] = axis_weights(filter, (double)t[a], &o[a], w[a]);
+        for (int c = 0; c < nt[2]; ++c)
+            for (int b = 0; b < nt[1]; ++b)
+                for (int a = 0; a < nt[0]; ++a) {
+                    double wgt = w[0][a] * w[1][b] * w[2][c];
+                    double T = fetch3d(g, i0[0] + o[0] + a, i0[1] + o[1] + b, i0[2] + o[2] + c);
+                    if (mode == M_BEFORE) {
+                        sum[0] += wgt * T;
+                    } else {
+                        planck3(T, e);
+                        for (int q = 0; q < 3; ++q)
+                            sum[q] += wgt * e[q];
+                    }
+                }
+        if (mode == M_BEFORE)
+            planck3(sum[0], sum);
+        for (int c = 0; c < 3; ++c)
+            acc[c] += sum[c];
+    }
+    for (int c = 0; c < 3; ++c)
+        L[c] = dt * acc[c];
+}
+
+ORC_EXPORT int orc_raymarch_emission(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
+                                     const float *scale, const float *rays, int64_t n, int steps, int filter,
+                                     int mode, int spp, uint32_t seed, int variant, double *L, int32_t *taps,
+                                     const int64_t *subset, int64_t nsub)
+{
+    grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
+    int64_t m = subset ? nsub : n;
+    int64_t per = (int64_t)3 * spp * steps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t ri = subset ? subset[i] : i;
+        emission_one(&g, rays + 8 * ri, ri, steps, filter, mode, spp, seed, variant, L + 3 * i,
+                     taps ? taps + per * i : NULL);
+    }
+    return 0;
+}
+
+/* Exact expectation of the stochastic emission with independent uniforms:
+ * dt * sum_k sum_taps P(tap) B(T_tap), with the exact 24-bit pick
+ * probabilities. */
+ORC_EXPORT int orc_raymarch_emission_expect(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
+                                            const float *scale, const float *rays, int64_t n, int steps,
+                                            int filter, double *L)
+{
+    grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        ray_setup rs = setup_ray(&g, rays + 8 * i, steps);
+        if (!rs.ok || rs.empty) {
+            for (int c = 0; c < 3; ++c)
+                L[3 * i + c] = rs.ok ? 0.0 : NAN;
+            continue;
+        }
+        int off = filter == F_BSPLINE3 ? -1 : 0;
+        int ntap = filter == F_BSPLINE3 ? 4 : (filter == F_LINEAR ? 2 : 1);
+        double acc[3] = {0.0, 0.0, 0.0}, e[3];
+        for (int k = 0; k < steps; ++k) {
+            int i0[3];
+            float t[3];
+            double P[3][4];
+            step_pos(&rs, k, i0, t);
+            int near[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a) {
+                orc_pick_pmf(filter, t[a], P[a]);
+                if (filter == F_NEAREST)
+                    near[a] = t[a] >= 0.5f;
+            }
+            for (int c = 0; c < ntap; ++c)
+                for (int b = 0; b < ntap; ++b)
+                    for (int a = 0; a < ntap; ++a) {
+                        double pr = P[0][a] * P[1][b] * P[2][c];
+                        if (pr == 0.0)
+                            continue;
+                        planck3(fetch3d(&g, i0[0] + off + a + near[0], i0[1] + off + b + near[1],
+                                        i0[2] + off + c + near[2]), e);
+                        for (int q = 0; q < 3; ++q)
+                            acc[q] += pr * e[q];
+                    }
+        }
+        for (int c = 0; c < 3; ++c)
+            L[3 * i + c] = (double)rs.dt * acc[c];
     }
     return 0;
 }

@@ -373,6 +373,18 @@ def cloud_grid(n: int = 512, seed: int = 4, device: str = "cpu", octaves: int = 
     return sig.to(torch.float16)
 
 
+def temperature_grid(density, t_min: float = 800.0, t_max: float = 6000.0):
+    """Temperature field (kelvin, float16, same shape) of a fire shaped like a
+    density cloud: 0 where the density is 0 (no emission), else
+    t_min + (t_max - t_min) sqrt(sigma / max sigma).  Computed in float32,
+    rounded once to float16 (spacing 4 K near 6000 K)."""
+    import torch
+    d = density.to(torch.float32)
+    peak = float(d.max())
+    T = t_min + (t_max - t_min) * torch.sqrt(d / peak if peak > 0 else d)
+    return torch.where(d > 0, T, torch.zeros_like(T)).to(torch.float16)
+
+
 def constant_grid(n: int, value: float, device: str = "cpu"):
     import torch
     return torch.full((n, n, n), value, dtype=torch.float16, device=device)
