@@ -113,7 +113,15 @@ enum { SF_WRAP_REPEAT = 0, SF_WRAP_CLAMP = 1 };
  * (a stochastic mode picks ONE of them with those probabilities). */
 enum { SF_MIP_NONE = 0, SF_MIP_NEAREST = 1, SF_MIP_LINEAR = 2 };
 enum { SF_SHADE_NONE = 0, SF_SHADE_GGX = 1 };             /* 2-D */
-enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1 }; /* 3-D points */
+enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1, SF_SHADE_PLANCK = 2 }; /* 3-D points */
+/* SF_SHADE_PLANCK: the grid holds temperatures in kelvin, shaded by black-body
+ * emission (Sec. 5 "Filtering nonlinear physical properties"): the spectral
+ * radiance in W sr^-1 m^-2 nm^-1 at the three wavelengths 700, 546.1 and
+ * 435.8 nm (the CIE 1931 RGB primaries),
+ *   B(lambda, T) = 2 h c^2 / (lambda^5 (exp(h c / (lambda k T)) - 1)) * 1e-9,
+ * lambda in metres, exact SI h, c, k; T <= 0 emits nothing, NaN gives NaN.
+ * Values (not decisions) in binary32 on the transcendental unit: relative
+ * error about (x + 3) * 2^-24, x = h c / (lambda k T). */
 
 typedef struct sf_sampling {
     int32_t filter;      /* SF_NEAREST .. SF_EWA (see above)                         */
@@ -342,8 +350,11 @@ sf_status sf_triplanar(const sf_tex2d *tex, const float *queries, int64_t n, con
  * sf_filter3d — filtered point lookups in a density grid.
  *   pos     : n x {x, y, z} float32 world positions.
  *   shade   : SF_SHADE_DENSITY -> out[i] = filtered sigma;
- *             SF_SHADE_TRANSMITTANCE -> out[i] = filtered exp(-sigma*ds).
- *   out     : n float32.
+ *             SF_SHADE_TRANSMITTANCE -> out[i] = filtered exp(-sigma*ds);
+ *             SF_SHADE_PLANCK -> out[3i..3i+2] = B at the three wavelengths
+ *             of the filtered temperature (before) / filtered B (after) /
+ *             mean B of the picked voxels (stochastic).
+ *   out     : n float32 (n x 3 for SF_SHADE_PLANCK).
  *   dbg_taps: NULL, or n x spp x {x, y, z} int32 raw tap indices (before the
  *             zero-outside rule), stochastic mode only.
  * Points whose raster coordinate exceeds 2^22 in magnitude give NaN.
@@ -379,6 +390,29 @@ sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const s
  */
 sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_t steps,
                       const sf_sampling *smp, float *T, int32_t *dbg_taps, void *stream);
+
+/*
+ * sf_raymarch_emission — radiance gathered along rays through an emitting,
+ * non-absorbing grid of temperatures (kelvin), shaded by black-body emission
+ * (Sec. 5 "Filtering nonlinear physical properties": filtering the
+ * temperatures before Planck's law differs from filtering the emission
+ * after it, and the stochastic filter gives the latter with one voxel per
+ * step).
+ *   rays, steps: as sf_raymarch (same raster positions, keys and picks).
+ *   L    : n x 3 float32, the radiance at 700, 546.1, 435.8 nm (see
+ *          SF_SHADE_PLANCK) integrated over the segment: dt * sum_k E_k with
+ *          SF_STOCHASTIC: E_k = B(T_j) of the one picked voxel (mean over spp);
+ *          SF_BEFORE: E_k = B(sum_i w_i T_i); SF_AFTER_EXACT: sum_i w_i B(T_i).
+ *          Sums in float64.  An empty segment gives 0.
+ *   dbg_taps: NULL, or n x spp x S x {x, y, z} int32 (stochastic only).
+ *   An occupancy mask (vol->occupancy, built by sf_build_occupancy from the
+ *   temperatures) skips bricks at 0 K exactly.
+ * Rays with a non-finite component, or whose raster positions exceed 2^22 in
+ * magnitude, give NaN.
+ * Errors: as sf_raymarch.
+ */
+sf_status sf_raymarch_emission(const sf_volume *vol, const float *rays, int64_t n, int32_t steps,
+                               const sf_sampling *smp, float *L, int32_t *dbg_taps, void *stream);
 
 /*
  * sf_build_occupancy — brick occupancy mask of a density grid for empty-space

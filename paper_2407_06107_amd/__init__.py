@@ -27,12 +27,13 @@ SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F, SF_DCT8 = 0, 1, 2, 3, 4
 SF_WRAP_REPEAT, SF_WRAP_CLAMP = 0, 1
 SF_MIP_NONE, SF_MIP_NEAREST, SF_MIP_LINEAR = 0, 1, 2
 SF_SHADE_NONE, SF_SHADE_GGX = 0, 1
-SF_SHADE_DENSITY, SF_SHADE_TRANSMITTANCE = 0, 1
+SF_SHADE_DENSITY, SF_SHADE_TRANSMITTANCE, SF_SHADE_PLANCK = 0, 1, 2
+PLANCK_NM = (700.0, 546.1, 435.8)
 SF_TAP_NONE = -(2 ** 31)
 SF_MAX_LEVELS = 16
 
 EXPORTED = ("sf_filter2d", "sf_filter2d_aniso", "sf_dct_layout", "sf_dct_encode", "sf_triplanar",
-            "sf_filter3d", "sf_raymarch", "sf_build_occupancy",
+            "sf_filter3d", "sf_raymarch", "sf_raymarch_emission", "sf_build_occupancy",
             "sf_occupancy_words", "sf_mlp_nparams", "sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
             "sf_neural_quantize", "sf_neural_train_step", "sf_neural_train_workspace",
             "sf_error_stats", "sf_error_stats_workspace", "sf_last_error", "sf_abi_version", "sf_rng_version")
@@ -105,6 +106,7 @@ def lib() -> C.CDLL:
         L.sf_triplanar.argtypes = [P, P, i64, P, C.c_float, i32, i32, P, P, P, P]
         L.sf_filter3d.argtypes = [P, P, i64, P, i32, C.c_float, P, P, P]
         L.sf_raymarch.argtypes = [P, P, i64, i32, P, P, P, P]
+        L.sf_raymarch_emission.argtypes = [P, P, i64, i32, P, P, P, P]
         L.sf_error_stats.argtypes = [P, P, i64, i32, P, P, C.c_size_t, P]
         L.sf_build_occupancy.argtypes = [P, P, i64, P]
         L.sf_build_occupancy.restype = i32
@@ -358,9 +360,10 @@ def sf_filter3d(vol: Volume, pos: torch.Tensor, smp: sf_sampling, shade: int = S
                 out: torch.Tensor | None = None, dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     _need(pos, torch.float32, "pos")
     n = pos.numel() // 3
+    ch = 3 if shade == SF_SHADE_PLANCK else 1
     if out is None:
-        out = torch.empty(n, dtype=torch.float32, device=pos.device)
-    _need(out, torch.float32, "out", n)
+        out = torch.empty((n, 3) if ch == 3 else n, dtype=torch.float32, device=pos.device)
+    _need(out, torch.float32, "out", n * ch)
     if dbg_taps is not None:
         _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * 3)
     _check(lib().sf_filter3d(C.byref(vol.desc), _ptr(pos), n, C.byref(smp), shade, ds, _ptr(out), _ptr(dbg_taps),
@@ -380,6 +383,23 @@ def sf_raymarch(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling, T
     _check(lib().sf_raymarch(C.byref(vol.desc), _ptr(rays), n, steps, C.byref(smp), _ptr(T), _ptr(dbg_taps),
                              _stream(stream)))
     return T
+
+
+def sf_raymarch_emission(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling,
+                         L: torch.Tensor | None = None, dbg_taps: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+    """Black-body emission gathered along rays through a temperature grid:
+    [n, 3] float32 at PLANCK_NM."""
+    _need(rays, torch.float32, "rays")
+    n = rays.numel() // 8
+    if L is None:
+        L = torch.empty((n, 3), dtype=torch.float32, device=rays.device)
+    _need(L, torch.float32, "L", 3 * n)
+    if dbg_taps is not None:
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * steps * 3)
+    _check(lib().sf_raymarch_emission(C.byref(vol.desc), _ptr(rays), n, steps, C.byref(smp), _ptr(L),
+                                      _ptr(dbg_taps), _stream(stream)))
+    return L
 
 
 def sf_occupancy_words(nx: int, ny: int, nz: int, brick_log2: int) -> int:

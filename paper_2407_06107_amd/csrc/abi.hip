@@ -427,7 +427,7 @@ sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const s
     sfk::Filter3DCall c{};
     if ((st = check_volume(vol, c.vol)) != SF_OK)
         return st;
-    if (shade != SF_SHADE_DENSITY && shade != SF_SHADE_TRANSMITTANCE)
+    if (shade != SF_SHADE_DENSITY && shade != SF_SHADE_TRANSMITTANCE && shade != SF_SHADE_PLANCK)
         return fail(SF_E_RANGE, "shade %d out of range", shade);
     if (!std::isfinite(ds))
         return fail(SF_E_RANGE, "ds must be finite");
@@ -479,6 +479,40 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
     c.T = T;
     c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
     return device_status(sfk::launch_raymarch(c, (hipStream_t)stream));
+}
+
+sf_status sf_raymarch_emission(const sf_volume *vol, const float *rays, int64_t n, int32_t steps,
+                               const sf_sampling *smp, float *L, int32_t *dbg_taps, void *stream)
+{
+    sf_status st;
+    if ((st = check_n(n)) != SF_OK)
+        return st;
+    if (steps < 1 || steps > SF_MAX_STEPS)
+        return fail(SF_E_RANGE, "steps %d outside 1..%d", steps, SF_MAX_STEPS);
+    if (n == 0)
+        return ok();
+    if (!rays || !L)
+        return fail(SF_E_NULL, "rays and L must be non-NULL");
+    if ((st = check_sampling(smp)) != SF_OK)
+        return st;
+    if (smp->filter > SF_BSPLINE3)
+        return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters are 2-D texture filters here");
+    sfk::RaymarchCall c{};
+    if ((st = check_volume(vol, c.vol)) != SF_OK)
+        return st;
+    if (!aligned(rays, 16) || !aligned(L, 4))
+        return fail(SF_E_RANGE, "rays must be 16-byte aligned, L 4-byte aligned");
+    c.rays = rays;
+    c.n = n;
+    c.steps = steps;
+    c.filter = smp->filter;
+    c.mode = smp->mode;
+    c.spp = smp->spp;
+    c.variant = smp->rng_variant;
+    c.seed = smp->seed;
+    c.T = L;
+    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    return device_status(sfk::launch_emission(c, (hipStream_t)stream));
 }
 
 int64_t sf_occupancy_words(int32_t nx, int32_t ny, int32_t nz, int32_t brick_log2)

@@ -98,7 +98,7 @@ struct RaymarchCall {
     int64_t n;
     int32_t steps, filter, mode, spp, variant;
     uint32_t seed;
-    float *T;
+    float *T;        // transmittance (n), or emission (n x 3)
     int32_t *taps;
 };
 
@@ -152,6 +152,7 @@ hipError_t launch_dct_encode(const DctEncodeCall &c, hipStream_t s);
 hipError_t launch_triplanar(const TriplanarCall &c, hipStream_t s);
 hipError_t launch_filter3d(const Filter3DCall &c, hipStream_t s);
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s);
+hipError_t launch_emission(const RaymarchCall &c, hipStream_t s);
 hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ, int64_t words, hipStream_t s);
 hipError_t launch_to_bf16(const float *in, int64_t n, uint16_t *out, hipStream_t s);
 hipError_t launch_quant_fp8(const float *lat, const LatentArgs &g, uint8_t *codes, float *scales, hipStream_t s);

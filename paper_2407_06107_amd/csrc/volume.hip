@@ -1,6 +1,8 @@
 // 3-D paths of libsf: transmittance ray marching through a density grid
 // (Sec. 5 "Offline rendering": density lookups with trilinear / tricubic
-// filters and their stochastic one-lookup forms) and filtered point lookups.
+// filters and their stochastic one-lookup forms), emission ray marching
+// through a temperature grid (Sec. 5 "Filtering nonlinear physical
+// properties") and filtered point lookups.
 //
 // One lane marches one ray.  The stochastic kernel is the hot path: per step
 // it forms the raster position, hashes (ray, sample, step, seed), picks one
@@ -114,6 +116,55 @@ __device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
         o[1] = pick_off_reuse<F>(t[1], u);
         o[2] = pick_off_reuse<F>(t[2], u);
     }
+}
+
+// Black-body emission (Sec. 5, "Filtering nonlinear physical properties"):
+// spectral radiance in W sr^-1 m^-2 nm^-1 at 700, 546.1 and 435.8 nm of a
+// temperature T in kelvin, B = A_l / (e^x - 1) with x = c2 / (lambda T).
+// e^x is evaluated as exp2(K_l / T) on the transcendental unit; below
+// x = 1/2 a degree-7 Taylor polynomial of e^x - 1 replaces the subtraction.
+// T <= 0 emits nothing, NaN stays NaN.  Binary32 values (not decisions):
+// the relative error is about (x + 3) ulp.
+struct PlanckConst {
+    static constexpr double h = 6.62607015e-34, c = 299792458.0, k = 1.380649e-23;
+    static constexpr double A(double nm)
+    {
+        return 2.0 * h * c * c / (nm * 1e-9 * nm * 1e-9 * nm * 1e-9 * nm * 1e-9 * nm * 1e-9) * 1e-9;
+    }
+    static constexpr double K(double nm) { return h * c / (nm * 1e-9 * k) * 1.4426950408889634074; }
+};
+
+__device__ __forceinline__ float planck_band(float r, float A, float K)
+{
+    const float y = K * r;   // x log2(e)
+    float em1;
+    if (y < 0.72134752f) {
+        const float x = y * 0.69314718f;
+        float p = __builtin_fmaf(x, 1.0f / 5040.0f, 1.0f / 720.0f);
+        p = __builtin_fmaf(x, p, 1.0f / 120.0f);
+        p = __builtin_fmaf(x, p, 1.0f / 24.0f);
+        p = __builtin_fmaf(x, p, 1.0f / 6.0f);
+        p = __builtin_fmaf(x, p, 0.5f);
+        p = __builtin_fmaf(x, p, 1.0f);
+        em1 = x * p;
+    } else {
+        em1 = __builtin_amdgcn_exp2f(y) - 1.0f;   // +inf beyond y = 128: B = 0
+    }
+    return A * __builtin_amdgcn_rcpf(em1);
+}
+
+__device__ __forceinline__ void planck3(float T, float B[3])
+{
+    constexpr float A0 = (float)PlanckConst::A(700.0), A1 = (float)PlanckConst::A(546.1),
+                    A2 = (float)PlanckConst::A(435.8);
+    constexpr float K0 = (float)PlanckConst::K(700.0), K1 = (float)PlanckConst::K(546.1),
+                    K2 = (float)PlanckConst::K(435.8);
+    float r = __builtin_amdgcn_rcpf(T);
+    r = __builtin_fmaf(__builtin_fmaf(-T, r, 1.0f), r, r);   // one Newton step
+    const bool cold = T <= 0.0f;
+    B[0] = cold ? 0.0f : planck_band(r, A0, K0);
+    B[1] = cold ? 0.0f : planck_band(r, A1, K1);
+    B[2] = cold ? 0.0f : planck_band(r, A2, K2);
 }
 
 // ---------------------------------------------------------------- ray march
@@ -238,7 +289,223 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
     c.T[i] = MODE == BEFORE ? (float)exp(-(double)g.dt * tau) : (float)Tp;
 }
 
+// ------------------------------------------------------------ emission march
+// An emitting, non-absorbing medium of temperatures: a ray gathers
+// dt * sum_k E_k at three wavelengths, E_k the step's emission.  Stochastic:
+// E_k = B(T) of the one voxel the step picks (keys, picks and the occupancy
+// skip as in the transmittance march; empty bricks emit nothing).  The sums
+// run in binary64.
+template <int F, bool HALF, int VAR, bool DBG, bool OCC, bool P2>
+__global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_pad)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
+    if (i >= c.n)
+        return;
+    RayGeom g;
+    int st = ray_setup_dev(c.vol.wmin, c.vol.scale, c.rays + 8 * i, c.steps, g);
+    if (st != 0) {
+        const float v = st == 1 ? 0.0f : __builtin_nanf("");
+        c.T[3 * i] = v;
+        c.T[3 * i + 1] = v;
+        c.T[3 * i + 2] = v;
+        if constexpr (DBG) {
+            int64_t per = (int64_t)3 * c.spp * c.steps;
+            for (int64_t k = 0; k < per; ++k)
+                c.taps[per * i + k] = SF_TAP_NONE;
+        }
+        return;
+    }
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
+                                                                  (int)c.vol.bytes, kBufferFlags);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < c.spp; ++s) {
+        StepHash h;
+        h.init((uint32_t)i, (uint32_t)s, c.seed);
+        uint32_t pend = 0;
+        bool pend_ok = false;
+        float kh = 0.5f;
+        for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
+            int i0[3], o[3];
+            float t[3];
+            step_coords(g, kh, i0, t);
+            if constexpr (OCC) {
+                if (!brick_occupied(c.vol, i0))
+                    continue;
+            }
+            pick3<F, VAR>(t, h.at((uint32_t)k), o);
+            int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
+            if constexpr (DBG) {
+                int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
+                tp[0] = x;
+                tp[1] = y;
+                tp[2] = z;
+            }
+            bool ok;
+            const uint32_t off = voxel_offset<HALF, P2>(c.vol, x, y, z, ok);
+            float B[3];
+            planck3(bits_value<HALF>(masked_bits(pend, pend_ok)), B);   // step k-1
+            acc[0] += (double)B[0];
+            acc[1] += (double)B[1];
+            acc[2] += (double)B[2];
+            pend = voxel_bits<HALF>(rs, off);                            // step k
+            pend_ok = ok;
+        }
+        float B[3];
+        planck3(bits_value<HALF>(masked_bits(pend, pend_ok)), B);
+        acc[0] += (double)B[0];
+        acc[1] += (double)B[1];
+        acc[2] += (double)B[2];
+    }
+    const double sc = (double)g.dt / (double)c.spp;
+    c.T[3 * i] = (float)(acc[0] * sc);
+    c.T[3 * i + 1] = (float)(acc[1] * sc);
+    c.T[3 * i + 2] = (float)(acc[2] * sc);
+}
+
+// Deterministic emission: E_k = B(sum_i w_i T_i) before shading,
+// sum_i w_i B(T_i) after; binary64 weights and sums.
+template <int F, bool HALF, int MODE, bool OCC>
+__global__ __launch_bounds__(256) void k_emit_det(RaymarchCall c, uint32_t nb_pad)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
+    if (i >= c.n)
+        return;
+    RayGeom g;
+    int st = ray_setup_dev(c.vol.wmin, c.vol.scale, c.rays + 8 * i, c.steps, g);
+    if (st != 0) {
+        const float v = st == 1 ? 0.0f : __builtin_nanf("");
+        c.T[3 * i] = v;
+        c.T[3 * i + 1] = v;
+        c.T[3 * i + 2] = v;
+        return;
+    }
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
+                                                                  (int)c.vol.bytes, kBufferFlags);
+    constexpr int NT = Taps<F>::n;
+    constexpr int F0 = Taps<F>::first;
+    double acc[3] = {0.0, 0.0, 0.0};
+    float kh = 0.5f;
+    for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
+        int i0[3];
+        float t[3];
+        double wx[4], wy[4], wz[4];
+        step_coords(g, kh, i0, t);
+        if constexpr (OCC) {
+            if (!brick_occupied(c.vol, i0))
+                continue;   // every tap is 0 K: no emission either way
+        }
+        if constexpr (F == NEAREST) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                i0[a] += t[a] >= 0.5f;
+        }
+        axis_weights64<F>(t[0], wx);
+        axis_weights64<F>(t[1], wy);
+        axis_weights64<F>(t[2], wz);
+        double e[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int cz = 0; cz < NT; ++cz) {
+#pragma unroll
+            for (int by = 0; by < NT; ++by) {
+                const double wyz = wy[by] * wz[cz];
+#pragma unroll
+                for (int ax = 0; ax < NT; ++ax) {
+                    const float T = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
+                    const double w = wx[ax] * wyz;
+                    if constexpr (MODE == BEFORE) {
+                        e[0] = __builtin_fma(w, (double)T, e[0]);
+                    } else {
+                        float B[3];
+                        planck3(T, B);
+                        e[0] = __builtin_fma(w, (double)B[0], e[0]);
+                        e[1] = __builtin_fma(w, (double)B[1], e[1]);
+                        e[2] = __builtin_fma(w, (double)B[2], e[2]);
+                    }
+                }
+            }
+        }
+        if constexpr (MODE == BEFORE) {
+            float B[3];
+            planck3((float)e[0], B);
+            acc[0] += (double)B[0];
+            acc[1] += (double)B[1];
+            acc[2] += (double)B[2];
+        } else {
+            acc[0] += e[0];
+            acc[1] += e[1];
+            acc[2] += e[2];
+        }
+    }
+    const double dt = (double)g.dt;
+    c.T[3 * i] = (float)(acc[0] * dt);
+    c.T[3 * i + 1] = (float)(acc[1] * dt);
+    c.T[3 * i + 2] = (float)(acc[2] * dt);
+}
+
 // ------------------------------------------------------------- point lookups
+// Point lookups shaded by black-body emission: out is n x 3.
+template <int F, bool HALF>
+__device__ void filter3d_planck(const Filter3DCall &c, int64_t i, int i0[3], const float t[3],
+                                __amdgpu_buffer_rsrc_t rs)
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (c.mode == STOCH) {
+        for (int s = 0; s < c.spp; ++s) {
+            uint4 w4 = pcg4d(make_uint4((uint32_t)i, (uint32_t)s, 0u, c.seed));
+            uint3 w = make_uint3(w4.x, w4.y, w4.z);
+            int o[3];
+            if (c.variant == 0)
+                pick3<F, 0>(t, w, o);
+            else
+                pick3<F, 1>(t, w, o);
+            int tx = i0[0] + o[0], ty = i0[1] + o[1], tz = i0[2] + o[2];
+            if (c.taps) {
+                int32_t *tp = c.taps + ((int64_t)i * c.spp + s) * 3;
+                tp[0] = tx;
+                tp[1] = ty;
+                tp[2] = tz;
+            }
+            float B[3];
+            planck3(voxel<HALF>(rs, c.vol, tx, ty, tz), B);
+            for (int k = 0; k < 3; ++k)
+                acc[k] += (double)B[k];
+        }
+        for (int k = 0; k < 3; ++k)
+            c.out[3 * i + k] = (float)(acc[k] / (double)c.spp);
+        return;
+    }
+    constexpr int NT = Taps<F>::n;
+    constexpr int F0 = Taps<F>::first;
+    if constexpr (F == NEAREST) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            i0[a] += t[a] >= 0.5f;
+    }
+    double wx[4], wy[4], wz[4];
+    axis_weights64<F>(t[0], wx);
+    axis_weights64<F>(t[1], wy);
+    axis_weights64<F>(t[2], wz);
+    for (int cz = 0; cz < NT; ++cz)
+        for (int by = 0; by < NT; ++by)
+            for (int ax = 0; ax < NT; ++ax) {
+                const double wgt = wx[ax] * wy[by] * wz[cz];
+                const float T = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
+                if (c.mode == BEFORE) {
+                    acc[0] += wgt * (double)T;
+                } else {
+                    float B[3];
+                    planck3(T, B);
+                    for (int k = 0; k < 3; ++k)
+                        acc[k] += wgt * (double)B[k];
+                }
+            }
+    float B[3];
+    if (c.mode == BEFORE)
+        planck3((float)acc[0], B);
+    for (int k = 0; k < 3; ++k)
+        c.out[3 * i + k] = c.mode == BEFORE ? B[k] : (float)acc[k];
+}
+
 template <int F, bool HALF>
 __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
 {
@@ -254,7 +521,9 @@ __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
         ok &= __builtin_fabsf(p[a]) <= 4194304.0f;
     }
     if (!ok) {
-        c.out[i] = __builtin_nanf("");
+        const int ch = c.shade == SF_SHADE_PLANCK ? 3 : 1;
+        for (int k = 0; k < ch; ++k)
+            c.out[ch * i + k] = __builtin_nanf("");
         if (c.taps && c.mode == STOCH)
             for (int k = 0; k < 3 * c.spp; ++k)
                 c.taps[(int64_t)3 * c.spp * i + k] = SF_TAP_NONE;
@@ -271,6 +540,10 @@ __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
     const bool trans = c.shade == SF_SHADE_TRANSMITTANCE;
+    if (c.shade == SF_SHADE_PLANCK) {
+        filter3d_planck<F, HALF>(c, i, i0, t, rs);
+        return;
+    }
     if (c.mode == STOCH) {
         double acc = 0.0;
         for (int s = 0; s < c.spp; ++s) {
@@ -412,6 +685,61 @@ static hipError_t launch_ray_f(const RaymarchCall &c, hipStream_t s)
             launch_ray_fo<F, HALF, false, false>(c, grid, s, nb_pad);
     }
     return hipGetLastError();
+}
+
+template <int F, bool HALF, bool OCC, bool P2>
+static void launch_emit_fo(const RaymarchCall &c, dim3 grid, hipStream_t s, uint32_t nb_pad)
+{
+    dim3 block(256);
+    if (c.mode == STOCH) {
+        if (c.variant)
+            k_emit_stoch<F, HALF, 1, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_emit_stoch<F, HALF, 0, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
+    } else if (c.mode == BEFORE) {
+        k_emit_det<F, HALF, BEFORE, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+    } else {
+        k_emit_det<F, HALF, AFTER, OCC><<<grid, block, 0, s>>>(c, nb_pad);
+    }
+}
+
+template <int F, bool HALF>
+static hipError_t launch_emit_f(const RaymarchCall &c, hipStream_t s)
+{
+    uint32_t nb = blocks_for(c.n);
+    uint32_t nb_pad = (nb + 7u) & ~7u;
+    dim3 grid(nb_pad), block(256);
+    const bool p2 = c.vol.lx >= 0;
+    if (c.mode == STOCH && c.taps) {
+        if (c.variant)
+            k_emit_stoch<F, HALF, 1, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_emit_stoch<F, HALF, 0, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
+    } else if (c.vol.occ) {
+        if (p2)
+            launch_emit_fo<F, HALF, true, true>(c, grid, s, nb_pad);
+        else
+            launch_emit_fo<F, HALF, true, false>(c, grid, s, nb_pad);
+    } else {
+        if (p2)
+            launch_emit_fo<F, HALF, false, true>(c, grid, s, nb_pad);
+        else
+            launch_emit_fo<F, HALF, false, false>(c, grid, s, nb_pad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_emission(const RaymarchCall &c, hipStream_t s)
+{
+    const bool half = c.vol.fmt == SF_R16F;
+    switch (c.filter) {
+    case NEAREST:
+        return half ? launch_emit_f<NEAREST, true>(c, s) : launch_emit_f<NEAREST, false>(c, s);
+    case LINEAR:
+        return half ? launch_emit_f<LINEAR, true>(c, s) : launch_emit_f<LINEAR, false>(c, s);
+    default:
+        return half ? launch_emit_f<BSPLINE3, true>(c, s) : launch_emit_f<BSPLINE3, false>(c, s);
+    }
 }
 
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s)

@@ -84,9 +84,10 @@ FAKE = C.c_void_p(0x10000)   # a host-side stand-in pointer: never dereferenced,
     ("n_negative", 2), ("n_zero", 0), ("null_rays", 1), ("steps_zero", 2), ("steps_big", 2),
     ("bad_filter", 2), ("bad_mode", 2), ("spp_zero", 2), ("bad_variant", 2), ("null_volume", 1),
     ("bad_format", 3), ("dims_zero", 2), ("scale_zero", 2), ("misaligned_rays", 2), ("n_huge", 2),
-    ("bad_brick", 2), ("reserved", 2),
+    ("bad_brick", 2), ("reserved", 2), ("keys", 3),
 ])
-def test_raymarch_validation(sf, case, status):
+@pytest.mark.parametrize("entry", ["sf_raymarch", "sf_raymarch_emission"])
+def test_raymarch_validation(sf, case, status, entry):
     L = sf.lib()
     smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1)
     vol = _vol(sf)
@@ -126,7 +127,9 @@ def test_raymarch_validation(sf, case, status):
         vol.brick_log2 = 9
     elif case == "reserved":
         vol.reserved = 1
-    st = L.sf_raymarch(C.byref(vol) if vol is not None else None, rays, n, steps, C.byref(smp), T, None, None)
+    elif case == "keys":
+        smp.filter = sf.SF_KEYS3
+    st = getattr(L, entry)(C.byref(vol) if vol is not None else None, rays, n, steps, C.byref(smp), T, None, None)
     assert st == status, sf.sf_last_error()
     if status:
         assert sf.sf_last_error()
@@ -315,7 +318,7 @@ def test_filter3d_validation(sf):
     L = sf.lib()
     smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)
     vol = _vol(sf)
-    assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(smp), 2, 1.0, FAKE, None, None) == 2
+    assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(smp), 3, 1.0, FAKE, None, None) == 2
     assert L.sf_filter3d(C.byref(vol), FAKE, 3, C.byref(smp), 1, float("nan"), FAKE, None, None) == 2
     assert L.sf_filter3d(C.byref(vol), None, 3, C.byref(smp), 0, 1.0, FAKE, None, None) == 1
     big = _vol(sf, nx=4096, ny=4096, nz=256)     # 8 GiB: beyond one 32-bit-offset buffer
