@@ -284,6 +284,53 @@ def aniso_bench(res):
     res["config2_aniso"] = ca
 
 
+def planck_bench(res):
+    """Emission: the 512^3 cloud as a fire of temperatures (0 K where the
+    density is 0, else 800-6000 K), 1 Mi orthographic rays x 256 steps,
+    black-body emission at 700 / 546.1 / 435.8 nm, occupancy mask.  Filtering
+    the temperatures before Planck's law against filtering the emission
+    after it, and the stochastic filter's one voxel per step."""
+    import torch
+    import oracle
+    import paper_2407_06107_amd as sf
+    from paper_2407_06107_amd import inputs
+
+    log("emission: temperature grid and rays")
+    dens = inputs.cloud_grid(GRID, seed=4, device="cuda")
+    temp = inputs.temperature_grid(dens)
+    del dens
+    rays = inputs.ortho_rays(N_PIX, RAYS_PER_PIX, side=SIDE, seed=11)
+    rd = torch.from_numpy(rays).cuda()
+    n = rays.shape[0]
+    vol = sf.Volume(temp, side=SIDE, brick_log2=BRICK_LOG2)
+    L = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    ce = {"rays": n, "steps": STEPS, "wavelengths_nm": list(sf.PLANCK_NM)}
+    outs = {}
+    for name, filt, mode in (("tricubic_stochastic", sf.SF_BSPLINE3, sf.SF_STOCHASTIC),
+                             ("trilinear_stochastic", sf.SF_LINEAR, sf.SF_STOCHASTIC),
+                             ("tricubic_after_64tap", sf.SF_BSPLINE3, sf.SF_AFTER_EXACT),
+                             ("tricubic_before_64tap", sf.SF_BSPLINE3, sf.SF_BEFORE),
+                             ("trilinear_after_8tap", sf.SF_LINEAR, sf.SF_AFTER_EXACT),
+                             ("trilinear_before_8tap", sf.SF_LINEAR, sf.SF_BEFORE)):
+        smp = sf.sampling(filt, mode, 1, seed=7)
+        t = time_launches(lambda: sf.sf_raymarch_emission(vol, rd, STEPS, smp, L=L), 5, 2, torch)
+        outs[name] = L.double().cpu().numpy().copy()
+        ce[name] = {"ms": t, "ray_steps_per_s": n * STEPS / (t * 1e-3)}
+    # pixel values (16 rays per pixel) against the tricubic filter-after pixel values
+    P = N_PIX * N_PIX
+    ref = outs["tricubic_after_64tap"].reshape(P, RAYS_PER_PIX, 3).mean(1)
+    scale = np.sqrt(np.mean(ref ** 2, axis=0))
+    for name, v in outs.items():
+        pix = v.reshape(P, RAYS_PER_PIX, 3).mean(1)
+        ce[name]["relative_rmse_vs_tricubic_after"] = [float(x) for x in
+                                                       np.sqrt(np.mean((pix - ref) ** 2, axis=0)) / scale]
+    ce["note"] = ("relative_rmse_vs_tricubic_after: RMSE over 65,536 pixels (16 rays each) per wavelength, "
+                  "divided by the RMS of the reference pixels; the before rows' error is the bias of filtering "
+                  "temperatures before the nonlinear shading, the stochastic rows' is variance")
+    ce["speedup_stochastic_vs_after"] = ce["tricubic_after_64tap"]["ms"] / ce["tricubic_stochastic"]["ms"]
+    res["emission"] = ce
+
+
 def texture_bench(args, res):
     """Configs 1 and 2: the 2-D path (magnification of a 64^2 RGBA32F texture;
     a 4096^2 RGBA8 pyramid seen by a 1920x1080 camera), GGX + Lambert."""
@@ -439,6 +486,7 @@ def neural_bench(args):
     rng = np.random.default_rng(5)
     res = {}
     texture_bench(args, res)
+    planck_bench(res)
 
     # ---- config 4: 1024^2 x 8 BF16 latent texture of the 64^2 RGBA32F texture
     log("config 4: targets and training")
@@ -572,6 +620,7 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="configs 1, 2 (2-D path), 4 and 5 (neural forms): one JSON line beside the headline run")
     ap.add_argument("--suite-aniso", action="store_true", help="only the anisotropic section of the suite")
+    ap.add_argument("--suite-planck", action="store_true", help="only the emission section of the suite")
     ap.add_argument("--epochs4", type=int, default=200)
     ap.add_argument("--epochs5", type=int, default=60)
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -582,9 +631,12 @@ def main():
               f"a split of the ray stream, described in DESIGN.md). --gpus {args.gpus} is not supported.",
               file=sys.stderr)
         sys.exit(2)
-    if args.suite_aniso:
+    if args.suite_aniso or args.suite_planck:
         res = {}
-        aniso_bench(res)
+        if args.suite_aniso:
+            aniso_bench(res)
+        if args.suite_planck:
+            planck_bench(res)
         print(json.dumps(res))
         return
     if args.suite:
