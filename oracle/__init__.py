@@ -115,7 +115,8 @@ def lib():
                                    P, P, P, i64]
         L.orc_raymarch_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
         L.orc_raymarch_emission.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, i32, i32, u32,
-                                            i32, P, P, P, i64]
+                                            i32, f32, P, P, P, i64]
+        L.orc_perp_jitter.argtypes = [P, P, P, i32, f32, i64, i32, i32, u32, P]
         L.orc_raymarch_emission_expect.argtypes = [P, i32, i32, i32, i32, P, P, P, i64, i32, i32, P]
         L.orc_planck.argtypes = [C.c_double, C.c_double]
         L.orc_planck.restype = C.c_double
@@ -554,9 +555,11 @@ def planck(lambda_nm: float, T: float) -> float:
 
 
 def raymarch_emission(g: Grid, rays: np.ndarray, steps: int, filt: int, mode: int, spp: int = 1, seed: int = 0,
-                      variant: int = 0, taps: bool = False, subset=None):
+                      variant: int = 0, taps: bool = False, subset=None, footprint: float = 0.0):
     """Emission gathered along rays through a temperature grid: [m, 3]
-    (700, 546.1, 435.8 nm)."""
+    (700, 546.1, 435.8 nm); ``footprint`` > 0 (stochastic) jitters every
+    step by a Gaussian of that standard deviation (world units)
+    perpendicular to the ray."""
     rays = _c(rays, np.float32).reshape(-1, 8)
     n = rays.shape[0]
     sub = None if subset is None else _c(subset, np.int64)
@@ -564,9 +567,17 @@ def raymarch_emission(g: Grid, rays: np.ndarray, steps: int, filt: int, mode: in
     L = np.zeros((m, 3))
     tp = np.zeros((m, spp, steps, 3), dtype=np.int32) if taps else None
     lib().orc_raymarch_emission(_p(g.data), g.nx, g.ny, g.nz, g.fmt, _p(g.wmin), _p(g.scale), _p(rays), n, steps,
-                                filt, mode, spp, seed & 0xFFFFFFFF, variant, _p(L), _p(tp), _p(sub),
-                                0 if sub is None else sub.size)
+                                filt, mode, spp, seed & 0xFFFFFFFF, variant, float(footprint), _p(L), _p(tp),
+                                _p(sub), 0 if sub is None else sub.size)
     return (L, tp) if taps else L
+
+
+def perp_jitter(g: Grid, ray, steps: int, sigma: float, ri: int, s: int, k: int, seed: int) -> np.ndarray:
+    """Jittered raster position of step k of a ray (sample s)."""
+    out = np.zeros(3, dtype=np.float32)
+    r = _c(ray, np.float32)
+    lib().orc_perp_jitter(_p(g.wmin), _p(g.scale), _p(r), steps, float(sigma), ri, s, k, seed & 0xFFFFFFFF, _p(out))
+    return out
 
 
 def raymarch_emission_expect(g: Grid, rays: np.ndarray, steps: int, filt: int):

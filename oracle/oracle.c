@@ -2273,10 +2273,70 @@ ORC_EXPORT int orc_raymarch_expect(const void *base, int nx, int ny, int nz, int
  * at three wavelengths.  The step's emission is B(sum_i w_i T_i) before
  * shading, sum_i w_i B(T_i) after, and B(T_j) of the one picked voxel in the
  * stochastic mode (mean over samples).  Picks, keys and raster positions as
- * in the transmittance ray march.  L: n x 3; a ray that misses reads 0, a
- * ray with a non-finite value or an overflowing raster position NaN. */
+ * in the transmittance ray march; with a footprint sigma > 0 (stochastic
+ * only) each step's position is first jittered by the perpendicular
+ * Gaussian below.  L: n x 3; a ray that misses reads 0, a ray with a
+ * non-finite value or an overflowing raster position NaN. */
+/* Gaussian footprint perpendicular to a ray (Sec. 5: filtering after
+ * shading under minification with a Gaussian in the plane perpendicular to
+ * the ray).  Basis of that plane from the unit direction d by the branchless
+ * construction of Duff et al., "Building an Orthonormal Basis, Revisited"
+ * (JCGT 6(1), 2017), binary32:
+ *   sg = copysign(1, d_z), a = -1/(sg + d_z), b = (d_x d_y) a,
+ *   e1 = (1 + ((sg d_x) d_x) a, sg b, -sg d_x), e2 = (b, sg + (d_y d_y) a, -d_y);
+ * raster-space axes A_i = (sigma e1_i) scale_i, B_i = (sigma e2_i) scale_i.
+ * Per step, the key (ray, sample | 2^31, step, seed) gives u0, u1 (words 0,
+ * 1); Box-Muller with the contract ln and cos/sin: r = sqrt(-2 ln(1 - u0)),
+ * g1 = r cos(2 pi u1), g2 = r sin(2 pi u1); the step's raster position p
+ * becomes fma(g2, B, fma(g1, A, p)) before the tap pick. */
+typedef struct {
+    float A[3], B[3];
+} perp_frame;
+
+static perp_frame perp_setup(const grid3d *g, const float *r, float sigma)
+{
+    const float dx = r[3], dy = r[4], dz = r[5];
+    const float sg = copysignf(1.0f, dz);
+    const float a = -1.0f / (sg + dz);
+    const float b = (dx * dy) * a;
+    const float e1[3] = {1.0f + ((sg * dx) * dx) * a, sg * b, -sg * dx};
+    const float e2[3] = {b, sg + (dy * dy) * a, -dy};
+    perp_frame f;
+    for (int i = 0; i < 3; ++i) {
+        f.A[i] = (sigma * e1[i]) * g->scale[i];
+        f.B[i] = (sigma * e2[i]) * g->scale[i];
+    }
+    return f;
+}
+
+static void perp_jitter(const perp_frame *f, int64_t ri, int s, int k, uint32_t seed, float p[3])
+{
+    uint32_t key[4] = {(uint32_t)ri, (uint32_t)s | 0x80000000u, (uint32_t)k, seed}, w[4];
+    orc_pcg4d(key, w);
+    const float u0 = uniform24(w[0]), u1 = uniform24(w[1]);
+    const float rr = sqrtf(-2.0f * orc_lnc(1.0f - u0));
+    float c, sn;
+    orc_sincos2pi(u1, &c, &sn);
+    const float g1 = rr * c, g2 = rr * sn;
+    for (int i = 0; i < 3; ++i)
+        p[i] = fmaf(g2, f->B[i], fmaf(g1, f->A[i], p[i]));
+}
+
+/* the raster positions of one step, jittered */
+ORC_EXPORT void orc_perp_jitter(const float *wmin, const float *scale, const float *ray, int steps, float sigma,
+                                int64_t ri, int s, int k, uint32_t seed, float *p_out)
+{
+    grid3d g = {NULL, 1, 1, 1, FMT_R32F, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
+    ray_setup rs = setup_ray(&g, ray, steps);
+    perp_frame f = perp_setup(&g, ray, sigma);
+    float kh = (float)k + 0.5f;
+    for (int a = 0; a < 3; ++a)
+        p_out[a] = fmaf(kh, rs.G[a], rs.E[a]);
+    perp_jitter(&f, ri, s, k, seed, p_out);
+}
+
 static void emission_one(const grid3d *g, const float *r, int64_t ri, int steps, int filter, int mode, int spp,
-                         uint32_t seed, int variant, double *L, int32_t *tp)
+                         uint32_t seed, int variant, float footprint, double *L, int32_t *tp)
 {
     ray_setup rs = setup_ray(g, r, steps);
     if (!rs.ok || rs.empty) {
@@ -2291,11 +2351,24 @@ static void emission_one(const grid3d *g, const float *r, int64_t ri, int steps,
     const int off = filter == F_BSPLINE3 ? -1 : 0;
     double e[3], acc[3] = {0.0, 0.0, 0.0};
     if (mode == M_STOCH) {
+        const perp_frame pf = perp_setup(g, r, footprint);
         for (int s = 0; s < spp; ++s)
             for (int k = 0; k < steps; ++k) {
                 int i0[3], j[3];
                 float t[3];
-                step_pos(&rs, k, i0, t);
+                if (footprint > 0.0f) {
+                    float p[3], kh = (float)k + 0.5f;
+                    for (int a = 0; a < 3; ++a)
+                        p[a] = fmaf(kh, rs.G[a], rs.E[a]);
+                    perp_jitter(&pf, ri, s, k, seed, p);
+                    for (int a = 0; a < 3; ++a) {
+                        float fl = floorf(p[a]);
+                        i0[a] = (int)fl;
+                        t[a] = p[a] - fl;
+                    }
+                } else {
+                    step_pos(&rs, k, i0, t);
+                }
                 uint32_t key[4] = {(uint32_t)ri, (uint32_t)s, (uint32_t)k, seed}, w[4];
                 orc_pcg4d(key, w);
                 pick3(filter, t, w, variant, j);
@@ -2345,8 +2418,8 @@ static void emission_one(const grid3d *g, const float *r, int64_t ri, int steps,
 
 ORC_EXPORT int orc_raymarch_emission(const void *base, int nx, int ny, int nz, int fmt, const float *wmin,
                                      const float *scale, const float *rays, int64_t n, int steps, int filter,
-                                     int mode, int spp, uint32_t seed, int variant, double *L, int32_t *taps,
-                                     const int64_t *subset, int64_t nsub)
+                                     int mode, int spp, uint32_t seed, int variant, float footprint, double *L,
+                                     int32_t *taps, const int64_t *subset, int64_t nsub)
 {
     grid3d g = {(const uint8_t *)base, nx, ny, nz, fmt, {wmin[0], wmin[1], wmin[2]}, {scale[0], scale[1], scale[2]}};
     int64_t m = subset ? nsub : n;
@@ -2354,7 +2427,7 @@ ORC_EXPORT int orc_raymarch_emission(const void *base, int nx, int ny, int nz, i
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < m; ++i) {
         int64_t ri = subset ? subset[i] : i;
-        emission_one(&g, rays + 8 * ri, ri, steps, filter, mode, spp, seed, variant, L + 3 * i,
+        emission_one(&g, rays + 8 * ri, ri, steps, filter, mode, spp, seed, variant, footprint, L + 3 * i,
                      taps ? taps + per * i : NULL);
     }
     return 0;

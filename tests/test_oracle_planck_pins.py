@@ -170,3 +170,72 @@ def test_emission_misses_and_nonfinite(orc):
     for m in (orc.BEFORE, orc.AFTER):
         L = orc.raymarch_emission(g, rays, 8, orc.BSPLINE3, m)
         assert np.all(L[0] == 0) and np.all(np.isnan(L[1:3]))
+
+
+# ------------------------------------------------------------ perpendicular Gaussian footprint
+def test_perp_jitter_is_perpendicular_and_gaussian(orc):
+    """World offsets of the jittered steps lie in the plane perpendicular to
+    the ray, and their components along any fixed orthonormal pair of that
+    plane are independent N(0, sigma^2) (Kolmogorov-Smirnov)."""
+    from scipy import stats
+    g = _grid(np.zeros((16, 16, 16), np.float16))
+    rng = np.random.default_rng(4)
+    sigma = 0.03
+    for d in ([0.0, 0.0, 1.0], [0.0, 0.0, -1.0], [0.3, -0.5, 0.81], [1.0, 0.0, 0.0]):
+        d = np.array(d) / np.linalg.norm(d)
+        ray = np.array([0.5, 0.5, 0.5, *d, -0.2, 0.2], np.float32)
+        base = orc.perp_jitter(g, ray, 8, 0.0, 0, 0, 3, 1).astype(np.float64)
+        offs = np.array([(orc.perp_jitter(g, ray, 8, sigma, i, s, 3, 1) - base) / g.scale
+                         for i in range(64) for s in range(32)], dtype=np.float64)
+        assert np.max(np.abs(offs @ d)) <= 1e-5 * sigma
+        # a fixed orthonormal pair of the plane
+        e1 = np.cross(d, [0.0, 1.0, 0.0] if abs(d[1]) < 0.9 else [1.0, 0.0, 0.0])
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(d, e1)
+        for e in (e1, e2):
+            assert stats.kstest(offs @ e / sigma, "norm").pvalue > 1e-3
+        assert abs(np.corrcoef(offs @ e1, offs @ e2)[0, 1]) < 0.1
+    del rng
+
+
+def test_footprint_blurs_an_edge_by_sigma(orc):
+    """A hot half-space (3000 K for x < 1/2) seen by a ray parallel to z at
+    x = 1/2 + delta: with the perpendicular Gaussian of standard deviation
+    sigma, the expected emission is B(3000) (t1 - t0) times the
+    B-spline-smoothed edge averaged over N(delta, sigma^2) — computed here by
+    quadrature — and the stochastic mean over 4096 samples matches it."""
+    from scipy import stats
+    n = 64
+    data = np.zeros((n, n, n), np.float16)
+    data[:, :, : n // 2] = 3000.0
+    g = _grid(data)
+    sigma = 4.0 / n
+    B = np.array([orc.planck(l, 3000.0) for l in orc.PLANCK_NM])
+
+    def edge(xw):
+        # filter-after fraction of the hot side at world x for the cubic B-spline
+        p = xw * n - 0.5
+        i0 = np.floor(p)
+        t = p - i0
+        w = [(1 - t) ** 3 / 6, (3 * t ** 3 - 6 * t ** 2 + 4) / 6, (-3 * t ** 3 + 3 * t ** 2 + 3 * t + 1) / 6, t ** 3 / 6]
+        return sum(wk for k, wk in enumerate(w) if i0 - 1 + k < n // 2)
+
+    for delta in (-1.5 * sigma, 0.0, 0.7 * sigma, 2.0 * sigma):
+        x = 0.5 + delta
+        ray = np.array([[x, 0.5, -1.0, 0.0, 0.0, 1.0, 1.1, 1.9]], np.float32)
+        L = orc.raymarch_emission(g, ray, 48, orc.BSPLINE3, orc.STOCHASTIC, spp=4096, seed=9,
+                                  footprint=sigma)[0]
+        frac, _ = integrate.quad(lambda y: edge(y) * stats.norm.pdf(y, loc=float(np.float32(x)), scale=sigma),
+                                 x - 8 * sigma, x + 8 * sigma, points=[0.5], limit=200)
+        expect = 0.8 * frac * B
+        assert np.all(np.abs(L - expect) <= 5 * 0.8 * B * 0.5 / math.sqrt(4096 * 48) + 1e-9 * B), (delta, L / (0.8 * B),
+                                                                                                   frac)
+
+
+def test_footprint_zero_is_the_plain_march(orc):
+    g = _grid(_fire())
+    rays = inputs.random_rays(50, 1.0, seed=13)
+    a, ta = orc.raymarch_emission(g, rays, 16, orc.BSPLINE3, orc.STOCHASTIC, spp=2, seed=5, taps=True)
+    b, tb = orc.raymarch_emission(g, rays, 16, orc.BSPLINE3, orc.STOCHASTIC, spp=2, seed=5, taps=True,
+                                  footprint=0.0)
+    assert np.array_equal(a, b) and np.array_equal(ta, tb)
