@@ -404,15 +404,32 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
  *          SF_STOCHASTIC: E_k = B(T_j) of the one picked voxel (mean over spp);
  *          SF_BEFORE: E_k = B(sum_i w_i T_i); SF_AFTER_EXACT: sum_i w_i B(T_i).
  *          Sums in float64.  An empty segment gives 0.
+ *   footprint: standard deviation (world units) of a Gaussian pixel
+ *          footprint in the plane perpendicular to the ray, sampled per step
+ *          (stochastic only; 0 = none; footprint * max scale <= 2^20): the
+ *          plane's basis from d by Duff et al. (JCGT 6(1), 2017),
+ *          sg = copysign(1, d_z), a = -1/(sg + d_z), b = (d_x d_y) a,
+ *          e1 = (1 + ((sg d_x) d_x) a, sg b, -sg d_x), e2 = (b, sg + (d_y d_y) a, -d_y),
+ *          A_i = (footprint e1_i) scale_i, B_i likewise; per step the key
+ *          (ray, sample | 2^31, step, seed) words 0, 1 give u0, u1,
+ *          r = sqrt(-2 ln(1 - u0)), g = r (cos, sin)(2 pi u1) with the
+ *          contract ln / cos / sin, and p_k becomes
+ *          fma(g2, B, fma(g1, A, p_k)) before the pick (Sec. 5: filtering
+ *          after shading under minification with a Gaussian perpendicular
+ *          to the ray; a prefiltered coarse grid passed with footprint 0 is
+ *          the filter-before comparator).
  *   dbg_taps: NULL, or n x spp x S x {x, y, z} int32 (stochastic only).
  *   An occupancy mask (vol->occupancy, built by sf_build_occupancy from the
- *   temperatures) skips bricks at 0 K exactly.
+ *   temperatures) skips bricks at 0 K exactly (tested at the jittered
+ *   position).
  * Rays with a non-finite component, or whose raster positions exceed 2^22 in
  * magnitude, give NaN.
- * Errors: as sf_raymarch.
+ * Errors: as sf_raymarch; SF_E_RANGE for a negative, non-finite or too wide
+ *         footprint, SF_E_UNSUPPORTED for a footprint with a deterministic mode.
  */
 sf_status sf_raymarch_emission(const sf_volume *vol, const float *rays, int64_t n, int32_t steps,
-                               const sf_sampling *smp, float *L, int32_t *dbg_taps, void *stream);
+                               const sf_sampling *smp, float footprint, float *L, int32_t *dbg_taps,
+                               void *stream);
 
 /*
  * sf_build_occupancy — brick occupancy mask of a density grid for empty-space

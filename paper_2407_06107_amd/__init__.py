@@ -106,7 +106,7 @@ def lib() -> C.CDLL:
         L.sf_triplanar.argtypes = [P, P, i64, P, C.c_float, i32, i32, P, P, P, P]
         L.sf_filter3d.argtypes = [P, P, i64, P, i32, C.c_float, P, P, P]
         L.sf_raymarch.argtypes = [P, P, i64, i32, P, P, P, P]
-        L.sf_raymarch_emission.argtypes = [P, P, i64, i32, P, P, P, P]
+        L.sf_raymarch_emission.argtypes = [P, P, i64, i32, P, C.c_float, P, P, P]
         L.sf_error_stats.argtypes = [P, P, i64, i32, P, P, C.c_size_t, P]
         L.sf_build_occupancy.argtypes = [P, P, i64, P]
         L.sf_build_occupancy.restype = i32
@@ -385,11 +385,12 @@ def sf_raymarch(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling, T
     return T
 
 
-def sf_raymarch_emission(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling,
+def sf_raymarch_emission(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sampling, footprint: float = 0.0,
                          L: torch.Tensor | None = None, dbg_taps: torch.Tensor | None = None,
                          stream=None) -> torch.Tensor:
     """Black-body emission gathered along rays through a temperature grid:
-    [n, 3] float32 at PLANCK_NM."""
+    [n, 3] float32 at PLANCK_NM; ``footprint`` > 0 samples a Gaussian pixel
+    footprint perpendicular to the ray (stochastic mode)."""
     _need(rays, torch.float32, "rays")
     n = rays.numel() // 8
     if L is None:
@@ -397,8 +398,8 @@ def sf_raymarch_emission(vol: Volume, rays: torch.Tensor, steps: int, smp: sf_sa
     _need(L, torch.float32, "L", 3 * n)
     if dbg_taps is not None:
         _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * steps * 3)
-    _check(lib().sf_raymarch_emission(C.byref(vol.desc), _ptr(rays), n, steps, C.byref(smp), _ptr(L),
-                                      _ptr(dbg_taps), _stream(stream)))
+    _check(lib().sf_raymarch_emission(C.byref(vol.desc), _ptr(rays), n, steps, C.byref(smp), float(footprint),
+                                      _ptr(L), _ptr(dbg_taps), _stream(stream)))
     return L
 
 

@@ -1,6 +1,7 @@
 // C ABI of libsf: argument validation on the host, derivation of per-call
 // constants, and dispatch to the kernel launchers.  Nothing is enqueued
 // unless every argument is valid.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -482,7 +483,7 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
 }
 
 sf_status sf_raymarch_emission(const sf_volume *vol, const float *rays, int64_t n, int32_t steps,
-                               const sf_sampling *smp, float *L, int32_t *dbg_taps, void *stream)
+                               const sf_sampling *smp, float footprint, float *L, int32_t *dbg_taps, void *stream)
 {
     sf_status st;
     if ((st = check_n(n)) != SF_OK)
@@ -502,6 +503,16 @@ sf_status sf_raymarch_emission(const sf_volume *vol, const float *rays, int64_t 
         return st;
     if (!aligned(rays, 16) || !aligned(L, 4))
         return fail(SF_E_RANGE, "rays must be 16-byte aligned, L 4-byte aligned");
+    if (!(footprint >= 0.0f) || !(footprint < __builtin_inff()))
+        return fail(SF_E_RANGE, "footprint %g must be finite and non-negative", (double)footprint);
+    if (footprint > 0.0f && smp->mode != SF_STOCHASTIC)
+        return fail(SF_E_UNSUPPORTED, "a footprint is sampled by the stochastic mode only");
+    {
+        const float smax = std::max(vol->scale[0], std::max(vol->scale[1], vol->scale[2]));
+        if ((double)footprint * (double)smax > 1048576.0)
+            return fail(SF_E_RANGE, "footprint %g spans more than 2^20 voxels", (double)footprint);
+    }
+    c.footprint = footprint;
     c.rays = rays;
     c.n = n;
     c.steps = steps;

@@ -100,6 +100,7 @@ struct RaymarchCall {
     uint32_t seed;
     float *T;        // transmittance (n), or emission (n x 3)
     int32_t *taps;
+    float footprint; // emission: perpendicular Gaussian, world units (0: none)
 };
 
 struct LatentArgs {

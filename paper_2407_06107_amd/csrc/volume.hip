@@ -295,7 +295,34 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
 // E_k = B(T) of the one voxel the step picks (keys, picks and the occupancy
 // skip as in the transmittance march; empty bricks emit nothing).  The sums
 // run in binary64.
-template <int F, bool HALF, int VAR, bool DBG, bool OCC, bool P2>
+// Gaussian footprint perpendicular to the ray (Sec. 5: filtering after
+// shading under minification): the plane's basis by the branchless
+// construction of Duff et al., "Building an Orthonormal Basis, Revisited"
+// (JCGT 6(1), 2017), scaled to raster axes A, B; per step the key
+// (ray, sample | 2^31, step, seed) gives u0, u1 and Box-Muller with the
+// contract ln and cos/sin moves p to fma(g2, B, fma(g1, A, p)).
+struct PerpFrame {
+    float A[3], B[3];
+};
+
+__device__ __forceinline__ PerpFrame perp_frame(const float *r8, const float *scale, float sigma)
+{
+    const float dx = r8[3], dy = r8[4], dz = r8[5];
+    const float sg = __builtin_copysignf(1.0f, dz);
+    const float a = -1.0f / (sg + dz);
+    const float b = (dx * dy) * a;
+    const float e1[3] = {1.0f + ((sg * dx) * dx) * a, sg * b, -sg * dx};
+    const float e2[3] = {b, sg + (dy * dy) * a, -dy};
+    PerpFrame f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f.A[i] = (sigma * e1[i]) * scale[i];
+        f.B[i] = (sigma * e2[i]) * scale[i];
+    }
+    return f;
+}
+
+template <int F, bool HALF, int VAR, bool DBG, bool OCC, bool P2, bool JIT = false>
 __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_pad)
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
@@ -318,16 +345,37 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
     double acc[3] = {0.0, 0.0, 0.0};
+    PerpFrame pf;
+    if constexpr (JIT)
+        pf = perp_frame(c.rays + 8 * i, c.vol.scale, c.footprint);
     for (int s = 0; s < c.spp; ++s) {
-        StepHash h;
+        StepHash h, hj;
         h.init((uint32_t)i, (uint32_t)s, c.seed);
+        if constexpr (JIT)
+            hj.init((uint32_t)i, (uint32_t)s | 0x80000000u, c.seed);
         uint32_t pend = 0;
         bool pend_ok = false;
         float kh = 0.5f;
         for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
             int i0[3], o[3];
             float t[3];
-            step_coords(g, kh, i0, t);
+            if constexpr (JIT) {
+                const uint3 wj = hj.at((uint32_t)k);
+                const float rr = __builtin_sqrtf(-2.0f * lnc(1.0f - u24(wj.x)));
+                float cs, sn;
+                sincos2pi(u24(wj.y), cs, sn);
+                const float g1 = rr * cs, g2 = rr * sn;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    float p = __builtin_fmaf(kh, g.G[a], g.E[a]);
+                    p = __builtin_fmaf(g2, pf.B[a], __builtin_fmaf(g1, pf.A[a], p));
+                    const float fl = __builtin_floorf(p);
+                    i0[a] = (int)fl;
+                    t[a] = p - fl;
+                }
+            } else {
+                step_coords(g, kh, i0, t);
+            }
             if constexpr (OCC) {
                 if (!brick_occupied(c.vol, i0))
                     continue;
@@ -692,8 +740,13 @@ static void launch_emit_fo(const RaymarchCall &c, dim3 grid, hipStream_t s, uint
 {
     dim3 block(256);
     if (c.mode == STOCH) {
-        if (c.variant)
+        const bool jit = c.footprint > 0.0f;
+        if (c.variant && jit)
+            k_emit_stoch<F, HALF, 1, false, OCC, P2, true><<<grid, block, 0, s>>>(c, nb_pad);
+        else if (c.variant)
             k_emit_stoch<F, HALF, 1, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
+        else if (jit)
+            k_emit_stoch<F, HALF, 0, false, OCC, P2, true><<<grid, block, 0, s>>>(c, nb_pad);
         else
             k_emit_stoch<F, HALF, 0, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
     } else if (c.mode == BEFORE) {
@@ -711,8 +764,13 @@ static hipError_t launch_emit_f(const RaymarchCall &c, hipStream_t s)
     dim3 grid(nb_pad), block(256);
     const bool p2 = c.vol.lx >= 0;
     if (c.mode == STOCH && c.taps) {
-        if (c.variant)
+        const bool jit = c.footprint > 0.0f;
+        if (c.variant && jit)
+            k_emit_stoch<F, HALF, 1, true, false, false, true><<<grid, block, 0, s>>>(c, nb_pad);
+        else if (c.variant)
             k_emit_stoch<F, HALF, 1, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
+        else if (jit)
+            k_emit_stoch<F, HALF, 0, true, false, false, true><<<grid, block, 0, s>>>(c, nb_pad);
         else
             k_emit_stoch<F, HALF, 0, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
     } else if (c.vol.occ) {

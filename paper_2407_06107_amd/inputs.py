@@ -385,6 +385,29 @@ def temperature_grid(density, t_min: float = 800.0, t_max: float = 6000.0):
     return torch.where(d > 0, T, torch.zeros_like(T)).to(torch.float16)
 
 
+def volume_level(grid, level: int):
+    """Level ``level`` of a 3-D MIP pyramid of a grid [nz, ny, nx] (sides
+    divisible by 2^level): means of 2^level-cubes, in float32, rounded once
+    to the grid's dtype — the prefiltered volume a filter-before renderer
+    minifies with."""
+    import torch
+    k = 1 << level
+    x = grid.to(torch.float32)[None, None]
+    return torch.nn.functional.avg_pool3d(x, kernel_size=k, stride=k)[0, 0].to(grid.dtype).contiguous()
+
+
+def ortho_pixel_width(pixels: int, side: float, direction=(0.3, 0.2, 1.0)) -> float:
+    """World width of one pixel of :func:`ortho_rays`' image plane."""
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    a = np.cross(d, [0.0, 1.0, 0.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(a, d)
+    corners = np.array([[x, y, z] for x in (0, side) for y in (0, side) for z in (0, side)], dtype=np.float64)
+    pa, pb = corners @ a, corners @ b
+    return float(max(pa.max() - pa.min(), pb.max() - pb.min()) / pixels)
+
+
 def constant_grid(n: int, value: float, device: str = "cpu"):
     import torch
     return torch.full((n, n, n), value, dtype=torch.float16, device=device)
@@ -410,13 +433,16 @@ def _clip_box(o: np.ndarray, d: np.ndarray, lo: np.ndarray, hi: np.ndarray):
 
 
 def ortho_rays(pixels: int = 256, spp: int = 16, side: float = 0.25, seed: int = 11,
-               direction=(0.3, 0.2, 1.0), strata: int = 4) -> np.ndarray:
+               direction=(0.3, 0.2, 1.0), strata: int = 4, gauss_px: float | None = None) -> np.ndarray:
     """Orthographic rays through the cube [0, side]^3.
 
     The image plane is perpendicular to ``direction`` and its square extent
     covers the cube's projection; ``pixels x pixels`` pixels, ``spp`` rays per
     pixel, jittered within a ``strata x strata`` grid of strata (``spp`` must
-    be a multiple of strata^2).  Rays are clipped to the cube in float64.
+    be a multiple of strata^2); ``strata = 0`` puts every ray through its
+    pixel's centre, and ``gauss_px`` instead offsets each ray from the
+    centre by a 2-D normal of that standard deviation in pixels (a Gaussian
+    pixel filter).  Rays are clipped to the cube in float64.
     Output ``[pixels*pixels*spp, 8]`` float32 rows
     ``{ox, oy, oz, dx, dy, dz, t0, t1}``, d of unit length, ordered by pixel in
     8x8-tile Morton order with the ``spp`` rays of one pixel consecutive.  A
@@ -439,11 +465,19 @@ def ortho_rays(pixels: int = 256, spp: int = 16, side: float = 0.25, seed: int =
     px = (order % pixels).astype(np.float64)
     py = (order // pixels).astype(np.float64)
     s = np.arange(spp)
-    sx = (s % strata).astype(np.float64)
-    sy = ((s // strata) % strata).astype(np.float64)
-    jit = rng.random((order.size, spp, 2))
-    fx = (px[:, None] + (sx[None] + jit[..., 0]) / strata) / pixels - 0.5
-    fy = (py[:, None] + (sy[None] + jit[..., 1]) / strata) / pixels - 0.5
+    if gauss_px is not None:
+        off = rng.normal(size=(order.size, spp, 2)) * gauss_px
+        fx = (px[:, None] + 0.5 + off[..., 0]) / pixels - 0.5
+        fy = (py[:, None] + 0.5 + off[..., 1]) / pixels - 0.5
+    elif strata == 0:
+        fx = np.broadcast_to((px[:, None] + 0.5) / pixels - 0.5, (order.size, spp))
+        fy = np.broadcast_to((py[:, None] + 0.5) / pixels - 0.5, (order.size, spp))
+    else:
+        sx = (s % strata).astype(np.float64)
+        sy = ((s // strata) % strata).astype(np.float64)
+        jit = rng.random((order.size, spp, 2))
+        fx = (px[:, None] + (sx[None] + jit[..., 0]) / strata) / pixels - 0.5
+        fy = (py[:, None] + (sy[None] + jit[..., 1]) / strata) / pixels - 0.5
     fa = ca + fx.ravel() * ext
     fb = cb + fy.ravel() * ext
     o = fa[:, None] * a[None] + fb[:, None] * b[None] + back * d[None]

@@ -129,7 +129,10 @@ def test_raymarch_validation(sf, case, status, entry):
         vol.reserved = 1
     elif case == "keys":
         smp.filter = sf.SF_KEYS3
-    st = getattr(L, entry)(C.byref(vol) if vol is not None else None, rays, n, steps, C.byref(smp), T, None, None)
+    args = (C.byref(vol) if vol is not None else None, rays, n, steps, C.byref(smp))
+    if entry == "sf_raymarch_emission":
+        args += (C.c_float(0.0),)
+    st = getattr(L, entry)(*args, T, None, None)
     assert st == status, sf.sf_last_error()
     if status:
         assert sf.sf_last_error()
@@ -311,6 +314,29 @@ def test_triplanar_validation(sf, case, status):
     elif case == "bad_shade":
         shade = 2
     st = L.sf_triplanar(C.byref(tex), q, n, C.byref(smp), scale, pm, shade, None, FAKE, None, None)
+    assert st == status, sf.sf_last_error()
+
+
+@pytest.mark.parametrize("case, status", [("negative", 2), ("nan", 2), ("inf", 2), ("too_wide", 2),
+                                          ("deterministic", 3), ("n_zero", 0)])
+def test_emission_footprint_validation(sf, case, status):
+    L = sf.lib()
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1)
+    vol = _vol(sf)                         # scale 8 voxels per unit
+    n, fp = 4, 0.1
+    if case == "negative":
+        fp = -0.1
+    elif case == "nan":
+        fp = float("nan")
+    elif case == "inf":
+        fp = float("inf")
+    elif case == "too_wide":
+        fp = 2.0 ** 20 / 8 * 1.01
+    elif case == "deterministic":
+        smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_AFTER_EXACT, 1)
+    elif case == "n_zero":
+        n = 0
+    st = L.sf_raymarch_emission(C.byref(vol), FAKE, n, 16, C.byref(smp), C.c_float(fp), FAKE, None, None)
     assert st == status, sf.sf_last_error()
 
 

@@ -204,3 +204,53 @@ def test_emission_full_size_sampled(sf, orc, full_fire, filt, mode):
     sub = np.sort(np.random.default_rng(6).choice(rays.shape[0], 300, replace=False))
     ref = orc.raymarch_emission(og, rays, steps, f, m, spp=1, seed=2024, subset=sub)
     _close(L[sub], ref)
+
+
+# ------------------------------------------------------------ perpendicular Gaussian footprint
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("spp, variant", [(1, 0), (3, 1)])
+@pytest.mark.parametrize("brick_log2", [None, 2])
+def test_emission_footprint_small(sf, orc, small_fire, filt, spp, variant, brick_log2):
+    """Every step jittered by the perpendicular Gaussian (2.5 voxels): picked
+    voxels bit-exact (the jitter's Box-Muller runs on the contract ln and
+    cos/sin on both sides), values to the tolerance, the occupancy skip
+    (tested at the jittered position) exact."""
+    _case("emission_footprint_small", filt, spp, variant, brick_log2)
+    og, vol = _grids(orc, sf, small_fire, brick_log2=brick_log2)
+    rays = inputs.random_rays(3001, 1.0, seed=23)
+    steps = 40
+    f = getattr(orc, filt)
+    fp = 2.5 / 44
+    smp = sf.sampling(f, 2, spp, seed=19, rng_variant=variant)
+    rays_d = torch.from_numpy(rays).cuda()
+    L = sf.sf_raymarch_emission(vol, rays_d, steps, smp, footprint=fp).cpu().numpy()
+    ref = orc.raymarch_emission(og, rays, steps, f, 2, spp=spp, seed=19, variant=variant, footprint=fp)
+    _close(L, ref)
+    if brick_log2 is None:
+        taps_d = torch.empty((rays.shape[0], spp, steps, 3), dtype=torch.int32, device="cuda")
+        L2 = sf.sf_raymarch_emission(vol, rays_d, steps, smp, footprint=fp, dbg_taps=taps_d).cpu().numpy()
+        _, taps = orc.raymarch_emission(og, rays, steps, f, 2, spp=spp, seed=19, variant=variant, footprint=fp,
+                                        taps=True)
+        assert np.array_equal(taps_d.cpu().numpy(), taps)
+        assert np.array_equal(L2, L)
+    else:
+        _, plain = _grids(orc, sf, small_fire)
+        L0 = sf.sf_raymarch_emission(plain, rays_d, steps, smp, footprint=fp).cpu().numpy()
+        assert np.array_equal(L0, L)
+
+
+def test_emission_minification_launch(sf, orc, full_fire):
+    """The minification launch the benchmark times: 64 x 64 pixel-centre
+    rays over the 512^3 fire, footprint half a pixel (about 5 voxels), every
+    ray against the oracle."""
+    _case("emission_minification")
+    temp, _, side = full_fire
+    vol = sf.Volume(temp, side=side, brick_log2=3)
+    og = orc.Grid(temp.cpu().numpy(), side=side)
+    rays = inputs.ortho_rays(64, 1, side=side, seed=12, strata=0)
+    fp = 0.5 * inputs.ortho_pixel_width(64, side)
+    for spp in (1, 4):
+        smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, spp, seed=31)
+        L = sf.sf_raymarch_emission(vol, torch.from_numpy(rays).cuda(), 256, smp, footprint=fp).cpu().numpy()
+        ref = orc.raymarch_emission(og, rays, 256, orc.BSPLINE3, orc.STOCHASTIC, spp=spp, seed=31, footprint=fp)
+        _close(L, ref)
