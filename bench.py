@@ -330,6 +330,61 @@ def planck_bench(res):
     ce["speedup_stochastic_vs_after"] = ce["tricubic_after_64tap"]["ms"] / ce["tricubic_stochastic"]["ms"]
     res["emission"] = ce
 
+    # ---- minification: 64x64 pixels over the cube (about 10 voxels per pixel)
+    log("emission: minification")
+    MP, M_REF = 64, 1024
+    pw = inputs.ortho_pixel_width(MP, SIDE)
+    sigma = 0.5 * pw                       # Gaussian pixel filter, half a pixel
+    centre_h = inputs.ortho_rays(MP, 1, side=SIDE, seed=12, strata=0)
+    centre = torch.from_numpy(centre_h).cuda()
+    nm = centre.shape[0]
+    # reference: the Gaussian pixel filter of the exact tricubic filter-after emission on level 0,
+    # by M_REF whole rays per pixel offset from the centre ray (same segment and steps, so only the
+    # footprint is integrated); their sampling variance is measured and subtracted
+    after = sf.sampling(sf.SF_BSPLINE3, sf.SF_AFTER_EXACT, 1)
+    acc = torch.zeros((nm, 3), dtype=torch.float64, device="cuda")
+    acc2 = torch.zeros((nm, 3), dtype=torch.float64, device="cuda")
+    chunk = 256
+    for c0 in range(0, M_REF, chunk):
+        r = torch.from_numpy(inputs.offset_rays(centre_h, sigma, chunk, seed=100 + c0)).cuda()
+        v = sf.sf_raymarch_emission(vol, r, STEPS, after).double().view(nm, chunk, 3)
+        acc += v.sum(1)
+        acc2 += (v * v).sum(1)
+    R = acc / M_REF
+    var_R = ((acc2 / M_REF - R * R).clamp(min=0) / (M_REF - 1)).mean(0)
+    Rn = R.cpu().numpy()
+    scale_m = np.sqrt(np.mean(Rn ** 2, axis=0))
+    cm = {"pixels": nm, "voxels_per_pixel": pw * GRID / SIDE, "footprint_sigma_world": sigma,
+          "reference": f"Gaussian pixel filter (sigma = 1/2 pixel) of the tricubic filter-after emission on the "
+                       f"512^3 level, {M_REF} rays per pixel offset from the centre ray"}
+    Lm = torch.empty((nm, 3), dtype=torch.float32, device="cuda")
+
+    def rel_rmse(out):
+        mse = np.mean((out.double().cpu().numpy() - Rn) ** 2, axis=0) - var_R.cpu().numpy()
+        return [float(x) for x in np.sqrt(np.maximum(mse, 0.0)) / scale_m]
+
+    for lvl in (3, 2):
+        coarse = inputs.volume_level(temp, lvl)
+        vc = sf.Volume(coarse, side=SIDE, brick_log2=BRICK_LOG2)
+        for fname, filt in (("tricubic", sf.SF_BSPLINE3), ("trilinear", sf.SF_LINEAR)):
+            smp = sf.sampling(filt, sf.SF_BEFORE, 1)
+            t = time_launches(lambda: sf.sf_raymarch_emission(vc, centre, STEPS, smp, L=Lm), 10, 3, torch)
+            cm[f"prefiltered_level{lvl}_{fname}_before"] = {"ms": t, "relative_rmse": rel_rmse(Lm)}
+        del vc, coarse
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_AFTER_EXACT, 1)
+    t = time_launches(lambda: sf.sf_raymarch_emission(vol, centre, STEPS, smp, L=Lm), 5, 2, torch)
+    cm["level0_tricubic_after_point_sampled"] = {"ms": t, "relative_rmse": rel_rmse(Lm)}
+    for spp in (1, 4, 16, 64):
+        smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, spp, seed=31)
+        t = time_launches(lambda: sf.sf_raymarch_emission(vol, centre, STEPS, smp, footprint=sigma, L=Lm), 10, 3,
+                          torch)
+        cm[f"stochastic_gaussian_footprint_{spp}spp"] = {"ms": t, "relative_rmse": rel_rmse(Lm)}
+    cm["note"] = ("relative_rmse: per wavelength (700 / 546.1 / 435.8 nm), pixel RMSE against the reference over "
+                  "the RMS of the reference, reference sampling variance subtracted; prefiltered rows march a "
+                  "box-averaged temperature level (filter before shading), the stochastic rows sample the "
+                  "Gaussian footprint on level 0 one voxel per step (filter after shading)")
+    res["emission_minification"] = cm
+
 
 def texture_bench(args, res):
     """Configs 1 and 2: the 2-D path (magnification of a 64^2 RGBA32F texture;

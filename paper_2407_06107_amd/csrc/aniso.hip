@@ -463,9 +463,7 @@ template <int SHADE>
 static void launch_ewa(const AnisoCall &c, hipStream_t s)
 {
     if (c.mode == STOCH) {
-        int G = 1;
-        while (G * 2 <= c.spp && G * 2 <= 64)
-            G *= 2;
+        const int G = lane_group(c.n, c.spp);
         const int64_t threads = c.n * G;
         k_ewa_stoch<SHADE><<<dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s>>>(c, __builtin_ctz(G));
     } else {
@@ -481,9 +479,7 @@ template <int F, int SHADE>
 static void launch_a2(const AnisoCall &c, hipStream_t s)
 {
     if (c.mode == STOCH) {
-        int G = 1;
-        while (G * 2 <= c.spp && G * 2 <= 64)
-            G *= 2;
+        const int G = lane_group(c.n, c.spp);
         const int64_t threads = c.n * G;
         k_aniso_stoch<F, SHADE><<<dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s>>>(c, __builtin_ctz(G));
     } else if constexpr (F != GAUSS_FIS) {

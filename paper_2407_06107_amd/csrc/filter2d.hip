@@ -278,9 +278,7 @@ template <int F, int SHADE>
 static void launch_f2(const Filter2DCall &c, hipStream_t s)
 {
     if (c.mode == STOCH) {
-        int G = 1;
-        while (G * 2 <= c.spp && G * 2 <= 64)
-            G *= 2;
+        const int G = lane_group(c.n, c.spp);
         int log_g = __builtin_ctz(G);
         int64_t threads = c.n * G;
         dim3 grid((uint32_t)((threads + 255) / 256)), block(256);

@@ -152,6 +152,17 @@ hipError_t launch_aniso(const AnisoCall &c, hipStream_t s);
 hipError_t launch_dct_encode(const DctEncodeCall &c, hipStream_t s);
 hipError_t launch_triplanar(const TriplanarCall &c, hipStream_t s);
 hipError_t launch_filter3d(const Filter3DCall &c, hipStream_t s);
+// Lanes per query for kernels that spread a query's samples over adjacent
+// lanes: the largest power of two up to min(spp, 64) that keeps the grid
+// within 2^31 work-items.
+inline int lane_group(int64_t n, int spp)
+{
+    int G = 1;
+    while (G * 2 <= spp && G * 2 <= 64 && n * (G * 2) <= (int64_t(1) << 31))
+        G *= 2;
+    return G;
+}
+
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s);
 hipError_t launch_emission(const RaymarchCall &c, hipStream_t s);
 hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ, int64_t words, hipStream_t s);

@@ -225,9 +225,7 @@ static void launch_t3(const TriplanarCall &c, hipStream_t s)
         k_tri_det<F, SHADE, MODE><<<dim3((uint32_t)((c.n + 255) / 256)), dim3(256), 0, s>>>(c);
         return;
     }
-    int G = 1;
-    while (G * 2 <= c.spp && G * 2 <= 64)
-        G *= 2;
+    const int G = lane_group(c.n, c.spp);
     const int64_t threads = c.n * G;
     k_tri_sampled<F, SHADE, MODE><<<dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s>>>(c, __builtin_ctz(G));
 }

@@ -322,23 +322,32 @@ __device__ __forceinline__ PerpFrame perp_frame(const float *r8, const float *sc
     return f;
 }
 
+// The samples of a ray are spread over G = 2^log_g adjacent lanes (a
+// power of two up to 64, inside one wave) and their sums reduced by a
+// butterfly, so small images with many samples still fill the chip.
 template <int F, bool HALF, int VAR, bool DBG, bool OCC, bool P2, bool JIT = false>
-__global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_pad)
+__global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_pad, int log_g)
 {
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
+    const int64_t gid = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
+    const int G = 1 << log_g;
+    const int64_t i = gid >> log_g;
+    const int lane = (int)(gid & (G - 1));
     if (i >= c.n)
-        return;
+        return;   // the whole group of lanes shares i
     RayGeom g;
     int st = ray_setup_dev(c.vol.wmin, c.vol.scale, c.rays + 8 * i, c.steps, g);
     if (st != 0) {
         const float v = st == 1 ? 0.0f : __builtin_nanf("");
-        c.T[3 * i] = v;
-        c.T[3 * i + 1] = v;
-        c.T[3 * i + 2] = v;
+        if (lane == 0) {
+            c.T[3 * i] = v;
+            c.T[3 * i + 1] = v;
+            c.T[3 * i + 2] = v;
+        }
         if constexpr (DBG) {
-            int64_t per = (int64_t)3 * c.spp * c.steps;
-            for (int64_t k = 0; k < per; ++k)
-                c.taps[per * i + k] = SF_TAP_NONE;
+            const int64_t per = (int64_t)3 * c.steps;
+            for (int s = lane; s < c.spp; s += G)
+                for (int64_t k = 0; k < per; ++k)
+                    c.taps[((int64_t)i * c.spp + s) * per + k] = SF_TAP_NONE;
         }
         return;
     }
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
     PerpFrame pf;
     if constexpr (JIT)
         pf = perp_frame(c.rays + 8 * i, c.vol.scale, c.footprint);
-    for (int s = 0; s < c.spp; ++s) {
+    for (int s = lane; s < c.spp; s += G) {
         StepHash h, hj;
         h.init((uint32_t)i, (uint32_t)s, c.seed);
         if constexpr (JIT)
@@ -404,10 +413,17 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
         acc[1] += (double)B[1];
         acc[2] += (double)B[2];
     }
-    const double sc = (double)g.dt / (double)c.spp;
-    c.T[3 * i] = (float)(acc[0] * sc);
-    c.T[3 * i + 1] = (float)(acc[1] * sc);
-    c.T[3 * i + 2] = (float)(acc[2] * sc);
+    for (int m = G >> 1; m >= 1; m >>= 1) {
+        acc[0] += __shfl_xor(acc[0], m);
+        acc[1] += __shfl_xor(acc[1], m);
+        acc[2] += __shfl_xor(acc[2], m);
+    }
+    if (lane == 0) {
+        const double sc = (double)g.dt / (double)c.spp;
+        c.T[3 * i] = (float)(acc[0] * sc);
+        c.T[3 * i + 1] = (float)(acc[1] * sc);
+        c.T[3 * i + 2] = (float)(acc[2] * sc);
+    }
 }
 
 // Deterministic emission: E_k = B(sum_i w_i T_i) before shading,
@@ -735,20 +751,28 @@ static hipError_t launch_ray_f(const RaymarchCall &c, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int F, bool HALF, int VAR, bool DBG, bool OCC, bool P2>
+static void launch_emit_stoch(const RaymarchCall &c, hipStream_t s)
+{
+    const int G = lane_group(c.n, c.spp);
+    const uint32_t nb = blocks_for(c.n * G);
+    const uint32_t nb_pad = (nb + 7u) & ~7u;
+    const int lg = __builtin_ctz(G);
+    if (c.footprint > 0.0f)
+        k_emit_stoch<F, HALF, VAR, DBG, OCC, P2, true><<<dim3(nb_pad), dim3(256), 0, s>>>(c, nb_pad, lg);
+    else
+        k_emit_stoch<F, HALF, VAR, DBG, OCC, P2, false><<<dim3(nb_pad), dim3(256), 0, s>>>(c, nb_pad, lg);
+}
+
 template <int F, bool HALF, bool OCC, bool P2>
 static void launch_emit_fo(const RaymarchCall &c, dim3 grid, hipStream_t s, uint32_t nb_pad)
 {
     dim3 block(256);
     if (c.mode == STOCH) {
-        const bool jit = c.footprint > 0.0f;
-        if (c.variant && jit)
-            k_emit_stoch<F, HALF, 1, false, OCC, P2, true><<<grid, block, 0, s>>>(c, nb_pad);
-        else if (c.variant)
-            k_emit_stoch<F, HALF, 1, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
-        else if (jit)
-            k_emit_stoch<F, HALF, 0, false, OCC, P2, true><<<grid, block, 0, s>>>(c, nb_pad);
+        if (c.variant)
+            launch_emit_stoch<F, HALF, 1, false, OCC, P2>(c, s);
         else
-            k_emit_stoch<F, HALF, 0, false, OCC, P2><<<grid, block, 0, s>>>(c, nb_pad);
+            launch_emit_stoch<F, HALF, 0, false, OCC, P2>(c, s);
     } else if (c.mode == BEFORE) {
         k_emit_det<F, HALF, BEFORE, OCC><<<grid, block, 0, s>>>(c, nb_pad);
     } else {
@@ -761,18 +785,13 @@ static hipError_t launch_emit_f(const RaymarchCall &c, hipStream_t s)
 {
     uint32_t nb = blocks_for(c.n);
     uint32_t nb_pad = (nb + 7u) & ~7u;
-    dim3 grid(nb_pad), block(256);
+    dim3 grid(nb_pad);
     const bool p2 = c.vol.lx >= 0;
     if (c.mode == STOCH && c.taps) {
-        const bool jit = c.footprint > 0.0f;
-        if (c.variant && jit)
-            k_emit_stoch<F, HALF, 1, true, false, false, true><<<grid, block, 0, s>>>(c, nb_pad);
-        else if (c.variant)
-            k_emit_stoch<F, HALF, 1, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
-        else if (jit)
-            k_emit_stoch<F, HALF, 0, true, false, false, true><<<grid, block, 0, s>>>(c, nb_pad);
+        if (c.variant)
+            launch_emit_stoch<F, HALF, 1, true, false, false>(c, s);
         else
-            k_emit_stoch<F, HALF, 0, true, false, false><<<grid, block, 0, s>>>(c, nb_pad);
+            launch_emit_stoch<F, HALF, 0, true, false, false>(c, s);
     } else if (c.vol.occ) {
         if (p2)
             launch_emit_fo<F, HALF, true, true>(c, grid, s, nb_pad);

@@ -494,6 +494,24 @@ def ortho_rays(pixels: int = 256, spp: int = 16, side: float = 0.25, seed: int =
     return rays
 
 
+def offset_rays(rays: np.ndarray, sigma: float, count: int, seed: int) -> np.ndarray:
+    """``count`` copies of every ray ``[n, 8]``, each with its origin moved by
+    a 2-D normal offset of standard deviation ``sigma`` (world units) in the
+    plane perpendicular to its direction, the segment [t0, t1] kept (a
+    Gaussian pixel footprint realised by whole rays).  ``[n*count, 8]``,
+    the copies of one ray consecutive."""
+    rng = np.random.default_rng(seed)
+    r = np.repeat(np.asarray(rays, dtype=np.float64), count, axis=0)
+    d = r[:, 3:6]
+    helper = np.where(np.abs(d[:, 1:2]) < 0.9, np.array([[0.0, 1.0, 0.0]]), np.array([[1.0, 0.0, 0.0]]))
+    e1 = np.cross(d, helper)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(d, e1)
+    g = rng.normal(size=(r.shape[0], 2)) * sigma
+    r[:, :3] += g[:, :1] * e1 + g[:, 1:] * e2
+    return r.astype(np.float32)
+
+
 def random_rays(n: int, side: float, seed: int) -> np.ndarray:
     """Rays between two uniform points on the cube's boundary region, for
     parity tests: origin uniform in the cube, direction uniform on the sphere,
