@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # enums of the oracle (its own copy; it does not include the library header)
 NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS, EWA = 0, 1, 2, 3, 4, 5, 6, 7
 SIGMA_MIN, SIGMA_MAX = 1.0 / 16.0, 4.0     # Gaussian standard deviation, texels
-BEFORE, AFTER, STOCHASTIC = 0, 1, 2
+BEFORE, AFTER, STOCHASTIC, SPLIT = 0, 1, 2, 3
 RGBA32F, RGBA8, R16F, R32F, DCT8 = 0, 1, 2, 3, 4
 REPEAT, CLAMP = 0, 1
 MIP_NONE, MIP_NEAREST, MIP_LINEAR = 0, 1, 2
@@ -299,7 +299,7 @@ def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed
     m = n if sub is None else sub.size
     ch = 3 if shade == 1 else 4
     out = np.zeros((m, ch))
-    tp = np.zeros((m, spp, 5 if filt == KEYS3 else 3), dtype=np.int32) if taps else None
+    tp = np.zeros((m, spp, 5 if (filt == KEYS3 and mode == STOCHASTIC) else 3), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_filter2d(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
                        _p(tex.dct_range), _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, sigma, shade, _p(g), _p(out), _p(tp),

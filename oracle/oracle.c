@@ -62,7 +62,7 @@
 
 enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2, F_KEYS3 = 3, F_GAUSS_FRS = 4, F_GAUSS_FIS = 5,
        F_BSPLINE3_FIS = 6, F_EWA = 7 };
-enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2 };
+enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2, M_SPLIT = 3 };
 enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3, FMT_DCT8 = 4 };
 enum { WRAP_REPEAT = 0, WRAP_CLAMP = 1 };
 enum { MIP_NONE = 0, MIP_NEAREST = 1, MIP_LINEAR = 2 };
@@ -839,7 +839,35 @@ static int query_finite(const tex2d *t, const float *q)
 #define AXIS_TAPS_MAX 64
 static int axis_weights_s(int filter, float sigma, double t, int *first_off, double *w);
 
-/* One query of the 2-D filter.  out has 4 (shade none) or 3 (GGX) channels. */
+/* The reconstruction filter alone at level l: sum_i w_i t_i (binary64
+ * weights and sums) at the wrapped coordinate (uu, vv). */
+static void recon_level(const tex2d *t, float uu, float vv, int l, int filter, float sigma, double rgba[4])
+{
+    int wl = lvl_dim(t->w, l), hl = lvl_dim(t->h, l);
+    int ix, iy;
+    float tx, ty;
+    raster(uu, wl, &ix, &tx);
+    raster(vv, hl, &iy, &ty);
+    double wx[AXIS_TAPS_MAX], wy[AXIS_TAPS_MAX];
+    int ox, oy;
+    int nx = axis_weights_s(filter, sigma, (double)tx, &ox, wx);
+    int ny = axis_weights_s(filter, sigma, (double)ty, &oy, wy);
+    for (int c = 0; c < 4; ++c)
+        rgba[c] = 0.0;
+    for (int b = 0; b < ny; ++b)
+        for (int a = 0; a < nx; ++a) {
+            double texel[4];
+            fetch2d(t, l, wrap_tap(t->wrap, ix + ox + a, wl), wrap_tap(t->wrap, iy + oy + b, hl), texel);
+            for (int c = 0; c < 4; ++c)
+                rgba[c] += wx[a] * wy[b] * texel[c];
+        }
+}
+
+/* One query of the 2-D filter.  out has 4 (shade none) or 3 (GGX) channels.
+ * M_SPLIT (the split-filtering estimator of Sec. 3 eq. split-filtering-shading
+ * and Sec. 4: the low-pass filter sampled, the reconstruction filter
+ * evaluated before shading): per sample the stochastic level of the key's
+ * word 3, then shade(sum_i w_i t_i) on that level; mean over samples. */
 static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter, int mode, int spp,
                          uint32_t seed, int variant, float sigma, int shade, const double *ggx, double *out,
                          int32_t *taps)
@@ -848,8 +876,8 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
     if (!query_finite(t, q)) {
         for (int c = 0; c < ch; ++c)
             out[c] = NAN;
-        if (taps && mode == M_STOCH)
-            for (int s = 0; s < (filter == F_KEYS3 ? 5 : 3) * spp; ++s)
+        if (taps && (mode == M_STOCH || mode == M_SPLIT))
+            for (int s = 0; s < (filter == F_KEYS3 && mode == M_STOCH ? 5 : 3) * spp; ++s)
                 taps[s] = INT32_MIN;
         return;
     }
@@ -858,6 +886,27 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
     int l0, l1;
     float f;
     levels_of(t, q[2], &l0, &l1, &f);
+
+    if (mode == M_SPLIT) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int s = 0; s < spp; ++s) {
+            uint32_t key[4] = {(uint32_t)qi, (uint32_t)s, 0u, seed}, w[4];
+            orc_pcg4d(key, w);
+            int l = (uniform24(w[3]) >= 1.0f - f) ? l1 : l0;
+            if (taps) {
+                taps[3 * s] = l;
+                taps[3 * s + 1] = taps[3 * s + 2] = INT32_MIN;
+            }
+            double rgba[4], v[4];
+            recon_level(t, uu, vv, l, filter, sigma, rgba);
+            shade2d(shade, ggx, rgba, v);
+            for (int c = 0; c < ch; ++c)
+                acc[c] += v[c];
+        }
+        for (int c = 0; c < ch; ++c)
+            out[c] = acc[c] / (double)spp;
+        return;
+    }
 
     if (mode == M_STOCH) {
         double acc[4] = {0, 0, 0, 0};
@@ -1035,7 +1084,7 @@ ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt,
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i) {
         int64_t qi = subset ? subset[i] : i;
-        int tw = filter == F_KEYS3 ? 5 : 3;
+        int tw = filter == F_KEYS3 && mode == M_STOCH ? 5 : 3;
         filter2d_one(&t, q + 3 * qi, qi, filter, mode, spp, seed, variant, sigma, shade, ggx, out + ch * i,
                      taps ? taps + (int64_t)tw * spp * i : NULL);
     }
@@ -1248,7 +1297,7 @@ static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, in
     if (!aniso_query_finite(q)) {
         for (int c = 0; c < ch; ++c)
             out[c] = NAN;
-        if (taps && mode == M_STOCH)
+        if (taps && (mode == M_STOCH || mode == M_SPLIT))
             for (int s = 0; s < 3 * spp; ++s)
                 taps[s] = INT32_MIN;
         return;
@@ -1256,6 +1305,34 @@ static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, in
     int major_y, np;
     float lam = orc_aniso_lod(t->w, t->h, q + 2, amax, &major_y, &np);
     const float lmax = (float)(t->levels - 1);
+    if (mode == M_SPLIT) {
+        /* split filtering: the low-pass filter (jitter over the pixel and the
+         * jittered level, key words 0, 1, 2 as the stochastic mode) sampled,
+         * the reconstruction filter evaluated before shading */
+        double acc[4] = {0, 0, 0, 0};
+        for (int s = 0; s < spp; ++s) {
+            uint32_t k0[4] = {(uint32_t)qi, (uint32_t)s, 0u, seed}, w0[4];
+            orc_pcg4d(k0, w0);
+            float jx = uniform24(w0[0]) - 0.5f, jy = uniform24(w0[1]) - 0.5f;
+            float u = fmaf(jy, q[4], fmaf(jx, q[2], q[0]));
+            float v = fmaf(jy, q[5], fmaf(jx, q[3], q[1]));
+            float lj = lam + (uniform24(w0[2]) - 0.5f);
+            lj = fminf(fmaxf(lj, 0.0f), lmax);
+            int l = (int)floorf(lj + 0.5f);
+            if (taps) {
+                taps[3 * s] = l;
+                taps[3 * s + 1] = taps[3 * s + 2] = INT32_MIN;
+            }
+            double rgba[4], val[4];
+            recon_level(t, wrap_coord(t->wrap, u), wrap_coord(t->wrap, v), l, filter, sigma, rgba);
+            shade2d(shade, ggx, rgba, val);
+            for (int c = 0; c < ch; ++c)
+                acc[c] += val[c];
+        }
+        for (int c = 0; c < ch; ++c)
+            out[c] = acc[c] / (double)spp;
+        return;
+    }
     if (mode == M_STOCH) {
         double acc[4] = {0, 0, 0, 0};
         for (int s = 0; s < spp; ++s) {
