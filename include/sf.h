@@ -103,8 +103,16 @@ enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3, SF_GAUSS_FR
  *     the key with step 0 for x, step 1 for y); offset q - 1 + [r 2^-24 >= 1 - t]. */
 /* SF_BEFORE: shade(sum_i w_i t_i)            (eq. filter-before-shading)
  * SF_AFTER_EXACT: sum_i w_i shade(t_i)        (eq. filtering-after-shading)
- * SF_STOCHASTIC: mean over spp of shade(t_j), P(j) = w_j (eq. stochastic-sum) */
-enum { SF_BEFORE = 0, SF_AFTER_EXACT = 1, SF_STOCHASTIC = 2 };
+ * SF_STOCHASTIC: mean over spp of shade(t_j), P(j) = w_j (eq. stochastic-sum)
+ * SF_SPLIT (2-D filters only): the split-filtering estimator (Sec. 3 eq.
+ *   split-filtering-shading, Sec. 4): per sample the low-pass filter is
+ *   sampled — the MIP level (sf_filter2d: key word 3, as SF_STOCHASTIC), and
+ *   for sf_filter2d_aniso also the jitter over the pixel (key words 0, 1, 2,
+ *   as SF_STOCHASTIC) — and the reconstruction filter is evaluated on that
+ *   level before shading: mean over spp of shade(sum_i w_i t_i).  Filters
+ *   NEAREST, LINEAR, BSPLINE3, KEYS3 (binary32 weights), rng_variant 0;
+ *   dbg_taps hold {level, SF_TAP_NONE, SF_TAP_NONE} per sample. */
+enum { SF_BEFORE = 0, SF_AFTER_EXACT = 1, SF_STOCHASTIC = 2, SF_SPLIT = 3 };
 enum { SF_RGBA32F = 0, SF_RGBA8_UNORM = 1, SF_R16F = 2, SF_R32F = 3, SF_DCT8 = 4 };
 enum { SF_WRAP_REPEAT = 0, SF_WRAP_CLAMP = 1 };
 /* MIP level use (Sec. 2.1 pyramids; single stochastic level, Sec. 4.2.1):
@@ -125,7 +133,7 @@ enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1, SF_SHADE_PLANCK = 2 }; 
 
 typedef struct sf_sampling {
     int32_t filter;      /* SF_NEAREST .. SF_EWA (see above)                         */
-    int32_t mode;        /* SF_BEFORE | SF_AFTER_EXACT | SF_STOCHASTIC                */
+    int32_t mode;        /* SF_BEFORE | SF_AFTER_EXACT | SF_STOCHASTIC | SF_SPLIT     */
     int32_t spp;         /* samples per query, 1..SF_MAX_SPP (deterministic: ignored) */
     uint32_t seed;       /* fourth word of the hash key                              */
     int32_t rng_variant; /* 0: one uniform per axis; 1: one uniform for all spatial

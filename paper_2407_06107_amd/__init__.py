@@ -22,7 +22,7 @@ SF_OK, SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED, SF_E_DEVICE, SF_E_WORKSPACE = ra
 SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3, SF_GAUSS_FRS, SF_GAUSS_FIS, SF_BSPLINE3_FIS, SF_EWA = range(8)
 SF_MAX_ANISO, SF_EWA_MAX_ANISO, SF_EWA_MAX_ASPECT = 64, 16, 8
 SF_SIGMA_MIN, SF_SIGMA_MAX = 0.0625, 4.0
-SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC = 0, 1, 2
+SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC, SF_SPLIT = 0, 1, 2, 3
 SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F, SF_DCT8 = 0, 1, 2, 3, 4
 SF_WRAP_REPEAT, SF_WRAP_CLAMP = 0, 1
 SF_MIP_NONE, SF_MIP_NEAREST, SF_MIP_LINEAR = 0, 1, 2
@@ -309,7 +309,8 @@ def sf_filter2d(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, shade: 
         out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
     _need(out, torch.float32, "out", n * ch)
     if dbg_taps is not None:
-        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * (5 if smp.filter == SF_KEYS3 else 3))
+        tw = 5 if (smp.filter == SF_KEYS3 and smp.mode == SF_STOCHASTIC) else 3
+        _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * tw)
     g = C.byref(ggx_params) if ggx_params is not None else None
     _check(lib().sf_filter2d(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), shade, g, _ptr(out),
                              _ptr(dbg_taps), _stream(stream)))

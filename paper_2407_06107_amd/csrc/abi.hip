@@ -30,14 +30,17 @@ sf_status ok()
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-sf_status check_sampling(const sf_sampling *smp)
+// allow_split: the entry point implements SF_SPLIT (the 2-D filters).
+sf_status check_sampling(const sf_sampling *smp, bool allow_split = false)
 {
     if (!smp)
         return fail(SF_E_NULL, "sampling descriptor is NULL");
     if (smp->filter < SF_NEAREST || smp->filter > SF_EWA)
         return fail(SF_E_RANGE, "filter %d out of range", smp->filter);
-    if (smp->mode < SF_BEFORE || smp->mode > SF_STOCHASTIC)
+    if (smp->mode < SF_BEFORE || smp->mode > SF_SPLIT)
         return fail(SF_E_RANGE, "mode %d out of range", smp->mode);
+    if (smp->mode == SF_SPLIT && !allow_split)
+        return fail(SF_E_UNSUPPORTED, "split filtering is a mode of the 2-D filters");
     if (smp->spp < 1 || smp->spp > SF_MAX_SPP)
         return fail(SF_E_RANGE, "spp %d outside 1..%d", smp->spp, SF_MAX_SPP);
     if (smp->rng_variant != 0 && smp->rng_variant != 1)
@@ -212,10 +215,12 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
         return ok();
     if (!tex || !queries || !out)
         return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
-    if ((st = check_sampling(smp)) != SF_OK)
+    if ((st = check_sampling(smp, true)) != SF_OK)
         return st;
     if (smp->filter == SF_EWA)
         return fail(SF_E_UNSUPPORTED, "EWA needs the screen derivatives: use sf_filter2d_aniso");
+    if (smp->mode == SF_SPLIT && (smp->filter > SF_KEYS3 || smp->rng_variant != 0))
+        return fail(SF_E_UNSUPPORTED, "split filtering takes NEAREST, LINEAR, BSPLINE3 or KEYS3 with rng_variant 0");
     if (smp->filter >= SF_KEYS3 && smp->rng_variant != 0)
         return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters draw independent uniforms (rng_variant 0)");
     if ((smp->filter == SF_GAUSS_FRS || smp->filter == SF_GAUSS_FIS) &&
@@ -246,7 +251,7 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
     c.sigma = smp->sigma;
     c.shade = shade;
     c.out = out;
-    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    c.taps = smp->mode == SF_STOCHASTIC || smp->mode == SF_SPLIT ? dbg_taps : nullptr;
     return device_status(sfk::launch_filter2d(c, (hipStream_t)stream));
 }
 
@@ -261,11 +266,15 @@ sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n
         return ok();
     if (!tex || !queries || !out)
         return fail(SF_E_NULL, "tex, queries and out must be non-NULL");
-    if ((st = check_sampling(smp)) != SF_OK)
+    if ((st = check_sampling(smp, true)) != SF_OK)
         return st;
     const int f = smp->filter;
-    if (f != SF_NEAREST && f != SF_LINEAR && f != SF_BSPLINE3 && f != SF_GAUSS_FIS && f != SF_EWA)
+    if (smp->mode == SF_SPLIT) {
+        if (f > SF_KEYS3)
+            return fail(SF_E_UNSUPPORTED, "split filtering takes NEAREST, LINEAR, BSPLINE3 or KEYS3");
+    } else if (f != SF_NEAREST && f != SF_LINEAR && f != SF_BSPLINE3 && f != SF_GAUSS_FIS && f != SF_EWA) {
         return fail(SF_E_UNSUPPORTED, "anisotropic filtering takes NEAREST, LINEAR, BSPLINE3, GAUSS_FIS or EWA");
+    }
     if (f == SF_GAUSS_FIS && smp->mode != SF_STOCHASTIC)
         return fail(SF_E_UNSUPPORTED, "the FIS Gaussian has no probe comparator here");
     if (smp->rng_variant != 0)
@@ -314,7 +323,7 @@ sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n
     c.amax = aniso_max;
     c.shade = shade;
     c.out = out;
-    c.taps = smp->mode == SF_STOCHASTIC ? dbg_taps : nullptr;
+    c.taps = smp->mode == SF_STOCHASTIC || smp->mode == SF_SPLIT ? dbg_taps : nullptr;
     return device_status(sfk::launch_aniso(c, (hipStream_t)stream));
 }
 

@@ -133,6 +133,65 @@ __global__ __launch_bounds__(256) void k_aniso_stoch(AnisoCall c, int log_g)
     }
 }
 
+// Split filtering over the pixel (Sec. 3 eq. split-filtering-shading,
+// estimated as in Sec. 4): per sample the jitter and the jittered level of
+// the stochastic mode (key words 0, 1, 2) sample the low-pass filter; the
+// reconstruction filter is evaluated on that level and shaded once.
+template <int F, int SHADE>
+__global__ __launch_bounds__(256) void k_aniso_split(AnisoCall c, int log_g)
+{
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int G = 1 << log_g;
+    const int64_t q = gid >> log_g;
+    const int lane = (int)(gid & (G - 1));
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool active = q < c.n;
+    if (active) {
+        float qq[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            qq[k] = c.q[6 * q + k];
+        if (!aniso_finite(qq)) {
+            const float nan = __builtin_nanf("");
+            acc = make_float4(nan, nan, nan, nan);
+            if (c.taps)
+                for (int s = lane; s < c.spp; s += G)
+                    for (int k = 0; k < 3; ++k)
+                        c.taps[(q * c.spp + s) * 3 + k] = SF_TAP_NONE;
+        } else {
+            const AnisoLod lod = aniso_lod(c.tex.w, c.tex.h, qq[2], qq[3], qq[4], qq[5], c.amax);
+            const float lmaxf = (float)(c.tex.levels - 1);
+            for (int s = lane; s < c.spp; s += G) {
+                const uint4 w0 = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
+                const float jx = u24(w0.x) - 0.5f, jy = u24(w0.y) - 0.5f;
+                const float u = __builtin_fmaf(jy, qq[4], __builtin_fmaf(jx, qq[2], qq[0]));
+                const float v = __builtin_fmaf(jy, qq[5], __builtin_fmaf(jx, qq[3], qq[1]));
+                float lj = lod.lam + (u24(w0.z) - 0.5f);
+                lj = __builtin_fminf(__builtin_fmaxf(lj, 0.0f), lmaxf);
+                const int l = (int)__builtin_floorf(lj + 0.5f);
+                if (c.taps) {
+                    int32_t *tp = c.taps + (q * c.spp + s) * 3;
+                    tp[0] = l;
+                    tp[1] = SF_TAP_NONE;
+                    tp[2] = SF_TAP_NONE;
+                }
+                const float4 r = recon_level<F>(c.tex, wrap_coord(c.tex.wrap, u), wrap_coord(c.tex.wrap, v), l);
+                acc = add4(acc, shade<SHADE>(c.g, r));
+            }
+        }
+    }
+    for (int m = G >> 1; m >= 1; m >>= 1) {
+        acc.x += __shfl_xor(acc.x, m);
+        acc.y += __shfl_xor(acc.y, m);
+        acc.z += __shfl_xor(acc.z, m);
+        acc.w += __shfl_xor(acc.w, m);
+    }
+    if (active && lane == 0) {
+        const float inv = 1.0f / (float)c.spp;
+        store<SHADE>(c.out, q, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
+    }
+}
+
 // Probe comparators (binary32 weights as the plain deterministic kernel,
 // binary64 sums over up to 64 probes x 2 levels x 16 taps).
 template <int F, int SHADE, int MODE>
@@ -478,7 +537,17 @@ static void launch_ewa(const AnisoCall &c, hipStream_t s)
 template <int F, int SHADE>
 static void launch_a2(const AnisoCall &c, hipStream_t s)
 {
-    if (c.mode == STOCH) {
+    if constexpr (F <= KEYS3) {
+        if (c.mode == SPLIT) {
+            const int G = lane_group(c.n, c.spp);
+            const int64_t threads = c.n * G;
+            k_aniso_split<F, SHADE><<<dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s>>>(c, __builtin_ctz(G));
+            return;
+        }
+    }
+    if constexpr (F == KEYS3)
+        return;   // the Keys cubic takes the split mode only here
+    else if (c.mode == STOCH) {
         const int G = lane_group(c.n, c.spp);
         const int64_t threads = c.n * G;
         k_aniso_stoch<F, SHADE><<<dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s>>>(c, __builtin_ctz(G));
@@ -511,6 +580,9 @@ hipError_t launch_aniso(const AnisoCall &c, hipStream_t s)
         break;
     case GAUSS_FIS:
         launch_a1<GAUSS_FIS>(c, s);
+        break;
+    case KEYS3:
+        launch_a1<KEYS3>(c, s);
         break;
     case EWA:
         if (c.shade == SF_SHADE_GGX)

@@ -141,6 +141,59 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
     }
 }
 
+// Split filtering (Sec. 3 eq. split-filtering-shading, estimated as in
+// Sec. 4): per sample the stochastic level of the key's word 3 (the low-pass
+// filter over levels, sampled), then shade(sum_i w_i t_i) of that level (the
+// reconstruction filter, evaluated before shading).
+template <int F, int SHADE>
+__global__ __launch_bounds__(256) void k_filter2d_split(Filter2DCall c, int log_g)
+{
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int G = 1 << log_g;
+    const int64_t q = gid >> log_g;
+    const int lane = (int)(gid & (G - 1));
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool active = q < c.n;
+    if (active) {
+        float3 qq = make_float3(c.q[3 * q], c.q[3 * q + 1], c.q[3 * q + 2]);
+        if (!query_ok(c.tex, qq)) {
+            float nan = __builtin_nanf("");
+            acc = make_float4(nan, nan, nan, nan);
+            if (c.taps)
+                for (int s = lane; s < c.spp; s += G)
+                    for (int k = 0; k < 3; ++k)
+                        c.taps[(q * c.spp + s) * 3 + k] = SF_TAP_NONE;
+        } else {
+            const float uu = wrap_coord(c.tex.wrap, qq.x), vv = wrap_coord(c.tex.wrap, qq.y);
+            int l0, l1;
+            float f;
+            levels_of(c.tex, qq.z, l0, l1, f);
+            const float cl = 1.0f - f;
+            for (int s = lane; s < c.spp; s += G) {
+                const uint4 w = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
+                const int l = u24(w.w) >= cl ? l1 : l0;
+                if (c.taps) {
+                    int32_t *tp = c.taps + (q * c.spp + s) * 3;
+                    tp[0] = l;
+                    tp[1] = SF_TAP_NONE;
+                    tp[2] = SF_TAP_NONE;
+                }
+                acc = add4(acc, shade<SHADE>(c.g, recon_level<F>(c.tex, uu, vv, l)));
+            }
+        }
+    }
+    for (int m = G >> 1; m >= 1; m >>= 1) {
+        acc.x += __shfl_xor(acc.x, m);
+        acc.y += __shfl_xor(acc.y, m);
+        acc.z += __shfl_xor(acc.z, m);
+        acc.w += __shfl_xor(acc.w, m);
+    }
+    if (active && lane == 0) {
+        const float inv = 1.0f / (float)c.spp;
+        store<SHADE>(c.out, q, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
+    }
+}
+
 template <int F, int SHADE, int MODE>
 __global__ __launch_bounds__(256) void k_filter2d_det(Filter2DCall c)
 {
@@ -277,6 +330,15 @@ __global__ __launch_bounds__(256) void k_filter2d_gauss_det(Filter2DCall c)
 template <int F, int SHADE>
 static void launch_f2(const Filter2DCall &c, hipStream_t s)
 {
+    if constexpr (F <= KEYS3) {
+        if (c.mode == SPLIT) {
+            const int G = lane_group(c.n, c.spp);
+            const int64_t threads = c.n * G;
+            k_filter2d_split<F, SHADE>
+                <<<dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s>>>(c, __builtin_ctz(G));
+            return;
+        }
+    }
     if (c.mode == STOCH) {
         const int G = lane_group(c.n, c.spp);
         int log_g = __builtin_ctz(G);

@@ -15,7 +15,7 @@
 namespace sfk {
 
 enum { NEAREST = 0, LINEAR = 1, BSPLINE3 = 2, KEYS3 = 3, GAUSS_FRS = 4, GAUSS_FIS = 5, BSPLINE3_FIS = 6, EWA = 7 };
-enum { BEFORE = 0, AFTER = 1, STOCH = 2 };
+enum { BEFORE = 0, AFTER = 1, STOCH = 2, SPLIT = 3 };
 
 // ---------------------------------------------------------------- random stream
 // 4-D PCG hash (Jarzynski & Olano, "Hash Functions for GPU Rendering",

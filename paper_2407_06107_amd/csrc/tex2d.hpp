@@ -151,4 +151,40 @@ __device__ __forceinline__ bool query_ok(const Tex2DArgs &tx, float3 q)
 
 __device__ __forceinline__ float4 add4(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
 
+// The reconstruction filter alone on level l at the wrapped coordinate
+// (uu, vv): sum_i w_i t_i with binary32 weights, as the deterministic kernels
+// (the split-filtering estimator shades this once per sample).
+template <int F>
+__device__ __forceinline__ float4 recon_level(const Tex2DArgs &tx, float uu, float vv, int l)
+{
+    constexpr int NT = Taps<F>::n;
+    constexpr int F0 = Taps<F>::first;
+    const int wl = max(1, tx.w >> l), hl = max(1, tx.h >> l);
+    int ix, iy;
+    float fx, fy, wx[4], wy[4];
+    raster(uu, wl, ix, fx);
+    raster(vv, hl, iy, fy);
+    if constexpr (F == NEAREST) {
+        ix += fx >= 0.5f;
+        iy += fy >= 0.5f;
+    }
+    axis_weights<F>(fx, wx);
+    axis_weights<F>(fy, wy);
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+        const int y = wrap_tap(tx.wrap, iy + F0 + b, hl);
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            const float wgt = wx[a] * wy[b];
+            const float4 t = texel(tx, l, wrap_tap(tx.wrap, ix + F0 + a, wl), y);
+            sum.x = __builtin_fmaf(wgt, t.x, sum.x);
+            sum.y = __builtin_fmaf(wgt, t.y, sum.y);
+            sum.z = __builtin_fmaf(wgt, t.z, sum.z);
+            sum.w = __builtin_fmaf(wgt, t.w, sum.w);
+        }
+    }
+    return sum;
+}
+
 }  // namespace sfk

@@ -84,7 +84,7 @@ FAKE = C.c_void_p(0x10000)   # a host-side stand-in pointer: never dereferenced,
     ("n_negative", 2), ("n_zero", 0), ("null_rays", 1), ("steps_zero", 2), ("steps_big", 2),
     ("bad_filter", 2), ("bad_mode", 2), ("spp_zero", 2), ("bad_variant", 2), ("null_volume", 1),
     ("bad_format", 3), ("dims_zero", 2), ("scale_zero", 2), ("misaligned_rays", 2), ("n_huge", 2),
-    ("bad_brick", 2), ("reserved", 2), ("keys", 3),
+    ("bad_brick", 2), ("reserved", 2), ("keys", 3), ("split", 3),
 ])
 @pytest.mark.parametrize("entry", ["sf_raymarch", "sf_raymarch_emission"])
 def test_raymarch_validation(sf, case, status, entry):
@@ -105,7 +105,7 @@ def test_raymarch_validation(sf, case, status, entry):
     elif case == "bad_filter":
         smp.filter = 8
     elif case == "bad_mode":
-        smp.mode = 3
+        smp.mode = 4
     elif case == "spp_zero":
         smp.spp = 0
     elif case == "bad_variant":
@@ -129,6 +129,8 @@ def test_raymarch_validation(sf, case, status, entry):
         vol.reserved = 1
     elif case == "keys":
         smp.filter = sf.SF_KEYS3
+    elif case == "split":
+        smp.mode = sf.SF_SPLIT
     args = (C.byref(vol) if vol is not None else None, rays, n, steps, C.byref(smp))
     if entry == "sf_raymarch_emission":
         args += (C.c_float(0.0),)
@@ -142,7 +144,7 @@ def test_raymarch_validation(sf, case, status, entry):
     ("ok_zero", 0), ("null_tex", 1), ("null_base", 1), ("bad_format", 3), ("levels_zero", 2),
     ("levels_too_many", 2), ("bad_wrap", 2), ("bad_mip", 2), ("ggx_missing", 1), ("bad_shade", 2),
     ("ggx_backfacing", 2), ("misaligned_level", 2), ("width_zero", 2), ("keys_ok_zero", 0),
-    ("keys_reuse", 3), ("filter_8", 2), ("ewa", 3), ("gauss_sigma_small", 2), ("gauss_sigma_nan", 2), ("fis_sigma_big", 2),
+    ("keys_reuse", 3), ("filter_8", 2), ("ewa", 3), ("split_gauss", 3), ("split_reuse", 3), ("mode_4", 2), ("gauss_sigma_small", 2), ("gauss_sigma_nan", 2), ("fis_sigma_big", 2),
     ("gauss_reuse", 3), ("fis_bspline_reuse", 3), ("fis_bspline_any_sigma_zero", 0),
 ])
 def test_filter2d_validation(sf, case, status):
@@ -190,6 +192,12 @@ def test_filter2d_validation(sf, case, status):
         smp = sf.sampling(8, sf.SF_STOCHASTIC, 4)
     elif case == "ewa":
         smp = sf.sampling(sf.SF_EWA, sf.SF_STOCHASTIC, 4)
+    elif case == "split_gauss":
+        smp = sf.sampling(sf.SF_GAUSS_FRS, sf.SF_SPLIT, 4)
+    elif case == "split_reuse":
+        smp = sf.sampling(sf.SF_LINEAR, sf.SF_SPLIT, 4, rng_variant=1)
+    elif case == "mode_4":
+        smp = sf.sampling(sf.SF_LINEAR, 4, 4)
     elif case == "gauss_sigma_small":
         smp = sf.sampling(sf.SF_GAUSS_FRS, sf.SF_STOCHASTIC, 4, sigma=0.05)
     elif case == "gauss_sigma_nan":
@@ -211,7 +219,7 @@ def test_filter2d_validation(sf, case, status):
     ("ok_zero", 0), ("null_tex", 1), ("null_q", 1), ("keys", 3), ("gauss_frs", 3), ("fis_det", 3),
     ("reuse", 3), ("aniso_0", 2), ("aniso_65", 2), ("fis_sigma", 2), ("bad_levels", 2), ("bad_shade", 2),
     ("ewa_ok_zero", 0), ("ewa_amax17", 2), ("ewa_partial", 3), ("ewa_aspect", 3), ("ewa_reuse", 3),
-    ("ewa_aspect8_partial", 3),
+    ("ewa_aspect8_partial", 3), ("split_ewa", 3), ("split_fis", 3),
 ])
 def test_filter2d_aniso_validation(sf, case, status):
     L = sf.lib()
@@ -244,6 +252,10 @@ def test_filter2d_aniso_validation(sf, case, status):
         tex.levels = 8
     elif case == "bad_shade":
         shade = 3
+    elif case == "split_ewa":
+        smp = sf.sampling(sf.SF_EWA, sf.SF_SPLIT, 4)
+    elif case == "split_fis":
+        smp = sf.sampling(sf.SF_GAUSS_FIS, sf.SF_SPLIT, 4)
     elif case.startswith("ewa"):
         smp = sf.sampling(sf.SF_EWA, sf.SF_STOCHASTIC, 4, rng_variant=1 if case == "ewa_reuse" else 0)
         amax = 16

@@ -468,6 +468,44 @@ def test_filter2d_gauss_fis_config2_full_sampled(sf, orc, c2_full, filt, sigma):
     _close(out[sub], ref)
 
 
+# ------------------------------------------------------------------ split filtering
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3", "KEYS3"])
+@pytest.mark.parametrize("mip", [0, 1, 2])
+@pytest.mark.parametrize("spp", [1, 8])
+@pytest.mark.parametrize("shade", [0, 1])
+def test_filter2d_split(sf, orc, c2_small, filt, mip, spp, shade):
+    """Split filtering: the level pick bit-exact, the reconstruction of
+    that level before shading to the float tolerance."""
+    _print_case("filter2d_split", filt, mip, spp, shade)
+    lv, q = c2_small
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, mip)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=mip)
+    f = getattr(orc, filt)
+    smp = sf.sampling(f, sf.SF_SPLIT, spp, seed=8)
+    taps_d = torch.full((q.shape[0], spp, 3), 99, dtype=torch.int32, device="cuda")
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=shade, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    ref, taps = orc.filter2d(ot, q, f, orc.SPLIT, spp=spp, seed=8, shade=shade, taps=True)
+    assert np.array_equal(taps_d.cpu().numpy(), taps)
+    if filt == "KEYS3":
+        _close_signed(out.cpu().numpy(), ref, np.nanmax(np.abs(ref)))
+    else:
+        _close(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("wrap", [0, 1])
+def test_filter2d_split_single_level_is_before(sf, orc, c1, wrap):
+    """One level: the split estimator returns the filter-before value."""
+    _print_case("filter2d_split_single", wrap)
+    tex, q = c1
+    gt = sf.Texture2D([tex], wrap=wrap)
+    qd = torch.from_numpy(q).cuda()
+    for f in (sf.SF_LINEAR, sf.SF_BSPLINE3):
+        a = sf.sf_filter2d(gt, qd, sf.sampling(f, sf.SF_SPLIT, 4, seed=2), shade=1, ggx_params=sf.ggx())
+        b = sf.sf_filter2d(gt, qd, sf.sampling(f, sf.SF_BEFORE, 1), shade=1, ggx_params=sf.ggx())
+        _close(a.cpu().numpy(), b.cpu().numpy(), rtol=1e-6)
+
+
 # ------------------------------------------------------------------ 2-D anisotropic minification
 @pytest.fixture(scope="module")
 def aniso_small(orc):
@@ -506,6 +544,31 @@ def test_filter2d_aniso_parity(sf, orc, aniso_small, filt, sigma, mode, spp, ama
     else:
         ref = res
     _close(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3", "KEYS3"])
+@pytest.mark.parametrize("spp", [1, 8])
+@pytest.mark.parametrize("amax", [64, 4])
+@pytest.mark.parametrize("shade", [0, 1])
+def test_filter2d_aniso_split(sf, orc, aniso_small, filt, spp, amax, shade):
+    """Split filtering over the pixel: jitter and level bit-exact (taps hold
+    the level), the level's reconstruction before shading to tolerance."""
+    _print_case("filter2d_aniso_split", filt, spp, amax, shade)
+    lv, q = aniso_small
+    buf, offs = inputs.pack_levels(lv)
+    ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+    gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    f = getattr(orc, filt)
+    smp = sf.sampling(f, sf.SF_SPLIT, spp, seed=12)
+    taps_d = torch.full((q.shape[0], spp, 3), 99, dtype=torch.int32, device="cuda")
+    out = sf.sf_filter2d_aniso(gt, torch.from_numpy(q).cuda(), smp, aniso_max=amax, shade=shade,
+                               ggx_params=sf.ggx(), dbg_taps=taps_d)
+    ref, taps = orc.filter2d_aniso(ot, q, f, orc.SPLIT, spp=spp, seed=12, shade=shade, taps=True, amax=amax)
+    assert np.array_equal(taps_d.cpu().numpy(), taps)
+    if filt == "KEYS3":
+        _close_signed(out.cpu().numpy(), ref, np.nanmax(np.abs(ref)))
+    else:
+        _close(out.cpu().numpy(), ref)
 
 
 @pytest.fixture(scope="module")
