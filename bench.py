@@ -259,6 +259,8 @@ def aniso_bench(res):
             ("aniso_bicubic_stochastic_16spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 16, 64),
             ("aniso_bilinear_stochastic_1spp", sf.SF_LINEAR, sf.SF_STOCHASTIC, 1, 64),
             ("aniso_gauss_fis_stochastic_16spp", sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 16, 64),
+            ("aniso_bicubic_split_1spp", sf.SF_BSPLINE3, sf.SF_SPLIT, 1, 64),
+            ("aniso_bicubic_split_16spp", sf.SF_BSPLINE3, sf.SF_SPLIT, 16, 64),
             ("aniso16_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 16),
             ("aniso64_trilinear_probes_before", sf.SF_LINEAR, sf.SF_BEFORE, 1, 64),
             ("aniso64_trilinear_probes_after", sf.SF_LINEAR, sf.SF_AFTER_EXACT, 1, 64),
