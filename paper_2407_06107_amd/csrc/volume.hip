@@ -82,13 +82,21 @@ __device__ __forceinline__ void step_coords(const RayGeom &g, float kh, int i0[3
 // filter lies within [i0-1, i0+2] per axis, inside the brick's 2-voxel
 // dilation, so a clear bit means every tap reads zero.  Bricks outside the
 // grid (points within a voxel of the lower faces) count as occupied.
+// P2: nx and ny are powers of two, so are the brick counts along x and y
+// (nx >> occ_log2, or 1 below one brick) and the index is built with shifts.
+template <bool P2 = false>
 __device__ __forceinline__ bool brick_occupied(const VolArgs &v, const int i0[3])
 {
     const int bx = i0[0] >> v.occ_log2, by = i0[1] >> v.occ_log2, bz = i0[2] >> v.occ_log2;
     const bool in = ((uint32_t)bx < (uint32_t)v.nbx) & ((uint32_t)by < (uint32_t)v.nby) &
                     ((uint32_t)bz < (uint32_t)v.nbz);
-    const uint32_t b =
-        __umul24(__umul24((uint32_t)bz, (uint32_t)v.nby) + (uint32_t)by, (uint32_t)v.nbx) + (uint32_t)bx;
+    uint32_t b;
+    if constexpr (P2) {
+        const int lbx = max(v.lx - v.occ_log2, 0), lby = max(v.ly - v.occ_log2, 0);
+        b = ((((uint32_t)bz << lby) | (uint32_t)by) << lbx) | (uint32_t)bx;
+    } else {
+        b = __umul24(__umul24((uint32_t)bz, (uint32_t)v.nby) + (uint32_t)by, (uint32_t)v.nbx) + (uint32_t)bx;
+    }
     const uint32_t w = v.occ[in ? (b >> 5) : 0u];
     return !in | (((w >> (b & 31u)) & 1u) != 0u);
 }
@@ -171,6 +179,7 @@ __device__ __forceinline__ void planck3(float T, float B[3])
 template <int F, bool HALF, int VAR, bool DBG, bool OCC, bool P2>
 __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_pad)
 {
+    static_assert(!(DBG && OCC), "the tap dump records every step, so it never skips bricks");
     const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
     if (i >= c.n)
         return;
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
             float t[3];
             step_coords(g, kh, i0, t);
             if constexpr (OCC) {
-                if (!brick_occupied(c.vol, i0))
+                if (!brick_occupied<P2>(c.vol, i0))
                     continue;   // the step would add exactly 0.0 to tau
             }
             pick3<F, VAR>(t, h.at((uint32_t)k), o);
@@ -386,7 +395,7 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
                 step_coords(g, kh, i0, t);
             }
             if constexpr (OCC) {
-                if (!brick_occupied(c.vol, i0))
+                if (!brick_occupied<P2>(c.vol, i0))
                     continue;
             }
             pick3<F, VAR>(t, h.at((uint32_t)k), o);
