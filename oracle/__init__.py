@@ -21,7 +21,7 @@ _SRCS = [_SRC, os.path.join(_HERE, "neural.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # enums of the oracle (its own copy; it does not include the library header)
-NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS, EWA = 0, 1, 2, 3, 4, 5, 6, 7
+NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS, EWA, MITCHELL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 SIGMA_MIN, SIGMA_MAX = 1.0 / 16.0, 4.0     # Gaussian standard deviation, texels
 BEFORE, AFTER, STOCHASTIC, SPLIT = 0, 1, 2, 3
 RGBA32F, RGBA8, R16F, R32F, DCT8 = 0, 1, 2, 3, 4
@@ -125,6 +125,11 @@ def lib():
         L.orc_k3.argtypes = [C.c_double]
         L.orc_keys_pick.argtypes = [f32, f32, P, P, P]
         L.orc_keys_expect2d.argtypes = [P, i32, i32, i32, i32, P, i64, i32, P, P]
+        L.orc_kmn.restype = C.c_double
+        L.orc_kmn.argtypes = [C.c_double]
+        L.orc_mitchell_pick.argtypes = [f32, f32, P, P, P]
+        L.orc_mitchell_axis.argtypes = [f32, P, P, P]
+        L.orc_mitchell_expect2d.argtypes = [P, i32, i32, i32, i32, P, i64, i32, P, P]
         L.orc_f32_to_bf16.restype = C.c_uint16
         L.orc_f32_to_bf16.argtypes = [f32]
         L.orc_bf16_to_double.restype = C.c_double
@@ -299,7 +304,8 @@ def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed
     m = n if sub is None else sub.size
     ch = 3 if shade == 1 else 4
     out = np.zeros((m, ch))
-    tp = np.zeros((m, spp, 5 if (filt == KEYS3 and mode == STOCHASTIC) else 3), dtype=np.int32) if taps else None
+    tp = np.zeros((m, spp, 5 if (filt in (KEYS3, MITCHELL) and mode == STOCHASTIC) else 3), dtype=np.int32) \
+        if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_filter2d(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip, _p(tex.off),
                        _p(tex.dct_range), _p(q), n, filt, mode, spp, seed & 0xFFFFFFFF, variant, sigma, shade, _p(g), _p(out), _p(tp),
@@ -714,4 +720,37 @@ def keys_expect2d(tex: Tex2D, q: np.ndarray, shade: int = 0, ggx=None):
     out = np.zeros((q.shape[0], ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_keys_expect2d(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(q), q.shape[0], shade, _p(g), _p(out))
+    return out
+
+
+def kmn(x: float) -> float:
+    """Mitchell-Netravali cubic, B = C = 1/3 (binary64)."""
+    return lib().orc_kmn(float(x))
+
+
+def mitchell_axis(t: float):
+    """Binary32 tap weights (taps i0-1..i0+2) and the positive / negative
+    sums of one axis."""
+    w = np.zeros(4, dtype=np.float32)
+    pp = np.zeros(1, dtype=np.float32)
+    pm = np.zeros(1, dtype=np.float32)
+    lib().orc_mitchell_axis(float(t), _p(w), _p(pp), _p(pm))
+    return w, float(pp[0]), float(pm[0])
+
+
+def mitchell_pick(tx: float, ty: float, u) -> tuple:
+    uu = _c(u, np.float32)
+    off = np.zeros(4, dtype=np.int32)
+    hn = np.zeros(1, dtype=np.int32)
+    lib().orc_mitchell_pick(float(tx), float(ty), _p(uu), _p(off), _p(hn))
+    return off, bool(hn[0])
+
+
+def mitchell_expect2d(tex: Tex2D, q: np.ndarray, shade: int = 0, ggx=None):
+    q = _c(q, np.float32).reshape(-1, 3)
+    ch = 3 if shade == 1 else 4
+    out = np.zeros((q.shape[0], ch))
+    g = _c(ggx if ggx is not None else ggx_params(), np.float64)
+    lib().orc_mitchell_expect2d(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(q), q.shape[0], shade, _p(g),
+                                _p(out))
     return out

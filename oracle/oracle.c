@@ -61,7 +61,7 @@
 #define ORC_EXPORT __attribute__((visibility("default")))
 
 enum { F_NEAREST = 0, F_LINEAR = 1, F_BSPLINE3 = 2, F_KEYS3 = 3, F_GAUSS_FRS = 4, F_GAUSS_FIS = 5,
-       F_BSPLINE3_FIS = 6, F_EWA = 7 };
+       F_BSPLINE3_FIS = 6, F_EWA = 7, F_MITCHELL = 8 };
 enum { M_BEFORE = 0, M_AFTER = 1, M_STOCH = 2, M_SPLIT = 3 };
 enum { FMT_RGBA32F = 0, FMT_RGBA8 = 1, FMT_R16F = 2, FMT_R32F = 3, FMT_DCT8 = 4 };
 enum { WRAP_REPEAT = 0, WRAP_CLAMP = 1 };
@@ -136,6 +136,21 @@ ORC_EXPORT double orc_k3(double x)
     return 0.0;
 }
 
+/* The Mitchell-Netravali cubic with B = C = 1/3 (Mitchell and Netravali,
+ * "Reconstruction Filters in Computer Graphics", 1988), the other reading of
+ * the paper's "Mitchell" filter: (7|x|^3 - 12|x|^2 + 16/3)/6 on |x| < 1 and
+ * (-7/3 |x|^3 + 12|x|^2 - 20|x| + 32/3)/6 on 1 <= |x| < 2, whose outer lobe
+ * changes sign at |x| = 8/7. */
+ORC_EXPORT double orc_kmn(double x)
+{
+    double t = fabs(x);
+    if (t < 1.0)
+        return (7.0 * t * t * t - 12.0 * t * t + 16.0 / 3.0) / 6.0;
+    if (t < 2.0)
+        return (-7.0 / 3.0 * t * t * t + 12.0 * t * t - 20.0 * t + 32.0 / 3.0) / 6.0;
+    return 0.0;
+}
+
 ORC_EXPORT double orc_ktent(double x)
 {
     double a = fabs(x);
@@ -163,6 +178,12 @@ static int axis_weights(int filter, double t, int *first_off, double w[4])
         *first_off = -1;
         for (int k = 0; k < 4; ++k)
             w[k] = orc_k3(t - (double)(k - 1));
+        return 4;
+    }
+    if (filter == F_MITCHELL) {
+        *first_off = -1;
+        for (int k = 0; k < 4; ++k)
+            w[k] = orc_kmn(t - (double)(k - 1));
         return 4;
     }
     /* nearest (box, S.2 K0): the texel whose cell contains the point */
@@ -291,6 +312,108 @@ static void keys_block_sums(double tx, double ty, double *Wp, double *Wm)
     double Ppy = wy[1] + wy[2], Pmy = -(wy[0] + wy[3]);
     *Wp = Ppx * Ppy + Pmx * Pmy;
     *Wm = Ppx * Pmy + Pmx * Ppy;
+}
+
+/* Positivisation of the separable Mitchell-Netravali cubic (Sec. 2.2
+ * "Positivization"; the paper's listing sorts each weight into a positive
+ * or a negative reservoir by its sign).  Per axis the weights of taps
+ * i0-1..i0+2 in factored binary32 form, s = 1-t:
+ *   w0 = ((s s) fma(-7, t, 1)) K18, w1 = fma(t t, fma(K76, t, -2), K89),
+ *   w2 = fma(s s, fma(K76, s, -2), K89), w3 = ((t t) fma(7, t, -6)) K18,
+ * K18 = fl(1/18), K76 = fl(7/6), K89 = fl(8/9) (the inner taps are always
+ * positive; w0 is positive for t < 1/7 and w3 for t > 6/7).  The positive
+ * set of an axis is its taps with w > 0, the negative set those with w < 0;
+ * P+ and P- are their |w| summed in tap order.  Inside a set the tap is the
+ * first (in tap order) whose running sum c of |w| satisfies u P < c (the
+ * set's last tap otherwise).  Blocks and their decisions as for the Keys
+ * cubic: (+,+) iff u (A + B) < A with A = P+x P+y, B = P-x P-y; (+,-) iff
+ * u (Cn + Dn) < Cn with Cn = P+x P-y, Dn = P-x P+y; the estimate is
+ * (A + B) f(t+) - (Cn + Dn) f(t-). */
+typedef struct {
+    float w[4], Pp, Pm;
+} pn_axis;
+
+static pn_axis mitchell_axis_of(float t)
+{
+    const float K18 = 1.0f / 18.0f, K76 = 7.0f / 6.0f, K89 = 8.0f / 9.0f;
+    pn_axis a;
+    float s = 1.0f - t;
+    a.w[0] = ((s * s) * fmaf(-7.0f, t, 1.0f)) * K18;
+    a.w[1] = fmaf(t * t, fmaf(K76, t, -2.0f), K89);
+    a.w[2] = fmaf(s * s, fmaf(K76, s, -2.0f), K89);
+    a.w[3] = ((t * t) * fmaf(7.0f, t, -6.0f)) * K18;
+    a.Pp = 0.0f;
+    a.Pm = 0.0f;
+    for (int k = 0; k < 4; ++k) {
+        if (a.w[k] > 0.0f)
+            a.Pp = a.Pp + a.w[k];
+        else if (a.w[k] < 0.0f)
+            a.Pm = a.Pm + (-a.w[k]);
+    }
+    return a;
+}
+
+/* tap (0..3) of the positive (sign > 0) or negative set of one axis */
+static int pn_pick(const pn_axis *a, int sign, float u)
+{
+    const float P = sign > 0 ? a->Pp : a->Pm;
+    const float uP = u * P;
+    float c = 0.0f;
+    int last = -1;
+    for (int k = 0; k < 4; ++k) {
+        float m = sign > 0 ? a->w[k] : -a->w[k];
+        if (!(m > 0.0f))
+            continue;
+        c = c + m;
+        last = k;
+        if (uP < c)
+            return k;
+    }
+    return last;
+}
+
+ORC_EXPORT void orc_mitchell_axis(float t, float w[4], float *Pp, float *Pm)
+{
+    pn_axis a = mitchell_axis_of(t);
+    for (int k = 0; k < 4; ++k)
+        w[k] = a.w[k];
+    *Pp = a.Pp;
+    *Pm = a.Pm;
+}
+
+/* Tap offsets (relative to i0) of the positive and negative samples. */
+ORC_EXPORT void orc_mitchell_pick(float tx, float ty, const float u[6], int off[4], int *has_neg)
+{
+    pn_axis ax = mitchell_axis_of(tx), ay = mitchell_axis_of(ty);
+    float A = ax.Pp * ay.Pp, B = ax.Pm * ay.Pm;
+    int pp = u[2] * (A + B) < A;
+    off[0] = pn_pick(&ax, pp ? 1 : -1, u[0]) - 1;
+    off[1] = pn_pick(&ay, pp ? 1 : -1, u[1]) - 1;
+    float Cn = ax.Pp * ay.Pm, Dn = ax.Pm * ay.Pp;
+    *has_neg = (Cn + Dn) > 0.0f;
+    int xpos = u[5] * (Cn + Dn) < Cn;
+    off[2] = pn_pick(&ax, xpos ? 1 : -1, u[3]) - 1;
+    off[3] = pn_pick(&ay, xpos ? -1 : 1, u[4]) - 1;
+}
+
+/* binary64 block sums of the positive and negative product weights of the
+ * Mitchell-Netravali cubic */
+static void mitchell_block_sums(double tx, double ty, double *Wp, double *Wm)
+{
+    double px = 0, mx = 0, py = 0, my = 0;
+    for (int k = 0; k < 4; ++k) {
+        double a = orc_kmn(tx - (double)(k - 1)), b = orc_kmn(ty - (double)(k - 1));
+        if (a > 0)
+            px += a;
+        else
+            mx -= a;
+        if (b > 0)
+            py += b;
+        else
+            my -= b;
+    }
+    *Wp = px * py + mx * my;
+    *Wm = px * my + mx * py;
 }
 
 /* Index of the picked tap among the filter's taps (0..3), ties advance. */
@@ -877,7 +1000,7 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
         for (int c = 0; c < ch; ++c)
             out[c] = NAN;
         if (taps && (mode == M_STOCH || mode == M_SPLIT))
-            for (int s = 0; s < (filter == F_KEYS3 && mode == M_STOCH ? 5 : 3) * spp; ++s)
+            for (int s = 0; s < ((filter == F_KEYS3 || filter == F_MITCHELL) && mode == M_STOCH ? 5 : 3) * spp; ++s)
                 taps[s] = INT32_MIN;
         return;
     }
@@ -921,15 +1044,20 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
             float tx, ty;
             raster(uu, wl, &ix, &tx);
             raster(vv, hl, &iy, &ty);
-            if (filter == F_KEYS3) {
+            if (filter == F_KEYS3 || filter == F_MITCHELL) {
                 /* positivised estimator: W+ shade(t+) - W- shade(t-) */
                 uint32_t key2[4] = {(uint32_t)qi, (uint32_t)s, 1u, seed}, w2[4];
                 orc_pcg4d(key2, w2);
                 float u6[6] = {ux, uy, uniform24(w[2]), uniform24(w2[0]), uniform24(w2[1]), uniform24(w2[2])};
                 int off[4], has_neg;
-                orc_keys_pick(tx, ty, u6, off, &has_neg);
                 double Wp, Wm;
-                keys_block_sums((double)tx, (double)ty, &Wp, &Wm);
+                if (filter == F_KEYS3) {
+                    orc_keys_pick(tx, ty, u6, off, &has_neg);
+                    keys_block_sums((double)tx, (double)ty, &Wp, &Wm);
+                } else {
+                    orc_mitchell_pick(tx, ty, u6, off, &has_neg);
+                    mitchell_block_sums((double)tx, (double)ty, &Wp, &Wm);
+                }
                 int xp = wrap_tap(t->wrap, ix + off[0], wl), yp = wrap_tap(t->wrap, iy + off[1], hl);
                 int xn = wrap_tap(t->wrap, ix + off[2], wl), yn = wrap_tap(t->wrap, iy + off[3], hl);
                 if (taps) {
@@ -1084,7 +1212,7 @@ ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt,
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i) {
         int64_t qi = subset ? subset[i] : i;
-        int tw = filter == F_KEYS3 && mode == M_STOCH ? 5 : 3;
+        int tw = (filter == F_KEYS3 || filter == F_MITCHELL) && mode == M_STOCH ? 5 : 3;
         filter2d_one(&t, q + 3 * qi, qi, filter, mode, spp, seed, variant, sigma, shade, ggx, out + ch * i,
                      taps ? taps + (int64_t)tw * spp * i : NULL);
     }
@@ -1101,7 +1229,7 @@ ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, i
                                    int filter,
                                    float sigma, int shade, const double *ggx, double *out)
 {
-    if (filter == F_KEYS3 || filter == F_GAUSS_FIS)
+    if (filter == F_KEYS3 || filter == F_MITCHELL || filter == F_GAUSS_FIS)
         return -1;
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off, dct_range};
     int ch = shade == 1 ? 3 : 4;
@@ -1967,6 +2095,70 @@ ORC_EXPORT int orc_keys_expect2d(const void *base, int w, int h, int fmt, int wr
         double pblk = frac_lt(A + B, A), nblk = (Cn + Dn) > 0.0f ? frac_lt(Cn + Dn, Cn) : 0.0;
         double PX[2][4] = {{0, pxp, 1 - pxp, 0}, {pxm, 0, 0, 1 - pxm}}; /* [pos/neg pair][tap] */
         double PY[2][4] = {{0, pyp, 1 - pyp, 0}, {pym, 0, 0, 1 - pym}};
+        double acc[4] = {0, 0, 0, 0};
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                double texel[4], v[4];
+                fetch2d(&t, 0, wrap_tap(wrap, ix - 1 + a, w), wrap_tap(wrap, iy - 1 + b, h), texel);
+                shade2d(shade, ggx, texel, v);
+                double ppos = pblk * PX[0][a] * PY[0][b] + (1 - pblk) * PX[1][a] * PY[1][b];
+                double pneg = nblk * PX[0][a] * PY[1][b] + (1 - nblk) * PX[1][a] * PY[0][b];
+                for (int c = 0; c < ch; ++c)
+                    acc[c] += Wp * ppos * v[c] - ((Cn + Dn) > 0.0f ? Wm * pneg * v[c] : 0.0);
+            }
+        for (int c = 0; c < ch; ++c)
+            out[ch * i + c] = acc[c];
+    }
+    return 0;
+}
+
+/* Per-tap probabilities of pn_pick on the positive (row 0) and negative
+ * (row 1) set of one axis over the 24-bit lattice. */
+static void pn_probs(const pn_axis *a, double P[2][4])
+{
+    for (int r = 0; r < 2; ++r) {
+        const float Ps = r == 0 ? a->Pp : a->Pm;
+        float c = 0.0f;
+        double prev = 0.0;
+        int last = -1;
+        for (int k = 0; k < 4; ++k) {
+            P[r][k] = 0.0;
+            float m = r == 0 ? a->w[k] : -a->w[k];
+            if (!(m > 0.0f))
+                continue;
+            c = c + m;
+            double cur = frac_lt(Ps, c);
+            P[r][k] = cur - prev;
+            prev = cur;
+            last = k;
+        }
+        if (last >= 0)
+            P[r][last] += 1.0 - prev;   /* the set's last tap takes the rest */
+    }
+}
+
+/* Exact expectation of the positivised Mitchell-Netravali estimator (level
+ * 0), as orc_keys_expect2d. */
+ORC_EXPORT int orc_mitchell_expect2d(const void *base, int w, int h, int fmt, int wrap, const float *q, int64_t n,
+                                     int shade, const double *ggx, double *out)
+{
+    const int64_t off0 = 0;
+    tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0};
+    int ch = shade == 1 ? 3 : 4;
+    for (int64_t i = 0; i < n; ++i) {
+        float uu = wrap_coord(wrap, q[3 * i]), vv = wrap_coord(wrap, q[3 * i + 1]);
+        int ix, iy;
+        float tx, ty;
+        raster(uu, w, &ix, &tx);
+        raster(vv, h, &iy, &ty);
+        pn_axis ax = mitchell_axis_of(tx), ay = mitchell_axis_of(ty);
+        double Wp, Wm;
+        mitchell_block_sums((double)tx, (double)ty, &Wp, &Wm);
+        double PX[2][4], PY[2][4];
+        pn_probs(&ax, PX);
+        pn_probs(&ay, PY);
+        float A = ax.Pp * ay.Pp, B = ax.Pm * ay.Pm, Cn = ax.Pp * ay.Pm, Dn = ax.Pm * ay.Pp;
+        double pblk = frac_lt(A + B, A), nblk = (Cn + Dn) > 0.0f ? frac_lt(Cn + Dn, Cn) : 0.0;
         double acc[4] = {0, 0, 0, 0};
         for (int b = 0; b < 4; ++b)
             for (int a = 0; a < 4; ++a) {
