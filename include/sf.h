@@ -75,7 +75,20 @@ enum {
  * one tap drawn from the positive and one from the negative product
  * weights, estimate W+ f(t+) - W- f(t-).  SF_KEYS3 is a 2-D texture filter. */
 enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3, SF_GAUSS_FRS = 4, SF_GAUSS_FIS = 5,
-       SF_BSPLINE3_FIS = 6, SF_EWA = 7 };
+       SF_BSPLINE3_FIS = 6, SF_EWA = 7, SF_MITCHELL = 8 };
+/* SF_MITCHELL: the Mitchell-Netravali cubic, B = C = 1/3 (Mitchell and
+ * Netravali 1988; the other reading of the paper's "Mitchell" filter of
+ * Sec. 5 and the bicubic listing of Suppl. S.4), on taps i0-1..i0+2, a 2-D
+ * texture filter.  Its outer lobe changes sign at |x| = 8/7, so the
+ * stochastic mode positivises by per-tap sign (as the listing's two
+ * reservoirs do): binary32 weights, s = 1-t,
+ *   w0 = ((s s) fma(-7, t, 1)) fl(1/18),  w1 = fma(t t, fma(fl(7/6), t, -2), fl(8/9)),
+ *   w2 likewise in s,                     w3 = ((t t) fma(7, t, -6)) fl(1/18);
+ * per axis the positive set holds the taps with w > 0 and the negative set
+ * those with w < 0, P+ / P- their |w| summed in tap order; inside a set the
+ * tap is the first whose running sum c satisfies u P < c (else its last);
+ * blocks, keys and the estimate (A + B) f(t+) - (Cn + Dn) f(t-) as SF_KEYS3;
+ * dbg_taps n x spp x {level, x+, y+, x-, y-}. */
 /* SF_EWA: the elliptically weighted average over the pixel footprint, and
  * its stochastic form (one texel per sample by weighted reservoir sampling);
  * sf_filter2d_aniso only (it needs the screen derivatives). */
@@ -132,7 +145,7 @@ enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1, SF_SHADE_PLANCK = 2 }; 
  * error about (x + 3) * 2^-24, x = h c / (lambda k T). */
 
 typedef struct sf_sampling {
-    int32_t filter;      /* SF_NEAREST .. SF_EWA (see above)                         */
+    int32_t filter;      /* SF_NEAREST .. SF_MITCHELL (see above)                    */
     int32_t mode;        /* SF_BEFORE | SF_AFTER_EXACT | SF_STOCHASTIC | SF_SPLIT     */
     int32_t spp;         /* samples per query, 1..SF_MAX_SPP (deterministic: ignored) */
     uint32_t seed;       /* fourth word of the hash key                              */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libsf.so")
 
 # enums (values fixed by include/sf.h)
 SF_OK, SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED, SF_E_DEVICE, SF_E_WORKSPACE = range(6)
-SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3, SF_GAUSS_FRS, SF_GAUSS_FIS, SF_BSPLINE3_FIS, SF_EWA = range(8)
+SF_NEAREST, SF_LINEAR, SF_BSPLINE3, SF_KEYS3, SF_GAUSS_FRS, SF_GAUSS_FIS, SF_BSPLINE3_FIS, SF_EWA, SF_MITCHELL = range(9)
 SF_MAX_ANISO, SF_EWA_MAX_ANISO, SF_EWA_MAX_ASPECT = 64, 16, 8
 SF_SIGMA_MIN, SF_SIGMA_MAX = 0.0625, 4.0
 SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC, SF_SPLIT = 0, 1, 2, 3
@@ -309,7 +309,7 @@ def sf_filter2d(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, shade: 
         out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
     _need(out, torch.float32, "out", n * ch)
     if dbg_taps is not None:
-        tw = 5 if (smp.filter == SF_KEYS3 and smp.mode == SF_STOCHASTIC) else 3
+        tw = 5 if (smp.filter in (SF_KEYS3, SF_MITCHELL) and smp.mode == SF_STOCHASTIC) else 3
         _need(dbg_taps, torch.int32, "dbg_taps", n * smp.spp * tw)
     g = C.byref(ggx_params) if ggx_params is not None else None
     _check(lib().sf_filter2d(C.byref(tex.desc), _ptr(queries), n, C.byref(smp), shade, g, _ptr(out),

@@ -35,7 +35,7 @@ sf_status check_sampling(const sf_sampling *smp, bool allow_split = false)
 {
     if (!smp)
         return fail(SF_E_NULL, "sampling descriptor is NULL");
-    if (smp->filter < SF_NEAREST || smp->filter > SF_EWA)
+    if (smp->filter < SF_NEAREST || smp->filter > SF_MITCHELL)
         return fail(SF_E_RANGE, "filter %d out of range", smp->filter);
     if (smp->mode < SF_BEFORE || smp->mode > SF_SPLIT)
         return fail(SF_E_RANGE, "mode %d out of range", smp->mode);
@@ -219,10 +219,12 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
         return st;
     if (smp->filter == SF_EWA)
         return fail(SF_E_UNSUPPORTED, "EWA needs the screen derivatives: use sf_filter2d_aniso");
-    if (smp->mode == SF_SPLIT && (smp->filter > SF_KEYS3 || smp->rng_variant != 0))
-        return fail(SF_E_UNSUPPORTED, "split filtering takes NEAREST, LINEAR, BSPLINE3 or KEYS3 with rng_variant 0");
+    if (smp->mode == SF_SPLIT && ((smp->filter > SF_KEYS3 && smp->filter != SF_MITCHELL) || smp->rng_variant != 0))
+        return fail(SF_E_UNSUPPORTED,
+                    "split filtering takes NEAREST, LINEAR, BSPLINE3, KEYS3 or MITCHELL with rng_variant 0");
     if (smp->filter >= SF_KEYS3 && smp->rng_variant != 0)
-        return fail(SF_E_UNSUPPORTED, "the Keys, Gaussian and FIS filters draw independent uniforms (rng_variant 0)");
+        return fail(SF_E_UNSUPPORTED,
+                    "the Keys, Mitchell, Gaussian and FIS filters draw independent uniforms (rng_variant 0)");
     if ((smp->filter == SF_GAUSS_FRS || smp->filter == SF_GAUSS_FIS) &&
         !(smp->sigma >= SF_SIGMA_MIN && smp->sigma <= SF_SIGMA_MAX))
         return fail(SF_E_RANGE, "sigma %g outside %g..%g", (double)smp->sigma, (double)SF_SIGMA_MIN,
@@ -270,8 +272,8 @@ sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n
         return st;
     const int f = smp->filter;
     if (smp->mode == SF_SPLIT) {
-        if (f > SF_KEYS3)
-            return fail(SF_E_UNSUPPORTED, "split filtering takes NEAREST, LINEAR, BSPLINE3 or KEYS3");
+        if (f > SF_KEYS3 && f != SF_MITCHELL)
+            return fail(SF_E_UNSUPPORTED, "split filtering takes NEAREST, LINEAR, BSPLINE3, KEYS3 or MITCHELL");
     } else if (f != SF_NEAREST && f != SF_LINEAR && f != SF_BSPLINE3 && f != SF_GAUSS_FIS && f != SF_EWA) {
         return fail(SF_E_UNSUPPORTED, "anisotropic filtering takes NEAREST, LINEAR, BSPLINE3, GAUSS_FIS or EWA");
     }

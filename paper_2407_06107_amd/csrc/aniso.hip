@@ -537,7 +537,7 @@ static void launch_ewa(const AnisoCall &c, hipStream_t s)
 template <int F, int SHADE>
 static void launch_a2(const AnisoCall &c, hipStream_t s)
 {
-    if constexpr (F <= KEYS3) {
+    if constexpr (F <= KEYS3 || F == MITCHELL) {
         if (c.mode == SPLIT) {
             const int G = lane_group(c.n, c.spp);
             const int64_t threads = c.n * G;
@@ -545,8 +545,8 @@ static void launch_a2(const AnisoCall &c, hipStream_t s)
             return;
         }
     }
-    if constexpr (F == KEYS3)
-        return;   // the Keys cubic takes the split mode only here
+    if constexpr (F == KEYS3 || F == MITCHELL)
+        return;   // the positivised cubics take the split mode only here
     else if (c.mode == STOCH) {
         const int G = lane_group(c.n, c.spp);
         const int64_t threads = c.n * G;
@@ -583,6 +583,9 @@ hipError_t launch_aniso(const AnisoCall &c, hipStream_t s)
         break;
     case KEYS3:
         launch_a1<KEYS3>(c, s);
+        break;
+    case MITCHELL:
+        launch_a1<MITCHELL>(c, s);
         break;
     case EWA:
         if (c.shade == SF_SHADE_GGX)

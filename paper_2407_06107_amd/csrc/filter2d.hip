@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
             float nan = __builtin_nanf("");
             acc = make_float4(nan, nan, nan, nan);
             if (c.taps) {
-                constexpr int TW = F == KEYS3 ? 5 : 3;
+                constexpr int TW = (F == KEYS3 || F == MITCHELL) ? 5 : 3;
                 for (int s = lane; s < c.spp; s += G)
                     for (int k = 0; k < TW; ++k)
                         c.taps[(q * c.spp + s) * TW + k] = SF_TAP_NONE;
@@ -49,28 +49,41 @@ __global__ __launch_bounds__(256) void k_filter2d_stoch(Filter2DCall c, int log_
                 float tx, ty;
                 raster(uu, wl, ix, tx);
                 raster(vv, hl, iy, ty);
-                if constexpr (F == KEYS3) {
+                if constexpr (F == KEYS3 || F == MITCHELL) {
                     // positivisation (Sec. 2.2): one tap from the positive and
                     // one from the negative product weights, W+ f(t+) - W- f(t-)
                     const uint4 w2 = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 1u, c.seed));
-                    const KeysAxis kx = keys_axis(tx), ky = keys_axis(ty);
-                    const float A = kx.Pp * ky.Pp, B = kx.Pm * ky.Pm, Cn = kx.Pp * ky.Pm, Dn = kx.Pm * ky.Pp;
                     int ox, oy, nx, ny;
-                    if (u24(w.z) * (A + B) < A) {
-                        ox = u24(w.x) * kx.Pp < kx.p1 ? 0 : 1;
-                        oy = u24(w.y) * ky.Pp < ky.p1 ? 0 : 1;
+                    float A, B, Cn, Dn;
+                    if constexpr (F == KEYS3) {
+                        const KeysAxis kx = keys_axis(tx), ky = keys_axis(ty);
+                        A = kx.Pp * ky.Pp, B = kx.Pm * ky.Pm, Cn = kx.Pp * ky.Pm, Dn = kx.Pm * ky.Pp;
+                        if (u24(w.z) * (A + B) < A) {
+                            ox = u24(w.x) * kx.Pp < kx.p1 ? 0 : 1;
+                            oy = u24(w.y) * ky.Pp < ky.p1 ? 0 : 1;
+                        } else {
+                            ox = u24(w.x) * kx.Pm < kx.m0 ? -1 : 2;
+                            oy = u24(w.y) * ky.Pm < ky.m0 ? -1 : 2;
+                        }
+                        if (u24(w2.z) * (Cn + Dn) < Cn) {
+                            nx = u24(w2.x) * kx.Pp < kx.p1 ? 0 : 1;
+                            ny = u24(w2.y) * ky.Pm < ky.m0 ? -1 : 2;
+                        } else {
+                            nx = u24(w2.x) * kx.Pm < kx.m0 ? -1 : 2;
+                            ny = u24(w2.y) * ky.Pp < ky.p1 ? 0 : 1;
+                        }
                     } else {
-                        ox = u24(w.x) * kx.Pm < kx.m0 ? -1 : 2;
-                        oy = u24(w.y) * ky.Pm < ky.m0 ? -1 : 2;
+                        // Mitchell-Netravali: the sets follow the taps' signs
+                        const PnAxis ax = mitchell_axis(tx), ay = mitchell_axis(ty);
+                        A = ax.Pp * ay.Pp, B = ax.Pm * ay.Pm, Cn = ax.Pp * ay.Pm, Dn = ax.Pm * ay.Pp;
+                        const bool pp = u24(w.z) * (A + B) < A;
+                        ox = pn_pick(ax, pp, u24(w.x)) - 1;
+                        oy = pn_pick(ay, pp, u24(w.y)) - 1;
+                        const bool xpos = u24(w2.z) * (Cn + Dn) < Cn;
+                        nx = pn_pick(ax, xpos, u24(w2.x)) - 1;
+                        ny = pn_pick(ay, !xpos, u24(w2.y)) - 1;
                     }
                     const bool has_neg = (Cn + Dn) > 0.0f;
-                    if (u24(w2.z) * (Cn + Dn) < Cn) {
-                        nx = u24(w2.x) * kx.Pp < kx.p1 ? 0 : 1;
-                        ny = u24(w2.y) * ky.Pm < ky.m0 ? -1 : 2;
-                    } else {
-                        nx = u24(w2.x) * kx.Pm < kx.m0 ? -1 : 2;
-                        ny = u24(w2.y) * ky.Pp < ky.p1 ? 0 : 1;
-                    }
                     const int xp = wrap_tap(c.tex.wrap, ix + ox, wl), yp = wrap_tap(c.tex.wrap, iy + oy, hl);
                     const int xn = wrap_tap(c.tex.wrap, ix + nx, wl), yn = wrap_tap(c.tex.wrap, iy + ny, hl);
                     if (c.taps) {
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(256) void k_filter2d_gauss_det(Filter2DCall c)
 template <int F, int SHADE>
 static void launch_f2(const Filter2DCall &c, hipStream_t s)
 {
-    if constexpr (F <= KEYS3) {
+    if constexpr (F <= KEYS3 || F == MITCHELL) {
         if (c.mode == SPLIT) {
             const int G = lane_group(c.n, c.spp);
             const int64_t threads = c.n * G;
@@ -389,6 +402,9 @@ hipError_t launch_filter2d(const Filter2DCall &c, hipStream_t s)
         break;
     case KEYS3:
         launch_f1<KEYS3>(c, s);
+        break;
+    case MITCHELL:
+        launch_f1<MITCHELL>(c, s);
         break;
     case GAUSS_FRS:
         launch_f1<GAUSS_FRS>(c, s);

@@ -14,7 +14,8 @@
 
 namespace sfk {
 
-enum { NEAREST = 0, LINEAR = 1, BSPLINE3 = 2, KEYS3 = 3, GAUSS_FRS = 4, GAUSS_FIS = 5, BSPLINE3_FIS = 6, EWA = 7 };
+enum { NEAREST = 0, LINEAR = 1, BSPLINE3 = 2, KEYS3 = 3, GAUSS_FRS = 4, GAUSS_FIS = 5, BSPLINE3_FIS = 6, EWA = 7,
+       MITCHELL = 8 };
 enum { BEFORE = 0, AFTER = 1, STOCH = 2, SPLIT = 3 };
 
 // ---------------------------------------------------------------- random stream
@@ -339,6 +340,54 @@ __device__ __forceinline__ KeysAxis keys_axis(float t)
     return k;
 }
 
+// Mitchell-Netravali cubic (B = C = 1/3) on taps i0-1..i0+2, factored
+// binary32 weights, s = 1-t: w0 = ((s s) fma(-7, t, 1))/18 (positive for
+// t < 1/7), w1 = fma(t t, fma(7/6, t, -2), 8/9), w2 likewise in s,
+// w3 = ((t t) fma(7, t, -6))/18 (positive for t > 6/7).  Positivisation
+// sorts each tap into the positive or negative set by the sign of its
+// binary32 weight; P+ and P- sum |w| in tap order.
+struct PnAxis {
+    float w[4], Pp, Pm;
+};
+__device__ __forceinline__ PnAxis mitchell_axis(float t)
+{
+    const float K18 = 1.0f / 18.0f, K76 = 7.0f / 6.0f, K89 = 8.0f / 9.0f;
+    PnAxis a;
+    const float s = 1.0f - t;
+    a.w[0] = ((s * s) * __builtin_fmaf(-7.0f, t, 1.0f)) * K18;
+    a.w[1] = __builtin_fmaf(t * t, __builtin_fmaf(K76, t, -2.0f), K89);
+    a.w[2] = __builtin_fmaf(s * s, __builtin_fmaf(K76, s, -2.0f), K89);
+    a.w[3] = ((t * t) * __builtin_fmaf(7.0f, t, -6.0f)) * K18;
+    a.Pp = 0.0f;
+    a.Pm = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a.Pp = a.w[k] > 0.0f ? a.Pp + a.w[k] : a.Pp;
+        a.Pm = a.w[k] < 0.0f ? a.Pm + (-a.w[k]) : a.Pm;
+    }
+    return a;
+}
+
+// Tap (0..3) of the positive (pos) or negative set: the first whose running
+// sum c of |w| (tap order) satisfies u P < c, else the set's last tap.
+__device__ __forceinline__ int pn_pick(const PnAxis &a, bool pos, float u)
+{
+    const float uP = u * (pos ? a.Pp : a.Pm);
+    float c = 0.0f;
+    int pick = -1;
+    bool done = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float m = pos ? a.w[k] : -a.w[k];
+        if (m > 0.0f && !done) {
+            c = c + m;
+            pick = k;
+            done = uP < c;
+        }
+    }
+    return pick;
+}
+
 // Weights of the taps (value path, binary32), same tap order as pick_off.
 template <int F>
 __device__ __forceinline__ void axis_weights(float t, float w[4])
@@ -360,6 +409,12 @@ __device__ __forceinline__ void axis_weights(float t, float w[4])
         w[1] = k.p1;
         w[2] = k.p2;
         w[3] = -k.m3;
+    } else if constexpr (F == MITCHELL) {
+        const PnAxis a = mitchell_axis(t);
+        w[0] = a.w[0];
+        w[1] = a.w[1];
+        w[2] = a.w[2];
+        w[3] = a.w[3];
     } else {
         w[0] = 1.0f;
     }
@@ -387,8 +442,8 @@ __device__ __forceinline__ void axis_weights64(float tf, double w[4])
 
 template <int F>
 struct Taps {
-    static constexpr int n = (F == BSPLINE3 || F == KEYS3 || F == GAUSS_FRS) ? 4 : (F == LINEAR ? 2 : 1);
-    static constexpr int first = (F == BSPLINE3 || F == KEYS3 || F == GAUSS_FRS) ? -1 : 0;
+    static constexpr int n = (F == BSPLINE3 || F == KEYS3 || F == GAUSS_FRS || F == MITCHELL) ? 4 : (F == LINEAR ? 2 : 1);
+    static constexpr int first = (F == BSPLINE3 || F == KEYS3 || F == GAUSS_FRS || F == MITCHELL) ? -1 : 0;
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip; map the

@@ -103,7 +103,7 @@ def test_raymarch_validation(sf, case, status, entry):
     elif case == "steps_big":
         steps = 70000
     elif case == "bad_filter":
-        smp.filter = 8
+        smp.filter = 9
     elif case == "bad_mode":
         smp.mode = 4
     elif case == "spp_zero":
@@ -144,7 +144,7 @@ def test_raymarch_validation(sf, case, status, entry):
     ("ok_zero", 0), ("null_tex", 1), ("null_base", 1), ("bad_format", 3), ("levels_zero", 2),
     ("levels_too_many", 2), ("bad_wrap", 2), ("bad_mip", 2), ("ggx_missing", 1), ("bad_shade", 2),
     ("ggx_backfacing", 2), ("misaligned_level", 2), ("width_zero", 2), ("keys_ok_zero", 0),
-    ("keys_reuse", 3), ("filter_8", 2), ("ewa", 3), ("split_gauss", 3), ("split_reuse", 3), ("mode_4", 2), ("gauss_sigma_small", 2), ("gauss_sigma_nan", 2), ("fis_sigma_big", 2),
+    ("keys_reuse", 3), ("filter_9", 2), ("mitchell_reuse", 3), ("ewa", 3), ("split_gauss", 3), ("split_reuse", 3), ("mode_4", 2), ("gauss_sigma_small", 2), ("gauss_sigma_nan", 2), ("fis_sigma_big", 2),
     ("gauss_reuse", 3), ("fis_bspline_reuse", 3), ("fis_bspline_any_sigma_zero", 0),
 ])
 def test_filter2d_validation(sf, case, status):
@@ -188,10 +188,12 @@ def test_filter2d_validation(sf, case, status):
         n = 0
     elif case == "keys_reuse":
         smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 4, rng_variant=1)
-    elif case == "filter_8":
-        smp = sf.sampling(8, sf.SF_STOCHASTIC, 4)
+    elif case == "filter_9":
+        smp = sf.sampling(9, sf.SF_STOCHASTIC, 4)
     elif case == "ewa":
         smp = sf.sampling(sf.SF_EWA, sf.SF_STOCHASTIC, 4)
+    elif case == "mitchell_reuse":
+        smp = sf.sampling(sf.SF_MITCHELL, sf.SF_STOCHASTIC, 4, rng_variant=1)
     elif case == "split_gauss":
         smp = sf.sampling(sf.SF_GAUSS_FRS, sf.SF_SPLIT, 4)
     elif case == "split_reuse":

@@ -325,19 +325,20 @@ def _close_signed(gpu, ref, scale):
     _close(gpu, ref, atol=RTOL * 1.6 * scale)
 
 
+@pytest.mark.parametrize("filt", ["KEYS3", "MITCHELL"])
 @pytest.mark.parametrize("mode, spp", [("STOCH", 16), ("STOCH", 5), ("STOCH", 1), ("BEFORE", 1), ("AFTER", 1)])
 @pytest.mark.parametrize("shade", [0, 1])
 @pytest.mark.parametrize("wrap", [0, 1])
-def test_filter2d_keys_config1(sf, orc, c1, mode, spp, shade, wrap):
-    _print_case("filter2d_keys_c1", mode, spp, shade, wrap)
+def test_filter2d_keys_config1(sf, orc, c1, filt, mode, spp, shade, wrap):
+    _print_case("filter2d_keys_c1", filt, mode, spp, shade, wrap)
     tex, q = c1
     ot = orc.Tex2D.rgba32f(tex, wrap=wrap)
     gt = sf.Texture2D([tex], wrap=wrap)
     m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
-    smp = sf.sampling(sf.SF_KEYS3, m, spp, seed=77)
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=77)
     taps_d = torch.full((q.shape[0], spp, 5), 99, dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
     out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=shade, ggx_params=sf.ggx(), dbg_taps=taps_d)
-    res = orc.filter2d(ot, q, orc.KEYS3, m, spp=spp, seed=77, shade=shade, taps=m == orc.STOCHASTIC)
+    res = orc.filter2d(ot, q, getattr(orc, filt), m, spp=spp, seed=77, shade=shade, taps=m == orc.STOCHASTIC)
     if m == orc.STOCHASTIC:
         ref, taps = res
         assert np.array_equal(taps_d.cpu().numpy(), taps)
@@ -346,19 +347,20 @@ def test_filter2d_keys_config1(sf, orc, c1, mode, spp, shade, wrap):
     _close_signed(out.cpu().numpy(), ref, np.nanmax(np.abs(ref)))
 
 
+@pytest.mark.parametrize("filt", ["KEYS3", "MITCHELL"])
 @pytest.mark.parametrize("mip", [0, 2])
-@pytest.mark.parametrize("mode, spp", [("STOCH", 8), ("AFTER", 1)])
-def test_filter2d_keys_mips_rgba8(sf, orc, c2_small, mip, mode, spp):
-    _print_case("filter2d_keys_mips", mip, mode, spp)
+@pytest.mark.parametrize("mode, spp", [("STOCH", 8), ("AFTER", 1), ("BEFORE", 1)])
+def test_filter2d_keys_mips_rgba8(sf, orc, c2_small, filt, mip, mode, spp):
+    _print_case("filter2d_keys_mips", filt, mip, mode, spp)
     lv, q = c2_small
     buf, offs = inputs.pack_levels(lv)
     ot = orc.Tex2D(buf, lv[0].shape[1], lv[0].shape[0], len(lv), orc.RGBA8, offs, orc.REPEAT, mip)
     gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=mip)
-    m = {"STOCH": orc.STOCHASTIC, "AFTER": orc.AFTER}[mode]
-    smp = sf.sampling(sf.SF_KEYS3, m, spp, seed=6)
+    m = {"STOCH": orc.STOCHASTIC, "AFTER": orc.AFTER, "BEFORE": orc.BEFORE}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, spp, seed=6)
     taps_d = torch.empty((q.shape[0], spp, 5), dtype=torch.int32, device="cuda") if m == orc.STOCHASTIC else None
     out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx(), dbg_taps=taps_d)
-    res = orc.filter2d(ot, q, orc.KEYS3, m, spp=spp, seed=6, shade=1, taps=m == orc.STOCHASTIC)
+    res = orc.filter2d(ot, q, getattr(orc, filt), m, spp=spp, seed=6, shade=1, taps=m == orc.STOCHASTIC)
     if m == orc.STOCHASTIC:
         ref, taps = res
         assert np.array_equal(taps_d.cpu().numpy(), taps)
@@ -385,16 +387,17 @@ def test_filter2d_keys_texel_centres_exact(sf, orc):
     assert np.array_equal(out, tex.reshape(-1, 4))
 
 
-def test_filter2d_keys_config2_full_sampled(sf, orc, c2_full):
-    _print_case("filter2d_keys_c2_full")
+@pytest.mark.parametrize("filt", ["KEYS3", "MITCHELL"])
+def test_filter2d_keys_config2_full_sampled(sf, orc, c2_full, filt):
+    _print_case("filter2d_keys_c2_full", filt)
     lv, q = c2_full
     buf, offs = inputs.pack_levels(lv)
     ot = orc.Tex2D(buf, 4096, 4096, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
     gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
-    smp = sf.sampling(sf.SF_KEYS3, sf.SF_STOCHASTIC, 16, seed=32)
+    smp = sf.sampling(getattr(sf, "SF_" + filt), sf.SF_STOCHASTIC, 16, seed=32)
     out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx()).cpu().numpy()
     sub = np.sort(np.random.default_rng(2).choice(q.shape[0], 3000, replace=False))
-    ref = orc.filter2d(ot, q, orc.KEYS3, orc.STOCHASTIC, spp=16, seed=32, shade=1, subset=sub)
+    ref = orc.filter2d(ot, q, getattr(orc, filt), orc.STOCHASTIC, spp=16, seed=32, shade=1, subset=sub)
     _close_signed(out[sub], ref, np.nanmax(np.abs(ref)))
 
 
@@ -469,7 +472,7 @@ def test_filter2d_gauss_fis_config2_full_sampled(sf, orc, c2_full, filt, sigma):
 
 
 # ------------------------------------------------------------------ split filtering
-@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3", "KEYS3"])
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3", "KEYS3", "MITCHELL"])
 @pytest.mark.parametrize("mip", [0, 1, 2])
 @pytest.mark.parametrize("spp", [1, 8])
 @pytest.mark.parametrize("shade", [0, 1])
@@ -487,7 +490,7 @@ def test_filter2d_split(sf, orc, c2_small, filt, mip, spp, shade):
     out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=shade, ggx_params=sf.ggx(), dbg_taps=taps_d)
     ref, taps = orc.filter2d(ot, q, f, orc.SPLIT, spp=spp, seed=8, shade=shade, taps=True)
     assert np.array_equal(taps_d.cpu().numpy(), taps)
-    if filt == "KEYS3":
+    if filt in ("KEYS3", "MITCHELL"):
         _close_signed(out.cpu().numpy(), ref, np.nanmax(np.abs(ref)))
     else:
         _close(out.cpu().numpy(), ref)
@@ -546,7 +549,7 @@ def test_filter2d_aniso_parity(sf, orc, aniso_small, filt, sigma, mode, spp, ama
     _close(out.cpu().numpy(), ref)
 
 
-@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3", "KEYS3"])
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3", "KEYS3", "MITCHELL"])
 @pytest.mark.parametrize("spp", [1, 8])
 @pytest.mark.parametrize("amax", [64, 4])
 @pytest.mark.parametrize("shade", [0, 1])
@@ -565,7 +568,7 @@ def test_filter2d_aniso_split(sf, orc, aniso_small, filt, spp, amax, shade):
                                ggx_params=sf.ggx(), dbg_taps=taps_d)
     ref, taps = orc.filter2d_aniso(ot, q, f, orc.SPLIT, spp=spp, seed=12, shade=shade, taps=True, amax=amax)
     assert np.array_equal(taps_d.cpu().numpy(), taps)
-    if filt == "KEYS3":
+    if filt in ("KEYS3", "MITCHELL"):
         _close_signed(out.cpu().numpy(), ref, np.nanmax(np.abs(ref)))
     else:
         _close(out.cpu().numpy(), ref)
