@@ -426,6 +426,16 @@ def texture_bench(args, res):
         t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
         c1[name] = {"ms": t, "queries_per_s": 4096 / (t * 1e-3),
                     "rmse_vs_oracle_keys_after": _rmse(o.cpu().numpy(), judge1k)}
+    # Mitchell-Netravali cubic (B = C = 1/3): positivised by per-tap sign vs all 16 taps
+    judge1m = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.MITCHELL, oracle.AFTER, shade=1)
+    for name, mode, spp in (("mitchell_positivised_stochastic_16spp", sf.SF_STOCHASTIC, 16),
+                            ("mitchell_positivised_stochastic_1spp", sf.SF_STOCHASTIC, 1),
+                            ("mitchell_after_16tap", sf.SF_AFTER_EXACT, 1)):
+        smp = sf.sampling(sf.SF_MITCHELL, mode, spp, seed=5)
+        o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
+        t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
+        c1[name] = {"ms": t, "queries_per_s": 4096 / (t * 1e-3),
+                    "rmse_vs_oracle_mitchell_after": _rmse(o.cpu().numpy(), judge1m)}
     # Gaussian by FRS (4x4 window) and by FIS (Box-Muller + nearest), and the
     # cubic B-spline by FIS (sum of three uniforms): RMSE against each
     # filter's own exact filter-after value, 16 samples per query
@@ -456,6 +466,7 @@ def texture_bench(args, res):
     sub = np.sort(rng.choice(n2, 20000, replace=False))
     judge2 = oracle.filter2d(otex, q2, oracle.BSPLINE3, oracle.AFTER, shade=1, subset=sub)
     judge2k = oracle.filter2d(otex, q2, oracle.KEYS3, oracle.AFTER, shade=1, subset=sub)
+    judge2m = oracle.filter2d(otex, q2, oracle.MITCHELL, oracle.AFTER, shade=1, subset=sub)
     c2 = {"queries": n2, "texture_bytes": int(buf.size)}
     for name, tex, filt, mode, spp in (
             ("bicubic_stochastic_1spp", tex2, sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1),
@@ -467,6 +478,9 @@ def texture_bench(args, res):
             ("bilinear_nearest_level_before_4tap", tex2n, sf.SF_LINEAR, sf.SF_BEFORE, 1),
             ("keys_positivised_stochastic_1spp", tex2, sf.SF_KEYS3, sf.SF_STOCHASTIC, 1),
             ("keys_after_2x16tap", tex2, sf.SF_KEYS3, sf.SF_AFTER_EXACT, 1),
+            ("mitchell_positivised_stochastic_1spp", tex2, sf.SF_MITCHELL, sf.SF_STOCHASTIC, 1),
+            ("mitchell_after_2x16tap", tex2, sf.SF_MITCHELL, sf.SF_AFTER_EXACT, 1),
+            ("bicubic_split_1spp", tex2, sf.SF_BSPLINE3, sf.SF_SPLIT, 1),
             ("bicubic_fis_stochastic_1spp", tex2, sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 1),
             ("bicubic_fis_stochastic_16spp", tex2, sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 16),
             ("gauss_frs_sigma0.5_stochastic_1spp", tex2, sf.SF_GAUSS_FRS, sf.SF_STOCHASTIC, 1),
@@ -474,15 +488,22 @@ def texture_bench(args, res):
         smp = sf.sampling(filt, mode, spp, seed=5, sigma=0.5)
         o = torch.empty((n2, 3), dtype=torch.float32, device="cuda")
         t = time_launches(lambda: sf.sf_filter2d(tex, qd2, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
-        cubic = filt in (sf.SF_BSPLINE3, sf.SF_KEYS3, sf.SF_GAUSS_FRS, sf.SF_BSPLINE3_FIS)
-        taps = (spp * (2 if filt == sf.SF_KEYS3 else 1) if mode == sf.SF_STOCHASTIC
-                else (2 if tex is tex2 else 1) * (16 if cubic else 4))
+        cubic = filt in (sf.SF_BSPLINE3, sf.SF_KEYS3, sf.SF_GAUSS_FRS, sf.SF_BSPLINE3_FIS, sf.SF_MITCHELL)
+        positivised = filt in (sf.SF_KEYS3, sf.SF_MITCHELL)
+        if mode == sf.SF_STOCHASTIC:
+            taps = spp * (2 if positivised else 1)
+        elif mode == sf.SF_SPLIT:
+            taps = spp * (16 if cubic else 4)
+        else:
+            taps = (2 if tex is tex2 else 1) * (16 if cubic else 4)
         algo = n2 * (taps * 4 + 12 + 12)
         c2[name] = {"ms": t, "queries_per_s": n2 / (t * 1e-3), "texel_reads_per_query": taps,
                     "algorithmic_gbs": algo / (t * 1e-3) / 1e9,
                     "rmse_vs_oracle_bicubic_trilinear_after": _rmse(o.cpu().numpy()[sub], judge2)}
         if filt == sf.SF_KEYS3:
             c2[name]["rmse_vs_oracle_keys_trilinear_after"] = _rmse(o.cpu().numpy()[sub], judge2k)
+        if filt == sf.SF_MITCHELL:
+            c2[name]["rmse_vs_oracle_mitchell_trilinear_after"] = _rmse(o.cpu().numpy()[sub], judge2m)
     t0 = time.perf_counter()
     oracle.filter2d(otex, q2, oracle.BSPLINE3, oracle.STOCHASTIC, spp=16, seed=5, shade=1, subset=sub)
     dt = time.perf_counter() - t0
