@@ -29,6 +29,7 @@ REPEAT, CLAMP = 0, 1
 MIP_NONE, MIP_NEAREST, MIP_LINEAR = 0, 1, 2
 TAP_NONE = np.iinfo(np.int32).min
 DENSITY, TRANSMITTANCE, PLANCK = 0, 1, 2     # 3-D shading
+SHADE_NONE, SHADE_GGX, SHADE_GGX_NORMAL = 0, 1, 2   # 2-D shading
 PLANCK_NM = (700.0, 546.1, 435.8)           # wavelengths of an emission result
 
 
@@ -125,6 +126,7 @@ def lib():
         L.orc_k3.argtypes = [C.c_double]
         L.orc_keys_pick.argtypes = [f32, f32, P, P, P]
         L.orc_keys_expect2d.argtypes = [P, i32, i32, i32, i32, P, i64, i32, P, P]
+        L.orc_shade_ggx_normal.argtypes = [P, P, P]
         L.orc_kmn.restype = C.c_double
         L.orc_kmn.argtypes = [C.c_double]
         L.orc_mitchell_pick.argtypes = [f32, f32, P, P, P]
@@ -235,6 +237,16 @@ def shade_ggx(params: np.ndarray, rgba) -> np.ndarray:
     return out
 
 
+def shade_ggx_normal(params: np.ndarray, rgba) -> np.ndarray:
+    """GGX + Lambert of a grey material (albedo 1/2) with the tangent-space
+    normal encoded in rgb (2 rgb - 1, renormalised), roughness parameter a."""
+    params = _c(params, np.float64)
+    rgba = _c(rgba, np.float64)
+    out = np.zeros(3)
+    lib().orc_shade_ggx_normal(_p(params), _p(rgba), _p(out))
+    return out
+
+
 def reuse_histogram2(filt: int, tx: float, ty: float) -> np.ndarray:
     c = np.zeros(16, dtype=np.int64)
     lib().orc_reuse_histogram2(filt, float(tx), float(ty), _p(c))
@@ -302,7 +314,7 @@ def filter2d(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1, seed
     n = q.shape[0]
     sub = None if subset is None else _c(subset, np.int64)
     m = n if sub is None else sub.size
-    ch = 3 if shade == 1 else 4
+    ch = 3 if shade else 4
     out = np.zeros((m, ch))
     tp = np.zeros((m, spp, 5 if (filt in (KEYS3, MITCHELL) and mode == STOCHASTIC) else 3), dtype=np.int32) \
         if taps else None
@@ -318,7 +330,7 @@ def filter2d_expect(tex: Tex2D, q: np.ndarray, filt: int, shade: int = 0, ggx=No
     _check_sigma(filt, sigma)
     q = _c(q, np.float32).reshape(-1, 3)
     n = q.shape[0]
-    ch = 3 if shade == 1 else 4
+    ch = 3 if shade else 4
     out = np.zeros((n, ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     st = lib().orc_filter2d_expect(_p(tex.buf), tex.w, tex.h, tex.levels, tex.fmt, tex.wrap, tex.mip,
@@ -350,7 +362,7 @@ def filter2d_aniso(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1
     n = q.shape[0]
     sub = None if subset is None else _c(subset, np.int64)
     m = n if sub is None else sub.size
-    ch = 3 if shade == 1 else 4
+    ch = 3 if shade else 4
     out = np.zeros((m, ch))
     tp = np.zeros((m, spp, 3), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
@@ -406,7 +418,7 @@ def aniso_reference(tex: Tex2D, q: np.ndarray, K: int = 16, filt: int = BSPLINE3
     q = _c(q, np.float32).reshape(-1, 6)
     sub = None if subset is None else _c(subset, np.int64)
     m = q.shape[0] if sub is None else sub.size
-    ch = 3 if shade == 1 else 4
+    ch = 3 if shade else 4
     out = np.zeros((m, ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_aniso_reference(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(tex.dct_range), _p(q), q.shape[0],
@@ -434,7 +446,7 @@ def triplanar(tex: Tex2D, q: np.ndarray, scale: float, plane_mode: int, filt: in
     n = q.shape[0]
     sub = None if subset is None else _c(subset, np.int64)
     m = n if sub is None else sub.size
-    ch = 3 if shade == 1 else 4
+    ch = 3 if shade else 4
     out = np.zeros((m, ch))
     tp = np.zeros((m, spp, 4), dtype=np.int32) if taps else None
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
@@ -716,7 +728,7 @@ def keys_pick(tx: float, ty: float, u) -> tuple:
 
 def keys_expect2d(tex: Tex2D, q: np.ndarray, shade: int = 0, ggx=None):
     q = _c(q, np.float32).reshape(-1, 3)
-    ch = 3 if shade == 1 else 4
+    ch = 3 if shade else 4
     out = np.zeros((q.shape[0], ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_keys_expect2d(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(q), q.shape[0], shade, _p(g), _p(out))
@@ -748,7 +760,7 @@ def mitchell_pick(tx: float, ty: float, u) -> tuple:
 
 def mitchell_expect2d(tex: Tex2D, q: np.ndarray, shade: int = 0, ggx=None):
     q = _c(q, np.float32).reshape(-1, 3)
-    ch = 3 if shade == 1 else 4
+    ch = 3 if shade else 4
     out = np.zeros((q.shape[0], ch))
     g = _c(ggx if ggx is not None else ggx_params(), np.float64)
     lib().orc_mitchell_expect2d(_p(tex.buf), tex.w, tex.h, tex.fmt, tex.wrap, _p(q), q.shape[0], shade, _p(g),

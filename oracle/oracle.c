@@ -940,10 +940,58 @@ static void levels_of(const tex2d *t, float lam, int *l0, int *l1, float *f)
     *f = fr;
 }
 
+/* Normal-mapped GGX (Sec. 3 "Normal maps": filtering normals before shading
+ * changes appearance).  The texel's RGB encodes a tangent-space normal
+ * m = 2 rgb - 1, A the roughness parameter as for GGX; the shading normal
+ * is m/|m| (z if m = 0) in the frame (e1, e2, n) of the geometric normal n
+ * (branchless basis of Duff et al., JCGT 6(1), 2017); a grey material,
+ * albedo 1/2, is shaded with the GGX + Lambert model above, and a shading
+ * normal facing away from the viewer or the light gives 0. */
+ORC_EXPORT void orc_shade_ggx_normal(const double *p, const double rgba[4], double out[3])
+{
+    const double *n = p, *wo = p + 3, *wi = p + 6, *rad = p + 9;
+    double f0 = p[12], rb = p[13], rs = p[14];
+    double sg = n[2] >= 0.0 ? 1.0 : -1.0;
+    double a_ = -1.0 / (sg + n[2]), b_ = n[0] * n[1] * a_;
+    double e1[3] = {1.0 + sg * n[0] * n[0] * a_, sg * b_, -sg * n[0]};
+    double e2[3] = {b_, sg + n[1] * n[1] * a_, -n[1]};
+    double m[3] = {2.0 * rgba[0] - 1.0, 2.0 * rgba[1] - 1.0, 2.0 * rgba[2] - 1.0};
+    double ml = sqrt(dot3(m, m));
+    double ns[3];
+    if (ml > 0.0) {
+        for (int c = 0; c < 3; ++c)
+            ns[c] = (m[0] * e1[c] + m[1] * e2[c] + m[2] * n[c]) / ml;
+    } else {
+        ns[0] = n[0], ns[1] = n[1], ns[2] = n[2];
+    }
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    double hl = sqrt(dot3(h, h));
+    h[0] /= hl;
+    h[1] /= hl;
+    h[2] /= hl;
+    double nh = dot3(ns, h), no = dot3(ns, wo), ni = dot3(ns, wi), ih = dot3(wi, h);
+    if (!(no > 0.0) || !(ni > 0.0)) {
+        out[0] = out[1] = out[2] = 0.0;
+        return;
+    }
+    double r = rb + rs * rgba[3];
+    double a = r * r, a2 = a * a;
+    double dd = nh * nh * (a2 - 1.0) + 1.0;
+    double D = a2 / (PI * dd * dd);
+    double G1o = 2.0 * no / (no + sqrt(a2 + (1.0 - a2) * no * no));
+    double G1i = 2.0 * ni / (ni + sqrt(a2 + (1.0 - a2) * ni * ni));
+    double F = f0 + (1.0 - f0) * pow(1.0 - ih, 5.0);
+    double spec = D * G1o * G1i * F / (4.0 * no * ni);
+    for (int c = 0; c < 3; ++c)
+        out[c] = rad[c] * (0.5 / PI + spec) * ni;
+}
+
 static void shade2d(int shade, const double *ggx, const double rgba[4], double *out)
 {
     if (shade == 1)
         orc_shade_ggx(ggx, rgba, out);
+    else if (shade == 2)
+        orc_shade_ggx_normal(ggx, rgba, out);
     else
         for (int c = 0; c < 4; ++c)
             out[c] = rgba[c];
@@ -995,7 +1043,7 @@ static void filter2d_one(const tex2d *t, const float *q, int64_t qi, int filter,
                          uint32_t seed, int variant, float sigma, int shade, const double *ggx, double *out,
                          int32_t *taps)
 {
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     if (!query_finite(t, q)) {
         for (int c = 0; c < ch; ++c)
             out[c] = NAN;
@@ -1207,7 +1255,7 @@ ORC_EXPORT int orc_filter2d(const void *base, int w, int h, int levels, int fmt,
                             double *out, int32_t *taps, const int64_t *subset, int64_t nsub)
 {
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off, dct_range};
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i) {
@@ -1232,7 +1280,7 @@ ORC_EXPORT int orc_filter2d_expect(const void *base, int w, int h, int levels, i
     if (filter == F_KEYS3 || filter == F_MITCHELL || filter == F_GAUSS_FIS)
         return -1;
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off, dct_range};
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     for (int64_t i = 0; i < n; ++i) {
         const float *qq = q + 3 * i;
         double *o = out + ch * i;
@@ -1371,7 +1419,7 @@ static int aniso_query_finite(const float *q)
 static void det_point(const tex2d *t, float u, float v, float lam, int filter, float sigma, int mode, int shade,
                       const double *ggx, double weight, double *sum)
 {
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     float uu = wrap_coord(t->wrap, u), vv = wrap_coord(t->wrap, v);
     int l0, l1;
     float f;
@@ -1421,7 +1469,7 @@ static void det_point(const tex2d *t, float u, float v, float lam, int filter, f
 static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, int mode, int spp, uint32_t seed,
                       float sigma, int amax, int shade, const double *ggx, double *out, int32_t *taps)
 {
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     if (!aniso_query_finite(q)) {
         for (int c = 0; c < ch; ++c)
             out[c] = NAN;
@@ -1678,7 +1726,7 @@ static int ewa_pick(const ewa_level *v, float u, int *px, int *py)
 static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int spp, uint32_t seed, int amax,
                     int shade, const double *ggx, double *out, int32_t *taps)
 {
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     ewa_frame e = ewa_setup(q, tx->w, tx->h, amax);
     const float lmax = (float)(tx->levels - 1);
     if (e.lod > lmax) {
@@ -1845,7 +1893,7 @@ ORC_EXPORT int orc_filter2d_aniso(const void *base, int w, int h, int levels, in
                                   int32_t *taps, const int64_t *subset, int64_t nsub)
 {
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, MIP_LINEAR, level_off, dct_range};
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     int64_t m = subset ? nsub : n;
     if (filter == F_EWA)
         ewa_lut_init();
@@ -1873,7 +1921,7 @@ ORC_EXPORT int orc_aniso_reference(const void *base, int w, int h, int fmt, int 
 {
     const int64_t off0 = 0;
     tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0, dct_range};
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < m; ++i) {
@@ -1976,7 +2024,7 @@ ORC_EXPORT int orc_triplanar(const void *base, int w, int h, int levels, int fmt
                              const double *ggx, double *out, int32_t *taps, const int64_t *subset, int64_t nsub)
 {
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, mip, level_off, dct_range};
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     int64_t m = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i) {
@@ -2078,7 +2126,7 @@ ORC_EXPORT int orc_keys_expect2d(const void *base, int w, int h, int fmt, int wr
 {
     const int64_t off0 = 0;
     tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0};
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     for (int64_t i = 0; i < n; ++i) {
         float uu = wrap_coord(wrap, q[3 * i]), vv = wrap_coord(wrap, q[3 * i + 1]);
         int ix, iy;
@@ -2144,7 +2192,7 @@ ORC_EXPORT int orc_mitchell_expect2d(const void *base, int w, int h, int fmt, in
 {
     const int64_t off0 = 0;
     tex2d t = {(const uint8_t *)base, w, h, 1, fmt, wrap, MIP_NONE, &off0};
-    int ch = shade == 1 ? 3 : 4;
+    int ch = shade != 0 ? 3 : 4;
     for (int64_t i = 0; i < n; ++i) {
         float uu = wrap_coord(wrap, q[3 * i]), vv = wrap_coord(wrap, q[3 * i + 1]);
         int ix, iy;

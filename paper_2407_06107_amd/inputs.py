@@ -93,6 +93,32 @@ def texture_sinusoids(size: int = 4096, seed: int = 3, waves: int = 32) -> np.nd
     return np.clip(out, 0.0, 1.0)
 
 
+def texture_normal_map(size: int = 4096, seed: int = 13, waves: int = 24, slope: float = 1.0,
+                       roughness: float = 0.15) -> np.ndarray:
+    """Tileable normal map of a bumpy surface, float64 ``[size,size,4]``:
+    height h = sum_k a_k sin(2 pi f_k . x / size + phi_k) scaled so that the
+    largest analytic slope |grad h| (texel units) is about ``slope``; RGB =
+    (n + 1)/2 with n = normalize(-dh/dx, -dh/dy, 1) (tangent space), A =
+    ``roughness`` (the roughness parameter of the GGX shading)."""
+    rng = np.random.default_rng(seed)
+    fx, fy, amp, phase = _wave_set(rng, waves, size)
+    x = np.arange(size, dtype=np.float64)
+    w = 2.0 * math.pi / size
+    ax = w * np.outer(x, fx)                    # [size, waves] along x
+    by = w * np.outer(x, fy) + phase            # [size, waves] along y
+    # d/dx sin(ax + by) = w fx cos(ax + by); cos(ax + by) = cos(ax) cos(by) - sin(ax) sin(by)
+    cosxy = lambda A: (np.cos(by) * A) @ np.cos(ax).T - (np.sin(by) * A) @ np.sin(ax).T
+    gx = cosxy(amp * w * fx)
+    gy = cosxy(amp * w * fy)
+    scale = slope / np.sum(amp * w * np.hypot(fx, fy))
+    n = np.stack([-gx * scale, -gy * scale, np.ones_like(gx)], axis=-1)
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    out = np.empty((size, size, 4), dtype=np.float64)
+    out[..., :3] = 0.5 * (n + 1.0)
+    out[..., 3] = roughness
+    return out
+
+
 def mip_chain(level0: np.ndarray) -> list[np.ndarray]:
     """Full MIP pyramid by 2x2 box averaging in float64, down to 1x1.
 

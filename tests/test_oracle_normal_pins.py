@@ -1,0 +1,121 @@
+"""Pins of the oracle's normal-mapped GGX shading (Sec. 3 "Normal maps":
+filtering normals before shading changes a minified surface's appearance)
+against the plain GGX shading of the same grey material under rotated
+directions, and the filters' closed cases."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2407_06107_amd import inputs
+
+
+def _enc(m):
+    m = np.asarray(m, np.float64)
+    return (m + 1.0) / 2.0
+
+
+def _rot_to_z(m):
+    """Rotation matrix taking unit vector m to +z (Rodrigues)."""
+    z = np.array([0.0, 0.0, 1.0])
+    v = np.cross(m, z)
+    c = float(m @ z)
+    if np.linalg.norm(v) < 1e-15:
+        return np.eye(3) if c > 0 else np.diag([1.0, -1.0, -1.0])
+    K = np.array([[0, -v[2], v[1]], [v[2], 0, -v[0]], [-v[1], v[0], 0]])
+    return np.eye(3) + K + K @ K / (1.0 + c)
+
+
+def test_flat_map_is_plain_ggx_of_a_grey_material(orc):
+    g = orc.ggx_params()
+    for a in (0.0, 0.3, 1.0):
+        out = orc.shade_ggx_normal(g, [0.5, 0.5, 1.0, a])
+        ref = orc.shade_ggx(g, [0.5, 0.5, 0.5, a])
+        assert np.allclose(out, ref, rtol=1e-14, atol=0)
+
+
+def test_tilted_normal_equals_rotated_directions(orc):
+    """Shading with normal m and directions (wo, wi) equals the flat shading
+    with directions (R wo, R wi), R the rotation taking m to z."""
+    rng = np.random.default_rng(5)
+    base = orc.ggx_params()
+    wo, wi = base[3:6], base[6:9]
+    checked = 0
+    for _ in range(300):
+        m = rng.normal(size=3)
+        m[2] = abs(m[2]) + 0.3
+        m /= np.linalg.norm(m)
+        if m @ wo <= 0.05 or m @ wi <= 0.05:
+            continue
+        R = _rot_to_z(m)
+        g2 = orc.ggx_params(wo=R @ wo, wi=R @ wi)
+        a = rng.random()
+        out = orc.shade_ggx_normal(base, [*_enc(m), a])
+        ref = orc.shade_ggx(g2, [0.5, 0.5, 0.5, a])
+        assert np.allclose(out, ref, rtol=1e-11, atol=1e-14), (m, out, ref)
+        checked += 1
+    assert checked > 100
+
+
+def test_geometric_normal_frame(orc):
+    """A flat map on a tilted surface shades like plain GGX with that surface
+    normal.  (For the z normal the frame is the identity, which the rotation
+    test above pins; a tilted frame's tangent axes are pinned only through the
+    GPU comparison.)"""
+    n = np.array([0.3, -0.2, 0.9])
+    n /= np.linalg.norm(n)
+    g = orc.ggx_params(n=n)
+    for a in (0.1, 0.4, 0.9):
+        assert np.allclose(orc.shade_ggx_normal(g, [0.5, 0.5, 1.0, a]), orc.shade_ggx(g, [0.5, 0.5, 0.5, a]),
+                           rtol=1e-13)
+
+
+def test_backfacing_and_normalisation(orc):
+    g = orc.ggx_params()
+    wi = g[6:9]
+    m = -wi + np.array([0.0, 0.0, 0.05])
+    m /= np.linalg.norm(m)
+    assert np.all(orc.shade_ggx_normal(g, [*_enc(m), 0.3]) == 0.0)
+    m = np.array([0.2, -0.1, 0.97])
+    m /= np.linalg.norm(m)
+    a = orc.shade_ggx_normal(g, [*_enc(m), 0.3])
+    b = orc.shade_ggx_normal(g, [*_enc(0.5 * m), 0.3])     # a shortened (filtered) normal
+    assert np.allclose(a, b, rtol=1e-13)
+    assert np.allclose(orc.shade_ggx_normal(g, [0.5, 0.5, 0.5, 0.3]), orc.shade_ggx_normal(g, [0.5, 0.5, 1.0, 0.3]))
+
+
+def test_before_after_on_two_normals(orc):
+    """Two texels with mirrored normals: after shading averages the two
+    shaded values, before shading shades their (flat) average."""
+    m1 = np.array([0.6, 0.0, 0.8])
+    m2 = np.array([-0.6, 0.0, 0.8])
+    tex = np.zeros((1, 2, 4), np.float32)
+    tex[0, 0] = [*_enc(m1), 0.2]
+    tex[0, 1] = [*_enc(m2), 0.2]
+    t = orc.Tex2D.rgba32f(tex, wrap=orc.CLAMP)
+    q = np.array([[0.5, 0.5, 0.0]], np.float32)         # halfway: tent weights 1/2, 1/2
+    g = orc.ggx_params()
+    after = orc.filter2d(t, q, orc.LINEAR, orc.AFTER, shade=2)[0]
+    before = orc.filter2d(t, q, orc.LINEAR, orc.BEFORE, shade=2)[0]
+    s1 = orc.shade_ggx_normal(g, tex[0, 0].astype(np.float64))
+    s2 = orc.shade_ggx_normal(g, tex[0, 1].astype(np.float64))
+    assert np.allclose(after, 0.5 * (s1 + s2), rtol=1e-13)
+    avg = 0.5 * (tex[0, 0].astype(np.float64) + tex[0, 1].astype(np.float64))
+    assert np.allclose(before, orc.shade_ggx_normal(g, avg), rtol=1e-13)
+    assert np.allclose(before, orc.shade_ggx_normal(g, [0.5, 0.5, 1.0, 0.2]), rtol=1e-6)
+    assert not np.allclose(before, after, rtol=1e-2)
+    spp = 8192
+    S = orc.filter2d(t, q, orc.LINEAR, orc.STOCHASTIC, spp=spp, seed=3, shade=2)[0]
+    assert np.all(np.abs(S - after) <= 5 * np.abs(s1 - s2) / 2 / math.sqrt(spp) + 1e-12)
+
+
+def test_generated_normal_map(orc):
+    """The synthetic map holds unit tangent-space normals facing out, tiles,
+    and is flatter at coarser MIP levels (the averaged normals shorten)."""
+    t = inputs.texture_normal_map(128, seed=2, slope=3.0)
+    n = 2 * t[..., :3] - 1
+    assert np.allclose(np.linalg.norm(n, axis=-1), 1.0, atol=1e-12)
+    assert np.all(n[..., 2] > 0) and n[..., 2].min() < 0.9
+    lv = inputs.mip_chain(t)
+    lens = [np.linalg.norm(2 * x[..., :3] - 1, axis=-1).mean() for x in lv]
+    assert all(a >= b - 1e-12 for a, b in zip(lens, lens[1:])) and lens[-1] < lens[0]
