@@ -133,7 +133,20 @@ enum { SF_WRAP_REPEAT = 0, SF_WRAP_CLAMP = 1 };
  * floor(lambda) and floor(lambda)+1 with weights (1-f, f), f = frac(lambda)
  * (a stochastic mode picks ONE of them with those probabilities). */
 enum { SF_MIP_NONE = 0, SF_MIP_NEAREST = 1, SF_MIP_LINEAR = 2 };
-enum { SF_SHADE_NONE = 0, SF_SHADE_GGX = 1 };             /* 2-D */
+enum { SF_SHADE_NONE = 0, SF_SHADE_GGX = 1, SF_SHADE_GGX_NORMAL = 2 }; /* 2-D */
+/* SF_SHADE_GGX_NORMAL (sf_filter2d, sf_filter2d_aniso): a normal-mapped grey
+ * material (Sec. 3 "Normal maps": filtering the normals before shading
+ * changes a minified surface's appearance).  The texel's RGB encodes the
+ * tangent-space normal m = 2 rgb - 1, renormalised (z for m = 0), A the
+ * roughness parameter as for SF_SHADE_GGX; the tangent frame (e1, e2, n) of
+ * the sf_ggx normal n is sg = sign(n_z), a = -1/(sg + n_z), b = n_x n_y a,
+ * e1 = (1 + sg n_x^2 a, sg b, -sg n_x), e2 = (b, sg + n_y^2 a, -n_y) (Duff et
+ * al., JCGT 6(1), 2017); the GGX + Lambert model of SF_SHADE_GGX with albedo
+ * 1/2 is evaluated at the shading normal with its cosines clamped at 0 and
+ * the masking factors divided by their cosines analytically (G1(c)/c =
+ * 2/(c + sqrt(a^2 + (1 - a^2) c^2))), a continuous function that is 0 where
+ * the normal faces away from wi.  Filtering before shading shades the
+ * filtered (shortened, then renormalised) normal.  Output: RGB. */
 enum { SF_SHADE_DENSITY = 0, SF_SHADE_TRANSMITTANCE = 1, SF_SHADE_PLANCK = 2 }; /* 3-D points */
 /* SF_SHADE_PLANCK: the grid holds temperatures in kelvin, shaded by black-body
  * emission (Sec. 5 "Filtering nonlinear physical properties"): the spectral

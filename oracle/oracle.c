@@ -945,8 +945,11 @@ static void levels_of(const tex2d *t, float lam, int *l0, int *l1, float *f)
  * m = 2 rgb - 1, A the roughness parameter as for GGX; the shading normal
  * is m/|m| (z if m = 0) in the frame (e1, e2, n) of the geometric normal n
  * (branchless basis of Duff et al., JCGT 6(1), 2017); a grey material,
- * albedo 1/2, is shaded with the GGX + Lambert model above, and a shading
- * normal facing away from the viewer or the light gives 0. */
+ * albedo 1/2, is shaded with the GGX + Lambert model above with the
+ * cosines clamped at 0 and the masking factors divided by their cosines
+ * analytically, G1(c)/c = 2/(c + sqrt(a^2 + (1 - a^2) c^2)): the result is
+ * continuous, 0 where the shading normal faces away from the light, and
+ * grazing (c = 0) where it faces away from the viewer. */
 ORC_EXPORT void orc_shade_ggx_normal(const double *p, const double rgba[4], double out[3])
 {
     const double *n = p, *wo = p + 3, *wi = p + 6, *rad = p + 9;
@@ -969,19 +972,15 @@ ORC_EXPORT void orc_shade_ggx_normal(const double *p, const double rgba[4], doub
     h[0] /= hl;
     h[1] /= hl;
     h[2] /= hl;
-    double nh = dot3(ns, h), no = dot3(ns, wo), ni = dot3(ns, wi), ih = dot3(wi, h);
-    if (!(no > 0.0) || !(ni > 0.0)) {
-        out[0] = out[1] = out[2] = 0.0;
-        return;
-    }
+    double nh = dot3(ns, h), no = fmax(dot3(ns, wo), 0.0), ni = fmax(dot3(ns, wi), 0.0), ih = dot3(wi, h);
     double r = rb + rs * rgba[3];
     double a = r * r, a2 = a * a;
     double dd = nh * nh * (a2 - 1.0) + 1.0;
     double D = a2 / (PI * dd * dd);
-    double G1o = 2.0 * no / (no + sqrt(a2 + (1.0 - a2) * no * no));
-    double G1i = 2.0 * ni / (ni + sqrt(a2 + (1.0 - a2) * ni * ni));
+    double go = 2.0 / (no + sqrt(a2 + (1.0 - a2) * no * no)); /* G1(no)/no */
+    double gi = 2.0 / (ni + sqrt(a2 + (1.0 - a2) * ni * ni));
     double F = f0 + (1.0 - f0) * pow(1.0 - ih, 5.0);
-    double spec = D * G1o * G1i * F / (4.0 * no * ni);
+    double spec = D * go * gi * F / 4.0;
     for (int c = 0; c < 3; ++c)
         out[c] = rad[c] * (0.5 / PI + spec) * ni;
 }

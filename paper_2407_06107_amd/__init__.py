@@ -26,7 +26,7 @@ SF_BEFORE, SF_AFTER_EXACT, SF_STOCHASTIC, SF_SPLIT = 0, 1, 2, 3
 SF_RGBA32F, SF_RGBA8_UNORM, SF_R16F, SF_R32F, SF_DCT8 = 0, 1, 2, 3, 4
 SF_WRAP_REPEAT, SF_WRAP_CLAMP = 0, 1
 SF_MIP_NONE, SF_MIP_NEAREST, SF_MIP_LINEAR = 0, 1, 2
-SF_SHADE_NONE, SF_SHADE_GGX = 0, 1
+SF_SHADE_NONE, SF_SHADE_GGX, SF_SHADE_GGX_NORMAL = 0, 1, 2
 SF_SHADE_DENSITY, SF_SHADE_TRANSMITTANCE, SF_SHADE_PLANCK = 0, 1, 2
 PLANCK_NM = (700.0, 546.1, 435.8)
 SF_TAP_NONE = -(2 ** 31)
@@ -304,7 +304,7 @@ def sf_filter2d(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, shade: 
                 dbg_taps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     _need(queries, torch.float32, "queries")
     n = queries.numel() // 3
-    ch = 3 if shade == SF_SHADE_GGX else 4
+    ch = 3 if shade != SF_SHADE_NONE else 4
     if out is None:
         out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
     _need(out, torch.float32, "out", n * ch)
@@ -325,7 +325,7 @@ def sf_filter2d_aniso(tex: Texture2D, queries: torch.Tensor, smp: sf_sampling, a
     if queries.numel() % 6:
         raise ValueError("queries must hold 6 floats per pixel")
     n = queries.numel() // 6
-    ch = 3 if shade == SF_SHADE_GGX else 4
+    ch = 3 if shade != SF_SHADE_NONE else 4
     if out is None:
         out = torch.empty((n, ch), dtype=torch.float32, device=queries.device)
     _need(out, torch.float32, "out", n * ch)

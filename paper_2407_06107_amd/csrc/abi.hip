@@ -144,6 +144,27 @@ sf_status ggx_constants(const sf_ggx *g, sfk::GgxConst &c)
     }
     c.r_bias = g->r_bias;
     c.r_scale = g->r_scale;
+    // tangent frame of n (Duff et al., JCGT 6(1), 2017) for normal-mapped shading
+    const double sg = n[2] >= 0.0 ? 1.0 : -1.0;
+    const double fa = -1.0 / (sg + n[2]), fb = n[0] * n[1] * fa;
+    const double e1[3] = {1.0 + sg * n[0] * n[0] * fa, sg * fb, -sg * n[0]};
+    const double e2[3] = {fb, sg + n[1] * n[1] * fa, -n[1]};
+    const double *vs[2] = {wo, wi};
+    float *ts[2] = {c.to, c.ti};
+    for (int v = 0; v < 2; ++v) {
+        const double *x = vs[v];
+        ts[v][0] = (float)(e1[0] * x[0] + e1[1] * x[1] + e1[2] * x[2]);
+        ts[v][1] = (float)(e2[0] * x[0] + e2[1] * x[1] + e2[2] * x[2]);
+        ts[v][2] = (float)(n[0] * x[0] + n[1] * x[1] + n[2] * x[2]);
+    }
+    c.th[0] = e1[0] * h[0] + e1[1] * h[1] + e1[2] * h[2];
+    c.th[1] = e2[0] * h[0] + e2[1] * h[1] + e2[2] * h[2];
+    c.th[2] = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+    c.F = (float)F;
+    for (int k = 0; k < 3; ++k) {
+        c.rad[k] = g->radiance[k];
+        c.kdn[k] = (float)(g->radiance[k] * 0.5 / pi);
+    }
     return SF_OK;
 }
 
@@ -231,12 +252,12 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
                     (double)SF_SIGMA_MAX);
     if ((st = check_tex2d(tex)) != SF_OK)
         return st;
-    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
+    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX && shade != SF_SHADE_GGX_NORMAL)
         return fail(SF_E_RANGE, "shade %d out of range", shade);
     if (!aligned(queries, 4) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))
         return fail(SF_E_RANGE, "queries or out misaligned");
     sfk::Filter2DCall c{};
-    if (shade == SF_SHADE_GGX) {
+    if (shade != SF_SHADE_NONE) {
         if (!ggx)
             return fail(SF_E_NULL, "GGX shading needs ggx parameters");
         if ((st = ggx_constants(ggx, c.g)) != SF_OK)
@@ -303,12 +324,12 @@ sf_status sf_filter2d_aniso(const sf_tex2d *tex, const float *queries, int64_t n
             return fail(SF_E_UNSUPPORTED, "EWA: aspect %dx%d beyond %d:1", tex->width, tex->height,
                         SF_EWA_MAX_ASPECT);
     }
-    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX)
+    if (shade != SF_SHADE_NONE && shade != SF_SHADE_GGX && shade != SF_SHADE_GGX_NORMAL)
         return fail(SF_E_RANGE, "shade %d out of range", shade);
     if (!aligned(queries, 4) || !aligned(out, shade == SF_SHADE_NONE ? 16 : 4))
         return fail(SF_E_RANGE, "queries or out misaligned");
     sfk::AnisoCall c{};
-    if (shade == SF_SHADE_GGX) {
+    if (shade != SF_SHADE_NONE) {
         if (!ggx)
             return fail(SF_E_NULL, "GGX shading needs ggx parameters");
         if ((st = ggx_constants(ggx, c.g)) != SF_OK)

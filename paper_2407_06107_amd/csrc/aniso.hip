@@ -565,6 +565,8 @@ static void launch_a1(const AnisoCall &c, hipStream_t s)
 {
     if (c.shade == SF_SHADE_GGX)
         launch_a2<F, SF_SHADE_GGX>(c, s);
+    else if (c.shade == SF_SHADE_GGX_NORMAL)
+        launch_a2<F, SF_SHADE_GGX_NORMAL>(c, s);
     else
         launch_a2<F, SF_SHADE_NONE>(c, s);
 }
@@ -590,6 +592,8 @@ hipError_t launch_aniso(const AnisoCall &c, hipStream_t s)
     case EWA:
         if (c.shade == SF_SHADE_GGX)
             launch_ewa<SF_SHADE_GGX>(c, s);
+        else if (c.shade == SF_SHADE_GGX_NORMAL)
+            launch_ewa<SF_SHADE_GGX_NORMAL>(c, s);
         else
             launch_ewa<SF_SHADE_NONE>(c, s);
         break;

@@ -387,6 +387,8 @@ static void launch_f1(const Filter2DCall &c, hipStream_t s)
 {
     if (c.shade == SF_SHADE_GGX)
         launch_f2<F, SF_SHADE_GGX>(c, s);
+    else if (c.shade == SF_SHADE_GGX_NORMAL)
+        launch_f2<F, SF_SHADE_GGX_NORMAL>(c, s);
     else
         launch_f2<F, SF_SHADE_NONE>(c, s);
 }

@@ -512,6 +512,42 @@ __device__ __forceinline__ float3 shade_ggx_dev(const GgxConst &g, float4 c)
                        __builtin_fmaf(g.kd[2], c.z, g.ks[2] * spec));
 }
 
+// Normal-mapped GGX + Lambert of a grey material (albedo 1/2): the texel's
+// RGB encodes the tangent-space normal m = 2 rgb - 1 (renormalised; z for
+// m = 0), A the roughness parameter; h, wo, wi come in the tangent frame, so
+// each cosine is one dot product with m.  Cosines are clamped at 0 and the
+// masking factors taken as G1(c)/c = 2/(c + sqrt(a^2 + (1 - a^2) c^2)), so
+// the result is continuous (0 where the normal faces away from the light).
+__device__ __forceinline__ float3 shade_ggx_normal_dev(const GgxConst &g, float4 c)
+{
+    float mx = __builtin_fmaf(2.0f, c.x, -1.0f), my = __builtin_fmaf(2.0f, c.y, -1.0f),
+          mz = __builtin_fmaf(2.0f, c.z, -1.0f);
+    const float ml2 = mx * mx + my * my + mz * mz;
+    float inv = 1.0f;
+    if (ml2 > 0.0f) {
+        inv = 1.0f / __builtin_sqrtf(ml2);
+    } else {
+        mx = 0.0f, my = 0.0f, mz = 1.0f;
+    }
+    const float no = __builtin_fmaxf((mx * g.to[0] + my * g.to[1] + mz * g.to[2]) * inv, 0.0f);
+    const float ni = __builtin_fmaxf((mx * g.ti[0] + my * g.ti[1] + mz * g.ti[2]) * inv, 0.0f);
+    const float r = __builtin_fmaf(g.r_scale, c.w, g.r_bias);
+    const float a = r * r;
+    const float a2 = a * a;
+    // 1 - (n.h)^2 (1 - alpha^2) cancels near the peak of a glossy lobe: binary64
+    const double mxd = mx, myd = my, mzd = mz;
+    const double nhd = mxd * g.th[0] + myd * g.th[1] + mzd * g.th[2];
+    const double c2 = (nhd * nhd) / (mxd * mxd + myd * myd + mzd * mzd);
+    const double dd = __builtin_fma(c2, (double)a2 - 1.0, 1.0);
+    const float D = (float)((double)a2 / (dd * dd));   // times 1/pi below
+    const float om = 1.0f - a2;
+    const float go = 2.0f / (no + __builtin_sqrtf(__builtin_fmaf(om, no * no, a2)));   // G1(no)/no
+    const float gi = 2.0f / (ni + __builtin_sqrtf(__builtin_fmaf(om, ni * ni, a2)));
+    const float spec = (D * go * gi * g.F) * (1.0f / (4.0f * 3.14159265f));
+    return make_float3(ni * __builtin_fmaf(g.rad[0], spec, g.kdn[0]), ni * __builtin_fmaf(g.rad[1], spec, g.kdn[1]),
+                       ni * __builtin_fmaf(g.rad[2], spec, g.kdn[2]));
+}
+
 __device__ __forceinline__ float half_bits_to_float(uint16_t h)
 {
     return (float)__builtin_bit_cast(_Float16, h);

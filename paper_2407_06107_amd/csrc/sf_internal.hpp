@@ -16,6 +16,12 @@ struct GgxConst {
     float spec_k;          // F / (4 (n.wo)(n.wi) pi)
     float kd[3], ks[3];    // radiance * (n.wi) / pi, radiance * (n.wi)
     float r_bias, r_scale;
+    // normal-mapped shading: h, wo, wi in the tangent frame (e1, e2, n) of
+    // the surface normal, Fresnel, radiance and the grey diffuse term
+    float to[3], ti[3];
+    double th[3];          // binary64: the distribution term cancels near its peak
+    float F;
+    float rad[3], kdn[3];  // radiance, radiance * (1/2) / pi
 };
 
 struct Tex2DArgs {

@@ -126,6 +126,9 @@ __device__ __forceinline__ float4 shade(const GgxConst &g, float4 c)
     if constexpr (SHADE == SF_SHADE_GGX) {
         float3 v = shade_ggx_dev(g, c);
         return make_float4(v.x, v.y, v.z, 0.0f);
+    } else if constexpr (SHADE == SF_SHADE_GGX_NORMAL) {
+        float3 v = shade_ggx_normal_dev(g, c);
+        return make_float4(v.x, v.y, v.z, 0.0f);
     } else {
         return c;
     }
@@ -134,7 +137,7 @@ __device__ __forceinline__ float4 shade(const GgxConst &g, float4 c)
 template <int SHADE>
 __device__ __forceinline__ void store(float *out, int64_t q, float4 v)
 {
-    if constexpr (SHADE == SF_SHADE_GGX) {
+    if constexpr (SHADE != SF_SHADE_NONE) {
         out[3 * q] = v.x;
         out[3 * q + 1] = v.y;
         out[3 * q + 2] = v.z;

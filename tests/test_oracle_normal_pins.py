@@ -71,11 +71,22 @@ def test_geometric_normal_frame(orc):
 
 
 def test_backfacing_and_normalisation(orc):
+    """0 where the shading normal faces away from the light, continuous
+    across the viewer's horizon, independent of the encoded normal's length."""
     g = orc.ggx_params()
-    wi = g[6:9]
+    wo, wi = g[3:6], g[6:9]
     m = -wi + np.array([0.0, 0.0, 0.05])
     m /= np.linalg.norm(m)
     assert np.all(orc.shade_ggx_normal(g, [*_enc(m), 0.3]) == 0.0)
+    # tilt a normal through the plane perpendicular to wo: the shading varies continuously
+    axis = np.cross(wo, wi)
+    axis /= np.linalg.norm(axis)
+    perp = np.cross(axis, wo)
+    perp /= np.linalg.norm(perp)            # perpendicular to wo, on wi's side
+    if perp @ wi < 0:
+        perp = -perp
+    vals = [orc.shade_ggx_normal(g, [*_enc(np.cos(e) * perp - np.sin(e) * wo), 0.3])[0] for e in (-1e-6, 0.0, 1e-6)]
+    assert vals[1] > 0 and abs(vals[0] - vals[1]) < 1e-3 * vals[1] and abs(vals[2] - vals[1]) < 1e-3 * vals[1]
     m = np.array([0.2, -0.1, 0.97])
     m /= np.linalg.norm(m)
     a = orc.shade_ggx_normal(g, [*_enc(m), 0.3])
