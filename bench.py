@@ -229,9 +229,11 @@ def _rmse(a, b):
 
 
 def aniso_bench(res):
-    """Config 2, anisotropic: a 4096^2 RGBA8 checkerboard pyramid under a
-    1920x1080 plane camera, footprint-driven levels; jittered minification,
-    hardware-style probes and EWA, against the pixel-integral reference."""
+    """Config 2, anisotropic: 4096^2 RGBA8 pyramids under a 1920x1080 plane
+    camera, footprint-driven levels; jittered minification, hardware-style
+    probes and EWA, against the pixel-integral reference.  Two surfaces: the
+    checkerboard shaded as a GGX material, and a bump normal map shaded with
+    its texel normals (filtering before shading averages the normals)."""
     import torch
     import oracle
     import paper_2407_06107_amd as sf
@@ -239,23 +241,11 @@ def aniso_bench(res):
 
     g = sf.ggx()
     rng = np.random.default_rng(9)
-    log("config 2 anisotropic: checkerboard")
-    lvc = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_checker(4096, 64)))
     qa = inputs.plane_queries_aniso(1920, 1080)
-    qi = inputs.plane_queries(1920, 1080, tex_size=4096, levels=len(lvc))
     na = qa.shape[0]
-    texc = sf.Texture2D(lvc, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
-    qad, qid = torch.from_numpy(qa).cuda(), torch.from_numpy(qi).cuda()
-    bufc, offc = inputs.pack_levels(lvc)
-    otc0 = oracle.Tex2D(bufc, 4096, 4096, 1, oracle.RGBA8, offc[:1], oracle.REPEAT, oracle.MIP_NONE)
+    qad = torch.from_numpy(qa).cuda()
     suba = np.sort(rng.choice(na, 2000, replace=False))
-    t0 = time.perf_counter()
-    ref_a = oracle.aniso_reference(otc0, qa, K=16, filt=oracle.BSPLINE3, shade=1, subset=suba)
-    dt_ref = time.perf_counter() - t0
-    ca = {"queries": na, "reference": f"pixel integral, 16x16 midpoints x bicubic filter-after on level 0, "
-                                      f"{suba.size} pixels ({dt_ref:.1f} s on the CPU)"}
-    for name, filt, mode, spp, amax in (
-            ("aniso_bicubic_stochastic_1spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, 64),
+    rows = (("aniso_bicubic_stochastic_1spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, 64),
             ("aniso_bicubic_stochastic_16spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 16, 64),
             ("aniso_bilinear_stochastic_1spp", sf.SF_LINEAR, sf.SF_STOCHASTIC, 1, 64),
             ("aniso_gauss_fis_stochastic_16spp", sf.SF_GAUSS_FIS, sf.SF_STOCHASTIC, 16, 64),
@@ -267,23 +257,41 @@ def aniso_bench(res):
             ("ewa16_after", sf.SF_EWA, sf.SF_AFTER_EXACT, 1, 16),
             ("ewa16_before", sf.SF_EWA, sf.SF_BEFORE, 1, 16),
             ("ewa16_stochastic_1spp", sf.SF_EWA, sf.SF_STOCHASTIC, 1, 16),
-            ("ewa16_stochastic_16spp", sf.SF_EWA, sf.SF_STOCHASTIC, 16, 16)):
-        smp = sf.sampling(filt, mode, spp, seed=5, sigma=0.5)
+            ("ewa16_stochastic_16spp", sf.SF_EWA, sf.SF_STOCHASTIC, 16, 16))
+    for key, label, levels, shade in (
+            ("config2_aniso", "checkerboard", lambda: inputs.texture_checker(4096, 64), sf.SF_SHADE_GGX),
+            ("config2_aniso_normal_map", "bump normal map",
+             lambda: inputs.texture_normal_map(4096, seed=13, slope=3.0), sf.SF_SHADE_GGX_NORMAL)):
+        log(f"config 2 anisotropic: {label}")
+        lv = inputs.quantize_unorm8(inputs.mip_chain(levels()))
+        qi = inputs.plane_queries(1920, 1080, tex_size=4096, levels=len(lv))
+        tex = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+        qid = torch.from_numpy(qi).cuda()
+        buf, off = inputs.pack_levels(lv)
+        ot0 = oracle.Tex2D(buf, 4096, 4096, 1, oracle.RGBA8, off[:1], oracle.REPEAT, oracle.MIP_NONE)
+        t0 = time.perf_counter()
+        ref_a = oracle.aniso_reference(ot0, qa, K=16, filt=oracle.BSPLINE3, shade=shade, subset=suba)
+        dt_ref = time.perf_counter() - t0
+        ca = {"queries": na, "texture": label,
+              "reference": f"pixel integral, 16x16 midpoints x bicubic filter-after on level 0, "
+                           f"{suba.size} pixels ({dt_ref:.1f} s on the CPU)",
+              "reference_rms": float(np.sqrt(np.mean(ref_a ** 2)))}
+        for name, filt, mode, spp, amax in rows:
+            smp = sf.sampling(filt, mode, spp, seed=5, sigma=0.5)
+            o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
+            t = time_launches(lambda: sf.sf_filter2d_aniso(tex, qad, smp, amax, shade, g, out=o), 10, 3, torch)
+            ca[name] = {"ms": t, "queries_per_s": na / (t * 1e-3),
+                        "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
+            if name == "ewa16_after":
+                ewa_after = o.cpu().numpy()
+            elif filt == sf.SF_EWA:
+                ca[name]["rmse_vs_ewa_after"] = _rmse(o.cpu().numpy(), ewa_after)
+        smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)
         o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
-        t = time_launches(lambda: sf.sf_filter2d_aniso(texc, qad, smp, amax, sf.SF_SHADE_GGX, g, out=o), 10, 3,
-                          torch)
-        ca[name] = {"ms": t, "queries_per_s": na / (t * 1e-3),
-                    "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
-        if name == "ewa16_after":
-            ewa_after = o.cpu().numpy()
-        elif filt == sf.SF_EWA:
-            ca[name]["rmse_vs_ewa_after"] = _rmse(o.cpu().numpy(), ewa_after)
-    smp = sf.sampling(sf.SF_LINEAR, sf.SF_BEFORE, 1)
-    o = torch.empty((na, 3), dtype=torch.float32, device="cuda")
-    t = time_launches(lambda: sf.sf_filter2d(texc, qid, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
-    ca["isotropic_trilinear_before"] = {"ms": t, "queries_per_s": na / (t * 1e-3),
-                                        "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
-    res["config2_aniso"] = ca
+        t = time_launches(lambda: sf.sf_filter2d(tex, qid, smp, shade, g, out=o), 10, 3, torch)
+        ca["isotropic_trilinear_before"] = {"ms": t, "queries_per_s": na / (t * 1e-3),
+                                            "rmse_vs_pixel_reference": _rmse(o.cpu().numpy()[suba], ref_a)}
+        res[key] = ca
 
 
 def planck_bench(res):
