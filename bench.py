@@ -43,10 +43,10 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # into the thresholds), thresholds (33), picks (21), address (12) and
 # accumulation (3).
 OPS_POSITION, OPS_OCCUPIED = 13, 85
-# The occupancy test of a step: brick coordinates (3 shifts), range test
-# (3 compares), brick index (2 24-bit multiply-adds), word index, load
-# select, bit extract and test.
-OPS_BRICK = 12
+# The occupancy test of a step: brick coordinates (3 shifts), clamp to the
+# grid's bricks (3), brick index (2 shift-ors or 24-bit multiply-adds), word
+# index, bit extract and test.
+OPS_BRICK = 11
 BRICK_LOG2 = 3
 
 
@@ -164,11 +164,10 @@ def count_occupied_steps(torch, occ, rays_d):
         kh = torch.arange(k0, min(STEPS, k0 + 32), device=rays_d.device, dtype=torch.float32) + 0.5
         p = E[:, None, :] + kh[None, :, None] * G[:, None, :]
         b = torch.div(torch.floor(p).to(torch.int64), 1 << BRICK_LOG2, rounding_mode="floor")
-        inr = ((b >= 0) & (b < nb)).all(-1)
-        bc = b.clamp(0, nb - 1)
+        bc = b.clamp(0, nb - 1)          # the kernel tests the nearest brick
         lin = (bc[..., 2] * nb + bc[..., 1]) * nb + bc[..., 0]
         bit = (words[lin >> 5] >> (lin & 31)) & 1
-        occupied = (bit.bool() | ~inr) & hit[:, None]
+        occupied = bit.bool() & hit[:, None]
         total += int(occupied.sum())
     return total
 

@@ -80,25 +80,38 @@ __device__ __forceinline__ void step_coords(const RayGeom &g, float kh, int i0[3
 
 // True unless the lookup point's brick is known to be empty: a tap of any
 // filter lies within [i0-1, i0+2] per axis, inside the brick's 2-voxel
-// dilation, so a clear bit means every tap reads zero.  Bricks outside the
-// grid (points within a voxel of the lower faces) count as occupied.
+// dilation, so a clear bit means every tap reads zero.  The brick
+// coordinates are clamped to the grid's bricks, which is exact as well: for
+// i0 < 0 the taps inside the grid lie in [0, 1], and for i0 at or beyond the
+// last brick's end they lie in {n-1} (or nowhere), both within the dilation
+// of the nearest brick; so no step whose taps can read a non-zero voxel is
+// skipped, and the index always lies inside the mask.  The bit is extracted
+// with the hardware's offset-mod-32 field extract.
 // P2: nx and ny are powers of two, so are the brick counts along x and y
 // (nx >> occ_log2, or 1 below one brick) and the index is built with shifts.
+// clamp(x, 0, hi) for a wave-uniform hi in one instruction (the compiler
+// forms v_med3_i32 only for compile-time bounds)
+__device__ __forceinline__ int clamp0_uniform(int x, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
+}
+
 template <bool P2 = false>
 __device__ __forceinline__ bool brick_occupied(const VolArgs &v, const int i0[3])
 {
-    const int bx = i0[0] >> v.occ_log2, by = i0[1] >> v.occ_log2, bz = i0[2] >> v.occ_log2;
-    const bool in = ((uint32_t)bx < (uint32_t)v.nbx) & ((uint32_t)by < (uint32_t)v.nby) &
-                    ((uint32_t)bz < (uint32_t)v.nbz);
+    const uint32_t bx = (uint32_t)clamp0_uniform(i0[0] >> v.occ_log2, v.nbx - 1);
+    const uint32_t by = (uint32_t)clamp0_uniform(i0[1] >> v.occ_log2, v.nby - 1);
+    const uint32_t bz = (uint32_t)clamp0_uniform(i0[2] >> v.occ_log2, v.nbz - 1);
     uint32_t b;
     if constexpr (P2) {
         const int lbx = max(v.lx - v.occ_log2, 0), lby = max(v.ly - v.occ_log2, 0);
-        b = ((((uint32_t)bz << lby) | (uint32_t)by) << lbx) | (uint32_t)bx;
+        b = (((bz << lby) | by) << lbx) | bx;
     } else {
-        b = __umul24(__umul24((uint32_t)bz, (uint32_t)v.nby) + (uint32_t)by, (uint32_t)v.nbx) + (uint32_t)bx;
+        b = __umul24(__umul24(bz, (uint32_t)v.nby) + by, (uint32_t)v.nbx) + bx;
     }
-    const uint32_t w = v.occ[in ? (b >> 5) : 0u];
-    return !in | (((w >> (b & 31u)) & 1u) != 0u);
+    return __builtin_amdgcn_ubfe(v.occ[b >> 5], b, 1u) != 0u;
 }
 
 // The loaded bits, or 0 (the value 0.0) for a tap outside the grid.  The
