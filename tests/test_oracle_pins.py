@@ -529,6 +529,37 @@ def test_occupancy_mask_property(orc):
     assert n_clear > 0
 
 
+def test_occupancy_nearest_brick_is_exact_outside_the_grid(orc):
+    """The ray march tests the brick nearest to a lookup point (its brick
+    coordinates clamped to the grid's bricks), also for points outside the
+    grid: a point whose trilinear or tricubic value is non-zero never meets a
+    clear bit.  Points on a raster range 4 voxels beyond every face; the data
+    are zero near the low x and z faces and the high x face, so clamped
+    bricks there are clear."""
+    data = inputs.cloud_grid(24, seed=6).numpy()
+    data[:, :, :6] = 0.0
+    data[:, :, 18:] = 0.0
+    data[:5] = 0.0
+    g = _grid(data)
+    lg, nb = 2, 6
+    words = orc.build_occupancy(g, lg)
+    rng = np.random.default_rng(1)
+    raster = rng.uniform(-4.0, 28.0, size=(40000, 3))
+    p = ((raster + 0.5) / 24.0).astype(np.float32)
+    r32 = (p.astype(np.float64) * 24.0 - 0.5).astype(np.float32)     # fma(p, 24, -1/2) in binary32
+    i0 = np.floor(r32).astype(np.int64)
+    bc = np.clip(i0 >> lg, 0, nb - 1)
+    b = (bc[:, 2] * nb + bc[:, 1]) * nb + bc[:, 0]
+    bit = (words[b >> 5] >> (b & 31)) & 1
+    outside = np.any((i0 < 0) | (i0 >= 24), axis=1)
+    clear = bit == 0
+    assert (clear & outside).sum() > 3000 and (~clear & outside).sum() > 3000
+    for filt in (orc.LINEAR, orc.BSPLINE3):
+        v = orc.filter3d(g, p, filt, orc.BEFORE)
+        assert np.all(v[clear] == 0.0)
+        assert np.any(v[~clear & outside] != 0.0)
+
+
 # ------------------------------------------------- Keys cubic, positivisation
 def test_keys_cubic_interpolates_and_reproduces_quadratics(orc):
     """S.2's K3 with a = -1/2 interpolates (K3(0) = 1, K3(+-1) = K3(+-2) = 0)
