@@ -172,6 +172,24 @@ def count_occupied_steps(torch, occ, rays_d):
     return total
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Streaming rate the chip reaches on a plain device-to-device copy of
+    nbytes (torch's copy), in GB/s of bytes read plus written."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del src, dst
+    return 2 * nbytes / t / 1e9
+
+
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -810,6 +828,8 @@ def main():
         extra["speedup_vs_tricubic_after_same_rays"] = rates["tricubic_after_64tap"]["ms"] / ms
         extra["speedup_vs_tricubic_before_same_rays"] = rates["tricubic_before_64tap"]["ms"] / ms
 
+    copy_gbs = copy_bandwidth(torch)
+
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
@@ -835,6 +855,8 @@ def main():
         "rays_per_s": n / (ms * 1e-3),
         "hbm_algorithmic_gbs": achieved_gbs,
         "hbm_algorithmic_frac": achieved_gbs / HBM_PEAK_GBS,
+        "hbm_copy_gbs": copy_gbs,
+        "hbm_algorithmic_frac_of_copy": achieved_gbs / copy_gbs,
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": traffic,
                      "algorithmic_ops": algo_ops, "algorithmic_bytes": algo_bytes},

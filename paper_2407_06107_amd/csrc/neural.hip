@@ -460,20 +460,25 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint32_t lo, uint32_t hi)
 }
 
 // The MLP on the 16 samples whose latents (K block of this lane) are in zb;
-// column scale cs multiplies layer 1's product (E4M3 block scale; 1 for
-// BF16 latents).  Returns the layer-3 accumulators: lanes 0..15 hold outputs
-// 0..3 of sample (lane).
-template <int C, int O>
+// column scale cs multiplies layer 1's product (E4M3 block scale, SCALED);
+// BF16 latents have no scale, and layer 1's bias enters its matrix product
+// as the accumulator, as layer 2's does.  Returns the layer-3 accumulators:
+// lanes 0..15 hold outputs 0..3 of sample (lane).
+template <int C, int O, bool SCALED>
 __device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x8 zb, float cs)
 {
     f32x4 d1[4];
     const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        d1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[m], zb, zero, 0, 0, 0);
+        if constexpr (SCALED) {
+            d1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[m], zb, zero, 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            d1[m][j] = __builtin_fmaf(cs, d1[m][j], F.b1[m][j]);
+            for (int j = 0; j < 4; ++j)
+                d1[m][j] = __builtin_fmaf(cs, d1[m][j], F.b1[m][j]);
+        } else {
+            d1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[m], zb, F.b1[m], 0, 0, 0);
+        }
     }
     const bf16x8 h1a = relu_pack(d1[0], d1[1]), h1b = relu_pack(d1[2], d1[3]);
     f32x4 d2[4];
@@ -521,16 +526,21 @@ __device__ __forceinline__ void decode_wave(const LatentArgs &g, const MlpFrags<
                                             float y[O])
 {
     const int lane = threadIdx.x & 63;
+    // the four groups' latents are gathered first, so their loads overlap
+    bf16x8 zb[4];
+    float cs[4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         const int src = 16 * G + (lane & 15);
         const int64_t sidx = ((int64_t)__shfl((int)(idx >> 32), src) << 32) | (uint32_t)__shfl((int)idx, src);
         const int sblk = FMT == SF_LATENT_BF16 ? 0 : __shfl(blk, src);
-        float cs;
-        const bf16x8 zb = latent_frag<C, FMT>(g, sidx, sblk, cs);
+        zb[G] = latent_frag<C, FMT>(g, sidx, sblk, cs[G]);
+    }
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
         if constexpr (FMT != SF_LATENT_BF16)
-            cs = __shfl(cs, lane & 15);   // the scale of this lane's column (lanes 0..15 loaded it)
-        const f32x4 d3 = mlp16<C, O>(F, zb, cs);
+            cs[G] = __shfl(cs[G], lane & 15);   // the scale of this lane's column (lanes 0..15 loaded it)
+        const f32x4 d3 = mlp16<C, O, FMT != SF_LATENT_BF16>(F, zb[G], cs[G]);
 #pragma unroll
         for (int o = 0; o < O; ++o) {
             const float v = __shfl(d3[o], lane & 15);
@@ -547,13 +557,13 @@ __device__ __forceinline__ int wrapi(int i, int n)
 }
 
 // 2-D neural texture lookups (repeat wrap).  Decoded texel = clamp(MLP, 0, 1).
+// One query per lane: filter the decoded latent texture at query q (every
+// lane of the wave takes part in the decodes; q >= n marks a lane with
+// nothing to do).
 template <int F_, int SHADE, int MODE, int FMT>
-__global__ __launch_bounds__(256) void k_neural2d(NeuralCall c)
+__device__ __forceinline__ void neural2d_query(const NeuralCall &c, const MlpFrags<8, 4> &Fr, int64_t q)
 {
     constexpr int C = 8, O = 4;
-    MlpFrags<C, O> Fr;
-    load_frags<C, O>(static_cast<const uint16_t *>(c.mlp.params), Fr);
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool active = q < c.n;
     float qx = 0.f, qy = 0.f;
     if (active) {
@@ -666,6 +676,22 @@ __global__ __launch_bounds__(256) void k_neural2d(NeuralCall c)
     }
 }
 
+// The MLP's fragments are loaded into registers once per workgroup, which
+// then walks the query stream in tiles of 256 (a grid of at most
+// N2D_MAX_BLOCKS workgroups), so their load is spread over several tiles.
+// The tile base is uniform over the workgroup.
+constexpr uint32_t N2D_MAX_BLOCKS = 2048;
+
+template <int F_, int SHADE, int MODE, int FMT>
+__global__ __launch_bounds__(256) void k_neural2d(NeuralCall c)
+{
+    MlpFrags<8, 4> Fr;
+    load_frags<8, 4>(static_cast<const uint16_t *>(c.mlp.params), Fr);
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < c.n; base += stride)
+        neural2d_query<F_, SHADE, MODE, FMT>(c, Fr, base + threadIdx.x);
+}
+
 // Decoded outputs at given lattice points (no filtering, no clamping).
 template <int C, int O, int FMT>
 __global__ __launch_bounds__(256) void k_decode_lattice(NeuralCall c, const int64_t *idx_in)
@@ -743,7 +769,7 @@ __device__ __forceinline__ void decode_loaded(const MlpFrags<C, O> &F, const Ste
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        const f32x4 d3 = mlp16<C, O>(F, latents_bf16<FMT>(L.raw[G]), L.cs[G]);
+        const f32x4 d3 = mlp16<C, O, FMT != SF_LATENT_BF16>(F, latents_bf16<FMT>(L.raw[G]), L.cs[G]);
 #pragma unroll
         for (int o = 0; o < O; ++o) {
             const float v = __shfl(d3[o], lane & 15);
@@ -878,7 +904,8 @@ int train_nparams(int C, int O) { return POff(C, O).n; }
 template <int F_, int SHADE, int MODE>
 static void launch_n2_m(const NeuralCall &c, hipStream_t s)
 {
-    dim3 grid((uint32_t)((c.n + 255) / 256)), block(256);
+    const int64_t tiles = (c.n + 255) / 256;
+    dim3 grid((uint32_t)(tiles < (int64_t)N2D_MAX_BLOCKS ? tiles : (int64_t)N2D_MAX_BLOCKS)), block(256);
     if (c.lat.fmt == SF_LATENT_BF16)
         k_neural2d<F_, SHADE, MODE, SF_LATENT_BF16><<<grid, block, 0, s>>>(c);
     else
