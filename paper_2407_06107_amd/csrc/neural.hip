@@ -147,31 +147,36 @@ __device__ __forceinline__ float wave_sum(float v)
 }
 
 // One wavefront (= one workgroup) per chunk of the batch.  Lane h holds
-// hidden unit h: its column of W1 and W2, its row of W2 and W3, and the
-// matching gradient accumulators.  S consecutive samples are processed
-// together: their loads and their multiply-add chains are independent, so
-// they overlap, while every per-sample sum and every accumulator update
-// keeps the sample order (the results equal those of one sample at a time).
+// hidden unit h: its column of W1, its row of W3 and the matching gradient
+// accumulators; W2 and W1 sit in LDS with rows padded to HID + 1 words, so
+// that lane h reads column h (W2[k][h], layer 2 forward) and row h (W2[h][k],
+// W1[h][k], the backward sums) without bank conflicts, and the wavefront
+// keeps few enough registers to share a SIMD.  S consecutive samples are
+// processed together: their loads and their multiply-add chains are
+// independent, so they overlap, while every per-sample sum and every
+// accumulator update keeps the sample order (the results equal those of one
+// sample at a time).
 template <int C, int O, int S>
 __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float *partials)
 {
+    constexpr int LD = HID + 1;
+    __shared__ float sw2[HID * LD], sw1[C * LD];
     __shared__ float sh_h1[HID][S], sh_da[HID][S];
     const POff P(C, O);
     const int h = threadIdx.x;
     const float *W = t.params;
-    float w1c[C], w2c[HID], w2r[HID], w3r[O], w1r[HID];
+    float w1c[C], w3r[O];
 #pragma unroll
-    for (int c = 0; c < C; ++c)
+    for (int c = 0; c < C; ++c) {
         w1c[c] = W[P.w1 + c * HID + h];
-#pragma unroll
-    for (int k = 0; k < HID; ++k) {
-        w2c[k] = W[P.w2 + k * HID + h];
-        w2r[k] = W[P.w2 + h * HID + k];
-        w1r[k] = h < C ? W[P.w1 + h * HID + k] : 0.0f;
+        sw1[c * LD + h] = w1c[c];
     }
+    for (int k = 0; k < HID; ++k)
+        sw2[k * LD + h] = W[P.w2 + k * HID + h];
 #pragma unroll
     for (int o = 0; o < O; ++o)
         w3r[o] = W[P.w3 + h * O + o];
+    __syncthreads();
     const float b1 = W[P.b1 + h], b2 = W[P.b2 + h];
     float b3[O];
 #pragma unroll
@@ -192,39 +197,79 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
     const float inv_b = 2.0f / (float)t.batch;
     const int64_t s0 = (int64_t)blockIdx.x * chunk;
     const int64_t s1 = min(s0 + chunk, t.batch);
-    for (int64_t sb = s0; sb < s1; sb += S) {
-        // the group's samples; an index outside the lattice (or past the
-        // chunk) contributes nothing
-        int64_t li[S];
-        bool use[S];
+    // Software pipeline over the groups of S samples, unrolled twice over two
+    // register sets so that no value still in flight is ever copied: while a
+    // group is computed, the next group's latents and targets and the batch
+    // indices of the group after it are being read, and the group's own Adam
+    // moments and latent values are read at its start.  The batch indices are
+    // distinct, so no value read ahead is one that an earlier group updates.
+    // An index outside the lattice (or past the chunk) contributes nothing.
+    // Every read ahead is unconditional, from element 0 where a sample is
+    // unused (past the chunk, or an index outside the lattice), and no value
+    // read ahead is selected on before its use: a select would make the wave
+    // wait for the load at once.  An unused sample's values only feed its
+    // own sums, which every update, store and gradient gates on use[j].
+    struct Group {
+        int32_t raw[S];   // batch indices as read
+        bool in[S];       // inside the chunk
         float z[S][C], tg[S][O];
+    };
+    Group A, B;
+    const auto read_idx = [&](int64_t sb, Group &G) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            li[j] = sb + j < s1 ? t.idx[sb + j] : -1;
-            use[j] = (uint64_t)li[j] < (uint64_t)t.n_lattice;
+            G.in[j] = sb + j < s1;
+            G.raw[j] = t.idx[min(sb + j, s1 - 1)];
+        }
+    };
+    const auto usable = [&](const Group &G, int j) {
+        return G.in[j] && (uint64_t)(int64_t)G.raw[j] < (uint64_t)t.n_lattice;
+    };
+    const auto read_group = [&](Group &G) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int64_t p = usable(G, j) ? (int64_t)G.raw[j] : 0;
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                z[j][c] = use[j] ? t.latents[li[j] * C + c] : 0.0f;
+                G.z[j][c] = t.latents[p * C + c];
 #pragma unroll
             for (int o = 0; o < O; ++o)
-                tg[j][o] = use[j] ? t.targets[li[j] * O + o] : 0.0f;
+                G.tg[j][o] = t.targets[p * O + o];
         }
+    };
+    const auto step = [&](int64_t sb, Group &cur, Group &nxt) {
+        int64_t li[S];
+        bool use[S];
+        float mq[S], vq[S], zq[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            use[j] = usable(cur, j);
+            li[j] = cur.raw[j];
+            const int64_t q = use[j] && h < C ? li[j] * C + h : 0;   // lane c < C owns channel c
+            mq[j] = t.m_lat[q];
+            vq[j] = t.v_lat[q];
+            zq[j] = t.latents[q];
+        }
+        read_group(nxt);              // nxt's indices were read one group earlier
+        read_idx(sb + 2 * S, cur);    // the group after nxt
         float a1[S], a2[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             a1[j] = b1;
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                a1[j] = __builtin_fmaf(z[j][c], w1c[c], a1[j]);
+                a1[j] = __builtin_fmaf(cur.z[j][c], w1c[c], a1[j]);
             sh_h1[h][j] = a1[j] > 0.0f ? a1[j] : 0.0f;
             a2[j] = b2;
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < HID; ++k)
+#pragma unroll 16
+        for (int k = 0; k < HID; ++k) {
+            const float w = sw2[k * LD + h];   // W2[k][h]
 #pragma unroll
             for (int j = 0; j < S; ++j)
-                a2[j] = __builtin_fmaf(sh_h1[k][j], w2c[k], a2[j]);
+                a2[j] = __builtin_fmaf(sh_h1[k][j], w, a2[j]);
+        }
         float da2[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
@@ -233,7 +278,7 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
 #pragma unroll
             for (int o = 0; o < O; ++o) {
                 const float y = wave_sum(h2 * w3r[o]) + b3[o];
-                const float e = y - tg[j][o];
+                const float e = y - cur.tg[j][o];
                 const float dy = e * inv_b;
                 if (use[j]) {
                     loss = __builtin_fmaf(e, e, loss);
@@ -262,11 +307,13 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
 #pragma unroll
         for (int j = 0; j < S; ++j)
             dh1[j] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < HID; ++k)
+#pragma unroll 16
+        for (int k = 0; k < HID; ++k) {
+            const float w = sw2[h * LD + k];   // W2[h][k]
 #pragma unroll
             for (int j = 0; j < S; ++j)
-                dh1[j] = __builtin_fmaf(w2r[k], sh_da[k][j], dh1[j]);
+                dh1[j] = __builtin_fmaf(w, sh_da[k][j], dh1[j]);
+        }
         float da1[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
@@ -276,24 +323,26 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
             gb1 += da1[j];
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                g1[c] = __builtin_fmaf(z[j][c], da1[j], g1[c]);
+                g1[c] = __builtin_fmaf(cur.z[j][c], da1[j], g1[c]);
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < S; ++j)
             sh_da[h][j] = da1[j];
         __syncthreads();
-        // latent gradients and their Adam steps: lane c owns channel c
+        // latent gradients and their Adam steps
         if (h < C) {
             float gz[S];
 #pragma unroll
             for (int j = 0; j < S; ++j)
                 gz[j] = 0.0f;
-#pragma unroll
-            for (int k = 0; k < HID; ++k)
+#pragma unroll 16
+            for (int k = 0; k < HID; ++k) {
+                const float w = sw1[h * LD + k];   // W1[h][k]
 #pragma unroll
                 for (int j = 0; j < S; ++j)
-                    gz[j] = __builtin_fmaf(w1r[k], sh_da[k][j], gz[j]);
+                    gz[j] = __builtin_fmaf(w, sh_da[k][j], gz[j]);
+            }
 #pragma unroll
             for (int j = 0; j < S; ++j) {
                 if (!use[j])
@@ -301,14 +350,22 @@ __global__ __launch_bounds__(64) void k_train(TrainCall t, int64_t chunk, float 
                 if (t.grad_latents)
                     t.grad_latents[(sb + j) * C + h] = gz[j];
                 const int64_t q = li[j] * C + h;
-                const float m = 0.9f * t.m_lat[q] + 0.1f * gz[j];
-                const float v = 0.999f * t.v_lat[q] + 0.001f * gz[j] * gz[j];
+                const float m = 0.9f * mq[j] + 0.1f * gz[j];
+                const float v = 0.999f * vq[j] + 0.001f * gz[j] * gz[j];
                 t.m_lat[q] = m;
                 t.v_lat[q] = v;
-                t.latents[q] -= t.lr_latent * (m / t.bc1) / (__builtin_sqrtf(v / t.bc2) + 1e-8f);
+                t.latents[q] = zq[j] - t.lr_latent * (m / t.bc1) / (__builtin_sqrtf(v / t.bc2) + 1e-8f);
             }
         }
         __syncthreads();
+    };
+    read_idx(s0, A);
+    read_idx(s0 + S, B);
+    read_group(A);
+    for (int64_t sb = s0; sb < s1; sb += 2 * S) {
+        step(sb, A, B);
+        if (sb + S < s1)
+            step(sb + S, B, A);
     }
     // per-wavefront partial gradients in the packed layout, then the loss
     float *out = partials + (int64_t)blockIdx.x * (P.n + 1);
