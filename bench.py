@@ -429,7 +429,7 @@ def texture_bench(args, res):
     q1 = inputs.queries_uniform(4096, seed=2)
     tex1 = sf.Texture2D([src])
     qd1 = torch.from_numpy(q1).cuda()
-    judge1 = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.BSPLINE3, oracle.AFTER, shade=1)
+    ref1 = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.BSPLINE3, oracle.AFTER, shade=1)
     c1 = {"queries": 4096}
     for name, filt, mode, spp in (("bicubic_stochastic_16spp", sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 16),
                                   ("bilinear_stochastic_16spp", sf.SF_LINEAR, sf.SF_STOCHASTIC, 16),
@@ -440,9 +440,9 @@ def texture_bench(args, res):
         t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
         c1[name] = {"ms": t, "queries_per_s": 4096 / (t * 1e-3)}
         if filt == sf.SF_BSPLINE3:
-            c1[name]["rmse_vs_oracle_bicubic_after"] = _rmse(o.cpu().numpy(), judge1)
+            c1[name]["rmse_vs_oracle_bicubic_after"] = _rmse(o.cpu().numpy(), ref1)
     # interpolating Keys cubic: positivised stochastic (two taps per sample) vs all 16 taps
-    judge1k = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.KEYS3, oracle.AFTER, shade=1)
+    ref1k = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.KEYS3, oracle.AFTER, shade=1)
     for name, mode, spp in (("keys_positivised_stochastic_16spp", sf.SF_STOCHASTIC, 16),
                             ("keys_positivised_stochastic_1spp", sf.SF_STOCHASTIC, 1),
                             ("keys_after_16tap", sf.SF_AFTER_EXACT, 1)):
@@ -450,9 +450,9 @@ def texture_bench(args, res):
         o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
         t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
         c1[name] = {"ms": t, "queries_per_s": 4096 / (t * 1e-3),
-                    "rmse_vs_oracle_keys_after": _rmse(o.cpu().numpy(), judge1k)}
+                    "rmse_vs_oracle_keys_after": _rmse(o.cpu().numpy(), ref1k)}
     # Mitchell-Netravali cubic (B = C = 1/3): positivised by per-tap sign vs all 16 taps
-    judge1m = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.MITCHELL, oracle.AFTER, shade=1)
+    ref1m = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.MITCHELL, oracle.AFTER, shade=1)
     for name, mode, spp in (("mitchell_positivised_stochastic_16spp", sf.SF_STOCHASTIC, 16),
                             ("mitchell_positivised_stochastic_1spp", sf.SF_STOCHASTIC, 1),
                             ("mitchell_after_16tap", sf.SF_AFTER_EXACT, 1)):
@@ -460,23 +460,23 @@ def texture_bench(args, res):
         o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
         t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
         c1[name] = {"ms": t, "queries_per_s": 4096 / (t * 1e-3),
-                    "rmse_vs_oracle_mitchell_after": _rmse(o.cpu().numpy(), judge1m)}
+                    "rmse_vs_oracle_mitchell_after": _rmse(o.cpu().numpy(), ref1m)}
     # Gaussian by FRS (4x4 window) and by FIS (Box-Muller + nearest), and the
     # cubic B-spline by FIS (sum of three uniforms): RMSE against each
     # filter's own exact filter-after value, 16 samples per query
     for sigma in (0.3, 0.5, 0.8):
         for fname, filt, ofilt in (("gauss_frs", sf.SF_GAUSS_FRS, oracle.GAUSS_FRS),
                                    ("gauss_fis", sf.SF_GAUSS_FIS, oracle.GAUSS_FIS)):
-            judge = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, ofilt, oracle.AFTER, shade=1, sigma=sigma)
+            ref_after = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, ofilt, oracle.AFTER, shade=1, sigma=sigma)
             smp = sf.sampling(filt, sf.SF_STOCHASTIC, 16, seed=5, sigma=sigma)
             o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
             t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
             c1[f"{fname}_sigma{sigma}_stochastic_16spp"] = {"ms": t, "rmse_vs_oracle_own_after": _rmse(o.cpu().numpy(),
-                                                                                                    judge)}
+                                                                                                    ref_after)}
     smp = sf.sampling(sf.SF_BSPLINE3_FIS, sf.SF_STOCHASTIC, 16, seed=5)
     o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
     t = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
-    c1["bicubic_fis_stochastic_16spp"] = {"ms": t, "rmse_vs_oracle_bicubic_after": _rmse(o.cpu().numpy(), judge1)}
+    c1["bicubic_fis_stochastic_16spp"] = {"ms": t, "rmse_vs_oracle_bicubic_after": _rmse(o.cpu().numpy(), ref1)}
     res["config1"] = c1
     # ---- config 2
     log("config 2: pyramid and camera")
@@ -489,9 +489,9 @@ def texture_bench(args, res):
     buf, offs = inputs.pack_levels(lv)
     otex = oracle.Tex2D(buf, 4096, 4096, len(lv), oracle.RGBA8, offs, oracle.REPEAT, oracle.MIP_LINEAR)
     sub = np.sort(rng.choice(n2, 20000, replace=False))
-    judge2 = oracle.filter2d(otex, q2, oracle.BSPLINE3, oracle.AFTER, shade=1, subset=sub)
-    judge2k = oracle.filter2d(otex, q2, oracle.KEYS3, oracle.AFTER, shade=1, subset=sub)
-    judge2m = oracle.filter2d(otex, q2, oracle.MITCHELL, oracle.AFTER, shade=1, subset=sub)
+    ref2 = oracle.filter2d(otex, q2, oracle.BSPLINE3, oracle.AFTER, shade=1, subset=sub)
+    ref2k = oracle.filter2d(otex, q2, oracle.KEYS3, oracle.AFTER, shade=1, subset=sub)
+    ref2m = oracle.filter2d(otex, q2, oracle.MITCHELL, oracle.AFTER, shade=1, subset=sub)
     c2 = {"queries": n2, "texture_bytes": int(buf.size)}
     for name, tex, filt, mode, spp in (
             ("bicubic_stochastic_1spp", tex2, sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1),
@@ -524,11 +524,11 @@ def texture_bench(args, res):
         algo = n2 * (taps * 4 + 12 + 12)
         c2[name] = {"ms": t, "queries_per_s": n2 / (t * 1e-3), "texel_reads_per_query": taps,
                     "algorithmic_gbs": algo / (t * 1e-3) / 1e9,
-                    "rmse_vs_oracle_bicubic_trilinear_after": _rmse(o.cpu().numpy()[sub], judge2)}
+                    "rmse_vs_oracle_bicubic_trilinear_after": _rmse(o.cpu().numpy()[sub], ref2)}
         if filt == sf.SF_KEYS3:
-            c2[name]["rmse_vs_oracle_keys_trilinear_after"] = _rmse(o.cpu().numpy()[sub], judge2k)
+            c2[name]["rmse_vs_oracle_keys_trilinear_after"] = _rmse(o.cpu().numpy()[sub], ref2k)
         if filt == sf.SF_MITCHELL:
-            c2[name]["rmse_vs_oracle_mitchell_trilinear_after"] = _rmse(o.cpu().numpy()[sub], judge2m)
+            c2[name]["rmse_vs_oracle_mitchell_trilinear_after"] = _rmse(o.cpu().numpy()[sub], ref2m)
     t0 = time.perf_counter()
     oracle.filter2d(otex, q2, oracle.BSPLINE3, oracle.STOCHASTIC, spp=16, seed=5, shade=1, subset=sub)
     dt = time.perf_counter() - t0
@@ -546,7 +546,7 @@ def texture_bench(args, res):
     otd = oracle.Tex2D.dct(lv, wrap=oracle.REPEAT, mip=oracle.MIP_LINEAR)
     cd = {"compressed_bytes": int(texd.buffer.numel()), "rgba8_bytes": int(buf.size), "encode_ms": t_enc,
           "codes_equal_oracle": bool(np.array_equal(texd.buffer.cpu().numpy()[:otd.buf.size], otd.buf))}
-    judged = oracle.filter2d(otd, q2, oracle.LINEAR, oracle.BEFORE, shade=1, subset=sub)
+    refd = oracle.filter2d(otd, q2, oracle.LINEAR, oracle.BEFORE, shade=1, subset=sub)
     for name, filt, mode in (("dct_trilinear_before_8decodes", sf.SF_LINEAR, sf.SF_BEFORE),
                              ("dct_trilinear_stochastic_1spp", sf.SF_LINEAR, sf.SF_STOCHASTIC),
                              ("dct_bicubic_after_32decodes", sf.SF_BSPLINE3, sf.SF_AFTER_EXACT),
@@ -555,14 +555,14 @@ def texture_bench(args, res):
         o = torch.empty((n2, 3), dtype=torch.float32, device="cuda")
         t = time_launches(lambda: sf.sf_filter2d(texd, qd2b, smp, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
         cd[name] = {"ms": t, "queries_per_s": n2 / (t * 1e-3),
-                    "rmse_vs_oracle_dct_trilinear_before": _rmse(o.cpu().numpy()[sub], judged)}
+                    "rmse_vs_oracle_dct_trilinear_before": _rmse(o.cpu().numpy()[sub], refd)}
     cd["stochastic_trilinear_speedup"] = (cd["dct_trilinear_before_8decodes"]["ms"] /
                                           cd["dct_trilinear_stochastic_1spp"]["ms"])
     qs = inputs.sphere_queries(1920, 1080, tex_size=4096, levels=len(lv))
     qsd = torch.from_numpy(qs).cuda()
     ns = qs.shape[0]
     subs = np.sort(rng.choice(ns, 5000, replace=False))
-    judget = oracle.triplanar(otd, qs, 1.0, 0, oracle.LINEAR, oracle.BEFORE, shade=1, subset=subs)
+    reft = oracle.triplanar(otd, qs, 1.0, 0, oracle.LINEAR, oracle.BEFORE, shade=1, subset=subs)
     ct = {"queries": ns}
     for name, pm, mode in (("blend_trilinear_before_24decodes", 0, sf.SF_BEFORE),
                            ("blend_trilinear_stochastic_3decodes", 0, sf.SF_STOCHASTIC),
@@ -572,7 +572,7 @@ def texture_bench(args, res):
         o = torch.empty((ns, 3), dtype=torch.float32, device="cuda")
         t = time_launches(lambda: sf.sf_triplanar(texd, qsd, smp, 1.0, pm, sf.SF_SHADE_GGX, g, out=o), 10, 3, torch)
         ct[name] = {"ms": t, "queries_per_s": ns / (t * 1e-3),
-                    "rmse_vs_oracle_blend_trilinear_before": _rmse(o.cpu().numpy()[subs], judget)}
+                    "rmse_vs_oracle_blend_trilinear_before": _rmse(o.cpu().numpy()[subs], reft)}
     ct["fully_stochastic_speedup"] = (ct["blend_trilinear_before_24decodes"]["ms"] /
                                       ct["pick_trilinear_stochastic_1decode"]["ms"])
     cd["triplanar_sphere_1920x1080"] = ct
@@ -619,7 +619,7 @@ def neural_bench(args):
         "plain_after": lambda o: sf.sf_filter2d(tex, qd, sf.sampling(sf.SF_BSPLINE3, sf.SF_AFTER_EXACT, 1), sf.SF_SHADE_GGX, g, out=o),
     }
     sub = np.sort(rng.choice(nq, 20000, replace=False))
-    judge = oracle.filter2d(oracle.Tex2D.rgba32f(src), q, oracle.BSPLINE3, oracle.AFTER, shade=1, subset=sub)
+    ref_after = oracle.filter2d(oracle.Tex2D.rgba32f(src), q, oracle.BSPLINE3, oracle.AFTER, shade=1, subset=sub)
     c4 = {"training": {"epochs": args.epochs4, "batch": 65536, "steps": args.epochs4 * 16, "ms": ms_train,
                        "loss_first_epoch": l_first, "loss_last_epoch": l_last,
                        "rmse_decoded_vs_targets": float(torch.sqrt(torch.mean((fit - targets) ** 2)))},
@@ -627,7 +627,7 @@ def neural_bench(args):
     for name, fn in runs.items():
         o = torch.empty((nq, 3), dtype=torch.float32, device="cuda")
         t = time_launches(lambda: fn(o), 10, 3, torch)
-        c4[name] = {"ms": t, "queries_per_s": nq / (t * 1e-3), "rmse_vs_oracle_plain_after": _rmse(o.cpu().numpy()[sub], judge)}
+        c4[name] = {"ms": t, "queries_per_s": nq / (t * 1e-3), "rmse_vs_oracle_plain_after": _rmse(o.cpu().numpy()[sub], ref_after)}
         if name.startswith("neural"):
             dec = nq * (1 if "stochastic" in name else 16)
             c4[name]["decodes_per_s"] = dec / (t * 1e-3)
@@ -679,8 +679,8 @@ def neural_bench(args):
     hit = int((rays[:, 7] > rays[:, 6]).sum())
     sub = np.nonzero(rays[:, 7] > rays[:, 6])[0]
     sub = np.sort(rng.choice(sub, 1500, replace=False))
-    log("config 5: oracle judge on the 1024^3 grid")
-    judge = oracle.raymarch(oracle.Grid(src3.cpu().numpy(), side=side), rays, steps, oracle.BSPLINE3, oracle.AFTER,
+    log("config 5: oracle filter-after reference on the 1024^3 grid")
+    ref_after = oracle.raymarch(oracle.Grid(src3.cpu().numpy(), side=side), rays, steps, oracle.BSPLINE3, oracle.AFTER,
                             subset=sub)
     c5 = {"training": {"epochs": args.epochs5, "batch": 262144, "steps": args.epochs5 * 64, "ms": ms_train,
                        "loss_first_epoch": l_first, "loss_last_epoch": l_last, "sigma_scale": sigma_max,
@@ -695,7 +695,7 @@ def neural_bench(args):
                      ("plain256_stochastic_equal_lattice", lambda: sf.sf_raymarch(v256, rd, steps, smp, T=T))):
         t = time_launches(fn, 5, 2, torch)
         c5[name] = {"ms": t, "ray_steps_per_s": hit * steps / (t * 1e-3),
-                    "rmse_vs_oracle_plain1024_after": _rmse(T.cpu().numpy()[sub], judge)}
+                    "rmse_vs_oracle_plain1024_after": _rmse(T.cpu().numpy()[sub], ref_after)}
         if name.startswith("neural"):
             c5[name]["decodes_per_s"] = hit * steps / (t * 1e-3)
             c5[name]["mfma_useful_tflops"] = hit * steps * MLP_FLOP[(16, 1)] / (t * 1e-3) / 1e12
@@ -730,8 +730,8 @@ def main():
                     help="first run one device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the path is single-GPU (rays are independent; sharding is "
-              f"a split of the ray stream, described in DESIGN.md). --gpus {args.gpus} is not supported.",
+        print(f"bench.py runs on one GPU only: the path is single-GPU (rays are independent, so more GPUs "
+              f"would each march a contiguous share of the ray stream). --gpus {args.gpus} is not supported.",
               file=sys.stderr)
         sys.exit(2)
     if args.suite_aniso or args.suite_planck:

@@ -328,7 +328,7 @@ def test_filter2d_nonlinear_gap(orc):
 @pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("shade", [0, 1])
 def test_filter2d_expectation_equals_after(orc, filt, shade):
-    """The benchmark spec pin: the stochastic estimator's exact expectation (exact
+    """Unbiasedness (Sec. 2.2): the stochastic estimator's exact expectation (exact
     pick probabilities of the 24-bit uniforms) equals the exact filtering
     after shading value, within sum |P - w| * max|shade|."""
     T = orc.Tex2D.rgba32f(inputs.texture_uniform(4, seed=9))
