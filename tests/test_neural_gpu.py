@@ -138,6 +138,39 @@ def test_neural_filter2d_parity(sf, orc, filt, mode, spp, fmt, shade):
     _close_bf16(out, ref)
 
 
+@pytest.mark.parametrize("mode", ["STOCHASTIC", "AFTER"])
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_neural_filter2d_many_tiles(sf, orc, mode, fmt):
+    """More queries than one pass of the decoder's capped grid holds (2048
+    workgroups of 256): every workgroup walks several query tiles.  3000
+    sampled queries, the ragged last tile among them, against the oracle
+    (taps bit-exact)."""
+    _case("neural_filter2d_many_tiles", mode, fmt)
+    res = (64, 48)
+    grid, Z = _grid(sf, orc, 2, res, 8, fmt, seed=8)
+    P = _params(8, 4, 9)
+    mlp = sf.MLP(torch.from_numpy(P).cuda(), 8, 4)
+    n = 2 * 2048 * 256 + 777
+    q = inputs.queries_uniform(n, seed=19)
+    rng = np.random.default_rng(3)
+    sub = np.unique(np.concatenate([rng.choice(n - 1000, 2000, replace=False), np.arange(n - 1000, n)]))
+    f = sf.SF_BSPLINE3
+    m = sf.SF_STOCHASTIC if mode == "STOCHASTIC" else sf.SF_AFTER_EXACT
+    smp = sf.sampling(f, m, 1, seed=13)
+    taps = torch.empty((n, 1, 2), dtype=torch.int32, device="cuda") if mode == "STOCHASTIC" else None
+    out = sf.sf_neural_decode(grid, mlp, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx(),
+                              dbg_taps=taps).cpu().numpy()
+    om = orc.STOCHASTIC if mode == "STOCHASTIC" else orc.AFTER
+    res_ = orc.neural_filter2d(res, 8, H, 4, Z, _bf16(P), q, orc.BSPLINE3, om, spp=1, seed=13, shade=1,
+                               act_bf16=True, taps=mode == "STOCHASTIC", subset=sub)
+    if mode == "STOCHASTIC":
+        ref, rt = res_
+        assert np.array_equal(taps.cpu().numpy()[sub], rt)
+    else:
+        ref = res_
+    _close_bf16(out[sub], ref)
+
+
 @pytest.mark.parametrize("filt", ["LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("fmt", [1, 2])
 def test_neural_raymarch_parity(sf, orc, filt, fmt):
@@ -168,14 +201,16 @@ def _normwise(a, b):
     return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30)
 
 
-@pytest.mark.parametrize("C, O", [(8, 4), (16, 1)])
-def test_train_step_parity(sf, orc, C, O):
+@pytest.mark.parametrize("C, O, B", [(8, 4, 700), (16, 1, 700), (8, 4, 690), (16, 1, 32769)])
+def test_train_step_parity(sf, orc, C, O, B):
     """Gradients of one step (FP32 GPU) vs the FP64 oracle at the same
     inputs; the Adam updates follow from the GPU's own gradients; latents
-    outside the batch are untouched."""
-    _case("train_step", C, O)
+    outside the batch are untouched.  Batch 690 leaves one chunk with an odd
+    number of two-sample groups; batch 32769 makes 17-sample chunks and
+    leaves the last workgroups without samples."""
+    _case("train_step", C, O, B)
     rng = np.random.default_rng(20)
-    nlat, B = 2000, 700
+    nlat = max(2000, B + 1000)
     lat = rng.normal(size=(nlat, C)).astype(np.float32)
     P = _params(C, O, 21, scale=0.2)
     targets = rng.uniform(0, 1, size=(nlat, O)).astype(np.float32)
