@@ -126,19 +126,20 @@ def cpu_baseline(grid_host, rays, seed, max_rays):
                       f"{dt:.2f} s wall on {oracle.num_threads()} threads"}
 
 
-def traffic_from_profile(source_digest):
+def traffic_from_profile(code_digest):
     """HBM bytes per launch measured by rocprofv3 FETCH_SIZE + WRITE_SIZE
     (scaled by the plain-copy calibration), read from the committed profile
-    summary; None if the kernel source changed since it was taken."""
+    summary; None if the timed kernel's machine code differs from the code
+    the counters were taken on."""
     path = os.path.join(ROOT, "profiles", "raymarch_stochastic_tricubic_512cloud_pmc.md")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or code_digest is None:
         return None
     fields = {}
     for line in open(path):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    if fields.get("kernel_source_sha256") != source_digest:
+    if fields.get("kernel_code_sha256") != code_digest:
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -190,17 +191,63 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     return 2 * nbytes / t / 1e9
 
 
-def kernel_source_digest():
+# The timed kernel: stochastic cubic B-spline, binary16 grid, independent
+# uniforms, no tap dump, occupancy mask, power-of-two addressing.
+TIMED_KERNEL = "_ZN3sfk11k_ray_stochILi2ELb1ELi0ELb0ELb1ELb1EEEvNS_12RaymarchCallEj"
+
+
+def kernel_code_digest(lib_path=None, name=TIMED_KERNEL):
+    """SHA-256 of a kernel's machine code in the built library: the bytes of
+    its function in the gfx950 code objects of libsf.so's offload bundles,
+    then its kernel descriptor with the code-entry offset (bytes 16..23,
+    which moves with the layout of other code) zeroed.  None if not found."""
     import hashlib
-    h = hashlib.sha256()
-    for f in ("sf_device.hpp", "sf_internal.hpp", "volume.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2407_06107_amd", "csrc", f), "rb").read())
-    return h.hexdigest()
-
-
-# ---------------------------------------------------------------- neural (configs 4 and 5)
-MLP_FLOP = {(8, 4): 2 * (8 * 64 + 64 * 64 + 64 * 4), (16, 1): 2 * (16 * 64 + 64 * 64 + 64)}
-MFMA_BF16_PEAK_TFLOPS = 2500.0
+    import struct
+    if lib_path is None:
+        lib_path = os.path.join(ROOT, "paper_2407_06107_amd", "libsf.so")
+    if not os.path.exists(lib_path):
+        return None
+    data = open(lib_path, "rb").read()
+    i = 0
+    while True:
+        i = data.find(b"__CLANG_OFFLOAD_BUNDLE__", i)
+        if i < 0:
+            return None
+        nent = struct.unpack_from("<Q", data, i + 24)[0]
+        off = i + 32
+        for _ in range(nent):
+            eo, es, tl = struct.unpack_from("<QQQ", data, off)
+            triple = data[off + 24:off + 24 + tl].decode()
+            off += 24 + tl
+            if "amdgcn" not in triple or not es:
+                continue
+            elf = data[i + eo:i + eo + es]
+            shoff = struct.unpack_from("<Q", elf, 0x28)[0]
+            shentsize, shnum = struct.unpack_from("<HH", elf, 0x3A)
+            secs = [struct.unpack_from("<IIQQQQIIQQ", elf, shoff + k * shentsize) for k in range(shnum)]
+            symtabs = [sec for sec in secs if sec[1] == 2]       # SHT_SYMTAB
+            if not symtabs:
+                continue
+            st = symtabs[0]
+            strtab = secs[st[6]]
+            syms = {}
+            for k in range(st[5] // 24):
+                nm, _, _, shndx, val, size = struct.unpack_from("<IBBHQQ", elf, st[4] + 24 * k)
+                o = strtab[4] + nm
+                syms[elf[o:elf.index(b"\0", o)].decode()] = (shndx, val, size)
+            if name not in syms or name + ".kd" not in syms:
+                continue
+            h = hashlib.sha256()
+            for sym, zero in ((name, None), (name + ".kd", (16, 24))):
+                shndx, val, size = syms[sym]
+                sec = secs[shndx]
+                start = sec[4] + (val - sec[3])
+                blob = bytearray(elf[start:start + size])
+                if zero:
+                    blob[zero[0]:zero[1]] = bytes(zero[1] - zero[0])
+                h.update(blob)
+            return h.hexdigest()
+        i += 24
 
 
 def _init_mlp(rng, C, O):
@@ -802,7 +849,7 @@ def main():
     achieved_gbs = algo_bytes / (ms * 1e-3) / 1e9
     algo_ops = hit_steps * (OPS_POSITION + OPS_BRICK) + occ_steps * OPS_OCCUPIED
     achieved_tops = algo_ops / (ms * 1e-3) / 1e12
-    traffic = traffic_from_profile(kernel_source_digest())
+    traffic = traffic_from_profile(kernel_code_digest())
 
     extra = {}
     if not args.no_compare:

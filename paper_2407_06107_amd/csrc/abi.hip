@@ -137,7 +137,7 @@ sf_status ggx_constants(const sf_ggx *g, sfk::GgxConst &c)
     c.no2 = (float)(no * no);
     c.ni = (float)ni;
     c.ni2 = (float)(ni * ni);
-    c.spec_k = (float)(F / (4.0 * no * ni * pi));
+    c.spec_c = (float)(F / pi);
     for (int k = 0; k < 3; ++k) {
         c.kd[k] = (float)(g->radiance[k] * ni / pi);
         c.ks[k] = (float)(g->radiance[k] * ni);

@@ -498,6 +498,10 @@ __device__ __forceinline__ int ray_setup_dev(const float *wmin, const float *sca
 // ----------------------------------------------------------------- shading
 // GGX + Lambert times the cosine for the fixed directions folded into g
 // (the texel supplies albedo RGB and the roughness parameter A).
+// With G1(c) = 2c / (c + sqrt(a^2 + (1 - a^2) c^2)) the specular term
+// D G1(no) G1(ni) F / (4 no ni) is a^2 (F/pi) / ((no + s_o)(ni + s_i) d^2):
+// one reciprocal.  Shaded values decide nothing, so the hardware reciprocal
+// and square root (about 1 ulp each) serve; the result is within a few ulp.
 __device__ __forceinline__ float3 shade_ggx_dev(const GgxConst &g, float4 c)
 {
     const float r = __builtin_fmaf(g.r_scale, c.w, g.r_bias);
@@ -505,9 +509,10 @@ __device__ __forceinline__ float3 shade_ggx_dev(const GgxConst &g, float4 c)
     const float a2 = a * a;
     const float d = __builtin_fmaf(g.nh2, a2 - 1.0f, 1.0f);
     const float om = 1.0f - a2;
-    const float go = (2.0f * g.no) / (g.no + __builtin_sqrtf(__builtin_fmaf(om, g.no2, a2)));
-    const float gi = (2.0f * g.ni) / (g.ni + __builtin_sqrtf(__builtin_fmaf(om, g.ni2, a2)));
-    const float spec = (a2 * go * gi * g.spec_k) / (d * d);
+    const float so = __builtin_amdgcn_sqrtf(__builtin_fmaf(om, g.no2, a2));
+    const float si = __builtin_amdgcn_sqrtf(__builtin_fmaf(om, g.ni2, a2));
+    const float den = ((g.no + so) * (g.ni + si)) * (d * d);
+    const float spec = (a2 * g.spec_c) * __builtin_amdgcn_rcpf(den);
     return make_float3(__builtin_fmaf(g.kd[0], c.x, g.ks[0] * spec), __builtin_fmaf(g.kd[1], c.y, g.ks[1] * spec),
                        __builtin_fmaf(g.kd[2], c.z, g.ks[2] * spec));
 }

@@ -13,7 +13,7 @@ namespace sfk {
 // on the texel, only the roughness does.
 struct GgxConst {
     float nh2, no, no2, ni, ni2;
-    float spec_k;          // F / (4 (n.wo)(n.wi) pi)
+    float spec_c;          // F / pi
     float kd[3], ks[3];    // radiance * (n.wi) / pi, radiance * (n.wi)
     float r_bias, r_scale;
     // normal-mapped shading: h, wo, wi in the tangent frame (e1, e2, n) of

@@ -473,3 +473,18 @@ def test_neural_raymarch_and_train_validation(sf):
     assert L.sf_neural_train_step(C.byref(st), FAKE, FAKE, 50, 0, 1e-2, 1e-3, FAKE, None, None, FAKE, ws, None) == 2
     st.hidden = 32
     assert L.sf_neural_train_step(C.byref(st), *args, ws, None) == 3
+
+
+def test_timed_kernel_code_digest(sf):
+    """bench.py keys the measured HBM traffic to the timed kernel's machine
+    code: its digest is found in the built library (function bytes and
+    kernel descriptor of the gfx950 code object)."""
+    import importlib.util
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_for_test", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    d = bench.kernel_code_digest()
+    assert d is not None and len(d) == 64 and int(d, 16) >= 0
+    assert bench.kernel_code_digest(name=bench.TIMED_KERNEL + "_absent") is None
