@@ -250,6 +250,11 @@ def kernel_code_digest(lib_path=None, name=TIMED_KERNEL):
         i += 24
 
 
+# ---------------------------------------------------------------- neural (configs 4 and 5)
+MLP_FLOP = {(8, 4): 2 * (8 * 64 + 64 * 64 + 64 * 4), (16, 1): 2 * (16 * 64 + 64 * 64 + 64)}
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
 def _init_mlp(rng, C, O):
     """He-normal weights, zero biases, packed W1 b1 W2 b2 W3 b3."""
     parts = []
