@@ -15,6 +15,7 @@
 //    columns of one v_mfma_f32_16x16x32_bf16 tile with hidden units as rows,
 //    so one layer's accumulators are, lane for lane, the next layer's B
 //    operand (the weights' K order is permuted to match, see kperm()).
+#include <algorithm>
 #include <type_traits>
 
 #include "sf_device.hpp"
@@ -734,10 +735,9 @@ __device__ __forceinline__ void neural2d_query(const NeuralCall &c, const MlpFra
 }
 
 // The MLP's fragments are loaded into registers once per workgroup, which
-// then walks the query stream in tiles of 256 (a grid of at most
-// N2D_MAX_BLOCKS workgroups), so their load is spread over several tiles.
-// The tile base is uniform over the workgroup.
-constexpr uint32_t N2D_MAX_BLOCKS = 2048;
+// then walks the query stream in tiles of 256 (a grid of as many
+// workgroups as the device holds at once), so their load is spread over
+// several tiles.  The tile base is uniform over the workgroup.
 
 template <int F_, int SHADE, int MODE, int FMT>
 __global__ __launch_bounds__(256) void k_neural2d(NeuralCall c)
@@ -958,15 +958,34 @@ int train_reduce_chunks(int nparts) { return (nparts + REDUCE_CHUNK - 1) / REDUC
 
 int train_nparams(int C, int O) { return POff(C, O).n; }
 
+// Workgroups of 256 lanes of kernel K resident on the current device at
+// once (occupancy x compute units), at least 1.
+template <typename K>
+static int64_t resident_blocks(K kernel)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess)
+        return 1024;
+    return std::max<int64_t>(1, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
+}
+
+template <int F_, int SHADE, int MODE, int FMT>
+static void launch_n2_k(const NeuralCall &c, hipStream_t s)
+{
+    static const int64_t resident = resident_blocks(k_neural2d<F_, SHADE, MODE, FMT>);
+    const int64_t tiles = (c.n + 255) / 256;
+    k_neural2d<F_, SHADE, MODE, FMT><<<dim3((uint32_t)std::min(tiles, resident)), dim3(256), 0, s>>>(c);
+}
+
 template <int F_, int SHADE, int MODE>
 static void launch_n2_m(const NeuralCall &c, hipStream_t s)
 {
-    const int64_t tiles = (c.n + 255) / 256;
-    dim3 grid((uint32_t)(tiles < (int64_t)N2D_MAX_BLOCKS ? tiles : (int64_t)N2D_MAX_BLOCKS)), block(256);
     if (c.lat.fmt == SF_LATENT_BF16)
-        k_neural2d<F_, SHADE, MODE, SF_LATENT_BF16><<<grid, block, 0, s>>>(c);
+        launch_n2_k<F_, SHADE, MODE, SF_LATENT_BF16>(c, s);
     else
-        k_neural2d<F_, SHADE, MODE, SF_LATENT_FP8E4M3><<<grid, block, 0, s>>>(c);
+        launch_n2_k<F_, SHADE, MODE, SF_LATENT_FP8E4M3>(c, s);
 }
 
 template <int F_, int SHADE>

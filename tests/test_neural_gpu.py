@@ -141,10 +141,10 @@ def test_neural_filter2d_parity(sf, orc, filt, mode, spp, fmt, shade):
 @pytest.mark.parametrize("mode", ["STOCHASTIC", "AFTER"])
 @pytest.mark.parametrize("fmt", [1, 2])
 def test_neural_filter2d_many_tiles(sf, orc, mode, fmt):
-    """More queries than one pass of the decoder's capped grid holds (2048
-    workgroups of 256): every workgroup walks several query tiles.  3000
-    sampled queries, the ragged last tile among them, against the oracle
-    (taps bit-exact)."""
+    """More queries than one pass of the decoder's grid holds (as many
+    workgroups of 256 as the device keeps resident, far below 2048 x 2):
+    every workgroup walks several query tiles.  3000 sampled queries, the
+    ragged last tile among them, against the oracle (taps bit-exact)."""
     _case("neural_filter2d_many_tiles", mode, fmt)
     res = (64, 48)
     grid, Z = _grid(sf, orc, 2, res, 8, fmt, seed=8)
