@@ -435,11 +435,16 @@ __global__ __launch_bounds__(256) void k_train_reduce(TrainCall t, int nchunks, 
 // Lane l of a 16x16x32 tile: column n = l % 16, K block g = l / 16 (8 K values
 // for A and B), accumulator rows 4g..4g+3.  Hidden unit at K position
 // 8g + j of K step ks: two accumulator tiles (2ks, 2ks+1) interleaved.
+// Layer 1 (C = 8 or 16 inputs) uses the 16x16x16 tile: K block g holds the
+// 4 input channels 4g..4g+3, the accumulator layout is the same.
 __device__ __forceinline__ int kperm(int ks, int g, int j) { return 16 * (2 * ks + (j >> 2)) + 4 * g + (j & 3); }
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 template <int C, int O>
 struct MlpFrags {
-    bf16x8 a1[4], a2[4][2], a3[2];
+    bf16x4 a1[4];
+    bf16x8 a2[4][2], a3[2];
     f32x4 b1[4], b2[4], b3;
 };
 
@@ -453,8 +458,8 @@ __device__ __forceinline__ void load_frags(const uint16_t *P, MlpFrags<C, O> &F)
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int c = 8 * g + j;
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * g + j;
             F.a1[m][j] = (__bf16)(c < C ? pbf(P, off.w1 + c * HID + 16 * m + n) : 0.0f);
         }
 #pragma unroll
@@ -506,15 +511,11 @@ __device__ __forceinline__ bf16x8 relu_pack(f32x4 lo, f32x4 hi)
     return __builtin_bit_cast(bf16x8, w);
 }
 
-// Eight OCP E4M3 codes (two words) -> bfloat16, exactly (an E4M3 value has 4
-// significant bits), through the packed FP8 conversion of the vector ALU.
-__device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint32_t lo, uint32_t hi)
+// Four OCP E4M3 codes (one word) -> bfloat16, exactly (4 significant bits).
+__device__ __forceinline__ bf16x4 fp8x4_to_bf16(uint32_t w)
 {
-    const f32x2 a0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)lo, false), a1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)lo, true);
-    const f32x2 b0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)hi, false), b1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)hi, true);
-    const uint4 w = make_uint4(pack_bf16(a0.x, a0.y), pack_bf16(a1.x, a1.y), pack_bf16(b0.x, b0.y),
-                               pack_bf16(b1.x, b1.y));
-    return __builtin_bit_cast(bf16x8, w);
+    const f32x2 a0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false), a1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+    return __builtin_bit_cast(bf16x4, make_uint2(pack_bf16(a0.x, a0.y), pack_bf16(a1.x, a1.y)));
 }
 
 // The MLP on the 16 samples whose latents (K block of this lane) are in zb;
@@ -523,19 +524,19 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint32_t lo, uint32_t hi)
 // as the accumulator, as layer 2's does.  Returns the layer-3 accumulators:
 // lanes 0..15 hold outputs 0..3 of sample (lane).
 template <int C, int O, bool SCALED>
-__device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x8 zb, float cs)
+__device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x4 zb, float cs)
 {
     f32x4 d1[4];
     const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         if constexpr (SCALED) {
-            d1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[m], zb, zero, 0, 0, 0);
+            d1[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.a1[m], zb, zero, 0, 0, 0);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 d1[m][j] = __builtin_fmaf(cs, d1[m][j], F.b1[m][j]);
         } else {
-            d1[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[m], zb, F.b1[m], 0, 0, 0);
+            d1[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.a1[m], zb, F.b1[m], 0, 0, 0);
         }
     }
     const bf16x8 h1a = relu_pack(d1[0], d1[1]), h1b = relu_pack(d1[2], d1[3]);
@@ -554,23 +555,23 @@ __device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x8 zb, float
 // This lane's K block of the latent of lattice point idx (zeros past C, or
 // for idx < 0); blk is the point's scale block (E4M3 latents).
 template <int C, int FMT>
-__device__ __forceinline__ bf16x8 latent_frag(const LatentArgs &g, int64_t idx, int blk, float &scale)
+__device__ __forceinline__ bf16x4 latent_frag(const LatentArgs &g, int64_t idx, int blk, float &scale)
 {
     const int kb = (threadIdx.x & 63) >> 4;
-    bf16x8 r;
+    bf16x4 r;
     scale = 1.0f;
-    if (8 * kb >= C || idx < 0) {
+    if (4 * kb >= C || idx < 0) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 4; ++j)
             r[j] = (__bf16)0.0f;
         return r;
     }
     if constexpr (FMT == SF_LATENT_BF16) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(g.latents) + idx * C + 8 * kb);
-        r = __builtin_bit_cast(bf16x8, v);
+        const uint2 v = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(g.latents) + idx * C + 4 * kb);
+        r = __builtin_bit_cast(bf16x4, v);
     } else {
-        const uint2 v = *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(g.latents) + idx * C + 8 * kb);
-        r = fp8x8_to_bf16(v.x, v.y);
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g.latents) + idx * C + 4 * kb);
+        r = fp8x4_to_bf16(v);
         scale = g.scales[blk];
     }
     return r;
@@ -585,7 +586,7 @@ __device__ __forceinline__ void decode_wave(const LatentArgs &g, const MlpFrags<
 {
     const int lane = threadIdx.x & 63;
     // the four groups' latents are gathered first, so their loads overlap
-    bf16x8 zb[4];
+    bf16x4 zb[4];
     float cs[4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(256) void k_decode_lattice(NeuralCall c, const int6
 // flight behind the matrix-core work.
 template <int FMT>
 struct StepLatents {
-    using Raw = typename std::conditional<FMT == SF_LATENT_BF16, uint4, uint2>::type;
+    using Raw = typename std::conditional<FMT == SF_LATENT_BF16, uint2, uint32_t>::type;
     Raw raw[4];
     float cs[4];
 };
@@ -794,15 +795,15 @@ __device__ __forceinline__ void issue_latents(const LatentArgs &g, int64_t idx, 
     for (int G = 0; G < 4; ++G) {
         const int src = 16 * G + (lane & 15);
         const int64_t sidx = ((int64_t)__shfl((int)(idx >> 32), src) << 32) | (uint32_t)__shfl((int)idx, src);
-        const bool use = 8 * kb < C && sidx >= 0;
+        const bool use = 4 * kb < C && sidx >= 0;
         L.cs[G] = 1.0f;
         if constexpr (FMT == SF_LATENT_BF16) {
-            L.raw[G] = use ? *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(g.latents) + sidx * C + 8 * kb)
-                           : make_uint4(0u, 0u, 0u, 0u);
+            L.raw[G] = use ? *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(g.latents) + sidx * C + 4 * kb)
+                           : make_uint2(0u, 0u);
         } else {
             const int sblk = __shfl(blk, src);
-            L.raw[G] = use ? *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(g.latents) + sidx * C + 8 * kb)
-                           : make_uint2(0u, 0u);
+            L.raw[G] = use ? *reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g.latents) + sidx * C + 4 * kb)
+                           : 0u;
             if (sidx >= 0)
                 L.cs[G] = g.scales[sblk];   // the scale of this lane's column
         }
@@ -810,12 +811,12 @@ __device__ __forceinline__ void issue_latents(const LatentArgs &g, int64_t idx, 
 }
 
 template <int FMT>
-__device__ __forceinline__ bf16x8 latents_bf16(const typename StepLatents<FMT>::Raw &v)
+__device__ __forceinline__ bf16x4 latents_bf16(const typename StepLatents<FMT>::Raw &v)
 {
     if constexpr (FMT == SF_LATENT_BF16) {
-        return __builtin_bit_cast(bf16x8, v);
+        return __builtin_bit_cast(bf16x4, v);
     } else {
-        return fp8x8_to_bf16(v.x, v.y);
+        return fp8x4_to_bf16(v);
     }
 }
 
