@@ -841,9 +841,9 @@ __device__ __forceinline__ void decode_loaded(const MlpFrags<C, O> &F, const Ste
 // picked lattice point is decoded (sigma = max(MLP, 0)); taps outside the
 // lattice read zero and are not decoded.  Every lane walks the same number
 // of steps so the wavefront can batch its decodes on the matrix cores.
-template <int F_, int FMT, bool DBG>
 // Three wavefronts per SIMD (168 VGPRs, a few spills) overlap one
 // wavefront's vector work with another's matrix work better than two.
+template <int F_, int FMT, bool DBG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_neural_ray(NeuralCall c, uint32_t nb_pad)
 {
     constexpr int C = 16, O = 1;
