@@ -18,7 +18,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRCS = [_SRC, os.path.join(_HERE, "neural.c")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 selects a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (errors abort); the process must then preload the
+# compiler's libasan (a test runs the pins that way in a child process).
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 
 # enums of the oracle (its own copy; it does not include the library header)
 NEAREST, LINEAR, BSPLINE3, KEYS3, GAUSS_FRS, GAUSS_FIS, BSPLINE3_FIS, EWA, MITCHELL = 0, 1, 2, 3, 4, 5, 6, 7, 8
@@ -39,7 +44,8 @@ def build(force: bool = False) -> str:
     if force or stale:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-fvisibility=hidden", *_SRCS, "-o", tmp, "-lm"]
+               "-fno-fast-math", "-fvisibility=hidden", *(_SAN_FLAGS if _SANITIZE else []), *_SRCS, "-o", tmp,
+               "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB

@@ -605,3 +605,51 @@ def test_keys_stochastic_mean_and_texel_centres(orc):
     assert np.allclose(v[0], tex[5, 3], rtol=1e-14)
     assert np.all(taps[0, :, 1] == 3) and np.all(taps[0, :, 2] == 5) and np.all(taps[0, :, 3] == orc.TAP_NONE)
     del one
+
+
+def test_ggx_schlick_fresnel_off_normal(orc):
+    """Schlick's Fresnel factor away from normal incidence.  With zero albedo
+    the shaded value is proportional to F, so L(f0) / L(1) isolates
+    F(f0) / F(1) = f0 + (1 - f0)(1 - wi.h)^5 (Schlick 1994: the fifth power of
+    one minus the cosine between the light and the half vector).  The ratio
+    must not depend on the surface normal (only wi.h enters F), must be affine
+    in f0, and must reach 1 at grazing half-angles (wo nearly opposite wi).
+    A wrong exponent, or n.wi / n.h in place of wi.h, fails one of these."""
+    rng = np.random.default_rng(11)
+    alb = np.zeros(4)
+    alb[3] = 0.4
+
+    def ratio(n, wo, wi, f0):
+        a = orc.shade_ggx(orc.ggx_params(n=n, wo=wo, wi=wi, f0=f0), alb)[0]
+        b = orc.shade_ggx(orc.ggx_params(n=n, wo=wo, wi=wi, f0=1.0), alb)[0]
+        return a / b
+
+    for _ in range(40):
+        wo = rng.normal(size=3); wo[2] = abs(wo[2]) + 0.3
+        wi = rng.normal(size=3); wi[2] = abs(wi[2]) + 0.3
+        wo /= np.linalg.norm(wo); wi /= np.linalg.norm(wi)
+        h = (wo + wi) / np.linalg.norm(wo + wi)
+        c = float(wi @ h)
+        r0 = ratio((0, 0, 1), wo, wi, 0.0)
+        assert abs(r0 - (1.0 - c) ** 5) <= 1e-12 * max(1.0, r0), (c, r0)
+        # tilt the normal (keeping both directions above it): F is unchanged
+        n2 = np.array([0.1, -0.15, 1.0]) + 0.05 * rng.normal(size=3)
+        n2 /= np.linalg.norm(n2)
+        if min(n2 @ wo, n2 @ wi, n2 @ h) > 0.05:
+            assert abs(ratio(n2, wo, wi, 0.0) - r0) <= 1e-12 * max(1.0, r0)
+        for f0 in (0.04, 0.5, 0.9):
+            assert abs(ratio((0, 0, 1), wo, wi, f0) - (f0 + (1 - f0) * r0)) <= 1e-12
+    # grazing half-angles: wo and wi nearly opposite in the tangent plane
+    for eps in (0.3, 0.1, 0.03):
+        wo = np.array([1.0, 0.0, eps]); wi = np.array([-1.0, 0.02, eps])
+        wo /= np.linalg.norm(wo); wi /= np.linalg.norm(wi)
+        h = (wo + wi) / np.linalg.norm(wo + wi)
+        c = float(wi @ h)
+        r0 = ratio((0, 0, 1), wo, wi, 0.0)
+        assert c < 0.31 and abs(r0 - (1 - c) ** 5) < 1e-12
+        assert r0 > (1 - 0.31) ** 5
+    # closed values at a fixed geometry: wi.h = cos 30 deg (wo, wi 60 deg apart)
+    wo = np.array([math.sin(math.radians(30)), 0.0, math.cos(math.radians(30))])
+    wi = np.array([-math.sin(math.radians(30)), 0.0, math.cos(math.radians(30))])
+    r0 = ratio((0, 0, 1), wo, wi, 0.0)
+    assert abs(r0 - (1 - math.sqrt(3) / 2) ** 5) < 1e-15
