@@ -607,6 +607,28 @@ sf_status sf_error_stats(const float *est, const double *ref, int64_t n, int32_t
                          void *workspace, size_t workspace_bytes, void *stream);
 size_t sf_error_stats_workspace(int64_t count);
 
+/*
+ * sf_error_stats_noalloc — sf_error_stats for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and the same result, bit for bit,
+ * with the reduction's partial rows kept in a static device array of the
+ * library instead of a caller workspace.  It calls no hipMalloc / hipFree and
+ * no allocating library routine.
+ *   est, ref, n, ch, out, stream: as sf_error_stats (device pointers, owned by
+ *   the caller).
+ *   Scratch: sf_error_stats_noalloc_max_bytes() bytes (64 KiB) per device,
+ *   taken on the first call on a device and held until the process ends.
+ *   Every call on one device shares that device's array: calls that overlap
+ *   on one device (two streams, two threads) race and give undefined results.
+ * Errors: SF_E_NULL, SF_E_RANGE (n < 0, ch < 1, n * ch overflowing, a call
+ * whose partial rows exceed the static scratch, misaligned pointers),
+ * SF_E_DEVICE (the scratch's device address cannot be found),
+ * SF_E_UNSUPPORTED (a device index of 64 or more).
+ */
+sf_status sf_error_stats_noalloc(const float *est, const double *ref, int64_t n, int32_t ch, double *out,
+                                 void *stream);
+size_t sf_error_stats_noalloc_max_bytes(void);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *sf_last_error(void);
 int32_t sf_abi_version(void);

@@ -36,7 +36,8 @@ EXPORTED = ("sf_filter2d", "sf_filter2d_aniso", "sf_dct_layout", "sf_dct_encode"
             "sf_filter3d", "sf_raymarch", "sf_raymarch_emission", "sf_build_occupancy",
             "sf_occupancy_words", "sf_mlp_nparams", "sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
             "sf_neural_quantize", "sf_neural_train_step", "sf_neural_train_workspace",
-            "sf_error_stats", "sf_error_stats_workspace", "sf_last_error", "sf_abi_version", "sf_rng_version")
+            "sf_error_stats", "sf_error_stats_workspace", "sf_error_stats_noalloc",
+            "sf_error_stats_noalloc_max_bytes", "sf_last_error", "sf_abi_version", "sf_rng_version")
 SF_LATENT_F32, SF_LATENT_BF16, SF_LATENT_FP8E4M3 = 0, 1, 2
 
 
@@ -125,6 +126,10 @@ def lib() -> C.CDLL:
         for f in ("sf_neural_decode", "sf_neural_raymarch", "sf_neural_decode_lattice", "sf_to_bf16",
                   "sf_neural_quantize", "sf_neural_train_step"):
             getattr(L, f).restype = i32
+        L.sf_error_stats_noalloc.argtypes = [P, P, i64, i32, P, P]
+        L.sf_error_stats_noalloc.restype = i32
+        L.sf_error_stats_noalloc_max_bytes.argtypes = []
+        L.sf_error_stats_noalloc_max_bytes.restype = C.c_size_t
         L.sf_error_stats_workspace.argtypes = [i64]
         L.sf_error_stats_workspace.restype = C.c_size_t
         for f in ("sf_filter2d", "sf_filter2d_aniso", "sf_dct_encode", "sf_triplanar", "sf_filter3d", "sf_raymarch",
@@ -440,6 +445,24 @@ def sf_error_stats(est: torch.Tensor, ref: torch.Tensor, out: torch.Tensor | Non
         workspace = torch.empty(max(1, sf_error_stats_workspace(count)), dtype=torch.uint8, device=est.device)
     _check(lib().sf_error_stats(_ptr(est), _ptr(ref), count, 1, _ptr(out), _ptr(workspace), workspace.numel(),
                                 _stream(stream)))
+    return out
+
+
+def sf_error_stats_noalloc_max_bytes() -> int:
+    return int(lib().sf_error_stats_noalloc_max_bytes())
+
+
+def sf_error_stats_noalloc(est: torch.Tensor, ref: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """sf_error_stats without a workspace: the library's static per-device
+    scratch holds the partial rows, so the call allocates nothing (the caller
+    passes `out`, 8 float64 on the device).  Calls that overlap on one device
+    race."""
+    _need(est, torch.float32, "est")
+    _need(ref, torch.float64, "ref")
+    if est.numel() != ref.numel():
+        raise ValueError("est and ref differ in size")
+    _need(out, torch.float64, "out", 8)
+    _check(lib().sf_error_stats_noalloc(_ptr(est), _ptr(ref), est.numel(), 1, _ptr(out), _stream(stream)))
     return out
 
 

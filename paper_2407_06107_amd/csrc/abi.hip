@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "sf_internal.hpp"
 
@@ -876,6 +877,75 @@ sf_status sf_error_stats(const float *est, const double *ref, int64_t n, int32_t
         return fail(SF_E_RANGE, "misaligned pointer");
     return device_status(
         sfk::launch_error_stats(est, ref, count, ch, out, (double *)workspace, err_blocks(count), (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+// Scratch of sf_error_stats_noalloc: the per-block partial rows of the
+// reduction, one copy per device, held until the process ends.  Every row
+// that the final pass reads is written by the first pass of the same call,
+// so nothing needs clearing between calls.
+namespace {
+
+constexpr int kNoallocRows = 1024;   // err_blocks() never asks for more
+static __device__ __align__(256) double scratch[kNoallocRows * 8];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's copy of `scratch`, looked up once per
+// device with that device current (the host-side name of the array is not a
+// device address).
+sf_status scratch_for_current_device(double **ptr)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return fail(SF_E_DEVICE, "hipGetDevice failed");
+    if (dev >= kMaxDevices)
+        return fail(SF_E_UNSUPPORTED, "device %d beyond the %d devices the static scratch supports", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SF_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return SF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sf_error_stats_noalloc_max_bytes(void) { return sizeof(scratch); }
+
+sf_status sf_error_stats_noalloc(const float *est, const double *ref, int64_t n, int32_t ch, double *out,
+                                 void *stream)
+{
+    if (n < 0 || ch < 1)
+        return fail(SF_E_RANGE, "n must be >= 0 and ch >= 1");
+    if (!out)
+        return fail(SF_E_NULL, "out must be non-NULL");
+    if (n > 0 && ch > INT64_MAX / n)
+        return fail(SF_E_RANGE, "n * ch overflows");
+    const int64_t count = n * (int64_t)ch;
+    if (count > 0 && (!est || !ref))
+        return fail(SF_E_NULL, "est and ref must be non-NULL");
+    const size_t need = sf_error_stats_workspace(count);
+    if (need > sizeof(scratch))
+        return fail(SF_E_RANGE, "this call needs %zu bytes of scratch, beyond the %zu bytes of the static scratch",
+                    need, sizeof(scratch));
+    if (!aligned(out, 8) || (ref && !aligned(ref, 8)) || (est && !aligned(est, 4)))
+        return fail(SF_E_RANGE, "misaligned pointer");
+    double *ws = nullptr;
+    const sf_status st = scratch_for_current_device(&ws);
+    if (st != SF_OK)
+        return st;
+    return device_status(
+        sfk::launch_error_stats(est, ref, count, ch, out, ws, err_blocks(count), (hipStream_t)stream));
 }
 
 }  // extern "C"

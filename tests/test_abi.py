@@ -377,6 +377,13 @@ def test_error_stats_validation(sf):
     assert L.sf_error_stats(FAKE, FAKE, 5000, 1, FAKE, FAKE, need - 8, None) == 5
     assert L.sf_error_stats(FAKE, FAKE, 5000, 0, FAKE, FAKE, need, None) == 2
     assert L.sf_error_stats(None, FAKE, 5000, 1, FAKE, FAKE, need, None) == 1
+    # the allocation-free variant validates the same way before touching a device
+    assert sf.sf_error_stats_noalloc_max_bytes() == 1024 * 64
+    assert L.sf_error_stats_noalloc(FAKE, FAKE, 5000, 0, FAKE, None) == 2
+    assert L.sf_error_stats_noalloc(FAKE, FAKE, -1, 1, FAKE, None) == 2
+    assert L.sf_error_stats_noalloc(FAKE, FAKE, 2 ** 62, 4, FAKE, None) == 2
+    assert L.sf_error_stats_noalloc(None, FAKE, 5000, 1, FAKE, None) == 1
+    assert L.sf_error_stats_noalloc(FAKE, FAKE, 5000, 1, None, None) == 1
 
 
 def test_product_path_has_no_fallback(sf, monkeypatch, tmp_path):
