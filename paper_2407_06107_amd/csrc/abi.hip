@@ -158,9 +158,13 @@ sf_status ggx_constants(const sf_ggx *g, sfk::GgxConst &c)
         ts[v][1] = (float)(e2[0] * x[0] + e2[1] * x[1] + e2[2] * x[2]);
         ts[v][2] = (float)(n[0] * x[0] + n[1] * x[1] + n[2] * x[2]);
     }
-    c.th[0] = e1[0] * h[0] + e1[1] * h[1] + e1[2] * h[2];
-    c.th[1] = e2[0] * h[0] + e2[1] * h[1] + e2[2] * h[2];
-    c.th[2] = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+    const double th[3] = {e1[0] * h[0] + e1[1] * h[1] + e1[2] * h[2], e2[0] * h[0] + e2[1] * h[1] + e2[2] * h[2],
+                          n[0] * h[0] + n[1] * h[1] + n[2] * h[2]};
+    for (int k = 0; k < 3; ++k) {
+        c.th[k] = (float)th[k];
+        c.thl[k] = (float)(th[k] - (double)c.th[k]);
+    }
+    c.th_defect = (float)(1.0 - (th[0] * th[0] + th[1] * th[1] + th[2] * th[2]));
     c.F = (float)F;
     for (int k = 0; k < 3; ++k) {
         c.rad[k] = g->radiance[k];

@@ -260,18 +260,20 @@ __global__ __launch_bounds__(256) void k_filter2d_det(Filter2DCall c)
     store<SHADE>(c.out, q, MODE == BEFORE ? shade<SHADE>(c.g, sum) : sum);
 }
 
-// Deterministic Gaussian comparators, binary64 weights and sums (the FIS
-// window has up to 60 x 60 taps): the discrete Gaussian's normalised
-// e^(-d^2 h) on the 4x4 window, or the FIS Gaussian's cell masses
+// Deterministic Gaussian comparators, binary32 weights and compensated sums
+// (the FIS window has up to 60 x 60 taps): the discrete Gaussian's
+// normalised e^(-d^2 h) on the 4x4 window, or the FIS Gaussian's cell masses
 // Phi((k + 1/2 - t)/sigma) - Phi((k - 1/2 - t)/sigma) on offsets -R..R+1,
-// R = ceil(7 sigma) + 1.
-__device__ __forceinline__ void gauss4(double t, double h, double w[4])
+// R = ceil(7 sigma) + 1, each mass taken from the tail on its own side of the
+// lookup point (erfc of a positive argument), so that no mass is the small
+// difference of two values near 1.
+__device__ __forceinline__ void gauss4(float t, float h, float w[4])
 {
-    double W = 0.0;
+    float W = 0.0f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double d = (double)(k - 1) - t;
-        w[k] = exp(-d * d * h);
+        const float d = (float)(k - 1) - t;
+        w[k] = expf(-((d * d) * h));
         W += w[k];
     }
 #pragma unroll
@@ -279,9 +281,12 @@ __device__ __forceinline__ void gauss4(double t, double h, double w[4])
         w[k] /= W;
 }
 
-__device__ __forceinline__ double gauss_cell(double r2, double t, int k)
+__device__ __forceinline__ float gauss_cell(float r2, float t, int k)
 {
-    return 0.5 * (erfc(((double)k - 0.5 - t) / r2) - erfc(((double)k + 0.5 - t) / r2));
+    const float a = ((float)k - 0.5f - t) / r2, b = ((float)k + 0.5f - t) / r2;
+    // right of the point: 0.5 (erfc(a) - erfc(b)); left: 0.5 (erfc(-b) - erfc(-a))
+    return a >= 0.0f ? 0.5f * (erfcf(a) - erfcf(b))
+                     : (b <= 0.0f ? 0.5f * (erfcf(-b) - erfcf(-a)) : 1.0f - 0.5f * (erfcf(-a) + erfcf(b)));
 }
 
 template <int F, int SHADE, int MODE>
@@ -300,15 +305,17 @@ __global__ __launch_bounds__(256) void k_filter2d_gauss_det(Filter2DCall c)
     int l0, l1;
     float f;
     levels_of(c.tex, qq.z, l0, l1, f);
-    const double sig = (double)c.sigma;
-    const double h = 0.5 / (sig * sig), r2 = 1.4142135623730951 * sig;
-    const int R = (int)ceil(7.0 * sig) + 1;
+    const float sig = c.sigma;
+    const float h = 0.5f / (sig * sig), r2 = 1.41421356f * sig;
+    const int R = (int)ceilf(7.0f * sig) + 1;
     const int first = F == GAUSS_FRS ? -1 : -R;
     const int ntap = F == GAUSS_FRS ? 4 : 2 * R + 2;
-    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    CompSum sum[4];
+    for (int k = 0; k < 4; ++k)
+        sum[k].init();
     for (int li = 0; li < 2; ++li) {
-        const double pl = li == 0 ? 1.0 - (double)f : (double)f;
-        if (pl == 0.0)
+        const float pl = li == 0 ? 1.0f - f : f;
+        if (pl == 0.0f)
             continue;
         const int l = li == 0 ? l0 : l1;
         const int wl = max(1, c.tex.w >> l), hl = max(1, c.tex.h >> l);
@@ -316,27 +323,27 @@ __global__ __launch_bounds__(256) void k_filter2d_gauss_det(Filter2DCall c)
         float tx, ty;
         raster(uu, wl, ix, tx);
         raster(vv, hl, iy, ty);
-        double gx[4], gy[4];
+        float gx[4], gy[4];
         if constexpr (F == GAUSS_FRS) {
-            gauss4((double)tx, h, gx);
-            gauss4((double)ty, h, gy);
+            gauss4(tx, h, gx);
+            gauss4(ty, h, gy);
         }
         for (int b = 0; b < ntap; ++b) {
-            const double wy = F == GAUSS_FRS ? gy[b & 3] : gauss_cell(r2, (double)ty, first + b);
+            const float wy = F == GAUSS_FRS ? gy[b & 3] : gauss_cell(r2, ty, first + b);
             const int y = wrap_any(c.tex.wrap, iy + first + b, hl);
             for (int a = 0; a < ntap; ++a) {
-                const double wx = F == GAUSS_FRS ? gx[a & 3] : gauss_cell(r2, (double)tx, first + a);
-                const double wgt = pl * wx * wy;
+                const float wx = F == GAUSS_FRS ? gx[a & 3] : gauss_cell(r2, tx, first + a);
+                const float wgt = (pl * wx) * wy;
                 const float4 t = texel(c.tex, l, wrap_any(c.tex.wrap, ix + first + a, wl), y);
                 const float4 v = MODE == BEFORE ? t : shade<SHADE>(c.g, t);
-                sum[0] += wgt * (double)v.x;
-                sum[1] += wgt * (double)v.y;
-                sum[2] += wgt * (double)v.z;
-                sum[3] += wgt * (double)v.w;
+                sum[0].add(wgt * v.x);
+                sum[1].add(wgt * v.y);
+                sum[2].add(wgt * v.z);
+                sum[3].add(wgt * v.w);
             }
         }
     }
-    const float4 r = make_float4((float)sum[0], (float)sum[1], (float)sum[2], (float)sum[3]);
+    const float4 r = make_float4(sum[0].value(), sum[1].value(), sum[2].value(), sum[3].value());
     store<SHADE>(c.out, q, MODE == BEFORE ? shade<SHADE>(c.g, r) : r);
 }
 

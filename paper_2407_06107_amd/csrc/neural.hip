@@ -856,7 +856,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (active)
         st = ray_setup_dev(c.lat.wmin, c.lat.scale, c.rays + 8 * i, c.steps, g);
     const bool march = active && st == 0;
-    double Tsum = 0.0;
+    // compensated binary32 sums, as in the plain march
+    CompSum Tsum;
+    Tsum.init();
     // lattice point (and scale block) of step k of this lane's ray; idx -1
     // outside the lattice or for lanes without a ray
     auto step_point = [&](const StepHash &h, int k, int s, int64_t &idx, int &blk) {
@@ -895,7 +897,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int s = 0; s < c.spp; ++s) {
         StepHash h;
         h.init((uint32_t)i, (uint32_t)s, c.seed);
-        double tau = 0.0;
+        CompSum tau;
+        tau.init();
         int64_t idx;
         int blk;
         step_point(h, 0, s, idx, blk);
@@ -910,11 +913,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             float sg[1];
             decode_loaded<C, O, FMT>(Fr, cur, sg);             // step k
             if (idx >= 0)
-                tau += (double)__builtin_fmaxf(sg[0], 0.0f);
+                tau.add(__builtin_fmaxf(sg[0], 0.0f));
             cur = nxt;
             idx = idx_n;
         }
-        Tsum += exp(-(double)g.dt * tau);
+        Tsum.add(expf(-(g.dt * tau.value())));
     }
     if (!active)
         return;
@@ -927,7 +930,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
         return;
     }
-    c.T[i] = (float)(Tsum / (double)c.spp);
+    c.T[i] = Tsum.value() / (float)c.spp;
 }
 
 // ---------------------------------------------------------------- launchers

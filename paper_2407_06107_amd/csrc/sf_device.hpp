@@ -420,24 +420,83 @@ __device__ __forceinline__ void axis_weights(float t, float w[4])
     }
 }
 
-// The same weights in binary64 from the binary32 fraction: they sum to one
-// within ~1e-16, which the long products of the exact-after comparator need.
-template <int F>
-__device__ __forceinline__ void axis_weights64(float tf, double w[4])
-{
-    const double t = (double)tf;
-    if constexpr (F == BSPLINE3) {
-        const double s = 1.0 - t, t2 = t * t, s2 = s * s;
-        w[0] = (s2 * s) * (1.0 / 6.0);
-        w[1] = 2.0 / 3.0 - t2 * (1.0 - 0.5 * t);
-        w[2] = 2.0 / 3.0 - s2 * (1.0 - 0.5 * s);
-        w[3] = (t2 * t) * (1.0 / 6.0);
-    } else if constexpr (F == LINEAR) {
-        w[0] = 1.0 - t;
-        w[1] = t;
-    } else {
-        w[0] = 1.0;
+// Compensated summation in binary32 (contraction is off in every source and
+// nothing reassociates): the running sum s is the plain binary32 sum, and the
+// exact rounding error of every addition, found by Knuth's TwoSum (six
+// operations, no branch, any signs), is accumulated in c.  s + c is then as
+// accurate as a sum in twice the working precision: within
+// u |sum| + gamma_{n-1}^2 sum |x_i| of the exact sum, u = 2^-24,
+// gamma_k = k u / (1 - k u) (Ogita, Rump and Oishi, "Accurate sum and dot
+// product", SIAM J. Sci. Comput. 26(6), 2005, algorithm Sum2).  Adding an
+// exact zero changes neither s nor c, so a sum that skips zero terms is
+// bit-identical to one that adds them.
+struct CompSum {
+    float s, c;
+    __device__ __forceinline__ void init()
+    {
+        s = 0.0f;
+        c = 0.0f;
     }
+    __device__ __forceinline__ void add(float x)
+    {
+        const float t = s + x;
+        const float bp = t - s;
+        const float e = (s - (t - bp)) + (x - bp);
+        s = t;
+        c = c + e;
+    }
+    __device__ __forceinline__ float value() const { return s + c; }
+};
+
+// A product of positive factors kept as an unevaluated binary32 pair
+// hi + lo: each multiplication keeps its rounding error through one fma (the
+// error-free product of Dekker, as in Ogita, Rump and Oishi), so the pair
+// carries about 44 significant bits and the relative error after n factors
+// is O(n u^2) on top of what the factors bring in.  A factor is passed as a
+// pair too: a transmittance close to 1 is best known as 1 - a with a
+// accurate to a few ulp of a (not of 1), and mul_one_minus splits it
+// exactly (Dekker's Fast2Sum, |1| >= |a|); a factor far from 1 is best known
+// directly and is passed as (f, 0).  Multiplying by exactly 1 changes nothing.
+struct PairProduct {
+    float hi, lo;
+    __device__ __forceinline__ void init()
+    {
+        hi = 1.0f;
+        lo = 0.0f;
+    }
+    __device__ __forceinline__ void mul(float fh, float fl)
+    {
+        const float p = hi * fh;
+        float e = __builtin_fmaf(hi, fh, -p);
+        e = __builtin_fmaf(hi, fl, e);
+        e = __builtin_fmaf(lo, fh, e);
+        const float s = p + e;
+        lo = e - (s - p);
+        hi = s;
+    }
+    __device__ __forceinline__ void mul_one_minus(float a)
+    {
+        const float fh = 1.0f - a;
+        mul(fh, (1.0f - fh) - a);
+    }
+    __device__ __forceinline__ float value() const { return hi + lo; }
+};
+
+// e = e^(-x) and m = 1 - e^(-x), each with a small relative error: e on the
+// transcendental unit (2^(-x log2 e)); m for |x| < 1/4 by the degree-7 Taylor
+// polynomial (first omitted term below 2e-9 of the value), otherwise as
+// 1 - e, whose 1-ulp error stays below 4 ulp of the difference there
+// (e <= 0.78 for x >= 1/4).
+__device__ __forceinline__ void exp_neg_pair(float x, float &e, float &m)
+{
+    float p = __builtin_fmaf(x, 1.0f / 5040.0f, -1.0f / 720.0f);
+    p = __builtin_fmaf(x, p, 1.0f / 120.0f);
+    p = __builtin_fmaf(x, p, -1.0f / 24.0f);
+    p = __builtin_fmaf(x, p, 1.0f / 6.0f);
+    p = __builtin_fmaf(x, p, -0.5f);
+    p = __builtin_fmaf(x, p, 1.0f);
+    e = __builtin_amdgcn_exp2f(x * -1.44269504088896341f);
+    m = __builtin_fabsf(x) < 0.25f ? x * p : 1.0f - e;
 }
 
 template <int F>
@@ -517,6 +576,16 @@ __device__ __forceinline__ float3 shade_ggx_dev(const GgxConst &g, float4 c)
                        __builtin_fmaf(g.kd[2], c.z, g.ks[2] * spec));
 }
 
+// a b - c d within about 1.5 ulp (Kahan's algorithm: the rounding error of
+// c d, recovered by an fma, is added back).
+__device__ __forceinline__ float diff_prod(float a, float b, float c, float d)
+{
+    const float w = c * d;
+    const float e = __builtin_fmaf(-c, d, w);
+    const float f = __builtin_fmaf(a, b, -w);
+    return f + e;
+}
+
 // Normal-mapped GGX + Lambert of a grey material (albedo 1/2): the texel's
 // RGB encodes the tangent-space normal m = 2 rgb - 1 (renormalised; z for
 // m = 0), A the roughness parameter; h, wo, wi come in the tangent frame, so
@@ -539,12 +608,23 @@ __device__ __forceinline__ float3 shade_ggx_normal_dev(const GgxConst &g, float4
     const float r = __builtin_fmaf(g.r_scale, c.w, g.r_bias);
     const float a = r * r;
     const float a2 = a * a;
-    // 1 - (n.h)^2 (1 - alpha^2) cancels near the peak of a glossy lobe: binary64
-    const double mxd = mx, myd = my, mzd = mz;
-    const double nhd = mxd * g.th[0] + myd * g.th[1] + mzd * g.th[2];
-    const double c2 = (nhd * nhd) / (mxd * mxd + myd * myd + mzd * mzd);
-    const double dd = __builtin_fma(c2, (double)a2 - 1.0, 1.0);
-    const float D = (float)((double)a2 / (dd * dd));   // times 1/pi below
+    // 1 - (n.h)^2 (1 - alpha^2) cancels near the peak of a glossy lobe; it is
+    // formed as sin^2 + cos^2 alpha^2 of the angle between m and h, the sine
+    // from the cross product, two non-negative terms.  h comes as a binary32
+    // pair th + thl (a direction rounded to binary32 moves a glossy lobe's
+    // value by ~1e-5), and each cross-product component keeps the rounding of
+    // its products (Kahan's a b - c d), where they cancel near the peak.
+    const float nh = (mx * g.th[0] + my * g.th[1] + mz * g.th[2]) + (mx * g.thl[0] + my * g.thl[1] + mz * g.thl[2]);
+    const float cx = diff_prod(my, g.th[2], mz, g.th[1]) + (my * g.thl[2] - mz * g.thl[1]);
+    const float cy = diff_prod(mz, g.th[0], mx, g.th[2]) + (mz * g.thl[0] - mx * g.thl[2]);
+    const float cz = diff_prod(mx, g.th[1], my, g.th[0]) + (mx * g.thl[1] - my * g.thl[0]);
+    const float il2 = 1.0f / ml2;
+    // 1 - c2 = s2 + (1 - |h|^2): the tangent frame of a binary32 normal is
+    // orthonormal only to ~1e-8, so |h|^2 differs from 1 by that much, which
+    // is not negligible beside s2 + c2 alpha^2 at a sharp lobe's peak
+    const float c2 = (nh * nh) * il2, s2 = ((cx * cx + cy * cy) + cz * cz) * il2;
+    const float dd = (s2 + g.th_defect) + c2 * a2;
+    const float D = a2 / (dd * dd);   // times 1/pi below
     const float om = 1.0f - a2;
     const float go = 2.0f / (no + __builtin_sqrtf(__builtin_fmaf(om, no * no, a2)));   // G1(no)/no
     const float gi = 2.0f / (ni + __builtin_sqrtf(__builtin_fmaf(om, ni * ni, a2)));

@@ -19,7 +19,8 @@ struct GgxConst {
     // normal-mapped shading: h, wo, wi in the tangent frame (e1, e2, n) of
     // the surface normal, Fresnel, radiance and the grey diffuse term
     float to[3], ti[3];
-    double th[3];          // binary64: the distribution term cancels near its peak
+    float th[3], thl[3];   // h as a binary32 pair: th + thl
+    float th_defect;       // 1 - |h|^2 in the (nearly orthonormal) frame
     float F;
     float rad[3], kdn[3];  // radiance, radiance * (1/2) / pi
 };

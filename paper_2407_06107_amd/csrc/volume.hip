@@ -7,137 +7,12 @@
 // One lane marches one ray.  The stochastic kernel is the hot path: per step
 // it forms the raster position, hashes (ray, sample, step, seed), picks one
 // tap per axis by inverse CDF on the separable weights (Sec. 4.1 FRS) and
-// gathers ONE voxel; the optical depth is summed in float64, exactly, since
-// every binary16 density is a multiple of 2^-24.
-#include "sf_device.hpp"
-#include "sf_internal.hpp"
+// gathers ONE voxel; the optical depth is a compensated binary32 sum.
+#include "volume_dev.hpp"
 
 #pragma clang fp contract(off)
 
 namespace sfk {
-
-constexpr uint32_t kBufferFlags = 0x00020000u;  // raw buffer, 32-bit data format
-
-// Byte offset of voxel (x, y, z) and whether it lies in the grid.  A tap
-// outside the grid gets offset 0 (always valid) and its value is discarded.
-// P2: nx and ny are powers of two, so the index is built with shifts.
-template <bool HALF, bool P2>
-__device__ __forceinline__ uint32_t voxel_offset(const VolArgs &v, int x, int y, int z, bool &ok)
-{
-    ok = ((uint32_t)x < (uint32_t)v.nx) & ((uint32_t)y < (uint32_t)v.ny) & ((uint32_t)z < (uint32_t)v.nz);
-    uint32_t idx;
-    if constexpr (P2)
-        idx = ((((uint32_t)z << v.ly) | (uint32_t)y) << v.lx) | (uint32_t)x;
-    else
-        idx = __umul24(__umul24((uint32_t)z, (uint32_t)v.ny) + (uint32_t)y, (uint32_t)v.nx) + (uint32_t)x;
-    return ok ? idx * (HALF ? 2u : 4u) : 0u;
-}
-
-template <bool HALF>
-__device__ __forceinline__ uint32_t voxel_bits(__amdgpu_buffer_rsrc_t rs, uint32_t off)
-{
-    if constexpr (HALF)
-        return __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
-    else
-        return __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
-}
-
-template <bool HALF>
-__device__ __forceinline__ float bits_value(uint32_t b)
-{
-    if constexpr (HALF)
-        return half_bits_to_float((uint16_t)b);
-    else
-        return __builtin_bit_cast(float, b);
-}
-
-template <bool HALF>
-__device__ __forceinline__ float voxel_load(__amdgpu_buffer_rsrc_t rs, uint32_t off)
-{
-    return bits_value<HALF>(voxel_bits<HALF>(rs, off));
-}
-
-// One voxel; zero outside the grid.
-template <bool HALF>
-__device__ __forceinline__ float voxel(__amdgpu_buffer_rsrc_t rs, const VolArgs &v, int x, int y, int z)
-{
-    bool ok;
-    const uint32_t off = voxel_offset<HALF, false>(v, x, y, z, ok);
-    const float val = voxel_load<HALF>(rs, off);
-    return ok ? val : 0.0f;
-}
-
-__device__ __forceinline__ void step_coords(const RayGeom &g, float kh, int i0[3], float t[3])
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float p = __builtin_fmaf(kh, g.G[a], g.E[a]);
-        float fl = __builtin_floorf(p);
-        i0[a] = (int)fl;
-        t[a] = p - fl;
-    }
-}
-
-// True unless the lookup point's brick is known to be empty: a tap of any
-// filter lies within [i0-1, i0+2] per axis, inside the brick's 2-voxel
-// dilation, so a clear bit means every tap reads zero.  The brick
-// coordinates are clamped to the grid's bricks, which is exact as well: for
-// i0 < 0 the taps inside the grid lie in [0, 1], and for i0 at or beyond the
-// last brick's end they lie in {n-1} (or nowhere), both within the dilation
-// of the nearest brick; so no step whose taps can read a non-zero voxel is
-// skipped, and the index always lies inside the mask.  The bit is extracted
-// with the hardware's offset-mod-32 field extract.
-// P2: nx and ny are powers of two, so are the brick counts along x and y
-// (nx >> occ_log2, or 1 below one brick) and the index is built with shifts.
-// clamp(x, 0, hi) for a wave-uniform hi in one instruction (the compiler
-// forms v_med3_i32 only for compile-time bounds)
-__device__ __forceinline__ int clamp0_uniform(int x, int hi)
-{
-    int r;
-    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
-    return r;
-}
-
-template <bool P2 = false>
-__device__ __forceinline__ bool brick_occupied(const VolArgs &v, const int i0[3])
-{
-    const uint32_t bx = (uint32_t)clamp0_uniform(i0[0] >> v.occ_log2, v.nbx - 1);
-    const uint32_t by = (uint32_t)clamp0_uniform(i0[1] >> v.occ_log2, v.nby - 1);
-    const uint32_t bz = (uint32_t)clamp0_uniform(i0[2] >> v.occ_log2, v.nbz - 1);
-    uint32_t b;
-    if constexpr (P2) {
-        const int lbx = max(v.lx - v.occ_log2, 0), lby = max(v.ly - v.occ_log2, 0);
-        b = (((bz << lby) | by) << lbx) | bx;
-    } else {
-        b = __umul24(__umul24(bz, (uint32_t)v.nby) + by, (uint32_t)v.nbx) + bx;
-    }
-    return __builtin_amdgcn_ubfe(v.occ[b >> 5], b, 1u) != 0u;
-}
-
-// The loaded bits, or 0 (the value 0.0) for a tap outside the grid.  The
-// empty asm keeps the select on the 32-bit word: otherwise it is moved past
-// the conversions and done twice on the float64 halves.
-__device__ __forceinline__ uint32_t masked_bits(uint32_t b, bool ok)
-{
-    uint32_t r = ok ? b : 0u;
-    asm volatile("" : "+v"(r));
-    return r;
-}
-
-template <int F, int VAR>
-__device__ __forceinline__ void pick3(const float t[3], uint3 w, int o[3])
-{
-    if constexpr (VAR == 0) {
-        o[0] = pick_off_2p24<F>(t[0], u24i(w.x));
-        o[1] = pick_off_2p24<F>(t[1], u24i(w.y));
-        o[2] = pick_off_2p24<F>(t[2], u24i(w.z));
-    } else {
-        float u = u24(w.x);
-        o[0] = pick_off_reuse<F>(t[0], u);
-        o[1] = pick_off_reuse<F>(t[1], u);
-        o[2] = pick_off_reuse<F>(t[2], u);
-    }
-}
 
 // Black-body emission (Sec. 5, "Filtering nonlinear physical properties"):
 // spectral radiance in W sr^-1 m^-2 nm^-1 at 700, 546.1 and 435.8 nm of a
@@ -209,11 +84,16 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
     }
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
-    double Tsum = 0.0;
+    // optical depth and the mean over samples as compensated binary32 sums:
+    // tau within 2u tau of its exact value, so T = e^(-dt tau) within about
+    // (2 tau + 3) u relative of the exact transmittance of the picked voxels
+    CompSum Tsum;
+    Tsum.init();
     for (int s = 0; s < c.spp; ++s) {
         StepHash h;
         h.init((uint32_t)i, (uint32_t)s, c.seed);
-        double tau = 0.0;
+        CompSum tau;
+        tau.init();
         // software pipeline: a step's voxel is added one step later, so its
         // load overlaps the next step's arithmetic
         uint32_t pend = 0;
@@ -237,21 +117,26 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
             }
             bool ok;
             const uint32_t off = voxel_offset<HALF, P2>(c.vol, x, y, z, ok);
-            tau += (double)bits_value<HALF>(masked_bits(pend, pend_ok));   // step k-1
-            pend = voxel_bits<HALF>(rs, off);                               // step k
+            tau.add(bits_value<HALF>(masked_bits(pend, pend_ok)));   // step k-1
+            pend = voxel_bits<HALF>(rs, off);                        // step k
             pend_ok = ok;
         }
-        tau += (double)bits_value<HALF>(masked_bits(pend, pend_ok));
-        Tsum += exp(-(double)g.dt * tau);
+        tau.add(bits_value<HALF>(masked_bits(pend, pend_ok)));
+        Tsum.add(expf(-(g.dt * tau.value())));
     }
-    c.T[i] = (float)(Tsum / (double)c.spp);
+    c.T[i] = Tsum.value() / (float)c.spp;
 }
 
 // Deterministic comparators: all taps of the separable footprint per step.
 // BEFORE: exp(-dt sum_k sum_i w_i sigma_i); AFTER: prod_k sum_i w_i e^{-dt sigma_i}.
-// Weights and the per-step sums are binary64 (the same issue rate as
-// non-packed binary32 on this chip): with binary32 weights the 64 products
-// sum to 1 +- 3e-7, a bias that a 256-factor product would amplify.
+// Binary32 throughout.  The AFTER product's factors are multiplied as
+// binary32 pairs, and a step's factor f_k enters in the form that is known
+// to a few ulp of itself: f_k = sum_i w_i e^{-dt sigma_i} when it is below
+// 1/2, else 1 - a_k with a_k = sum_i w_i (1 - e^{-dt sigma_i}) (a factor
+// close to 1 formed directly would carry the rounding of the binary32
+// weights, which sum to 1 +- 3e-7, into every one of 256 factors).  Both
+// modes then stay within about 20 u tau of the exact transmittance,
+// tau = -ln T, u = 2^-24.
 template <int F, bool HALF, int MODE, bool OCC>
 __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad)
 {
@@ -268,47 +153,64 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
                                                                   (int)c.vol.bytes, kBufferFlags);
     constexpr int NT = Taps<F>::n;
     constexpr int F0 = Taps<F>::first;
-    const float cexp = (float)(-(double)g.dt * 1.4426950408889634074);   // -dt log2(e)
-    double tau = 0.0, Tp = 1.0;
+    const float dt = g.dt;
+    CompSum tau;
+    tau.init();
+    PairProduct Tp;
+    Tp.init();
     float kh = 0.5f;
     for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
         int i0[3];
         float t[3];
-        double wx[4], wy[4], wz[4];
+        float wx[4], wy[4], wz[4];
         step_coords(g, kh, i0, t);
         if constexpr (OCC) {
             if (!brick_occupied(c.vol, i0))
-                continue;   // every tap is zero: before adds 0, after multiplies by sum w = 1
+                continue;   // every tap is zero: before adds 0, after multiplies by 1 - 0
         }
         if constexpr (F == NEAREST) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 i0[a] += t[a] >= 0.5f;
         }
-        axis_weights64<F>(t[0], wx);
-        axis_weights64<F>(t[1], wy);
-        axis_weights64<F>(t[2], wz);
-        double acc = 0.0;
+        axis_weights<F>(t[0], wx);
+        axis_weights<F>(t[1], wy);
+        axis_weights<F>(t[2], wz);
+        // BEFORE: acc = sum_i w_i sigma_i.  AFTER: acc = a_k, accf = f_k.
+        float acc = 0.0f, accf = 0.0f;
 #pragma unroll
         for (int cz = 0; cz < NT; ++cz) {
 #pragma unroll
             for (int by = 0; by < NT; ++by) {
-                double row = 0.0;
+                float row = 0.0f, rowf = 0.0f;
 #pragma unroll
                 for (int ax = 0; ax < NT; ++ax) {
                     float sg = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
-                    float v = MODE == BEFORE ? sg : __builtin_amdgcn_exp2f(sg * cexp);
-                    row = __builtin_fma(wx[ax], (double)v, row);
+                    if constexpr (MODE == BEFORE) {
+                        row = __builtin_fmaf(wx[ax], sg, row);
+                    } else {
+                        float e, m;
+                        exp_neg_pair(sg * dt, e, m);
+                        row = __builtin_fmaf(wx[ax], m, row);
+                        rowf = __builtin_fmaf(wx[ax], e, rowf);
+                    }
                 }
-                acc = __builtin_fma(wy[by] * wz[cz], row, acc);
+                const float wyz = wy[by] * wz[cz];
+                acc = __builtin_fmaf(wyz, row, acc);
+                if constexpr (MODE != BEFORE)
+                    accf = __builtin_fmaf(wyz, rowf, accf);
             }
         }
-        if constexpr (MODE == BEFORE)
-            tau += acc;
-        else
-            Tp *= acc;
+        if constexpr (MODE == BEFORE) {
+            tau.add(acc);
+        } else {
+            if (accf < 0.5f)
+                Tp.mul(accf, 0.0f);
+            else
+                Tp.mul_one_minus(acc);
+        }
     }
-    c.T[i] = MODE == BEFORE ? (float)exp(-(double)g.dt * tau) : (float)Tp;
+    c.T[i] = MODE == BEFORE ? expf(-(dt * tau.value())) : Tp.value();
 }
 
 // ------------------------------------------------------------ emission march
@@ -316,7 +218,7 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
 // dt * sum_k E_k at three wavelengths, E_k the step's emission.  Stochastic:
 // E_k = B(T) of the one voxel the step picks (keys, picks and the occupancy
 // skip as in the transmittance march; empty bricks emit nothing).  The sums
-// run in binary64.
+// are compensated binary32 sums of positive terms.
 // Gaussian footprint perpendicular to the ray (Sec. 5: filtering after
 // shading under minification): the plane's basis by the branchless
 // construction of Duff et al., "Building an Orthonormal Basis, Revisited"
@@ -375,7 +277,10 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
     }
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
-    double acc[3] = {0.0, 0.0, 0.0};
+    CompSum acc[3];
+    acc[0].init();
+    acc[1].init();
+    acc[2].init();
     PerpFrame pf;
     if constexpr (JIT)
         pf = perp_frame(c.rays + 8 * i, c.vol.scale, c.footprint);
@@ -423,33 +328,36 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
             const uint32_t off = voxel_offset<HALF, P2>(c.vol, x, y, z, ok);
             float B[3];
             planck3(bits_value<HALF>(masked_bits(pend, pend_ok)), B);   // step k-1
-            acc[0] += (double)B[0];
-            acc[1] += (double)B[1];
-            acc[2] += (double)B[2];
+            acc[0].add(B[0]);
+            acc[1].add(B[1]);
+            acc[2].add(B[2]);
             pend = voxel_bits<HALF>(rs, off);                            // step k
             pend_ok = ok;
         }
         float B[3];
         planck3(bits_value<HALF>(masked_bits(pend, pend_ok)), B);
-        acc[0] += (double)B[0];
-        acc[1] += (double)B[1];
-        acc[2] += (double)B[2];
+        acc[0].add(B[0]);
+        acc[1].add(B[1]);
+        acc[2].add(B[2]);
     }
+    // the lanes' sums (at most 64, positive) meet in a butterfly
+    float e[3] = {acc[0].value(), acc[1].value(), acc[2].value()};
     for (int m = G >> 1; m >= 1; m >>= 1) {
-        acc[0] += __shfl_xor(acc[0], m);
-        acc[1] += __shfl_xor(acc[1], m);
-        acc[2] += __shfl_xor(acc[2], m);
+        e[0] += __shfl_xor(e[0], m);
+        e[1] += __shfl_xor(e[1], m);
+        e[2] += __shfl_xor(e[2], m);
     }
     if (lane == 0) {
-        const double sc = (double)g.dt / (double)c.spp;
-        c.T[3 * i] = (float)(acc[0] * sc);
-        c.T[3 * i + 1] = (float)(acc[1] * sc);
-        c.T[3 * i + 2] = (float)(acc[2] * sc);
+        const float sc = g.dt / (float)c.spp;
+        c.T[3 * i] = e[0] * sc;
+        c.T[3 * i + 1] = e[1] * sc;
+        c.T[3 * i + 2] = e[2] * sc;
     }
 }
 
 // Deterministic emission: E_k = B(sum_i w_i T_i) before shading,
-// sum_i w_i B(T_i) after; binary64 weights and sums.
+// sum_i w_i B(T_i) after; binary32 weights and per-step sums of positive
+// terms, steps summed with compensation.
 template <int F, bool HALF, int MODE, bool OCC>
 __global__ __launch_bounds__(256) void k_emit_det(RaymarchCall c, uint32_t nb_pad)
 {
@@ -469,12 +377,15 @@ __global__ __launch_bounds__(256) void k_emit_det(RaymarchCall c, uint32_t nb_pa
                                                                   (int)c.vol.bytes, kBufferFlags);
     constexpr int NT = Taps<F>::n;
     constexpr int F0 = Taps<F>::first;
-    double acc[3] = {0.0, 0.0, 0.0};
+    CompSum acc[3];
+    acc[0].init();
+    acc[1].init();
+    acc[2].init();
     float kh = 0.5f;
     for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
         int i0[3];
         float t[3];
-        double wx[4], wy[4], wz[4];
+        float wx[4], wy[4], wz[4];
         step_coords(g, kh, i0, t);
         if constexpr (OCC) {
             if (!brick_occupied(c.vol, i0))
@@ -485,47 +396,46 @@ __global__ __launch_bounds__(256) void k_emit_det(RaymarchCall c, uint32_t nb_pa
             for (int a = 0; a < 3; ++a)
                 i0[a] += t[a] >= 0.5f;
         }
-        axis_weights64<F>(t[0], wx);
-        axis_weights64<F>(t[1], wy);
-        axis_weights64<F>(t[2], wz);
-        double e[3] = {0.0, 0.0, 0.0};
+        axis_weights<F>(t[0], wx);
+        axis_weights<F>(t[1], wy);
+        axis_weights<F>(t[2], wz);
+        float e[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int cz = 0; cz < NT; ++cz) {
 #pragma unroll
             for (int by = 0; by < NT; ++by) {
-                const double wyz = wy[by] * wz[cz];
+                const float wyz = wy[by] * wz[cz];
 #pragma unroll
                 for (int ax = 0; ax < NT; ++ax) {
                     const float T = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
-                    const double w = wx[ax] * wyz;
+                    const float w = wx[ax] * wyz;
                     if constexpr (MODE == BEFORE) {
-                        e[0] = __builtin_fma(w, (double)T, e[0]);
+                        e[0] = __builtin_fmaf(w, T, e[0]);
                     } else {
                         float B[3];
                         planck3(T, B);
-                        e[0] = __builtin_fma(w, (double)B[0], e[0]);
-                        e[1] = __builtin_fma(w, (double)B[1], e[1]);
-                        e[2] = __builtin_fma(w, (double)B[2], e[2]);
+                        e[0] = __builtin_fmaf(w, B[0], e[0]);
+                        e[1] = __builtin_fmaf(w, B[1], e[1]);
+                        e[2] = __builtin_fmaf(w, B[2], e[2]);
                     }
                 }
             }
         }
         if constexpr (MODE == BEFORE) {
             float B[3];
-            planck3((float)e[0], B);
-            acc[0] += (double)B[0];
-            acc[1] += (double)B[1];
-            acc[2] += (double)B[2];
+            planck3(e[0], B);
+            acc[0].add(B[0]);
+            acc[1].add(B[1]);
+            acc[2].add(B[2]);
         } else {
-            acc[0] += e[0];
-            acc[1] += e[1];
-            acc[2] += e[2];
+            acc[0].add(e[0]);
+            acc[1].add(e[1]);
+            acc[2].add(e[2]);
         }
     }
-    const double dt = (double)g.dt;
-    c.T[3 * i] = (float)(acc[0] * dt);
-    c.T[3 * i + 1] = (float)(acc[1] * dt);
-    c.T[3 * i + 2] = (float)(acc[2] * dt);
+    c.T[3 * i] = acc[0].value() * g.dt;
+    c.T[3 * i + 1] = acc[1].value() * g.dt;
+    c.T[3 * i + 2] = acc[2].value() * g.dt;
 }
 
 // ------------------------------------------------------------- point lookups
@@ -534,7 +444,10 @@ template <int F, bool HALF>
 __device__ void filter3d_planck(const Filter3DCall &c, int64_t i, int i0[3], const float t[3],
                                 __amdgpu_buffer_rsrc_t rs)
 {
-    double acc[3] = {0.0, 0.0, 0.0};
+    CompSum acc[3];
+    acc[0].init();
+    acc[1].init();
+    acc[2].init();
     if (c.mode == STOCH) {
         for (int s = 0; s < c.spp; ++s) {
             uint4 w4 = pcg4d(make_uint4((uint32_t)i, (uint32_t)s, 0u, c.seed));
@@ -554,10 +467,10 @@ __device__ void filter3d_planck(const Filter3DCall &c, int64_t i, int i0[3], con
             float B[3];
             planck3(voxel<HALF>(rs, c.vol, tx, ty, tz), B);
             for (int k = 0; k < 3; ++k)
-                acc[k] += (double)B[k];
+                acc[k].add(B[k]);
         }
         for (int k = 0; k < 3; ++k)
-            c.out[3 * i + k] = (float)(acc[k] / (double)c.spp);
+            c.out[3 * i + k] = acc[k].value() / (float)c.spp;
         return;
     }
     constexpr int NT = Taps<F>::n;
@@ -567,29 +480,31 @@ __device__ void filter3d_planck(const Filter3DCall &c, int64_t i, int i0[3], con
         for (int a = 0; a < 3; ++a)
             i0[a] += t[a] >= 0.5f;
     }
-    double wx[4], wy[4], wz[4];
-    axis_weights64<F>(t[0], wx);
-    axis_weights64<F>(t[1], wy);
-    axis_weights64<F>(t[2], wz);
+    float wx[4], wy[4], wz[4];
+    axis_weights<F>(t[0], wx);
+    axis_weights<F>(t[1], wy);
+    axis_weights<F>(t[2], wz);
+    // binary32 weights; the weighted terms are summed with compensation
+    // (before: signed temperatures are allowed, so no positivity is assumed)
     for (int cz = 0; cz < NT; ++cz)
         for (int by = 0; by < NT; ++by)
             for (int ax = 0; ax < NT; ++ax) {
-                const double wgt = wx[ax] * wy[by] * wz[cz];
+                const float wgt = (wx[ax] * wy[by]) * wz[cz];
                 const float T = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
                 if (c.mode == BEFORE) {
-                    acc[0] += wgt * (double)T;
+                    acc[0].add(wgt * T);
                 } else {
                     float B[3];
                     planck3(T, B);
                     for (int k = 0; k < 3; ++k)
-                        acc[k] += wgt * (double)B[k];
+                        acc[k].add(wgt * B[k]);
                 }
             }
     float B[3];
     if (c.mode == BEFORE)
-        planck3((float)acc[0], B);
+        planck3(acc[0].value(), B);
     for (int k = 0; k < 3; ++k)
-        c.out[3 * i + k] = c.mode == BEFORE ? B[k] : (float)acc[k];
+        c.out[3 * i + k] = c.mode == BEFORE ? B[k] : acc[k].value();
 }
 
 template <int F, bool HALF>
@@ -631,7 +546,8 @@ __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
         return;
     }
     if (c.mode == STOCH) {
-        double acc = 0.0;
+        CompSum acc;
+        acc.init();
         for (int s = 0; s < c.spp; ++s) {
             uint4 w4 = pcg4d(make_uint4((uint32_t)i, (uint32_t)s, 0u, c.seed));
             uint3 w = make_uint3(w4.x, w4.y, w4.z);
@@ -648,9 +564,9 @@ __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
                 tp[2] = tz;
             }
             float sg = voxel<HALF>(rs, c.vol, tx, ty, tz);
-            acc += trans ? exp(-(double)sg * (double)c.ds) : (double)sg;
+            acc.add(trans ? expf(-(sg * c.ds)) : sg);
         }
-        c.out[i] = (float)(acc / (double)c.spp);
+        c.out[i] = acc.value() / (float)c.spp;
         return;
     }
     constexpr int NT = Taps<F>::n;
@@ -660,22 +576,25 @@ __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
         for (int a = 0; a < 3; ++a)
             i0[a] += t[a] >= 0.5f;
     }
-    double wx[4], wy[4], wz[4];
-    axis_weights64<F>(t[0], wx);
-    axis_weights64<F>(t[1], wy);
-    axis_weights64<F>(t[2], wz);
-    double sum = 0.0;
+    float wx[4], wy[4], wz[4];
+    axis_weights<F>(t[0], wx);
+    axis_weights<F>(t[1], wy);
+    axis_weights<F>(t[2], wz);
+    // binary32 weights, compensated sum (densities may be signed here)
+    CompSum sum;
+    sum.init();
     for (int cz = 0; cz < NT; ++cz)
         for (int by = 0; by < NT; ++by)
             for (int ax = 0; ax < NT; ++ax) {
-                double wgt = wx[ax] * wy[by] * wz[cz];
-                float sg = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
-                double v = (c.mode == BEFORE || !trans) ? (double)sg : exp(-(double)sg * (double)c.ds);
-                sum += wgt * v;
+                const float wgt = (wx[ax] * wy[by]) * wz[cz];
+                const float sg = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
+                const float v = (c.mode == BEFORE || !trans) ? sg : expf(-(sg * c.ds));
+                sum.add(wgt * v);
             }
+    float r = sum.value();
     if (c.mode == BEFORE && trans)
-        sum = exp(-sum * (double)c.ds);
-    c.out[i] = (float)sum;
+        r = expf(-(r * c.ds));
+    c.out[i] = r;
 }
 
 // ---------------------------------------------------------- occupancy bricks
