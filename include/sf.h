@@ -90,7 +90,7 @@ enum { SF_NEAREST = 0, SF_LINEAR = 1, SF_BSPLINE3 = 2, SF_KEYS3 = 3, SF_GAUSS_FR
  * blocks, keys and the estimate (A + B) f(t+) - (Cn + Dn) f(t-) as SF_KEYS3;
  * dbg_taps n x spp x {level, x+, y+, x-, y-}. */
 /* SF_EWA: the elliptically weighted average over the pixel footprint, and
- * its stochastic form (one texel per sample by weighted reservoir sampling);
+ * its stochastic form (one texel per sample drawn from the EWA weights);
  * sf_filter2d_aniso only (it needs the screen derivatives). */
 /* Gaussian filters and filter importance sampling (2-D textures only):
  *   SF_GAUSS_FRS    discrete Gaussian of standard deviation sigma (texels) on
@@ -292,31 +292,37 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
  *     filtered on levels floor(lambda), floor(lambda)+1 (weights 1-f, f),
  *     averaged; before shades the average, after averages shaded texels.
  * SF_EWA (Sec. 4.1, stochastic EWA: a level chosen from the ellipse's
- *   extent, then one texel of all the EWA weights by weighted reservoir
- *   sampling; Suppl. S.4, the EWA kernel).  Needs a complete pyramid
+ *   extent, then one texel drawn from all the EWA weights; the EWA kernel of
+ *   Greene and Heckbert).  Needs a complete pyramid
  *   (levels = floor(log2(max(W, H))) + 1, the last level 1 x 1), aspect
  *   max(W, H) <= SF_EWA_MAX_ASPECT min(W, H) and aniso_max <=
  *   SF_EWA_MAX_ANISO, which bound the ellipse's box at a level a sample
- *   reads to (4 r_x (aniso_max + 1) + 3) x (4 r_y (aniso_max + 1) + 3) cells,
- *   r_x = max(W, H)/W, r_y = max(W, H)/H.  Binary32 contract:
- *   a = (du/dx, dv/dx), b = (du/dy, dv/dy); lengths |(W a_x, H a_y)|, longer
- *   first; beyond the limit b and its length times longer/(shorter
- *   aniso_max); a zero shorter length becomes longer/aniso_max;
- *   lod = max(0, log2(shorter)).  lod > levels-1: every mode returns the
- *   (shaded) texel of the 1 x 1 level.  Else at level l (W_l x H_l):
- *   s = u W_l - 1/2, t = v H_l - 1/2 (u, v wrapped); axes scaled by
- *   (W_l, H_l): A = a_y^2 + b_y^2 + 1, B = -2 (a_x a_y + b_x b_y),
- *   C = a_x^2 + b_x^2 + 1; A, B, C divided by A C - B^2/4;
- *   det = -B^2 + 4 A C; s0 = ceil(s - 2/det sqrt(det C)),
- *   s1 = floor(s + 2/det sqrt(det C)), t0, t1 likewise with sqrt(A det);
- *   rows it = t0..t1, columns is = s0..s1: r^2 = A ss^2 + B ss tt + C tt^2,
- *   ss = is - s, tt = it - t; cells with r^2 >= 1 skipped; weight
- *   LUT[min(floor(128 r^2), 127)], LUT[i] = exp(-2 i/127) - exp(-2) with
- *   the contract exp; zero weights skipped.
+ *   reads to (4 r_x aniso_max + 3) x (4 r_y aniso_max + 3) cells,
+ *   r_x = max(W, H)/W, r_y = max(W, H)/H.  Binary32 contract, in this order
+ *   (no contraction):
+ *   J in level-0 texels: jsx = W du/dx, jtx = H dv/dx, jsy = W du/dy,
+ *   jty = H dv/dy; m = max |j..|, m >= 2^40 gives lod = +inf; else
+ *   S = J J^T: Sss = jsx jsx + jsy jsy, Stt = jtx jtx + jty jty,
+ *   Sst = jsx jtx + jsy jty; dJ = jsx jty - jtx jsy, det = dJ dJ;
+ *   lp = (Sss + Stt)/2 + sqrt(((Sss - Stt)/2)^2 + Sst^2), s1 = sqrt(lp),
+ *   minor = lp > 0 ? |dJ| / s1 : 0; if minor aniso_max < s1:
+ *   lm = det / lp, minor = s1 / aniso_max,
+ *   k = lp > lm ? (minor^2 - lm)/(lp - lm) : 1, Sss += k (lp - Sss),
+ *   Stt += k (lp - Stt), Sst -= k Sst, det = lp minor^2;
+ *   lod = minor > 0 ? max(0, log2(minor)) : 0 (contract log2).
+ *   lod > levels-1: every mode returns the (shaded) texel of the 1 x 1
+ *   level.  Else at level l (W_l x H_l): fs = W_l/W, ft = H_l/H,
+ *   a = Sss fs^2 + 1, c = Stt ft^2 + 1, D = ((det fs^2 ft^2 + Sss fs^2)
+ *   + Stt ft^2) + 1; V^-1 = (c/D, a/D, -(2 Sst fs ft)/D) for (ss, tt, 2 st);
+ *   s = u W_l - 1/2, t = v H_l - 1/2 (u, v wrapped); s0 = ceil(s - sqrt(a)),
+ *   s1 = floor(s + sqrt(a)), t0, t1 likewise with sqrt(c); rows it = t0..t1,
+ *   columns is = s0..s1: r^2 = (qss ds^2 + qtt dt^2) + q2st ds dt,
+ *   ds = is - s, dt = it - t; weight e^(-2 r^2) - e^(-2) (contract exp) for
+ *   r^2 < 1, else 0; cells of weight <= 0 skipped.
  *   SF_STOCHASTIC, per sample: key (query, sample, 0, seed); word 3 picks
  *     level floor(lod) + [u_3 >= 1 - frac(lod)] (at most levels-1); word 0
- *     is the reservoir's uniform u: per weight w, W += w, p = w/W; u < p
- *     picks the cell and sets u = u/p, else u = (u - p)/(1 - p).
+ *     is the uniform u: W = sum of the weights in scan order, then the first
+ *     cell whose running sum exceeds u W (the last positive cell if none).
  *     dbg_taps: n x spp x {level, x, y} of the picked (wrapped) texel.
  *   SF_BEFORE / SF_AFTER_EXACT: the EWA sums on levels floor(lod) and
  *     floor(lod)+1 (weights 1-f, f), each divided by its weight total;

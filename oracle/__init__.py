@@ -101,8 +101,9 @@ def lib():
         L.orc_gauss_h.argtypes = [f32]
         L.orc_gauss_h.restype = f32
         L.orc_gauss_pick_pmf.argtypes = [f32, f32, P]
-        L.orc_ewa_lut.argtypes = [i32]
-        L.orc_ewa_lut.restype = f32
+        L.orc_ewa_gauss.argtypes = [f32]
+        L.orc_ewa_gauss.restype = f32
+        L.orc_ewa_frame.argtypes = [P, i32, i32, i32, P]
         L.orc_ewa_lod.argtypes = [P, i32, i32, i32]
         L.orc_ewa_box.argtypes = [i32, i32, i32, P, i32, i32, P]
         L.orc_ewa_lod.restype = f32
@@ -379,8 +380,17 @@ def filter2d_aniso(tex: Tex2D, q: np.ndarray, filt: int, mode: int, spp: int = 1
     return (out, tp) if taps else out
 
 
-def ewa_lut() -> np.ndarray:
-    return np.array([lib().orc_ewa_lut(i) for i in range(128)], dtype=np.float32)
+def ewa_gauss(r2: float) -> float:
+    """The EWA weight e^(-2 r^2) - e^(-2) (0 for r^2 >= 1), binary32."""
+    return float(lib().orc_ewa_gauss(float(r2)))
+
+
+def ewa_frame(q, w: int, h: int, amax: int = 8) -> np.ndarray:
+    """{lod, S_ss, S_tt, S_st, det S}: the footprint covariance in level-0
+    texels after the anisotropy limit, binary32."""
+    out = np.zeros(5, np.float32)
+    lib().orc_ewa_frame(_p(_c(q, np.float32)), w, h, amax, _p(out))
+    return out
 
 
 def ewa_lod(q, w: int, h: int, amax: int = 8) -> float:
@@ -397,7 +407,7 @@ def ewa_box(w: int, h: int, levels: int, q, level: int, amax: int = 8):
 
 
 def ewa_pick_pmf(w: int, h: int, levels: int, q, level: int, amax: int = 8, wrap: int = REPEAT, maxcells: int = 4096):
-    """Exact pick probabilities of the one-uniform reservoir over the level's
+    """Exact pick probabilities of the inverse-CDF pick over the level's
     bounding box (all 2^24 uniforms), with the box (s0, s1, t0, t1)."""
     qq = _c(q, np.float32)
     P = np.zeros(maxcells)

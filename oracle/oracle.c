@@ -1569,80 +1569,70 @@ static void aniso_one(const tex2d *t, const float *q, int64_t qi, int filter, in
 }
 
 /* ------------------------------------------------------------------------ */
-/* Elliptically weighted average (EWA) and its stochastic form (Sec. 4.1:    */
-/* select a MIP level from the ellipse's extent, evaluate all EWA weights,   */
-/* keep one texel by weighted reservoir sampling; Suppl. S.4, EWA listing).  */
-/* The ellipse is the pixel footprint given by the derivatives; weights are  */
-/* the truncated Gaussian e^(-2 r^2) - e^(-2) of the ellipse radius, read     */
-/* from a 128-entry table.  Binary32 contract, in the listing's order:        */
-/*   axes a = (du/dx, dv/dx), b = (du/dy, dv/dy) (texture units); lengths in  */
-/*   level-0 texels |(W a_x, H a_y)|, longer first; beyond the limit the      */
-/*   shorter is lengthened to longer/amax (b and its length times            */
-/*   longer/(shorter amax)); a zero shorter axis takes the length            */
-/*   longer/amax (b stays zero); lod = max(0, log2(shorter)), the level of   */
-/*   detail of the anisotropic filter.  The pyramid is complete (its last    */
-/*   level is 1 x 1): lod > L-1, a footprint wider than the texture, reads   */
-/*   the last level's one texel; else level floor(lod) + [u_l >= 1 - f],     */
-/*   at most L-1.                                                            */
-/*   At level l (W_l x H_l texels): s = u W_l - 1/2,                         */
-/*   t = v H_l - 1/2, axes scaled by (W_l, H_l); A = a_y a_y + b_y b_y + 1,   */
-/*   B = -2 (a_x a_y + b_x b_y), C = a_x a_x + b_x b_x + 1,                  */
-/*   F = 1/(A C - B B/4), A, B, C times F; det = -B B + 4 A C,               */
-/*   s0 = ceil(s - 2 sqrt(det C)/det), s1 = floor(s + 2 sqrt(det C)/det),    */
-/*   t0, t1 likewise with sqrt(A det); for it = t0..t1, is = s0..s1:          */
-/*   r2 = A (ss ss) + (B ss) tt + C (tt tt), ss = is - s, tt = it - t;       */
-/*   skip r2 >= 1; w = LUT[min(floor(r2 128), 127)], skip w <= 0; reservoir: */
-/*   W += w, p = w/W, u < p ? (pick, u = u/p) : u = (u - p)/(1 - p).          */
-/*   LUT[i] = exp(-2 i/127) - exp(-2) with the binary32 exp of the contract. */
-/* Uniforms: word 0 of the sample's key drives the reservoir, word 3 the     */
-/* level.  Comparators: the EWA sums on levels floor(lod), floor(lod)+1      */
-/* (weights 1-f, f), each normalised by its weight total.                    */
+/* Elliptically weighted average (EWA) and its stochastic form (Sec. 4.1: a  */
+/* MIP level chosen from the ellipse's extent, then all EWA weights are      */
+/* computed and one texel is drawn from their distribution).                 */
+/*                                                                          */
+/* The ellipse (Greene and Heckbert's EWA): the footprint Jacobian J maps    */
+/* the pixel's unit circle to texture space, so the footprint is the         */
+/* ellipse of covariance S = J J^T; adding the unit covariance of one texel  */
+/* (reconstruction) gives V = S + I, and a texel at offset d from the lookup */
+/* point has radius r^2 = d^T V^-1 d and weight e^(-2 r^2) - e^(-2) inside   */
+/* r^2 < 1 (a Gaussian truncated to the ellipse).                            */
+/* Level of detail: from the singular values s1 >= s2 of J in level-0        */
+/* texels (the ellipse's semi-axes): the minor axis is lengthened to         */
+/* s1/amax when s2 amax < s1, by adding (s1^2/amax^2 - s2^2) times the       */
+/* projector on the minor eigenvector, (s1^2 I - S)/(s1^2 - s2^2), to S;     */
+/* lod = max(0, log2(minor)) (a zero footprint has lod 0).  A footprint     */
+/* wider than the texture (lod > L-1) reads the last (1 x 1) level.          */
+/* Sampling (Sec. 2.2, "Sampling arrays"): the weights of the cells of the   */
+/* ellipse's bounding box are summed in scan order (rows t, then columns s), */
+/* and the sample takes the first cell whose running sum exceeds u W; the    */
+/* box's half-extents are sqrt(V_ss) and sqrt(V_tt), the ellipse's support   */
+/* along s and t.  Comparators: the EWA sums on levels floor(lod),           */
+/* floor(lod)+1 (weights 1-f, f), each normalised by its weight total.       */
+/* Binary32 decisions in the order written here, without contraction (the    */
+/* GPU follows the same sequence); the Gaussian uses the contract exp.       */
 /* ------------------------------------------------------------------------ */
-#define EWA_LUT 128
-static float ewa_lut[EWA_LUT];
-static void ewa_lut_init(void)
-{
-    const float e2 = orc_expc(-2.0f);
-    for (int i = 0; i < EWA_LUT; ++i) {
-        float r2 = (float)i / 127.0f;
-        ewa_lut[i] = orc_expc(-2.0f * r2) - e2;
-    }
-}
-
-ORC_EXPORT float orc_ewa_lut(int i)
-{
-    ewa_lut_init();
-    return ewa_lut[i];
-}
-
 typedef struct {
     float lod;
-    float a[2], b[2]; /* the axes after the anisotropy limit, texture units */
+    float vss, vtt, vst, det; /* S after the anisotropy limit (level-0 texels^2), det S */
 } ewa_frame;
 
 static ewa_frame ewa_setup(const float *q, int w, int h, int amax)
 {
     ewa_frame e;
-    float a0 = q[2], a1 = q[3], b0 = q[4], b1 = q[5];
-    float ax = (float)w * a0, ay = (float)h * a1, bx = (float)w * b0, by = (float)h * b1;
-    float la2 = ax * ax + ay * ay, lb2 = bx * bx + by * by;
-    if (la2 < lb2) {
-        float x = a0, y = a1, l = la2;
-        a0 = b0, a1 = b1, la2 = lb2;
-        b0 = x, b1 = y, lb2 = l;
+    /* J: columns d(s,t)/dx and d(s,t)/dy in level-0 texels */
+    const float jsx = (float)w * q[2], jtx = (float)h * q[3];
+    const float jsy = (float)w * q[4], jty = (float)h * q[5];
+    const float m = fmaxf(fmaxf(fabsf(jsx), fabsf(jtx)), fmaxf(fabsf(jsy), fabsf(jty)));
+    if (!(m < 0x1p40f)) {
+        /* s1 >= m, so the minor axis is at least 2^40/amax texels: beyond the
+         * last level of any pyramid (at most 2^15 texels wide) */
+        e.lod = INFINITY;
+        e.vss = e.vtt = e.vst = e.det = 0.0f;
+        return e;
     }
-    float la = sqrtf(la2), lb = sqrtf(lb2);
-    const float A = (float)amax;
-    if (lb > 0.0f && lb * A < la) {
-        float scale = la / (lb * A);
-        b0 = b0 * scale;
-        b1 = b1 * scale;
-        lb = lb * scale;
-    } else if (lb == 0.0f) {
-        lb = la / A;
+    float vss = jsx * jsx + jsy * jsy;
+    float vtt = jtx * jtx + jty * jty;
+    float vst = jsx * jtx + jsy * jty;
+    const float dj = jsx * jty - jtx * jsy;
+    float det = dj * dj;
+    const float half = (vss - vtt) * 0.5f, mean = (vss + vtt) * 0.5f;
+    const float lp = mean + sqrtf(half * half + vst * vst); /* larger eigenvalue of S */
+    const float s1 = sqrtf(lp);
+    float minor = lp > 0.0f ? fabsf(dj) / s1 : 0.0f;
+    if (minor * (float)amax < s1) {
+        const float lm = det / lp; /* smaller eigenvalue */
+        minor = s1 / (float)amax;
+        const float k = lp > lm ? (minor * minor - lm) / (lp - lm) : 1.0f;
+        vss = vss + k * (lp - vss);
+        vtt = vtt + k * (lp - vtt);
+        vst = vst - k * vst;
+        det = lp * (minor * minor);
     }
-    e.a[0] = a0, e.a[1] = a1, e.b[0] = b0, e.b[1] = b1;
-    e.lod = fmaxf(0.0f, orc_log2c(lb));
+    e.vss = vss, e.vtt = vtt, e.vst = vst, e.det = det;
+    e.lod = minor > 0.0f ? fmaxf(0.0f, orc_log2c(minor)) : 0.0f;
     return e;
 }
 
@@ -1652,74 +1642,79 @@ ORC_EXPORT float orc_ewa_lod(const float *q, int w, int h, int amax)
 }
 
 typedef struct {
-    float s, t, A, B, C;
-    int s0, s1, t0, t1;
+    float s, t;            /* lookup point in the level's raster coordinates */
+    float qss, qtt, q2st;  /* V^-1 (its off-diagonal doubled) */
+    int s0, s1, t0, t1;    /* bounding box of the ellipse */
 } ewa_level;
 
 static ewa_level ewa_at(const tex2d *tx, const float *q, const ewa_frame *e, int l)
 {
     ewa_level v;
-    int wl = lvl_dim(tx->w, l), hl = lvl_dim(tx->h, l);
-    float u = wrap_coord(tx->wrap, q[0]), w = wrap_coord(tx->wrap, q[1]);
-    v.s = u * (float)wl - 0.5f;
-    v.t = w * (float)hl - 0.5f;
-    float d00 = e->a[0] * (float)wl, d01 = e->a[1] * (float)hl;
-    float d10 = e->b[0] * (float)wl, d11 = e->b[1] * (float)hl;
-    float A = d01 * d01 + d11 * d11 + 1.0f;
-    float B = -2.0f * (d00 * d01 + d10 * d11);
-    float C = d00 * d00 + d10 * d10 + 1.0f;
-    float invF = 1.0f / (A * C - B * B * 0.25f);
-    A = A * invF;
-    B = B * invF;
-    C = C * invF;
-    float det = -B * B + 4.0f * A * C;
-    float invDet = 1.0f / det;
-    float uS = sqrtf(fmaxf(0.0f, det * C)), vS = sqrtf(fmaxf(0.0f, A * det));
-    v.s0 = (int)ceilf(v.s - 2.0f * invDet * uS);
-    v.s1 = (int)floorf(v.s + 2.0f * invDet * uS);
-    v.t0 = (int)ceilf(v.t - 2.0f * invDet * vS);
-    v.t1 = (int)floorf(v.t + 2.0f * invDet * vS);
-    v.A = A, v.B = B, v.C = C;
+    const int wl = lvl_dim(tx->w, l), hl = lvl_dim(tx->h, l);
+    const float fs = (float)wl / (float)tx->w, ft = (float)hl / (float)tx->h;
+    const float lss = e->vss * (fs * fs), ltt = e->vtt * (ft * ft), lst = e->vst * (fs * ft);
+    const float ldet = e->det * ((fs * fs) * (ft * ft));
+    const float a = lss + 1.0f, c = ltt + 1.0f;          /* V = S_l + I */
+    const float D = ((ldet + lss) + ltt) + 1.0f;          /* det V, a sum of non-negative terms */
+    v.qss = c / D;
+    v.qtt = a / D;
+    v.q2st = -(2.0f * lst) / D;
+    const float ex = sqrtf(a), ey = sqrtf(c);
+    v.s = wrap_coord(tx->wrap, q[0]) * (float)wl - 0.5f;
+    v.t = wrap_coord(tx->wrap, q[1]) * (float)hl - 0.5f;
+    v.s0 = (int)ceilf(v.s - ex);
+    v.s1 = (int)floorf(v.s + ex);
+    v.t0 = (int)ceilf(v.t - ey);
+    v.t1 = (int)floorf(v.t + ey);
     return v;
 }
 
-static int ewa_weight(const ewa_level *v, int is, int it, float *w)
+/* The truncated Gaussian of the ellipse radius; 0 outside (r^2 >= 1). */
+static float ewa_gauss(float r2)
 {
-    float ss = (float)is - v->s, tt = (float)it - v->t;
-    float r2 = v->A * (ss * ss) + v->B * ss * tt + v->C * (tt * tt);
     if (!(r2 < 1.0f))
-        return 0;
-    int idx = (int)(r2 * (float)EWA_LUT); /* r2 >= 0 up to rounding: index 0 */
-    if (idx > EWA_LUT - 1)
-        idx = EWA_LUT - 1;
-    if (idx < 0)
-        idx = 0;
-    *w = ewa_lut[idx];
-    return *w > 0.0f;
+        return 0.0f;
+    return orc_expc(-2.0f * r2) - orc_expc(-2.0f);
 }
 
-/* one texel by weighted reservoir sampling with one uniform; returns 0 when
- * no weight is positive (then the sample reads nothing) */
+ORC_EXPORT float orc_ewa_gauss(float r2)
+{
+    return ewa_gauss(r2);
+}
+
+static float ewa_weight(const ewa_level *v, int is, int it)
+{
+    const float ds = (float)is - v->s, dt = (float)it - v->t;
+    const float r2 = (v->qss * (ds * ds) + v->qtt * (dt * dt)) + v->q2st * (ds * dt);
+    return ewa_gauss(r2);
+}
+
+/* One texel by inverse CDF over the positive weights in scan order; returns
+ * 0 when no weight is positive (the sample then reads nothing). */
 static int ewa_pick(const ewa_level *v, float u, int *px, int *py)
 {
-    float sum = 0.0f;
-    int found = 0;
+    float W = 0.0f;
     for (int it = v->t0; it <= v->t1; ++it)
         for (int is = v->s0; is <= v->s1; ++is) {
-            float w;
-            if (!ewa_weight(v, is, it, &w))
-                continue;
-            sum += w;
-            float p = w / sum;
-            if (u < p) {
-                *px = is, *py = it;
-                found = 1;
-                u = u / p;
-            } else {
-                u = (u - p) / (1.0f - p);
-            }
+            const float w = ewa_weight(v, is, it);
+            if (w > 0.0f)
+                W = W + w;
         }
-    return found;
+    if (!(W > 0.0f))
+        return 0;
+    const float thr = u * W;
+    float S = 0.0f;
+    for (int it = v->t0; it <= v->t1; ++it)
+        for (int is = v->s0; is <= v->s1; ++is) {
+            const float w = ewa_weight(v, is, it);
+            if (!(w > 0.0f))
+                continue;
+            S = S + w;
+            *px = is, *py = it; /* the last positive cell if u W rounds up to W */
+            if (S > thr)
+                return 1;
+        }
+    return 1;
 }
 
 static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int spp, uint32_t seed, int amax,
@@ -1729,8 +1724,8 @@ static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int s
     ewa_frame e = ewa_setup(q, tx->w, tx->h, amax);
     const float lmax = (float)(tx->levels - 1);
     if (e.lod > lmax) {
-        /* a footprint wider than the whole texture reads texel (0, 0) of the
-         * coarsest level (as pbrt's EWA does) */
+        /* a footprint wider than the whole texture reads the one texel of the
+         * coarsest level */
         double texel[4], val[4];
         fetch2d(tx, tx->levels - 1, 0, 0, texel);
         shade2d(shade, ggx, texel, val);
@@ -1743,14 +1738,13 @@ static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int s
             }
         return;
     }
+    const float fl = floorf(e.lod);
     if (mode == M_STOCH) {
         double acc[4] = {0, 0, 0, 0};
         for (int s = 0; s < spp; ++s) {
             uint32_t key[4] = {(uint32_t)qi, (uint32_t)s, 0u, seed}, w[4];
             orc_pcg4d(key, w);
-            float lc = fminf(e.lod, lmax);
-            float fl = floorf(lc);
-            int l = (int)fl + (uniform24(w[3]) >= 1.0f - (lc - fl) ? 1 : 0);
+            int l = (int)fl + (uniform24(w[3]) >= 1.0f - (e.lod - fl) ? 1 : 0);
             if (l > tx->levels - 1)
                 l = tx->levels - 1;
             ewa_level v = ewa_at(tx, q, &e, l);
@@ -1775,10 +1769,8 @@ static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int s
         return;
     }
     double sum[4] = {0, 0, 0, 0};
-    float lc = fminf(e.lod, lmax);
-    float fl = floorf(lc);
     int lv[2] = {(int)fl, (int)fl + 1 > tx->levels - 1 ? tx->levels - 1 : (int)fl + 1};
-    double pl[2] = {1.0 - (double)(lc - fl), (double)(lc - fl)};
+    double pl[2] = {1.0 - (double)(e.lod - fl), (double)(e.lod - fl)};
     for (int li = 0; li < 2; ++li) {
         if (pl[li] == 0.0)
             continue;
@@ -1787,8 +1779,8 @@ static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int s
         double part[4] = {0, 0, 0, 0}, W = 0.0;
         for (int it = v.t0; it <= v.t1; ++it)
             for (int is = v.s0; is <= v.s1; ++is) {
-                float w;
-                if (!ewa_weight(&v, is, it, &w))
+                const float w = ewa_weight(&v, is, it);
+                if (!(w > 0.0f))
                     continue;
                 double texel[4], val[4];
                 fetch2d(tx, lv[li], wrap_tap(tx->wrap, is, wl), wrap_tap(tx->wrap, it, hl), texel);
@@ -1812,12 +1804,11 @@ static void ewa_one(const tex2d *tx, const float *q, int64_t qi, int mode, int s
             out[c] = sum[c];
 }
 
-/* Exact pick probabilities of the one-uniform reservoir at one level, by
- * running the chain on all 2^24 uniforms; P[(it - t0) * nx + (is - s0)]. */
+/* Exact pick probabilities at one level, by running the pick on all 2^24
+ * uniforms; P[(it - t0) * nx + (is - s0)]. */
 ORC_EXPORT int orc_ewa_pick_pmf(int w, int h, int levels, int wrap, const float *q, int amax, int level, double *P,
                                 int maxcells, int32_t *box)
 {
-    ewa_lut_init();
     const int64_t off0 = 0;
     tex2d tx = {NULL, w, h, levels, FMT_RGBA32F, wrap, MIP_LINEAR, &off0, NULL};
     ewa_frame e = ewa_setup(q, w, h, amax);
@@ -1858,11 +1849,10 @@ ORC_EXPORT void orc_ewa_box(int w, int h, int levels, const float *q, int amax, 
 }
 
 /* The normalised EWA weights at one level on the same box (binary64 of the
- * binary32 table weights). */
+ * binary32 weights). */
 ORC_EXPORT int orc_ewa_weights(int w, int h, int levels, int wrap, const float *q, int amax, int level, double *P,
                                int maxcells)
 {
-    ewa_lut_init();
     const int64_t off0 = 0;
     tex2d tx = {NULL, w, h, levels, FMT_RGBA32F, wrap, MIP_LINEAR, &off0, NULL};
     ewa_frame e = ewa_setup(q, w, h, amax);
@@ -1873,14 +1863,22 @@ ORC_EXPORT int orc_ewa_weights(int w, int h, int levels, int wrap, const float *
     double W = 0.0;
     for (int it = v.t0; it <= v.t1; ++it)
         for (int is = v.s0; is <= v.s1; ++is) {
-            float wt;
-            double x = ewa_weight(&v, is, it, &wt) ? (double)wt : 0.0;
+            const float wt = ewa_weight(&v, is, it);
+            const double x = wt > 0.0f ? (double)wt : 0.0;
             P[(it - v.t0) * nx + (is - v.s0)] = x;
             W += x;
         }
     for (int i = 0; i < nx * ny; ++i)
         P[i] /= W;
     return nx * ny;
+}
+
+/* The level-0 footprint frame after the anisotropy limit:
+ * {lod, S_ss, S_tt, S_st, det S}. */
+ORC_EXPORT void orc_ewa_frame(const float *q, int w, int h, int amax, float *out5)
+{
+    ewa_frame e = ewa_setup(q, w, h, amax);
+    out5[0] = e.lod, out5[1] = e.vss, out5[2] = e.vtt, out5[3] = e.vst, out5[4] = e.det;
 }
 
 /* queries: n x {u, v, du/dx, dv/dx, du/dy, dv/dy}; the texture's mip field
@@ -1894,8 +1892,6 @@ ORC_EXPORT int orc_filter2d_aniso(const void *base, int w, int h, int levels, in
     tex2d t = {(const uint8_t *)base, w, h, levels, fmt, wrap, MIP_LINEAR, level_off, dct_range};
     int ch = shade != 0 ? 3 : 4;
     int64_t m = subset ? nsub : n;
-    if (filter == F_EWA)
-        ewa_lut_init();
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i) {
         int64_t qi = subset ? subset[i] : i;

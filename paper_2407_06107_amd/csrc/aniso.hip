@@ -218,15 +218,18 @@ __global__ __launch_bounds__(256) void k_aniso_det(AnisoCall c)
     const float mu = lod.major_y ? qq[4] : qq[2], mv = lod.major_y ? qq[5] : qq[3];
     constexpr int NT = Taps<F>::n;
     constexpr int F0 = Taps<F>::first;
-    const double wp = 1.0 / (double)lod.nprobe;
-    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    // binary32 weights, compensated sums (up to 64 probes x 2 levels x 16 taps)
+    const float wp = 1.0f / (float)lod.nprobe;
+    CompSum sum[4];
+    for (int k = 0; k < 4; ++k)
+        sum[k].init();
     for (int k = 0; k < lod.nprobe; ++k) {
         const float o = ((float)k + 0.5f) / (float)lod.nprobe - 0.5f;
         const float uu = wrap_coord(c.tex.wrap, __builtin_fmaf(o, mu, qq[0]));
         const float vv = wrap_coord(c.tex.wrap, __builtin_fmaf(o, mv, qq[1]));
         for (int li = 0; li < 2; ++li) {
-            const double pl = li == 0 ? 1.0 - (double)f : (double)f;
-            if (pl == 0.0)
+            const float pl = li == 0 ? 1.0f - f : f;
+            if (pl == 0.0f)
                 continue;
             const int l = li == 0 ? l0 : l1;
             const int wl = max(1, c.tex.w >> l), hl = max(1, c.tex.h >> l);
@@ -238,139 +241,130 @@ __global__ __launch_bounds__(256) void k_aniso_det(AnisoCall c)
                 ix += tx >= 0.5f;
                 iy += ty >= 0.5f;
             }
-            double wx[4], wy[4];
-            axis_weights64<F>(tx, wx);
-            axis_weights64<F>(ty, wy);
+            float wx[4], wy[4];
+            axis_weights<F>(tx, wx);
+            axis_weights<F>(ty, wy);
 #pragma unroll
             for (int b = 0; b < NT; ++b) {
                 const int y = wrap_tap(c.tex.wrap, iy + F0 + b, hl);
 #pragma unroll
                 for (int a = 0; a < NT; ++a) {
-                    const double wgt = wp * pl * wx[a] * wy[b];
+                    const float wgt = ((wp * pl) * wx[a]) * wy[b];
                     const float4 t = texel(c.tex, l, wrap_tap(c.tex.wrap, ix + F0 + a, wl), y);
                     const float4 val = MODE == BEFORE ? t : shade<SHADE>(c.g, t);
-                    sum[0] += wgt * (double)val.x;
-                    sum[1] += wgt * (double)val.y;
-                    sum[2] += wgt * (double)val.z;
-                    sum[3] += wgt * (double)val.w;
+                    sum[0].add(wgt * val.x);
+                    sum[1].add(wgt * val.y);
+                    sum[2].add(wgt * val.z);
+                    sum[3].add(wgt * val.w);
                 }
             }
         }
     }
-    const float4 r = make_float4((float)sum[0], (float)sum[1], (float)sum[2], (float)sum[3]);
+    const float4 r = make_float4(sum[0].value(), sum[1].value(), sum[2].value(), sum[3].value());
     store<SHADE>(c.out, q, MODE == BEFORE ? shade<SHADE>(c.g, r) : r);
 }
 
 // ---------------------------------------------------------------- EWA
 // Elliptically weighted average and its stochastic form (Sec. 4.1: a level
-// from the ellipse's extent, then one texel by weighted reservoir sampling
-// over all EWA weights; Suppl. S.4, the EWA kernel).  The footprint ellipse
-// of the derivatives, regularised by one texel (the +1 of A and C), is
-// scanned over its bounding box row by row; weights e^(-2 r^2) - e^(-2) come
-// from a 128-entry table built per block in LDS.  All decisions are binary32
-// in the order written below (no contraction), so picks are reproducible
-// bit for bit.
-constexpr int EWA_LUT = 128;
-
+// from the ellipse's extent, then one texel drawn from all the EWA weights).
+// The footprint Jacobian J (columns d(s,t)/dx, d(s,t)/dy in level-0 texels)
+// gives the footprint covariance S = J J^T (Greene and Heckbert's EWA); the
+// minor axis (J's smaller singular value) is lengthened to major/amax beyond
+// the anisotropy limit by adding to S a multiple of the projector on the
+// minor eigenvector; lod = max(0, log2(minor)).  At a level, V = S_l + I
+// (one texel of reconstruction), a texel at offset d has radius
+// r^2 = d^T V^-1 d and weight e^(-2 r^2) - e^(-2) (contract exp) for
+// r^2 < 1, and the ellipse's bounding box has half-extents sqrt(V_ss),
+// sqrt(V_tt).  The stochastic form takes the first cell in scan order (rows,
+// then columns) whose running weight sum exceeds u W (Sec. 2.2, sampling
+// arrays): one pass for W, one for the pick.  All decisions are binary32 in
+// the order written below (no contraction), so picks are reproducible bit
+// for bit.
 struct EwaFrame {
     float lod;
-    float a0, a1, b0, b1;  // axes after the anisotropy limit, texture units
+    float vss, vtt, vst, det;  // S after the anisotropy limit, and det S
 };
 
-// Longer axis first (lengths in level-0 texels); the shorter lengthened to
-// longer/amax beyond the limit, a zero shorter axis counting as longer/amax;
-// lod = max(0, log2(shorter)).
 __device__ __forceinline__ EwaFrame ewa_frame(int W, int H, const float *q, int amax)
 {
-    float a0 = q[2], a1 = q[3], b0 = q[4], b1 = q[5];
-    const float ax = (float)W * a0, ay = (float)H * a1, bx = (float)W * b0, by = (float)H * b1;
-    float la2 = ax * ax + ay * ay, lb2 = bx * bx + by * by;
-    if (la2 < lb2) {
-        float x = a0, y = a1, l = la2;
-        a0 = b0, a1 = b1, la2 = lb2;
-        b0 = x, b1 = y, lb2 = l;
-    }
-    const float la = __builtin_sqrtf(la2);
-    float lb = __builtin_sqrtf(lb2);
-    const float A = (float)amax;
-    if (lb > 0.0f && lb * A < la) {
-        const float scale = la / (lb * A);
-        b0 = b0 * scale;
-        b1 = b1 * scale;
-        lb = lb * scale;
-    } else if (lb == 0.0f) {
-        lb = la / A;
-    }
     EwaFrame e;
-    e.a0 = a0, e.a1 = a1, e.b0 = b0, e.b1 = b1;
-    e.lod = __builtin_fmaxf(0.0f, log2c(lb));
+    const float jsx = (float)W * q[2], jtx = (float)H * q[3];
+    const float jsy = (float)W * q[4], jty = (float)H * q[5];
+    const float m = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(jsx), __builtin_fabsf(jtx)),
+                                    __builtin_fmaxf(__builtin_fabsf(jsy), __builtin_fabsf(jty)));
+    if (!(m < 0x1p40f)) {
+        // the major axis is at least m texels, so the minor at least
+        // 2^40/amax: beyond the last level of any pyramid
+        e.lod = __builtin_inff();
+        e.vss = e.vtt = e.vst = e.det = 0.0f;
+        return e;
+    }
+    float vss = jsx * jsx + jsy * jsy;
+    float vtt = jtx * jtx + jty * jty;
+    float vst = jsx * jtx + jsy * jty;
+    const float dj = jsx * jty - jtx * jsy;
+    float det = dj * dj;
+    const float half = (vss - vtt) * 0.5f, mean = (vss + vtt) * 0.5f;
+    const float lp = mean + __builtin_sqrtf(half * half + vst * vst);   // larger eigenvalue
+    const float s1 = __builtin_sqrtf(lp);
+    float minor = lp > 0.0f ? __builtin_fabsf(dj) / s1 : 0.0f;
+    if (minor * (float)amax < s1) {
+        const float lm = det / lp;   // smaller eigenvalue
+        minor = s1 / (float)amax;
+        const float k = lp > lm ? (minor * minor - lm) / (lp - lm) : 1.0f;
+        vss = vss + k * (lp - vss);
+        vtt = vtt + k * (lp - vtt);
+        vst = vst - k * vst;
+        det = lp * (minor * minor);
+    }
+    e.vss = vss, e.vtt = vtt, e.vst = vst, e.det = det;
+    e.lod = minor > 0.0f ? __builtin_fmaxf(0.0f, log2c(minor)) : 0.0f;
     return e;
 }
 
 struct EwaLevel {
-    float s, t, A, B, C;
+    float s, t, qss, qtt, q2st;
     int s0, s1, t0, t1;
 };
 
-// Ellipse coefficients and bounding box at level l (W_l x H_l texels) for
-// the wrapped coordinate (u, v).
-__device__ __forceinline__ EwaLevel ewa_level(int wl, int hl, float u, float v, const EwaFrame &e)
+// V^-1 and the bounding box at level l (wl x hl texels of a W x H texture)
+// for the wrapped coordinate (u, v).
+__device__ __forceinline__ EwaLevel ewa_level(int W, int H, int wl, int hl, float u, float v, const EwaFrame &e)
 {
     EwaLevel r;
+    const float fs = (float)wl / (float)W, ft = (float)hl / (float)H;
+    const float lss = e.vss * (fs * fs), ltt = e.vtt * (ft * ft), lst = e.vst * (fs * ft);
+    const float ldet = e.det * ((fs * fs) * (ft * ft));
+    const float a = lss + 1.0f, c = ltt + 1.0f;
+    const float D = ((ldet + lss) + ltt) + 1.0f;   // det V, non-negative terms
+    r.qss = c / D;
+    r.qtt = a / D;
+    r.q2st = -(2.0f * lst) / D;
+    const float ex = __builtin_sqrtf(a), ey = __builtin_sqrtf(c);
     r.s = u * (float)wl - 0.5f;
     r.t = v * (float)hl - 0.5f;
-    const float d00 = e.a0 * (float)wl, d01 = e.a1 * (float)hl;
-    const float d10 = e.b0 * (float)wl, d11 = e.b1 * (float)hl;
-    float A = d01 * d01 + d11 * d11 + 1.0f;
-    float B = -2.0f * (d00 * d01 + d10 * d11);
-    float C = d00 * d00 + d10 * d10 + 1.0f;
-    const float invF = 1.0f / (A * C - B * B * 0.25f);
-    A = A * invF;
-    B = B * invF;
-    C = C * invF;
-    const float det = -B * B + 4.0f * A * C;
-    const float invDet = 1.0f / det;
-    const float uS = __builtin_sqrtf(__builtin_fmaxf(0.0f, det * C));
-    const float vS = __builtin_sqrtf(__builtin_fmaxf(0.0f, A * det));
-    r.s0 = (int)__builtin_ceilf(r.s - 2.0f * invDet * uS);
-    r.s1 = (int)__builtin_floorf(r.s + 2.0f * invDet * uS);
-    r.t0 = (int)__builtin_ceilf(r.t - 2.0f * invDet * vS);
-    r.t1 = (int)__builtin_floorf(r.t + 2.0f * invDet * vS);
-    r.A = A, r.B = B, r.C = C;
+    r.s0 = (int)__builtin_ceilf(r.s - ex);
+    r.s1 = (int)__builtin_floorf(r.s + ex);
+    r.t0 = (int)__builtin_ceilf(r.t - ey);
+    r.t1 = (int)__builtin_floorf(r.t + ey);
     return r;
 }
 
-// Weight of cell (is, it): 0 outside the ellipse (r^2 >= 1).
-__device__ __forceinline__ float ewa_weight(const EwaLevel &v, const float *lut, int is, int it)
+// Weight of cell (is, it): 0 outside the ellipse (r^2 >= 1).  e2 = e^(-2)
+// by the contract exp.
+__device__ __forceinline__ float ewa_weight(const EwaLevel &v, float e2, int is, int it)
 {
-    const float ss = (float)is - v.s, tt = (float)it - v.t;
-    const float r2 = v.A * (ss * ss) + v.B * ss * tt + v.C * (tt * tt);
-    if (!(r2 < 1.0f))
-        return 0.0f;
-    const int idx = max(0, min((int)(r2 * (float)EWA_LUT), EWA_LUT - 1));
-    return lut[idx];
-}
-
-// Table of e^(-2 r^2) - e^(-2), r^2 = i/127, with the contract exp; the
-// block's first 128 threads fill it.
-__device__ __forceinline__ void ewa_fill_lut(float *lut)
-{
-    if (threadIdx.x < EWA_LUT) {
-        const float r2 = (float)threadIdx.x / 127.0f;
-        lut[threadIdx.x] = expc(-2.0f * r2) - expc(-2.0f);
-    }
-    __syncthreads();
+    const float ds = (float)is - v.s, dt = (float)it - v.t;
+    const float r2 = (v.qss * (ds * ds) + v.qtt * (dt * dt)) + v.q2st * (ds * dt);
+    return r2 < 1.0f ? expc(-2.0f * r2) - e2 : 0.0f;
 }
 
 // Stochastic EWA: per sample, key (query, sample, 0, seed); word 3 picks
-// level floor(lod) + [u >= 1 - f], word 0 drives the one-uniform reservoir
-// (the uniform is reused after each step: u/p on a pick, (u-p)/(1-p)
-// otherwise).  Samples of a query spread over G lanes.
+// level floor(lod) + [u >= 1 - f], word 0 is the uniform of the inverse-CDF
+// pick.  Samples of a query spread over G lanes.
 template <int SHADE>
 __global__ __launch_bounds__(256) void k_ewa_stoch(AnisoCall c, int log_g)
 {
-    __shared__ float lut[EWA_LUT];
-    ewa_fill_lut(lut);
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int G = 1 << log_g;
     const int64_t q = gid >> log_g;
@@ -407,29 +401,34 @@ __global__ __launch_bounds__(256) void k_ewa_stoch(AnisoCall c, int log_g)
                 }
             } else {
                 const float uu = wrap_coord(c.tex.wrap, qq[0]), vv = wrap_coord(c.tex.wrap, qq[1]);
-                const float lc = __builtin_fminf(e.lod, lmax);
-                const float fl = __builtin_floorf(lc);
-                const float th = 1.0f - (lc - fl);
+                const float fl = __builtin_floorf(e.lod);
+                const float th = 1.0f - (e.lod - fl);
+                const float e2 = expc(-2.0f);
                 for (int s = lane; s < c.spp; s += G) {
                     const uint4 w = pcg4d(make_uint4((uint32_t)q, (uint32_t)s, 0u, c.seed));
                     const int l = min((int)fl + (u24(w.w) >= th ? 1 : 0), L1);
                     const int wl = max(1, c.tex.w >> l), hl = max(1, c.tex.h >> l);
-                    const EwaLevel v = ewa_level(wl, hl, uu, vv, e);
-                    float u = u24(w.x), sum = 0.0f;
-                    int px = 0, py = 0;
-                    bool found = false;
+                    const EwaLevel v = ewa_level(c.tex.w, c.tex.h, wl, hl, uu, vv, e);
+                    float W = 0.0f;
                     for (int it = v.t0; it <= v.t1; ++it)
                         for (int is = v.s0; is <= v.s1; ++is) {
-                            const float wt = ewa_weight(v, lut, is, it);
+                            const float wt = ewa_weight(v, e2, is, it);
+                            W = wt > 0.0f ? W + wt : W;
+                        }
+                    const float thr = u24(w.x) * W;
+                    const bool found = W > 0.0f;
+                    float S = 0.0f;
+                    int px = 0, py = 0;
+                    bool done = !found;
+                    for (int it = v.t0; it <= v.t1 && !done; ++it)
+                        for (int is = v.s0; is <= v.s1 && !done; ++is) {
+                            const float wt = ewa_weight(v, e2, is, it);
                             if (!(wt > 0.0f))
                                 continue;
-                            sum += wt;
-                            const float p = wt / sum;
-                            const bool take = u < p;
-                            px = take ? is : px;
-                            py = take ? it : py;
-                            found |= take;
-                            u = (take ? u : u - p) / (take ? p : 1.0f - p);
+                            S = S + wt;
+                            px = is;   // the last positive cell if u W rounds up to W
+                            py = it;
+                            done = S > thr;
                         }
                     const int x = wrap_any(c.tex.wrap, px, wl), y = wrap_any(c.tex.wrap, py, hl);
                     if (c.taps) {
@@ -457,12 +456,10 @@ __global__ __launch_bounds__(256) void k_ewa_stoch(AnisoCall c, int log_g)
 }
 
 // Deterministic EWA on levels floor(lod), floor(lod)+1 (weights 1-f, f),
-// each normalised by its weight total; binary64 sums.
+// each normalised by its weight total; binary32 weights, compensated sums.
 template <int SHADE, int MODE>
 __global__ __launch_bounds__(256) void k_ewa_det(AnisoCall c)
 {
-    __shared__ float lut[EWA_LUT];
-    ewa_fill_lut(lut);
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= c.n)
         return;
@@ -483,38 +480,41 @@ __global__ __launch_bounds__(256) void k_ewa_det(AnisoCall c)
         return;
     }
     const float uu = wrap_coord(c.tex.wrap, qq[0]), vv = wrap_coord(c.tex.wrap, qq[1]);
-    const float lc = __builtin_fminf(e.lod, lmax);
-    const float fl = __builtin_floorf(lc);
-    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    const float fl = __builtin_floorf(e.lod);
+    const float e2 = expc(-2.0f);
+    float sum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int li = 0; li < 2; ++li) {
-        const double pl = li == 0 ? 1.0 - (double)(lc - fl) : (double)(lc - fl);
-        if (pl == 0.0)
+        const float pl = li == 0 ? 1.0f - (e.lod - fl) : e.lod - fl;
+        if (pl == 0.0f)
             continue;
         const int l = min((int)fl + li, L1);
         const int wl = max(1, c.tex.w >> l), hl = max(1, c.tex.h >> l);
-        const EwaLevel v = ewa_level(wl, hl, uu, vv, e);
-        double part[4] = {0.0, 0.0, 0.0, 0.0}, W = 0.0;
+        const EwaLevel v = ewa_level(c.tex.w, c.tex.h, wl, hl, uu, vv, e);
+        CompSum part[4], W;
+        W.init();
+        for (int k = 0; k < 4; ++k)
+            part[k].init();
         for (int it = v.t0; it <= v.t1; ++it) {
             const int y = wrap_any(c.tex.wrap, it, hl);
             for (int is = v.s0; is <= v.s1; ++is) {
-                const float wt = ewa_weight(v, lut, is, it);
+                const float wt = ewa_weight(v, e2, is, it);
                 if (!(wt > 0.0f))
                     continue;
                 const float4 t = texel(c.tex, l, wrap_any(c.tex.wrap, is, wl), y);
                 const float4 val = MODE == BEFORE ? t : shade<SHADE>(c.g, t);
-                const double wd = (double)wt;
-                W += wd;
-                part[0] += wd * (double)val.x;
-                part[1] += wd * (double)val.y;
-                part[2] += wd * (double)val.z;
-                part[3] += wd * (double)val.w;
+                W.add(wt);
+                part[0].add(wt * val.x);
+                part[1].add(wt * val.y);
+                part[2].add(wt * val.z);
+                part[3].add(wt * val.w);
             }
         }
-        if (W > 0.0)
+        const float Wv = W.value();
+        if (Wv > 0.0f)
             for (int k = 0; k < 4; ++k)
-                sum[k] += pl * part[k] / W;
+                sum[k] += pl * (part[k].value() / Wv);
     }
-    const float4 r = make_float4((float)sum[0], (float)sum[1], (float)sum[2], (float)sum[3]);
+    const float4 r = make_float4(sum[0], sum[1], sum[2], sum[3]);
     store<SHADE>(c.out, q, MODE == BEFORE ? shade<SHADE>(c.g, r) : r);
 }
 
