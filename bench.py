@@ -35,18 +35,13 @@ METRIC = "shaded queries/s: stochastic vs 64-tap tricubic at equal RMSE; HBM GB/
 N_PIX, RAYS_PER_PIX, STEPS, SIDE, GRID = 256, 16, 256, 0.25, 512
 HBM_PEAK_GBS = 8000.0
 # Non-packed VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, in
-# tera lane-operations per second (an FMA counts as one operation).
+# tera lane-operations per second (one wave64 VALU instruction occupies a
+# SIMD for 4 cycles, so a CU issues one per cycle).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Lane operations per ray step of the stochastic tricubic decision contract
-# plus its gather and accumulation: position (13), then hash (10), uniform
-# lattice indices (6: shift and convert per axis; the 2^-24 scale is folded
-# into the thresholds), thresholds (33), picks (21), address (12) and
-# accumulation (3).
-OPS_POSITION, OPS_OCCUPIED = 13, 85
-# The occupancy test of a step: brick coordinates (3 shifts), clamp to the
-# grid's bricks (3), brick index (2 shift-ors or 24-bit multiply-adds), word
-# index, bit extract and test.
-OPS_BRICK = 11
+# Algorithmic HBM bytes of one ray of the stochastic march: one binary16
+# voxel per step (256 x 2 B) plus the 32-byte ray record read and the 4-byte
+# transmittance written.
+BYTES_PER_RAY = STEPS * 2 + 32 + 4
 BRICK_LOG2 = 3
 
 
@@ -126,25 +121,31 @@ def cpu_baseline(grid_host, rays, seed, max_rays):
                       f"{dt:.2f} s wall on {oracle.num_threads()} threads"}
 
 
-def traffic_from_profile(code_digest):
-    """HBM bytes per launch measured by rocprofv3 FETCH_SIZE + WRITE_SIZE
-    (scaled by the plain-copy calibration), read from the committed profile
-    summary; None if the timed kernel's machine code differs from the code
-    the counters were taken on."""
-    path = os.path.join(ROOT, "profiles", "raymarch_stochastic_tricubic_512cloud_pmc.md")
-    if not os.path.exists(path) or code_digest is None:
-        return None
+PMC_PROFILE = os.path.join(ROOT, "profiles", "raymarch_stochastic_tricubic_512cloud_pmc.md")
+
+
+def counters_from_profile(code_digest):
+    """Per-launch hardware counters of the timed kernel read from the
+    committed rocprofv3 summary (its machine-readable list): HBM bytes
+    (FETCH_SIZE + WRITE_SIZE scaled by the plain-copy calibration) and the
+    VALU / memory instruction counts.  Empty if the timed kernel's machine
+    code differs from the code the counters were taken on."""
+    if not os.path.exists(PMC_PROFILE) or code_digest is None:
+        return {}
     fields = {}
-    for line in open(path):
+    for line in open(PMC_PROFILE):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
     if fields.get("kernel_code_sha256") != code_digest:
-        return None
-    try:
-        return float(fields["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for k, v in fields.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
 
 
 def count_occupied_steps(torch, occ, rays_d):
@@ -189,6 +190,30 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     t = e0.elapsed_time(e1) / reps * 1e-3
     del src, dst
     return 2 * nbytes / t / 1e9
+
+
+def gather_twin(torch, vol_occ, grid, rays_d, T):
+    """A launch of the benchmark-only gather twin (libsf_bench.so) on the
+    same rays, grid and occupancy mask as the timed kernel, on torch's
+    current stream."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2407_06107_amd", "libsf_bench.so"))
+    lib.sfb_gather_twin.restype = C.c_int
+    lib.sfb_gather_twin.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                    C.c_void_p]
+    nz, ny, nx = grid.shape
+    wmin = (C.c_float * 3)(0.0, 0.0, 0.0)
+    scale = (C.c_float * 3)(nx / SIDE, ny / SIDE, nz / SIDE)
+    occ = vol_occ.occupancy
+
+    def launch():
+        st = lib.sfb_gather_twin(C.c_void_p(grid.data_ptr()), nx, ny, nz, wmin, scale, C.c_void_p(occ.data_ptr()),
+                                 BRICK_LOG2, C.c_void_p(rays_d.data_ptr()), rays_d.shape[0], STEPS,
+                                 C.c_void_p(T.data_ptr()), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if st != 0:
+            raise RuntimeError(f"sfb_gather_twin failed: {st}")
+    return launch
 
 
 # The timed kernel: stochastic cubic B-spline, binary16 grid, independent
@@ -787,6 +812,57 @@ def neural_bench(args):
     print(json.dumps(line))
 
 
+def neural_pmc(args):
+    """Counter runs of the neural kernels at the config-4 and config-5 shapes:
+    seeded random latents (E4M3 codes and block scales for config 5, BF16
+    for config 4) and MLP weights built on the host and copied to the device,
+    so that no torch device kernel runs.  The decoders' work does not depend
+    on trained values: the same launches as the suite times (4 Mi rays x 128
+    steps; 2 Mi queries), then training steps of both shapes."""
+    import torch
+    import paper_2407_06107_amd as sf
+    from paper_2407_06107_amd import inputs
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(41)
+    side, L, C5 = 0.25, 256, 16
+    codes = rng.integers(0, 0x7E, size=L ** 3 * C5, dtype=np.uint8)       # finite E4M3 codes
+    codes[rng.random(codes.size) < 0.5] |= 0x80                             # either sign
+    scales = rng.uniform(1e-3, 1e-2, size=(L // 8) ** 3).astype(np.float32)
+    grid5 = sf.LatentGrid(3, (L, L, L), C5, sf.SF_LATENT_FP8E4M3, torch.from_numpy(codes).cuda(),
+                          torch.from_numpy(scales).cuda(), 3, (0.0, 0.0, 0.0), (L / side,) * 3)
+    mlp5 = sf.MLP(torch.from_numpy(_init_mlp(rng, C5, 1)).cuda(), C5, 1)
+    rays = torch.from_numpy(inputs.ortho_rays(512, 16, side=side, seed=12)).cuda()
+    T = torch.empty(rays.shape[0], dtype=torch.float32, device="cuda")
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=4)
+    t5 = time_launches(lambda: sf.sf_neural_raymarch(grid5, mlp5, rays, 128, smp, T=T), 3, 1, torch)
+    del grid5, codes
+    R = 1024
+    b16 = rng.integers(0x3C00, 0x3F80, size=R * R * 8, dtype=np.uint16)   # BF16 bits of 2^-7 .. 1
+    b16[rng.random(b16.size) < 0.5] |= 0x8000
+    lat4 = torch.from_numpy(b16.view(np.int16)).cuda()
+    grid4 = sf.LatentGrid(2, (R, R), 8, sf.SF_LATENT_BF16, lat4)
+    mlp4 = sf.MLP(torch.from_numpy(_init_mlp(rng, 8, 4)).cuda(), 8, 4)
+    q = torch.from_numpy(inputs.queries_uniform(2 * 1024 * 1024, seed=6)).cuda()
+    out = torch.empty((q.shape[0], 3), dtype=torch.float32, device="cuda")
+    s4 = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=3)
+    t4 = time_launches(lambda: sf.sf_neural_decode(grid4, mlp4, q, s4, sf.SF_SHADE_GGX, sf.ggx(), out=out), 3, 1,
+                       torch)
+    times = {"neural_ray_ms": t5, "neural2d_ms": t4}
+    for name, (n, C, O, batch) in {"train5": (L ** 3, 16, 1, 262144), "train4": (R * R, 8, 4, 65536)}.items():
+        lat = torch.from_numpy((rng.standard_normal(n * C, dtype=np.float32) * 0.5)).cuda()
+        tg = torch.from_numpy(rng.random(n * O, dtype=np.float32)).cuda()
+        idx = torch.from_numpy(rng.permutation(n)[:batch].astype(np.int32)).cuda()
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        for tag, compute in (("", sf.SF_TRAIN_BF16), ("_fp32", sf.SF_TRAIN_FP32)):
+            st = sf.TrainState(lat, torch.from_numpy(_init_mlp(rng, C, O)).cuda(), C, O, compute=compute)
+            times[name + tag + "_ms"] = time_launches(
+                lambda: sf.sf_neural_train_step(st, idx, tg, 1e-2, 1e-3, loss_out=loss), 3, 1, torch)
+            del st
+        del lat, tg
+    print(json.dumps(times))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -801,6 +877,12 @@ def main():
     ap.add_argument("--suite-planck", action="store_true", help="only the emission section of the suite")
     ap.add_argument("--epochs4", type=int, default=200)
     ap.add_argument("--epochs5", type=int, default=60)
+    ap.add_argument("--save-inputs", default="", help="write the headline workload (grid, rays) to this .npz and exit")
+    ap.add_argument("--load-inputs", default="", help="read the headline workload from this .npz")
+    ap.add_argument("--pmc-neural", action="store_true",
+                    help="counter runs of the neural decoders and training steps on seeded random data")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="counter runs: time the headline kernel and its gather twin only, launch nothing else")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -820,12 +902,24 @@ def main():
     if args.suite:
         neural_bench(args)
         return
+    if args.pmc_neural:
+        neural_pmc(args)
+        return
 
     import torch
     import paper_2407_06107_amd as sf
     from paper_2407_06107_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.save_inputs:
+        # the workload, written once for counter runs (which then launch no
+        # torch device kernel besides the calibration copy)
+        log("generating workload")
+        grid = inputs.cloud_grid(GRID, seed=4, device="cuda").cpu()
+        rays = inputs.ortho_rays(N_PIX, RAYS_PER_PIX, side=SIDE, seed=11)
+        np.savez(args.save_inputs, grid=grid.view(torch.int16).numpy(), rays=rays)
+        log(f"wrote {args.save_inputs}")
+        return
     if args.copy_probe:
         # a plain streaming kernel of known traffic: reads and writes
         # copy_probe bytes (torch's elementwise negation)
@@ -834,9 +928,15 @@ def main():
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    log("generating workload")
-    grid = inputs.cloud_grid(GRID, seed=4, device="cuda")
-    rays = inputs.ortho_rays(N_PIX, RAYS_PER_PIX, side=SIDE, seed=11)
+    if args.load_inputs:
+        log(f"loading workload from {args.load_inputs}")
+        z = np.load(args.load_inputs)
+        grid = torch.from_numpy(z["grid"]).view(torch.float16).cuda()   # host-to-device copies only
+        rays = z["rays"]
+    else:
+        log("generating workload")
+        grid = inputs.cloud_grid(GRID, seed=4, device="cuda")
+        rays = inputs.ortho_rays(N_PIX, RAYS_PER_PIX, side=SIDE, seed=11)
     rays_d = torch.from_numpy(rays).cuda()
     n = rays.shape[0]
     # Every path runs with the 8^3 occupancy mask (exact empty-space
@@ -866,18 +966,27 @@ def main():
     queries = n * STEPS
     value = queries / (ms * 1e-3)
 
-    # algorithmic work of one launch: every ray of the stream is read (32 B)
-    # and its T written (4 B); every step of a ray that meets the grid forms
-    # its position and tests its brick; a step in an occupied brick hashes,
-    # picks, gathers one binary16 voxel and accumulates.
+    log("timing the gather-only twin")
+    twin_fn = gather_twin(torch, vol_occ, grid, rays_d, T)
+    t_twin = time_launches(twin_fn, args.steps, args.warmup, torch)
+    t_real = time_launches(fn, args.steps, args.warmup, torch)
+    if args.pmc_run:
+        # counter runs: the kernels have run; nothing else touches the device
+        print(json.dumps({"ms_per_step": ms, "gather_twin_ms": t_twin, "ms_again": t_real}))
+        return
+
+    # algorithmic HBM bytes of one launch (548 B per ray: one binary16 voxel
+    # per step, the ray record and the result), and the bytes of the steps
+    # the kernel actually gathers (steps of rays that meet the grid, in
+    # occupied bricks)
     hit = rays[:, 7] > rays[:, 6]
     hit_steps = int(hit.sum()) * STEPS
     occ_steps = count_occupied_steps(torch, vol_occ.occupancy, rays_d)
-    algo_bytes = occ_steps * 2 + n * 32 + n * 4
-    achieved_gbs = algo_bytes / (ms * 1e-3) / 1e9
-    algo_ops = hit_steps * (OPS_POSITION + OPS_BRICK) + occ_steps * OPS_OCCUPIED
-    achieved_tops = algo_ops / (ms * 1e-3) / 1e12
-    traffic = traffic_from_profile(kernel_code_digest())
+    algo_bytes = n * BYTES_PER_RAY
+    gathered_bytes = occ_steps * 2 + n * 36
+    counters = counters_from_profile(kernel_code_digest())
+    valu = counters.get("valu_insts_per_launch")
+    achieved_tops = valu * 64 / (ms * 1e-3) / 1e12 if valu else None
 
     extra = {}
     if not args.no_compare:
@@ -893,9 +1002,6 @@ def main():
             v2 = vol_plain if name.endswith("without_mask") else vol_occ
             t = time_launches(lambda: sf.sf_raymarch(v2, rays_d, STEPS, s2, T=T), 5, 2, torch)
             rates[name] = {"ms": t, "queries_per_s": queries / (t * 1e-3)}
-        rates["tricubic_stochastic_without_mask"]["valu_frac"] = (
-            hit_steps * (OPS_POSITION + OPS_OCCUPIED) / (rates["tricubic_stochastic_without_mask"]["ms"] * 1e-3)
-            / 1e12 / VALU_PEAK_TOPS)
         extra["comparators"] = rates
         log("equal-RMSE protocol")
         extra["equal_rmse_vs_tricubic_after"] = equal_rmse(sf, torch, vol_occ, rays_d, ms,
@@ -922,19 +1028,30 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "precision": "binary16 texels, binary32 decisions, binary64 optical depth",
+        "precision": "binary16 texels, binary32 decisions, compensated binary32 optical depth",
         "data": "synthetic: fractal-noise cloud stands in for the Disney Cloud",
         "config": {"workload": "512^3 fp16 cloud, 1,048,576 rays (256x256 px x 16), 256 steps, "
                                "stochastic tricubic transmittance, 1 lookup per step, 8^3 occupancy bricks",
                    "rays": n, "steps": STEPS, "grid": [GRID, GRID, GRID], "parallelism": "single GPU"},
         "rays_per_s": n / (ms * 1e-3),
-        "hbm_algorithmic_gbs": achieved_gbs,
-        "hbm_algorithmic_frac": achieved_gbs / HBM_PEAK_GBS,
-        "hbm_copy_gbs": copy_gbs,
-        "hbm_algorithmic_frac_of_copy": achieved_gbs / copy_gbs,
+        # the kernel is bound by VALU issue: achieved = the VALU lane-operations
+        # it issues per launch (the SQ_INSTS_VALU counter of the committed
+        # rocprofv3 run x 64 lanes) over the launch's HIP-event duration, null
+        # when the counters were taken on other machine code
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": traffic,
-                     "algorithmic_ops": algo_ops, "algorithmic_bytes": algo_bytes},
+                     "frac": achieved_tops / VALU_PEAK_TOPS if achieved_tops else None,
+                     "traffic": counters.get("hbm_bytes_per_launch"),
+                     "valu_insts_per_launch": valu,
+                     "valu_busy_frac": counters.get("valu_busy_frac"),
+                     "counters": os.path.relpath(PMC_PROFILE, ROOT)},
+        # the gather ceiling of this access pattern: the same launch with the
+        # random pick replaced by a fixed tap (libsf_bench.so), t(twin) / t(real)
+        "gather_twin_frac": t_twin / t_real,
+        "gather_twin_ms": t_twin,
+        "hbm_roofline": {"achieved": algo_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": algo_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_per_ray": BYTES_PER_RAY,
+                         "algorithmic_bytes": algo_bytes, "gathered_bytes": gathered_bytes,
+                         "copy_gbs": copy_gbs},
         "ray_steps": hit_steps,
         "ray_steps_in_occupied_bricks": occ_steps,
         "cpu_baseline": cpu,

@@ -18,6 +18,10 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsf.so")
+# The benchmark's gather-only twin of the stochastic ray march, in a library
+# of its own that no product path loads.
+BENCH_SOURCES = ["bench_gather_twin.hip"]
+BENCH_LIB = os.path.join(PKG, "libsf_bench.so")
 
 # Per-source flags: the neural decoder's matrix-core accumulators live in
 # ordinary VGPRs (gfx950 MFMA accepts them), so the bias / ReLU / packing
@@ -58,14 +62,15 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(jobs, len(SOURCES))) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    with ThreadPoolExecutor(max_workers=min(jobs, len(SOURCES) + len(BENCH_SOURCES))) as ex:
+        objs = list(ex.map(compile_one, SOURCES + BENCH_SOURCES))
+    for lib, part in ((LIB, objs[:len(SOURCES)]), (BENCH_LIB, objs[len(SOURCES):])):
+        tmp = lib + ".tmp"
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *part, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link of {os.path.basename(lib)} failed:\n{r.stderr}")
+        os.replace(tmp, lib)
     return LIB
 
 
