@@ -269,3 +269,122 @@ def test_training_converges_and_decodes(sf, orc):
     dec = sf.sf_neural_decode_lattice(grid, mlp, torch.arange(R * R, device="cuda", dtype=torch.int64))
     rmse = torch.sqrt(torch.mean((dec - targets) ** 2)).item()
     assert rmse < 0.05, rmse
+
+
+# ------------------------------------------------ config 4 and 5 at full size
+def test_neural_filter2d_config4_full_sampled(sf, orc):
+    """Config 4 at its size, in the launch the benchmark times: a 1024^2 x 8
+    BF16 latent texture, the 8-64-64-4 MLP, 2 Mi uniform queries shaded by
+    GGX + Lambert, stochastic B-spline (one decode) and the 16-decode
+    filter-after and filter-before comparators.  3000 sampled queries (the
+    ragged tail among them) against the oracle; every stochastic tap of the
+    sample bit-exact.  Latents and weights are seeded random values: the
+    decoder's arithmetic does not depend on them being trained."""
+    R, n = 1024, 2 * 1024 * 1024
+    rng = np.random.default_rng(61)
+    lat = (rng.standard_normal(R * R * 8, dtype=np.float32) * np.float32(0.7)).reshape(R * R, 8)
+    grid = sf.sf_neural_quantize(torch.from_numpy(lat.ravel()).cuda(), 2, (R, R), 8, sf.SF_LATENT_BF16)
+    Z = _bf16(lat)
+    P = _params(8, 4, 62)
+    mlp = sf.MLP(torch.from_numpy(P).cuda(), 8, 4)
+    q = inputs.queries_uniform(n, seed=6)
+    qd = torch.from_numpy(q).cuda()
+    sub = np.unique(np.concatenate([rng.choice(n - 500, 2500, replace=False), np.arange(n - 500, n)]))
+    for mode in ("STOCHASTIC", "AFTER", "BEFORE"):
+        _case("neural_filter2d_config4_full", mode)
+        m = {"STOCHASTIC": sf.SF_STOCHASTIC, "AFTER": sf.SF_AFTER_EXACT, "BEFORE": sf.SF_BEFORE}[mode]
+        smp = sf.sampling(sf.SF_BSPLINE3, m, 1, seed=3)
+        out = sf.sf_neural_decode(grid, mlp, qd, smp, shade=sf.SF_SHADE_GGX, ggx_params=sf.ggx()).cpu().numpy()
+        om = {"STOCHASTIC": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+        res_ = orc.neural_filter2d((R, R), 8, H, 4, Z, _bf16(P), q, orc.BSPLINE3, om, spp=1, seed=3, shade=1,
+                                   act_bf16=True, taps=mode == "STOCHASTIC", subset=sub)
+        if mode == "STOCHASTIC":
+            ref, rt = res_
+            taps = torch.empty((n, 1, 2), dtype=torch.int32, device="cuda")
+            out_t = sf.sf_neural_decode(grid, mlp, qd, smp, shade=sf.SF_SHADE_GGX, ggx_params=sf.ggx(),
+                                        dbg_taps=taps).cpu().numpy()
+            assert np.array_equal(taps.cpu().numpy()[sub], rt)
+            assert np.array_equal(out_t, out)   # the tap dump changes nothing else
+        else:
+            ref = res_
+        _close_bf16(out[sub], ref)
+
+
+def test_neural_quantize_config5_full_sampled_blocks(sf, orc):
+    """The E4M3 quantiser at config 5's size (256^3 x 16 FP32 latents, 8^3
+    blocks): the codes and scale of 48 sampled blocks, corner blocks among
+    them, equal the oracle's quantisation of each block alone, bit for bit
+    (a block's scale and codes depend only on its own values)."""
+    _case("quantize_config5_full")
+    L, C, B = 256, 16, 8
+    rng = np.random.default_rng(63)
+    lat = rng.standard_normal(L ** 3 * C, dtype=np.float32) * np.float32(0.5)
+    lat[: 4096 * C] *= np.float32(100.0)        # a slab of much larger values
+    grid = sf.sf_neural_quantize(torch.from_numpy(lat).cuda(), 3, (L, L, L), C, sf.SF_LATENT_FP8E4M3, 3,
+                                 (0.0, 0.0, 0.0), (L / 0.25,) * 3)
+    nb = L // B
+    blocks = np.concatenate([[0, nb - 1, nb ** 3 - 1, nb * nb * (nb - 1)], rng.choice(nb ** 3, 44, replace=False)])
+    lat4 = lat.reshape(L, L, L, C)
+    scales = grid.scales.cpu().numpy()
+    for b in blocks:
+        bz, by, bx = b // (nb * nb), (b // nb) % nb, b % nb
+        vals = np.ascontiguousarray(lat4[bz * B:(bz + 1) * B, by * B:(by + 1) * B, bx * B:(bx + 1) * B])
+        codes, sc = orc.quantize_fp8(vals.ravel(), 3, (B, B, B), C, 3)
+        zz, yy, xx = np.meshgrid(np.arange(bz * B, bz * B + B), np.arange(by * B, by * B + B),
+                                 np.arange(bx * B, bx * B + B), indexing="ij")
+        lin = ((zz * L + yy) * L + xx).ravel()
+        got = grid.latents.view(L ** 3, C)[torch.from_numpy(lin).cuda()].cpu().numpy()
+        assert np.array_equal(got.ravel(), codes), b
+        assert scales[b] == sc[0], (b, scales[b], sc[0])
+
+
+def test_neural_raymarch_config5_full_sampled(sf, orc):
+    """Config 5 at its size, in the launch the benchmark times: a 256^3 x 16
+    E4M3 latent volume with 8^3 block scales over a cube of side 0.25, the
+    16-64-64-1 MLP, 512^2 pixels x 16 orthographic rays (4 Mi) x 128 steps,
+    stochastic tricubic on the latent lattice.  The codes and scales are
+    seeded inputs given to both sides.  450 sampled rays (misses among them)
+    against the oracle; their taps, taken from a tap-dump launch over all
+    4 Mi rays, bit-exact; and that launch's transmittances equal the timed
+    launch's."""
+    _case("neural_raymarch_config5_full")
+    L, C, side, steps = 256, 16, 0.25, 128
+    rng = np.random.default_rng(64)
+    # E4M3 codes of magnitudes 1/4 .. 7.5 (exponent fields 5..9, any mantissa), either sign
+    codes = (rng.integers(5, 10, size=L ** 3 * C, dtype=np.uint8) << 3) | rng.integers(0, 8, size=L ** 3 * C,
+                                                                                          dtype=np.uint8)
+    codes[rng.random(codes.size) < 0.5] |= 0x80
+    nb = L // 8
+    scales = rng.uniform(0.1, 0.5, size=nb ** 3).astype(np.float32)
+    grid = sf.LatentGrid(3, (L, L, L), C, sf.SF_LATENT_FP8E4M3, torch.from_numpy(codes).cuda(),
+                         torch.from_numpy(scales).cuda(), 3, (0.0, 0.0, 0.0), (L / side,) * 3)
+    P = _params(C, 1, 65, scale=0.2)
+    P[-1] = 3.0
+    mlp = sf.MLP(torch.from_numpy(P).cuda(), C, 1)
+    rays = inputs.ortho_rays(512, 16, side=side, seed=12)
+    n = rays.shape[0]
+    rd = torch.from_numpy(rays).cuda()
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=4)
+    T = sf.sf_neural_raymarch(grid, mlp, rd, steps, smp).cpu().numpy()
+    taps_d = torch.empty((n, 1, steps, 3), dtype=torch.int32, device="cuda")
+    T_dbg = sf.sf_neural_raymarch(grid, mlp, rd, steps, smp, dbg_taps=taps_d).cpu().numpy()
+    assert np.array_equal(T_dbg, T, equal_nan=True)
+    hit = np.nonzero(rays[:, 7] > rays[:, 6])[0]
+    miss = np.nonzero(~(rays[:, 7] > rays[:, 6]))[0]
+    sub = np.unique(np.concatenate([rng.choice(hit, 400, replace=False), rng.choice(miss, 50, replace=False),
+                                    np.arange(n - 8, n)]))
+    taps = taps_d[torch.from_numpy(sub).cuda()].cpu().numpy()
+    del taps_d
+    torch.cuda.empty_cache()
+    # the oracle decodes the same codes by the E4M3 definition times the block scale
+    i = np.arange(L)
+    blk = ((i[:, None, None] >> 3) * nb * nb + (i[None, :, None] >> 3) * nb + (i[None, None, :] >> 3)).ravel()
+    Z = orc.fp8_table()[codes.reshape(-1, C)]
+    Z *= scales[blk][:, None].astype(np.float64)
+    ref, rt = orc.neural_raymarch((L, L, L), C, H, Z, _bf16(P), (0, 0, 0), np.array((L / side,) * 3, np.float32),
+                                  rays, steps, orc.BSPLINE3, orc.STOCHASTIC, spp=1, seed=4, act_bf16=True, taps=True,
+                                  subset=sub)
+    assert np.array_equal(taps, rt)
+    assert np.all(T[miss] == 1.0)
+    assert 0.05 < np.median(ref[np.isin(sub, hit)]) < 0.95   # a medium neither empty nor opaque
+    _close_bf16(T[sub], ref)
