@@ -572,13 +572,22 @@ sf_status sf_neural_quantize(const float *latents, const sf_latent_grid *grid, v
 
 /* Training state, all FP32 device arrays updated in place by a step:
  * latents [n_lattice x channels], params (packed, sf_mlp layout), and the
- * Adam moments of both. */
+ * Adam moments of both (FP32 master copies in either compute mode). */
 typedef struct sf_train_state {
     float *latents, *params, *m_latents, *v_latents, *m_params, *v_params;
     int64_t n_lattice;
     int32_t channels, hidden, out_dim;
-    int32_t reserved; /* must be 0 */
+    int32_t compute; /* SF_TRAIN_BF16 (0) or SF_TRAIN_FP32 (1) */
 } sf_train_state;
+
+/* How a training step computes its products:
+ *   SF_TRAIN_BF16  matrix cores: BF16 operands (latents, weights, hidden
+ *                  activations and the pre-activation gradients rounded to
+ *                  nearest even), FP32 accumulation; forward, backward and
+ *                  the weight gradients (K = the batch's samples) on
+ *                  v_mfma_f32_16x16x{16,32}_bf16.
+ *   SF_TRAIN_FP32  the vector ALU in FP32 throughout (reference mode). */
+enum { SF_TRAIN_BF16 = 0, SF_TRAIN_FP32 = 1 };
 
 /*
  * sf_neural_train_step — one Adam step (beta 0.9/0.999, eps 1e-8, bias
@@ -590,7 +599,14 @@ typedef struct sf_train_state {
  *   grad_params (nullable): the summed parameter gradient; grad_latents
  *   (nullable): batch x channels latent gradients.
  *   workspace: sf_neural_train_workspace() bytes of device scratch.
- * Errors: SF_E_NULL, SF_E_RANGE, SF_E_UNSUPPORTED (shape), SF_E_WORKSPACE.
+ *   st->compute selects the matrix-core BF16 step or the FP32 one; both
+ *   keep the state in FP32 and reduce the parameter gradients in a fixed
+ *   order (bit-reproducible for a given batch).
+ * Defines: the training of the learned stand-in (the paper trains no
+ * network; the objective is this library's reading, a lattice-point
+ * autodecoder fitted to texels the plain method generates).
+ * Errors: SF_E_NULL, SF_E_RANGE (also compute outside 0..1),
+ * SF_E_UNSUPPORTED (shape), SF_E_WORKSPACE.
  */
 sf_status sf_neural_train_step(const sf_train_state *st, const int32_t *batch_idx, const float *targets,
                                int64_t batch, int32_t step, float lr_latent, float lr_mlp, float *loss_out,

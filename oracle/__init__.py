@@ -150,7 +150,7 @@ def lib():
         L.orc_quantize_fp8.argtypes = [P, i32, P, i32, i32, P, P]
         L.orc_mlp_forward.argtypes = [i32, i32, i32, P, P, i64, i32, P]
         L.orc_mlp_grad.restype = C.c_double
-        L.orc_mlp_grad.argtypes = [i32, i32, i32, P, P, P, i64, P, P]
+        L.orc_mlp_grad.argtypes = [i32, i32, i32, P, P, P, i64, i32, P, P]
         L.orc_adam.argtypes = [P, P, P, P, i64, i32, C.c_double]
         L.orc_neural_filter2d.argtypes = [i32, i32, i32, i32, i32, P, P, i32, P, i64, i32, i32, i32, u32, i32, P,
                                           P, P, P, i64]
@@ -677,13 +677,13 @@ def mlp_forward(C, H, O, P, Z, act_bf16=False):
     return Y
 
 
-def mlp_grad(C, H, O, P, Z, T):
+def mlp_grad(C, H, O, P, Z, T, act_bf16=False):
     P = _c(P, np.float64)
     Z = _c(Z, np.float64).reshape(-1, C)
     T = _c(T, np.float64).reshape(-1, O)
     gP = np.zeros(P.size)
     gZ = np.zeros_like(Z)
-    loss = lib().orc_mlp_grad(C, H, O, _p(P), _p(Z), _p(T), Z.shape[0], _p(gP), _p(gZ))
+    loss = lib().orc_mlp_grad(C, H, O, _p(P), _p(Z), _p(T), Z.shape[0], int(act_bf16), _p(gP), _p(gZ))
     return loss, gP, gZ
 
 

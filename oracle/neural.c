@@ -182,9 +182,11 @@ ORC_EXPORT void orc_mlp_forward(int C, int H, int O, const double *P, const doub
 
 /* Gradients of the batch loss (1/B) sum_s ||y_s - t_s||^2 with respect to
  * the packed parameters (gP, summed over the batch) and to each sample's
- * latent (gZ, B x C).  Returns the loss. */
+ * latent (gZ, B x C).  Returns the loss.  act_bf16: the hidden activations
+ * are stored in BF16 as a matrix-core implementation reads them (the same
+ * reading as the decoder's); everything else is FP64. */
 ORC_EXPORT double orc_mlp_grad(int C, int H, int O, const double *P, const double *Z, const double *T, int64_t B,
-                               double *gP, double *gZ)
+                               int act_bf16, double *gP, double *gZ)
 {
     dims_t d = {C, H, O};
     const double *W1 = P, *W2 = W1 + C * H + H, *W3 = W2 + H * H + H;
@@ -195,7 +197,7 @@ ORC_EXPORT double orc_mlp_grad(int C, int H, int O, const double *P, const doubl
     double a1[256], h1[256], a2[256], h2[256], y[16], dy[16], da2[256], da1[256];
     for (int64_t s = 0; s < B; ++s) {
         const double *z = Z + s * C;
-        mlp_forward(d, P, z, 0, a1, h1, a2, h2, y);
+        mlp_forward(d, P, z, act_bf16, a1, h1, a2, h2, y);
         for (int o = 0; o < O; ++o) {
             double e = y[o] - T[s * O + o];
             loss += e * e;

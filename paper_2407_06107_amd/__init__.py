@@ -39,6 +39,7 @@ EXPORTED = ("sf_filter2d", "sf_filter2d_aniso", "sf_dct_layout", "sf_dct_encode"
             "sf_error_stats", "sf_error_stats_workspace", "sf_error_stats_noalloc",
             "sf_error_stats_noalloc_max_bytes", "sf_last_error", "sf_abi_version", "sf_rng_version")
 SF_LATENT_F32, SF_LATENT_BF16, SF_LATENT_FP8E4M3 = 0, 1, 2
+SF_TRAIN_BF16, SF_TRAIN_FP32 = 0, 1
 
 
 class sf_sampling(C.Structure):
@@ -78,7 +79,7 @@ class sf_train_state(C.Structure):
     _fields_ = [("latents", C.c_void_p), ("params", C.c_void_p), ("m_latents", C.c_void_p),
                 ("v_latents", C.c_void_p), ("m_params", C.c_void_p), ("v_params", C.c_void_p),
                 ("n_lattice", C.c_int64), ("channels", C.c_int32), ("hidden", C.c_int32), ("out_dim", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("compute", C.c_int32)]
 
 
 class SFError(RuntimeError):
@@ -573,9 +574,12 @@ def sf_neural_decode_lattice(grid: LatentGrid, mlp: MLP, idx: torch.Tensor, out:
 
 
 class TrainState:
-    """FP32 master latents and MLP parameters with their Adam moments."""
+    """FP32 master latents and MLP parameters with their Adam moments, the
+    step count, and how the steps compute (SF_TRAIN_BF16 on the matrix cores,
+    SF_TRAIN_FP32 on the vector ALU)."""
 
-    def __init__(self, latents: torch.Tensor, params: torch.Tensor, channels: int, out_dim: int, hidden: int = 64):
+    def __init__(self, latents: torch.Tensor, params: torch.Tensor, channels: int, out_dim: int, hidden: int = 64,
+                 compute: int = SF_TRAIN_BF16):
         _need(latents, torch.float32, "latents")
         _need(params, torch.float32, "params")
         if params.numel() != sf_mlp_nparams(channels, hidden, out_dim) or latents.numel() % channels:
@@ -586,10 +590,43 @@ class TrainState:
         self.channels, self.out_dim, self.hidden = channels, out_dim, hidden
         self.n_lattice = latents.numel() // channels
         self.step = 0
-        self.desc = sf_train_state(latents.data_ptr(), params.data_ptr(), self.m_lat.data_ptr(),
-                                   self.v_lat.data_ptr(), self.m_par.data_ptr(), self.v_par.data_ptr(),
-                                   self.n_lattice, channels, hidden, out_dim, 0)
+        self.compute = compute
+        self._bind()
         self._ws = None
+
+    def _bind(self):
+        self.desc = sf_train_state(self.latents.data_ptr(), self.params.data_ptr(), self.m_lat.data_ptr(),
+                                   self.v_lat.data_ptr(), self.m_par.data_ptr(), self.v_par.data_ptr(),
+                                   self.n_lattice, self.channels, self.hidden, self.out_dim, self.compute)
+
+    def save(self, path: str, seed: int = 0, stream=None):
+        """Checkpoint: latents, parameters, both Adam moments (FP32, exact),
+        the step count, the compute mode and the caller's batch-sampling
+        seed, to an .npz file (no pickled objects)."""
+        import numpy as np
+        (stream or torch.cuda.current_stream()).synchronize()
+        np.savez(path, latents=self.latents.cpu().numpy(), params=self.params.cpu().numpy(),
+                 m_latents=self.m_lat.cpu().numpy(), v_latents=self.v_lat.cpu().numpy(),
+                 m_params=self.m_par.cpu().numpy(), v_params=self.v_par.cpu().numpy(),
+                 meta=np.array([self.step, self.channels, self.out_dim, self.hidden, self.compute, seed],
+                               dtype=np.int64))
+
+    @classmethod
+    def load(cls, path: str, device="cuda"):
+        """A state restored from save(); returns (state, seed).  Resuming and
+        taking the same steps gives the same state, bit for bit, as never
+        stopping."""
+        import numpy as np
+        z = np.load(path, allow_pickle=False)
+        step, ch, od, hid, comp, seed = (int(v) for v in z["meta"])
+        st = cls(torch.from_numpy(z["latents"]).to(device), torch.from_numpy(z["params"]).to(device), ch, od, hid,
+                 comp)
+        st.m_lat.copy_(torch.from_numpy(z["m_latents"]))
+        st.v_lat.copy_(torch.from_numpy(z["v_latents"]))
+        st.m_par.copy_(torch.from_numpy(z["m_params"]))
+        st.v_par.copy_(torch.from_numpy(z["v_params"]))
+        st.step = step
+        return st, seed
 
 
 def sf_neural_train_workspace(channels: int, out_dim: int, batch: int) -> int:

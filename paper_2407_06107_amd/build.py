@@ -29,7 +29,7 @@ BENCH_LIB = os.path.join(PKG, "libsf_bench.so")
 EXTRA_FLAGS = {"neural.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 SOURCES = ["abi.hip", "filter2d.hip", "aniso.hip", "dct.hip", "triplanar.hip", "volume.hip", "neural.hip",
-           "reduce.hip"]
+           "train.hip", "reduce.hip"]
 ARCH = "gfx950"
 
 CFLAGS = [

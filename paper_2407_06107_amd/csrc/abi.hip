@@ -797,6 +797,13 @@ static int train_parts(int64_t batch)
     return (int)(p < 1 ? 1 : (p > 2048 ? 2048 : p));
 }
 
+// Never more than train_parts(batch), so one workspace size serves both modes.
+static int train_parts_mfma(int64_t batch)
+{
+    int64_t p = (batch + 127) / 128;
+    return (int)(p < 1 ? 1 : (p > 2048 ? 2048 : p));
+}
+
 size_t sf_neural_train_workspace(int32_t channels, int32_t out_dim, int64_t batch)
 {
     if (!((channels == 8 && out_dim == 4) || (channels == 16 && out_dim == 1)) || batch < 1)
@@ -814,8 +821,10 @@ sf_status sf_neural_train_step(const sf_train_state *stt, const int32_t *batch_i
     if (!stt)
         return fail(SF_E_NULL, "training state is NULL");
     if (!((stt->channels == 8 && stt->out_dim == 4) || (stt->channels == 16 && stt->out_dim == 1)) ||
-        stt->hidden != 64 || stt->reserved != 0)
+        stt->hidden != 64)
         return fail(SF_E_UNSUPPORTED, "training shapes: 8-64-4 or 16-64-1");
+    if (stt->compute != SF_TRAIN_BF16 && stt->compute != SF_TRAIN_FP32)
+        return fail(SF_E_RANGE, "compute %d must be SF_TRAIN_BF16 or SF_TRAIN_FP32", stt->compute);
     if (batch < 1 || batch > stt->n_lattice || stt->n_lattice < 1 || stt->n_lattice > (1LL << 31) || step < 1)
         return fail(SF_E_RANGE, "batch must be in 1..n_lattice and step >= 1");
     if (!std::isfinite(lr_latent) || !std::isfinite(lr_mlp))
@@ -846,6 +855,16 @@ sf_status sf_neural_train_step(const sf_train_state *stt, const int32_t *batch_i
     t.loss_out = loss_out;
     t.grad_params = grad_params;
     t.grad_latents = grad_latents;
+    if (stt->compute == SF_TRAIN_BF16) {
+        // fewer, longer chunks than the FP32 path (at most as many partials):
+        // a wavefront loads its weight fragments once for 8 tiles of 16
+        const int parts = train_parts_mfma(batch);
+        const int64_t chunk = ((batch + parts - 1) / parts + 15) / 16 * 16;
+        hipError_t e = sfk::launch_train_mfma(t, (float *)workspace, parts, chunk, (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = sfk::launch_train_reduce(t, (float *)workspace, parts, (hipStream_t)stream);
+        return device_status(e);
+    }
     const int parts = train_parts(batch);
     const int64_t chunk = (batch + parts - 1) / parts;
     return device_status(sfk::launch_train(t, (float *)workspace, parts, chunk, (hipStream_t)stream));

@@ -952,6 +952,11 @@ hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_
         k_train<8, 4, TRAIN_GROUP><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
     else
         k_train<16, 1, TRAIN_GROUP><<<dim3(nparts), dim3(64), 0, s>>>(t, chunk, workspace);
+    return launch_train_reduce(t, workspace, nparts, s);
+}
+
+hipError_t launch_train_reduce(const TrainCall &t, float *workspace, int nparts, hipStream_t s)
+{
     const int npar = POff(t.C, t.O).n;
     const int nchunks = (nparts + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
     float *chunks = workspace + (int64_t)nparts * (npar + 1);

@@ -176,6 +176,10 @@ hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ
 hipError_t launch_to_bf16(const float *in, int64_t n, uint16_t *out, hipStream_t s);
 hipError_t launch_quant_fp8(const float *lat, const LatentArgs &g, uint8_t *codes, float *scales, hipStream_t s);
 hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_t chunk, hipStream_t s);
+// BF16 matrix-core training: per-wavefront partial gradients into
+// `partials`, then launch_train_reduce (fixed-order sum and Adam).
+hipError_t launch_train_mfma(const TrainCall &t, float *partials, int nparts, int64_t chunk, hipStream_t s);
+hipError_t launch_train_reduce(const TrainCall &t, float *workspace, int nparts, hipStream_t s);
 int train_nparams(int C, int O);
 int train_reduce_chunks(int nparts);
 hipError_t launch_neural2d(const NeuralCall &c, hipStream_t s);

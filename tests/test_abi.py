@@ -478,6 +478,9 @@ def test_neural_raymarch_and_train_validation(sf):
     assert L.sf_neural_train_step(C.byref(st), *args, ws - 4, None) == 5
     assert L.sf_neural_train_step(C.byref(st), FAKE, FAKE, 500, 1, 1e-2, 1e-3, FAKE, None, None, FAKE, 10 ** 9, None) == 2
     assert L.sf_neural_train_step(C.byref(st), FAKE, FAKE, 50, 0, 1e-2, 1e-3, FAKE, None, None, FAKE, ws, None) == 2
+    st.compute = 2   # neither SF_TRAIN_BF16 nor SF_TRAIN_FP32
+    assert L.sf_neural_train_step(C.byref(st), *args, ws, None) == 2
+    st.compute = sf.SF_TRAIN_FP32
     st.hidden = 32
     assert L.sf_neural_train_step(C.byref(st), *args, ws, None) == 3
 

@@ -6,7 +6,9 @@ activations to BF16; the oracle emulates that storage in FP64, so the
 residual differences are FP32-vs-FP64 accumulation and the rare BF16
 rounding flip it causes (one activation off by one BF16 step, ~0.4%).
 Tolerance: normwise relative 2e-3 and elementwise 2e-2 of the output scale.
-Training gradients are FP32 on the GPU vs FP64 in the oracle: normwise 1e-5.
+Training gradients: the FP32 step (vector ALU) vs FP64 in the oracle,
+normwise 1e-5; the matrix-core step (BF16 operands, FP32 accumulation) vs
+the FP64 oracle on the BF16-rounded weights and latents, normwise 2e-2.
 """
 import math
 
@@ -203,7 +205,7 @@ def _normwise(a, b):
 
 @pytest.mark.parametrize("C, O, B", [(8, 4, 700), (16, 1, 700), (8, 4, 690), (16, 1, 32769)])
 def test_train_step_parity(sf, orc, C, O, B):
-    """Gradients of one step (FP32 GPU) vs the FP64 oracle at the same
+    """Gradients of one FP32 step (vector ALU) vs the FP64 oracle at the same
     inputs; the Adam updates follow from the GPU's own gradients; latents
     outside the batch are untouched.  Batch 690 leaves one chunk with an odd
     number of two-sample groups; batch 32769 makes 17-sample chunks and
@@ -215,7 +217,8 @@ def test_train_step_parity(sf, orc, C, O, B):
     P = _params(C, O, 21, scale=0.2)
     targets = rng.uniform(0, 1, size=(nlat, O)).astype(np.float32)
     idx = rng.permutation(nlat)[:B].astype(np.int32)
-    st = sf.TrainState(torch.from_numpy(lat.ravel()).cuda(), torch.from_numpy(P).cuda(), C, O)
+    st = sf.TrainState(torch.from_numpy(lat.ravel()).cuda(), torch.from_numpy(P).cuda(), C, O,
+                       compute=sf.SF_TRAIN_FP32)
     gP = torch.zeros(P.size, dtype=torch.float32, device="cuda")
     gZ = torch.zeros((B, C), dtype=torch.float32, device="cuda")
     loss = sf.sf_neural_train_step(st, torch.from_numpy(idx).cuda(), torch.from_numpy(targets.ravel()).cuda(),
@@ -239,10 +242,100 @@ def test_train_step_parity(sf, orc, C, O, B):
     assert np.array_equal(newZ[rest], lat[rest].astype(np.float64))
 
 
+def _weights_bf16(P, C, O):
+    """The parameter vector with its weight blocks rounded to BF16 and its
+    biases kept in FP32: the operands of the matrix-core step."""
+    offs = np.cumsum([0, C * H, H, H * H, H, H * O, O])
+    Q = P.astype(np.float64).copy()
+    for k in (0, 2, 4):
+        Q[offs[k]:offs[k + 1]] = _bf16(P[offs[k]:offs[k + 1]])
+    return Q
+
+
+@pytest.mark.parametrize("C, O, B", [(8, 4, 700), (16, 1, 700), (8, 4, 4099), (16, 1, 32769)])
+def test_train_step_bf16_parity(sf, orc, C, O, B):
+    """One matrix-core step (BF16 operands, FP32 accumulation): loss and
+    gradients within 2e-2 normwise of the FP64 oracle run on the BF16-rounded
+    weights and latents with its hidden activations stored in BF16 (so that
+    both sides rectify the same second-layer pre-activations; the backward
+    signals are rounded to BF16 on the GPU only, a relative 2^-9 each); Adam
+    moves the FP32 master copies by the GPU's own gradients; latents outside
+    the batch are untouched.  Batches of 4099 and 32769 leave ragged 16-sample tiles and
+    empty trailing tiles."""
+    _case("train_step_bf16", C, O, B)
+    rng = np.random.default_rng(22)
+    nlat = max(2000, B + 1000)
+    lat = rng.normal(size=(nlat, C)).astype(np.float32)
+    P = _params(C, O, 23, scale=0.2)
+    targets = rng.uniform(0, 1, size=(nlat, O)).astype(np.float32)
+    idx = rng.permutation(nlat)[:B].astype(np.int32)
+    st = sf.TrainState(torch.from_numpy(lat.ravel()).cuda(), torch.from_numpy(P).cuda(), C, O)
+    assert st.compute == sf.SF_TRAIN_BF16
+    gP = torch.zeros(P.size, dtype=torch.float32, device="cuda")
+    gZ = torch.zeros((B, C), dtype=torch.float32, device="cuda")
+    loss = sf.sf_neural_train_step(st, torch.from_numpy(idx).cuda(), torch.from_numpy(targets.ravel()).cuda(),
+                                   lr_latent=1e-2, lr_mlp=1e-3, grad_params=gP, grad_latents=gZ)
+    oloss, ogP, ogZ = orc.mlp_grad(C, H, O, _weights_bf16(P, C, O), _bf16(lat[idx]), targets[idx].astype(np.float64),
+                                   act_bf16=True)
+    assert abs(loss.item() - oloss) <= 2e-2 * oloss
+    gp = gP.cpu().numpy()
+    offs = np.cumsum([0, C * H, H, H * H, H, H * O, O])
+    for a, b in zip(offs[:-1], offs[1:]):
+        assert _normwise(gp[a:b], ogP[a:b]) <= 2e-2, (a, b, _normwise(gp[a:b], ogP[a:b]))
+    assert _normwise(gZ.cpu().numpy(), ogZ) <= 2e-2
+    newP = st.params.cpu().numpy().astype(np.float64)
+    g = gp.astype(np.float64)
+    assert np.allclose(newP, P + -1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=2e-7)
+    newZ = st.latents.cpu().numpy().reshape(nlat, C).astype(np.float64)
+    gz = gZ.cpu().numpy().astype(np.float64)
+    assert np.allclose(newZ[idx], lat[idx] - 1e-2 * gz / (np.abs(gz) + 1e-8), rtol=0, atol=2e-6)
+    rest = np.setdiff1d(np.arange(nlat), idx)
+    assert np.array_equal(newZ[rest], lat[rest].astype(np.float64))
+
+
+def test_checkpoint_resume_is_bit_exact(sf, tmp_path):
+    """Training state saved after k steps and restored (latents, MLP, both
+    Adam moments, step, seed) continues to the same state, bit for bit, as an
+    uninterrupted run over the same batches; both compute modes."""
+    _case("checkpoint_resume")
+    rng = np.random.default_rng(30)
+    C, O, nlat, B, steps, k = 16, 1, 6000, 1024, 12, 5
+    lat0 = rng.normal(size=nlat * C).astype(np.float32)
+    P0 = _params(C, O, 31, scale=0.2)
+    tg = torch.from_numpy(rng.uniform(0, 1, size=nlat * O).astype(np.float32)).cuda()
+
+    def batches(seed, first, last):
+        for s in range(first, last):
+            r = np.random.default_rng([seed, s])
+            yield torch.from_numpy(r.permutation(nlat)[:B].astype(np.int32)).cuda()
+
+    for compute in (sf.SF_TRAIN_BF16, sf.SF_TRAIN_FP32):
+        full = sf.TrainState(torch.from_numpy(lat0.copy()).cuda(), torch.from_numpy(P0.copy()).cuda(), C, O,
+                             compute=compute)
+        for b in batches(7, 0, steps):
+            sf.sf_neural_train_step(full, b, tg, 1e-2, 1e-3)
+        part = sf.TrainState(torch.from_numpy(lat0.copy()).cuda(), torch.from_numpy(P0.copy()).cuda(), C, O,
+                             compute=compute)
+        for b in batches(7, 0, k):
+            sf.sf_neural_train_step(part, b, tg, 1e-2, 1e-3)
+        path = str(tmp_path / f"ckpt{compute}.npz")
+        part.save(path, seed=7)
+        del part
+        res, seed = sf.TrainState.load(path)
+        assert seed == 7 and res.step == k and res.compute == compute
+        for b in batches(seed, k, steps):
+            sf.sf_neural_train_step(res, b, tg, 1e-2, 1e-3)
+        torch.cuda.synchronize()
+        for a, b in ((full.latents, res.latents), (full.params, res.params), (full.m_lat, res.m_lat),
+                     (full.v_lat, res.v_lat), (full.m_par, res.m_par), (full.v_par, res.v_par)):
+            assert torch.equal(a, b)
+        assert res.step == full.step == steps
+
+
 def test_training_converges_and_decodes(sf, orc):
-    """A small neural texture trained on plain B-spline magnification
-    targets: the loss drops by more than 20x and the BF16 matrix-core
-    decoder reproduces the targets closely."""
+    """A small neural texture trained on the matrix cores (BF16) on plain
+    B-spline magnification targets: the loss drops by more than 20x and the
+    BF16 matrix-core decoder reproduces the targets closely."""
     _case("train_converge")
     src = inputs.texture_uniform(8, seed=1)
     R = 64

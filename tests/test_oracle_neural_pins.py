@@ -100,6 +100,42 @@ def test_mlp_gradient_finite_differences(orc, C, O):
     assert loss == pytest.approx(np.sum((Y - T) ** 2) / 5, rel=1e-12)
 
 
+@pytest.mark.parametrize("C, O", [(8, 4), (16, 1)])
+def test_mlp_gradient_with_bf16_activations(orc, C, O):
+    """With the hidden activations stored in BF16, the oracle's gradients are
+    those of backpropagation (numpy matrix form, FP64) through the network
+    whose stored activations are the rounded ones: rectifier masks from the
+    pre-activations, weight gradients from the rounded activations."""
+    import torch
+    rng = np.random.default_rng(8)
+    P = _rand_params(C, O, 9)
+    Z = rng.normal(size=(40, C))
+    T = rng.normal(size=(40, O))
+    B = Z.shape[0]
+    bf = lambda x: torch.from_numpy(np.asarray(x, np.float32)).to(torch.bfloat16).double().numpy()
+    W1 = P[:C * H].reshape(C, H); b1 = P[C * H:C * H + H]
+    o = C * H + H
+    W2 = P[o:o + H * H].reshape(H, H); b2 = P[o + H * H:o + H * H + H]
+    o += H * H + H
+    W3 = P[o:o + H * O].reshape(H, O); b3 = P[o + H * O:]
+    A1 = Z @ W1 + b1
+    H1 = bf(np.maximum(A1, 0.0))
+    A2 = H1 @ W2 + b2
+    H2 = bf(np.maximum(A2, 0.0))
+    Y = H2 @ W3 + b3
+    dY = 2.0 * (Y - T) / B
+    dA2 = (dY @ W3.T) * (A2 > 0)
+    dA1 = (dA2 @ W2.T) * (A1 > 0)
+    ref = np.concatenate([(Z.T @ dA1).ravel(), dA1.sum(0), (H1.T @ dA2).ravel(), dA2.sum(0),
+                          (H2.T @ dY).ravel(), dY.sum(0)])
+    loss, gP, gZ = orc.mlp_grad(C, H, O, P, Z, T, act_bf16=True)
+    assert np.allclose(gP, ref, rtol=1e-10, atol=1e-13)
+    assert np.allclose(gZ, dA1 @ W1.T, rtol=1e-10, atol=1e-13)
+    assert loss == pytest.approx(np.sum((Y - T) ** 2) / B, rel=1e-12)
+    # the rounding matters: the plain FP64 gradient differs
+    assert not np.allclose(orc.mlp_grad(C, H, O, P, Z, T)[1], gP, rtol=1e-6, atol=0)
+
+
 def test_mlp_forward_is_the_textbook_network(orc):
     """Forward pass = numpy matmul/relu on the unpacked parameters."""
     C, O = 8, 4
