@@ -717,7 +717,10 @@ def neural_bench(args):
         "neural_before_16_decodes": lambda o: sf.sf_neural_decode(grid, mlp, qd, sf.sampling(sf.SF_BSPLINE3, sf.SF_BEFORE, 1), sf.SF_SHADE_GGX, g, out=o),
         "plain_stochastic": lambda o: sf.sf_filter2d(tex, qd, sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=3), sf.SF_SHADE_GGX, g, out=o),
         "plain_after": lambda o: sf.sf_filter2d(tex, qd, sf.sampling(sf.SF_BSPLINE3, sf.SF_AFTER_EXACT, 1), sf.SF_SHADE_GGX, g, out=o),
+        # equal memory: the 1024^2 targets as an RGBA32F texture (16 B per texel, as the BF16 latents)
+        "plain1024_equal_memory_stochastic": lambda o: sf.sf_filter2d(eqmem_tex, qd, sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=3), sf.SF_SHADE_GGX, g, out=o),
     }
+    eqmem_tex = sf.Texture2D([targets.cpu().numpy().reshape(R, R, 4)])
     sub = np.sort(rng.choice(nq, 20000, replace=False))
     ref_after = oracle.filter2d(oracle.Tex2D.rgba32f(src), q, oracle.BSPLINE3, oracle.AFTER, shade=1, subset=sub)
     c4 = {"training": {"epochs": args.epochs4, "batch": 65536, "steps": args.epochs4 * 16, "ms": ms_train,
@@ -732,6 +735,13 @@ def neural_bench(args):
             dec = nq * (1 if "stochastic" in name else 16)
             c4[name]["decodes_per_s"] = dec / (t * 1e-3)
             c4[name]["mfma_useful_tflops"] = dec * MLP_FLOP[(8, 4)] / (t * 1e-3) / 1e12
+    c4["gain"] = {
+        "equal_lookups_rmse_ratio_plain64_over_neural": c4["plain_stochastic"]["rmse_vs_oracle_plain_after"]
+        / c4["neural_stochastic_1_decode"]["rmse_vs_oracle_plain_after"],
+        "equal_memory_rmse_ratio_neural_over_plain1024": c4["neural_stochastic_1_decode"]["rmse_vs_oracle_plain_after"]
+        / c4["plain1024_equal_memory_stochastic"]["rmse_vs_oracle_plain_after"],
+        "decodes_saved_vs_exact_after": 16,
+        "time_ratio_after_over_stochastic": c4["neural_after_16_decodes"]["ms"] / c4["neural_stochastic_1_decode"]["ms"]}
     res["config4"] = c4
     del st, grid, fit, targets, lat0, par0
     torch.cuda.empty_cache()
@@ -800,6 +810,13 @@ def neural_bench(args):
             c5[name]["decodes_per_s"] = hit * steps / (t * 1e-3)
             c5[name]["mfma_useful_tflops"] = hit * steps * MLP_FLOP[(16, 1)] / (t * 1e-3) / 1e12
             c5[name]["mfma_frac_of_bf16_peak"] = c5[name]["mfma_useful_tflops"] / MFMA_BF16_PEAK_TFLOPS
+    c5["gain"] = {
+        "equal_memory_rmse_ratio_neural_over_plain512": c5["neural_stochastic_1_decode"]["rmse_vs_oracle_plain1024_after"]
+        / c5["plain512_stochastic_equal_memory"]["rmse_vs_oracle_plain1024_after"],
+        "equal_lattice_rmse_ratio_neural_over_plain256": c5["neural_stochastic_1_decode"]["rmse_vs_oracle_plain1024_after"]
+        / c5["plain256_stochastic_equal_lattice"]["rmse_vs_oracle_plain1024_after"],
+        "winner_equal_memory": "plain" if c5["plain512_stochastic_equal_memory"]["rmse_vs_oracle_plain1024_after"]
+        < c5["neural_stochastic_1_decode"]["rmse_vs_oracle_plain1024_after"] else "neural"}
     res["config5"] = c5
     n5 = c5["neural_stochastic_1_decode"]
     line = {"metric": "neural decodes/s: stochastic tricubic through a 256^3x16 E4M3 latent volume (1 decode per "
