@@ -148,6 +148,7 @@ def lib():
         L.orc_f32_to_fp8.restype = C.c_uint8
         L.orc_f32_to_fp8.argtypes = [f32]
         L.orc_quantize_fp8.argtypes = [P, i32, P, i32, i32, P, P]
+        L.orc_dequant_fp8.argtypes = [P, P, i64, i32, P]
         L.orc_mlp_forward.argtypes = [i32, i32, i32, P, P, i64, i32, P]
         L.orc_mlp_grad.restype = C.c_double
         L.orc_mlp_grad.argtypes = [i32, i32, i32, P, P, P, i64, i32, P, P]
@@ -663,6 +664,17 @@ def quantize_fp8(lat: np.ndarray, dims: int, res, C: int, block_log2: int):
     scales = np.zeros(nb, dtype=np.float32)
     lib().orc_quantize_fp8(_p(lat), dims, _p(r), C, block_log2, _p(codes), _p(scales))
     return codes, scales
+
+
+def dequant_fp8(codes: np.ndarray, point_scale: np.ndarray, C: int) -> np.ndarray:
+    """The BF16 values an MLP reads from E4M3 latents: codes n x C, one
+    block scale per lattice point; binary32 product rounded to BF16."""
+    codes = _c(codes, np.uint8).reshape(-1, C)
+    s = _c(point_scale, np.float32).reshape(-1)
+    assert s.size == codes.shape[0]
+    out = np.zeros(codes.shape)
+    lib().orc_dequant_fp8(_p(codes), _p(s), codes.shape[0], C, _p(out))
+    return out
 
 
 def mlp_nparams(C: int, H: int, O: int) -> int:

@@ -129,6 +129,19 @@ ORC_EXPORT void orc_quantize_fp8(const float *lat, int dims, const int *res, int
             }
 }
 
+/* The value an E4M3 latent feeds to the MLP, whose operands are BF16: the
+ * code's value times its block scale, that product rounded to binary32, and
+ * the binary32 product rounded to BF16 (nearest, ties to even).  codes: n x C;
+ * scale: one per lattice point (its block's); out: n x C binary64. */
+ORC_EXPORT void orc_dequant_fp8(const uint8_t *codes, const float *scale, int64_t n, int C, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < C; ++c) {
+            float p = (float)orc_fp8_to_double(codes[i * C + c]) * scale[i];
+            out[i * C + c] = orc_bf16_to_double(orc_f32_to_bf16(p));
+        }
+}
+
 /* ----------------------------------------------------------------- MLP  */
 typedef struct {
     int C, H, O;

@@ -70,6 +70,29 @@ def test_fp8_block_quantisation_error_bound(orc):
     assert np.all(scales[blk[:4, :4, :4]] == 1.0)          # all-zero block
 
 
+def test_fp8_dequant_is_bf16_of_binary32_product(orc):
+    """An E4M3 latent enters the BF16 MLP as bf16(binary32(code value x
+    scale)): torch's E4M3 decoding, a float32 product and torch's
+    round-to-nearest-even BF16 conversion give the same values; three
+    products worked by hand pin the rounding (two ties to even, one below
+    half an ulp)."""
+    rng = np.random.default_rng(5)
+    C = 16
+    codes = rng.integers(0, 256, size=(500, C), dtype=np.uint8)
+    codes[(codes & 0x7F) == 0x7F] = 0x3A                 # no NaN codes
+    scale = np.exp(rng.uniform(-20, 5, size=500)).astype(np.float32)
+    ours = orc.dequant_fp8(codes, scale, C)
+    z = torch.from_numpy(codes).view(torch.float8_e4m3fn).float()
+    ref = (z * torch.from_numpy(scale)[:, None]).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(ours, ref)
+    # 1.0 x (1 + 2^-8) = 1.00000001b: a tie, to the even 1.0
+    # 1.0 x (1 + 3 2^-8) = 1.00000011b: a tie, to the even 1.0000010b
+    # 1.125 x (1 + 2^-7) = 1.0010001001b: below half an ulp, to 1.0010001b
+    hand = orc.dequant_fp8(np.array([[0x38], [0x38], [0x39]], np.uint8),
+                           np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -7], np.float32), 1)
+    assert hand.ravel().tolist() == [1.0, 1.0 + 2.0 ** -6, 1.1328125]
+
+
 @pytest.mark.parametrize("C, O", [(8, 4), (16, 1)])
 def test_mlp_gradient_finite_differences(orc, C, O):
     """Backward pass vs central differences of the batch loss (FP64)."""
