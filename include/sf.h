@@ -501,9 +501,10 @@ int64_t sf_occupancy_words(int32_t nx, int32_t ny, int32_t nz, int32_t brick_log
 enum { SF_LATENT_F32 = 0, SF_LATENT_BF16 = 1, SF_LATENT_FP8E4M3 = 2 };
 
 /* Lattice point (x, y, z) stores channels at latents + ((z*res[1] + y)*res[0]
- * + x)*channels.  SF_LATENT_FP8E4M3 (OCP E4M3, saturating): value = code *
- * block_scale[b], b the block of side 2^block_log2 lattice points holding the
- * point, blocks numbered x fastest.  2-D grids use res[2] = 1 and map a
+ * + x)*channels.  SF_LATENT_FP8E4M3 (OCP E4M3, saturating): the MLP reads
+ * bf16(code * block_scale[b]), the binary32 product rounded to BF16 (nearest
+ * even), b the block of side 2^block_log2 lattice points holding the point,
+ * blocks numbered x fastest.  2-D grids use res[2] = 1 and map a
  * texture coordinate u to raster p = u*res - 0.5 with repeat wrap; 3-D grids
  * map world x to p = (x - wmin)*scale - 0.5 and read zero outside. */
 typedef struct sf_latent_grid {
@@ -544,6 +545,9 @@ sf_status sf_neural_decode(const sf_latent_grid *grid, const sf_mlp *mlp, const 
  * sf_neural_raymarch — sf_raymarch through a 3-D neural density volume,
  * sigma_c = max(D_c, 0).  SF_STOCHASTIC only (the deterministic forms would
  * decode 8 or 64 lattice points per step; the CPU reference computes them).
+ *   Latents of at most 2^31 bytes are read through 32-bit buffer offsets,
+ *   larger lattices with 64-bit addresses (the environment variable
+ *   SF_NEURAL_ADDR64=1 forces the latter, for testing; results are equal).
  * Errors: as sf_raymarch; SF_E_UNSUPPORTED for other modes, shapes, formats.
  */
 sf_status sf_neural_raymarch(const sf_latent_grid *grid, const sf_mlp *mlp, const float *rays, int64_t n,

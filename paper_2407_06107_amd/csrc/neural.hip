@@ -16,10 +16,12 @@
 //    so one layer's accumulators are, lane for lane, the next layer's B
 //    operand (the weights' K order is permuted to match, see kperm()).
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "sf_device.hpp"
 #include "sf_internal.hpp"
+#include "volume_dev.hpp"
 
 #pragma clang fp contract(off)
 
@@ -511,34 +513,26 @@ __device__ __forceinline__ bf16x8 relu_pack(f32x4 lo, f32x4 hi)
     return __builtin_bit_cast(bf16x8, w);
 }
 
-// Four OCP E4M3 codes (one word) -> bfloat16, exactly (4 significant bits).
-__device__ __forceinline__ bf16x4 fp8x4_to_bf16(uint32_t w)
+// Four OCP E4M3 codes (one word) times their block scale s, as the MLP's
+// BF16 operands: each code's value (exact in binary32) times s, rounded to
+// binary32, then to bfloat16 (nearest even).
+__device__ __forceinline__ bf16x4 fp8x4_dequant(uint32_t w, float s)
 {
     const f32x2 a0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false), a1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
-    return __builtin_bit_cast(bf16x4, make_uint2(pack_bf16(a0.x, a0.y), pack_bf16(a1.x, a1.y)));
+    return __builtin_bit_cast(bf16x4, make_uint2(pack_bf16(a0.x * s, a0.y * s), pack_bf16(a1.x * s, a1.y * s)));
 }
 
-// The MLP on the 16 samples whose latents (K block of this lane) are in zb;
-// column scale cs multiplies layer 1's product (E4M3 block scale, SCALED);
-// BF16 latents have no scale, and layer 1's bias enters its matrix product
-// as the accumulator, as layer 2's does.  Returns the layer-3 accumulators:
-// lanes 0..15 hold outputs 0..3 of sample (lane).
-template <int C, int O, bool SCALED>
-__device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x4 zb, float cs)
+// The MLP on the 16 samples whose latents (K block of this lane, BF16, E4M3
+// latents already scaled) are in zb; each layer's bias enters its matrix
+// product as the accumulator.  Returns the layer-3 accumulators: lanes
+// 0..15 hold outputs 0..3 of sample (lane).
+template <int C, int O>
+__device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x4 zb)
 {
     f32x4 d1[4];
-    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        if constexpr (SCALED) {
-            d1[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.a1[m], zb, zero, 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                d1[m][j] = __builtin_fmaf(cs, d1[m][j], F.b1[m][j]);
-        } else {
-            d1[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.a1[m], zb, F.b1[m], 0, 0, 0);
-        }
-    }
+    for (int m = 0; m < 4; ++m)
+        d1[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.a1[m], zb, F.b1[m], 0, 0, 0);
     const bf16x8 h1a = relu_pack(d1[0], d1[1]), h1b = relu_pack(d1[2], d1[3]);
     f32x4 d2[4];
 #pragma unroll
@@ -552,14 +546,14 @@ __device__ __forceinline__ f32x4 mlp16(const MlpFrags<C, O> &F, bf16x4 zb, float
     return d3;
 }
 
-// This lane's K block of the latent of lattice point idx (zeros past C, or
-// for idx < 0); blk is the point's scale block (E4M3 latents).
+// This lane's K block of the latent of lattice point idx as BF16 operands
+// (zeros past C, or for idx < 0); blk is the point's scale block (E4M3
+// latents).
 template <int C, int FMT>
-__device__ __forceinline__ bf16x4 latent_frag(const LatentArgs &g, int64_t idx, int blk, float &scale)
+__device__ __forceinline__ bf16x4 latent_frag(const LatentArgs &g, int64_t idx, int blk)
 {
     const int kb = (threadIdx.x & 63) >> 4;
     bf16x4 r;
-    scale = 1.0f;
     if (4 * kb >= C || idx < 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -571,8 +565,7 @@ __device__ __forceinline__ bf16x4 latent_frag(const LatentArgs &g, int64_t idx, 
         r = __builtin_bit_cast(bf16x4, v);
     } else {
         const uint32_t v = *reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g.latents) + idx * C + 4 * kb);
-        r = fp8x4_to_bf16(v);
-        scale = g.scales[blk];
+        r = fp8x4_dequant(v, g.scales[blk]);
     }
     return r;
 }
@@ -587,19 +580,16 @@ __device__ __forceinline__ void decode_wave(const LatentArgs &g, const MlpFrags<
     const int lane = threadIdx.x & 63;
     // the four groups' latents are gathered first, so their loads overlap
     bf16x4 zb[4];
-    float cs[4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         const int src = 16 * G + (lane & 15);
         const int64_t sidx = ((int64_t)__shfl((int)(idx >> 32), src) << 32) | (uint32_t)__shfl((int)idx, src);
         const int sblk = FMT == SF_LATENT_BF16 ? 0 : __shfl(blk, src);
-        zb[G] = latent_frag<C, FMT>(g, sidx, sblk, cs[G]);
+        zb[G] = latent_frag<C, FMT>(g, sidx, sblk);
     }
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        if constexpr (FMT != SF_LATENT_BF16)
-            cs[G] = __shfl(cs[G], lane & 15);   // the scale of this lane's column (lanes 0..15 loaded it)
-        const f32x4 d3 = mlp16<C, O, FMT != SF_LATENT_BF16>(F, zb[G], cs[G]);
+        const f32x4 d3 = mlp16<C, O>(F, zb[G]);
 #pragma unroll
         for (int o = 0; o < O; ++o) {
             const float v = __shfl(d3[o], lane & 15);
@@ -776,79 +766,91 @@ __global__ __launch_bounds__(256) void k_decode_lattice(NeuralCall c, const int6
             c.out[i * O + o] = valid ? y[o] : __builtin_nanf("");
 }
 
-// Latents of one ray step for the wave's four 16-sample groups, as loaded
-// (E4M3 codes or BF16 bits), with each lane's column scale.  Issuing the
-// loads of step k+1 before the MLP of step k keeps one step of gathers in
-// flight behind the matrix-core work.
+// The march's lattice point of one ray step, per lane: `at` is the byte
+// offset of the point's latent (OFF32: the latents span at most 2^31 bytes
+// and are read through a buffer resource) or its linear index, and
+// kNoLatent (negative as int32) when the tap is outside the lattice or the
+// lane has no ray; cs is the point's block scale (E4M3 latents).  The loads
+// of one step for the wave's four 16-sample groups are issued before the
+// MLPs of the previous step, so one step of gathers stays in flight behind
+// the matrix-core work.
+constexpr uint32_t kNoLatent = 0x80000000u;
+
 template <int FMT>
 struct StepLatents {
     using Raw = typename std::conditional<FMT == SF_LATENT_BF16, uint2, uint32_t>::type;
-    Raw raw[4];
-    float cs[4];
+    Raw raw[4];     // this lane's K block of group G's sample latents, as loaded
+    uint32_t at;    // this lane's own point (validity of its sample)
+    float cs;       // this lane's own block scale, shuffled to the groups at decode time
 };
 
-template <int C, int FMT>
-__device__ __forceinline__ void issue_latents(const LatentArgs &g, int64_t idx, int blk, StepLatents<FMT> &L)
+template <int FMT, bool OFF32>
+__device__ __forceinline__ void issue_latents(const LatentArgs &g, __amdgpu_buffer_rsrc_t rs, uint32_t at, float cs,
+                                              StepLatents<FMT> &L)
 {
+    constexpr uint32_t kBytes = FMT == SF_LATENT_BF16 ? 8u : 4u;   // one K block: 4 channels
     const int lane = threadIdx.x & 63, kb = lane >> 4;
+    L.at = at;
+    L.cs = cs;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        const int src = 16 * G + (lane & 15);
-        const int64_t sidx = ((int64_t)__shfl((int)(idx >> 32), src) << 32) | (uint32_t)__shfl((int)idx, src);
-        const bool use = 4 * kb < C && sidx >= 0;
-        L.cs[G] = 1.0f;
-        if constexpr (FMT == SF_LATENT_BF16) {
-            L.raw[G] = use ? *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(g.latents) + sidx * C + 4 * kb)
-                           : make_uint2(0u, 0u);
+        const uint32_t sat = __shfl(at, 16 * G + (lane & 15));
+        if constexpr (OFF32) {
+            // a point outside the lattice reads past the buffer's end: zeros
+            const uint32_t off = sat + kb * kBytes;
+            if constexpr (FMT == SF_LATENT_BF16) {
+                typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+                const u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+                L.raw[G] = make_uint2(v.x, v.y);
+            } else {
+                L.raw[G] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+            }
         } else {
-            const int sblk = __shfl(blk, src);
-            L.raw[G] = use ? *reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g.latents) + sidx * C + 4 * kb)
-                           : 0u;
-            if (sidx >= 0)
-                L.cs[G] = g.scales[sblk];   // the scale of this lane's column
+            const uint8_t *p = static_cast<const uint8_t *>(g.latents) + (uint64_t)sat * (4 * kBytes) + kb * kBytes;
+            if constexpr (FMT == SF_LATENT_BF16)
+                L.raw[G] = (int32_t)sat >= 0 ? *reinterpret_cast<const uint2 *>(p) : make_uint2(0u, 0u);
+            else
+                L.raw[G] = (int32_t)sat >= 0 ? *reinterpret_cast<const uint32_t *>(p) : 0u;
         }
     }
 }
 
-template <int FMT>
-__device__ __forceinline__ bf16x4 latents_bf16(const typename StepLatents<FMT>::Raw &v)
-{
-    if constexpr (FMT == SF_LATENT_BF16) {
-        return __builtin_bit_cast(bf16x4, v);
-    } else {
-        return fp8x4_to_bf16(v);
-    }
-}
-
-// The wave's MLPs on loaded step latents; y = this lane's O raw outputs.
-template <int C, int O, int FMT>
-__device__ __forceinline__ void decode_loaded(const MlpFrags<C, O> &F, const StepLatents<FMT> &L, float y[O])
+// The wave's MLPs on one step's loaded latents; returns this lane's raw
+// output (density before the clamp at zero).
+template <int C, int FMT>
+__device__ __forceinline__ float decode_loaded(const MlpFrags<C, 1> &F, const StepLatents<FMT> &L)
 {
     const int lane = threadIdx.x & 63;
+    float y = 0.0f;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        const f32x4 d3 = mlp16<C, O, FMT != SF_LATENT_BF16>(F, latents_bf16<FMT>(L.raw[G]), L.cs[G]);
-#pragma unroll
-        for (int o = 0; o < O; ++o) {
-            const float v = __shfl(d3[o], lane & 15);
-            if ((lane >> 4) == G)
-                y[o] = v;
-        }
+        bf16x4 zb;
+        if constexpr (FMT == SF_LATENT_BF16)
+            zb = __builtin_bit_cast(bf16x4, L.raw[G]);
+        else
+            zb = fp8x4_dequant(L.raw[G], __shfl(L.cs, 16 * G + (lane & 15)));
+        const f32x4 d3 = mlp16<C, 1>(F, zb);
+        const float v = __shfl(d3[0], lane & 15);
+        if ((lane >> 4) == G)
+            y = v;
     }
+    return y;
 }
 
 // Ray march through a neural density volume: per step the lookup point's
 // picked lattice point is decoded (sigma = max(MLP, 0)); taps outside the
 // lattice read zero and are not decoded.  Every lane walks the same number
-// of steps so the wavefront can batch its decodes on the matrix cores.
-// Three wavefronts per SIMD (168 VGPRs, a few spills) overlap one
-// wavefront's vector work with another's matrix work better than two.
-template <int F_, int FMT, bool DBG>
+// of steps so the wavefront can batch its decodes on the matrix cores; the
+// step loop is unrolled twice so the two steps' latent registers alternate.
+// Three wavefronts per SIMD overlap one wavefront's vector work with
+// another's matrix work.
+template <int F_, int FMT, bool DBG, bool OFF32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_neural_ray(NeuralCall c, uint32_t nb_pad)
 {
-    constexpr int C = 16, O = 1;
-    MlpFrags<C, O> Fr;
-    load_frags<C, O>(static_cast<const uint16_t *>(c.mlp.params), Fr);
+    constexpr int C = 16;
+    constexpr uint32_t kPointBytes = FMT == SF_LATENT_BF16 ? 32u : 16u;
+    MlpFrags<C, 1> Fr;
+    load_frags<C, 1>(static_cast<const uint16_t *>(c.mlp.params), Fr);
     const int64_t i = (int64_t)xcd_block(blockIdx.x, nb_pad) * 256 + threadIdx.x;
     const bool active = i < c.n;
     RayGeom g = {};
@@ -856,16 +858,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (active)
         st = ray_setup_dev(c.lat.wmin, c.lat.scale, c.rays + 8 * i, c.steps, g);
     const bool march = active && st == 0;
+    const uint32_t npts = (uint32_t)c.lat.res[0] * (uint32_t)c.lat.res[1] * (uint32_t)c.lat.res[2];
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.lat.latents), 0,
+                                                                  OFF32 ? (int)(npts * kPointBytes) : 0, kBufferFlags);
     // compensated binary32 sums, as in the plain march
     CompSum Tsum;
     Tsum.init();
-    // lattice point (and scale block) of step k of this lane's ray; idx -1
-    // outside the lattice or for lanes without a ray
-    auto step_point = [&](const StepHash &h, int k, int s, int64_t &idx, int &blk) {
-        idx = -1;
-        blk = 0;
-        if (!march)
-            return;
+    // the block scales through a buffer resource too: an index outside the
+    // block array reads zero
+    const uint32_t nblk = (uint32_t)c.lat.nblocks();
+    __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(c.lat.scales), 0,
+                                                                   FMT != SF_LATENT_BF16 ? (int)(nblk * 4u) : 0,
+                                                                   kBufferFlags);
+    if (!march)
+        g = RayGeom{};   // lanes without a ray walk a dummy ray whose points are all discarded
+    // lattice point (and block scale) of step k of this lane's ray.  Computed
+    // by every lane without branches, so the compiler can schedule it among
+    // the matrix products of the step before; kNoLatent for lanes without a
+    // ray, steps past the last and taps outside the lattice.
+    auto step_point = [&](const StepHash &h, int k, int s, uint32_t &at, float &cs) {
         int i0[3], o[3];
         float t[3];
         const float kh = (float)k + 0.5f;
@@ -882,40 +893,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         o[2] = pick_off_2p24<F_>(t[2], u24i(w.z));
         const int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
         if constexpr (DBG) {
-            int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
-            tp[0] = x;
-            tp[1] = y;
-            tp[2] = z;
+            if (march && k < c.steps) {
+                int32_t *tp = c.taps + (((int64_t)i * c.spp + s) * c.steps + k) * 3;
+                tp[0] = x;
+                tp[1] = y;
+                tp[2] = z;
+            }
         }
-        const bool in = ((uint32_t)x < (uint32_t)c.lat.res[0]) & ((uint32_t)y < (uint32_t)c.lat.res[1]) &
-                        ((uint32_t)z < (uint32_t)c.lat.res[2]);
-        if (in) {
-            idx = ((int64_t)z * c.lat.res[1] + y) * c.lat.res[0] + x;
-            blk = c.lat.block_at(x, y, z);
-        }
+        const bool in = march & (k < c.steps) & ((uint32_t)x < (uint32_t)c.lat.res[0]) &
+                        ((uint32_t)y < (uint32_t)c.lat.res[1]) & ((uint32_t)z < (uint32_t)c.lat.res[2]);
+        const uint32_t pt = ((uint32_t)z * (uint32_t)c.lat.res[1] + (uint32_t)y) * (uint32_t)c.lat.res[0] + (uint32_t)x;
+        // (a select written as an OR, which keeps the compiler from branching here)
+        at = (OFF32 ? pt * kPointBytes : pt) | ((uint32_t)!in << 31);
+        cs = 0.0f;
+        if constexpr (FMT != SF_LATENT_BF16)
+            cs = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srs, (uint32_t)c.lat.block_at(x, y, z) * 4u,
+                                                                                0, 0));
     };
     for (int s = 0; s < c.spp; ++s) {
         StepHash h;
         h.init((uint32_t)i, (uint32_t)s, c.seed);
         CompSum tau;
         tau.init();
-        int64_t idx;
-        int blk;
-        step_point(h, 0, s, idx, blk);
-        StepLatents<FMT> cur, nxt;
-        issue_latents<C, FMT>(c.lat, idx, blk, cur);
-        for (int k = 0; k < c.steps; ++k) {
-            int64_t idx_n = -1;
-            int blk_n = 0;
-            if (k + 1 < c.steps)
-                step_point(h, k + 1, s, idx_n, blk_n);
-            issue_latents<C, FMT>(c.lat, idx_n, blk_n, nxt);   // step k+1 in flight
-            float sg[1];
-            decode_loaded<C, O, FMT>(Fr, cur, sg);             // step k
-            if (idx >= 0)
-                tau.add(__builtin_fmaxf(sg[0], 0.0f));
-            cur = nxt;
-            idx = idx_n;
+        StepLatents<FMT> A, B;
+        uint32_t at;
+        float cs;
+        step_point(h, 0, s, at, cs);
+        issue_latents<FMT, OFF32>(c.lat, rs, at, cs, A);
+        for (int k = 0; k < c.steps; k += 2) {
+            step_point(h, k + 1, s, at, cs);
+            issue_latents<FMT, OFF32>(c.lat, rs, at, cs, B);   // step k+1 in flight
+            // adding +0 for a point not decoded leaves the compensated sum as it is
+            float y = decode_loaded<C, FMT>(Fr, A);             // step k
+            tau.add((int32_t)A.at >= 0 ? __builtin_fmaxf(y, 0.0f) : 0.0f);
+            if (k + 1 >= c.steps)
+                break;
+            step_point(h, k + 2, s, at, cs);
+            issue_latents<FMT, OFF32>(c.lat, rs, at, cs, A);   // step k+2 in flight
+            y = decode_loaded<C, FMT>(Fr, B);                   // step k+1
+            tau.add((int32_t)B.at >= 0 ? __builtin_fmaxf(y, 0.0f) : 0.0f);
         }
         Tsum.add(expf(-(g.dt * tau.value())));
     }
@@ -1052,21 +1068,41 @@ hipError_t launch_decode_lattice(const NeuralCall &c, const int64_t *idx, hipStr
     return hipGetLastError();
 }
 
+// SF_NEURAL_ADDR64=1 in the environment sends every neural march through
+// the 64-bit addressing variant that lattices of more than 2^31 bytes of
+// latents take (so tests can run it on small lattices).
+static bool addr64_forced()
+{
+    const char *e = getenv("SF_NEURAL_ADDR64");
+    return e && e[0] == '1';
+}
+
+template <int F_, int FMT>
+static void launch_nr_m(const NeuralCall &c, hipStream_t s, dim3 grid, uint32_t nb_pad)
+{
+    dim3 block(256);
+    const uint64_t bytes = (uint64_t)c.lat.res[0] * c.lat.res[1] * c.lat.res[2] * (FMT == SF_LATENT_BF16 ? 32u : 16u);
+    const bool off32 = bytes <= (uint64_t)kNoLatent && !addr64_forced();
+    if (c.taps) {
+        if (off32)
+            k_neural_ray<F_, FMT, true, true><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_neural_ray<F_, FMT, true, false><<<grid, block, 0, s>>>(c, nb_pad);
+    } else {
+        if (off32)
+            k_neural_ray<F_, FMT, false, true><<<grid, block, 0, s>>>(c, nb_pad);
+        else
+            k_neural_ray<F_, FMT, false, false><<<grid, block, 0, s>>>(c, nb_pad);
+    }
+}
+
 template <int F_>
 static void launch_nr_f(const NeuralCall &c, hipStream_t s, dim3 grid, uint32_t nb_pad)
 {
-    dim3 block(256);
-    if (c.lat.fmt == SF_LATENT_BF16) {
-        if (c.taps)
-            k_neural_ray<F_, SF_LATENT_BF16, true><<<grid, block, 0, s>>>(c, nb_pad);
-        else
-            k_neural_ray<F_, SF_LATENT_BF16, false><<<grid, block, 0, s>>>(c, nb_pad);
-    } else {
-        if (c.taps)
-            k_neural_ray<F_, SF_LATENT_FP8E4M3, true><<<grid, block, 0, s>>>(c, nb_pad);
-        else
-            k_neural_ray<F_, SF_LATENT_FP8E4M3, false><<<grid, block, 0, s>>>(c, nb_pad);
-    }
+    if (c.lat.fmt == SF_LATENT_BF16)
+        launch_nr_m<F_, SF_LATENT_BF16>(c, s, grid, nb_pad);
+    else
+        launch_nr_m<F_, SF_LATENT_FP8E4M3>(c, s, grid, nb_pad);
 }
 
 hipError_t launch_neural_ray(const NeuralCall &c, hipStream_t s)

@@ -78,7 +78,7 @@ def _grid(sf, orc, dims, res, C, fmt, seed, block_log2=2, wmin=(0, 0, 0), scale=
         r3 = list(res) + [1] * (3 - len(res))
         z, y, x = np.meshgrid(np.arange(r3[2]), np.arange(r3[1]), np.arange(r3[0]), indexing="ij")
         blk = (((z // B) * nb[1] + (y // B)) * nb[0] + (x // B)).ravel()
-        Z = orc.fp8_table()[codes.reshape(npts, C)] * scales[blk][:, None].astype(np.float64)
+        Z = orc.dequant_fp8(codes, scales[blk], C)
     return grid, Z
 
 
@@ -175,8 +175,13 @@ def test_neural_filter2d_many_tiles(sf, orc, mode, fmt):
 
 @pytest.mark.parametrize("filt", ["LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("fmt", [1, 2])
-def test_neural_raymarch_parity(sf, orc, filt, fmt):
-    _case("neural_raymarch", filt, fmt)
+@pytest.mark.parametrize("addr64", [False, True])
+def test_neural_raymarch_parity(sf, orc, filt, fmt, addr64, monkeypatch):
+    """addr64: the variant lattices of more than 2^31 bytes of latents take
+    (64-bit addresses instead of buffer offsets), forced on this small one."""
+    _case("neural_raymarch", filt, fmt, addr64)
+    if addr64:
+        monkeypatch.setenv("SF_NEURAL_ADDR64", "1")
     res = (12, 11, 10)
     grid, Z = _grid(sf, orc, 3, res, 16, fmt, seed=8, wmin=(0, 0, 0), scale=res)
     P = _params(16, 1, 9, scale=0.2)
@@ -469,11 +474,10 @@ def test_neural_raymarch_config5_full_sampled(sf, orc):
     taps = taps_d[torch.from_numpy(sub).cuda()].cpu().numpy()
     del taps_d
     torch.cuda.empty_cache()
-    # the oracle decodes the same codes by the E4M3 definition times the block scale
+    # the oracle decodes the same codes: E4M3 value times the block scale, as a BF16 operand
     i = np.arange(L)
     blk = ((i[:, None, None] >> 3) * nb * nb + (i[None, :, None] >> 3) * nb + (i[None, None, :] >> 3)).ravel()
-    Z = orc.fp8_table()[codes.reshape(-1, C)]
-    Z *= scales[blk][:, None].astype(np.float64)
+    Z = orc.dequant_fp8(codes, scales[blk], C)
     ref, rt = orc.neural_raymarch((L, L, L), C, H, Z, _bf16(P), (0, 0, 0), np.array((L / side,) * 3, np.float32),
                                   rays, steps, orc.BSPLINE3, orc.STOCHASTIC, spp=1, seed=4, act_bf16=True, taps=True,
                                   subset=sub)
