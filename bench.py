@@ -68,11 +68,13 @@ def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed):
     """Pixel-integral equal-RMSE protocol.
 
     Reference pixel value R_p = mean of the exact-after 64-tap transmittance
-    over 256 stratified rays per pixel (its own sampling variance is measured
-    and subtracted).  Both 16-ray estimates are compared with R_p; the
+    over 16 independent sets of 16 stratified rays per pixel (256 rays); its
+    own sampling variance, the variance of the 16 set means over 16, is
+    subtracted.  Both 16-ray estimates are compared with R_p; the
     stochastic path needs spp* = 16 (RMSE_s/RMSE_d)^2 rays per pixel to match
     the deterministic path, so the throughput ratio at equal RMSE is
-    (t_det / t_stoch) (RMSE_d / RMSE_s)^2."""
+    (t_det / t_stoch) (RMSE_d / RMSE_s)^2.  The stochastic march is then run
+    at ceil(spp*/16) sets of 16 rays per pixel, timed, and its RMSE checked."""
     import numpy as np
     from paper_2407_06107_amd import inputs
 
@@ -81,27 +83,43 @@ def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed):
     stoch = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=seed)
     T_s = sf.sf_raymarch(vol, rays_d, STEPS, stoch).double().view(P, RAYS_PER_PIX).mean(1)
     T_d = sf.sf_raymarch(vol, rays_d, STEPS, after).double().view(P, RAYS_PER_PIX).mean(1)
-    # reference: 256 rays per pixel in 16 chunks of 16 rays (different jitter)
+    # reference: 16 sets of 16 stratified rays per pixel (independent jitter);
+    # the rays of one set are stratified, so the spread of the set means (not
+    # of single rays) measures the reference's own error
     acc = torch.zeros(P, dtype=torch.float64, device="cuda")
     acc2 = torch.zeros(P, dtype=torch.float64, device="cuda")
-    m = 0
-    for c in range(16):
+    sets = 16
+    for c in range(sets):
         r = inputs.ortho_rays(N_PIX, RAYS_PER_PIX, side=SIDE, seed=1000 + c)
-        T = sf.sf_raymarch(vol, torch.from_numpy(r).cuda(), STEPS, after).double().view(P, RAYS_PER_PIX)
-        acc += T.sum(1)
-        acc2 += (T * T).sum(1)
-        m += RAYS_PER_PIX
-    R = acc / m
-    var_R = (acc2 / m - R * R).clamp(min=0) / (m - 1)
+        M = sf.sf_raymarch(vol, torch.from_numpy(r).cuda(), STEPS, after).double().view(P, RAYS_PER_PIX).mean(1)
+        acc += M
+        acc2 += M * M
+    m = sets * RAYS_PER_PIX
+    R = acc / sets
+    var_R = (acc2 / sets - R * R).clamp(min=0) / (sets - 1)
     bias_corr = float(var_R.mean())
     mse_s = float(((T_s - R) ** 2).mean()) - bias_corr
     mse_d = float(((T_d - R) ** 2).mean()) - bias_corr
     rmse_s, rmse_d = math.sqrt(max(mse_s, 0.0)), math.sqrt(max(mse_d, 0.0))
     spp_star = RAYS_PER_PIX * (rmse_s / rmse_d) ** 2
     ratio = (t_det / t_stoch) * (rmse_d / rmse_s) ** 2
+    # verification at spp*: the stochastic march over ceil(spp* / 16) x 16
+    # jittered rays per pixel (new jitter), one launch, timed, and its RMSE
+    # against the same reference
+    chunks = max(1, math.ceil(spp_star / RAYS_PER_PIX))
+    rv = np.concatenate([inputs.ortho_rays(N_PIX, RAYS_PER_PIX, side=SIDE, seed=2000 + c) for c in range(chunks)])
+    rv_d = torch.from_numpy(rv).cuda()
+    Tv = torch.empty(rv.shape[0], dtype=torch.float32, device="cuda")
+    t_v = time_launches(lambda: sf.sf_raymarch(vol, rv_d, STEPS, stoch, T=Tv), 3, 1, torch)
+    T_v = Tv.double().view(chunks, P, RAYS_PER_PIX).mean((0, 2))
+    rmse_v = math.sqrt(max(float(((T_v - R) ** 2).mean()) - bias_corr, 0.0))
+    del rv_d, Tv
     return {"rmse_stochastic_16": rmse_s, "rmse_det_after_16": rmse_d,
             "mse_increase": mse_s / mse_d - 1.0, "spp_star": spp_star, "ratio": ratio,
-            "reference_rays_per_pixel": m, "reference_var_subtracted": bias_corr}
+            "reference_rays_per_pixel": m, "reference_var_subtracted": bias_corr,
+            "verified_at_spp_star": {"rays_per_pixel": chunks * RAYS_PER_PIX, "ms": t_v, "rmse": rmse_v,
+                                     "rmse_at_most_det": rmse_v <= rmse_d,
+                                     "ratio_measured": t_det / t_v}}
 
 
 def cpu_baseline(grid_host, rays, seed, max_rays):
@@ -1071,6 +1089,10 @@ def main():
                          "copy_gbs": copy_gbs},
         "ray_steps": hit_steps,
         "ray_steps_in_occupied_bricks": occ_steps,
+        # the same launch counted by the steps that meet the grid, and by the
+        # steps that gather a voxel (value counts every step of every ray)
+        "ray_steps_per_s": hit_steps / (ms * 1e-3),
+        "gathering_steps_per_s": occ_steps / (ms * 1e-3),
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
     }
