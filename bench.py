@@ -307,10 +307,14 @@ def _init_mlp(rng, C, O):
     return np.concatenate(parts).astype(np.float32)
 
 
-def _train(sf, torch, latents, params, targets, C, O, epochs, batch, lr_lat, lr_mlp, seed):
+def _train(sf, torch, latents, params, targets, C, O, epochs, batch, lr_lat, lr_mlp, seed, compute=None,
+           cosine=False):
     """Epochs of shuffled mini-batches through sf_neural_train_step; returns
-    (state, first and last epoch losses, milliseconds)."""
-    st = sf.TrainState(latents, params, C, O)
+    (state, first and last epoch losses, milliseconds).  cosine: both
+    learning rates follow a cosine from their start value down to 1% of it
+    over the epochs (a latent is updated once per epoch, so Adam's step on it
+    stays near lr x m / sqrt(v), about 4 lr, until the rate decays)."""
+    st = sf.TrainState(latents, params, C, O, compute=sf.SF_TRAIN_BF16 if compute is None else compute)
     n = st.n_lattice
     gen = torch.Generator(device="cuda").manual_seed(seed)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
@@ -323,7 +327,8 @@ def _train(sf, torch, latents, params, targets, C, O, epochs, batch, lr_lat, lr_
         nb = 0
         for b0 in range(0, n, batch):
             idx = perm[b0:b0 + batch]
-            sf.sf_neural_train_step(st, idx, targets, lr_lat, lr_mlp, loss_out=loss)
+            f = max(0.01, 0.5 * (1.0 + math.cos(math.pi * ep / epochs))) if cosine else 1.0
+            sf.sf_neural_train_step(st, idx, targets, lr_lat * f, lr_mlp * f, loss_out=loss)
             acc += loss.double()
             nb += 1
         if ep == 0:
@@ -779,18 +784,39 @@ def neural_bench(args):
     log("config 5: training")
     lat0 = torch.from_numpy((rng.normal(size=L ** 3 * 16) * 0.5).astype(np.float32)).cuda()
     par0 = torch.from_numpy(_init_mlp(rng, 16, 1)).cuda()
-    st, l_first, l_last, ms_train = _train(sf, torch, lat0, par0, targets, 16, 1, args.epochs5, 262144, 1e-2,
-                                           1e-3, 2)
-    # the network was fitted to sigma / sigma_max: fold sigma_max into the last layer
-    o3 = 16 * 64 + 64 + 64 * 64 + 64
-    params = st.params.clone()
-    params[o3:] *= sigma_max
-    grid = sf.sf_neural_quantize(st.latents, 3, (L, L, L), 16, sf.SF_LATENT_FP8E4M3, 3, (0, 0, 0),
-                                 (L / side,) * 3)
-    mlp = sf.MLP(params, 16, 1)
-    fit = sf.sf_neural_decode_lattice(grid, mlp, torch.arange(L ** 3, device="cuda", dtype=torch.int64))
-    fit_rmse = float(torch.sqrt(torch.mean((fit.view(-1).clamp(min=0) - sig_t) ** 2)))
-    del st, lat0, par0
+    all_pts = torch.arange(L ** 3, device="cuda", dtype=torch.int64)
+
+    def c5_network(compute):
+        """Train the C5 network in one compute mode; the E4M3 grid and MLP it
+        decodes with, the training record, and the lattice RMSE of its
+        decoded density with E4M3 and with BF16 latents."""
+        st, l_first, l_last, ms_train = _train(sf, torch, lat0.clone(), par0.clone(), targets, 16, 1, args.epochs5,
+                                               262144, 1e-2, 1e-3, 2, compute=compute, cosine=True)
+        # the network was fitted to sigma / sigma_max: fold sigma_max into the last layer
+        o3 = 16 * 64 + 64 + 64 * 64 + 64
+        params = st.params.clone()
+        params[o3:] *= sigma_max
+        mlp = sf.MLP(params, 16, 1)
+        rmse = {}
+        for tag, fmt in (("e4m3", sf.SF_LATENT_FP8E4M3), ("bf16", sf.SF_LATENT_BF16)):
+            gq = sf.sf_neural_quantize(st.latents, 3, (L, L, L), 16, fmt, 3, (0, 0, 0), (L / side,) * 3)
+            fit = sf.sf_neural_decode_lattice(gq, mlp, all_pts)
+            rmse[tag] = float(torch.sqrt(torch.mean((fit.view(-1).clamp(min=0) - sig_t) ** 2)))
+            if tag == "e4m3":
+                grid = gq
+            del fit
+        rec = {"epochs": args.epochs5, "batch": 262144, "steps": args.epochs5 * 64, "ms": ms_train,
+               "learning_rates": "latents 1e-2, MLP 1e-3, cosine decay to 1%",
+               "loss_first_epoch": l_first, "loss_last_epoch": l_last, "sigma_scale": sigma_max,
+               "rmse_decoded_sigma_vs_targets": rmse["e4m3"],
+               "rmse_decoded_sigma_vs_targets_bf16_latents": rmse["bf16"]}
+        del st
+        return grid, mlp, rec
+
+    grid, mlp, train_rec = c5_network(sf.SF_TRAIN_BF16)
+    log("config 5: training in FP32 (comparison)")
+    grid32, mlp32, train_rec32 = c5_network(sf.SF_TRAIN_FP32)
+    del lat0, par0
     torch.cuda.empty_cache()
     # equal-memory (512^3 fp16 = 256 MiB) and equal-lattice (256^3) plain grids, box-averaged
     log("config 5: rays and timing")
@@ -810,14 +836,15 @@ def neural_bench(args):
     log("config 5: oracle filter-after reference on the 1024^3 grid")
     ref_after = oracle.raymarch(oracle.Grid(src3.cpu().numpy(), side=side), rays, steps, oracle.BSPLINE3, oracle.AFTER,
                             subset=sub)
-    c5 = {"training": {"epochs": args.epochs5, "batch": 262144, "steps": args.epochs5 * 64, "ms": ms_train,
-                       "loss_first_epoch": l_first, "loss_last_epoch": l_last, "sigma_scale": sigma_max,
-                       "rmse_decoded_sigma_vs_targets": fit_rmse},
+    c5 = {"training": dict(train_rec, compute="bf16 matrix cores"),
+          "training_fp32_comparison": dict(train_rec32, compute="fp32 vector ALU"),
           "rays": nr, "hit_rays": hit, "steps": steps,
           "memory_bytes": {"latents_fp8": L ** 3 * 16, "block_scales": int(grid.scales.numel()) * 4,
                            "plain_1024": 1024 ** 3 * 2, "plain_512": 512 ** 3 * 2, "plain_256": 256 ** 3 * 2}}
     T = torch.empty(nr, dtype=torch.float32, device="cuda")
     for name, fn in (("neural_stochastic_1_decode", lambda: sf.sf_neural_raymarch(grid, mlp, rd, steps, smp, T=T)),
+                     ("neural_fp32_trained_stochastic_1_decode",
+                      lambda: sf.sf_neural_raymarch(grid32, mlp32, rd, steps, smp, T=T)),
                      ("plain1024_stochastic", lambda: sf.sf_raymarch(vol1024, rd, steps, smp, T=T)),
                      ("plain512_stochastic_equal_memory", lambda: sf.sf_raymarch(v512, rd, steps, smp, T=T)),
                      ("plain256_stochastic_equal_lattice", lambda: sf.sf_raymarch(v256, rd, steps, smp, T=T))):
@@ -911,7 +938,7 @@ def main():
     ap.add_argument("--suite-aniso", action="store_true", help="only the anisotropic section of the suite")
     ap.add_argument("--suite-planck", action="store_true", help="only the emission section of the suite")
     ap.add_argument("--epochs4", type=int, default=200)
-    ap.add_argument("--epochs5", type=int, default=60)
+    ap.add_argument("--epochs5", type=int, default=120)
     ap.add_argument("--save-inputs", default="", help="write the headline workload (grid, rays) to this .npz and exit")
     ap.add_argument("--load-inputs", default="", help="read the headline workload from this .npz")
     ap.add_argument("--pmc-neural", action="store_true",
