@@ -749,6 +749,80 @@ def test_triplanar_parity(sf, orc, tri_small, texkind, filt, plane_mode, mode, s
     _close(out.cpu().numpy(), ref)
 
 
+@pytest.fixture(scope="module")
+def dct_full(orc, sf, c2_full):
+    """The config-2 pyramid (4096^2 RGBA8, 13 levels) compressed by both sides."""
+    _print_case("dct_full generate")
+    lv, _ = c2_full
+    ot = orc.Tex2D.dct(lv, wrap=orc.REPEAT, mip=orc.MIP_LINEAR)
+    gt = sf.Texture2D.dct(sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR))
+    torch.cuda.synchronize()
+    return lv, ot, gt
+
+
+def test_dct_config2_full_codes_bit_exact(sf, orc, dct_full):
+    """Every block and range of the full 4096^2 pyramid equals the oracle's."""
+    _print_case("dct_full_codes")
+    lv, ot, gt = dct_full
+    assert np.array_equal(gt.buffer.cpu().numpy()[:ot.buf.size], ot.buf)
+    assert np.array_equal(gt.ranges.cpu().numpy(), ot.dct_range)
+
+
+@pytest.mark.parametrize("filt, mode", [("LINEAR", "STOCH"), ("LINEAR", "BEFORE"), ("BSPLINE3", "STOCH"),
+                                        ("BSPLINE3", "AFTER")])
+def test_dct_plane_4k_sampled(sf, orc, dct_full, filt, mode):
+    """The DCT pyramid seen by the 3840x2160 plane camera, in the launch the
+    suite times: 3000 sampled queries against the oracle, stochastic taps
+    bit-exact."""
+    _print_case("dct_plane_4k", filt, mode)
+    lv, ot, gt = dct_full
+    q = inputs.plane_queries(3840, 2160, tex_size=4096, levels=len(lv))
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE, "AFTER": orc.AFTER}[mode]
+    smp = sf.sampling(getattr(sf, "SF_" + filt), m, 1, seed=5)
+    stoch = m == orc.STOCHASTIC
+    taps_d = torch.empty((q.shape[0], 1, 3), dtype=torch.int32, device="cuda") if stoch else None
+    out = sf.sf_filter2d(gt, torch.from_numpy(q).cuda(), smp, shade=1, ggx_params=sf.ggx(), dbg_taps=taps_d)
+    sub = np.sort(np.random.default_rng(8).choice(q.shape[0], 3000, replace=False))
+    res = orc.filter2d(ot, q, getattr(orc, filt), m, spp=1, seed=5, shade=1, subset=sub, taps=stoch)
+    if stoch:
+        ref, taps = res
+        assert np.array_equal(taps_d[torch.from_numpy(sub).cuda()].cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy()[sub], ref)
+
+
+@pytest.mark.parametrize("texkind", ["rgba8", "dct"])
+@pytest.mark.parametrize("plane_mode, mode", [(1, "STOCH"), (0, "STOCH"), (0, "BEFORE"), (1, "BEFORE")])
+def test_triplanar_sphere_4k_sampled(sf, orc, c2_full, dct_full, texkind, plane_mode, mode):
+    """Triplanar mapping of the config-2 pyramid (plain and DCT) on the
+    3840x2160 sphere, in the launches the suite times: 3000 sampled hit
+    pixels against the oracle, the one-plane pick's taps bit-exact."""
+    _print_case("triplanar_4k", texkind, plane_mode, mode)
+    lv, _ = c2_full
+    if texkind == "dct":
+        _, ot, gt = dct_full
+    else:
+        buf, offs = inputs.pack_levels(lv)
+        ot = orc.Tex2D(buf, 4096, 4096, len(lv), orc.RGBA8, offs, orc.REPEAT, orc.MIP_LINEAR)
+        gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    q = inputs.sphere_queries(3840, 2160, tex_size=4096, levels=len(lv))
+    m = {"STOCH": orc.STOCHASTIC, "BEFORE": orc.BEFORE}[mode]
+    smp = sf.sampling(sf.SF_LINEAR, m, 1, seed=5)
+    want_taps = plane_mode == 1 and m == orc.STOCHASTIC
+    taps_d = torch.empty((q.shape[0], 1, 4), dtype=torch.int32, device="cuda") if want_taps else None
+    out = sf.sf_triplanar(gt, torch.from_numpy(q).cuda(), smp, 1.0, plane_mode, shade=1, ggx_params=sf.ggx(),
+                          dbg_taps=taps_d)
+    sub = np.sort(np.random.default_rng(9).choice(q.shape[0], 3000, replace=False))
+    res = orc.triplanar(ot, q, 1.0, plane_mode, orc.LINEAR, m, spp=1, seed=5, shade=1, subset=sub, taps=want_taps)
+    if want_taps:
+        ref, taps = res
+        assert np.array_equal(taps_d[torch.from_numpy(sub).cuda()].cpu().numpy(), taps)
+    else:
+        ref = res
+    _close(out.cpu().numpy()[sub], ref)
+
+
 # ------------------------------------------------------------------ 3-D points
 @pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
 @pytest.mark.parametrize("mode, spp, variant", [("STOCH", 4, 0), ("STOCH", 3, 1), ("BEFORE", 1, 0), ("AFTER", 1, 0)])
