@@ -541,6 +541,17 @@ def texture_bench(args, res):
         c1[name] = {"ms": t, "queries_per_s": 4096 / (t * 1e-3)}
         if filt == sf.SF_BSPLINE3:
             c1[name]["rmse_vs_oracle_bicubic_after"] = _rmse(o.cpu().numpy(), ref1)
+    # the 64 KiB texture staged in LDS by each workgroup (the stochastic
+    # kernel's default for textures up to 64 KiB when each workgroup has one
+    # tile of lookups) against texel reads from global memory
+    smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 16, seed=5)
+    o = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
+    lds = {}
+    for key, flag in (("lds_ms", "0"), ("global_ms", "1")):
+        os.environ["SF_NO_LDS_TEXTURE"] = flag
+        lds[key] = time_launches(lambda: sf.sf_filter2d(tex1, qd1, smp, sf.SF_SHADE_GGX, g, out=o), 50, 5, torch)
+    os.environ.pop("SF_NO_LDS_TEXTURE", None)
+    c1["bicubic_stochastic_16spp_texture_in_lds_vs_global"] = lds
     # interpolating Keys cubic: positivised stochastic (two taps per sample) vs all 16 taps
     ref1k = oracle.filter2d(oracle.Tex2D.rgba32f(src), q1, oracle.KEYS3, oracle.AFTER, shade=1)
     for name, mode, spp in (("keys_positivised_stochastic_16spp", sf.SF_STOCHASTIC, 16),

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -231,6 +232,26 @@ static void tex_args(const sf_tex2d *tex, sfk::Tex2DArgs &a)
 
 static int level_dim(int n, int l) { return (n >> l) > 0 ? (n >> l) : 1; }
 
+// Bytes from the texture's base pointer to the end of its last-placed level
+// when the stochastic 2-D kernel can hold all of it in LDS (plain formats,
+// at most kMaxLdsTexture bytes, 16-byte aligned base), else 0.
+// SF_NO_LDS_TEXTURE=1 in the environment keeps every texture in global
+// memory (so tests can compare both reads).
+static int32_t lds_texture_bytes(const sf_tex2d *tex)
+{
+    if (tex->format == SF_DCT8 || !aligned(tex->base, 16))
+        return 0;
+    const char *e = getenv("SF_NO_LDS_TEXTURE");
+    if (e && e[0] == '1')
+        return 0;
+    const int64_t esz = tex->format == SF_RGBA8_UNORM ? 4 : 16;
+    int64_t end = 0;
+    for (int l = 0; l < tex->levels; ++l)
+        end = std::max<int64_t>(end, tex->level_offset[l] +
+                                         esz * level_dim(tex->width, l) * level_dim(tex->height, l));
+    return end <= sfk::kMaxLdsTexture ? (int32_t)end : 0;
+}
+
 sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, const sf_sampling *smp, int32_t shade,
                       const sf_ggx *ggx, float *out, int32_t *dbg_taps, void *stream)
 {
@@ -280,6 +301,7 @@ sf_status sf_filter2d(const sf_tex2d *tex, const float *queries, int64_t n, cons
     c.shade = shade;
     c.out = out;
     c.taps = smp->mode == SF_STOCHASTIC || smp->mode == SF_SPLIT ? dbg_taps : nullptr;
+    c.lds_bytes = smp->mode == SF_STOCHASTIC ? lds_texture_bytes(tex) : 0;
     return device_status(sfk::launch_filter2d(c, (hipStream_t)stream));
 }
 

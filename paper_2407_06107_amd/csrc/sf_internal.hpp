@@ -52,7 +52,12 @@ struct Filter2DCall {
     GgxConst g;
     float *out;
     int32_t *taps;
+    int32_t lds_bytes;  // > 0: the stochastic kernel stages the texture's first lds_bytes bytes in LDS
 };
+
+// Largest texture (all levels, from the base pointer) that the stochastic
+// 2-D kernel stages in LDS.
+constexpr int kMaxLdsTexture = 65536;
 
 struct AnisoCall {
     Tex2DArgs tex;

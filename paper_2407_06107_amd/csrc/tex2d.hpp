@@ -98,11 +98,13 @@ __device__ __forceinline__ float dct_channel(uint32_t wd, float R, float c1x, fl
     return __builtin_fminf(__builtin_fmaxf(v, 0.0f), 1.0f);
 }
 
-__device__ __forceinline__ float4 texel(const Tex2DArgs &tx, int l, int x, int y)
+// Texel (x, y) of level l, the texture's levels read from `base` (its own
+// base pointer, or a copy of its bytes at the same offsets).
+__device__ __forceinline__ float4 texel(const Tex2DArgs &tx, const uint8_t *base, int l, int x, int y)
 {
     int wl = max(1, tx.w >> l);
     int64_t idx = (int64_t)y * wl + x;
-    const uint8_t *lv = tx.base + tx.off[l];
+    const uint8_t *lv = base + tx.off[l];
     if (tx.fmt == SF_DCT8) {
         const int bw = (wl + 7) >> 3;
         const uint4 b = reinterpret_cast<const uint4 *>(lv)[(int64_t)(y >> 3) * bw + (x >> 3)];
@@ -119,6 +121,8 @@ __device__ __forceinline__ float4 texel(const Tex2DArgs &tx, int l, int x, int y
     return make_float4((float)(px & 0xffu) * k, (float)((px >> 8) & 0xffu) * k, (float)((px >> 16) & 0xffu) * k,
                        (float)(px >> 24) * k);
 }
+
+__device__ __forceinline__ float4 texel(const Tex2DArgs &tx, int l, int x, int y) { return texel(tx, tx.base, l, x, y); }
 
 template <int SHADE>
 __device__ __forceinline__ float4 shade(const GgxConst &g, float4 c)

@@ -254,6 +254,39 @@ def test_filter2d_config1(sf, orc, c1, filt, mode, spp, variant, shade, wrap):
     _close(out.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("filt", ["NEAREST", "LINEAR", "BSPLINE3"])
+@pytest.mark.parametrize("texkind", ["rgba32f_64", "rgba8_64_mips", "rgba8_100x60_mips"])
+@pytest.mark.parametrize("spp, variant, shade", [(16, 0, 1), (5, 1, 0), (1, 0, 1)])
+def test_filter2d_texture_in_lds_equals_global(sf, c1, filt, texkind, spp, variant, shade, monkeypatch):
+    """Textures of at most 64 KiB are staged in LDS by the stochastic kernel
+    (RGBA32F 64^2 is exactly 64 KiB; the RGBA8 pyramids end on a 4-byte
+    tail): outputs and taps equal, bit for bit, those of the same launch
+    reading global memory (SF_NO_LDS_TEXTURE=1)."""
+    _print_case("tex_lds", filt, texkind, spp, variant, shade)
+    _, q = c1
+    if texkind == "rgba32f_64":
+        gt = sf.Texture2D([inputs.texture_uniform(64, seed=1)])
+    else:
+        full = inputs.quantize_unorm8(inputs.mip_chain(inputs.texture_sinusoids(128, seed=4, waves=6)))
+        if texkind == "rgba8_64_mips":
+            lv = full[1:]
+        else:
+            lv = [np.ascontiguousarray(f[:max(1, 60 >> l), :max(1, 100 >> l)]) for l, f in enumerate(full[:7])]
+        gt = sf.Texture2D(lv, wrap=sf.SF_WRAP_REPEAT, mip=sf.SF_MIP_LINEAR)
+    qq = q.copy()
+    qq[:, 2] = np.linspace(0.0, 7.0, qq.shape[0], dtype=np.float32)   # levels across the pyramid
+    qd = torch.from_numpy(qq).cuda()
+    smp = sf.sampling(getattr(sf, "SF_" + filt), sf.SF_STOCHASTIC, spp, seed=17, rng_variant=variant)
+    res = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("SF_NO_LDS_TEXTURE", flag)
+        taps = torch.empty((qq.shape[0], spp, 3), dtype=torch.int32, device="cuda")
+        out = sf.sf_filter2d(gt, qd, smp, shade=shade, ggx_params=sf.ggx() if shade else None, dbg_taps=taps)
+        res.append((out.cpu().numpy(), taps.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0], equal_nan=True)
+    assert np.array_equal(res[0][1], res[1][1])
+
+
 @pytest.fixture(scope="module")
 def c2_small(orc):
     size = 256
