@@ -251,6 +251,11 @@ typedef struct sf_volume {
  *             D = P-x P+y; uniforms: words 0,1,2 of the sample's key for the
  *             positive draw (x, y, block) and of its key with step 1 for the
  *             negative draw.
+ * Stochastic NEAREST / LINEAR / BSPLINE3 lookups in a plain-format texture
+ * of at most 64 KiB (from base to the end of its last level, 16-byte aligned
+ * base) read a copy of it in LDS when the launch has at most one 256-lane
+ * tile per resident workgroup; SF_NO_LDS_TEXTURE=1 in the environment keeps
+ * the reads in global memory (results are equal).
  * Defines: Sec. 2.2 eqs. filtered-texture and stochastic-sum; Sec. 3 eqs.
  * filter-before-shading and filtering-after-shading; Sec. 4.1 eq.
  * bicubic-bspline-texfilt; Suppl. S.1 stochastic bilerp; MIP level pick of
