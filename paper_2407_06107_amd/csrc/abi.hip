@@ -819,11 +819,13 @@ static int train_parts(int64_t batch)
     return (int)(p < 1 ? 1 : (p > 2048 ? 2048 : p));
 }
 
+// One wavefront per 16-sample tile up to 1024 wavefronts (one per SIMD of
+// a 256-CU device: each holds the registers of one), then longer chunks.
 // Never more than train_parts(batch), so one workspace size serves both modes.
 static int train_parts_mfma(int64_t batch)
 {
-    int64_t p = (batch + 127) / 128;
-    return (int)(p < 1 ? 1 : (p > 2048 ? 2048 : p));
+    int64_t p = (batch + 15) / 16;
+    return (int)(p < 1 ? 1 : (p > 1024 ? 1024 : p));
 }
 
 size_t sf_neural_train_workspace(int32_t channels, int32_t out_dim, int64_t batch)

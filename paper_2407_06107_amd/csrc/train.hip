@@ -189,24 +189,52 @@ __global__ __launch_bounds__(64) void k_train_mfma(TrainCall t, int64_t chunk, f
     const float inv_b = 2.0f / (float)t.batch;
     const int64_t s0 = (int64_t)blockIdx.x * chunk;
     const int64_t s1 = min(s0 + chunk, t.batch);
-    for (int64_t sb = s0; sb < s1; sb += 16) {
-        // sample of this lane's column; unused columns (past the chunk, or
-        // an index outside the lattice) read element 0 and contribute nothing
-        const int64_t si = sb + n;
-        const int32_t raw = t.idx[min(si, s1 - 1)];
-        const bool use = si < s1 && (uint64_t)(int64_t)raw < (uint64_t)t.n_lattice;
-        const int64_t p = use ? (int64_t)raw : 0;
-        f32x4 z = zero;
-        if (4 * g < C)
-            z = *reinterpret_cast<const f32x4 *>(t.latents + p * C + 4 * g);
-        if (!use)
-            z = zero;   // finite inputs, so that the column's zero gradients stay zero
-        float tg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (g == 0) {
-#pragma unroll
-            for (int o = 0; o < O; ++o)
-                tg[o] = t.targets[p * O + o];
+    // The tiles are software-pipelined: the batch indices of tile k+2 and
+    // the latents, targets and latent Adam moments of tile k+1 are loaded
+    // while tile k computes (batch entries own distinct latents, so the
+    // Adam step of tile k never writes what tile k+1 has read).
+    // Batch index of this lane's column of the tile at sb (an address inside
+    // the chunk also past its end).
+    auto index_at = [&](int64_t sb) -> int32_t { return t.idx[min(sb + n, s1 - 1)]; };
+    struct TileIn {
+        bool use;       // the column holds a sample of the chunk inside the lattice
+        int64_t si, p;  // its batch entry and lattice point (0 for unused columns)
+        f32x4 z, mq, vq;
+        float tg[4];
+    };
+    // unused columns read element 0 and contribute nothing
+    auto load_tile = [&](int64_t sb, int32_t raw, TileIn &T) {
+        T.si = sb + n;
+        T.use = T.si < s1 && (uint64_t)(int64_t)raw < (uint64_t)t.n_lattice;
+        T.p = T.use ? (int64_t)raw : 0;
+        T.z = zero;
+        T.mq = zero;
+        T.vq = zero;
+        if (4 * g < C) {
+            const int64_t q = T.p * C + 4 * g;
+            T.z = *reinterpret_cast<const f32x4 *>(t.latents + q);
+            T.mq = *reinterpret_cast<const f32x4 *>(t.m_lat + q);
+            T.vq = *reinterpret_cast<const f32x4 *>(t.v_lat + q);
         }
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            T.tg[o] = (g == 0 && o < O) ? t.targets[T.p * O + o] : 0.0f;
+    };
+    TileIn cur, nxt;
+    int32_t raw_next = 0;
+    if (s0 < s1) {
+        load_tile(s0, index_at(s0), cur);
+        raw_next = index_at(s0 + 16);
+    }
+    for (int64_t sb = s0; sb < s1; sb += 16) {
+        if (sb + 16 < s1)
+            load_tile(sb + 16, raw_next, nxt);   // tile k+1
+        raw_next = index_at(sb + 32);             // tile k+2
+        const bool use = cur.use;
+        const int64_t si = cur.si, p = cur.p;
+        // finite inputs for unused columns, so that their zero gradients stay zero
+        const f32x4 z = use ? cur.z : zero;
+        const float *tg = cur.tg;
         const bf16x4 zb = to_bf16x4(z);
 
         // forward: A1, H1, A2, H2, Y (columns = samples)
@@ -262,8 +290,7 @@ __global__ __launch_bounds__(64) void k_train_mfma(TrainCall t, int64_t chunk, f
             if (t.grad_latents)
                 *reinterpret_cast<f32x4 *>(t.grad_latents + si * C + 4 * g) = dz;
             const int64_t q = p * C + 4 * g;
-            const f32x4 mq = *reinterpret_cast<const f32x4 *>(t.m_lat + q);
-            const f32x4 vq = *reinterpret_cast<const f32x4 *>(t.v_lat + q);
+            const f32x4 mq = cur.mq, vq = cur.vq;
             f32x4 mo, vo, zo;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -318,6 +345,7 @@ __global__ __launch_bounds__(64) void k_train_mfma(TrainCall t, int64_t chunk, f
         for (int m = 0; m < 4; ++m)
             gw3[m] = mfma16(col4<RS>(sH2, g, 16 * m + n), yc, gw3[m]);
         __syncthreads();
+        cur = nxt;
     }
 
     // this wavefront's partial gradients in the packed layout, then the loss
