@@ -178,27 +178,64 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
         axis_weights<F>(t[2], wz);
         // BEFORE: acc = sum_i w_i sigma_i.  AFTER: acc = a_k, accf = f_k.
         float acc = 0.0f, accf = 0.0f;
+        // one x row of taps (NT voxels) into the sums, in tap order
+        auto add_row = [&](const float *sg, int by, int cz) {
+            float row = 0.0f, rowf = 0.0f;
 #pragma unroll
-        for (int cz = 0; cz < NT; ++cz) {
-#pragma unroll
-            for (int by = 0; by < NT; ++by) {
-                float row = 0.0f, rowf = 0.0f;
-#pragma unroll
-                for (int ax = 0; ax < NT; ++ax) {
-                    float sg = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
-                    if constexpr (MODE == BEFORE) {
-                        row = __builtin_fmaf(wx[ax], sg, row);
-                    } else {
-                        float e, m;
-                        exp_neg_pair(sg * dt, e, m);
-                        row = __builtin_fmaf(wx[ax], m, row);
-                        rowf = __builtin_fmaf(wx[ax], e, rowf);
-                    }
+            for (int ax = 0; ax < NT; ++ax) {
+                if constexpr (MODE == BEFORE) {
+                    row = __builtin_fmaf(wx[ax], sg[ax], row);
+                } else {
+                    float e, m;
+                    exp_neg_pair(sg[ax] * dt, e, m);
+                    row = __builtin_fmaf(wx[ax], m, row);
+                    rowf = __builtin_fmaf(wx[ax], e, rowf);
                 }
-                const float wyz = wy[by] * wz[cz];
-                acc = __builtin_fmaf(wyz, row, acc);
-                if constexpr (MODE != BEFORE)
-                    accf = __builtin_fmaf(wyz, rowf, accf);
+            }
+            const float wyz = wy[by] * wz[cz];
+            acc = __builtin_fmaf(wyz, row, acc);
+            if constexpr (MODE != BEFORE)
+                accf = __builtin_fmaf(wyz, rowf, accf);
+        };
+        // Binary16 tricubic steps whose 4x4x4 taps lie inside the grid (with
+        // two voxels to spare past the row in x) read each row of four
+        // voxels with one 12-byte load at the 4-byte boundary at or below it
+        // and take the voxels by a funnel shift; other steps load tap by tap.
+        // The values, and so the sums, are the same either way.
+        bool rows = false;
+        if constexpr (HALF && NT == 4)
+            rows = i0[0] - 1 >= 0 && i0[0] + 4 < c.vol.nx && i0[1] - 1 >= 0 && i0[1] + 2 < c.vol.ny &&
+                   i0[2] - 1 >= 0 && i0[2] + 2 < c.vol.nz;
+        if (rows) {
+            const uint32_t nx = (uint32_t)c.vol.nx, ny = (uint32_t)c.vol.ny;
+            const uint32_t e0 = ((uint32_t)(i0[2] - 1) * ny + (uint32_t)(i0[1] - 1)) * nx + (uint32_t)(i0[0] - 1);
+#pragma unroll
+            for (int cz = 0; cz < NT; ++cz) {
+#pragma unroll
+                for (int by = 0; by < NT; ++by) {
+                    const uint32_t e = e0 + ((uint32_t)cz * ny + (uint32_t)by) * nx;   // voxel index of the row
+                    typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+                    const u32x3 w = __builtin_bit_cast(
+                        u32x3, __builtin_amdgcn_raw_buffer_load_b96(rs, (2u * e) & ~3u, 0, 0));
+                    const uint32_t sh = (e & 1u) * 16u;   // the row starts in the high half of its first word
+                    const uint32_t d0 = __builtin_amdgcn_alignbit(w.y, w.x, sh);
+                    const uint32_t d1 = __builtin_amdgcn_alignbit(w.z, w.y, sh);
+                    const float sg[4] = {half_bits_to_float((uint16_t)d0), half_bits_to_float((uint16_t)(d0 >> 16)),
+                                         half_bits_to_float((uint16_t)d1), half_bits_to_float((uint16_t)(d1 >> 16))};
+                    add_row(sg, by, cz);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int cz = 0; cz < NT; ++cz) {
+#pragma unroll
+                for (int by = 0; by < NT; ++by) {
+                    float sg[NT];
+#pragma unroll
+                    for (int ax = 0; ax < NT; ++ax)
+                        sg[ax] = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
+                    add_row(sg, by, cz);
+                }
             }
         }
         if constexpr (MODE == BEFORE) {
