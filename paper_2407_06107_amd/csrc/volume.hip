@@ -204,8 +204,7 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
         // The values, and so the sums, are the same either way.
         bool rows = false;
         if constexpr (HALF && NT == 4)
-            rows = i0[0] - 1 >= 0 && i0[0] + 4 < c.vol.nx && i0[1] - 1 >= 0 && i0[1] + 2 < c.vol.ny &&
-                   i0[2] - 1 >= 0 && i0[2] + 2 < c.vol.nz;
+            rows = rows4_inside(c.vol, i0);
         if (rows) {
             const uint32_t nx = (uint32_t)c.vol.nx, ny = (uint32_t)c.vol.ny;
             const uint32_t e0 = ((uint32_t)(i0[2] - 1) * ny + (uint32_t)(i0[1] - 1)) * nx + (uint32_t)(i0[0] - 1);
@@ -213,15 +212,8 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
             for (int cz = 0; cz < NT; ++cz) {
 #pragma unroll
                 for (int by = 0; by < NT; ++by) {
-                    const uint32_t e = e0 + ((uint32_t)cz * ny + (uint32_t)by) * nx;   // voxel index of the row
-                    typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
-                    const u32x3 w = __builtin_bit_cast(
-                        u32x3, __builtin_amdgcn_raw_buffer_load_b96(rs, (2u * e) & ~3u, 0, 0));
-                    const uint32_t sh = (e & 1u) * 16u;   // the row starts in the high half of its first word
-                    const uint32_t d0 = __builtin_amdgcn_alignbit(w.y, w.x, sh);
-                    const uint32_t d1 = __builtin_amdgcn_alignbit(w.z, w.y, sh);
-                    const float sg[4] = {half_bits_to_float((uint16_t)d0), half_bits_to_float((uint16_t)(d0 >> 16)),
-                                         half_bits_to_float((uint16_t)d1), half_bits_to_float((uint16_t)(d1 >> 16))};
+                    float sg[4];
+                    voxel_row4_half(rs, e0 + ((uint32_t)cz * ny + (uint32_t)by) * nx, sg);
                     add_row(sg, by, cz);
                 }
             }
@@ -437,24 +429,51 @@ __global__ __launch_bounds__(256) void k_emit_det(RaymarchCall c, uint32_t nb_pa
         axis_weights<F>(t[1], wy);
         axis_weights<F>(t[2], wz);
         float e[3] = {0.0f, 0.0f, 0.0f};
+        // one x row of temperatures into the sums, in tap order
+        auto add_row = [&](const float *Tr, int by, int cz) {
+            const float wyz = wy[by] * wz[cz];
 #pragma unroll
-        for (int cz = 0; cz < NT; ++cz) {
+            for (int ax = 0; ax < NT; ++ax) {
+                const float T = Tr[ax];
+                const float w = wx[ax] * wyz;
+                if constexpr (MODE == BEFORE) {
+                    e[0] = __builtin_fmaf(w, T, e[0]);
+                } else {
+                    float B[3];
+                    planck3(T, B);
+                    e[0] = __builtin_fmaf(w, B[0], e[0]);
+                    e[1] = __builtin_fmaf(w, B[1], e[1]);
+                    e[2] = __builtin_fmaf(w, B[2], e[2]);
+                }
+            }
+        };
+        // rows of four binary16 voxels by one load where every tap is inside
+        // the grid, as in the transmittance comparators
+        bool rows = false;
+        if constexpr (HALF && NT == 4)
+            rows = rows4_inside(c.vol, i0);
+        if (rows) {
+            const uint32_t nx = (uint32_t)c.vol.nx, ny = (uint32_t)c.vol.ny;
+            const uint32_t e0 = ((uint32_t)(i0[2] - 1) * ny + (uint32_t)(i0[1] - 1)) * nx + (uint32_t)(i0[0] - 1);
 #pragma unroll
-            for (int by = 0; by < NT; ++by) {
-                const float wyz = wy[by] * wz[cz];
+            for (int cz = 0; cz < NT; ++cz) {
 #pragma unroll
-                for (int ax = 0; ax < NT; ++ax) {
-                    const float T = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
-                    const float w = wx[ax] * wyz;
-                    if constexpr (MODE == BEFORE) {
-                        e[0] = __builtin_fmaf(w, T, e[0]);
-                    } else {
-                        float B[3];
-                        planck3(T, B);
-                        e[0] = __builtin_fmaf(w, B[0], e[0]);
-                        e[1] = __builtin_fmaf(w, B[1], e[1]);
-                        e[2] = __builtin_fmaf(w, B[2], e[2]);
-                    }
+                for (int by = 0; by < NT; ++by) {
+                    float Tr[4];
+                    voxel_row4_half(rs, e0 + ((uint32_t)cz * ny + (uint32_t)by) * nx, Tr);
+                    add_row(Tr, by, cz);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int cz = 0; cz < NT; ++cz) {
+#pragma unroll
+                for (int by = 0; by < NT; ++by) {
+                    float Tr[NT];
+#pragma unroll
+                    for (int ax = 0; ax < NT; ++ax)
+                        Tr[ax] = voxel<HALF>(rs, c.vol, i0[0] + F0 + ax, i0[1] + F0 + by, i0[2] + F0 + cz);
+                    add_row(Tr, by, cz);
                 }
             }
         }

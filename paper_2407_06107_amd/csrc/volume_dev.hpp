@@ -51,6 +51,31 @@ __device__ __forceinline__ float voxel_load(__amdgpu_buffer_rsrc_t rs, uint32_t 
     return bits_value<HALF>(voxel_bits<HALF>(rs, off));
 }
 
+// Whether the 4x4x4 taps around raster cell i0 (offsets -1..2 per axis) lie
+// inside the grid with two voxels to spare past each x row, so that
+// voxel_row4_half may read every row.
+__device__ __forceinline__ bool rows4_inside(const VolArgs &v, const int i0[3])
+{
+    return i0[0] - 1 >= 0 && i0[0] + 4 < v.nx && i0[1] - 1 >= 0 && i0[1] + 2 < v.ny && i0[2] - 1 >= 0 &&
+           i0[2] + 2 < v.nz;
+}
+
+// The four binary16 voxels e..e+3 (e a voxel index; a row of the grid that
+// extends at least two voxels past e+3) read with one 12-byte load at the
+// 4-byte boundary at or below voxel e and a funnel shift.
+__device__ __forceinline__ void voxel_row4_half(__amdgpu_buffer_rsrc_t rs, uint32_t e, float sg[4])
+{
+    typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+    const u32x3 w = __builtin_bit_cast(u32x3, __builtin_amdgcn_raw_buffer_load_b96(rs, (2u * e) & ~3u, 0, 0));
+    const uint32_t sh = (e & 1u) * 16u;   // the row starts in the high half of its first word
+    const uint32_t d0 = __builtin_amdgcn_alignbit(w.y, w.x, sh);
+    const uint32_t d1 = __builtin_amdgcn_alignbit(w.z, w.y, sh);
+    sg[0] = half_bits_to_float((uint16_t)d0);
+    sg[1] = half_bits_to_float((uint16_t)(d0 >> 16));
+    sg[2] = half_bits_to_float((uint16_t)d1);
+    sg[3] = half_bits_to_float((uint16_t)(d1 >> 16));
+}
+
 // One voxel; zero outside the grid.
 template <bool HALF>
 __device__ __forceinline__ float voxel(__amdgpu_buffer_rsrc_t rs, const VolArgs &v, int x, int y, int z)
