@@ -397,15 +397,24 @@ constexpr int TRAIN_GROUP = 2;   // samples per iteration of k_train
 // consecutive per-wavefront partials, summed in order.
 constexpr int REDUCE_CHUNK = 64;
 
+// All REDUCE_CHUNK loads are issued before the first addition (a partial
+// past the last reads the last one's address and adds +0).
 __global__ __launch_bounds__(256) void k_train_chunks(int nparts, const float *partials, int npar, float *chunks)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p > npar)
         return;
     const int w0 = blockIdx.y * REDUCE_CHUNK, w1 = min(w0 + REDUCE_CHUNK, nparts);
+    float v[REDUCE_CHUNK];
+#pragma unroll
+    for (int j = 0; j < REDUCE_CHUNK; ++j) {
+        const float x = partials[(int64_t)min(w0 + j, w1 - 1) * (npar + 1) + p];
+        v[j] = w0 + j < w1 ? x : 0.0f;
+    }
     float g = 0.0f;
-    for (int w = w0; w < w1; ++w)
-        g += partials[(int64_t)w * (npar + 1) + p];
+#pragma unroll
+    for (int j = 0; j < REDUCE_CHUNK; ++j)
+        g += v[j];
     chunks[(int64_t)blockIdx.y * (npar + 1) + p] = g;
 }
 
@@ -417,9 +426,20 @@ __global__ __launch_bounds__(256) void k_train_reduce(TrainCall t, int nchunks, 
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p > npar)
         return;
+    // the chunk sums in order, loaded MAX_CHUNKS at a time before they are added
+    constexpr int MAX_CHUNKS = 32;
     float g = 0.0f;
-    for (int w = 0; w < nchunks; ++w)
-        g += chunks[(int64_t)w * (npar + 1) + p];
+    for (int w0 = 0; w0 < nchunks; w0 += MAX_CHUNKS) {
+        float v[MAX_CHUNKS];
+#pragma unroll
+        for (int j = 0; j < MAX_CHUNKS; ++j) {
+            const float x = chunks[(int64_t)min(w0 + j, nchunks - 1) * (npar + 1) + p];
+            v[j] = w0 + j < nchunks ? x : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < MAX_CHUNKS; ++j)
+            g += v[j];
+    }
     if (p == npar) {
         t.loss_out[0] = g / (float)t.batch;
         return;
