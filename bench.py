@@ -139,6 +139,29 @@ def cpu_baseline(grid_host, rays, seed, max_rays):
                       f"{dt:.2f} s wall on {oracle.num_threads()} threads"}
 
 
+def cpu_comparators(grid_host, rays, seed, nrays=4096):
+    """The oracle's other C3 modes (64- and 8-tap filter-before and exact
+    filter-after, stochastic trilinear) timed on ``nrays`` rays spread evenly
+    over the same stream, all host cores, as shaded queries/s: context beside
+    the GPU comparators, not a baseline."""
+    import oracle
+    og = oracle.Grid(grid_host, side=SIDE)
+    sub = np.unique(np.linspace(0, rays.shape[0] - 1, min(nrays, rays.shape[0])).astype(np.int64))
+    out = {}
+    for name, filt, mode in (("tricubic_after_64tap", oracle.BSPLINE3, oracle.AFTER),
+                             ("tricubic_before_64tap", oracle.BSPLINE3, oracle.BEFORE),
+                             ("trilinear_after_8tap", oracle.LINEAR, oracle.AFTER),
+                             ("trilinear_before_8tap", oracle.LINEAR, oracle.BEFORE),
+                             ("trilinear_stochastic", oracle.LINEAR, oracle.STOCHASTIC)):
+        t0 = time.perf_counter()
+        oracle.raymarch(og, rays, STEPS, filt, mode, seed=seed, subset=sub)
+        dt = time.perf_counter() - t0
+        out[name] = {"queries_per_s": sub.size * STEPS / dt,
+                     "sample": f"{sub.size} rays spread over the stream, {dt:.2f} s"}
+    out["cores"] = oracle.num_threads()
+    return out
+
+
 PMC_PROFILE = os.path.join(ROOT, "profiles", "raymarch_stochastic_tricubic_512cloud_pmc.md")
 
 
@@ -1088,6 +1111,8 @@ def main():
     if not args.no_cpu:
         log("CPU oracle baseline")
         cpu = cpu_baseline(grid.cpu().numpy(), rays, seed, args.cpu_rays)
+        if not args.no_compare:
+            extra["cpu_oracle_comparators"] = cpu_comparators(grid.cpu().numpy(), rays, seed)
 
     line = {
         "metric": METRIC,
