@@ -6,11 +6,13 @@
 // the plain texture (Sec. 4.1 FRS) and therefore runs ONE decode per sample
 // instead of 16 (bicubic) or 64 (tricubic).
 //
-//  - Training (FP32, vector ALU): one wavefront streams a chunk of the batch;
-//    lane h owns hidden unit h, so both matrix-vector products of a sample
-//    are 64-lane broadcasts from LDS.  Per-wavefront parameter gradients are
-//    summed in a fixed order by a second kernel that also applies Adam;
-//    latent gradients are applied at once (each batch entry owns its latent).
+//  - Training in FP32 on the vector ALU (the SF_TRAIN_FP32 step; the default
+//    matrix-core step is in train.hip): one wavefront streams a chunk of the
+//    batch; lane h owns hidden unit h, so both matrix-vector products of a
+//    sample are 64-lane broadcasts from LDS.  Per-wavefront parameter
+//    gradients of either step are summed in a fixed order by two kernels here,
+//    the second of which applies Adam; latent gradients are applied at once
+//    (each batch entry owns its latent).
 //  - Decoding (BF16 matrix cores, FP32 accumulation): 16 samples form the
 //    columns of one v_mfma_f32_16x16x32_bf16 tile with hidden units as rows,
 //    so one layer's accumulators are, lane for lane, the next layer's B
@@ -43,17 +45,6 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 }
 
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
-
-// OCP E4M3 code -> binary32 (codes 0x7f/0xff, NaN in the format, are never
-// produced by the quantizer).
-__device__ __forceinline__ float fp8_to_f32(uint32_t b)
-{
-    const uint32_t em = b & 0x7fu;
-    const uint32_t sign = (b & 0x80u) << 24;
-    float nrm = __builtin_bit_cast(float, sign | ((em << 20) + 0x3c000000u));
-    float sub = __builtin_bit_cast(float, sign | __builtin_bit_cast(uint32_t, (float)em * 0x1p-9f));
-    return em >= 8u ? nrm : sub;
-}
 
 // binary32 -> E4M3, round to nearest even, saturating at +-448.
 __device__ __forceinline__ uint8_t f32_to_fp8_rne(float f)
