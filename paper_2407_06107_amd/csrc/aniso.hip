@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_aniso_split(AnisoCall c, int log_g)
 }
 
 // Probe comparators (binary32 weights as the plain deterministic kernel,
-// binary64 sums over up to 64 probes x 2 levels x 16 taps).
+// compensated binary32 sums over up to 64 probes x 2 levels x 16 taps).
 template <int F, int SHADE, int MODE>
 __global__ __launch_bounds__(256) void k_aniso_det(AnisoCall c)
 {
