@@ -64,7 +64,7 @@ def time_launches(fn, steps, warmup, torch):
     return s.elapsed_time(e) / steps
 
 
-def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed):
+def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed, t_before=None):
     """Pixel-integral equal-RMSE protocol.
 
     Reference pixel value R_p = mean of the exact-after 64-tap transmittance
@@ -74,7 +74,9 @@ def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed):
     stochastic path needs spp* = 16 (RMSE_s/RMSE_d)^2 rays per pixel to match
     the deterministic path, so the throughput ratio at equal RMSE is
     (t_det / t_stoch) (RMSE_d / RMSE_s)^2.  The stochastic march is then run
-    at ceil(spp*/16) sets of 16 rays per pixel, timed, and its RMSE checked."""
+    at ceil(spp*/16) sets of 16 rays per pixel, timed, and its RMSE checked.
+    The 64-tap filter-before image (biased: the density is filtered before
+    the exponential) is compared with the same reference beside it."""
     import numpy as np
     from paper_2407_06107_amd import inputs
 
@@ -83,6 +85,8 @@ def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed):
     stoch = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=seed)
     T_s = sf.sf_raymarch(vol, rays_d, STEPS, stoch).double().view(P, RAYS_PER_PIX).mean(1)
     T_d = sf.sf_raymarch(vol, rays_d, STEPS, after).double().view(P, RAYS_PER_PIX).mean(1)
+    before = sf.sampling(sf.SF_BSPLINE3, sf.SF_BEFORE, 1)
+    T_b = sf.sf_raymarch(vol, rays_d, STEPS, before).double().view(P, RAYS_PER_PIX).mean(1)
     # reference: 16 sets of 16 stratified rays per pixel (independent jitter);
     # the rays of one set are stratified, so the spread of the set means (not
     # of single rays) measures the reference's own error
@@ -100,6 +104,7 @@ def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed):
     bias_corr = float(var_R.mean())
     mse_s = float(((T_s - R) ** 2).mean()) - bias_corr
     mse_d = float(((T_d - R) ** 2).mean()) - bias_corr
+    mse_b = float(((T_b - R) ** 2).mean()) - bias_corr
     rmse_s, rmse_d = math.sqrt(max(mse_s, 0.0)), math.sqrt(max(mse_d, 0.0))
     spp_star = RAYS_PER_PIX * (rmse_s / rmse_d) ** 2
     ratio = (t_det / t_stoch) * (rmse_d / rmse_s) ** 2
@@ -119,7 +124,10 @@ def equal_rmse(sf, torch, vol, rays_d, t_stoch, t_det, seed):
             "reference_rays_per_pixel": m, "reference_var_subtracted": bias_corr,
             "verified_at_spp_star": {"rays_per_pixel": chunks * RAYS_PER_PIX, "ms": t_v, "rmse": rmse_v,
                                      "rmse_at_most_det": rmse_v <= rmse_d,
-                                     "ratio_measured": t_det / t_v}}
+                                     "ratio_measured": t_det / t_v},
+            "det_before_16": {"rmse": math.sqrt(max(mse_b, 0.0)),
+                              "ratio_at_equal_rmse": None if t_before is None else
+                              (t_before / t_stoch) * max(mse_b, 0.0) / max(mse_s, 1e-30)}}
 
 
 def cpu_baseline(grid_host, rays, seed, max_rays):
@@ -1101,7 +1109,8 @@ def main():
         extra["comparators"] = rates
         log("equal-RMSE protocol")
         extra["equal_rmse_vs_tricubic_after"] = equal_rmse(sf, torch, vol_occ, rays_d, ms,
-                                                           rates["tricubic_after_64tap"]["ms"], seed)
+                                                           rates["tricubic_after_64tap"]["ms"], seed,
+                                                           rates["tricubic_before_64tap"]["ms"])
         extra["speedup_vs_tricubic_after_same_rays"] = rates["tricubic_after_64tap"]["ms"] / ms
         extra["speedup_vs_tricubic_before_same_rays"] = rates["tricubic_before_64tap"]["ms"] / ms
 
