@@ -498,3 +498,17 @@ def test_timed_kernel_code_digest(sf):
     d = bench.kernel_code_digest()
     assert d is not None and len(d) == 64 and int(d, 16) >= 0
     assert bench.kernel_code_digest(name=bench.TIMED_KERNEL + "_absent") is None
+
+
+def test_committed_counters_belong_to_the_timed_kernel(sf):
+    """The hardware counters committed under profiles/ were taken on the
+    machine code of the kernel bench.py times (same digest), so the bench
+    line's roofline and traffic figures are not stale."""
+    import importlib.util
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_for_test2", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    c = bench.counters_from_profile(bench.kernel_code_digest())
+    assert c.get("valu_insts_per_launch") and c.get("hbm_bytes_per_launch"), c
