@@ -973,6 +973,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--pmc-comparators", action="store_true",
+                    help="with --pmc-run: also launch each ray-march comparator three times")
     ap.add_argument("--no-compare", action="store_true", help="skip comparators and the equal-RMSE protocol")
     ap.add_argument("--cpu-rays", type=int, default=1 << 20, help="rays in the CPU oracle sample")
     ap.add_argument("--suite", action="store_true",
@@ -1076,7 +1078,17 @@ def main():
     t_real = time_launches(fn, args.steps, args.warmup, torch)
     if args.pmc_run:
         # counter runs: the kernels have run; nothing else touches the device
-        print(json.dumps({"ms_per_step": ms, "gather_twin_ms": t_twin, "ms_again": t_real}))
+        # but, with --pmc-comparators, three launches of each comparator
+        out = {"ms_per_step": ms, "gather_twin_ms": t_twin, "ms_again": t_real}
+        if args.pmc_comparators:
+            for name, filt, mode in (("tricubic_after_64tap", sf.SF_BSPLINE3, sf.SF_AFTER_EXACT),
+                                     ("tricubic_before_64tap", sf.SF_BSPLINE3, sf.SF_BEFORE),
+                                     ("trilinear_after_8tap", sf.SF_LINEAR, sf.SF_AFTER_EXACT),
+                                     ("trilinear_before_8tap", sf.SF_LINEAR, sf.SF_BEFORE)):
+                s2 = sf.sampling(filt, mode, 1, seed=seed)
+                out[name + "_ms"] = time_launches(lambda: sf.sf_raymarch(vol_occ, rays_d, STEPS, s2, T=T), 3, 0,
+                                                  torch)
+        print(json.dumps(out))
         return
 
     # algorithmic HBM bytes of one launch (548 B per ray: one binary16 voxel
