@@ -34,10 +34,16 @@ if ROOT not in sys.path:
 METRIC = "shaded queries/s: stochastic vs 64-tap tricubic at equal RMSE; HBM GB/s"
 N_PIX, RAYS_PER_PIX, STEPS, SIDE, GRID = 256, 16, 256, 0.25, 512
 HBM_PEAK_GBS = 8000.0
-# Non-packed VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, in
-# tera lane-operations per second (one wave64 VALU instruction occupies a
-# SIMD for 4 cycles, so a CU issues one per cycle).
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Vector-ALU peak in tera lane-operations per second: the published binary32
+# vector rate, 157.3 TFLOP/s = 256 CUs x 128 lanes x 2.4 GHz x 2 flops per
+# fused multiply-add, i.e. two wave64 instructions per CU per cycle (simple
+# binary32 and 32-bit integer operations on vector registers reach about
+# that rate; the issue-rate probe of libsf_bench.so measures it).
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# One wave64 instruction per CU per cycle: the rate of conversions, compares,
+# three-operand integer operations and instructions that read a scalar
+# register (the probe's slower class).
+VALU_ONE_ISSUE_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Algorithmic HBM bytes of one ray of the stochastic march: one binary16
 # voxel per step (256 x 2 B) plus the 32-byte ray record read and the 4-byte
 # transmittance written.
@@ -198,12 +204,14 @@ def counters_from_profile(code_digest):
 
 
 def count_occupied_steps(torch, occ, rays_d):
-    """Ray steps whose lookup point lies in an occupied brick (those the
-    kernel does not skip), from the same raster positions evaluated with
-    torch float32 operations; a step on a brick boundary may round the other
-    way, so the count is exact to a few parts per million."""
+    """Ray steps that the kernel marches (lookup point not in a brick known
+    to be empty: those that gather a voxel), from the same raster positions
+    evaluated with torch float32 operations and the kernel's lookup in the
+    padded bit mask; a step on a brick boundary may round the other way, so
+    the count is exact to a few parts per million."""
     words = occ.to(torch.int64) & 0xFFFFFFFF
     nb = GRID >> BRICK_LOG2
+    sx = sy = nb + 1                   # rows of nb + 1 bits, planes of nb + 1 rows
     o, d, t0, t1 = rays_d[:, :3], rays_d[:, 3:6], rays_d[:, 6:7], rays_d[:, 7:8]
     hit = (rays_d[:, 7] > rays_d[:, 6])
     dt = (t1 - t0) / STEPS
@@ -215,12 +223,36 @@ def count_occupied_steps(torch, occ, rays_d):
         kh = torch.arange(k0, min(STEPS, k0 + 32), device=rays_d.device, dtype=torch.float32) + 0.5
         p = E[:, None, :] + kh[None, :, None] * G[:, None, :]
         b = torch.div(torch.floor(p).to(torch.int64), 1 << BRICK_LOG2, rounding_mode="floor")
-        bc = b.clamp(0, nb - 1)          # the kernel tests the nearest brick
-        lin = (bc[..., 2] * nb + bc[..., 1]) * nb + bc[..., 0]
-        bit = (words[lin >> 5] >> (lin & 31)) & 1
-        occupied = bit.bool() & hit[:, None]
-        total += int(occupied.sum())
+        idx = (b[..., 2] * sy + b[..., 1]) * sx + b[..., 0]
+        inside = (idx >= 0) & ((idx >> 5) < words.numel())
+        empty = torch.zeros_like(inside)
+        ii = idx[inside]
+        empty[inside] = ((words[ii >> 5] >> (ii & 31)) & 1).bool()
+        total += int((~empty & hit[:, None]).sum())
     return total
+
+
+def valu_issue_rates(torch, reps=5):
+    """CU cycles per wave64 instruction of each case of the issue-rate probe
+    (libsf_bench.so): 8 resident workgroups of 256 lanes per CU, HIP events
+    over `reps` launches, at the nominal 2.4 GHz clock."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2407_06107_amd", "libsf_bench.so"))
+    lib.sfb_valu_rate_name.restype = C.c_char_p
+    lib.sfb_valu_rate_launch.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = cus * 8
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    insts = lib.sfb_valu_rate_insts()
+    rates = {}
+    for w in range(lib.sfb_valu_rate_cases()):
+        def launch():
+            if lib.sfb_valu_rate_launch(w, C.c_void_p(out.data_ptr()), blocks, stream) != 0:
+                raise RuntimeError("sfb_valu_rate_launch failed")
+        ms = time_launches(launch, reps, 2, torch)
+        rates[lib.sfb_valu_rate_name(w).decode()] = ms * 1e-3 * 2.4e9 / (32 * insts)
+    return rates
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
@@ -991,6 +1023,8 @@ def main():
                     help="counter runs: time the headline kernel and its gather twin only, launch nothing else")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (HBM counter calibration)")
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="only the vector-ALU issue-rate probe (CU cycles per wave64 instruction)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the path is single-GPU (rays are independent, so more GPUs "
@@ -1017,6 +1051,10 @@ def main():
     from paper_2407_06107_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.valu_rates:
+        print(json.dumps({"valu_issue_probe_cu_cycles_per_inst": valu_issue_rates(torch, reps=20),
+                          "device": torch.cuda.get_device_name(0)}))
+        return
     if args.save_inputs:
         # the workload, written once for counter runs (which then launch no
         # torch device kernel besides the calibration copy)
@@ -1127,6 +1165,7 @@ def main():
         extra["speedup_vs_tricubic_before_same_rays"] = rates["tricubic_before_64tap"]["ms"] / ms
 
     copy_gbs = copy_bandwidth(torch)
+    valu_rates = valu_issue_rates(torch)
 
     cpu = None
     if not args.no_cpu:
@@ -1159,6 +1198,8 @@ def main():
         # when the counters were taken on other machine code
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved_tops / VALU_PEAK_TOPS if achieved_tops else None,
+                     "frac_of_one_issue_per_cu_cycle": achieved_tops / VALU_ONE_ISSUE_TOPS if achieved_tops else None,
+                     "valu_issue_probe_cu_cycles_per_inst": valu_rates,
                      "traffic": counters.get("hbm_bytes_per_launch"),
                      "valu_insts_per_launch": valu,
                      "valu_busy_frac": counters.get("valu_busy_frac"),

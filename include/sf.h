@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SF_ABI_VERSION 2
+#define SF_ABI_VERSION 3
 #define SF_RNG_VERSION 1
 #define SF_TAP_NONE INT32_MIN
 #define SF_MAX_LEVELS 16
@@ -480,13 +480,21 @@ sf_status sf_raymarch_emission(const sf_volume *vol, const float *rays, int64_t 
  * sf_build_occupancy — brick occupancy mask of a density grid for empty-space
  * skipping in sf_raymarch.
  *   vol->brick_log2 sets the brick side B = 2^brick_log2 (vol->occupancy is
- *   ignored).  Bricks are numbered b = (bz*nby + by)*nbx + bx with
- *   nbx = ceil(nx/B) (likewise y, z); bit (b & 31) of word b >> 5 is 1 iff some
- *   voxel within 2 voxels of the brick (the support of a cubic B-spline tap
- *   around any point of the brick) is non-zero or not a number.
- *   occupancy: device buffer of `words` uint32, at least sf_occupancy_words().
+ *   ignored).  With nbx = ceil(nx/B) bricks along x (likewise y, z), the mask
+ *   holds one bit per brick in nbz planes of sy = nby + 1 rows of
+ *   sx = nbx + 1 bits: brick (bx, by, bz) is bit b = (bz*sy + by)*sx + bx,
+ *   bit (b & 31) of word b >> 5, which is 1 iff every voxel within 2 voxels
+ *   of the brick (the support of a cubic B-spline tap around any point of the
+ *   brick) is zero, else 0; the last bit of every row, the last row of every
+ *   plane and the bits past the last plane are 0.  The padding lets the
+ *   march test a lookup point's brick without clamping its coordinates (a
+ *   point just outside the grid meets a 0 and is marched).
+ *   occupancy: device buffer of `words` uint32, at least
+ *   sf_occupancy_words() = ceil(sx*sy*nbz/32); the mask holds at most 2^30
+ *   bits (sf_occupancy_words returns 0 beyond that: use larger bricks).
  * Errors: SF_E_NULL, SF_E_RANGE (brick_log2 outside 1..6, words too small),
- *         SF_E_UNSUPPORTED (grid as in sf_raymarch), SF_E_DEVICE.
+ *         SF_E_UNSUPPORTED (grid as in sf_raymarch, mask over 2^30 bits),
+ *         SF_E_DEVICE.
  */
 sf_status sf_build_occupancy(const sf_volume *vol, uint32_t *occupancy, int64_t words, void *stream);
 int64_t sf_occupancy_words(int32_t nx, int32_t ny, int32_t nz, int32_t brick_log2);

@@ -415,7 +415,8 @@ def sf_occupancy_words(nx: int, ny: int, nz: int, brick_log2: int) -> int:
 
 
 def sf_build_occupancy(vol: Volume, brick_log2: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Brick occupancy mask of ``vol`` (int32 words, bit layout of sf.h)."""
+    """Brick occupancy mask of ``vol``: int32 words holding the padded bit
+    mask of sf.h (one bit per brick, 1 = provably empty)."""
     d = vol.desc
     words = sf_occupancy_words(d.nx, d.ny, d.nz, brick_log2)
     if out is None:

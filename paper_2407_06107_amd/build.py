@@ -18,9 +18,10 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsf.so")
-# The benchmark's gather-only twin of the stochastic ray march, in a library
-# of its own that no product path loads.
-BENCH_SOURCES = ["bench_gather_twin.hip"]
+# Benchmark-only kernels (the gather-only twin of the stochastic ray march,
+# the vector-ALU issue-rate probe), in a library of their own that no product
+# path loads.
+BENCH_SOURCES = ["bench_gather_twin.hip", "bench_valu_rates.hip"]
 BENCH_LIB = os.path.join(PKG, "libsf_bench.so")
 
 # Per-source flags: the neural decoder's matrix-core accumulators live in

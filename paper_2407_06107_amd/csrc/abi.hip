@@ -83,18 +83,26 @@ sf_status check_volume(const sf_volume *v, sfk::VolArgs &a)
     if (v->reserved != 0)
         return fail(SF_E_RANGE, "volume reserved field must be 0");
     a.occ = nullptr;
-    a.occ_log2 = a.nbx = a.nby = a.nbz = 0;
+    a.occ_log2 = a.nbx = a.nby = a.nbz = a.occ_sx = a.occ_sy = 0;
+    a.occ_bytes = 0;
     if (v->occupancy) {
         if (v->brick_log2 < 1 || v->brick_log2 > 6)
             return fail(SF_E_RANGE, "brick_log2 %d outside 1..6", v->brick_log2);
         if (!aligned(v->occupancy, 4))
             return fail(SF_E_RANGE, "occupancy pointer misaligned");
-        const int32_t B = 1 << v->brick_log2;
+        const sfk::OccLayout o = sfk::occ_layout(v->nx, v->ny, v->nz, v->brick_log2);
+        // the kernels form bit indices with signed 24-bit multiplies
+        if (o.bits > sfk::kMaxOccBits || (int64_t)o.sy * (o.nbz + 1) >= (1LL << 23))
+            return fail(SF_E_UNSUPPORTED, "occupancy mask of %lld bits exceeds 2^30 (use larger bricks)",
+                        (long long)o.bits);
         a.occ = v->occupancy;
         a.occ_log2 = v->brick_log2;
-        a.nbx = (v->nx + B - 1) / B;
-        a.nby = (v->ny + B - 1) / B;
-        a.nbz = (v->nz + B - 1) / B;
+        a.nbx = o.nbx;
+        a.nby = o.nby;
+        a.nbz = o.nbz;
+        a.occ_sx = o.sx;
+        a.occ_sy = o.sy;
+        a.occ_bytes = (uint32_t)(o.words * 4);
     }
     a.lx = a.ly = -1;
     if ((v->nx & (v->nx - 1)) == 0 && (v->ny & (v->ny - 1)) == 0) {
@@ -589,9 +597,8 @@ int64_t sf_occupancy_words(int32_t nx, int32_t ny, int32_t nz, int32_t brick_log
 {
     if (nx < 1 || ny < 1 || nz < 1 || brick_log2 < 1 || brick_log2 > 6)
         return 0;
-    const int64_t B = 1LL << brick_log2;
-    const int64_t nb = ((nx + B - 1) / B) * ((ny + B - 1) / B) * ((nz + B - 1) / B);
-    return (nb + 31) / 32;
+    const sfk::OccLayout o = sfk::occ_layout(nx, ny, nz, brick_log2);
+    return o.bits > sfk::kMaxOccBits || (int64_t)o.sy * (o.nbz + 1) >= (1LL << 23) ? 0 : o.words;
 }
 
 sf_status sf_build_occupancy(const sf_volume *vol, uint32_t *occupancy, int64_t words, void *stream)
@@ -604,12 +611,10 @@ sf_status sf_build_occupancy(const sf_volume *vol, uint32_t *occupancy, int64_t 
     sf_status st;
     if ((st = check_volume(&v, a)) != SF_OK)
         return st;
-    const int64_t need = sf_occupancy_words(v.nx, v.ny, v.nz, v.brick_log2);
-    if (need > (1LL << 26))
-        return fail(SF_E_UNSUPPORTED, "more than 2^31 bricks");
+    const int64_t need = (int64_t)a.occ_bytes / 4;
     if (words < need)
         return fail(SF_E_RANGE, "occupancy needs %lld words, %lld given", (long long)need, (long long)words);
-    return device_status(sfk::launch_build_occupancy(a, v.brick_log2, occupancy, words, (hipStream_t)stream));
+    return device_status(sfk::launch_build_occupancy(a, occupancy, (hipStream_t)stream));
 }
 
 // ---------------------------------------------------------------- neural

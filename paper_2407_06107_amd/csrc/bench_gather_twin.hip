@@ -6,8 +6,8 @@
 // kernel (k_ray_stoch for the cubic B-spline, binary16 grid, independent
 // uniforms, occupancy mask, power-of-two addressing) with the random pick
 // taken out: the same ray setup, XCD block mapping, per-step raster position,
-// brick test, pipelined binary16 voxel load (one per step in an occupied
-// brick) and result write; the tap of step k on axis a is
+// brick words loaded a step ahead, pipelined binary16 voxel load (one per
+// step, past the grid's end in an empty brick) and result write; the tap of step k on axis a is
 // i0 - 1 + ((k >> 2a) & 3), which walks all 64 taps of the 4 x 4 x 4 range
 // the B-spline pick draws from (so the gathers spread over the same cache
 // footprint), and the densities are added in a plain binary32 sum.
@@ -32,24 +32,41 @@ __global__ __launch_bounds__(256) void k_ray_gather_twin(RaymarchCall c, uint32_
     }
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
-    float tau = 0.0f;
-    uint32_t pend = 0;
-    bool pend_ok = false;
-    float kh = 0.5f;
-    for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
+    const __amdgpu_buffer_rsrc_t rm = occ_rsrc(c.vol);
+    constexpr uint32_t kOut = 0xfffffffeu;
+    struct At {
+        float p[3];
         int i0[3];
-        float t[3];
-        step_coords(g, kh, i0, t);
-        if (!brick_occupied<true>(c.vol, i0))
-            continue;
-        bool ok;
-        const uint32_t off = voxel_offset<true, true>(c.vol, i0[0] + (k & 3) - 1, i0[1] + ((k >> 2) & 3) - 1,
-                                                      i0[2] + ((k >> 4) & 3) - 1, ok);
-        tau += bits_value<true>(masked_bits(pend, pend_ok));   // step k-1
-        pend = voxel_bits<true>(rs, off);                      // step k
-        pend_ok = ok;
+        uint32_t word, bit;
+    };
+    float tau = 0.0f;
+    uint32_t pend;
+    float kh = 0.5f;
+    auto step = [&](int k, const At &cur, At &nxt) {
+        const bool empty = __builtin_amdgcn_ubfe(cur.word, cur.bit, 1u) != 0u;
+        kh += 1.0f;
+        step_pos(g, kh, nxt.p, nxt.i0);
+        nxt.word = brick_word(rm, c.vol, nxt.i0, nxt.bit);
+        tau += bits_value<true>(pend);     // step k - 1
+        uint32_t off = kOut;
+        if (!empty)
+            off = voxel_offset_or_outside<true, true>(c.vol, cur.i0[0] + (k & 3) - 1, cur.i0[1] + ((k >> 2) & 3) - 1,
+                                                      cur.i0[2] + ((k >> 4) & 3) - 1);
+        pend = voxel_bits<true>(rs, off);  // step k
+    };
+    At a, b;
+    step_pos(g, kh, a.p, a.i0);
+    a.word = brick_word(rm, c.vol, a.i0, a.bit);
+    __builtin_amdgcn_sched_barrier(0);
+    pend = voxel_bits<true>(rs, kOut | (a.bit >> 31));
+    int k = 0;
+    for (; k + 1 < c.steps; k += 2) {
+        step(k, a, b);
+        step(k + 1, b, a);
     }
-    tau += bits_value<true>(masked_bits(pend, pend_ok));
+    if (k < c.steps)
+        step(k, a, b);
+    tau += bits_value<true>(pend);
     c.T[i] = expf(-(g.dt * tau));
 }
 
@@ -82,12 +99,17 @@ extern "C" int sfb_gather_twin(const void *grid, int32_t nx, int32_t ny, int32_t
         c.vol.wmin[k] = wmin[k];
         c.vol.scale[k] = scale[k];
     }
-    const int32_t B = 1 << brick_log2;
+    const sfk::OccLayout o = sfk::occ_layout(nx, ny, nz, brick_log2);
+    if (o.bits > sfk::kMaxOccBits || (int64_t)o.sy * (o.nbz + 1) >= (1LL << 23))
+        return -1;
     c.vol.occ = occ;
     c.vol.occ_log2 = brick_log2;
-    c.vol.nbx = (nx + B - 1) / B;
-    c.vol.nby = (ny + B - 1) / B;
-    c.vol.nbz = (nz + B - 1) / B;
+    c.vol.nbx = o.nbx;
+    c.vol.nby = o.nby;
+    c.vol.nbz = o.nbz;
+    c.vol.occ_sx = o.sx;
+    c.vol.occ_sy = o.sy;
+    c.vol.occ_bytes = (uint32_t)(o.words * 4);
     c.vol.lx = __builtin_ctz((unsigned)nx);
     c.vol.ly = __builtin_ctz((unsigned)ny);
     c.rays = rays;

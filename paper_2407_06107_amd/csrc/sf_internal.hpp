@@ -37,10 +37,39 @@ struct VolArgs {
     int32_t nx, ny, nz, fmt;
     uint32_t bytes;          // size of the grid in bytes (< 2^32)
     float wmin[3], scale[3];
-    const uint32_t *occ;     // brick occupancy mask or null
+    const uint32_t *occ;     // brick mask (see OccLayout) or null
     int32_t occ_log2, nbx, nby, nbz;
+    int32_t occ_sx, occ_sy;  // the mask's row length and rows per plane, in bricks
+    uint32_t occ_bytes;      // size of the mask in bytes
     int32_t lx, ly;          // log2(nx), log2(ny) when both are powers of two, else -1
 };
+
+// Layout of the brick mask: one bit per brick, 1 when every voxel within 2
+// voxels of the brick is zero (the brick is provably empty), else 0, in
+// planes of sy = nby + 1 rows of sx = nbx + 1 bits: every row ends in a
+// padding bit and every plane in a padding row, all 0.  Brick (bx, by, bz)
+// is bit b = (bz*sy + by)*sx + bx, bit (b & 31) of 32-bit word b >> 5; the
+// bits past the last brick in the last word are 0.  At most kMaxOccBits bits.
+struct OccLayout {
+    int32_t nbx, nby, nbz, sx, sy;
+    int64_t bits, words;
+};
+
+constexpr int64_t kMaxOccBits = 1LL << 30;
+
+inline OccLayout occ_layout(int32_t nx, int32_t ny, int32_t nz, int32_t log2b)
+{
+    OccLayout o;
+    const int32_t B = 1 << log2b;
+    o.nbx = (nx + B - 1) / B;
+    o.nby = (ny + B - 1) / B;
+    o.nbz = (nz + B - 1) / B;
+    o.sx = o.nbx + 1;
+    o.sy = o.nby + 1;
+    o.bits = (int64_t)o.sx * o.sy * o.nbz;
+    o.words = (o.bits + 31) / 32;
+    return o;
+}
 
 struct Filter2DCall {
     Tex2DArgs tex;
@@ -177,7 +206,7 @@ inline int lane_group(int64_t n, int spp)
 
 hipError_t launch_raymarch(const RaymarchCall &c, hipStream_t s);
 hipError_t launch_emission(const RaymarchCall &c, hipStream_t s);
-hipError_t launch_build_occupancy(const VolArgs &v, int32_t log2b, uint32_t *occ, int64_t words, hipStream_t s);
+hipError_t launch_build_occupancy(const VolArgs &v, uint32_t *occ, hipStream_t s);
 hipError_t launch_to_bf16(const float *in, int64_t n, uint16_t *out, hipStream_t s);
 hipError_t launch_quant_fp8(const float *lat, const LatentArgs &g, uint8_t *codes, float *scales, hipStream_t s);
 hipError_t launch_train(const TrainCall &t, float *workspace, int nparts, int64_t chunk, hipStream_t s);

@@ -87,6 +87,9 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
     // optical depth and the mean over samples as compensated binary32 sums:
     // tau within 2u tau of its exact value, so T = e^(-dt tau) within about
     // (2 tau + 3) u relative of the exact transmittance of the picked voxels
+    __amdgpu_buffer_rsrc_t rm;
+    if constexpr (OCC)
+        rm = occ_rsrc(c.vol);
     CompSum Tsum;
     Tsum.init();
     for (int s = 0; s < c.spp; ++s) {
@@ -97,16 +100,62 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
         // software pipeline: a step's voxel is added one step later, so its
         // load overlaps the next step's arithmetic
         uint32_t pend = 0;
-        bool pend_ok = false;
         float kh = 0.5f;
+        if constexpr (OCC) {
+            // With the brick mask, the brick word of step k + 1 is loaded
+            // during step k as well, ahead of step k's voxel, and every step
+            // loads a voxel (a step in an empty brick loads past the grid's
+            // end and adds the 0.0 it reads, which leaves the compensated
+            // sum unchanged): every pass then finds the same two loads in
+            // flight in the same order, and a step waits only for loads
+            // issued one step earlier.  Two steps per pass, so that the
+            // state of step k + 1 is formed in place of step k - 1's.
+            constexpr uint32_t kOut = HALF ? 0xfffffffeu : 0xfffffffcu;
+            struct At {
+                float p[3];
+                int i0[3];
+                uint32_t word, bit;   // brick word and bit index
+            };
+            auto step = [&](int k, const At &cur, At &nxt) {
+                const bool empty = __builtin_amdgcn_ubfe(cur.word, cur.bit, 1u) != 0u;
+                kh += 1.0f;
+                step_pos(g, kh, nxt.p, nxt.i0);
+                nxt.word = brick_word(rm, c.vol, nxt.i0, nxt.bit);
+                tau.add(bits_value<HALF>(pend));   // step k - 1
+                uint32_t off = kOut;
+                if (!empty) {
+                    float t[3];
+                    int o[3];
+                    step_frac(cur.p, cur.i0, t);
+                    pick3<F, VAR>(t, h.at((uint32_t)k), o);
+                    off = voxel_offset_or_outside<HALF, P2>(c.vol, cur.i0[0] + o[0], cur.i0[1] + o[1],
+                                                             cur.i0[2] + o[2]);
+                }
+                pend = voxel_bits<HALF>(rs, off);  // step k
+            };
+            At a, b;
+            step_pos(g, kh, a.p, a.i0);
+            a.word = brick_word(rm, c.vol, a.i0, a.bit);
+            // a first load of zero behind the first brick word (its offset
+            // depends on the brick index so that it is not moved ahead)
+            __builtin_amdgcn_sched_barrier(0);
+            pend = voxel_bits<HALF>(rs, kOut | (a.bit >> 31));
+            int k = 0;
+            for (; k + 1 < c.steps; k += 2) {
+                step(k, a, b);
+                step(k + 1, b, a);
+            }
+            if (k < c.steps)
+                step(k, a, b);
+            tau.add(bits_value<HALF>(pend));
+            Tsum.add(expf(-(g.dt * tau.value())));
+            continue;
+        }
         for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
             int i0[3], o[3];
-            float t[3];
-            step_coords(g, kh, i0, t);
-            if constexpr (OCC) {
-                if (!brick_occupied<P2>(c.vol, i0))
-                    continue;   // the step would add exactly 0.0 to tau
-            }
+            float p[3], t[3];
+            step_pos(g, kh, p, i0);
+            step_frac(p, i0, t);
             pick3<F, VAR>(t, h.at((uint32_t)k), o);
             int x = i0[0] + o[0], y = i0[1] + o[1], z = i0[2] + o[2];
             if constexpr (DBG) {
@@ -115,13 +164,11 @@ __global__ __launch_bounds__(256) void k_ray_stoch(RaymarchCall c, uint32_t nb_p
                 tp[1] = y;
                 tp[2] = z;
             }
-            bool ok;
-            const uint32_t off = voxel_offset<HALF, P2>(c.vol, x, y, z, ok);
-            tau.add(bits_value<HALF>(masked_bits(pend, pend_ok)));   // step k-1
-            pend = voxel_bits<HALF>(rs, off);                        // step k
-            pend_ok = ok;
+            const uint32_t off = voxel_offset_or_outside<HALF, P2>(c.vol, x, y, z);
+            tau.add(bits_value<HALF>(pend));     // step k-1
+            pend = voxel_bits<HALF>(rs, off);    // step k (0 outside the grid)
         }
-        tau.add(bits_value<HALF>(masked_bits(pend, pend_ok)));
+        tau.add(bits_value<HALF>(pend));
         Tsum.add(expf(-(g.dt * tau.value())));
     }
     c.T[i] = Tsum.value() / (float)c.spp;
@@ -151,6 +198,9 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
     }
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
+    __amdgpu_buffer_rsrc_t rm;
+    if constexpr (OCC)
+        rm = occ_rsrc(c.vol);
     constexpr int NT = Taps<F>::n;
     constexpr int F0 = Taps<F>::first;
     const float dt = g.dt;
@@ -165,7 +215,7 @@ __global__ __launch_bounds__(256) void k_ray_det(RaymarchCall c, uint32_t nb_pad
         float wx[4], wy[4], wz[4];
         step_coords(g, kh, i0, t);
         if constexpr (OCC) {
-            if (!brick_occupied(c.vol, i0))
+            if (brick_empty_clamped(rm, c.vol, i0))
                 continue;   // every tap is zero: before adds 0, after multiplies by 1 - 0
         }
         if constexpr (F == NEAREST) {
@@ -306,6 +356,9 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
     }
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
+    __amdgpu_buffer_rsrc_t rm;
+    if constexpr (OCC)
+        rm = occ_rsrc(c.vol);
     CompSum acc[3];
     acc[0].init();
     acc[1].init();
@@ -319,7 +372,6 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
         if constexpr (JIT)
             hj.init((uint32_t)i, (uint32_t)s | 0x80000000u, c.seed);
         uint32_t pend = 0;
-        bool pend_ok = false;
         float kh = 0.5f;
         for (int k = 0; k < c.steps; ++k, kh += 1.0f) {
             int i0[3], o[3];
@@ -342,7 +394,7 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
                 step_coords(g, kh, i0, t);
             }
             if constexpr (OCC) {
-                if (!brick_occupied<P2>(c.vol, i0))
+                if (brick_empty(rm, c.vol, i0))
                     continue;
             }
             pick3<F, VAR>(t, h.at((uint32_t)k), o);
@@ -353,18 +405,16 @@ __global__ __launch_bounds__(256) void k_emit_stoch(RaymarchCall c, uint32_t nb_
                 tp[1] = y;
                 tp[2] = z;
             }
-            bool ok;
-            const uint32_t off = voxel_offset<HALF, P2>(c.vol, x, y, z, ok);
+            const uint32_t off = voxel_offset_or_outside<HALF, P2>(c.vol, x, y, z);
             float B[3];
-            planck3(bits_value<HALF>(masked_bits(pend, pend_ok)), B);   // step k-1
+            planck3(bits_value<HALF>(pend), B);    // step k-1
             acc[0].add(B[0]);
             acc[1].add(B[1]);
             acc[2].add(B[2]);
-            pend = voxel_bits<HALF>(rs, off);                            // step k
-            pend_ok = ok;
+            pend = voxel_bits<HALF>(rs, off);      // step k (0 outside the grid)
         }
         float B[3];
-        planck3(bits_value<HALF>(masked_bits(pend, pend_ok)), B);
+        planck3(bits_value<HALF>(pend), B);
         acc[0].add(B[0]);
         acc[1].add(B[1]);
         acc[2].add(B[2]);
@@ -404,6 +454,9 @@ __global__ __launch_bounds__(256) void k_emit_det(RaymarchCall c, uint32_t nb_pa
     }
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(c.vol.base), 0,
                                                                   (int)c.vol.bytes, kBufferFlags);
+    __amdgpu_buffer_rsrc_t rm;
+    if constexpr (OCC)
+        rm = occ_rsrc(c.vol);
     constexpr int NT = Taps<F>::n;
     constexpr int F0 = Taps<F>::first;
     CompSum acc[3];
@@ -417,7 +470,7 @@ __global__ __launch_bounds__(256) void k_emit_det(RaymarchCall c, uint32_t nb_pa
         float wx[4], wy[4], wz[4];
         step_coords(g, kh, i0, t);
         if constexpr (OCC) {
-            if (!brick_occupied(c.vol, i0))
+            if (brick_empty_clamped(rm, c.vol, i0))
                 continue;   // every tap is 0 K: no emission either way
         }
         if constexpr (F == NEAREST) {
@@ -654,34 +707,40 @@ __global__ __launch_bounds__(256) void k_filter3d(Filter3DCall c)
 }
 
 // ---------------------------------------------------------- occupancy bricks
-// One lane per brick scans the brick grown by 2 voxels on every side; a
+// One lane per bit of the mask (OccLayout): a padding bit is 0; a brick's
+// bit is 1 when its box grown by 2 voxels on every side holds only zeros (a
+// NaN counts as non-zero), the scan stopping at the first other voxel.  A
 // wave's 64 bits are gathered with a ballot and written as two words.
 template <bool HALF>
-__global__ __launch_bounds__(256) void k_build_occ(VolArgs v, int32_t lg, uint32_t *occ, int64_t words)
+__global__ __launch_bounds__(256) void k_build_occ(VolArgs v, uint32_t *occ, int64_t words)
 {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
-    bool bit = false;
-    if (b < nb) {
-        const int bx = (int)(b % v.nbx), by = (int)((b / v.nbx) % v.nby), bz = (int)(b / ((int64_t)v.nbx * v.nby));
-        const int B = 1 << lg;
-        const int x0 = max(bx * B - 2, 0), x1 = min(bx * B + B + 2, v.nx);
-        const int y0 = max(by * B - 2, 0), y1 = min(by * B + B + 2, v.ny);
-        const int z0 = max(bz * B - 2, 0), z1 = min(bz * B + B + 2, v.nz);
-        for (int z = z0; z < z1 && !bit; ++z)
-            for (int y = y0; y < y1 && !bit; ++y) {
-                const int64_t row = ((int64_t)z * v.ny + y) * v.nx;
-                for (int x = x0; x < x1; ++x) {
-                    float val;
-                    if constexpr (HALF)
-                        val = half_bits_to_float(static_cast<const uint16_t *>(v.base)[row + x]);
-                    else
-                        val = static_cast<const float *>(v.base)[row + x];
-                    bit |= !(val == 0.0f);   // non-zero or NaN
+    const int64_t bits = (int64_t)v.occ_sx * v.occ_sy * v.nbz;
+    bool empty = false;
+    if (b < bits) {
+        const int bx = (int)(b % v.occ_sx), by = (int)((b / v.occ_sx) % v.occ_sy);
+        const int bz = (int)(b / ((int64_t)v.occ_sx * v.occ_sy));
+        if (bx < v.nbx && by < v.nby) {
+            const int B = 1 << v.occ_log2;
+            const int x0 = max(bx * B - 2, 0), x1 = min(bx * B + B + 2, v.nx);
+            const int y0 = max(by * B - 2, 0), y1 = min(by * B + B + 2, v.ny);
+            const int z0 = max(bz * B - 2, 0), z1 = min(bz * B + B + 2, v.nz);
+            empty = true;
+            for (int z = z0; z < z1 && empty; ++z)
+                for (int y = y0; y < y1 && empty; ++y) {
+                    const int64_t row = ((int64_t)z * v.ny + y) * v.nx;
+                    for (int x = x0; x < x1; ++x) {
+                        float val;
+                        if constexpr (HALF)
+                            val = half_bits_to_float(static_cast<const uint16_t *>(v.base)[row + x]);
+                        else
+                            val = static_cast<const float *>(v.base)[row + x];
+                        empty &= val == 0.0f;
+                    }
                 }
-            }
+        }
     }
-    const uint64_t m = __ballot(bit);
+    const uint64_t m = __ballot(empty);
     if ((threadIdx.x & 63) == 0) {
         const int64_t w0 = b >> 5;   // b is a multiple of 64 here
         if (w0 < words)
@@ -691,14 +750,14 @@ __global__ __launch_bounds__(256) void k_build_occ(VolArgs v, int32_t lg, uint32
     }
 }
 
-hipError_t launch_build_occupancy(const VolArgs &v, int32_t lg, uint32_t *occ, int64_t words, hipStream_t s)
+hipError_t launch_build_occupancy(const VolArgs &v, uint32_t *occ, hipStream_t s)
 {
-    const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
-    dim3 grid((uint32_t)((nb + 255) / 256)), block(256);
+    const int64_t words = v.occ_bytes / 4;
+    dim3 grid((uint32_t)((words * 32 + 255) / 256)), block(256);
     if (v.fmt == SF_R16F)
-        k_build_occ<true><<<grid, block, 0, s>>>(v, lg, occ, words);
+        k_build_occ<true><<<grid, block, 0, s>>>(v, occ, words);
     else
-        k_build_occ<false><<<grid, block, 0, s>>>(v, lg, occ, words);
+        k_build_occ<false><<<grid, block, 0, s>>>(v, occ, words);
     return hipGetLastError();
 }
 

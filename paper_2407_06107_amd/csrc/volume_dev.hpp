@@ -86,28 +86,96 @@ __device__ __forceinline__ float voxel(__amdgpu_buffer_rsrc_t rs, const VolArgs 
     return ok ? val : 0.0f;
 }
 
-__device__ __forceinline__ void step_coords(const RayGeom &g, float kh, int i0[3], float t[3])
+// floor(p) as an integer in one instruction (a conversion that rounds toward
+// -inf); exact for the raster positions the ray setup admits (|p| < 2^22).
+__device__ __forceinline__ int floor_to_int(float p)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(p));
+    return r;
+}
+
+// Raster position p of the step at kh = k + 1/2 and its cell i0 = floor(p).
+__device__ __forceinline__ void step_pos(const RayGeom &g, float kh, float p[3], int i0[3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float p = __builtin_fmaf(kh, g.G[a], g.E[a]);
-        float fl = __builtin_floorf(p);
-        i0[a] = (int)fl;
-        t[a] = p - fl;
+        p[a] = __builtin_fmaf(kh, g.G[a], g.E[a]);
+        i0[a] = floor_to_int(p[a]);
     }
 }
 
-// True unless the lookup point's brick is known to be empty: a tap of any
-// filter lies within [i0-1, i0+2] per axis, inside the brick's 2-voxel
-// dilation, so a clear bit means every tap reads zero.  The brick
-// coordinates are clamped to the grid's bricks, which is exact as well: for
-// i0 < 0 the taps inside the grid lie in [0, 1], and for i0 at or beyond the
-// last brick's end they lie in {n-1} (or nowhere), both within the dilation
-// of the nearest brick; so no step whose taps can read a non-zero voxel is
-// skipped, and the index always lies inside the mask.  The bit is extracted
-// with the hardware's offset-mod-32 field extract.
-// P2: nx and ny are powers of two, so are the brick counts along x and y
-// (nx >> occ_log2, or 1 below one brick) and the index is built with shifts.
+// The fractions t = p - i0: exact, and equal to p - floor(p) (i0 converts
+// back to binary32 exactly).
+__device__ __forceinline__ void step_frac(const float p[3], const int i0[3], float t[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        t[a] = p[a] - (float)i0[a];
+}
+
+__device__ __forceinline__ void step_coords(const RayGeom &g, float kh, int i0[3], float t[3])
+{
+    float p[3];
+    step_pos(g, kh, p, i0);
+    step_frac(p, i0, t);
+}
+
+// Byte offset of voxel (x, y, z), or for a tap outside the grid an offset at
+// or past the end of every grid (a grid holds less than 2^32 bytes, a
+// multiple of its voxel size), where the raw buffer load reads 0, the value
+// +0.0: no select on the loaded value is needed.
+template <bool HALF, bool P2>
+__device__ __forceinline__ uint32_t voxel_offset_or_outside(const VolArgs &v, int x, int y, int z)
+{
+    const bool ok = ((uint32_t)x < (uint32_t)v.nx) & ((uint32_t)y < (uint32_t)v.ny) & ((uint32_t)z < (uint32_t)v.nz);
+    uint32_t idx;
+    if constexpr (P2)
+        idx = ((((uint32_t)z << v.ly) | (uint32_t)y) << v.lx) | (uint32_t)x;
+    else
+        idx = __umul24(__umul24((uint32_t)z, (uint32_t)v.ny) + (uint32_t)y, (uint32_t)v.nx) + (uint32_t)x;
+    return ok ? idx * (HALF ? 2u : 4u) : (HALF ? 0xfffffffeu : 0xfffffffcu);
+}
+
+// The brick mask (OccLayout) as a raw buffer: loads past its end read 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t occ_rsrc(const VolArgs &v)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(v.occ), 0, (int)v.occ_bytes, kBufferFlags);
+}
+
+// The mask word that holds the bit of the lookup point's brick, and the
+// bit's index b (bit b & 31 of the word).  A 1 bit means the brick is
+// provably empty, so that a step there can be skipped exactly: a tap of any
+// filter lies within [i0-1, i0+2] per axis, inside the 2-voxel dilation of
+// i0's brick.  Brick coordinates are arithmetic shifts of i0, and the bit
+// index is formed without clamps:
+// - a point whose brick coordinates all lie in [-1, nb] (every point of the
+//   grid's raster box, i0 >= -1) reads its own brick's bit, or a 0: a
+//   coordinate of -1 in x or y lands on the padding bit that ends the
+//   previous row or the padding row that ends the previous plane, -1 in z
+//   gives a negative index (a word offset past the end, read as 0), nb in x
+//   or y lands on padding and nb in z on padding or past the end;
+// - a point with a brick coordinate below -1 or above nb has i0 <= -3 or
+//   i0 >= n + 2 on that axis (bricks of at least 2 voxels), so all of its
+//   taps lie outside the grid and read zero whatever the bit says.
+// The 24-bit multiplies are exact for coordinates in [-1, nb]: nbz*sy and sx
+// stay below 2^23, and the mask holds at most 2^30 bits.
+__device__ __forceinline__ uint32_t brick_word(__amdgpu_buffer_rsrc_t rm, const VolArgs &v, const int i0[3],
+                                               uint32_t &b)
+{
+    const int bx = i0[0] >> v.occ_log2, by = i0[1] >> v.occ_log2, bz = i0[2] >> v.occ_log2;
+    b = (uint32_t)(__mul24(__mul24(bz, v.occ_sy) + by, v.occ_sx) + bx);
+    return __builtin_amdgcn_raw_buffer_load_b32(rm, (b >> 3) & ~3u, 0, 0);
+}
+
+// True when the lookup point's brick is provably empty (brick_word's bit).
+__device__ __forceinline__ bool brick_empty(__amdgpu_buffer_rsrc_t rm, const VolArgs &v, const int i0[3])
+{
+    uint32_t b;
+    const uint32_t w = brick_word(rm, v, i0, b);
+    return __builtin_amdgcn_ubfe(w, b, 1u) != 0u;
+}
+
 // clamp(x, 0, hi) for a wave-uniform hi in one instruction (the compiler
 // forms v_med3_i32 only for compile-time bounds)
 __device__ __forceinline__ int clamp0_uniform(int x, int hi)
@@ -117,30 +185,20 @@ __device__ __forceinline__ int clamp0_uniform(int x, int hi)
     return r;
 }
 
-template <bool P2 = false>
-__device__ __forceinline__ bool brick_occupied(const VolArgs &v, const int i0[3])
+// brick_empty with the brick coordinates clamped to the grid's bricks, for
+// the comparators: a point just outside the grid (i0 = -1, or at or past the
+// last brick's end) tests the nearest brick, whose 2-voxel dilation holds
+// every tap of such a point that lies inside the grid, so it too may be
+// skipped exactly (the comparators' steps at the grid's faces read their
+// taps one by one, so skipping them matters there).
+__device__ __forceinline__ bool brick_empty_clamped(__amdgpu_buffer_rsrc_t rm, const VolArgs &v, const int i0[3])
 {
-    const uint32_t bx = (uint32_t)clamp0_uniform(i0[0] >> v.occ_log2, v.nbx - 1);
-    const uint32_t by = (uint32_t)clamp0_uniform(i0[1] >> v.occ_log2, v.nby - 1);
-    const uint32_t bz = (uint32_t)clamp0_uniform(i0[2] >> v.occ_log2, v.nbz - 1);
-    uint32_t b;
-    if constexpr (P2) {
-        const int lbx = max(v.lx - v.occ_log2, 0), lby = max(v.ly - v.occ_log2, 0);
-        b = (((bz << lby) | by) << lbx) | bx;
-    } else {
-        b = __umul24(__umul24(bz, (uint32_t)v.nby) + by, (uint32_t)v.nbx) + bx;
-    }
-    return __builtin_amdgcn_ubfe(v.occ[b >> 5], b, 1u) != 0u;
-}
-
-// The loaded bits, or 0 (the value 0.0) for a tap outside the grid.  The
-// empty asm pins the select to the loaded 32-bit word, ahead of the
-// conversion, so that the compiler does not move it past the conversion.
-__device__ __forceinline__ uint32_t masked_bits(uint32_t b, bool ok)
-{
-    uint32_t r = ok ? b : 0u;
-    asm volatile("" : "+v"(r));
-    return r;
+    const int bx = clamp0_uniform(i0[0] >> v.occ_log2, v.nbx - 1);
+    const int by = clamp0_uniform(i0[1] >> v.occ_log2, v.nby - 1);
+    const int bz = clamp0_uniform(i0[2] >> v.occ_log2, v.nbz - 1);
+    const uint32_t b = (uint32_t)(__mul24(__mul24(bz, v.occ_sy) + by, v.occ_sx) + bx);
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rm, (b >> 3) & ~3u, 0, 0);
+    return __builtin_amdgcn_ubfe(w, b, 1u) != 0u;
 }
 
 template <int F, int VAR>

@@ -40,7 +40,7 @@ def test_header_symbols_exported(sf):
 
 
 def test_versions(sf):
-    assert sf.sf_abi_version() == 2
+    assert sf.sf_abi_version() == 3
     assert sf.sf_rng_version() == 1
 
 
@@ -395,8 +395,12 @@ def test_product_path_has_no_fallback(sf, monkeypatch, tmp_path):
 
 
 def test_occupancy_words_and_validation(sf):
-    assert sf.sf_occupancy_words(512, 512, 512, 3) == 64 ** 3 // 32
-    assert sf.sf_occupancy_words(10, 9, 8, 2) == -(-(3 * 3 * 2) // 32)
+    # one bit per brick in rows of nbx + 1 and planes of nby + 1 rows, in 32-bit words
+    assert sf.sf_occupancy_words(512, 512, 512, 3) == -(-(65 * 65 * 64) // 32)
+    assert sf.sf_occupancy_words(10, 9, 8, 2) == 1                     # 4 x 4 x 2 bits
+    assert sf.sf_occupancy_words(1, 1, 1, 1) == 1
+    assert sf.sf_occupancy_words(4096, 4096, 1024, 1) == 0             # 2049^2 x 512 bits: over 2^30
+    assert sf.sf_occupancy_words(4096, 2048, 256, 1) == -(-(2049 * 1025 * 128) // 32)
     assert sf.sf_occupancy_words(8, 8, 8, 0) == 0
     L = sf.lib()
     vol = _vol(sf, brick_log2=2)

@@ -530,9 +530,9 @@ def test_occupancy_mask_property(orc):
 
 
 def test_occupancy_nearest_brick_is_exact_outside_the_grid(orc):
-    """The ray march tests the brick nearest to a lookup point (its brick
-    coordinates clamped to the grid's bricks), also for points outside the
-    grid: a point whose trilinear or tricubic value is non-zero never meets a
+    """The deterministic comparators test the brick nearest to a lookup point
+    (its brick coordinates clamped to the grid's bricks), also for points
+    outside the grid: a point whose trilinear or tricubic value is non-zero never meets a
     clear bit.  Points on a raster range 4 voxels beyond every face; the data
     are zero near the low x and z faces and the high x face, so clamped
     bricks there are clear."""
@@ -558,6 +558,52 @@ def test_occupancy_nearest_brick_is_exact_outside_the_grid(orc):
         v = orc.filter3d(g, p, filt, orc.BEFORE)
         assert np.all(v[clear] == 0.0)
         assert np.any(v[~clear & outside] != 0.0)
+
+
+def test_occupancy_lookup_without_clamps_is_exact(orc):
+    """The ray march tests a lookup point's brick in the padded mask (one
+    bit per brick, 1 = the oracle's clear bit, in rows of nb + 1 bits and
+    planes of nb + 1 rows, the padding 0) at bit index (bz*sy + by)*sx + bx
+    from arithmetic shifts of floor(raster), reading 0 past the end.  For
+    points anywhere on a raster range far beyond every face (brick
+    coordinates -10..16 of 6), a point that meets a 1 has trilinear and
+    tricubic value exactly 0.  The data are zero near the low x and z faces
+    and the high x face, so bricks there hold 1s; points within one brick
+    outside the grid always meet a 0 (padding, or past the end), and points
+    further out alias onto arbitrary bits, which is exact because all of
+    their taps lie outside the grid."""
+    data = inputs.cloud_grid(24, seed=6).numpy()
+    data[:, :, :6] = 0.0
+    data[:, :, 18:] = 0.0
+    data[:5] = 0.0
+    g = _grid(data)
+    lg, nb = 2, 6
+    words = orc.build_occupancy(g, lg)
+    bits = np.unpackbits(words.view(np.uint8), bitorder="little")[:nb ** 3].reshape(nb, nb, nb)
+    sx = sy = nb + 1
+    mask = np.zeros((nb, sy, sx), np.uint8)
+    mask[:, :nb, :nb] = 1 - bits
+    flat = np.concatenate([mask.ravel(), np.zeros(-mask.size % 32, np.uint8)])   # whole 32-bit words
+    rng = np.random.default_rng(1)
+    raster = rng.uniform(-40.0, 64.0, size=(60000, 3))
+    p = ((raster + 0.5) / 24.0).astype(np.float32)
+    r32 = (p.astype(np.float64) * 24.0 - 0.5).astype(np.float32)     # fma(p, 24, -1/2) in binary32
+    i0 = np.floor(r32).astype(np.int64)
+    b = i0 >> lg
+    idx = (b[:, 2] * sy + b[:, 1]) * sx + b[:, 0]        # within 24-bit operands here
+    u = idx % 2 ** 32                                    # the unsigned index; word offset (u >> 3) & ~3
+    skip = np.zeros(len(u), bool)
+    inside = (u >> 5) < flat.size // 32
+    skip[inside] = flat[u[inside]] == 1
+    near = np.all((b >= -1) & (b <= nb), axis=1)
+    outside = np.any((i0 < 0) | (i0 >= 24), axis=1)
+    assert (skip & ~outside).sum() > 100                 # empty bricks inside the grid are skipped
+    assert not (skip & near & outside).any()             # points just outside meet padding or the end
+    assert (skip & ~near).sum() > 2000                   # far points alias onto bytes: any answer is exact
+    for filt in (orc.LINEAR, orc.BSPLINE3):
+        v = orc.filter3d(g, p, filt, orc.BEFORE)
+        assert np.all(v[skip] == 0.0)
+        assert np.any(v[~skip & outside & near] != 0.0)
 
 
 # ------------------------------------------------- Keys cubic, positivisation

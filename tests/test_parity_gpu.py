@@ -190,9 +190,20 @@ def test_occupancy_parity(sf, orc, small_cloud, lg):
     data = small_cloud.copy()
     data[:, :, 30:] = 0.0                                  # a slab of empty space
     og, vol = _grids(orc, sf, data)
+    nz, ny, nx = data.shape
     occ = sf.sf_build_occupancy(vol, lg).cpu().numpy().view(np.uint32)
     ref = orc.build_occupancy(og, lg)
-    assert np.array_equal(occ[:ref.size], ref)
+    B = 1 << lg
+    nb = [-(-n // B) for n in (nx, ny, nz)]
+    sx, sy = nb[0] + 1, nb[1] + 1
+    assert occ.size == -(-(sx * sy * nb[2]) // 32)
+    bits = np.unpackbits(occ.view(np.uint8), bitorder="little")
+    m = bits[:sx * sy * nb[2]].reshape(nb[2], sy, sx)
+    rbits = np.unpackbits(ref.view(np.uint8), bitorder="little")[:nb[0] * nb[1] * nb[2]]
+    # one bit per brick, 1 = provably empty = the oracle's clear bit; padding and tail 0
+    assert np.array_equal(m[:, :nb[1], :nb[0]].ravel(), 1 - rbits)
+    assert not m[:, nb[1]:, :].any() and not m[:, :, nb[0]:].any()
+    assert not bits[sx * sy * nb[2]:].any()
 
 
 @pytest.mark.parametrize("filt", ["LINEAR", "BSPLINE3"])
