@@ -228,6 +228,33 @@ def test_raymarch_occupancy_skip_is_exact(sf, orc, small_cloud, filt):
         _close(b, ref)
 
 
+@pytest.mark.parametrize("steps", [1, 2, 3, 7, 41])
+@pytest.mark.parametrize("filt, spp, variant", [("BSPLINE3", 1, 0), ("BSPLINE3", 3, 0), ("LINEAR", 1, 0),
+                                                ("BSPLINE3", 2, 1)])
+def test_raymarch_occupancy_pow2_odd_steps(sf, orc, filt, spp, variant, steps):
+    """The skipping march on a grid with power-of-two x and y (the
+    benchmark's addressing) over odd and even step counts (its loop takes two
+    steps per pass and a last single step): bit-identical to the march without
+    the mask, and equal to the oracle, for bricks of 2^2 and 2^3 voxels."""
+    _print_case("raymarch_occupancy_pow2", filt, spp, variant, steps)
+    data = inputs.cloud_grid(64, seed=9).numpy()[:40, :32, :64].copy()   # nz, ny, nx = 40, 32, 64
+    data[:, :, 40:] = 0.0
+    data[:6] = 0.0
+    og, plain = _grids(orc, sf, data)
+    nz, ny, nx = data.shape
+    rays = inputs.random_rays(2049, 1.0, seed=23)
+    rays_d = torch.from_numpy(rays).cuda()
+    f = getattr(sf, "SF_" + filt)
+    smp = sf.sampling(f, sf.SF_STOCHASTIC, spp, seed=29, rng_variant=variant)
+    a = sf.sf_raymarch(plain, rays_d, steps, smp).cpu().numpy()
+    for lg in (2, 3):
+        skip = sf.Volume(plain.data, scale=(nx, ny, nz), brick_log2=lg)
+        b = sf.sf_raymarch(skip, rays_d, steps, smp).cpu().numpy()
+        assert np.array_equal(a, b, equal_nan=True), lg
+    ref = orc.raymarch(og, rays, steps, getattr(orc, filt), orc.STOCHASTIC, spp=spp, seed=29, variant=variant)
+    _close(a, ref)
+
+
 # ------------------------------------------------------------------ 2-D
 @pytest.fixture(scope="module")
 def c1(orc):
