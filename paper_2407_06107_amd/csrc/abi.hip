@@ -881,6 +881,8 @@ sf_status sf_neural_train_step(const sf_train_state *stt, const int32_t *batch_i
     t.lr_mlp = lr_mlp;
     t.bc1 = (float)(1.0 - std::pow(0.9, step));
     t.bc2 = (float)(1.0 - std::pow(0.999, step));
+    t.inv_bc1 = (float)(1.0 / (1.0 - std::pow(0.9, step)));
+    t.inv_bc2 = (float)(1.0 / (1.0 - std::pow(0.999, step)));
     t.loss_out = loss_out;
     t.grad_params = grad_params;
     t.grad_latents = grad_latents;

@@ -184,6 +184,7 @@ struct TrainCall {
     int64_t batch, n_lattice;
     int32_t C, O;
     float lr_latent, lr_mlp, bc1, bc2;
+    float inv_bc1, inv_bc2;   // 1 / bc1, 1 / bc2 (binary32 of the exact reciprocals)
     float *loss_out, *grad_params, *grad_latents;
 };
 

@@ -296,7 +296,10 @@ __global__ __launch_bounds__(64) void k_train_mfma(TrainCall t, int64_t chunk, f
             for (int j = 0; j < 4; ++j) {
                 mo[j] = 0.9f * mq[j] + 0.1f * dz[j];
                 vo[j] = 0.999f * vq[j] + 0.001f * dz[j] * dz[j];
-                zo[j] = z[j] - t.lr_latent * (mo[j] / t.bc1) / (__builtin_sqrtf(vo[j] / t.bc2) + 1e-8f);
+                // bias corrections by the reciprocals, the step by the hardware
+                // square root and reciprocal (1 ulp each)
+                const float den = __builtin_amdgcn_sqrtf(vo[j] * t.inv_bc2) + 1e-8f;
+                zo[j] = z[j] - t.lr_latent * (mo[j] * t.inv_bc1) * __builtin_amdgcn_rcpf(den);
             }
             *reinterpret_cast<f32x4 *>(t.m_lat + q) = mo;
             *reinterpret_cast<f32x4 *>(t.v_lat + q) = vo;
