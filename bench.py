@@ -251,7 +251,9 @@ def valu_issue_rates(torch, reps=5):
             if lib.sfb_valu_rate_launch(w, C.c_void_p(out.data_ptr()), blocks, stream) != 0:
                 raise RuntimeError("sfb_valu_rate_launch failed")
         ms = time_launches(launch, reps, 2, torch)
-        rates[lib.sfb_valu_rate_name(w).decode()] = ms * 1e-3 * 2.4e9 / (32 * insts)
+        name = lib.sfb_valu_rate_name(w).decode()
+        per = 2 if name.endswith("(pairs)") else 1
+        rates[name] = ms * 1e-3 * 2.4e9 / (32 * insts * per)
     return rates
 
 
@@ -1025,6 +1027,8 @@ def main():
                     help="first run one device-to-device copy of this many bytes (HBM counter calibration)")
     ap.add_argument("--valu-rates", action="store_true",
                     help="only the vector-ALU issue-rate probe (CU cycles per wave64 instruction)")
+    ap.add_argument("--dense-probe", action="store_true",
+                    help="only the timed launch on constant-density grids of 16^3 to 512^3 (every step marched)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the path is single-GPU (rays are independent, so more GPUs "
@@ -1051,6 +1055,22 @@ def main():
     from paper_2407_06107_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.dense_probe:
+        # the timed launch (same rays, steps, mask and filter) on grids of
+        # constant density 0.5 filling the cube: every step gathers, so the
+        # instruction count is the same for every grid size and the time shows
+        # what the grid's size (its place in the cache hierarchy) costs
+        rays_d = torch.from_numpy(inputs.ortho_rays(N_PIX, RAYS_PER_PIX, side=1.0, seed=11)).cuda()
+        T = torch.empty(rays_d.shape[0], dtype=torch.float32, device="cuda")
+        smp = sf.sampling(sf.SF_BSPLINE3, sf.SF_STOCHASTIC, 1, seed=2024)
+        out = {}
+        for n in (16, 64, 256, 512):
+            g = torch.full((n, n, n), 0.5, dtype=torch.float16, device="cuda")
+            v = sf.Volume(g, side=1.0, brick_log2=BRICK_LOG2)
+            out[f"dense_{n}^3_ms"] = time_launches(lambda: sf.sf_raymarch(v, rays_d, STEPS, smp, T=T), 50, 5, torch)
+            del v, g
+        print(json.dumps(out))
+        return
     if args.valu_rates:
         print(json.dumps({"valu_issue_probe_cu_cycles_per_inst": valu_issue_rates(torch, reps=20),
                           "device": torch.cuda.get_device_name(0)}))

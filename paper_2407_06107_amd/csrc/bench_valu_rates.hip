@@ -52,6 +52,12 @@ SFB_RATE_KERNEL(k_xor_sdwa,
                 uint32_t, threadIdx.x + c)
 SFB_RATE_KERNEL(k_exp_f32, "v_exp_f32 %0, %0", float, 1.0f + (float)threadIdx.x)
 
+// two instructions per chain step: a binary32 add and a slower-class
+// instruction on another register
+SFB_RATE_KERNEL(k_add_cvt, "v_add_f32 %0, %0, %2\n\tv_cvt_f32_u32 v40, %0", float, 1.0f + (float)threadIdx.x, : "v40")
+SFB_RATE_KERNEL(k_add_cmp, "v_add_f32 %0, %0, %2\n\tv_cmp_le_f32 vcc, %0, %3", float, 1.0f + (float)threadIdx.x,
+                : "vcc")
+
 #undef SFB_RATE_KERNEL
 
 typedef void (*RateKernel)(uint32_t *, uint32_t);
@@ -72,6 +78,8 @@ const Case kCases[] = {
     {"v_mad_u64_u32 v,v,0", k_mad_u64_u32},
     {"v_xor_b32 sdwa", k_xor_sdwa},
     {"v_exp_f32 v", k_exp_f32},
+    {"v_add_f32 v,v + v_cvt_f32_u32 (pairs)", k_add_cvt},
+    {"v_add_f32 v,v + v_cmp_le_f32 (pairs)", k_add_cmp},
 };
 
 }  // namespace sfb
@@ -85,7 +93,8 @@ extern "C" const char *sfb_valu_rate_name(int which)
 
 // One launch of case `which`: blocks x 256 lanes, each writing one uint32 to
 // out (blocks * 256 words, device memory).  Wave64 instructions per lane:
-// kIter * kChains (the value sfb_valu_rate_insts returns).  Returns 0, -1
+// kIter * kChains (the value sfb_valu_rate_insts returns), twice that for the
+// cases named "(pairs)".  Returns 0, -1
 // for arguments outside these limits, or the HIP error of the launch.
 extern "C" int sfb_valu_rate_insts(void) { return sfb::kIter * sfb::kChains; }
 extern "C" int sfb_valu_rate_launch(int which, uint32_t *out, int blocks, void *stream)
