@@ -184,7 +184,7 @@ def test_raymarch_full_size_sampled(sf, orc, full_cloud, filt, mode):
         assert np.array_equal(Tk.cpu().numpy(), T[:k])
 
 
-@pytest.mark.parametrize("lg", [1, 2, 3])
+@pytest.mark.parametrize("lg", [1, 2, 3, 5, 6])
 def test_occupancy_parity(sf, orc, small_cloud, lg):
     _print_case("occupancy_parity", lg)
     data = small_cloud.copy()
@@ -247,7 +247,7 @@ def test_raymarch_occupancy_pow2_odd_steps(sf, orc, filt, spp, variant, steps):
     f = getattr(sf, "SF_" + filt)
     smp = sf.sampling(f, sf.SF_STOCHASTIC, spp, seed=29, rng_variant=variant)
     a = sf.sf_raymarch(plain, rays_d, steps, smp).cpu().numpy()
-    for lg in (2, 3):
+    for lg in (2, 3, 6):   # 6: one brick per axis, mask rows and planes of two
         skip = sf.Volume(plain.data, scale=(nx, ny, nz), brick_log2=lg)
         b = sf.sf_raymarch(skip, rays_d, steps, smp).cpu().numpy()
         assert np.array_equal(a, b, equal_nan=True), lg
