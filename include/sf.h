@@ -421,7 +421,8 @@ sf_status sf_filter3d(const sf_volume *vol, const float *pos, int64_t n, const s
  *          G = dt*B (fused multiply-adds), A = (o - wmin)*scale - 0.5 and
  *          B = d*scale.
  *   T    : n float32.  SF_STOCHASTIC: mean over spp of exp(-dt * sum_k sigma_k)
- *          with ONE picked voxel per step (sum accumulated in float64);
+ *          with ONE picked voxel per step (the sum over steps and the mean
+ *          over spp are compensated binary32 sums);
  *          SF_BEFORE: exp(-dt * sum_k sum_i w_i sigma_i);
  *          SF_AFTER_EXACT: prod_k sum_i w_i exp(-dt*sigma_i).
  *   dbg_taps: NULL, or n x spp x S x {x, y, z} int32 (stochastic only).
@@ -448,7 +449,8 @@ sf_status sf_raymarch(const sf_volume *vol, const float *rays, int64_t n, int32_
  *          SF_SHADE_PLANCK) integrated over the segment: dt * sum_k E_k with
  *          SF_STOCHASTIC: E_k = B(T_j) of the one picked voxel (mean over spp);
  *          SF_BEFORE: E_k = B(sum_i w_i T_i); SF_AFTER_EXACT: sum_i w_i B(T_i).
- *          Sums in float64.  An empty segment gives 0.
+ *          Sums over steps are compensated binary32 sums.  An empty segment
+ *          gives 0.
  *   footprint: standard deviation (world units) of a Gaussian pixel
  *          footprint in the plane perpendicular to the ray, sampled per step
  *          (stochastic only; 0 = none; footprint * max scale <= 2^20): the
